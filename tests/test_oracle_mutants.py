@@ -1,0 +1,58 @@
+"""Planted mistakes in the oracle must fail its pins.
+
+Each mutant is a copy of the oracle's C source with one plausible mistake (a flipped
+sign, a dropped normalisation, a wrong index or representative, an off-by-one median,
+a strict instead of inclusive comparison, a wrong transpose, a wrong constant).  It is
+compiled on the CPU and the pin suite is run against it in a subprocess; the suite
+must fail for every mutant.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "mr1l_oracle.c")
+
+MUTANTS = {
+    "dft_sign": ("sw[r] = (ld)sign * sinl(ang);", "sw[r] = -(ld)sign * sinl(ang);"),
+    "dft_no_normalisation": ("y[2 * q] = (double)(re / (ld)Ml);", "y[2 * q] = (double)(re);"),
+    "floor_mod_representative": ("if (r < 0) r += m;", "if (r < 0) r = -r;"),
+    "hash_drops_first_dim": ("for (int32_t u = 0; u < d; ++u)\n        acc += (__int128)k",
+                             "for (int32_t u = 1; u < d; ++u)\n        acc += (__int128)k"),
+    "median_off_by_one": ("if (L & 1) return v[L / 2];", "if (L & 1) return v[L / 2 + 1 < L ? L / 2 + 1 : 0];"),
+    "vote_strict": ("if (v[i] >= vote_min) {", "if (v[i] > vote_min) {"),
+    "singleton_test": ("if (cnt[off[l] + hh[q * L + l]] == 1) {", "if (cnt[off[l] + hh[q * L + l]] <= 2) {"),
+    "sort_ascending": ("if (x->key > y->key) return -1;\n    if (x->key < y->key) return 1;",
+                       "if (x->key < y->key) return -1;\n    if (x->key > y->key) return 1;"),
+    "sample_phase_sign": ("ld ang = TWO_PI_L * frac;", "ld ang = -TWO_PI_L * frac;"),
+    "adjoint_not_transposed": ("re += a * c - b * sn;\n                im += a * sn + b * c;",
+                               "re += a * c + b * sn;\n                im += -a * sn + b * c;"),
+    "anchor_index": ("(uint64_t)anchor[u - t]);\n        aph[i] = acc;", "(uint64_t)anchor[0]);\n        aph[i] = acc;"),
+    "splitmix_shift": ("x ^= x >> 27;", "x ^= x >> 26;"),
+    "eq42_factor": ("double bound = 0.25 *", "double bound = 0.5 *"),
+    "bucket_sum_conjugate": ("acc[2 * h + 1] += (ld)coef[2 * i + 1];", "acc[2 * h + 1] -= (ld)coef[2 * i + 1];"),
+    "threshold_not_squared": ("return m2 >= theta * theta;", "return m2 >= theta;"),
+    "driver_range": ("J[(int64_t)(t - 1) * nJ + q] = b - N;", "J[(int64_t)(t - 1) * nJ + q] = b - N + 1;"),
+    "median_weight_even": ("wq[2 * vs[L / 2].l + part] = 1.0;", "wq[2 * vs[0].l + part] = 1.0;"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique/found: {name}"
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(src.replace(old, new))
+    mlib = str(tmp_path / "libmutant.so")
+    oracle.build_from(str(msrc), mlib)
+    env = dict(os.environ, MR1L_ORACLE_LIB=mlib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, capture_output=True, text=True, timeout=600, cwd=ROOT)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

@@ -1,0 +1,427 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here compares the oracle with something other than itself: values
+printed in arXiv:2006.13053, closed forms (the aliasing formula eq. (2.4), Parseval),
+library routines in special cases (numpy's FFT, Python's sort and big integers),
+invariants of modular arithmetic and brute force on tiny inputs.  A planted mistake
+in the oracle (wrong sign, dropped normalisation, wrong index, wrong median, wrong
+threshold) fails at least one of them (see test_oracle_mutants.py).
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+# ---------------------------------------------------------------- parameters
+def test_primality_against_sieve():
+    P = set(synth.primes_in(0, 20000).tolist())
+    for n in range(0, 20001):
+        assert oracle.is_prime(n) == (n in P), n
+
+
+def test_lattice_sizes_printed_in_paper():
+    g = _gold("lattice_sizes.json")
+    for case in g["cases"]:
+        M = synth.next_prime_above(g["c"] * case["I"])
+        assert M == case["M"]
+        assert oracle.is_prime(M)
+        assert not any(oracle.is_prime(m) for m in range(int(g["c"] * case["I"]) + 1, M))
+
+
+def test_eq42_lattice_count_against_printed_cor27_bounds():
+    """Corollary 2.7's bound |Gamma| exp(-L / K) with K = 4c/((c-2) ln(c-1)) is printed
+    for L = 37..47.  Recover K from the printed values and check that the oracle's
+    eq. (4.2) count is the smallest odd L >= (K / 4)(ln|J| - ln delta)."""
+    g = _gold("cor27_failure_bound.json")
+    Ks = []
+    for st in g["sets"]:
+        for L, b in st["points"]:
+            Ks.append(L / math.log(st["Gamma"] / b))
+    K_lo, K_hi = min(Ks), max(Ks)
+    assert K_hi - K_lo < 0.02          # the printed values agree on one constant
+    rng = np.random.default_rng(5)
+    for _ in range(400):
+        nJ = int(rng.integers(10, 10**7))
+        delta = float(rng.uniform(0.05, 0.99))
+        L = oracle.num_lattices_eq42(nJ, 10.33, delta)
+        assert L % 2 == 1
+        x = math.log(nJ) - math.log(delta)
+        # L is odd, covers the bound and the odd number below does not
+        assert L >= 0.25 * K_lo * x - 1e-9 or L == 1
+        assert L - 2 < 0.25 * K_hi * x + 1e-9
+    # Theorem 1.1: K + 2/ln 8 <= 3.183
+    assert 0.5 * (K_lo + K_hi) + 2 / math.log(8) <= 3.1835
+
+
+def test_splitmix64_reference_sequence():
+    g = _gold("splitmix64.json")
+    for n, v in enumerate(g["outputs"], start=1):
+        assert oracle.splitmix64(g["seed"], n) == int(v)
+
+
+# ---------------------------------------------------------------- hashing
+def test_hash_against_big_integers_and_invariants():
+    rng = np.random.default_rng(11)
+    d, n, L = 7, 300, 4
+    freq = rng.integers(-2**40, 2**40, size=(d, n), dtype=np.int64)
+    freq[:, :5] = 0
+    freq[0, 5] = -1
+    freq[:, 6] = -(2**40)
+    M = np.array([2, 3, 10331, 2147483647], np.int64)
+    z = np.stack([rng.integers(0, m, size=d, dtype=np.int64) for m in M])
+    z[1, :] = 0
+    h = oracle.hash_buckets(freq, M, z)
+    for l in range(L):
+        for i in range(n):
+            ref = sum(int(freq[u, i]) * int(z[l, u]) for u in range(d)) % int(M[l])
+            assert h[l, i] == ref
+    # shift invariance h(k + M e_u) = h(k), negation, additivity
+    M2 = np.array([10331, 163], np.int64)
+    z2 = np.stack([rng.integers(0, m, size=d, dtype=np.int64) for m in M2])
+    k = rng.integers(-500, 500, size=(d, 50), dtype=np.int64)
+    k2 = rng.integers(-500, 500, size=(d, 50), dtype=np.int64)
+    hk, hk2 = oracle.hash_buckets(k, M2, z2), oracle.hash_buckets(k2, M2, z2)
+    hsum, hneg = oracle.hash_buckets(k + k2, M2, z2), oracle.hash_buckets(-k, M2, z2)
+    for l, m in enumerate(M2):
+        sh = k.copy()
+        sh[3] += m
+        assert np.array_equal(oracle.hash_buckets(sh, M2[l:l + 1], z2[l:l + 1])[0], hk[l])
+        assert np.array_equal(hsum[l], (hk[l] + hk2[l]) % m)
+        assert np.array_equal(hneg[l], (-hk[l]) % m)
+        e = np.eye(d, dtype=np.int64)
+        assert np.array_equal(oracle.hash_buckets(e, M2[l:l + 1], z2[l:l + 1])[0], z2[l] % m)
+
+
+def test_counts_brute_force():
+    p = synth.small_config(0)
+    c = oracle.counts(p.cand, p.M, p.z)
+    off = 0
+    for l, m in enumerate(p.M):
+        ref = np.zeros(int(m), np.int64)
+        for i in range(p.n):
+            ref[sum(int(p.cand[u, i]) * int(p.z[l, u]) for u in range(p.d)) % int(m)] += 1
+        assert np.array_equal(c[off:off + m], ref)
+        off += int(m)
+
+
+# ---------------------------------------------------------------- sampling + DFT
+def test_dft_equals_numpy_fft_for_equispaced_grid():
+    """d = 1, z = 1, L = 1: the lattice is the equispaced grid and the normalised DFT
+    is numpy's FFT divided by M (and the +1 sign is numpy's ifft)."""
+    rng = np.random.default_rng(3)
+    for m in (2, 3, 5, 163, 1009):
+        f = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+        g = oracle.dft(f, np.array([m]))
+        assert np.allclose(g, np.fft.fft(f) / m, rtol=0, atol=1e-13 * max(1, np.abs(f).max()))
+        gi = oracle.dft(f, np.array([m]), sign=+1)
+        assert np.allclose(gi, np.fft.ifft(f), rtol=0, atol=1e-13 * max(1, np.abs(f).max()))
+
+
+def test_sample_matches_floating_evaluation_at_lattice_nodes():
+    """eq. (2.1)/(2.2): evaluate p at x_j = j z / M mod 1 in plain floating point."""
+    p = synth.small_config(1)
+    f = oracle.sample(p.supp, p.coef, p.M, p.z)
+    off = 0
+    rng = np.random.default_rng(0)
+    for l, m in enumerate(p.M):
+        for j in rng.integers(0, m, size=12):
+            x = np.mod(j * p.z[l].astype(np.float64) / float(m), 1.0)
+            val = np.sum(p.coef * np.exp(2j * np.pi * (p.supp.T.astype(np.float64) @ x)))
+            assert abs(f[off + j] - val) < 1e-9
+        off += int(m)
+
+
+def test_sample_with_anchors_matches_floating_evaluation():
+    rng = np.random.default_rng(4)
+    d, t, s = 6, 3, 9
+    freq = rng.integers(-32, 33, size=(d, s), dtype=np.int64)
+    coef = rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    anc = rng.integers(0, 2**32, size=d - t, dtype=np.uint64).astype(np.uint32)
+    M = np.array([101, 103], np.int64)
+    z = np.stack([rng.integers(0, m, size=t, dtype=np.int64) for m in M])
+    f = oracle.sample(freq, coef, M, z, anchor=anc, t=t)
+    xa = anc.astype(np.float64) / 2.0**32
+    off = 0
+    for l, m in enumerate(M):
+        for j in (0, 1, 50, int(m) - 1):
+            x = np.concatenate([np.mod(j * z[l] / float(m), 1.0), xa])
+            val = np.sum(coef * np.exp(2j * np.pi * (freq.T.astype(np.float64) @ x)))
+            assert abs(f[off + j] - val) < 1e-9
+        f1 = oracle.sample_nodes(freq, coef, z[l], m, [0, 1, 50], anchor=anc, t=t)
+        assert np.allclose(f1, f[off + np.array([0, 1, 50])], atol=1e-15, rtol=0)
+        off += int(m)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_aliasing_formula_and_parseval(seed):
+    """eq. (2.4): the normalised lattice DFT of the samples is the bucket sum of the
+    coefficients; Parseval: sum |ghat|^2 = (1/M) sum |f|^2 per lattice."""
+    p = synth.small_config(seed)
+    f = oracle.sample(p.supp, p.coef, p.M, p.z)
+    g = oracle.dft(f, p.M)
+    b = oracle.bucket_sums(p.supp, p.coef, p.M, p.z)
+    assert np.abs(g - b).max() < 1e-14 * max(1.0, np.abs(b).max())
+    # bucket sums by brute force with Python integers
+    off = 0
+    for l, m in enumerate(p.M):
+        ref = np.zeros(int(m), np.complex128)
+        for i in range(p.supp.shape[1]):
+            h = sum(int(p.supp[u, i]) * int(p.z[l, u]) for u in range(p.d)) % int(m)
+            ref[h] += p.coef[i]
+        assert np.abs(b[off:off + m] - ref).max() < 1e-14
+        fl = f[off:off + m]
+        assert abs(np.sum(np.abs(g[off:off + m]) ** 2) - np.sum(np.abs(fl) ** 2) / m) < 1e-12
+        bins = np.array([0, 1, int(m) - 1])
+        assert np.abs(oracle.dft_bins(fl, m, bins) - g[off + bins]).max() < 1e-15
+        off += int(m)
+
+
+def test_dirichlet_counts_brute_force_median():
+    """Section 4.1.1, eq. (4.1): with all-ones coefficients on I the value read for k in
+    lattice l counts the members of I that k aliases to; its median decides the
+    classification of Table 4.1.  Counted here pair by pair with Python integers."""
+    p = synth.small_config(2, n=300, s=20, L=5, mlo=23, mhi=60)   # small M: many aliases
+    ones = np.ones(p.supp.shape[1], np.complex128)
+    f = oracle.sample(p.supp, ones, p.M, p.z)
+    g = oracle.dft(f, p.M)
+    assert np.abs(g.imag).max() < 1e-12
+    cnt_I = oracle.counts(p.supp, p.M, p.z)
+    assert np.array_equal(np.rint(g.real).astype(np.int64), cnt_I)
+    r = oracle.extract(p.cand, p.M, p.z, g, theta=0.5, s_cap=p.n)
+    offs = np.concatenate([[0], np.cumsum(p.M)])
+    supp = [tuple(int(v) for v in p.cand[:, i]) for i in p.supp_idx]
+    for q, i in enumerate(r["det_idx"]):
+        k = [int(v) for v in p.cand[:, i]]
+        per_l = []
+        for l, m in enumerate(p.M):
+            m = int(m)
+            per_l.append(sum(1 for kp in supp
+                             if sum((kp[u] - k[u]) * int(p.z[l, u]) for u in range(p.d)) % m == 0))
+        assert r["det_med"][q].real == pytest.approx(float(np.median(per_l)), abs=1e-12)
+    # votes: number of lattices whose bucket is occupied by I
+    for i in range(p.n):
+        k = [int(v) for v in p.cand[:, i]]
+        v = 0
+        for l, m in enumerate(p.M):
+            h = sum(k[u] * int(p.z[l, u]) for u in range(p.d)) % int(m)
+            v += cnt_I[offs[l] + h] > 0
+        assert r["votes"][i] == v
+
+
+# ---------------------------------------------------------------- Algorithms 2 and 4
+def _predicted_safe(p):
+    """Table 4.1 criterion: k is classified correctly for every coefficient choice if in
+    more than half of the lattices it aliases to no other member of I."""
+    cntI = oracle.counts(p.supp, p.M, p.z)
+    h = oracle.hash_buckets(p.cand, p.M, p.z)
+    offs = np.concatenate([[0], np.cumsum(p.M)])[:-1]
+    inI = np.zeros(p.n, bool)
+    inI[p.supp_idx] = True
+    others = cntI[(offs[:, None] + h)] - inI[None, :]
+    clean = (others == 0).sum(0)
+    return bool(np.all(2 * clean > p.L))
+
+
+def test_exact_recovery_when_no_potential_false_detection():
+    """After Corollary 2.7 (median paragraph): if every candidate aliases to no other
+    member of I in a majority of lattices, Algorithm 2 returns I and the exact
+    coefficients (median) -- checked against the known polynomial."""
+    ok_runs = 0
+    for seed in range(12):
+        p = synth.small_config(seed, mlo=800, mhi=1600)
+        f = oracle.sample(p.supp, p.coef, p.M, p.z)
+        g = oracle.dft(f, p.M)
+        r = oracle.extract(p.cand, p.M, p.z, g, p.theta, s_cap=p.n, postproc=False)
+        if not _predicted_safe(p):
+            continue
+        ok_runs += 1
+        assert np.array_equal(r["det_idx"], p.supp_idx)
+        assert np.abs(r["det_med"] - p.coef).max() < 1e-13
+        assert np.abs(r["det_coef"] - p.coef).max() < 1e-13
+        # Algorithm 4: the output is the support sorted by modulus, descending
+        order = sorted(range(len(p.coef)), key=lambda q: (-abs(p.coef[q]), p.supp_idx[q]))
+        assert np.array_equal(r["out_idx"], p.supp_idx[order])
+    assert ok_runs >= 3
+
+
+def test_full_grid_brute_force_tiny():
+    """d = 2, Gamma = [0, n)^2: a full tensor DFT on the n x n grid recovers the
+    coefficients exactly; the lattice method must agree when predicted safe."""
+    rng = np.random.default_rng(9)
+    nn = 12
+    grid = np.array(list(itertools.product(range(nn), range(nn))), np.int64).T
+    hits = 0
+    for trial in range(40):
+        s = 4
+        supp_idx = np.sort(rng.choice(grid.shape[1], size=s, replace=False))
+        coef = rng.standard_normal(s) + 1j * rng.standard_normal(s)
+        x = np.zeros((nn, nn), np.complex128)
+        x[grid[0, supp_idx], grid[1, supp_idx]] = coef
+        vals = np.fft.ifft2(x) * nn * nn          # samples on the n x n grid
+        exact = np.fft.fft2(vals) / (nn * nn)     # tensor DFT recovers x
+        M, z = synth.draw_lattices(rng, 5, 2, 37, 97)
+        p = synth.Problem(2, grid, supp_idx.astype(np.int64), coef, M, z, theta=1e-12)
+        f = oracle.sample(p.supp, coef, M, z)
+        g = oracle.dft(f, M)
+        r = oracle.extract(grid, M, z, g, 1e-12, s_cap=grid.shape[1])
+        if _predicted_safe(p):
+            hits += 1
+            assert np.array_equal(r["det_idx"], supp_idx)
+            got = np.zeros((nn, nn), np.complex128)
+            got[grid[0, r["det_idx"]], grid[1, r["det_idx"]]] = r["det_coef"]
+            assert np.abs(got - exact).max() < 1e-12
+    assert hits >= 5
+
+
+def test_postprocessing_repairs_median_failure():
+    """Remark 2.9: a frequency that aliases inside the detected set in most lattices has a
+    wrong median, but averaging the lattices where it is alone restores it."""
+    rng = np.random.default_rng(21)
+    found = 0
+    for trial in range(4000):
+        d, n, s, L = 2, 60, 6, 3
+        cand = synth.distinct_uniform_points(rng, n, d, -20, 20)
+        supp_idx = np.sort(rng.choice(n, size=s, replace=False)).astype(np.int64)
+        coef = rng.standard_normal(s) + 1j * rng.standard_normal(s)
+        M, z = synth.draw_lattices(rng, L, d, 7, 13, distinct=False)
+        f = oracle.sample(cand[:, supp_idx], coef, M, z)
+        g = oracle.dft(f, M)
+        r = oracle.extract(cand, M, z, g, 1e-12, s_cap=n, postproc=True)
+        if not set(supp_idx.tolist()) <= set(r["det_idx"].tolist()):
+            continue
+        pos = {int(i): q for q, i in enumerate(r["det_idx"])}
+        for q_s, i in enumerate(supp_idx):
+            q = pos[int(i)]
+            if r["det_mask"][q] != 0 and abs(r["det_med"][q] - coef[q_s]) > 1e-6:
+                found += 1
+                assert abs(r["det_coef"][q] - coef[q_s]) < 1e-12
+        if found >= 5:
+            break
+    assert found >= 5
+    # masks: bit l set iff alone among the detected set in lattice l (brute force)
+    h = oracle.hash_buckets(cand[:, r["det_idx"]], M, z)
+    for q in range(len(r["det_idx"])):
+        m = 0
+        for l in range(L):
+            if np.sum(h[l] == h[l, q]) == 1:
+                m |= 1 << l
+        assert r["det_mask"][q] == m
+
+
+def test_limit_matches_python_sort_and_threshold():
+    """Algorithm 4: threshold theta, modulus descending (ties by index), first s~."""
+    p = synth.mid_config(0, n=3000, s=30, L=7)
+    f = oracle.sample(p.supp, p.coef, p.M, p.z)
+    f = f + synth.noise_for(f, p.M, 40.0, 1)
+    g = oracle.dft(f, p.M)
+    for s_cap in (1, 7, 30, 100):
+        r = oracle.extract(p.cand, p.M, p.z, g, p.theta, s_cap=s_cap)
+        keep = [(abs(c) ** 2, int(i), q) for q, (i, c) in enumerate(zip(r["det_idx"], r["det_coef"]))
+                if abs(c) ** 2 >= p.theta ** 2]
+        keep.sort(key=lambda t: (-t[0], t[1]))
+        keep = keep[:s_cap]
+        assert np.array_equal(r["out_idx"], [t[1] for t in keep])
+        assert np.array_equal(r["out_pos"], [t[2] for t in keep])
+
+
+def test_vote_threshold_general_nu():
+    """Algorithm 1: a candidate is kept iff its number of non-zero buckets is >= nu L."""
+    p = synth.small_config(3, mlo=40, mhi=80)
+    f = oracle.sample(p.supp, p.coef, p.M, p.z)
+    g = oracle.dft(f, p.M)
+    for vm in (1, 2, 3, 4, 5):
+        r = oracle.extract(p.cand, p.M, p.z, g, p.theta, s_cap=p.n, vote_min=vm)
+        assert np.array_equal(r["det_idx"], np.nonzero(r["votes"] >= vm)[0])
+
+
+# ---------------------------------------------------------------- adjoint
+def test_adjoint_is_transpose_of_forward_and_matches_finite_differences():
+    """For a fixed support and selection the coefficients are a real-linear map of the
+    samples; orc_adjoint must be its transpose: checked by the dot-product identity
+    against the forward map (extract) and by central differences of extract."""
+    p = synth.mid_config(1, n=2000, s=12, L=5)
+    f = oracle.sample(p.supp, p.coef, p.M, p.z)
+    f = f + synth.noise_for(f, p.M, 40.0, 3)          # no exact median ties
+    g = oracle.dft(f, p.M)
+    r = oracle.extract(p.cand, p.M, p.z, g, p.theta, s_cap=p.n, postproc=True)
+    w = oracle.weights(p.cand, p.M, p.z, g, r["det_idx"], r["det_mask"], postproc=True)
+    rng = np.random.default_rng(7)
+    y = rng.standard_normal(len(r["det_idx"])) + 1j * rng.standard_normal(len(r["det_idx"]))
+    gf = oracle.adjoint(p.cand, p.M, p.z, r["det_idx"], w, y)
+
+    def forward(ff):
+        rr = oracle.extract(p.cand, p.M, p.z, oracle.dft(ff, p.M), p.theta, s_cap=p.n)
+        assert np.array_equal(rr["det_idx"], r["det_idx"])
+        return rr["det_coef"]
+
+    def loss(ff):
+        return float(np.real(np.vdot(y, forward(ff))))
+    # dot-product identity with a random direction
+    x = rng.standard_normal(f.shape[0]) + 1j * rng.standard_normal(f.shape[0])
+    lin = (loss(f + 1e-3 * x) - loss(f - 1e-3 * x)) / 2e-3
+    assert lin == pytest.approx(float(np.real(np.vdot(gf, x))), rel=1e-8, abs=1e-10)
+    # central differences on individual coordinates (real and imaginary parts)
+    for j in rng.integers(0, f.shape[0], size=6):
+        for unit in (1.0, 1j):
+            e = np.zeros_like(f)
+            e[j] = unit
+            fd = (loss(f + 1e-6 * e) - loss(f - 1e-6 * e)) / 2e-6
+            an = gf[j].real if unit == 1.0 else gf[j].imag
+            assert fd == pytest.approx(an, rel=1e-5, abs=1e-9)
+
+
+# ---------------------------------------------------------------- driver
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dimincr_recovers_random_sparse_polynomial(seed):
+    """Algorithm 3 Step 2 with Algorithm 4 (Section 4.2.1 setting, small): the support
+    is recovered and the coefficients are exact to rounding."""
+    d, s = 5, 8
+    freq, coef = synth.sparse_poly_box(seed, d=d, s=s, box=4)
+    out_f, out_c, nsamp = oracle.dimincr(freq, coef, N=4, s=s, s_local=2 * s, r=2,
+                                         theta=1e-12, c=10.33, delta=0.9,
+                                         Mlat=synth.next_prime_above(10.33 * 2 * s), seed=77 + seed)
+    truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
+    assert [tuple(r) for r in out_f.tolist()] == [t[0] for t in truth]
+    err = np.linalg.norm(out_c - np.array([t[1] for t in truth])) / np.linalg.norm(coef)
+    assert err < 1e-13
+    assert nsamp > 0
+
+
+def test_threshold_boundary_is_inclusive_on_modulus():
+    """Remark 2.3 / Algorithm 4: a bucket counts as non-zero iff |ghat| >= theta, and the
+    output keeps |p| >= theta.  Buckets are set directly around the boundary."""
+    d, L = 1, 3
+    M = np.array([11, 13, 17], np.int64)
+    z = np.array([[1], [1], [1]], np.int64)
+    cand = np.arange(0, 9, dtype=np.int64).reshape(1, -1)     # k = 0..8, bucket h = k
+    theta = 0.25
+    mags = [0.0, 0.5 * theta, 0.99 * theta, theta, 1.01 * theta, 2 * theta, 4.0, 0.9999999 * theta, 7.0]
+    g = np.zeros(int(M.sum()), np.complex128)
+    off = np.concatenate([[0], np.cumsum(M)])
+    for l in range(L):
+        for k, m in enumerate(mags):
+            ang = 0.3 + 0.7 * k + l
+            g[off[l] + k] = m * np.exp(1j * ang)
+    r = oracle.extract(cand, M, z, g, theta, s_cap=9, postproc=False)
+    expect = np.array([3 if m >= theta else 0 for m in mags])
+    # |.| computed from rounded components: compare with the same rule in double
+    expect = np.array([3 if (g[k].real ** 2 + g[k].imag ** 2) >= theta ** 2 else 0 for k in range(9)])
+    assert np.array_equal(r["votes"], expect)
+    assert set(np.nonzero(expect)[0]) >= {4, 5, 6, 8}
+    assert not set(np.nonzero(expect)[0]) & {0, 1, 2, 7}
+    # median of three equal-modulus but rotated values; output ordered by modulus
+    assert list(r["out_idx"][:2]) == [8, 6]
