@@ -1,0 +1,315 @@
+/*
+ * mr1l.h -- C ABI of the MI355X (gfx950) multiple-rank-1-lattice sparse FFT.
+ *
+ * Method: Kaemmerer, Krahmer, Volkmer, "A sample efficient sparse FFT for
+ * arbitrary frequency candidate sets in high dimensions" (arXiv:2006.13053).
+ * The library computes, on one GPU, the step the paper builds everything on:
+ * samples of a function on L random rank-1 lattices (eq. (2.1)), one
+ * normalised length-M_l DFT per lattice (Algorithm 2, first loop), the bucket
+ * h_l(k) = k . z_l mod M_l of every candidate frequency (Section 2.2 and
+ * the "Gamma mod M" representative of Section 2.1), the non-zero vote of
+ * Algorithms 1 and 2 with the threshold test of Remark 2.3, the median
+ * coefficients of eq. (2.10), the singleton ("alias-free") averaging of
+ * Remark 2.9, the output limitation of Algorithm 4, the adjoint of the
+ * coefficient map, and the dimension-incremental Step 2 of Algorithm 3.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - A plan describes a batch of F >= 1 functions with the same number of
+ *    lattice dimensions d and the same number of lattices L per function.
+ *    F = 1 is the plain method.  Lattice (f, l) has prime size M[f*L + l]
+ *    and generating vector z[(f*L + l)*d + u], 0 <= z < M.
+ *  - Nodes.  Samples f, DFT values ghat, bucket counts and the non-zero
+ *    bitmap are concatenated over (f, l) in that order: lattice (f, l)
+ *    occupies nodes [O_{f,l}, O_{f,l} + M_{f,l}), O the running sum of the
+ *    sizes.  mr1l_plan_nodes() returns the total.  Bitmap bit g of node g
+ *    lives in word g / 32, bit g % 32.
+ *  - Candidate sets are structure-of-arrays int64: freq[u * n_total + i] is
+ *    coordinate u of candidate i (u < d).  Function f owns candidates
+ *    [set_off[f], set_off[f+1]); set_off is a DEVICE array of F + 1 int64
+ *    (may be NULL when F == 1, meaning [0, n_total)).  Indices written by
+ *    the library (det_idx, out_idx) are relative to the function's own
+ *    range.  Any int64 frequency is hashed exactly.
+ *  - Complex arrays are interleaved (re, im) in the plan's dtype:
+ *    MR1L_C128 = double, MR1L_C64 = float.
+ *  - Every pointer argument marked "dev" is device memory owned by the
+ *    caller; "host" is host memory owned by the caller and read before the
+ *    call returns.  The plan owns only its tables and scratch.
+ *  - Calls are asynchronous on the plan's stream and never synchronise
+ *    unless stated; sizes produced on the device (detected counts) stay in
+ *    device memory, so a sequence of calls can be captured in a HIP graph.
+ *  - Errors are status codes (MR1L_OK = 0, negative on error); no C++
+ *    exception crosses the ABI.  mr1l_last_error() returns a message for
+ *    the calling thread's last failure.  A plan is not thread-safe; distinct
+ *    plans are independent.
+ */
+#ifndef MR1L_H
+#define MR1L_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { MR1L_C64 = 1, MR1L_C128 = 2 };
+
+enum {
+    MR1L_OK = 0,
+    MR1L_E_ARG = -1,          /* invalid argument (size, pointer, range)        */
+    MR1L_E_NOT_PRIME = -2,    /* a lattice size is not prime (Section 2.1)     */
+    MR1L_E_OVERFLOW = -3,     /* a size would overflow the index types          */
+    MR1L_E_NOT_INJECTIVE = -4,/* candidate set not injective mod M (Section 2.1)*/
+    MR1L_E_CAPACITY = -5,     /* an output capacity is too small               */
+    MR1L_E_NOMEM = -6,        /* device allocation failed                      */
+    MR1L_E_HIP = -7           /* a HIP runtime call failed                     */
+};
+
+typedef struct mr1l_plan_s *mr1l_plan;
+
+/* Version of the library (major * 10000 + minor * 100 + patch). */
+int mr1l_version(void);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *mr1l_last_error(void);
+
+/*
+ * Create a plan for F functions of d lattice dimensions with L lattices each
+ * (the multiple rank-1 lattice configuration of Section 2.1).
+ *   M     host [F*L]   lattice sizes; each must be a prime (checked with a
+ *                      deterministic Miller-Rabin test) with 2 <= M < 2^23.
+ *   z     host [F*L*d] generating vectors, 0 <= z < M (checked).
+ *   dtype MR1L_C128 or MR1L_C64.
+ *   stream hipStream_t (as void*) the plan's calls are ordered on; NULL is
+ *          the default stream.
+ * The plan precomputes the Bluestein chirps, kernel spectra and twiddle
+ * tables of the per-lattice DFTs and the constants of the exact bucket
+ * hash, and allocates its scratch.  Returns MR1L_E_NOT_PRIME, MR1L_E_ARG,
+ * MR1L_E_NOMEM or MR1L_E_HIP on failure (*out is then NULL).
+ */
+int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L,
+                     const int64_t *M, const int64_t *z, int32_t dtype,
+                     void *stream);
+
+int mr1l_plan_destroy(mr1l_plan p);
+
+/* Total number of nodes (sum of all M); sizes f, ghat, counts. */
+int64_t mr1l_plan_nodes(mr1l_plan p);
+
+/* Replace the plan's stream (the next calls are ordered on it). */
+int mr1l_plan_set_stream(mr1l_plan p, void *stream);
+
+/* Replace the generating vectors (host [F*L*d], same M), keeping the DFT
+ * tables; used when new random lattices of the same sizes are drawn. */
+int mr1l_plan_set_z(mr1l_plan p, const int64_t *z);
+
+/*
+ * Sample a sparse trigonometric polynomial (eq. (2.2)) at the lattice nodes
+ * x_j = j z_l / M_l mod 1 (eq. (2.1)).
+ *   d_poly   number of coordinates of the polynomial's frequencies, >= d.
+ *            The lattice sets coordinates u < d; coordinates d <= u < d_poly
+ *            are fixed anchors x'_u = anchor[f*(d_poly-d) + u-d] / 2^32 for
+ *            all nodes of function f (the embedding of Algorithm 3,
+ *            Step 2a).
+ *   term_off dev [F+1] or NULL (F == 1): function f's terms are
+ *            [term_off[f], term_off[f+1]).
+ *   n_terms  total number of terms.
+ *   freq     dev [d_poly][n_terms] int64;  coef dev [n_terms] complex.
+ *   anchor   dev uint32 [F][d_poly-d], or NULL when d_poly == d.
+ *   f        dev [nodes] complex output.
+ *   mode     0 = automatic, 1 = direct sum over terms per node (exact
+ *            integer phases), 2 = bucket sums (eq. (2.4)) followed by an
+ *            inverse lattice DFT; for many terms per node.
+ */
+int mr1l_sample(mr1l_plan p, int32_t d_poly, const int64_t *term_off,
+                int64_t n_terms, const int64_t *freq, const void *coef,
+                const uint32_t *anchor, void *f, int32_t mode);
+
+/*
+ * Normalised lattice DFT of Algorithm 2 (first loop):
+ *   ghat[O + h] = (1/M) sum_{j<M} f[O + j] exp(-2 pi i j h / M), h < M,
+ * for every lattice (Bluestein's chirp transform with LDS-staged Stockham
+ * FFTs), and the non-zero test of Remark 2.3 as a bitmap:
+ *   bit (O + h) of nz_bitmap = (|ghat[O+h]|^2 >= theta^2).
+ *   f, ghat   dev [nodes] complex (may not alias);
+ *   nz_bitmap dev uint32 [ceil(nodes/32)] or NULL.
+ */
+int mr1l_fft(mr1l_plan p, const void *f, void *ghat, double theta,
+             uint32_t *nz_bitmap);
+
+/*
+ * Buckets and bucket occupancy of a frequency set S:
+ *   hash[l * n_total + i] = h_{f,l}(k_i)  (i in function f's range),
+ *   counts[O_{f,l} + h]   = #{k in S_f : h_{f,l}(k) = h}
+ * (the occupancy behind Remark 2.9 and the counting polynomial of
+ * eq. (4.1)).  Either output may be NULL; counts is overwritten.
+ */
+int mr1l_hash_count(mr1l_plan p, int64_t n_total, const int64_t *set_off,
+                    const int64_t *freq, int32_t *hash, int32_t *counts);
+
+/* Options of mr1l_extract. */
+typedef struct {
+    double theta;      /* threshold of Remark 2.3 and Algorithm 4 (>= 0)      */
+    int32_t vote_min;  /* keep k iff #non-zero buckets >= vote_min; 0 means
+                          ceil(L/2), i.e. Algorithm 2 (nu = 1/2); otherwise
+                          ceil(nu L) of Algorithm 1                          */
+    int32_t postproc;  /* 1: singleton averaging of Remark 2.9, median as
+                          fall-back; 0: medians of eq. (2.10) only           */
+    int64_t s_cap;     /* Algorithm 4 sparsity s~ per function (>= 1)         */
+    int64_t cap;       /* detected-list capacity per function, 1..8192       */
+} mr1l_extract_opts;
+
+/* Outputs of mr1l_extract (all dev; optional ones may be NULL). */
+typedef struct {
+    int64_t *n_det;     /* [F] |detected set| (may exceed cap: then only cap
+                           entries are kept and the call's later stages see
+                           the first cap in ascending order)               */
+    int64_t *det_idx;   /* [F][cap] detected candidates, ascending          */
+    void *det_coef;     /* [F][cap] coefficient: singleton average, else
+                           median (postproc = 1); median (postproc = 0)    */
+    void *det_med;      /* [F][cap] median coefficient, eq. (2.10) | NULL   */
+    uint32_t *det_mask; /* [F][cap] bit l set iff the candidate is alone
+                           among the detected set in its bucket of lattice
+                           l (Remark 2.9) | NULL                           */
+    int32_t *det_hash;  /* [F][cap][L] buckets of the detected set | NULL   */
+    double *det_w;      /* [F][cap][L][2] real weights (re, im) of the
+                           coefficient as a linear map of the lattice
+                           values, for the adjoint | NULL                  */
+    int64_t *n_out;     /* [F] Algorithm 4 output size (<= s_cap)           */
+    int64_t *out_idx;   /* [F][s_cap] candidates by descending modulus      */
+    void *out_coef;     /* [F][s_cap] their coefficients                    */
+    int32_t *out_pos;   /* [F][s_cap] position in the detected list | NULL  */
+    uint8_t *votes;     /* [n_total] number of non-zero buckets | NULL      */
+} mr1l_extract_out;
+
+/*
+ * One pass of Algorithm 2 (+ Remark 2.9) + Algorithm 4 over the candidate
+ * sets, given the DFT values and the non-zero bitmap of mr1l_fft:
+ *   1. votes v(k) = #{l : bit h_l(k) of the bitmap is set}; the detected set
+ *      is {k : v(k) >= vote_min} in ascending candidate order;
+ *   2. occupancy of every bucket by the detected set, singleton masks;
+ *   3. coefficients: medians of the real and imaginary parts over the L
+ *      lattice values (even L: mean of the two middle order statistics),
+ *      and the singleton average when postproc;
+ *   4. keep |p| >= theta, order by |p| descending (ties: ascending index),
+ *      keep the first s_cap.
+ * Hashing and votes are bit-exact for any int64 input.  Returns
+ * MR1L_E_ARG for invalid options.  A detected count above cap is reported
+ * in n_det (device) and is not an error of the call.
+ */
+int mr1l_extract(mr1l_plan p, int64_t n_total, const int64_t *set_off,
+                 const int64_t *freq, const void *ghat,
+                 const uint32_t *nz_bitmap, const mr1l_extract_opts *o,
+                 const mr1l_extract_out *out);
+
+/*
+ * Adjoint of the coefficient map for a fixed support and fixed selections
+ * (the transpose of the real-linear map samples -> out_coef that one
+ * mr1l_fft + mr1l_extract computed):
+ *   gbar_{f,l}[h] = sum over outputs o of f with bucket h in lattice l of
+ *                   w_re * Re(grad[o]) + i w_im * Im(grad[o]),
+ *   grad_f[O + j] = (1/M) sum_h gbar[h] exp(+2 pi i j h / M).
+ *   cap, s_cap       the values used in the extract call;
+ *   n_out, out_pos,
+ *   det_hash, det_w  dev outputs of that extract call;
+ *   grad_out         dev [F][s_cap] complex (entries o >= n_out ignored);
+ *   grad_f           dev [nodes] complex output.
+ */
+int mr1l_adjoint(mr1l_plan p, int64_t cap, int64_t s_cap,
+                 const int64_t *n_out, const int32_t *out_pos,
+                 const int32_t *det_hash, const double *det_w,
+                 const void *grad_out, void *grad_f);
+
+/*
+ * HIP graphs: record the plan's subsequent calls into a graph instead of
+ * running them (mr1l_graph_begin), finish and instantiate it
+ * (mr1l_graph_end), replay it on the plan's stream (mr1l_graph_launch).
+ * Calls recorded this way must not change pointers or sizes between
+ * replays.  The library records only kernel launches (no memsets).
+ */
+typedef struct mr1l_graph_s *mr1l_graph;
+int mr1l_graph_begin(mr1l_plan p);
+int mr1l_graph_end(mr1l_plan p, mr1l_graph *g);
+int mr1l_graph_launch(mr1l_graph g, void *stream);
+int mr1l_graph_destroy(mr1l_graph g);
+
+/* Parameters of the dimension-incremental driver. */
+typedef struct {
+    int32_t d;         /* spatial dimension of the function                */
+    int64_t N;         /* single-coordinate candidate range [-N, N]        */
+    int64_t s;         /* sparsity s of the final step                     */
+    int64_t s_local;   /* sparsity of the intermediate steps (2 s default) */
+    int32_t r;         /* detection repetitions per step t < d             */
+    double theta;      /* threshold                                        */
+    double c;          /* constant of eq. (4.2) (10.33)                    */
+    double delta;      /* failure parameter of eq. (4.2)                   */
+    int64_t M;         /* prime lattice size used for every lattice        */
+    int32_t postproc;  /* Remark 2.9 averaging on/off                      */
+    uint64_t seed;     /* SplitMix64 seed of all random draws               */
+    int32_t dtype;     /* MR1L_C128 or MR1L_C64                            */
+} mr1l_dimincr_params;
+
+/*
+ * Sampling callback for the driver: write the samples of the black-box
+ * function at the nodes of L lattices in t dimensions with anchors
+ * x'_u = anchor[u - t] / 2^32 (u = t..d-1) into the device array f_dev
+ * (L*M complex, lattice-major), ordered on `stream`.  Return 0 on success.
+ */
+typedef int (*mr1l_sample_fn)(void *user, int32_t t, int32_t L,
+                              const int64_t *M, const int64_t *z,
+                              const uint32_t *anchor, void *f_dev,
+                              void *stream);
+
+/*
+ * Step 2 of Algorithm 3 with Algorithm 4 as the detection method
+ * (Section 3.2.2), the single-coordinate sets being the full range [-N, N]:
+ * for t = 2..d and i = 1..r~ (r~ = r for t < d, 1 for t = d), candidates
+ * J_t = I^(1..t-1) x [-N, N] in lexicographic order, L lattices by
+ * eq. (4.2) on |J_t| (smallest odd L >= (c/((c-2) ln(c-1))) (ln|J_t| -
+ * ln delta)), every lattice of size M, random anchors and generating
+ * vectors drawn from SplitMix64 outputs of the stream (seed, t, i)
+ * (n = ((t*64 + i) << 24) + c + 1; anchors u = t..d-1 first, then z_{l,u}
+ * for l < L, u < t; integers in [0, m) by floor(x m / 2^64); anchors x >> 32),
+ * Algorithm 4 with s~ = s_local (t < d) or s (t = d), and the union of the
+ * detected tuples (sorted, without repeats).  The output of the t = d call
+ * is the result.
+ *   fn/user   sampling callback; if fn is NULL the built-in sampler of the
+ *             sparse polynomial (poly_freq dev [d][poly_s] int64,
+ *             poly_coef dev [poly_s] complex) is used.
+ *   cap       capacity of freq_out / coef_out and of every intermediate
+ *             union (entries).
+ *   n_out     host: number of recovered frequencies.
+ *   freq_out  host [cap][d] int64, lexicographically sorted;
+ *   coef_out  host [cap] complex (dtype of the params).
+ *   total_samples host (may be NULL): sum over calls of L*M.
+ * Synchronises the stream.  MR1L_E_CAPACITY if a union exceeds cap.
+ */
+int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn,
+                 void *user, const int64_t *poly_freq, const void *poly_coef,
+                 int64_t poly_s, int64_t cap, int64_t *n_out,
+                 int64_t *freq_out, void *coef_out, int64_t *total_samples,
+                 void *stream);
+
+/*
+ * Stage timing.  While enabled, every call records a pair of HIP events on
+ * the plan's stream around each stage it launches: MR1L_STAGE_FFT (the
+ * lattice DFTs), MR1L_STAGE_VOTE (hashing + vote kernel), MR1L_STAGE_TAIL
+ * (sort, singleton masks, combine, limit), MR1L_STAGE_SAMPLE.
+ * mr1l_profile_read synchronises the stream, adds the elapsed milliseconds
+ * of every recorded pair into ms[stage] and the number of pairs into
+ * count[stage] (host arrays of MR1L_NSTAGE), and forgets the pairs.  Do not
+ * enable it while recording a graph.
+ */
+enum { MR1L_STAGE_FFT = 0, MR1L_STAGE_VOTE = 1, MR1L_STAGE_TAIL = 2, MR1L_STAGE_SAMPLE = 3,
+       MR1L_NSTAGE = 4 };
+int mr1l_profile(mr1l_plan p, int32_t enable);
+int mr1l_profile_read(mr1l_plan p, double *ms, int64_t *count);
+
+/* Number of lattices of eq. (4.2) for |J| candidates (host helper). */
+int32_t mr1l_num_lattices(int64_t nJ, double c, double delta);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MR1L_H */

@@ -730,6 +730,7 @@ int64_t orc_dimincr(int32_t d, int64_t N, int64_t s_poly, const int64_t *poly_fr
             }
             int64_t *tmp = prev; prev = cur; cur = tmp;
             nprev = m;
+            if (nprev == 0) break;   /* nothing detected: the result is empty */
         }
     }
     free(prev);

@@ -1,0 +1,336 @@
+"""MI355X (gfx950) multiple-rank-1-lattice sparse FFT (arXiv:2006.13053).
+
+Thin Python binding of the C ABI in ``include/mr1l.h``: every function here only
+marshals torch tensors (device memory) and the current HIP stream into the library
+``_lib/libmr1l.so``; all arithmetic runs in the library's HIP kernels.  There is no
+CPU fallback: if the library is missing or no GPU is present the calls raise.
+
+Names follow the ABI: ``mr1l_sample``, ``mr1l_fft``, ``mr1l_hash_count``,
+``mr1l_extract``, ``mr1l_adjoint``, ``mr1l_dimincr``, plus ``Plan`` (plan
+create/destroy), ``Graph`` (HIP graph capture of a plan's calls) and
+``LatticeCoefficients`` (torch.autograd.Function: forward = DFT + extract,
+backward = adjoint).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmr1l.so")
+
+MR1L_C64, MR1L_C128 = 1, 2
+MAX_CAP = 8192
+_lib = None
+
+
+class Mr1lError(RuntimeError):
+    """A library call returned an error status."""
+
+
+class ExtractOpts(C.Structure):
+    _fields_ = [("theta", C.c_double), ("vote_min", C.c_int32), ("postproc", C.c_int32),
+                ("s_cap", C.c_int64), ("cap", C.c_int64)]
+
+
+class ExtractOut(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in
+                ("n_det", "det_idx", "det_coef", "det_med", "det_mask", "det_hash", "det_w",
+                 "n_out", "out_idx", "out_coef", "out_pos", "votes")]
+
+
+class DimincrParams(C.Structure):
+    _fields_ = [("d", C.c_int32), ("N", C.c_int64), ("s", C.c_int64), ("s_local", C.c_int64),
+                ("r", C.c_int32), ("theta", C.c_double), ("c", C.c_double), ("delta", C.c_double),
+                ("M", C.c_int64), ("postproc", C.c_int32), ("seed", C.c_uint64), ("dtype", C.c_int32)]
+
+
+SAMPLE_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
+                        C.POINTER(C.c_int64), C.POINTER(C.c_uint32), C.c_void_p, C.c_void_p)
+
+_P, _I32, _I64, _D, _U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64
+
+# exported symbols and their argument types (kept in the order of include/mr1l.h)
+SIGNATURES = {
+    "mr1l_version": ([], C.c_int),
+    "mr1l_last_error": ([], C.c_char_p),
+    "mr1l_plan_create": ([C.POINTER(_P), _I32, _I32, _I32, _P, _P, _I32, _P], C.c_int),
+    "mr1l_plan_destroy": ([_P], C.c_int),
+    "mr1l_plan_nodes": ([_P], _I64),
+    "mr1l_plan_set_stream": ([_P, _P], C.c_int),
+    "mr1l_plan_set_z": ([_P, _P], C.c_int),
+    "mr1l_sample": ([_P, _I32, _P, _I64, _P, _P, _P, _P, _I32], C.c_int),
+    "mr1l_fft": ([_P, _P, _P, _D, _P], C.c_int),
+    "mr1l_hash_count": ([_P, _I64, _P, _P, _P, _P], C.c_int),
+    "mr1l_extract": ([_P, _I64, _P, _P, _P, _P, C.POINTER(ExtractOpts), C.POINTER(ExtractOut)], C.c_int),
+    "mr1l_adjoint": ([_P, _I64, _I64, _P, _P, _P, _P, _P, _P], C.c_int),
+    "mr1l_graph_begin": ([_P], C.c_int),
+    "mr1l_graph_end": ([_P, C.POINTER(_P)], C.c_int),
+    "mr1l_graph_launch": ([_P, _P], C.c_int),
+    "mr1l_graph_destroy": ([_P], C.c_int),
+    "mr1l_dimincr": ([C.POINTER(DimincrParams), SAMPLE_FN, _P, _P, _P, _I64, _I64, C.POINTER(_I64), _P, _P,
+                      C.POINTER(_I64), _P], C.c_int),
+    "mr1l_profile": ([_P, _I32], C.c_int),
+    "mr1l_profile_read": ([_P, _P, _P], C.c_int),
+    "mr1l_num_lattices": ([_I64, _D, _D], _I32),
+}
+
+STAGES = ("fft", "vote", "tail", "sample")
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"mr1l HIP library not built: {LIB_PATH} missing "
+                              "(run __graft_entry__.build() or paper_2006_13053_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().mr1l_last_error()
+        raise Mr1lError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise Mr1lError("device tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ctype(dtype):
+    if dtype == torch.complex128:
+        return MR1L_C128
+    if dtype == torch.complex64:
+        return MR1L_C64
+    raise Mr1lError("dtype must be torch.complex128 or torch.complex64")
+
+
+class Plan:
+    """Multiple rank-1 lattice configuration of F functions (mr1l_plan_create)."""
+
+    def __init__(self, d: int, M, z, F: int = 1, dtype=torch.complex128, stream=None):
+        M = np.ascontiguousarray(np.asarray(M, dtype=np.int64).reshape(-1))
+        if M.shape[0] % F:
+            raise Mr1lError("len(M) must be a multiple of F")
+        L = M.shape[0] // F
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.int64).reshape(F * L * d))
+        self.d, self.F, self.L, self.dtype = int(d), int(F), int(L), dtype
+        self.M = M.copy()
+        self._stream = stream
+        h = _P()
+        _check(lib().mr1l_plan_create(C.byref(h), self.d, self.F, self.L, M.ctypes.data_as(_P),
+                                      z.ctypes.data_as(_P), _ctype(dtype), _stream_handle(stream)),
+               "mr1l_plan_create")
+        self.handle = h
+        self.nodes = int(lib().mr1l_plan_nodes(h))
+        self.offsets = np.concatenate([[0], np.cumsum(M)]).astype(np.int64)
+
+    def set_stream(self, stream=None):
+        self._stream = stream
+        _check(lib().mr1l_plan_set_stream(self.handle, _stream_handle(stream)), "mr1l_plan_set_stream")
+
+    def set_z(self, z):
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.int64).reshape(-1))
+        _check(lib().mr1l_plan_set_z(self.handle, z.ctypes.data_as(_P)), "mr1l_plan_set_z")
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around every stage of the following calls."""
+        _check(lib().mr1l_profile(self.handle, int(bool(enable))), "mr1l_profile")
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} of the recorded calls (synchronises)."""
+        ms = np.zeros(len(STAGES), np.float64)
+        cnt = np.zeros(len(STAGES), np.int64)
+        _check(lib().mr1l_profile_read(self.handle, ms.ctypes.data_as(_P), cnt.ctypes.data_as(_P)),
+               "mr1l_profile_read")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(STAGES)}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.mr1l_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev():
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def mr1l_sample(plan: Plan, freq, coef, f=None, term_off=None, anchor=None, mode: int = 0):
+    """Samples of sum_k c_k e^{2 pi i k.x} at the plan's lattice nodes -> complex [nodes]."""
+    d_poly = int(freq.shape[0])
+    n_terms = int(freq.shape[1])
+    if f is None:
+        f = torch.empty(plan.nodes, dtype=plan.dtype, device=_dev())
+    _check(lib().mr1l_sample(plan.handle, d_poly, _ptr(term_off), n_terms, _ptr(freq), _ptr(coef),
+                             _ptr(anchor), _ptr(f), int(mode)), "mr1l_sample")
+    return f
+
+
+def mr1l_fft(plan: Plan, f, theta: float, ghat=None, bitmap=None, want_bitmap: bool = True):
+    """Normalised lattice DFTs and the non-zero bitmap -> (ghat, bitmap)."""
+    if ghat is None:
+        ghat = torch.empty(plan.nodes, dtype=plan.dtype, device=_dev())
+    if bitmap is None and want_bitmap:
+        bitmap = torch.empty((plan.nodes + 31) // 32, dtype=torch.int32, device=_dev())
+    _check(lib().mr1l_fft(plan.handle, _ptr(f), _ptr(ghat), float(theta), _ptr(bitmap)), "mr1l_fft")
+    return ghat, bitmap
+
+
+def mr1l_hash_count(plan: Plan, freq, set_off=None, want_hash: bool = True, want_counts: bool = True):
+    """Buckets [L, n] (int32) and occupancy counts [nodes] (int32)."""
+    n = int(freq.shape[1])
+    h = torch.empty((plan.L, n), dtype=torch.int32, device=_dev()) if want_hash else None
+    c = torch.empty(plan.nodes, dtype=torch.int32, device=_dev()) if want_counts else None
+    _check(lib().mr1l_hash_count(plan.handle, n, _ptr(set_off), _ptr(freq), _ptr(h), _ptr(c)),
+           "mr1l_hash_count")
+    return h, c
+
+
+class Extracted(dict):
+    """Device outputs of mr1l_extract (dict of tensors + the options used)."""
+
+
+def extract_buffers(plan: Plan, cap: int, s_cap: int, n_total: int, want_votes=False, want_w=True):
+    dev = _dev()
+    F, L = plan.F, plan.L
+    e = Extracted(
+        n_det=torch.zeros(F, dtype=torch.int64, device=dev),
+        det_idx=torch.zeros((F, cap), dtype=torch.int64, device=dev),
+        det_coef=torch.zeros((F, cap), dtype=plan.dtype, device=dev),
+        det_med=torch.zeros((F, cap), dtype=plan.dtype, device=dev),
+        det_mask=torch.zeros((F, cap), dtype=torch.int32, device=dev),
+        det_hash=torch.zeros((F, cap, L), dtype=torch.int32, device=dev),
+        det_w=torch.zeros((F, cap, L, 2), dtype=torch.float64, device=dev) if want_w else None,
+        n_out=torch.zeros(F, dtype=torch.int64, device=dev),
+        out_idx=torch.zeros((F, s_cap), dtype=torch.int64, device=dev),
+        out_coef=torch.zeros((F, s_cap), dtype=plan.dtype, device=dev),
+        out_pos=torch.zeros((F, s_cap), dtype=torch.int32, device=dev),
+        votes=torch.zeros(n_total, dtype=torch.uint8, device=dev) if want_votes else None,
+    )
+    e.cap, e.s_cap = int(cap), int(s_cap)
+    return e
+
+
+def mr1l_extract(plan: Plan, freq, ghat, bitmap, theta: float, s_cap: int, cap: int | None = None,
+                 vote_min: int = 0, postproc: bool = True, set_off=None, want_votes: bool = False,
+                 want_w: bool = True, out: Extracted | None = None):
+    """Algorithm 2 (+ Remark 2.9) + Algorithm 4 over the candidate sets -> Extracted."""
+    n = int(freq.shape[1])
+    cap = MAX_CAP if cap is None else int(cap)
+    if out is None:
+        out = extract_buffers(plan, cap, s_cap, n, want_votes, want_w)
+    o = ExtractOpts(float(theta), int(vote_min), int(bool(postproc)), int(s_cap), int(cap))
+    x = ExtractOut(*[None if out.get(k) is None else out[k].data_ptr() for k, _ in ExtractOut._fields_])
+    _check(lib().mr1l_extract(plan.handle, n, _ptr(set_off), _ptr(freq), _ptr(ghat), _ptr(bitmap),
+                              C.byref(o), C.byref(x)), "mr1l_extract")
+    out.theta, out.postproc = float(theta), bool(postproc)
+    return out
+
+
+def mr1l_adjoint(plan: Plan, ex: Extracted, grad_out, grad_f=None):
+    """Transpose of samples -> out_coef for the support/selection of ``ex``."""
+    if grad_f is None:
+        grad_f = torch.empty(plan.nodes, dtype=plan.dtype, device=_dev())
+    g = grad_out.contiguous().to(plan.dtype)
+    _check(lib().mr1l_adjoint(plan.handle, ex.cap, ex.s_cap, _ptr(ex["n_out"]), _ptr(ex["out_pos"]),
+                              _ptr(ex["det_hash"]), _ptr(ex["det_w"]), _ptr(g), _ptr(grad_f)),
+           "mr1l_adjoint")
+    return grad_f
+
+
+class Graph:
+    """HIP graph of a plan's calls: ``with Graph(plan) as g: ...`` then ``g.launch()``."""
+
+    def __init__(self, plan: Plan):
+        self.plan, self.handle = plan, None
+
+    def __enter__(self):
+        _check(lib().mr1l_graph_begin(self.plan.handle), "mr1l_graph_begin")
+        return self
+
+    def __exit__(self, et, ev, tb):
+        h = _P()
+        rc = lib().mr1l_graph_end(self.plan.handle, C.byref(h))
+        if et is None:
+            _check(rc, "mr1l_graph_end")
+            self.handle = h
+        return False
+
+    def launch(self, stream=None):
+        _check(lib().mr1l_graph_launch(self.handle, _stream_handle(stream)), "mr1l_graph_launch")
+
+    def __del__(self):
+        try:
+            if self.handle is not None and _lib is not None:
+                _lib.mr1l_graph_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def mr1l_num_lattices(nJ: int, c: float = 10.33, delta: float = 0.9) -> int:
+    return int(lib().mr1l_num_lattices(int(nJ), float(c), float(delta)))
+
+
+def mr1l_dimincr(d: int, N: int, s: int, s_local: int, r: int, theta: float, M: int, seed: int,
+                 poly_freq=None, poly_coef=None, c: float = 10.33, delta: float = 0.9,
+                 postproc: bool = True, dtype=torch.complex128, cap: int = 1 << 16, sample_fn=None):
+    """Algorithm 3 Step 2 driver -> (freq [n, d] int64 numpy, coef [n] numpy, total samples)."""
+    prm = DimincrParams(int(d), int(N), int(s), int(s_local), int(r), float(theta), float(c), float(delta),
+                        int(M), int(bool(postproc)), int(seed) & (2**64 - 1), _ctype(dtype))
+    fo = np.zeros((cap, d), np.int64)
+    co = np.zeros(cap, np.complex128 if dtype == torch.complex128 else np.complex64)
+    n_out, tot = C.c_int64(0), C.c_int64(0)
+    cb = SAMPLE_FN(0) if sample_fn is None else SAMPLE_FN(sample_fn)
+    ps = 0 if poly_freq is None else int(poly_freq.shape[1])
+    _check(lib().mr1l_dimincr(C.byref(prm), cb, None, _ptr(poly_freq), _ptr(poly_coef), ps, int(cap),
+                              C.byref(n_out), fo.ctypes.data_as(_P), co.ctypes.data_as(_P), C.byref(tot),
+                              _stream_handle()), "mr1l_dimincr")
+    n = n_out.value
+    return fo[:n], co[:n], int(tot.value)
+
+
+class LatticeCoefficients(torch.autograd.Function):
+    """Coefficients of Algorithm 4 as a function of the samples.
+
+    forward(f) runs mr1l_fft + mr1l_extract and returns out_coef [F, s_cap]; the
+    support and the selections (singleton masks, median order statistics) are held
+    fixed, so the map is real-linear and backward is mr1l_adjoint.
+    """
+
+    @staticmethod
+    def forward(ctx, f, plan, freq, theta, s_cap, cap, postproc, set_off=None):
+        ghat, bitmap = mr1l_fft(plan, f.detach(), theta)
+        ex = mr1l_extract(plan, freq, ghat, bitmap, theta, s_cap, cap, postproc=postproc, set_off=set_off)
+        ctx.plan, ctx.ex = plan, ex
+        ctx.mark_non_differentiable(ex["n_out"], ex["out_idx"])
+        return ex["out_coef"].clone(), ex["n_out"], ex["out_idx"]
+
+    @staticmethod
+    def backward(ctx, grad_coef, _g_nout=None, _g_idx=None):
+        gf = mr1l_adjoint(ctx.plan, ctx.ex, grad_coef)
+        return gf, None, None, None, None, None, None, None

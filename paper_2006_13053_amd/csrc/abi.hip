@@ -1,0 +1,581 @@
+// C ABI of the library: plan construction and the entry points of mr1l.h.
+#include "mr1l_internal.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+
+namespace mr1l {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int num_cus()
+{
+    static int cached = 0;
+    if (cached == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            cached = n;
+        else
+            cached = 256;
+    }
+    return cached;
+}
+
+// ---------------------------------------------------------------- number theory
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m)
+{
+    return (uint64_t)((unsigned __int128)a * b % m);
+}
+
+static uint64_t powmod(uint64_t a, uint64_t e, uint64_t m)
+{
+    uint64_t r = 1 % m;
+    a %= m;
+    while (e) {
+        if (e & 1) r = mulmod(r, a, m);
+        a = mulmod(a, a, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Deterministic Miller-Rabin for 64-bit integers (first twelve prime bases).
+static bool is_prime_u64(uint64_t n)
+{
+    if (n < 2) return false;
+    static const uint64_t small[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (uint64_t p : small) {
+        if (n == p) return true;
+        if (n % p == 0) return false;
+    }
+    uint64_t dd = n - 1;
+    int s = 0;
+    while ((dd & 1) == 0) { dd >>= 1; ++s; }
+    for (uint64_t a : small) {
+        uint64_t x = powmod(a, dd, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int r = 1; r < s; ++r) {
+            x = mulmod(x, x, n);
+            if (x == n - 1) { comp = false; break; }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+static bool smooth235(int64_t n)
+{
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+static int64_t next_smooth(int64_t n)
+{
+    while (!smooth235(n)) ++n;
+    return n;
+}
+
+// ---------------------------------------------------------------- tables (host, long double)
+template <typename T>
+static void push_twiddles(std::vector<T> &tab, int64_t n)
+{
+    const long double tp = 6.283185307179586476925286766559005768L;
+    for (int64_t m = 0; m < n; ++m) {
+        long double a = -tp * (long double)m / (long double)n;
+        tab.push_back((T)cosl(a));
+        tab.push_back((T)sinl(a));
+    }
+}
+
+// e^{-pi i r / M}: low part r < S, high part r = hi * S
+template <typename T>
+static void push_chirp(std::vector<T> &tab, int64_t M, int32_t &shift, int32_t &nlo)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    shift = 0;
+    while ((int64_t(1) << (2 * shift)) < 2 * M) ++shift;
+    nlo = 1 << shift;
+    const int64_t nhi = (2 * M + nlo - 1) / nlo;
+    for (int64_t r = 0; r < nlo; ++r) {
+        long double a = -pi * (long double)r / (long double)M;
+        tab.push_back((T)cosl(a));
+        tab.push_back((T)sinl(a));
+    }
+    for (int64_t h = 0; h < nhi; ++h) {
+        long double a = -pi * (long double)(h * nlo) / (long double)M;
+        tab.push_back((T)cosl(a));
+        tab.push_back((T)sinl(a));
+    }
+}
+
+// float reciprocal of M rounded down by at least 2^-21 relative
+static float inv_m_down(int64_t M)
+{
+    const double x = (1.0 / (double)M) * (1.0 - std::ldexp(1.0, -21));
+    float f = (float)x;
+    while ((double)f > x) f = std::nextafter(f, 0.0f);
+    return f;
+}
+
+// Largest |k_u| for which the 24-bit hash of every lattice of a function is exact.
+static int32_t fast_bound(int d, const int64_t *M, int L)
+{
+    int64_t kb = (int64_t(1) << 23) - 1;
+    kb = std::min<int64_t>(kb, ((int64_t(1) << 19) - 2) / d);
+    for (int l = 0; l < L; ++l) {
+        const int64_t m = M[l];
+        if (m > 1) kb = std::min<int64_t>(kb, ((int64_t(1) << 31) - m - 1) / ((int64_t)d * (m - 1)));
+    }
+    return (int32_t)std::max<int64_t>(kb, 0);
+}
+
+template <typename T>
+static int build_tables(Plan &p)
+{
+    constexpr int NMAX = lds_max_n<T>();
+    std::map<int64_t, int32_t> mid_of;
+    std::map<int64_t, int64_t> tw_of;
+    std::vector<T> tw, ch;
+    int64_t spec_len = 0;
+    auto twoff = [&](int64_t n) -> int64_t {
+        auto it = tw_of.find(n);
+        if (it != tw_of.end()) return it->second;
+        const int64_t off = (int64_t)tw.size() / 2;
+        push_twiddles(tw, n);
+        tw_of[n] = off;
+        return off;
+    };
+    std::vector<std::array<int32_t, 3>> mN;   // per mid: N, N1, N2
+    for (int64_t i = 0; i < (int64_t)p.M.size(); ++i) {
+        const int64_t M = p.M[i];
+        if (mid_of.count(M)) continue;
+        const int32_t mid = (int32_t)p.mdesc.size();
+        mid_of[M] = mid;
+        MDesc md{};
+        const int64_t N = next_smooth(std::max<int64_t>(2 * M - 1, 2));
+        int64_t N1 = N, N2 = 1;
+        if (N > NMAX) {
+            // most balanced split with both factors in LDS
+            int64_t best = -1;
+            for (int64_t a = 2; a <= NMAX; ++a)
+                if (N % a == 0 && N / a <= NMAX) {
+                    if (best < 0 || std::llabs(a - N / a) < std::llabs(best - N / best)) best = a;
+                }
+            if (best < 0) return fail(MR1L_E_OVERFLOW, "lattice size too large for the DFT");
+            N1 = best;
+            N2 = N / best;
+        }
+        md.spec_off = spec_len;
+        spec_len += N;
+        md.chirp_off = (int64_t)ch.size() / 2;
+        push_chirp(ch, M, md.chirp_shift, md.chirp_nlo);
+        md.tw_N = twoff(N);
+        md.tw_N1 = N2 > 1 ? twoff(N1) : md.tw_N;
+        md.tw_N2 = N2 > 1 ? twoff(N2) : md.tw_N;
+        p.mdesc.push_back(md);
+        mN.push_back({(int32_t)N, (int32_t)N1, (int32_t)N2});
+    }
+    p.lat.resize(p.M.size());
+    int64_t off = 0;
+    p.lds_lats.clear();
+    p.big_lats.clear();
+    p.big_maxN = 0;
+    for (int f = 0; f < p.F; ++f) {
+        const int32_t kb = fast_bound(p.d, p.M.data() + (size_t)f * p.L, p.L);
+        p.kb.push_back(kb);
+        for (int l = 0; l < p.L; ++l) {
+            const int64_t i = (int64_t)f * p.L + l;
+            const int64_t M = p.M[i];
+            LatDesc ld{};
+            ld.node_off = off;
+            ld.M = (int32_t)M;
+            ld.mid = mid_of[M];
+            ld.N = mN[ld.mid][0];
+            ld.N1 = mN[ld.mid][1];
+            ld.N2 = mN[ld.mid][2];
+            ld.func = f;
+            ld.inv_m = inv_m_down(M);
+            const int64_t S = (int64_t)p.d * kb * (M - 1);
+            ld.off32 = (uint32_t)(((S + M - 1) / M) * M);
+            ld.z_off = i * p.d;
+            p.lat[i] = ld;
+            off += M;
+            if (ld.N2 == 1) p.lds_lats.push_back((int32_t)i);
+            else {
+                p.big_lats.push_back((int32_t)i);
+                p.big_maxN = std::max(p.big_maxN, ld.N);
+            }
+        }
+    }
+    p.nodes = off;
+    p.spec_len = spec_len;
+    p.tw_len = (int64_t)tw.size() / 2;
+    p.chirp_len = (int64_t)ch.size() / 2;
+    const size_t esz = 2 * sizeof(T);
+    MR1L_HIP(hipMalloc(&p.d_spec, (size_t)spec_len * esz));
+    MR1L_HIP(hipMalloc(&p.d_tw, tw.size() * sizeof(T)));
+    MR1L_HIP(hipMemcpy(p.d_tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
+    MR1L_HIP(hipMalloc(&p.d_chirp, ch.size() * sizeof(T)));
+    MR1L_HIP(hipMemcpy(p.d_chirp, ch.data(), ch.size() * sizeof(T), hipMemcpyHostToDevice));
+    return MR1L_OK;
+}
+
+static int upload(Plan &p)
+{
+    MR1L_HIP(hipMalloc(&p.d_lat, p.lat.size() * sizeof(LatDesc)));
+    MR1L_HIP(hipMemcpy(p.d_lat, p.lat.data(), p.lat.size() * sizeof(LatDesc), hipMemcpyHostToDevice));
+    MR1L_HIP(hipMalloc(&p.d_mdesc, p.mdesc.size() * sizeof(MDesc)));
+    MR1L_HIP(hipMemcpy(p.d_mdesc, p.mdesc.data(), p.mdesc.size() * sizeof(MDesc), hipMemcpyHostToDevice));
+    std::vector<int32_t> z32(p.z.begin(), p.z.end());
+    MR1L_HIP(hipMalloc(&p.d_z32, z32.size() * sizeof(int32_t)));
+    MR1L_HIP(hipMemcpy(p.d_z32, z32.data(), z32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MR1L_HIP(hipMalloc(&p.d_z64, p.z.size() * sizeof(int64_t)));
+    MR1L_HIP(hipMemcpy(p.d_z64, p.z.data(), p.z.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    MR1L_HIP(hipMalloc(&p.d_kb, p.kb.size() * sizeof(int32_t)));
+    MR1L_HIP(hipMemcpy(p.d_kb, p.kb.data(), p.kb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!p.lds_lats.empty()) {
+        MR1L_HIP(hipMalloc(&p.d_lds_lats, p.lds_lats.size() * sizeof(int32_t)));
+        MR1L_HIP(hipMemcpy(p.d_lds_lats, p.lds_lats.data(), p.lds_lats.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice));
+    }
+    const size_t esz = p.dtype == MR1L_C128 ? 16 : 8;
+    if (!p.big_lats.empty()) {
+        MR1L_HIP(hipMalloc(&p.d_big_lats, p.big_lats.size() * sizeof(int32_t)));
+        MR1L_HIP(hipMemcpy(p.d_big_lats, p.big_lats.data(), p.big_lats.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice));
+        p.fft_slots = std::min<int>((int)p.big_lats.size(), num_cus());
+        MR1L_HIP(hipMalloc(&p.d_fft_scratch, (size_t)p.fft_slots * 2 * (size_t)p.big_maxN * esz));
+    }
+    MR1L_HIP(hipMalloc(&p.d_nodes_scratch, (size_t)std::max<int64_t>(p.nodes, 1) * esz));
+    MR1L_HIP(hipMalloc(&p.d_det_tmp, sizeof(int64_t) * (size_t)p.F));
+    MR1L_HIP(hipMalloc(&p.d_setoff_default, 2 * sizeof(int64_t)));
+    MR1L_HIP(hipMalloc(&p.d_termoff_default, 2 * sizeof(int64_t)));
+    return MR1L_OK;
+}
+
+static void release(Plan *p)
+{
+    void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_spec, p->d_chirp, p->d_tw,
+                    p->d_lds_lats, p->d_big_lats, p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
+                    p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
+                    p->d_termoff_default};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+__global__ void k_set_pair(int64_t *dst, int64_t a, int64_t b)
+{
+    if (threadIdx.x == 0) { dst[0] = a; dst[1] = b; }
+}
+
+static int default_offsets(Plan &p, int64_t *dst, int64_t n)
+{
+    hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(64), 0, p.stream, dst, (int64_t)0, n);
+    MR1L_LAUNCH_CHECK();
+    return MR1L_OK;
+}
+
+static int grow(Plan &p, void **ptr, int64_t bytes, int64_t &have)
+{
+    if (have >= bytes && *ptr) return MR1L_OK;
+    if (p.capturing) return fail(MR1L_E_ARG, "scratch must be sized before graph capture (run the call once)");
+    if (*ptr) (void)hipFree(*ptr);
+    *ptr = nullptr;
+    MR1L_HIP(hipMalloc(ptr, (size_t)std::max<int64_t>(bytes, 16)));
+    have = bytes;
+    return MR1L_OK;
+}
+
+}  // namespace mr1l
+
+using namespace mr1l;
+
+struct mr1l_plan_s : public Plan {
+    int64_t h_bytes = 0, w_bytes = 0, m_bytes = 0, med_bytes = 0, pos_bytes = 0;
+};
+
+struct mr1l_graph_s : public Graph {};
+
+extern "C" {
+
+int mr1l_version(void) { return 10000; }
+
+const char *mr1l_last_error(void) { return g_err.c_str(); }
+
+int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int64_t *M, const int64_t *z,
+                     int32_t dtype, void *stream)
+{
+    if (!out) return fail(MR1L_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (d < 1 || d > kMaxD) return fail(MR1L_E_ARG, "d must be in [1, 64]");
+    if (F < 1) return fail(MR1L_E_ARG, "F must be >= 1");
+    if (L < 1 || L > kMaxL) return fail(MR1L_E_ARG, "L must be in [1, 32]");
+    if (dtype != MR1L_C128 && dtype != MR1L_C64) return fail(MR1L_E_ARG, "dtype must be MR1L_C128 or MR1L_C64");
+    if (!M || !z) return fail(MR1L_E_ARG, "M or z is NULL");
+    const int64_t nl = (int64_t)F * L;
+    for (int64_t i = 0; i < nl; ++i) {
+        if (M[i] < 2 || M[i] >= (int64_t(1) << 23))
+            return fail(MR1L_E_ARG, "lattice size out of range [2, 2^23): " + std::to_string(M[i]));
+        if (!is_prime_u64((uint64_t)M[i]))
+            return fail(MR1L_E_NOT_PRIME, "lattice size is not prime: " + std::to_string(M[i]));
+        for (int u = 0; u < d; ++u) {
+            const int64_t v = z[i * d + u];
+            if (v < 0 || v >= M[i]) return fail(MR1L_E_ARG, "generating vector entry outside [0, M)");
+        }
+    }
+    static bool attrs_done = false;
+    if (!attrs_done) {
+        fft_init_attrs();
+        extract_init_attrs();
+        attrs_done = true;
+    }
+    mr1l_plan_s *p = new (std::nothrow) mr1l_plan_s();
+    if (!p) return fail(MR1L_E_NOMEM, "host allocation failed");
+    p->d = d; p->F = F; p->L = L; p->dtype = dtype;
+    p->stream = (hipStream_t)stream;
+    p->M.assign(M, M + nl);
+    p->z.assign(z, z + nl * d);
+    int rc = dtype == MR1L_C128 ? build_tables<double>(*p) : build_tables<float>(*p);
+    if (rc == MR1L_OK) rc = upload(*p);
+    if (rc == MR1L_OK) rc = fft_prepare_spectra(*p);
+    if (rc != MR1L_OK) {
+        std::string keep = g_err;
+        release(p);
+        g_err = keep;
+        return rc;
+    }
+    *out = p;
+    return MR1L_OK;
+}
+
+int mr1l_plan_destroy(mr1l_plan p)
+{
+    if (!p) return MR1L_OK;
+    (void)hipStreamSynchronize(p->stream);
+    release(p);
+    return MR1L_OK;
+}
+
+int64_t mr1l_plan_nodes(mr1l_plan p) { return p ? p->nodes : -1; }
+
+int mr1l_plan_set_stream(mr1l_plan p, void *stream)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    p->stream = (hipStream_t)stream;
+    return MR1L_OK;
+}
+
+int mr1l_plan_set_z(mr1l_plan p, const int64_t *z)
+{
+    if (!p || !z) return fail(MR1L_E_ARG, "plan or z is NULL");
+    const int64_t nl = (int64_t)p->F * p->L;
+    for (int64_t i = 0; i < nl; ++i)
+        for (int u = 0; u < p->d; ++u)
+            if (z[i * p->d + u] < 0 || z[i * p->d + u] >= p->M[i])
+                return fail(MR1L_E_ARG, "generating vector entry outside [0, M)");
+    p->z.assign(z, z + nl * p->d);
+    std::vector<int32_t> z32(p->z.begin(), p->z.end());
+    MR1L_HIP(hipMemcpyAsync(p->d_z32, z32.data(), z32.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+    MR1L_HIP(hipMemcpyAsync(p->d_z64, p->z.data(), p->z.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                            p->stream));
+    MR1L_HIP(hipStreamSynchronize(p->stream));
+    return MR1L_OK;
+}
+
+int mr1l_sample(mr1l_plan p, int32_t d_poly, const int64_t *term_off, int64_t n_terms, const int64_t *freq,
+                const void *coef, const uint32_t *anchor, void *f, int32_t mode)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (d_poly < p->d || d_poly > kMaxD) return fail(MR1L_E_ARG, "d_poly must be in [d, 64]");
+    if (n_terms < 0 || (n_terms > 0 && (!freq || !coef)) || !f) return fail(MR1L_E_ARG, "null buffer");
+    if (d_poly > p->d && !anchor) return fail(MR1L_E_ARG, "anchors required when d_poly > d");
+    if (mode < 0 || mode > 2) return fail(MR1L_E_ARG, "mode must be 0, 1 or 2");
+    if (!term_off) {
+        if (p->F != 1) return fail(MR1L_E_ARG, "term_off required when F > 1");
+        int rc = default_offsets(*p, p->d_termoff_default, n_terms);
+        if (rc) return rc;
+        term_off = p->d_termoff_default;
+    }
+    if (mode == 1)
+        for (auto m : p->M)
+            if (m > (int64_t(1) << 22)) mode = 2;
+    StageTimer tm(*p, MR1L_STAGE_SAMPLE);
+    return sample_run(*p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode);
+}
+
+int mr1l_fft(mr1l_plan p, const void *f, void *ghat, double theta, uint32_t *nz_bitmap)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (!f || !ghat || f == ghat) return fail(MR1L_E_ARG, "f and ghat must be distinct device buffers");
+    if (!(theta >= 0.0)) return fail(MR1L_E_ARG, "theta must be >= 0");
+    StageTimer tm(*p, MR1L_STAGE_FFT);
+    return fft_run(*p, f, ghat, theta, nz_bitmap, FFT_FWD, 1.0);
+}
+
+int mr1l_hash_count(mr1l_plan p, int64_t n_total, const int64_t *set_off, const int64_t *freq, int32_t *hash,
+                    int32_t *counts)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (n_total < 0 || (n_total > 0 && !freq)) return fail(MR1L_E_ARG, "invalid candidate set");
+    if (!set_off) {
+        if (p->F != 1) return fail(MR1L_E_ARG, "set_off required when F > 1");
+        int rc = default_offsets(*p, p->d_setoff_default, n_total);
+        if (rc) return rc;
+        set_off = p->d_setoff_default;
+    }
+    return hash_count_run(*p, n_total, set_off, freq, hash, counts);
+}
+
+int mr1l_extract(mr1l_plan p, int64_t n_total, const int64_t *set_off, const int64_t *freq, const void *ghat,
+                 const uint32_t *nz_bitmap, const mr1l_extract_opts *o, const mr1l_extract_out *out)
+{
+    if (!p || !o || !out) return fail(MR1L_E_ARG, "plan, options or outputs NULL");
+    if (n_total < 0 || (n_total > 0 && !freq) || !ghat || !nz_bitmap) return fail(MR1L_E_ARG, "null input buffer");
+    if (o->cap < 1 || o->cap > kMaxCap) return fail(MR1L_E_ARG, "cap must be in [1, 8192]");
+    if (o->s_cap < 1 || o->s_cap > o->cap) return fail(MR1L_E_ARG, "s_cap must be in [1, cap]");
+    if (!(o->theta >= 0.0)) return fail(MR1L_E_ARG, "theta must be >= 0");
+    if (o->vote_min < 0 || o->vote_min > p->L) return fail(MR1L_E_ARG, "vote_min must be in [0, L]");
+    if (!out->n_det || !out->det_idx || !out->det_coef || !out->n_out || !out->out_idx || !out->out_coef)
+        return fail(MR1L_E_ARG, "required output NULL");
+    if (!set_off) {
+        if (p->F != 1) return fail(MR1L_E_ARG, "set_off required when F > 1");
+        int rc = default_offsets(*p, p->d_setoff_default, n_total);
+        if (rc) return rc;
+        set_off = p->d_setoff_default;
+    }
+    const int32_t vmin = o->vote_min ? o->vote_min : (p->L + 1) / 2;
+    const int64_t F = p->F, cap = o->cap, L = p->L;
+    const size_t esz = p->dtype == MR1L_C128 ? 16 : 8;
+    int32_t *dh = out->det_hash;
+    double *dw = out->det_w;
+    uint32_t *dm = out->det_mask;
+    void *dmed = out->det_med;
+    int32_t *dpos = out->out_pos;
+    int rc = MR1L_OK;
+    if (!dh && (rc = grow(*p, (void **)&p->d_ex_hash, F * cap * L * 4, p->h_bytes))) return rc;
+    if (!dh) dh = p->d_ex_hash;
+    if (!dm && (rc = grow(*p, (void **)&p->d_ex_mask, F * cap * 4, p->m_bytes))) return rc;
+    if (!dm) dm = p->d_ex_mask;
+    if (!dpos && (rc = grow(*p, (void **)&p->d_ex_pos, F * o->s_cap * 4, p->pos_bytes))) return rc;
+    if (!dpos) dpos = p->d_ex_pos;
+    (void)dmed;
+    (void)esz;
+    {
+        StageTimer tm(*p, MR1L_STAGE_VOTE);
+        rc = vote_run(*p, n_total, set_off, freq, nz_bitmap, vmin, cap, out->n_det, out->det_idx, out->votes);
+    }
+    if (rc) return rc;
+    StageTimer tm(*p, MR1L_STAGE_TAIL);
+    return extract_tail_run(*p, n_total, set_off, freq, ghat, *o, *out, dh, dw, dm, dmed, dpos);
+}
+
+int mr1l_adjoint(mr1l_plan p, int64_t cap, int64_t s_cap, const int64_t *n_out, const int32_t *out_pos,
+                 const int32_t *det_hash, const double *det_w, const void *grad_out, void *grad_f)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (cap < 1 || cap > kMaxCap || s_cap < 1 || s_cap > cap) return fail(MR1L_E_ARG, "invalid cap/s_cap");
+    if (!n_out || !out_pos || !det_hash || !det_w || !grad_out || !grad_f)
+        return fail(MR1L_E_ARG, "null buffer (out_pos, det_hash and det_w of the extract call are required)");
+    return adjoint_run(*p, cap, s_cap, n_out, out_pos, det_hash, det_w, grad_out, grad_f);
+}
+
+int mr1l_graph_begin(mr1l_plan p)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (!p->stream) return fail(MR1L_E_ARG, "graph capture needs a non-default stream");
+    MR1L_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    p->capturing = true;
+    return MR1L_OK;
+}
+
+int mr1l_graph_end(mr1l_plan p, mr1l_graph *g)
+{
+    if (!p || !g) return fail(MR1L_E_ARG, "plan or graph pointer is NULL");
+    p->capturing = false;
+    mr1l_graph_s *G = new (std::nothrow) mr1l_graph_s();
+    if (!G) return fail(MR1L_E_NOMEM, "host allocation failed");
+    hipError_t e = hipStreamEndCapture(p->stream, &G->graph);
+    if (e != hipSuccess) {
+        delete G;
+        return fail(MR1L_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(G->graph);
+        delete G;
+        return fail(MR1L_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    *g = G;
+    return MR1L_OK;
+}
+
+int mr1l_graph_launch(mr1l_graph g, void *stream)
+{
+    if (!g) return fail(MR1L_E_ARG, "graph is NULL");
+    MR1L_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return MR1L_OK;
+}
+
+int mr1l_graph_destroy(mr1l_graph g)
+{
+    if (!g) return MR1L_OK;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return MR1L_OK;
+}
+
+int mr1l_profile(mr1l_plan p, int32_t enable)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (enable && p->capturing) return fail(MR1L_E_ARG, "cannot profile while recording a graph");
+    p->profiling = enable != 0;
+    return MR1L_OK;
+}
+
+int mr1l_profile_read(mr1l_plan p, double *ms, int64_t *count)
+{
+    if (!p || !ms || !count) return fail(MR1L_E_ARG, "null argument");
+    MR1L_HIP(hipStreamSynchronize(p->stream));
+    for (auto &e : p->prof) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e.second.first, e.second.second) == hipSuccess && e.first >= 0 &&
+            e.first < MR1L_NSTAGE) {
+            ms[e.first] += t;
+            count[e.first] += 1;
+        }
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    p->prof.clear();
+    return MR1L_OK;
+}
+
+int32_t mr1l_num_lattices(int64_t nJ, double c, double delta)
+{
+    if (nJ < 1 || !(c > 2.0) || !(delta > 0.0) || !(delta < 1.0)) return -1;
+    // eq. (4.2): a quarter of the Corollary 2.7 count
+    const double bound = 0.25 * (4.0 * c / ((c - 2.0) * std::log(c - 1.0))) * (std::log((double)nJ) - std::log(delta));
+    int32_t L = (int32_t)std::ceil(bound);
+    if (L < 1) L = 1;
+    if ((L & 1) == 0) ++L;
+    return L;
+}
+
+}  // extern "C"

@@ -1,0 +1,214 @@
+// Dimension-incremental driver: Step 2 of Algorithm 3 with Algorithm 4 as
+// the detection method (Section 3.2.2), the single-coordinate candidate sets
+// being the whole range [-N, N].
+//
+// Per step t = 2..d and repetition i = 1..r~:
+//   J_t = I^(1..t-1) x [-N, N]                (k_cartesian, lexicographic)
+//   L   = eq. (4.2) on |J_t|, every lattice of size M
+//   draws from SplitMix64 stream (seed, t, i): anchors, then generating vectors
+//   samples on the t-dimensional lattices with the anchors fixed (Step 2b)
+//   mr1l_fft + mr1l_extract with s~ (Step 2c)
+//   union of the detected tuples (Step 2d, sorted without repeats on the host)
+#include "mr1l_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+namespace mr1l {
+
+// SplitMix64 (Steele, Lea, Flood 2014): output n of seed S is the finaliser of
+// S + n * 0x9E3779B97F4A7C15.
+static uint64_t splitmix(uint64_t seed, uint64_t n)
+{
+    uint64_t x = seed + n * 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+
+struct Stream {
+    uint64_t seed, base, c = 0;
+    Stream(uint64_t s, int t, int i) : seed(s), base(((uint64_t)t * 64u + (uint64_t)i) << 24) {}
+    uint64_t next() { return splitmix(seed, base + (c++) + 1u); }
+    int64_t below(int64_t m) { return (int64_t)(((unsigned __int128)next() * (uint64_t)m) >> 64); }
+};
+
+__global__ void k_cartesian(const int64_t *__restrict__ prev, int64_t nprev, int tm1, int64_t N,
+                            int64_t *__restrict__ J)
+{
+    const int64_t K = 2 * N + 1;
+    const int64_t nJ = nprev * K;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nJ; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = q / K, b = q - a * K;
+        for (int u = 0; u < tm1; ++u) J[(int64_t)u * nJ + q] = prev[(int64_t)u * nprev + a];
+        J[(int64_t)tm1 * nJ + q] = b - N;
+    }
+}
+
+template <typename P> struct DevBuf {
+    P *p = nullptr;
+    int64_t n = 0;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    int need(int64_t cnt)
+    {
+        if (cnt <= n) return MR1L_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        MR1L_HIP(hipMalloc(&p, sizeof(P) * (size_t)std::max<int64_t>(cnt, 1)));
+        n = cnt;
+        return MR1L_OK;
+    }
+};
+
+struct PlanHolder {
+    mr1l_plan p = nullptr;
+    ~PlanHolder() { if (p) mr1l_plan_destroy(p); }
+};
+
+}  // namespace mr1l
+
+using namespace mr1l;
+
+extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, void *user,
+                            const int64_t *poly_freq, const void *poly_coef, int64_t poly_s, int64_t cap,
+                            int64_t *n_out, int64_t *freq_out, void *coef_out, int64_t *total_samples, void *stream)
+{
+    if (!prm || !n_out || !freq_out || !coef_out) return fail(MR1L_E_ARG, "null argument");
+    const mr1l_dimincr_params P = *prm;
+    if (P.d < 2 || P.d > kMaxD) return fail(MR1L_E_ARG, "d must be in [2, 64]");
+    if (P.N < 0 || P.s < 1 || P.s_local < P.s || P.r < 1) return fail(MR1L_E_ARG, "invalid N, s, s_local or r");
+    if (P.dtype != MR1L_C128 && P.dtype != MR1L_C64) return fail(MR1L_E_ARG, "invalid dtype");
+    if (!fn && (poly_s < 0 || (poly_s > 0 && (!poly_freq || !poly_coef))))
+        return fail(MR1L_E_ARG, "built-in sampler needs the polynomial");
+    if (cap < P.s) return fail(MR1L_E_CAPACITY, "cap below s");
+    const hipStream_t st = (hipStream_t)stream;
+    const int d = P.d;
+    const int64_t K = 2 * P.N + 1;
+    const size_t esz = P.dtype == MR1L_C128 ? 16 : 8;
+    *n_out = 0;
+    int64_t samples = 0;
+
+    // I^(1) = [-N, N], row-major tuples
+    std::vector<int64_t> prev(K);
+    for (int64_t a = 0; a < K; ++a) prev[a] = a - P.N;
+    int64_t nprev = K;
+    DevBuf<int64_t> dprev, dJ, n_det, det_idx, n_o, out_idx;
+    DevBuf<unsigned char> fbuf, gbuf, det_coef, out_coef;
+    DevBuf<uint32_t> bitmap, danc;
+
+    for (int t = 2; t <= d; ++t) {
+        const int rt = (t < d) ? P.r : 1;
+        const int64_t s_t = (t < d) ? P.s_local : P.s;
+        const int64_t nJ = nprev * K;
+        const int32_t L = mr1l_num_lattices(nJ, P.c, P.delta);
+        if (L < 1 || L > kMaxL) return fail(MR1L_E_ARG, "eq. (4.2) lattice count out of range");
+        int rc;
+        // previous tuples as SoA [t-1][nprev]
+        std::vector<int64_t> soa((size_t)(t - 1) * nprev);
+        for (int64_t a = 0; a < nprev; ++a)
+            for (int u = 0; u < t - 1; ++u) soa[(size_t)u * nprev + a] = prev[(size_t)a * (t - 1) + u];
+        if ((rc = dprev.need((int64_t)soa.size()))) return rc;
+        MR1L_HIP(hipMemcpyAsync(dprev.p, soa.data(), soa.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        if ((rc = dJ.need(nJ * t))) return rc;
+        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((nJ + 255) / 256, 4096));
+        hipLaunchKernelGGL(k_cartesian, dim3((unsigned)blocks), dim3(256), 0, st, dprev.p, nprev, t - 1, P.N, dJ.p);
+        MR1L_LAUNCH_CHECK();
+
+        std::vector<int64_t> Ms(L, P.M);
+        const int64_t nodes = (int64_t)L * P.M;
+        if ((rc = fbuf.need(nodes * esz)) || (rc = gbuf.need(nodes * esz)) || (rc = bitmap.need((nodes + 31) / 32)))
+            return rc;
+        const int64_t ecap = kMaxCap;
+        if ((rc = n_det.need(1)) || (rc = det_idx.need(ecap)) || (rc = det_coef.need(ecap * esz)) ||
+            (rc = n_o.need(1)) || (rc = out_idx.need(s_t)) || (rc = out_coef.need(s_t * esz)) ||
+            (rc = danc.need(std::max(1, d - t))))
+            return rc;
+
+        std::vector<int64_t> cur;   // row-major t-tuples
+        std::vector<unsigned char> cur_coef;
+        PlanHolder plan;
+        for (int i = 1; i <= rt; ++i) {
+            Stream rs(P.seed, t, i);
+            std::vector<uint32_t> anc(std::max(1, d - t), 0u);
+            for (int u = t; u < d; ++u) anc[u - t] = (uint32_t)(rs.next() >> 32);
+            std::vector<int64_t> z((size_t)L * t);
+            for (int l = 0; l < L; ++l)
+                for (int u = 0; u < t; ++u) z[(size_t)l * t + u] = rs.below(P.M);
+            if (!plan.p) {
+                if ((rc = mr1l_plan_create(&plan.p, t, 1, L, Ms.data(), z.data(), P.dtype, stream))) return rc;
+            } else if ((rc = mr1l_plan_set_z(plan.p, z.data()))) {
+                return rc;
+            }
+            MR1L_HIP(hipMemcpyAsync(danc.p, anc.data(), anc.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+            if (fn) {
+                if (fn(user, t, L, Ms.data(), z.data(), anc.data(), fbuf.p, stream) != 0)
+                    return fail(MR1L_E_ARG, "sampling callback failed");
+            } else if ((rc = mr1l_sample(plan.p, d, nullptr, poly_s, poly_freq, poly_coef, d > t ? danc.p : nullptr,
+                                         fbuf.p, 1))) {
+                return rc;
+            }
+            samples += nodes;
+            if ((rc = mr1l_fft(plan.p, fbuf.p, gbuf.p, P.theta, bitmap.p))) return rc;
+            mr1l_extract_opts o{P.theta, 0, P.postproc, s_t, ecap};
+            mr1l_extract_out ex{};
+            ex.n_det = n_det.p; ex.det_idx = det_idx.p; ex.det_coef = det_coef.p;
+            ex.n_out = n_o.p; ex.out_idx = out_idx.p; ex.out_coef = out_coef.p;
+            if ((rc = mr1l_extract(plan.p, nJ, nullptr, dJ.p, gbuf.p, bitmap.p, &o, &ex))) return rc;
+            int64_t h_ndet = 0, h_nout = 0;
+            MR1L_HIP(hipMemcpyAsync(&h_ndet, n_det.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            MR1L_HIP(hipMemcpyAsync(&h_nout, n_o.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            MR1L_HIP(hipStreamSynchronize(st));
+            if (h_ndet > ecap) return fail(MR1L_E_CAPACITY, "detected set exceeds 8192 entries in one step");
+            std::vector<int64_t> oi(h_nout);
+            std::vector<unsigned char> oc(h_nout * esz);
+            if (h_nout > 0) {
+                MR1L_HIP(hipMemcpy(oi.data(), out_idx.p, h_nout * sizeof(int64_t), hipMemcpyDeviceToHost));
+                MR1L_HIP(hipMemcpy(oc.data(), out_coef.p, h_nout * esz, hipMemcpyDeviceToHost));
+            }
+            for (int64_t q = 0; q < h_nout; ++q) {
+                const int64_t a = oi[q] / K, b = oi[q] - a * K;
+                for (int u = 0; u < t - 1; ++u) cur.push_back(prev[(size_t)a * (t - 1) + u]);
+                cur.push_back(b - P.N);
+            }
+            if (t == d) cur_coef = oc;
+            if ((int64_t)(cur.size() / t) > cap) return fail(MR1L_E_CAPACITY, "union exceeds cap");
+        }
+        const int64_t ncur = (int64_t)(cur.size() / t);
+        std::vector<int64_t> order(ncur);
+        for (int64_t q = 0; q < ncur; ++q) order[q] = q;
+        auto lex = [&](int64_t x, int64_t y) {
+            for (int u = 0; u < t; ++u) {
+                const int64_t a = cur[(size_t)x * t + u], b = cur[(size_t)y * t + u];
+                if (a != b) return a < b;
+            }
+            return x < y;
+        };
+        std::sort(order.begin(), order.end(), lex);
+        if (t == d) {
+            for (int64_t q = 0; q < ncur; ++q) {
+                for (int u = 0; u < d; ++u) freq_out[q * d + u] = cur[(size_t)order[q] * d + u];
+                std::memcpy((unsigned char *)coef_out + q * esz, cur_coef.data() + order[q] * esz, esz);
+            }
+            *n_out = ncur;
+        } else {
+            std::vector<int64_t> next;
+            for (int64_t q = 0; q < ncur; ++q) {
+                const int64_t *row = &cur[(size_t)order[q] * t];
+                if (!next.empty() && std::equal(row, row + t, next.end() - t)) continue;
+                next.insert(next.end(), row, row + t);
+            }
+            prev.swap(next);
+            nprev = (int64_t)(prev.size() / t);
+            if (nprev == 0) {
+                *n_out = 0;
+                if (total_samples) *total_samples = samples;
+                return MR1L_OK;   // nothing detected: the result is empty
+            }
+        }
+    }
+    if (total_samples) *total_samples = samples;
+    return MR1L_OK;
+}

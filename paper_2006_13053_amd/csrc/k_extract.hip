@@ -1,0 +1,375 @@
+// After the vote: ordered detected set, singleton masks, coefficients and the
+// output limitation.
+//
+//  k_sort_det    detected set of each function in ascending candidate order
+//                (one workgroup per function, bitonic sort in LDS).
+//  k_det_hash    buckets h_l(k) of every detected candidate.
+//  k_singleton   occupancy of each bucket by the detected set, one workgroup
+//                per lattice with an LDS histogram; bit l of mask[q] is set
+//                when candidate q is alone in its bucket (the sets of
+//                Remark 2.9).
+//  k_combine     medians of the real and imaginary parts of the L lattice
+//                values (eq. (2.10); even L: mean of the two middle order
+//                statistics; order by value, ties by lattice index) and the
+//                singleton average of Remark 2.9, plus the weights of the
+//                coefficient as a real-linear map of the lattice values.
+//  k_limit       Algorithm 4: |p| >= theta, descending modulus, ties by
+//                ascending candidate index, first s~ (bitonic sort in LDS).
+//  k_adjoint_scatter  transpose of the gather/combination: coefficient
+//                gradients into buckets (the inverse lattice DFT follows).
+#include "mr1l_internal.h"
+
+namespace mr1l {
+
+constexpr int kSortThreads = 1024;
+
+__device__ __forceinline__ int64_t n_of(const int64_t *n_det, int f, int64_t cap)
+{
+    const int64_t n = n_det[f];
+    return n < cap ? n : cap;
+}
+
+// ------------------------------------------------------------------ sort detected
+__global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__restrict__ n_det, int64_t cap,
+                                                           int64_t *__restrict__ det_idx)
+{
+    __shared__ int64_t key[kMaxCap];
+    const int f = blockIdx.x;
+    const int n = (int)n_of(n_det, f, cap);
+    if (n <= 1) return;
+    int P = 1;
+    while (P < n) P <<= 1;
+    int64_t *src = det_idx + (int64_t)f * cap;
+    for (int i = threadIdx.x; i < P; i += kSortThreads) key[i] = (i < n) ? src[i] : INT64_MAX;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += kSortThreads) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const bool asc = (i & k) == 0;
+                    const int64_t a = key[i], b = key[ixj];
+                    if ((a > b) == asc) { key[i] = b; key[ixj] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += kSortThreads) src[i] = key[i];
+}
+
+// ------------------------------------------------------------------ hashes of detected
+__global__ __launch_bounds__(256) void k_det_hash(
+    const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int L, int d,
+    const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32, const int64_t *__restrict__ z64,
+    const int32_t *__restrict__ kbound, const int64_t *__restrict__ n_det, int64_t cap,
+    const int64_t *__restrict__ det_idx, int32_t *__restrict__ det_hash)
+{
+    const int f = blockIdx.y;
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n_of(n_det, f, cap)) return;
+    const int64_t ci = set_off[f] + det_idx[(int64_t)f * cap + q];
+    const int32_t kb = kbound[f];
+    int32_t lo[kMaxD];
+    bool fast = true;
+    for (int u = 0; u < d; ++u) {
+        const int64_t k = freq[(int64_t)u * n_total + ci];
+        lo[u] = (int32_t)k;
+        fast = fast && (k >= -kb) && (k <= kb);
+    }
+    for (int l = 0; l < L; ++l) {
+        const LatDesc ld = lat[f * L + l];
+        int32_t h;
+        if (fast) {
+            uint32_t s = ld.off32;
+            for (int u = 0; u < d; ++u) s += (uint32_t)__mul24(lo[u], z32[ld.z_off + u]);
+            h = (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m);
+        } else {
+            h = exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
+        }
+        det_hash[((int64_t)f * cap + q) * L + l] = h;
+    }
+}
+
+// ------------------------------------------------------------------ singletons
+constexpr int kHistBins = 40960;   // 160 KiB of int32 counters
+
+__global__ __launch_bounds__(1024) void k_singleton(const LatDesc *__restrict__ lat, int L,
+                                                    const int64_t *__restrict__ n_det, int64_t cap,
+                                                    const int32_t *__restrict__ det_hash,
+                                                    uint32_t *__restrict__ mask)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t *hist = reinterpret_cast<int32_t *>(smem);
+    const int l = blockIdx.x, f = blockIdx.y;
+    const int n = (int)n_of(n_det, f, cap);
+    if (n == 0) return;
+    const int M = lat[f * L + l].M;
+    const int32_t *hh = det_hash + (int64_t)f * cap * L;
+    for (int c0 = 0; c0 < M; c0 += kHistBins) {
+        const int c1 = min(M, c0 + kHistBins);
+        for (int i = threadIdx.x; i < c1 - c0; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            const int h = hh[(int64_t)q * L + l];
+            if (h >= c0 && h < c1) atomicAdd(hist + (h - c0), 1);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            const int h = hh[(int64_t)q * L + l];
+            if (h >= c0 && h < c1 && hist[h - c0] == 1) atomicOr(mask + (int64_t)f * cap + q, 1u << l);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ combine
+// Median position(s) by rank: rank_l = #{m : (v_m, m) < (v_l, l)}.
+template <typename T, int LMAX>
+__device__ __forceinline__ void median_sel(const T *v, int L, T &med, int &s0, int &s1)
+{
+    const int want0 = (L - 1) / 2, want1 = L / 2;
+    s0 = 0; s1 = 0;
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+        if (l < L) {
+            int rank = 0;
+#pragma unroll
+            for (int m = 0; m < LMAX; ++m)
+                if (m < L) rank += (v[m] < v[l]) || (v[m] == v[l] && m < l);
+            if (rank == want0) s0 = l;
+            if (rank == want1) s1 = l;
+        }
+    }
+    T a = 0, b = 0;
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+        if (l == s0) a = v[l];
+        if (l == s1) b = v[l];
+    }
+    med = (L & 1) ? a : T(0.5) * (a + b);
+}
+
+template <typename T, int LMAX>
+__global__ __launch_bounds__(256) void k_combine(
+    const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ n_det, int64_t cap,
+    const int32_t *__restrict__ det_hash, const uint32_t *__restrict__ mask,
+    const typename cvec<T>::type *__restrict__ ghat, int postproc,
+    typename cvec<T>::type *__restrict__ det_coef, typename cvec<T>::type *__restrict__ det_med,
+    double *__restrict__ det_w)
+{
+    using V = typename cvec<T>::type;
+    const int f = blockIdx.y;
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n_of(n_det, f, cap)) return;
+    const int64_t e = (int64_t)f * cap + q;
+    T vr[LMAX], vi[LMAX];
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+        vr[l] = 0; vi[l] = 0;
+        if (l < L) {
+            const V g = ghat[lat[f * L + l].node_off + det_hash[e * L + l]];
+            vr[l] = g.x; vi[l] = g.y;
+        }
+    }
+    T mr, mi;
+    int r0, r1, i0, i1;
+    median_sel<T, LMAX>(vr, L, mr, r0, r1);
+    median_sel<T, LMAX>(vi, L, mi, i0, i1);
+    const uint32_t mk = mask[e];
+    const int na = __popc(mk);
+    V med; med.x = mr; med.y = mi;
+    if (det_med) det_med[e] = med;
+    V out = med;
+    const bool avg = postproc && na > 0;
+    if (avg) {
+        T sr = 0, si = 0;
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l)
+            if (l < L && ((mk >> l) & 1u)) { sr += vr[l]; si += vi[l]; }
+        out.x = sr / (T)na;
+        out.y = si / (T)na;
+    }
+    det_coef[e] = out;
+    if (det_w) {
+        double *w = det_w + e * L * 2;
+        for (int l = 0; l < L; ++l) {
+            double wr = 0.0, wi = 0.0;
+            if (avg) {
+                if ((mk >> l) & 1u) { wr = 1.0 / na; wi = 1.0 / na; }
+            } else if (L & 1) {
+                wr = (l == r0) ? 1.0 : 0.0;
+                wi = (l == i0) ? 1.0 : 0.0;
+            } else {
+                wr = 0.5 * ((l == r0) + (l == r1));
+                wi = 0.5 * ((l == i0) + (l == i1));
+            }
+            w[2 * l] = wr;
+            w[2 * l + 1] = wi;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ limit (Algorithm 4)
+template <typename T>
+__global__ __launch_bounds__(kSortThreads) void k_limit(
+    const int64_t *__restrict__ n_det, int64_t cap, const int64_t *__restrict__ det_idx,
+    const typename cvec<T>::type *__restrict__ det_coef, T th2, int64_t s_cap, int64_t *__restrict__ n_out,
+    int64_t *__restrict__ out_idx, typename cvec<T>::type *__restrict__ out_coef, int32_t *__restrict__ out_pos)
+{
+    using V = typename cvec<T>::type;
+    __shared__ uint64_t key[kMaxCap];
+    __shared__ int32_t pos[kMaxCap];
+    __shared__ int npass;
+    const int f = blockIdx.x;
+    const int n = (int)n_of(n_det, f, cap);
+    if (threadIdx.x == 0) npass = 0;
+    int P = 1;
+    while (P < n) P <<= 1;
+    __syncthreads();
+    const V *dc = det_coef + (int64_t)f * cap;
+    for (int i = threadIdx.x; i < P; i += kSortThreads) {
+        uint64_t k = ~0ull;
+        int32_t ps = INT32_MAX;
+        if (i < n) {
+            const V c = dc[i];
+            const T m2 = c.x * c.x + c.y * c.y;
+            if (m2 >= th2) {
+                const double md = (double)m2;
+                k = ~(uint64_t)__double_as_longlong(md);   // m2 >= 0: bits are monotonic
+                ps = i;
+                atomicAdd(&npass, 1);
+            }
+        }
+        key[i] = k;
+        pos[i] = ps;
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += kSortThreads) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const bool asc = (i & k) == 0;
+                    const uint64_t a = key[i], b = key[ixj];
+                    const int32_t pa = pos[i], pb = pos[ixj];
+                    const bool gt = (a > b) || (a == b && pa > pb);
+                    if (gt == asc) {
+                        key[i] = b; key[ixj] = a;
+                        pos[i] = pb; pos[ixj] = pa;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int64_t no = min((int64_t)npass, s_cap);
+    if (threadIdx.x == 0) n_out[f] = no;
+    for (int o = threadIdx.x; o < no; o += kSortThreads) {
+        const int q = pos[o];
+        out_idx[(int64_t)f * s_cap + o] = det_idx[(int64_t)f * cap + q];
+        out_coef[(int64_t)f * s_cap + o] = dc[q];
+        if (out_pos) out_pos[(int64_t)f * s_cap + o] = q;
+    }
+}
+
+// ------------------------------------------------------------------ adjoint scatter
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjoint_scatter(
+    const LatDesc *__restrict__ lat, int L, int64_t cap, int64_t s_cap, const int64_t *__restrict__ n_out,
+    const int32_t *__restrict__ out_pos, const int32_t *__restrict__ det_hash, const double *__restrict__ det_w,
+    const typename cvec<T>::type *__restrict__ grad, T *__restrict__ gbar)
+{
+    const int f = blockIdx.y;
+    const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (o >= n_out[f]) return;
+    const auto g = grad[(int64_t)f * s_cap + o];
+    const int64_t e = (int64_t)f * cap + out_pos[(int64_t)f * s_cap + o];
+    for (int l = 0; l < L; ++l) {
+        const double wr = det_w[(e * L + l) * 2], wi = det_w[(e * L + l) * 2 + 1];
+        if (wr == 0.0 && wi == 0.0) continue;
+        const int64_t node = lat[f * L + l].node_off + det_hash[e * L + l];
+        if (wr != 0.0) unsafeAtomicAdd(gbar + 2 * node, (T)(wr * (double)g.x));
+        if (wi != 0.0) unsafeAtomicAdd(gbar + 2 * node + 1, (T)(wi * (double)g.y));
+    }
+}
+
+// ------------------------------------------------------------------ host
+template <typename T>
+static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, const int32_t *det_hash,
+                          const uint32_t *mask, const void *ghat, int postproc, void *det_coef, void *det_med,
+                          double *det_w)
+{
+    using V = typename cvec<T>::type;
+    dim3 grid((unsigned)((cap + 255) / 256), (unsigned)p.F), blk(256);
+#define MR1L_COMB(LM)                                                                                       \
+    hipLaunchKernelGGL((k_combine<T, LM>), grid, blk, 0, p.stream, p.d_lat, p.L, n_det, cap, det_hash, mask, \
+                       (const V *)ghat, postproc, (V *)det_coef, (V *)det_med, det_w)
+    if (p.L <= 8) MR1L_COMB(8);
+    else if (p.L <= 16) MR1L_COMB(16);
+    else MR1L_COMB(32);
+#undef MR1L_COMB
+    MR1L_LAUNCH_CHECK();
+    return MR1L_OK;
+}
+
+void extract_init_attrs()
+{
+    (void)hipFuncSetAttribute((const void *)k_singleton, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kHistBins * (int)sizeof(int32_t));
+}
+
+int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, const void *ghat,
+                     const mr1l_extract_opts &o, const mr1l_extract_out &out, int32_t *det_hash, double *det_w,
+                     uint32_t *det_mask, void *det_med, int32_t *out_pos)
+{
+    const int64_t cap = o.cap;
+    hipLaunchKernelGGL(k_sort_det, dim3(p.F), dim3(kSortThreads), 0, p.stream, out.n_det, cap, out.det_idx);
+    MR1L_LAUNCH_CHECK();
+    dim3 gq((unsigned)((cap + 255) / 256), (unsigned)p.F);
+    hipLaunchKernelGGL(k_det_hash, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat, p.d_z32,
+                       p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
+    MR1L_LAUNCH_CHECK();
+    int rc = launch_fill_u32(det_mask, (int64_t)p.F * cap, 0u, p.stream);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_singleton, dim3(p.L, p.F), dim3(1024), kHistBins * sizeof(int32_t), p.stream, p.d_lat,
+                       p.L, out.n_det, cap, det_hash, det_mask);
+    MR1L_LAUNCH_CHECK();
+    if (p.dtype == MR1L_C128)
+        rc = combine_launch<double>(p, out.n_det, cap, det_hash, det_mask, ghat, o.postproc, out.det_coef,
+                                    det_med, det_w);
+    else
+        rc = combine_launch<float>(p, out.n_det, cap, det_hash, det_mask, ghat, o.postproc, out.det_coef,
+                                   det_med, det_w);
+    if (rc) return rc;
+    if (p.dtype == MR1L_C128) {
+        hipLaunchKernelGGL(k_limit<double>, dim3(p.F), dim3(kSortThreads), 0, p.stream, out.n_det, cap,
+                           out.det_idx, (const double2 *)out.det_coef, o.theta * o.theta, o.s_cap, out.n_out,
+                           out.out_idx, (double2 *)out.out_coef, out_pos);
+    } else {
+        hipLaunchKernelGGL(k_limit<float>, dim3(p.F), dim3(kSortThreads), 0, p.stream, out.n_det, cap,
+                           out.det_idx, (const float2 *)out.det_coef, (float)(o.theta * o.theta), o.s_cap,
+                           out.n_out, out.out_idx, (float2 *)out.out_coef, out_pos);
+    }
+    MR1L_LAUNCH_CHECK();
+    return MR1L_OK;
+}
+
+int adjoint_run(Plan &p, int64_t cap, int64_t s_cap, const int64_t *n_out, const int32_t *out_pos,
+                const int32_t *det_hash, const double *det_w, const void *grad_out, void *grad_f)
+{
+    const size_t esz = p.dtype == MR1L_C128 ? 16 : 8;
+    int rc = launch_fill_bytes(p.d_nodes_scratch, (int64_t)(p.nodes * esz), p.stream);
+    if (rc) return rc;
+    dim3 grid((unsigned)((s_cap + 255) / 256), (unsigned)p.F), blk(256);
+    if (p.dtype == MR1L_C128)
+        hipLaunchKernelGGL(k_adjoint_scatter<double>, grid, blk, 0, p.stream, p.d_lat, p.L, cap, s_cap, n_out,
+                           out_pos, det_hash, det_w, (const double2 *)grad_out, (double *)p.d_nodes_scratch);
+    else
+        hipLaunchKernelGGL(k_adjoint_scatter<float>, grid, blk, 0, p.stream, p.d_lat, p.L, cap, s_cap, n_out,
+                           out_pos, det_hash, det_w, (const float2 *)grad_out, (float *)p.d_nodes_scratch);
+    MR1L_LAUNCH_CHECK();
+    return fft_run(p, p.d_nodes_scratch, grad_f, 0.0, nullptr, FFT_INV, 1.0);
+}
+
+}  // namespace mr1l

@@ -1,0 +1,221 @@
+// Samples of a sparse trigonometric polynomial (eq. (2.2)) at rank-1 lattice
+// nodes x_j = j z_l / M_l mod 1 (eq. (2.1)), with optional fixed anchor
+// coordinates x'_u = a_u / 2^32 for u >= d (the embedding of Algorithm 3).
+//
+// For term k: k . x_j = (j h_l(k) mod M_l) / M_l + (sum_{u>=d} k_u a_u mod 2^32) / 2^32,
+// both reduced exactly in integers.  The anchor factor is folded into the
+// coefficient once per term.
+//   direct  one thread per node sums all terms of its function; the phase
+//           e^{2 pi i r / M} comes from a two-level table (r = hi S + lo) in LDS.
+//   bucket  the aliasing formula eq. (2.4): coefficients are summed into the
+//           buckets h_l(k) (atomics), then f_l[j] = sum_h B[h] e^{2 pi i j h / M}
+//           is an inverse lattice DFT (scaled by M).
+#include "mr1l_internal.h"
+
+namespace mr1l {
+
+__device__ __forceinline__ int func_of_terms(const int64_t *off, int F, int64_t i)
+{
+    int lo = 0, hi = F;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Per term: anchored coefficient and buckets in all lattices of its function.
+template <typename T>
+__global__ __launch_bounds__(256) void k_term_prep(
+    const int64_t *__restrict__ freq, int64_t n_terms, const int64_t *__restrict__ term_off, int F, int L, int d,
+    int d_poly, const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32, const int64_t *__restrict__ z64,
+    const int32_t *__restrict__ kbound, const typename cvec<T>::type *__restrict__ coef,
+    const uint32_t *__restrict__ anchor, typename cvec<T>::type *__restrict__ cterm, int32_t *__restrict__ thash)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_terms;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int f = func_of_terms(term_off, F, t);
+        auto c = coef[t];
+        if (d_poly > d) {
+            uint32_t acc = 0;
+            for (int u = d; u < d_poly; ++u)
+                acc += (uint32_t)freq[(int64_t)u * n_terms + t] * anchor[(int64_t)f * (d_poly - d) + (u - d)];
+            double sn, cs;
+            sincospi((double)acc * 4.656612873077392578125e-10, &sn, &cs);  // acc / 2^31
+            const T cr = c.x, ci = c.y;
+            c.x = (T)(cr * cs - ci * sn);
+            c.y = (T)(cr * sn + ci * cs);
+        }
+        cterm[t] = c;
+        const int32_t kb = kbound[f];
+        int32_t lo[kMaxD];
+        bool fast = true;
+        for (int u = 0; u < d; ++u) {
+            const int64_t k = freq[(int64_t)u * n_terms + t];
+            lo[u] = (int32_t)k;
+            fast = fast && (k >= -kb) && (k <= kb);
+        }
+        for (int l = 0; l < L; ++l) {
+            const LatDesc ld = lat[f * L + l];
+            int32_t h;
+            if (fast) {
+                uint32_t s = ld.off32;
+                for (int u = 0; u < d; ++u) s += (uint32_t)__mul24(lo[u], z32[ld.z_off + u]);
+                h = (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m);
+            } else {
+                h = exact_bucket(freq + t, n_terms, d, z64 + ld.z_off, ld.M);
+            }
+            thash[(int64_t)l * n_terms + t] = h;
+        }
+    }
+}
+
+constexpr int kTermTile = 256;
+constexpr int kPhaseTab = 4096;   // entries of the two-level phase table (both levels)
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample_direct(
+    const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ term_off, int64_t n_terms,
+    const typename cvec<T>::type *__restrict__ cterm, const int32_t *__restrict__ thash,
+    typename cvec<T>::type *__restrict__ out)
+{
+    using V = typename cvec<T>::type;
+    __shared__ V tab[kPhaseTab];
+    __shared__ int32_t sh[kTermTile];
+    __shared__ V sc[kTermTile];
+    const int li = blockIdx.y;
+    const LatDesc ld = lat[li];
+    const int f = li / L, l = li - f * L;
+    const int M = ld.M;
+    // two-level table of e^{2 pi i r / M}: S = 2^shift >= sqrt(M)
+    int shift = 0;
+    while ((1 << (2 * shift)) < M) ++shift;
+    const int S = 1 << shift;
+    const int nhi = (M + S - 1) / S;
+    for (int i = threadIdx.x; i < S + nhi; i += blockDim.x) {
+        const int64_t r = i < S ? i : (int64_t)(i - S) * S;
+        double sn, cs;
+        sincospi(2.0 * (double)r / (double)M, &sn, &cs);
+        V v; v.x = (T)cs; v.y = (T)sn;
+        tab[i] = v;
+    }
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t0 = term_off[f], t1 = term_off[f + 1];
+    const double invM = 1.0 / (double)M;
+    T ar = 0, ai = 0;
+    for (int64_t tb = t0; tb < t1; tb += kTermTile) {
+        __syncthreads();
+        const int cnt = (int)min<int64_t>(kTermTile, t1 - tb);
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+            sh[i] = thash[(int64_t)l * n_terms + tb + i];
+            sc[i] = cterm[tb + i];
+        }
+        __syncthreads();
+        if (j < M) {
+            for (int i = 0; i < cnt; ++i) {
+                // r = (j h) mod M, j h < 2^46 is exact in double
+                const double pr = (double)j * (double)sh[i];
+                int64_t q = (int64_t)(pr * invM);
+                int64_t r = (int64_t)pr - q * M;
+                if (r < 0) r += M;
+                if (r >= M) r -= M;
+                const V a = tab[r & (S - 1)], b = tab[S + (r >> shift)];
+                const T er = a.x * b.x - a.y * b.y, ei = a.x * b.y + a.y * b.x;
+                const V c = sc[i];
+                ar += c.x * er - c.y * ei;
+                ai += c.x * ei + c.y * er;
+            }
+        }
+    }
+    if (j < M) {
+        V o; o.x = ar; o.y = ai;
+        out[ld.node_off + j] = o;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample_scatter(
+    const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ term_off, int F, int64_t n_terms,
+    const typename cvec<T>::type *__restrict__ cterm, const int32_t *__restrict__ thash, T *__restrict__ buckets)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_terms;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int f = func_of_terms(term_off, F, t);
+        const auto c = cterm[t];
+        for (int l = 0; l < L; ++l) {
+            const int64_t node = lat[f * L + l].node_off + thash[(int64_t)l * n_terms + t];
+            unsafeAtomicAdd(buckets + 2 * node, c.x);
+            unsafeAtomicAdd(buckets + 2 * node + 1, c.y);
+        }
+    }
+}
+
+template <typename T>
+static int sample_impl(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms, const int64_t *freq,
+                       const void *coef, const uint32_t *anchor, void *f, int32_t mode, void *cterm,
+                       int32_t *thash)
+{
+    using V = typename cvec<T>::type;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n_terms + 255) / 256, (int64_t)num_cus() * 16));
+    if (n_terms > 0) {
+        hipLaunchKernelGGL(k_term_prep<T>, dim3((unsigned)blocks), dim3(256), 0, p.stream, freq, n_terms, term_off,
+                           p.F, p.L, p.d, d_poly, p.d_lat, p.d_z32, p.d_z64, p.d_kb, (const V *)coef, anchor,
+                           (V *)cterm, thash);
+        MR1L_LAUNCH_CHECK();
+    }
+    if (mode == 1) {
+        int32_t maxM = 0;
+        for (auto m : p.M) maxM = std::max<int32_t>(maxM, (int32_t)m);
+        dim3 grid((unsigned)((maxM + 255) / 256), (unsigned)(p.F * p.L));
+        hipLaunchKernelGGL(k_sample_direct<T>, grid, dim3(256), 0, p.stream, p.d_lat, p.L, term_off, n_terms,
+                           (const V *)cterm, thash, (V *)f);
+        MR1L_LAUNCH_CHECK();
+        return MR1L_OK;
+    }
+    int rc = launch_fill_bytes(p.d_nodes_scratch, p.nodes * (int64_t)sizeof(V), p.stream);
+    if (rc) return rc;
+    if (n_terms > 0) {
+        hipLaunchKernelGGL(k_sample_scatter<T>, dim3((unsigned)blocks), dim3(256), 0, p.stream, p.d_lat, p.L,
+                           term_off, p.F, n_terms, (const V *)cterm, thash, (T *)p.d_nodes_scratch);
+        MR1L_LAUNCH_CHECK();
+    }
+    return fft_run(p, p.d_nodes_scratch, f, 0.0, nullptr, FFT_INV, -1.0);   // times M
+}
+
+static int ensure(void **ptr, int64_t *have, int64_t want)
+{
+    if (*have >= want) return MR1L_OK;
+    if (*ptr) (void)hipFree(*ptr);
+    *ptr = nullptr;
+    *have = 0;
+    MR1L_HIP(hipMalloc(ptr, (size_t)std::max<int64_t>(want, 16)));
+    *have = want;
+    return MR1L_OK;
+}
+
+// plan-owned term scratch (grown outside graph capture only)
+static thread_local void *g_cterm = nullptr;
+static thread_local int64_t g_cterm_n = 0;
+static thread_local void *g_thash = nullptr;
+static thread_local int64_t g_thash_n = 0;
+
+int sample_run(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms, const int64_t *freq,
+               const void *coef, const uint32_t *anchor, void *f, int32_t mode)
+{
+    const int64_t esz = p.dtype == MR1L_C128 ? 16 : 8;
+    if (mode == 0) {
+        // direct when a function has few terms per node; buckets otherwise
+        mode = (n_terms / std::max(1, p.F) > 2048) ? 2 : 1;
+    }
+    int rc = ensure(&g_cterm, &g_cterm_n, std::max<int64_t>(1, n_terms) * esz);
+    if (rc) return rc;
+    rc = ensure(&g_thash, &g_thash_n, std::max<int64_t>(1, n_terms) * 4 * p.L);
+    if (rc) return rc;
+    if (p.dtype == MR1L_C128)
+        return sample_impl<double>(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, g_cterm,
+                                   (int32_t *)g_thash);
+    return sample_impl<float>(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, g_cterm,
+                              (int32_t *)g_thash);
+}
+
+}  // namespace mr1l

@@ -1,0 +1,192 @@
+// Internal declarations of the mr1l library (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mr1l.h"
+
+namespace mr1l {
+
+// ---------------------------------------------------------------- limits
+constexpr int kMaxL = 32;          // lattices per function (masks are uint32)
+constexpr int kMaxD = 64;          // lattice dimensions
+constexpr int kMaxCap = 8192;      // detected-list capacity per function
+constexpr int kFftThreads = 1024;  // threads of a DFT workgroup
+constexpr int kLdsBytes = 163840;  // LDS of one gfx950 workgroup
+
+// Largest transform held whole in LDS (re and im planes).
+template <typename T> constexpr int lds_max_n() { return kLdsBytes / (2 * (int)sizeof(T)); }
+
+// ---------------------------------------------------------------- descriptors
+// One lattice (f, l) of the batch.
+struct LatDesc {
+    int64_t node_off;   // O_{f,l}
+    int32_t M;          // prime lattice size
+    int32_t N;          // Bluestein length, 5-smooth, >= 2M - 1
+    int32_t N1, N2;     // N = N1 * N2; N2 == 1 when the transform fits LDS
+    int32_t mid;        // index of the distinct-size tables (MDesc)
+    int32_t func;       // function f
+    float inv_m;        // 1/M rounded down (fast modulo)
+    uint32_t off32;     // multiple of M added before the fast modulo
+    int64_t z_off;      // offset of z_{f,l} in the z tables
+};
+
+// Tables shared by every lattice of one size M.
+struct MDesc {
+    int64_t spec_off;   // kernel spectrum (N complex) in the spectrum table
+    int64_t chirp_off;  // two-level chirp table e^{-pi i r / M}, r < 2M
+    int32_t chirp_shift;// log2 of the low table size S
+    int32_t chirp_nlo;  // S
+    int64_t tw_N, tw_N1, tw_N2; // twiddle tables e^{-2 pi i m / n}
+};
+
+// ---------------------------------------------------------------- plan
+struct Plan {
+    int32_t d = 0, F = 0, L = 0, dtype = MR1L_C128;
+    hipStream_t stream = nullptr;
+    int64_t nodes = 0;
+    std::vector<int64_t> M;          // host [F*L]
+    std::vector<int64_t> z;          // host [F*L*d]
+    std::vector<LatDesc> lat;        // host copy
+    std::vector<MDesc> mdesc;
+    std::vector<int32_t> kb;         // per function: fast-hash bound on |k_u|
+    // device tables
+    LatDesc *d_lat = nullptr;
+    MDesc *d_mdesc = nullptr;
+    int32_t *d_z32 = nullptr;        // [F*L*d] z as int32
+    int64_t *d_z64 = nullptr;        // [F*L*d] z as int64
+    int32_t *d_kb = nullptr;         // [F]
+    void *d_spec = nullptr;          // kernel spectra (dtype complex)
+    void *d_chirp = nullptr;         // chirp tables (dtype complex)
+    void *d_tw = nullptr;            // twiddle tables (dtype complex)
+    int64_t spec_len = 0, chirp_len = 0, tw_len = 0;
+    // lattice lists per DFT path
+    std::vector<int32_t> lds_lats, big_lats;
+    int32_t *d_lds_lats = nullptr, *d_big_lats = nullptr;
+    int32_t big_maxN = 0;
+    // scratch
+    void *d_fft_scratch = nullptr;   // [slots][big_maxN] complex (four-step)
+    int32_t fft_slots = 0;
+    void *d_nodes_scratch = nullptr; // [nodes] complex (sampler, adjoint)
+    int64_t *d_det_tmp = nullptr;    // [F] detected counters
+    // persistent scratch of extract when the caller passes NULL outputs
+    int64_t ex_cap = 0;
+    int32_t *d_ex_hash = nullptr;    // [F][cap][L]
+    double *d_ex_w = nullptr;        // [F][cap][L][2]
+    uint32_t *d_ex_mask = nullptr;   // [F][cap]
+    void *d_ex_med = nullptr;        // [F][cap] complex
+    int32_t *d_ex_pos = nullptr;     // [F][s_cap]
+    int64_t ex_scap = 0;
+    int64_t *d_setoff_default = nullptr; // [2] = {0, n} for F == 1 calls
+    int64_t setoff_n = -1;
+    int64_t *d_termoff_default = nullptr;
+    int64_t termoff_n = -1;
+    bool capturing = false;
+    // stage timing
+    bool profiling = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof;
+};
+
+// Records an event pair around a stage when the plan is profiling.
+struct StageTimer {
+    Plan &p;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(Plan &pl, int st) : p(pl), stage(st)
+    {
+        if (p.profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, p.stream);
+    }
+    ~StageTimer()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, p.stream);
+            p.prof.push_back({stage, {a, b}});
+        }
+    }
+};
+
+struct Graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+#define MR1L_HIP(call)                                                           \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess)                                                    \
+            return ::mr1l::fail(MR1L_E_HIP, std::string(#call) + ": " +          \
+                                                hipGetErrorString(e_));          \
+    } while (0)
+#define MR1L_LAUNCH_CHECK() MR1L_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- complex
+template <typename T> struct cplx { T x, y; };
+template <typename T> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+
+// ---------------------------------------------------------------- exact hash
+// Fast path: valid when every |k_u| <= kb (host-proved bound per function):
+// sum_u k_u z_u fits int32, every product fits the 24-bit multiplier, and the
+// float-reciprocal quotient of (s + off32) / M is exact or one too small.
+__device__ __forceinline__ uint32_t fast_mod(uint32_t s, uint32_t m, float inv_m)
+{
+    uint32_t q = (uint32_t)((float)s * inv_m);
+    uint32_t r = s - __umul24(q, m);
+    return r >= m ? r - m : r;
+}
+
+// Exact bucket of any int64 frequency (coordinates strided by `stride`).
+__device__ __forceinline__ int32_t exact_bucket(const int64_t *k, int64_t stride, int d,
+                                                const int64_t *z, int64_t m)
+{
+    int64_t acc = 0;
+    for (int u = 0; u < d; ++u) {
+        int64_t ku = k[(int64_t)u * stride] % m;       // |ku| < m
+        if (ku < 0) ku += m;
+        acc = (acc + (ku * z[u]) % m) % m;            // ku, z < m < 2^23
+    }
+    return (int32_t)acc;
+}
+
+// ---------------------------------------------------------------- launches
+int launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+int launch_fill_bytes(void *p, int64_t nbytes, hipStream_t s);  // zero fill
+
+int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap,
+            int mode, double scale);
+int fft_prepare_spectra(Plan &p);
+void fft_init_attrs();
+void extract_init_attrs();
+
+int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
+             const uint32_t *bitmap, int32_t vote_min, int64_t cap, int64_t *n_det,
+             int64_t *det_idx, uint8_t *votes);
+int hash_count_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
+                   int32_t *hash, int32_t *counts);
+int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
+                     const void *ghat, const mr1l_extract_opts &o, const mr1l_extract_out &out,
+                     int32_t *det_hash, double *det_w, uint32_t *det_mask, void *det_med,
+                     int32_t *out_pos);
+int sample_run(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms,
+               const int64_t *freq, const void *coef, const uint32_t *anchor, void *f,
+               int32_t mode);
+int adjoint_run(Plan &p, int64_t cap, int64_t s_cap, const int64_t *n_out,
+                const int32_t *out_pos, const int32_t *det_hash, const double *det_w,
+                const void *grad_out, void *grad_f);
+
+enum { FFT_FWD = 0, FFT_INV = 1, FFT_SPEC = 2 };
+
+// Number of compute units of the current device.
+int num_cus();
+
+}  // namespace mr1l

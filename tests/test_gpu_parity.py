@@ -1,0 +1,499 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on the same seeded inputs.
+
+Integer results (buckets, counts, votes, detected sets, singleton masks, output order)
+must be bit-exact; floating point within 1e-11 (complex128) or 1e-5 (complex64)
+relative to the scale of the compared vector.  A threshold decision whose oracle
+modulus lies within a rounding band of theta is reported and excluded from the exact
+comparison (expected: none).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex128: 1e-11, torch.complex64: 1e-5}
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_2006_13053_amd as mod
+    mod.lib()
+    torch.cuda.set_device(0)
+    return mod
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+def close(a, b, tol, what):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    if a.size == 0:
+        return
+    scale = max(1e-300, float(np.abs(b).max()))
+    err = float(np.abs(a - b).max()) / scale
+    assert err <= tol, f"{what}: rel err {err:.3e} > {tol:.0e}"
+
+
+def unpack_bits(words, nodes):
+    w = np.asarray(words).view(np.uint32)
+    bits = ((w[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).reshape(-1)
+    return bits[:nodes].astype(bool)
+
+
+def oracle_bitmap(g, theta):
+    return (g.real ** 2 + g.imag ** 2) >= theta * theta
+
+
+EPS = {torch.complex128: 2.0 ** -53, torch.complex64: 2.0 ** -24}
+
+
+def fragile(g, theta, eps):
+    """Threshold decisions whose oracle modulus lies within the DFT's rounding error of
+    theta (unit roundoff of the working precision times 16 log2 of the largest
+    Bluestein length, relative to the largest modulus)."""
+    mag = np.abs(g)
+    return np.abs(mag - theta) <= 16 * 16 * eps * max(1e-300, mag.max())
+
+
+def check_limit(r, ro, eps, tol):
+    """Algorithm 4 output: same entries and the same order except among entries whose
+    moduli are equal within rounding (their order is not unique)."""
+    gi, go_ = r["out_idx"], ro["out_idx"]
+    gc, oc = r["out_coef"], ro["out_coef"]
+    assert gi.shape == go_.shape, (gi.shape, go_.shape)
+    if gi.size == 0:
+        return
+    scale = max(1e-300, float(np.abs(oc).max()))
+    delta = 256 * eps * scale
+    omag = dict(zip(go_.tolist(), np.abs(oc).tolist()))
+    mag_min = float(np.abs(oc).min())
+    boundary = {i for i, mg in omag.items() if abs(mg - mag_min) <= delta}
+    missing = set(go_.tolist()) - set(gi.tolist())
+    assert missing <= boundary, f"outputs differ beyond boundary ties: {sorted(missing)[:10]}"
+    close(np.sort(np.abs(gc))[::-1], np.sort(np.abs(oc))[::-1], tol, "output moduli")
+    seq = [omag.get(i, mag_min) for i in gi.tolist()]
+    assert all(seq[o] >= seq[o + 1] - delta for o in range(len(seq) - 1)), "order differs beyond ties"
+    ocd = dict(zip(go_.tolist(), oc.tolist()))
+    for i, c in zip(gi.tolist(), gc.tolist()):
+        if i in ocd:
+            assert abs(c - ocd[i]) <= tol * scale
+
+
+# ------------------------------------------------------------------ hashing
+@pytest.mark.parametrize("d,n,box,L,mlo,mhi", [
+    (5, 2000, 32, 5, 160, 320),
+    (10, 20000, 64, 10, 800, 1600),
+    (25, 5000, 32, 7, 4133, 4133),
+    (3, 3000, 2**40, 6, 10000, 16000),      # beyond the 24-bit bound: exact 64-bit path
+    (10, 4000, 512, 20, 16001, 16001),
+])
+def test_hash_count_bit_exact(m, d, n, box, L, mlo, mhi):
+    say("hash_count", d, n, box, L)
+    rng = np.random.default_rng(d * 7 + L)
+    freq = rng.integers(-box, box + 1, size=(d, n), dtype=np.int64)
+    freq[:, 0] = box
+    freq[:, 1] = -box
+    if box < 2**20:
+        freq[0, 2] = 2**45            # one candidate outside the fast bound
+    M, z = synth.draw_lattices(rng, L, d, mlo, mhi, distinct=mlo != mhi)
+    plan = m.Plan(d, M, z)
+    h, c = m.mr1l_hash_count(plan, T(freq))
+    torch.cuda.synchronize()
+    assert np.array_equal(h.cpu().numpy(), oracle.hash_buckets(freq, M, z))
+    assert np.array_equal(c.cpu().numpy(), oracle.counts(freq, M, z))
+
+
+def test_hash_count_batched_functions(m):
+    say("hash_count batched F=3")
+    rng = np.random.default_rng(3)
+    d, L = 6, 4
+    sizes = [100, 1, 777]
+    sets = [rng.integers(-100, 101, size=(d, n), dtype=np.int64) for n in sizes]
+    Ms, zs = [], []
+    for f in range(3):
+        M, z = synth.draw_lattices(rng, L, d, 200, 600)
+        Ms.append(M)
+        zs.append(z)
+    plan = m.Plan(d, np.concatenate(Ms), np.concatenate(zs), F=3)
+    allf = np.concatenate(sets, axis=1)
+    off = T(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
+    h, c = m.mr1l_hash_count(plan, T(allf), set_off=off)
+    torch.cuda.synchronize()
+    h, c = h.cpu().numpy(), c.cpu().numpy()
+    pos, nodes = 0, 0
+    for f in range(3):
+        ho = oracle.hash_buckets(sets[f], Ms[f], zs[f])
+        assert np.array_equal(h[:, pos:pos + sizes[f]], ho)
+        co = oracle.counts(sets[f], Ms[f], zs[f])
+        assert np.array_equal(c[nodes:nodes + co.shape[0]], co)
+        pos += sizes[f]
+        nodes += co.shape[0]
+
+
+# ------------------------------------------------------------------ DFT
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("Ms", [[2, 3, 5, 7], [163, 211, 317], [1009, 4133], [5113, 5119], [16001], [15991, 12007]])
+def test_fft_matches_direct_dft(m, Ms, dtype):
+    say("fft", Ms, dtype)
+    rng = np.random.default_rng(sum(Ms))
+    M = np.array(Ms, np.int64)
+    z = rng.integers(0, 2, size=(len(Ms), 1)).astype(np.int64)
+    f = rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum()))
+    plan = m.Plan(1, M, z % M[:, None], dtype=dtype)
+    g, bm = m.mr1l_fft(plan, T(f.astype(np.complex128)).to(dtype), theta=0.05)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.complex128)
+    off = 0
+    for mm in M:
+        mm = int(mm)
+        if mm <= 5200:
+            go = oracle.dft(f[off:off + mm], np.array([mm]))
+            bins = np.arange(mm)
+        else:   # large prime: direct DFT on sampled bins (O(M) each)
+            bins = np.unique(np.concatenate([[0, 1, mm - 1], rng.integers(0, mm, 400)]))
+            go = oracle.dft_bins(f[off:off + mm], mm, bins)
+        scale = np.abs(go).max()
+        err = np.abs(g[off + bins] - go).max() / scale
+        assert err <= TOL[dtype], f"M={mm} err {err:.2e}"
+        off += mm
+
+
+def test_fft_bitmap_and_aliasing_formula(m):
+    """Sample -> DFT on a sparse polynomial equals the bucket sums (eq. (2.4)); the
+    bitmap is exactly the set of occupied buckets."""
+    say("fft bitmap eq. 2.4")
+    p = synth.small_config(4)
+    plan = m.Plan(p.d, p.M, p.z)
+    f = oracle.sample(p.supp, p.coef, p.M, p.z)
+    g, bm = m.mr1l_fft(plan, T(f), p.theta)
+    torch.cuda.synchronize()
+    b = oracle.bucket_sums(p.supp, p.coef, p.M, p.z)
+    close(g.cpu().numpy(), b, 1e-11, "ghat vs bucket sums")
+    occupied = oracle.counts(p.supp, p.M, p.z) > 0
+    assert np.array_equal(unpack_bits(bm.cpu().numpy(), plan.nodes), occupied)
+
+
+def test_inverse_dft_via_sampler_bucket_mode(m):
+    say("sample bucket mode")
+    p = synth.small_config(5)
+    plan = m.Plan(p.d, p.M, p.z)
+    fb = m.mr1l_sample(plan, T(p.supp), T(p.coef), mode=2)
+    fd = m.mr1l_sample(plan, T(p.supp), T(p.coef), mode=1)
+    torch.cuda.synchronize()
+    fo = oracle.sample(p.supp, p.coef, p.M, p.z)
+    close(fd.cpu().numpy(), fo, 1e-11, "direct samples")
+    close(fb.cpu().numpy(), fo, 1e-11, "bucket-mode samples")
+
+
+def test_sample_with_anchors(m):
+    say("sample anchors")
+    rng = np.random.default_rng(8)
+    d, t, s = 8, 3, 40
+    freq = rng.integers(-32, 33, size=(d, s), dtype=np.int64)
+    coef = rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    anc = rng.integers(0, 2**32, size=d - t, dtype=np.uint64).astype(np.uint32)
+    M, z = synth.draw_lattices(rng, 5, t, 300, 700)
+    plan = m.Plan(t, M, z)
+    for mode in (1, 2):
+        f = m.mr1l_sample(plan, T(freq), T(coef), anchor=T(anc.view(np.int32)), mode=mode)
+        torch.cuda.synchronize()
+        close(f.cpu().numpy(), oracle.sample(freq, coef, M, z, anchor=anc, t=t), 1e-11, f"anchored mode {mode}")
+
+
+# ------------------------------------------------------------------ full pass
+def gpu_pass(m, p, f_np=None, dtype=torch.complex128, s_cap=None, cap=4096, postproc=True, vote_min=0,
+             want_votes=True):
+    plan = m.Plan(p.d, p.M, p.z, dtype=dtype)
+    if f_np is None:
+        f = m.mr1l_sample(plan, T(p.supp), T(p.coef.astype(np.complex128)).to(dtype))
+    else:
+        f = T(f_np).to(dtype)
+    g, bm = m.mr1l_fft(plan, f, p.theta)
+    s_cap = s_cap or min(cap, p.n)
+    ex = m.mr1l_extract(plan, T(p.cand), g, bm, p.theta, s_cap=s_cap, cap=cap, postproc=postproc,
+                        vote_min=vote_min, want_votes=want_votes)
+    torch.cuda.synchronize()
+    nd = int(ex["n_det"][0])
+    k = min(nd, cap)
+    no = int(ex["n_out"][0])
+    r = dict(n_det=nd, ghat=g.cpu().numpy(), bitmap=unpack_bits(bm.cpu().numpy(), plan.nodes),
+             det_idx=ex["det_idx"][0, :k].cpu().numpy(), det_mask=ex["det_mask"][0, :k].cpu().numpy().view(np.uint32),
+             det_coef=ex["det_coef"][0, :k].cpu().numpy(), det_med=ex["det_med"][0, :k].cpu().numpy(),
+             out_idx=ex["out_idx"][0, :no].cpu().numpy(), out_coef=ex["out_coef"][0, :no].cpu().numpy(),
+             out_pos=ex["out_pos"][0, :no].cpu().numpy())
+    if want_votes:
+        r["votes"] = ex["votes"].cpu().numpy()
+    return r, plan, ex, f
+
+
+def compare_pass(r, ro, go, theta, tol, s_cap, eps=EPS[torch.complex128]):
+    band = fragile(go, theta, eps)
+    exact = ~band
+    assert np.array_equal(r["bitmap"][exact], oracle_bitmap(go, theta)[exact])
+    if band.any():
+        pytest.skip(f"{int(band.sum())} threshold decisions inside the rounding band")
+    if "votes" in r:
+        assert np.array_equal(r["votes"], ro["votes"])
+    assert r["n_det"] == ro["n_det"]
+    assert np.array_equal(r["det_idx"], ro["det_idx"])
+    assert np.array_equal(r["det_mask"], ro["det_mask"])
+    close(r["det_med"], ro["det_med"], tol, "median coefficients")
+    close(r["det_coef"], ro["det_coef"], tol, "post-processed coefficients")
+    check_limit(r, ro, eps, tol)
+    # out_pos points into the detected list at the output's candidate
+    assert np.array_equal(r["det_idx"][r["out_pos"]], r["out_idx"])
+
+
+@pytest.mark.parametrize("seed", list(range(10)))
+def test_small_config_full_pass(m, seed):
+    """d = 5, 2000 candidates, s = 20, L = 5, noise-free complex128 (the small plain case)."""
+    say("small full pass seed", seed)
+    p = synth.small_config(seed)
+    r, *_ = gpu_pass(m, p, s_cap=40, cap=2000)
+    fo = oracle.sample(p.supp, p.coef, p.M, p.z)
+    go = oracle.dft(fo, p.M)
+    close(r["ghat"], go, 1e-11, "ghat")
+    ro = oracle.extract(p.cand, p.M, p.z, go, p.theta, s_cap=40, cap=2000)
+    compare_pass(r, ro, go, p.theta, 1e-11, 40)
+
+
+@pytest.mark.parametrize("postproc", [True, False])
+def test_small_config_complex64(m, postproc):
+    say("small full pass c64", postproc)
+    p = synth.small_config(11)
+    p.theta = 1e-3
+    fo = oracle.sample(p.supp, p.coef, p.M, p.z)
+    r, *_ = gpu_pass(m, p, f_np=fo, dtype=torch.complex64, s_cap=40, cap=2000, postproc=postproc)
+    go = oracle.dft(fo, p.M)
+    ro = oracle.extract(p.cand, p.M, p.z, go, p.theta, s_cap=40, cap=2000, postproc=postproc)
+    compare_pass(r, ro, go, p.theta, 1e-5, 40, eps=EPS[torch.complex64])
+
+
+def test_mid_config_full_pass_with_noise(m):
+    """d = 10, 1e5 candidates in [-64,64]^10, s = 100, L = 10, 40 dB noise, theta = 1/3."""
+    say("mid full pass")
+    p = synth.mid_config(0)
+    fo = oracle.sample(p.supp, p.coef, p.M, p.z)
+    f = fo + synth.noise_for(fo, p.M, 40.0, p.meta["noise_seed"])
+    r, *_ = gpu_pass(m, p, f_np=f, s_cap=200, cap=4096)
+    go = oracle.dft(f, p.M)
+    ro = oracle.extract(p.cand, p.M, p.z, go, p.theta, s_cap=200, cap=4096)
+    compare_pass(r, ro, go, p.theta, 1e-11, 200)
+    # the support is found and its coefficients are within the noise of the truth
+    assert set(p.supp_idx.tolist()) <= set(r["out_idx"].tolist())
+
+
+def test_vote_min_general_nu(m):
+    say("vote_min")
+    p = synth.small_config(6, mlo=40, mhi=90)
+    fo = oracle.sample(p.supp, p.coef, p.M, p.z)
+    go = oracle.dft(fo, p.M)
+    for vm in (1, 2, 4, 5):
+        r, *_ = gpu_pass(m, p, f_np=fo, s_cap=64, cap=2000, vote_min=vm)
+        ro = oracle.extract(p.cand, p.M, p.z, go, p.theta, s_cap=64, cap=2000, vote_min=vm)
+        compare_pass(r, ro, go, p.theta, 1e-11, 64)
+
+
+def test_dirichlet_counting_polynomial(m):
+    """eq. (4.1): all-ones coefficients on I; the lattice values are the integer alias
+    counts and the median classification of Table 4.1 follows."""
+    say("dirichlet")
+    p = synth.dirichlet(synth.small_config(7, mlo=30, mhi=60))
+    r, *_ = gpu_pass(m, p, s_cap=2000, cap=2000, postproc=False)
+    cnt = oracle.counts(p.supp, p.M, p.z)
+    assert np.abs(r["ghat"] - cnt).max() < 1e-11
+    go = oracle.dft(oracle.sample(p.supp, p.coef, p.M, p.z), p.M)
+    ro = oracle.extract(p.cand, p.M, p.z, go, p.theta, s_cap=2000, cap=2000, postproc=False)
+    compare_pass(r, ro, go, p.theta, 1e-11, 2000)
+
+
+def test_empty_and_ragged_inputs(m):
+    say("empty/ragged")
+    p = synth.small_config(8)
+    plan = m.Plan(p.d, p.M, p.z)
+    f = m.mr1l_sample(plan, T(p.supp), T(p.coef))
+    g, bm = m.mr1l_fft(plan, f, p.theta)
+    empty = torch.zeros((p.d, 0), dtype=torch.int64, device=dev())
+    ex = m.mr1l_extract(plan, empty, g, bm, p.theta, s_cap=4, cap=16)
+    torch.cuda.synchronize()
+    assert int(ex["n_det"][0]) == 0 and int(ex["n_out"][0]) == 0
+    for n in (1, 63, 65, 257, 1999):
+        sub = p.cand[:, :n]
+        ex = m.mr1l_extract(plan, T(sub), g, bm, p.theta, s_cap=min(8, n), cap=n)
+        torch.cuda.synchronize()
+        go = oracle.dft(oracle.sample(p.supp, p.coef, p.M, p.z), p.M)
+        ro = oracle.extract(sub, p.M, p.z, go, p.theta, s_cap=min(8, n), cap=n)
+        assert int(ex["n_det"][0]) == ro["n_det"]
+        assert np.array_equal(ex["det_idx"][0, :ro["n_det"]].cpu().numpy(), ro["det_idx"])
+        no = int(ex["n_out"][0])
+        assert np.array_equal(ex["out_idx"][0, :no].cpu().numpy(), ro["out_idx"])
+
+
+def test_capacity_overflow_reports_required_size(m):
+    say("capacity")
+    p = synth.dirichlet(synth.small_config(9, mlo=20, mhi=30))
+    plan = m.Plan(p.d, p.M, p.z)
+    f = m.mr1l_sample(plan, T(p.supp), T(p.coef))
+    g, bm = m.mr1l_fft(plan, f, p.theta)
+    ex = m.mr1l_extract(plan, T(p.cand), g, bm, p.theta, s_cap=4, cap=8)
+    torch.cuda.synchronize()
+    go = oracle.dft(oracle.sample(p.supp, p.coef, p.M, p.z), p.M)
+    ro = oracle.extract(p.cand, p.M, p.z, go, p.theta, s_cap=4, cap=p.n)
+    assert ro["n_det"] > 8
+    assert int(ex["n_det"][0]) == ro["n_det"]
+
+
+# ------------------------------------------------------------------ adjoint / autograd
+def test_adjoint_dense_transpose_and_dot_product(m):
+    say("adjoint")
+    p = synth.mid_config(1, n=3000, s=15, L=5)
+    fo = oracle.sample(p.supp, p.coef, p.M, p.z)
+    f = fo + synth.noise_for(fo, p.M, 40.0, 5)
+    r, plan, ex, fdev = gpu_pass(m, p, f_np=f, s_cap=30, cap=512)
+    no = int(ex["n_out"][0])
+    rng = np.random.default_rng(1)
+    y = np.zeros((1, 30), np.complex128)
+    y[0, :no] = rng.standard_normal(no) + 1j * rng.standard_normal(no)
+    gf = m.mr1l_adjoint(plan, ex, T(y)).cpu().numpy()
+    # oracle dense transpose with the oracle's own selection
+    go = oracle.dft(f, p.M)
+    ro = oracle.extract(p.cand, p.M, p.z, go, p.theta, s_cap=30, cap=512)
+    w = oracle.weights(p.cand, p.M, p.z, go, ro["det_idx"], ro["det_mask"])
+    yd = np.zeros(len(ro["det_idx"]), np.complex128)
+    yd[ro["out_pos"]] = y[0, :no]
+    ga = oracle.adjoint(p.cand, p.M, p.z, ro["det_idx"], w, yd)
+    close(gf, ga, 1e-11, "adjoint vs dense transpose")
+    # dot-product identity against the forward map of the library
+    x = rng.standard_normal(f.shape[0]) + 1j * rng.standard_normal(f.shape[0])
+    eps = 1e-4
+
+    def coef_of(ff):
+        rr, *_ = gpu_pass(m, p, f_np=ff, s_cap=30, cap=512)
+        assert np.array_equal(rr["out_idx"], r["out_idx"])
+        return rr["out_coef"]
+    lin = (coef_of(f + eps * x) - coef_of(f - eps * x)) / (2 * eps)
+    lhs = float(np.real(np.vdot(y[0, :no], lin)))
+    rhs = float(np.real(np.vdot(gf, x)))
+    assert abs(lhs - rhs) <= 1e-7 * max(1.0, abs(rhs))
+
+
+def test_autograd_function_finite_differences(m):
+    say("autograd FD")
+    p = synth.mid_config(2, n=2000, s=10, L=5)
+    fo = oracle.sample(p.supp, p.coef, p.M, p.z)
+    f0 = fo + synth.noise_for(fo, p.M, 40.0, 9)
+    plan = m.Plan(p.d, p.M, p.z)
+    freq = T(p.cand)
+    f = T(f0).requires_grad_(True)
+    out, n_out, idx = m.LatticeCoefficients.apply(f, plan, freq, p.theta, 20, 512, True)
+    rng = np.random.default_rng(2)
+    wv = T(rng.standard_normal(20) + 1j * rng.standard_normal(20))
+    loss = torch.real(torch.sum(torch.conj(wv) * out[0]))
+    loss.backward()
+    g = f.grad.cpu().numpy()
+
+    def L_of(ff):
+        o, _, ii = m.LatticeCoefficients.apply(T(ff), plan, freq, p.theta, 20, 512, True)
+        assert torch.equal(ii, idx)
+        return float(torch.real(torch.sum(torch.conj(wv) * o[0])).item())
+    h = 1e-6
+    for j in rng.integers(0, f0.shape[0], 16):
+        for unit in (1.0, 1j):
+            e = np.zeros_like(f0)
+            e[j] = unit
+            fd = (L_of(f0 + h * e) - L_of(f0 - h * e)) / (2 * h)
+            an = g[j].real if unit == 1.0 else g[j].imag
+            assert fd == pytest.approx(an, rel=1e-5, abs=1e-8)
+
+
+# ------------------------------------------------------------------ batched and graphs
+def test_batched_plan_equals_plain_calls(m):
+    say("batched vs plain")
+    probs = synth.batch_config(0, nfunc=5, scale=0.01)
+    d, L = probs[0].d, probs[0].L
+    Ms = np.concatenate([q.M for q in probs])
+    zs = np.concatenate([q.z for q in probs])
+    plan = m.Plan(d, Ms, zs, F=len(probs))
+    toff = T(np.concatenate([[0], np.cumsum([q.supp.shape[1] for q in probs])]).astype(np.int64))
+    soff = T(np.concatenate([[0], np.cumsum([q.n for q in probs])]).astype(np.int64))
+    supp = T(np.concatenate([q.supp for q in probs], axis=1))
+    coef = T(np.concatenate([q.coef for q in probs]))
+    cand = T(np.concatenate([q.cand for q in probs], axis=1))
+    f = m.mr1l_sample(plan, supp, coef, term_off=toff)
+    g, bm = m.mr1l_fft(plan, f, 1e-12)
+    exb = m.mr1l_extract(plan, cand, g, bm, 1e-12, s_cap=512, cap=2048, set_off=soff)
+    torch.cuda.synchronize()
+    for fi, q in enumerate(probs):
+        r, *_ = gpu_pass(m, q, s_cap=512, cap=2048, want_votes=False)
+        nd = int(exb["n_det"][fi])
+        assert nd == r["n_det"]
+        assert np.array_equal(exb["det_idx"][fi, :nd].cpu().numpy(), r["det_idx"])
+        no = int(exb["n_out"][fi])
+        assert np.array_equal(exb["out_idx"][fi, :no].cpu().numpy(), r["out_idx"])
+        close(exb["out_coef"][fi, :no].cpu().numpy(), r["out_coef"], 1e-11, "batched coef")
+        # and both equal the oracle
+        go = oracle.dft(oracle.sample(q.supp, q.coef, q.M, q.z), q.M)
+        ro = oracle.extract(q.cand, q.M, q.z, go, 1e-12, s_cap=512, cap=2048)
+        assert np.array_equal(r["out_idx"], ro["out_idx"])
+
+
+def test_graph_replay_matches_eager(m):
+    say("graph replay")
+    p = synth.small_config(3)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan = m.Plan(p.d, p.M, p.z, stream=s)
+        freq = T(p.cand)
+        f = m.mr1l_sample(plan, T(p.supp), T(p.coef))
+        g, bm = m.mr1l_fft(plan, f, p.theta)
+        ex = m.mr1l_extract(plan, freq, g, bm, p.theta, s_cap=40, cap=2000)
+        s.synchronize()
+        ref = ex["out_coef"].clone(), ex["out_idx"].clone(), ex["n_out"].clone()
+        graph = m.Graph(plan)
+        with graph:
+            m.mr1l_fft(plan, f, p.theta, ghat=g, bitmap=bm)
+            m.mr1l_extract(plan, freq, g, bm, p.theta, s_cap=40, cap=2000, out=ex)
+        for rep in range(4):
+            ex["out_coef"].zero_()
+            ex["n_out"].zero_()
+            s.synchronize()
+            graph.launch(s)
+            s.synchronize()
+            assert torch.equal(ex["n_out"], ref[2])
+            assert torch.equal(ex["out_idx"], ref[1])
+            assert torch.equal(ex["out_coef"], ref[0])
+
+
+# ------------------------------------------------------------------ driver
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dimincr_matches_oracle_driver(m, seed):
+    say("dimincr seed", seed)
+    d, s = 6, 12
+    freq, coef = synth.sparse_poly_box(seed, d=d, s=s, box=6)
+    Mlat = synth.next_prime_above(10.33 * 2 * s)
+    of, oc, ns = oracle.dimincr(freq, coef, N=6, s=s, s_local=2 * s, r=3, theta=1e-12, c=10.33, delta=0.9,
+                                Mlat=Mlat, seed=100 + seed)
+    gf, gc, gs = m.mr1l_dimincr(d, 6, s, 2 * s, 3, 1e-12, Mlat, 100 + seed, poly_freq=T(freq), poly_coef=T(coef))
+    assert ns == gs
+    assert np.array_equal(gf, of)
+    close(gc, oc, 1e-11, "driver coefficients")
+    truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
+    assert [tuple(r) for r in gf.tolist()] == [t[0] for t in truth]
