@@ -1,0 +1,348 @@
+#!/usr/bin/env python3
+"""Throughput of the multiple-rank-1-lattice step on one MI355X.
+
+Default workload ("large"): a batch of 64 functions, each with |Gamma| = 10^7
+candidate frequencies uniform in [-512, 512]^10 (structure-of-arrays int64, 51 GB for
+the batch), coefficients (1 + ||k||_1)^-2 with random unit phase on all of Gamma plus
+1000 dominant entries of modulus 10, L = 20 lattices of prime size 16001 per function
+with random generating vectors, complex128, theta = 1.  The samples are generated
+once (untimed, bucket sampler) and stay resident in HBM.
+
+One step = one pass of the method over the whole batch: the normalised lattice DFTs
+with the non-zero bitmap (Algorithm 2, first loop) and the hash / vote / detected set
+/ singleton masks / median and singleton coefficients / Algorithm 4 limit, as one
+batched launch per stage.  value = candidates x lattices per second over the batch.
+
+Also reported: per-stage times from HIP events recorded by the library on its stream,
+the roofline of the dominant kernel (the vote pass), functions/s of the batched call
+vs the per-function loop, a sampled parity check against the CPU oracle, and the
+oracle's own throughput on a bounded sample (cpu_baseline).
+
+Workload "batch": 512 functions with s log-uniform in [10, 1000], |Gamma| log-uniform
+in [10^3, 10^6] from [-128, 128]^10, L = 8, M distinct primes in [8s, 16s],
+noise-free, theta = 1e-12 (complex128, or complex64 with --c64).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "vote_large_pmc.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def vote_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_hash.hip", "mr1l_internal.h"):
+        with open(os.path.join(ROOT, "paper_2006_13053_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# ----------------------------------------------------------------------------- large
+def setup_large(m, torch, F, n, seed=2026):
+    import synth.counter as sc
+    d, L, M, box = 10, 20, 16001, 512
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(seed)
+    Ms = np.full(F * L, M, np.int64)
+    zs = rng.integers(0, M, size=(F, L, d), dtype=np.int64)
+    nodes_f = L * M
+    t0 = time.time()
+    gam = torch.empty((d, F * n), dtype=torch.int64, device=dev)      # batched SoA
+    per = []                                                           # per-function SoA
+    f_all = torch.empty(F * nodes_f, dtype=torch.complex128, device=dev)
+    table = sc.phase_table(dev)
+    plans = []
+    for f in range(F):
+        g = sc.candidates(seed, f, d, n, box, device=dev)
+        gam[:, f * n:(f + 1) * n] = g
+        per.append(g)
+        c = sc.compressible_coefs(seed, f, g, table)
+        dom = torch.from_numpy(sc.dominant_indices(seed, f, n, 1000)).to(dev)
+        c[dom] = 10.0 * torch.from_numpy(sc.dominant_phases(seed, f, 1000)).to(dev)
+        pf = m.Plan(d, Ms[f * L:(f + 1) * L], zs[f])
+        m.mr1l_sample(pf, g, c, f=f_all[f * nodes_f:(f + 1) * nodes_f], mode=2)
+        plans.append(pf)
+        del c
+        if f % 8 == 7:
+            torch.cuda.synchronize()
+            log(f"  {f + 1}/{F} functions generated and sampled ({time.time() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    log(f"generated {F} functions x {n} candidates and their samples in {time.time() - t0:.1f}s")
+    plan = m.Plan(d, Ms, zs.reshape(-1), F=F)
+    set_off = torch.arange(0, (F + 1) * n, n, dtype=torch.int64, device=dev)
+    return dict(d=d, L=L, M=M, F=F, n=n, gam=gam, per=per, f=f_all, plan=plan, plans=plans,
+                set_off=set_off, theta=1.0, zs=zs, seed=seed, box=box, nodes_f=nodes_f,
+                cap=4096, s_cap=2048)
+
+
+# ----------------------------------------------------------------------------- batch
+def setup_batch(m, torch, F, seed=2027, c64=False):
+    import synth
+    import synth.counter as sc
+    d, L, box = 10, 8, 128
+    dev = torch.device("cuda", 0)
+    dtype = torch.complex64 if c64 else torch.complex128
+    rng = np.random.default_rng(seed)
+    s = np.rint(np.exp(rng.uniform(math.log(10), math.log(1000), F))).astype(np.int64)
+    n = np.rint(np.exp(rng.uniform(math.log(1e3), math.log(1e6), F))).astype(np.int64)
+    n = np.maximum(n, s)
+    Ms, zs, supp_idx = [], [], []
+    for f in range(F):
+        M, z = synth.draw_lattices(rng, L, d, 8 * int(s[f]), 16 * int(s[f]))
+        Ms.append(M)
+        zs.append(z)
+        supp_idx.append(np.sort(rng.choice(int(n[f]), size=int(s[f]), replace=False)))
+    Ms = np.concatenate(Ms)
+    zs = np.concatenate(zs)
+    off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    toff = np.concatenate([[0], np.cumsum(s)]).astype(np.int64)
+    gam = torch.empty((d, int(off[-1])), dtype=torch.int64, device=dev)
+    per, supp, coef = [], [], []
+    for f in range(F):
+        g = sc.candidates(seed, f, d, int(n[f]), box, device=dev)
+        gam[:, off[f]:off[f + 1]] = g
+        per.append(g)
+        supp.append(g[:, torch.from_numpy(supp_idx[f]).to(dev)])
+        coef.append(torch.from_numpy(rng.standard_normal(int(s[f])) + 1j * rng.standard_normal(int(s[f]))))
+    supp = torch.cat(supp, dim=1).contiguous()
+    coef = torch.cat(coef).to(dev).to(dtype)
+    plan = m.Plan(d, Ms, zs, F=F, dtype=dtype)
+    f_all = m.mr1l_sample(plan, supp, coef, term_off=torch.from_numpy(toff).to(dev), mode=1)
+    plans = [m.Plan(d, Ms[f * L:(f + 1) * L], zs[f * L:(f + 1) * L], dtype=dtype) for f in range(F)]
+    node_off = np.concatenate([[0], np.cumsum([int(Ms[f * L:(f + 1) * L].sum()) for f in range(F)])])
+    torch.cuda.synchronize()
+    return dict(d=d, L=L, F=F, n=n, gam=gam, per=per, f=f_all, plan=plan, plans=plans,
+                set_off=torch.from_numpy(off).to(dev), theta=1e-3 if c64 else 1e-12, cap=4096,
+                s_cap=2048, node_off=node_off, s=s, dtype=dtype)
+
+
+# ----------------------------------------------------------------------------- steps
+def make_step(m, w):
+    plan, f, gam, so = w["plan"], w["f"], w["gam"], w["set_off"]
+    ghat, bm = m.mr1l_fft(plan, f, w["theta"])
+    ex = m.mr1l_extract(plan, gam, ghat, bm, w["theta"], s_cap=w["s_cap"], cap=w["cap"], set_off=so,
+                        want_w=False)
+
+    def step():
+        m.mr1l_fft(plan, f, w["theta"], ghat=ghat, bitmap=bm)
+        m.mr1l_extract(plan, gam, ghat, bm, w["theta"], s_cap=w["s_cap"], cap=w["cap"], set_off=so, out=ex)
+    return step, ex, ghat
+
+
+def plain_pass(m, torch, w, reps=2):
+    """Per-function loop: F separate plans, one fft + extract call pair each."""
+    bufs = []
+    nodes = [p.nodes for p in w["plans"]]
+    off = np.concatenate([[0], np.cumsum(nodes)])
+    for fi, pf in enumerate(w["plans"]):
+        fv = w["f"][off[fi]:off[fi + 1]]
+        g, b = m.mr1l_fft(pf, fv, w["theta"])
+        e = m.mr1l_extract(pf, w["per"][fi], g, b, w["theta"], s_cap=w["s_cap"], cap=w["cap"], want_w=False)
+        bufs.append((fv, g, b, e))
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for fi, pf in enumerate(w["plans"]):
+            fv, g, b, e = bufs[fi]
+            m.mr1l_fft(pf, fv, w["theta"], ghat=g, bitmap=b)
+            m.mr1l_extract(pf, w["per"][fi], g, b, w["theta"], s_cap=w["s_cap"], cap=w["cap"], out=e)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best, bufs
+
+
+# ----------------------------------------------------------------------------- oracle legs
+def cpu_baseline_large(w, n_sample, budget_s=10.0):
+    """Oracle on one function of the batch, repeated until ~budget_s of CPU time: direct
+    O(M^2) DFTs of its 20 lattices (on synthetic samples of the same size) and Algorithm 2
+    + Remark 2.9 + Algorithm 4 over all of its candidates; value = candidates x lattices
+    per second of one function."""
+    import oracle
+    import synth.counter as sc
+    import torch
+    d, L, M, n, seed = w["d"], w["L"], w["M"], w["n"], w["seed"]
+    Ms = np.full(L, M, np.int64)
+    z = w["zs"][0]
+    rng = np.random.default_rng(7)
+    fs = rng.standard_normal(L * M) + 1j * rng.standard_normal(L * M)
+    # the oracle's own coefficients of function 0 (eq. (2.4): bucket sums of the polynomial)
+    cand = sc.candidates(seed, 0, d, n, w["box"], device="cpu")
+    coef = sc.compressible_coefs(seed, 0, cand, sc.phase_table("cpu"))
+    dom = torch.from_numpy(sc.dominant_indices(seed, 0, n, 1000))
+    coef[dom] = 10.0 * torch.from_numpy(sc.dominant_phases(seed, 0, 1000))
+    cand_np = np.ascontiguousarray(cand.numpy())
+    g_exact = oracle.bucket_sums(cand_np, coef.numpy(), Ms, z)
+    reps, t_dft, t_ex = 0, 0.0, 0.0
+    while reps == 0 or (t_dft + t_ex) < budget_s:
+        t0 = time.perf_counter()
+        oracle.dft(fs, Ms)
+        t1 = time.perf_counter()
+        ro = oracle.extract(cand_np, Ms, z, g_exact, w["theta"], s_cap=w["s_cap"], cap=w["cap"])
+        t2 = time.perf_counter()
+        t_dft += t1 - t0
+        t_ex += t2 - t1
+        reps += 1
+    value = reps * n * L / (t_dft + t_ex)
+    sub = np.ascontiguousarray(cand_np[:, :n_sample])
+    ro_sub = oracle.extract(sub, Ms, z, g_exact, w["theta"], s_cap=w["s_cap"], cap=w["cap"])
+    return dict(value=value, unit="candidates\u00b7lattices/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"function 0 of the batch, {reps} repetitions: direct O(M^2) DFTs of its {L} lattices "
+                        f"({t_dft / reps:.2f}s each) + Algorithm 2/Remark 2.9/Algorithm 4 over all {n} "
+                        f"candidates ({t_ex / reps:.2f}s each)")), ro_sub, g_exact
+
+
+def parity_large(m, torch, w, ex, ghat, ro, g_exact, n_sample):
+    """Function 0 of the batched pass vs the oracle on the candidate sample: detected
+    sets bit-exact, median coefficients (eq. (2.10), which depend on the candidate alone)
+    within 1e-11, and the lattice DFT values within 1e-11 of the bucket sums (eq. (2.4))."""
+    k = min(int(ex["n_det"][0]), w["cap"])
+    di = ex["det_idx"][0, :k].cpu().numpy()
+    dc = ex["det_med"][0, :k].cpu().numpy()
+    sel = di < n_sample
+    same = np.array_equal(di[sel], ro["det_idx"])
+    err = float(np.abs(dc[sel] - ro["det_med"]).max() / np.abs(ro["det_med"]).max()) if sel.any() else 0.0
+    gerr = float(np.abs(ghat[: w["nodes_f"]].cpu().numpy() - g_exact).max() / np.abs(g_exact).max())
+    return dict(sampled_candidates=n_sample, detected_in_sample=int(sel.sum()), detected_equal=bool(same),
+                coef_max_rel_err=err, ghat_max_rel_err=gerr, ok=bool(same and err <= 1e-11 and gerr <= 1e-11))
+
+
+# ----------------------------------------------------------------------------- main
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=("large", "batch"), default="large")
+    ap.add_argument("--functions", type=int, default=None)
+    ap.add_argument("--candidates", type=int, default=10_000_000)
+    ap.add_argument("--c64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-function loop")
+    ap.add_argument("--graph", action="store_true", help="time a captured HIP graph of the step")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); the method's "
+                          "multi-GPU sharding is described in DESIGN.md but not built"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2006_13053_amd as m
+    torch.cuda.set_device(0)
+    m.lib()
+
+    if args.workload == "large":
+        F = args.functions or 64
+        w = setup_large(m, torch, F, args.candidates)
+        cfg = dict(workload="large compressible: d=10, |I|=1e7 per function in [-512,512]^10, "
+                            "c_k=(1+|k|_1)^-2 x unit phase + 1000 dominants of modulus 10, L=20, "
+                            "M=16001, complex128, theta=1", functions=F, candidates_per_function=args.candidates,
+                   lattices=20, M=16001, d=10)
+        dtype = "c128"
+    else:
+        F = args.functions or 512
+        w = setup_batch(m, torch, F, c64=args.c64)
+        cfg = dict(workload="batched: 512 functions, d=10, s log-uniform [10,1000], |I| log-uniform "
+                            "[1e3,1e6] from [-128,128]^10, L=8, M primes in [8s,16s], noise-free",
+                   functions=F, candidates_total=int(w["gam"].shape[1]), lattices=8, d=10)
+        dtype = "c64" if args.c64 else "c128"
+
+    log("setup done; warming up")
+    step, ex, ghat = make_step(m, w)
+    plan = w["plan"]
+    n_total = int(w["gam"].shape[1])
+    L = w["L"]
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if args.graph:
+        s = torch.cuda.Stream()
+        plan.set_stream(s)
+        with torch.cuda.stream(s):
+            step()
+            s.synchronize()
+            graph = m.Graph(plan)
+            with graph:
+                step()
+            s.synchronize()
+
+            def run():
+                graph.launch(s)
+        runner = run
+    else:
+        runner = step
+
+    plan.profile(not args.graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        runner()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = plan.profile_read() if not args.graph else {}
+    plan.profile(False)
+    ms_step = 1000.0 * elapsed / args.steps
+    value = n_total * L / (elapsed / args.steps)
+
+    out = {"metric": "candidates\u00b7lattices hashed+extracted/s and functions/s, batched vs plain, "
+                     "at rel err \u22641e-11",
+           "value": value, "unit": "candidates\u00b7lattices/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": cfg}
+    out["functions_per_s_batched"] = F / (elapsed / args.steps)
+    if stages:
+        out["stages_ms"] = {k: (v[0] / v[1] if v[1] else None) for k, v in stages.items()}
+        vote_ms = out["stages_ms"]["vote"]
+        nd = ex["n_det"].cpu().numpy()
+        algo_bytes = 8.0 * w["d"] * n_total + 8.0 * float(np.minimum(nd, w["cap"]).sum())
+        achieved = algo_bytes / (vote_ms * 1e-3) / 1e9
+        traffic = None
+        if os.path.exists(PMC_FILE):
+            with open(PMC_FILE) as fh:
+                pmc = json.load(fh)
+            if pmc.get("source_hash") == vote_source_hash() and pmc.get("workload") == args.workload:
+                traffic = pmc.get("bytes_per_launch")
+        out["roofline"] = {"bound": "hbm", "kernel": "k_vote (hash + vote + compaction)", "achieved": achieved,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": traffic, "algorithmic_bytes_per_launch": algo_bytes,
+                           "vote_ms_per_launch": vote_ms}
+        fft_ms = out["stages_ms"]["fft"]
+        fft_bytes = 2.0 * 16 * plan.nodes if dtype == "c128" else 2.0 * 8 * plan.nodes
+        out["fft_roofline"] = {"achieved": fft_bytes / (fft_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "algorithmic_bytes_per_launch": fft_bytes}
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
+    if not args.no_plain:
+        t_plain, _ = plain_pass(m, torch, w)
+        log(f"plain per-function loop: {1000 * t_plain:.3f} ms")
+        out["functions_per_s_plain"] = F / t_plain
+        out["plain_ms_per_pass"] = 1000.0 * t_plain
+    if not args.no_cpu and args.workload == "large":
+        n_sample = min(1_000_000, w["n"])
+        log("oracle leg (CPU) ...")
+        cpu, ro, g_exact = cpu_baseline_large(w, n_sample)
+        out["cpu_baseline"] = cpu
+        out["parity"] = parity_large(m, torch, w, ex, ghat, ro, g_exact, n_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -195,8 +195,11 @@ static int build_tables(Plan &p)
     p.lds_lats.clear();
     p.big_lats.clear();
     p.big_maxN = 0;
+    bool all16 = true;
+    for (auto m : p.M) all16 = all16 && m <= (int64_t(1) << 15);
     for (int f = 0; f < p.F; ++f) {
-        const int32_t kb = fast_bound(p.d, p.M.data() + (size_t)f * p.L, p.L);
+        int32_t kb = fast_bound(p.d, p.M.data() + (size_t)f * p.L, p.L);
+        if (all16) kb = std::min<int32_t>(kb, 32767);   // k_u must fit the 16-bit dot products
         p.kb.push_back(kb);
         for (int l = 0; l < p.L; ++l) {
             const int64_t i = (int64_t)f * p.L + l;
@@ -246,6 +249,19 @@ static int upload(Plan &p)
     MR1L_HIP(hipMemcpy(p.d_z32, z32.data(), z32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     MR1L_HIP(hipMalloc(&p.d_z64, p.z.size() * sizeof(int64_t)));
     MR1L_HIP(hipMemcpy(p.d_z64, p.z.data(), p.z.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    // packed 16-bit pairs of z for the dot2 hash (valid when every M <= 2^15)
+    p.dot2 = true;
+    for (auto m : p.M) p.dot2 = p.dot2 && m <= (int64_t(1) << 15);
+    if (p.dot2) {
+        const int dh = (p.d + 1) / 2;
+        const int64_t nl = (int64_t)p.F * p.L;
+        std::vector<uint32_t> z16((size_t)nl * dh, 0u);
+        for (int64_t i = 0; i < nl; ++i)
+            for (int u = 0; u < p.d; ++u)
+                z16[(size_t)i * dh + u / 2] |= (uint32_t)(p.z[(size_t)i * p.d + u] & 0xffff) << (16 * (u & 1));
+        MR1L_HIP(hipMalloc(&p.d_z16, z16.size() * sizeof(uint32_t)));
+        MR1L_HIP(hipMemcpy(p.d_z16, z16.data(), z16.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
     MR1L_HIP(hipMalloc(&p.d_kb, p.kb.size() * sizeof(int32_t)));
     MR1L_HIP(hipMemcpy(p.d_kb, p.kb.data(), p.kb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!p.lds_lats.empty()) {
@@ -270,7 +286,7 @@ static int upload(Plan &p)
 
 static void release(Plan *p)
 {
-    void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_spec, p->d_chirp, p->d_tw,
+    void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_spec, p->d_chirp, p->d_tw,
                     p->d_lds_lats, p->d_big_lats, p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
                     p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
                     p->d_termoff_default};
@@ -343,6 +359,7 @@ int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int6
     if (!attrs_done) {
         fft_init_attrs();
         extract_init_attrs();
+        vote_init_attrs();
         attrs_done = true;
     }
     mr1l_plan_s *p = new (std::nothrow) mr1l_plan_s();
@@ -394,6 +411,16 @@ int mr1l_plan_set_z(mr1l_plan p, const int64_t *z)
     MR1L_HIP(hipMemcpyAsync(p->d_z32, z32.data(), z32.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
     MR1L_HIP(hipMemcpyAsync(p->d_z64, p->z.data(), p->z.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                             p->stream));
+    std::vector<uint32_t> z16;
+    if (p->dot2) {
+        const int dh = (p->d + 1) / 2;
+        z16.assign((size_t)nl * dh, 0u);
+        for (int64_t i = 0; i < nl; ++i)
+            for (int u = 0; u < p->d; ++u)
+                z16[(size_t)i * dh + u / 2] |= (uint32_t)(p->z[(size_t)i * p->d + u] & 0xffff) << (16 * (u & 1));
+        MR1L_HIP(hipMemcpyAsync(p->d_z16, z16.data(), z16.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                p->stream));
+    }
     MR1L_HIP(hipStreamSynchronize(p->stream));
     return MR1L_OK;
 }
@@ -476,6 +503,7 @@ int mr1l_extract(mr1l_plan p, int64_t n_total, const int64_t *set_off, const int
     if (!dpos) dpos = p->d_ex_pos;
     (void)dmed;
     (void)esz;
+    if ((rc = launch_fill_bytes(out->n_det, (int64_t)sizeof(int64_t) * p->F, p->stream))) return rc;
     {
         StageTimer tm(*p, MR1L_STAGE_VOTE);
         rc = vote_run(*p, n_total, set_off, freq, nz_bitmap, vmin, cap, out->n_det, out->det_idx, out->votes);

@@ -55,34 +55,40 @@ __device__ __forceinline__ int func_of(const int64_t *set_off, int F, int64_t i)
 }
 
 // ------------------------------------------------------------------ vote
-constexpr int kVoteThreads = 256;
-constexpr int kVoteLdsWords = 16384;   // 64 KiB of bitmap words per workgroup
+constexpr int kVoteThreads = 512;
+constexpr int kVoteCPT = 1;                   // candidates per thread
+constexpr int kVoteLdsWords = 20480;          // 80 KiB: two workgroups per CU
 
-// Candidate range of this workgroup: contiguous share of [0, n_total).
-template <int D, bool VOTES, bool LDS_BITS>
+// Each workgroup owns a contiguous, tile-aligned range of the concatenated
+// candidate sets; the current function's bitmap words sit in LDS (reloaded at
+// function boundaries).  Thread t of a tile handles candidates 2t and 2t + 1.
+template <int D, bool LDSB, int CPT, bool DOT2>
 __global__ __launch_bounds__(kVoteThreads) void k_vote(
     const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int F,
     int L, int d_rt, const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32,
-    const int64_t *__restrict__ z64, const int32_t *__restrict__ kbound,
-    const uint32_t *__restrict__ bitmap, int vote_min, int64_t cap, int64_t *__restrict__ det_cnt,
-    int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes)
+    const int64_t *__restrict__ z64, const uint32_t *__restrict__ z16, const int32_t *__restrict__ kbound,
+    const uint32_t *__restrict__ bitmap, int vote_min, int64_t cap,
+    int64_t *__restrict__ det_cnt, int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes, int aligned)
 {
     const int d = D > 0 ? D : d_rt;
-    __shared__ uint32_t bits[LDS_BITS ? kVoteLdsWords : 1];
+    constexpr int DM = D > 0 ? D : kMaxD;
+    extern __shared__ __align__(16) uint32_t bits[];
     __shared__ int s_f;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int64_t per = (n_total + gridDim.x - 1) / gridDim.x;
-    const int64_t beg = (int64_t)blockIdx.x * per;
-    const int64_t end = min(n_total, beg + per);
+    constexpr int TILE = kVoteThreads * CPT;
+    const int64_t ntiles = (n_total + TILE - 1) / TILE;
+    const int64_t tper = (ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * tper * TILE;
+    const int64_t end = min(n_total, beg + tper * TILE);
+    const bool want_votes = votes != nullptr;
     int cur_f = -1;
-    int64_t f_lo = 0, f_hi = 0;      // candidate range of cur_f
-    int64_t word0 = 0;               // first bitmap word of cur_f
+    int64_t f_lo = 0, f_hi = 0;
+    int64_t word0 = 0;
 
-    for (int64_t t0 = beg; t0 < end; t0 += kVoteThreads) {
-        // function segments inside this tile
+    for (int64_t t0 = beg; t0 < end; t0 += TILE) {
+        const int64_t tend = min(end, t0 + TILE);
         int64_t seg = t0;
-        const int64_t tend = min(end, t0 + kVoteThreads);
         while (seg < tend) {
             if (!(seg >= f_lo && seg < f_hi)) {
                 if (tid == 0) s_f = func_of(set_off, F, seg);
@@ -94,7 +100,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
                 const LatDesc l0 = lat[cur_f * L];
                 const LatDesc lL = lat[cur_f * L + L - 1];
                 word0 = l0.node_off >> 5;
-                if (LDS_BITS) {
+                if (LDSB) {
                     const int64_t wN = ((lL.node_off + lL.M - 1) >> 5) - word0 + 1;
                     for (int64_t w = tid; w < wN; w += kVoteThreads) bits[w] = bitmap[word0 + w];
                     __syncthreads();
@@ -102,102 +108,209 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
             }
             if (f_hi <= seg) break;   // inconsistent offsets: stop instead of spinning
             const int64_t sEnd = min(tend, f_hi);
-            // thread tid handles candidate t0 + tid if it lies in [seg, sEnd)
-            const int64_t ci = t0 + tid;
-            const bool valid = (ci >= seg) && (ci < sEnd);
             const int f = __builtin_amdgcn_readfirstlane(cur_f);
-            int v = 0;
-            if (valid) {
-                int32_t lo[D > 0 ? D : kMaxD];
-                bool fast = true;
-                const int32_t kb = kbound[f];
+            const int64_t c0 = t0 + CPT * tid;
+            bool val[CPT];
+            int32_t lo[CPT][DM];
+            bool fast[CPT];
+            const int32_t kb = kbound[f];
 #pragma unroll
-                for (int u = 0; u < (D > 0 ? D : kMaxD); ++u) {
-                    if (u < d) {
-                        const int64_t k = freq[(int64_t)u * n_total + ci];
-                        lo[u] = (int32_t)k;
-                        fast = fast && (k >= -kb) && (k <= kb);
+            for (int c = 0; c < CPT; ++c) {
+                val[c] = (c0 + c >= seg) && (c0 + c < sEnd);
+                fast[c] = true;
+            }
+            // coalesced loads of the thread's candidates, one column per coordinate
+#pragma unroll
+            for (int u = 0; u < DM; ++u) {
+                if (u < d) {
+                    const int64_t *row = freq + (int64_t)u * n_total;
+                    int64_t k[CPT];
+                    if constexpr (CPT == 2) {
+                        if (aligned && val[0] && val[1]) {
+                            const longlong2 vv = *reinterpret_cast<const longlong2 *>(row + c0);
+                            k[0] = vv.x;
+                            k[1] = vv.y;
+                        } else {
+                            k[0] = val[0] ? row[c0] : 0;
+                            k[1] = val[1] ? row[c0 + 1] : 0;
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c) k[c] = val[c] ? __builtin_nontemporal_load(row + c0 + c) : 0;
+                    }
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) {
+                        lo[c][u] = (int32_t)k[c];
+                        fast[c] = fast[c] && (k[c] >= -kb) && (k[c] <= kb);
                     }
                 }
-                const LatDesc *lf = lat + f * L;
-                if (fast) {
+            }
+            int v[CPT];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) v[c] = 0;
+            const LatDesc *lf = lat + f * L;
+            // fast path for candidates within the 24-bit bound (all but adversarial inputs)
+            bool act[CPT], any = false;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                act[c] = val[c] && fast[c];
+                any = any || act[c];
+            }
+            if (any) {
+                // lattice constants are wave-uniform; the next lattice's are loaded while
+                // the current one is hashed
+                constexpr int ZW = DOT2 ? (DM + 1) / 2 : DM;     // z words per lattice
+                const int zw = DOT2 ? (d + 1) / 2 : d;
+                const int32_t *zf = DOT2 ? reinterpret_cast<const int32_t *>(z16) + (int64_t)f * L * zw
+                                         : z32 + (int64_t)f * L * d;
+                // k as packed 16-bit pairs for the dot2 path
+                uint32_t kp[CPT][(DM + 1) / 2];
+                if constexpr (DOT2) {
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                        for (int j = 0; j < (DM + 1) / 2; ++j) {
+                            const uint32_t a = (2 * j < d) ? ((uint32_t)lo[c][2 * j] & 0xffffu) : 0u;
+                            const uint32_t b = (2 * j + 1 < d) ? ((uint32_t)lo[c][2 * j + 1] << 16) : 0u;
+                            kp[c][j] = a | b;
+                        }
+                }
+                LatDesc ld = lf[0];
+                int32_t zc[ZW];
+#pragma unroll
+                for (int u = 0; u < ZW; ++u) zc[u] = (u < zw) ? zf[u] : 0;
+                const int64_t fbit0 = word0 << 5;
+                for (int l = 0; l < L; ++l) {
+                    const int ln = (l + 1 < L) ? l + 1 : l;
+                    const LatDesc ldn = lf[ln];
+                    int32_t zn[ZW];
+#pragma unroll
+                    for (int u = 0; u < ZW; ++u) zn[u] = (u < zw) ? zf[ln * zw + u] : 0;
+                    const uint32_t bbase = (uint32_t)(ld.node_off - fbit0);   // bit of bucket 0 in the function
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) {
+                        uint32_t s = ld.off32;
+                        if constexpr (DOT2) {
+                            typedef short v2s __attribute__((ext_vector_type(2)));
+#pragma unroll
+                            for (int j = 0; j < ZW; ++j)
+                                if (j < zw)
+                                    s = (uint32_t)__builtin_amdgcn_sdot2(__builtin_bit_cast(v2s, kp[c][j]),
+                                                                         __builtin_bit_cast(v2s, zc[j]), (int)s,
+                                                                         false);
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < DM; ++u)
+                                if (u < d) s += (uint32_t)__mul24(lo[c][u], zc[u]);
+                        }
+                        const uint32_t g = bbase + fast_mod(s, (uint32_t)ld.M, ld.inv_m);
+                        uint32_t word;
+                        if constexpr (LDSB) word = bits[g >> 5];
+                        else word = bitmap[word0 + (g >> 5)];
+                        v[c] += act[c] ? (int)((word >> (g & 31)) & 1u) : 0;
+                    }
+                    ld = ldn;
+#pragma unroll
+                    for (int u = 0; u < ZW; ++u) zc[u] = zn[u];
+                    if (!want_votes) {
+                        // leave once every candidate of the wave has reached vote_min or can no longer
+                        const int rest = L - 1 - l;
+                        bool decided = true;
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c)
+                            decided = decided && (!act[c] || v[c] >= vote_min || v[c] + rest < vote_min);
+                        if (__all(decided)) break;
+                    }
+                }
+            }
+            // exact 64-bit path for candidates beyond the bound (rare, divergent)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                if (val[c] && !fast[c]) {
                     for (int l = 0; l < L; ++l) {
                         const LatDesc ld = lf[l];
-                        const int32_t *zl = z32 + ld.z_off;
-                        uint32_t s = ld.off32;
-#pragma unroll
-                        for (int u = 0; u < (D > 0 ? D : kMaxD); ++u)
-                            if (u < d) s += (uint32_t)__mul24(lo[u], zl[u]);
-                        const uint32_t h = fast_mod(s, (uint32_t)ld.M, ld.inv_m);
+                        const int32_t h = exact_bucket(freq + c0 + c, n_total, d, z64 + ld.z_off, ld.M);
                         const int64_t g = ld.node_off + h;
                         uint32_t word;
-                        if (LDS_BITS) word = bits[(g >> 5) - word0];
+                        if constexpr (LDSB) word = bits[(g >> 5) - word0];
                         else word = bitmap[g >> 5];
-                        v += (word >> (g & 31)) & 1u;
-                        if (!VOTES) {
-                            // cannot reach vote_min any more: leave the loop
-                            const bool hopeless = (v + (L - 1 - l)) < vote_min;
-                            const bool done = v >= vote_min;
-                            if (__all(hopeless || done)) break;
-                        }
-                    }
-                } else {
-                    for (int l = 0; l < L; ++l) {
-                        const LatDesc ld = lf[l];
-                        const int32_t h = exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
-                        const int64_t g = ld.node_off + h;
-                        v += (bitmap[g >> 5] >> (g & 31)) & 1u;
+                        v[c] += (word >> (g & 31)) & 1u;
                     }
                 }
-                if (VOTES) votes[ci] = (uint8_t)v;
             }
-            // ordered compaction is done later by a sort; here: wave-aggregated append
-            const bool det = valid && v >= vote_min;
-            const uint64_t bal = __ballot(det);
-            if (bal) {
-                const int cnt = __popcll(bal);
-                const int first = __ffsll((unsigned long long)bal) - 1;
-                const int rank = __popcll(bal & ((1ull << lane) - 1ull));
-                unsigned long long base = 0;
-                if (lane == first) base = atomicAdd((unsigned long long *)(det_cnt + f), (unsigned long long)cnt);
-                base = __shfl(base, first);
-                if (det && (int64_t)(base + rank) < cap) det_idx[f * cap + base + rank] = ci - f_lo;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                if (want_votes && val[c]) votes[c0 + c] = (uint8_t)v[c];
+                const bool det = val[c] && v[c] >= vote_min;
+                const uint64_t bal = __ballot(det);
+                if (bal) {
+                    const int cnt = __popcll(bal);
+                    const int first = __ffsll((unsigned long long)bal) - 1;
+                    const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+                    unsigned long long base = 0;
+                    if (lane == first)
+                        base = atomicAdd((unsigned long long *)(det_cnt + f), (unsigned long long)cnt);
+                    base = __shfl(base, first);
+                    if (det && (int64_t)(base + rank) < cap) det_idx[f * cap + base + rank] = c0 + c - f_lo;
+                }
             }
             seg = sEnd;
         }
     }
 }
 
-#define MR1L_VOTE_DISPATCH(Dv)                                                                    \
-    case Dv:                                                                                      \
-        if (votes) {                                                                              \
-            if (lds) hipLaunchKernelGGL((k_vote<Dv, true, true>), grid, blk, 0, p.stream, ARGS);  \
-            else hipLaunchKernelGGL((k_vote<Dv, true, false>), grid, blk, 0, p.stream, ARGS);     \
-        } else {                                                                                  \
-            if (lds) hipLaunchKernelGGL((k_vote<Dv, false, true>), grid, blk, 0, p.stream, ARGS); \
-            else hipLaunchKernelGGL((k_vote<Dv, false, false>), grid, blk, 0, p.stream, ARGS);    \
-        }                                                                                         \
+#define MR1L_VOTE_LAUNCH(Dv, LD, D2)                                                                 \
+    hipLaunchKernelGGL((k_vote<Dv, LD, kVoteCPT, D2>), grid, blk, LD ? shm : 0, p.stream, freq, n_total,  \
+                       set_off, p.F, p.L, p.d, p.d_lat, p.d_z32, p.d_z64, p.d_z16, p.d_kb, bitmap,         \
+                       vote_min, cap, n_det, det_idx, votes, aligned)
+#define MR1L_VOTE_DISPATCH(Dv)                                          \
+    case Dv:                                                            \
+        if (lds) {                                                      \
+            if (p.dot2) MR1L_VOTE_LAUNCH(Dv, true, true);               \
+            else MR1L_VOTE_LAUNCH(Dv, true, false);                     \
+        } else {                                                        \
+            if (p.dot2) MR1L_VOTE_LAUNCH(Dv, false, true);              \
+            else MR1L_VOTE_LAUNCH(Dv, false, false);                    \
+        }                                                               \
         break;
+
+void vote_init_attrs()
+{
+#define MR1L_VOTE_ATTR(Dv)                                                                        \
+    (void)hipFuncSetAttribute((const void *)k_vote<Dv, true, kVoteCPT, true>,                          \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsWords * 4);          \
+    (void)hipFuncSetAttribute((const void *)k_vote<Dv, true, kVoteCPT, false>,                         \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsWords * 4);
+    MR1L_VOTE_ATTR(0) MR1L_VOTE_ATTR(1) MR1L_VOTE_ATTR(2) MR1L_VOTE_ATTR(3) MR1L_VOTE_ATTR(4)
+    MR1L_VOTE_ATTR(5) MR1L_VOTE_ATTR(6) MR1L_VOTE_ATTR(7) MR1L_VOTE_ATTR(8) MR1L_VOTE_ATTR(9)
+    MR1L_VOTE_ATTR(10) MR1L_VOTE_ATTR(12) MR1L_VOTE_ATTR(16) MR1L_VOTE_ATTR(20) MR1L_VOTE_ATTR(25)
+    MR1L_VOTE_ATTR(30)
+#undef MR1L_VOTE_ATTR
+}
 
 int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
              const uint32_t *bitmap, int32_t vote_min, int64_t cap, int64_t *n_det, int64_t *det_idx,
              uint8_t *votes)
 {
-    int rc = launch_fill_bytes(n_det, sizeof(int64_t) * p.F, p.stream);
-    if (rc) return rc;
+    // n_det is zero-filled by the caller (outside the timed vote stage)
     if (n_total <= 0) return MR1L_OK;
-    // LDS bitmap when every function's lattice bits fit 64 KiB
+    // LDS bitmap when every function's lattice bits fit
     int64_t maxw = 0;
     for (int f = 0; f < p.F; ++f) {
         const LatDesc &a = p.lat[(size_t)f * p.L], &b = p.lat[(size_t)f * p.L + p.L - 1];
         maxw = std::max<int64_t>(maxw, ((b.node_off + b.M - 1) >> 5) - (a.node_off >> 5) + 1);
     }
     const bool lds = maxw <= kVoteLdsWords;
-    const int64_t want = (n_total + kVoteThreads - 1) / kVoteThreads;
-    const int64_t gridn = std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cus() * 8));
+    const size_t shm = lds ? (size_t)maxw * 4 : 0;
+    const int aligned = ((reinterpret_cast<uintptr_t>(freq) & 15) == 0 && (n_total & 1) == 0) ? 1 : 0;
+    const int64_t tiles = (n_total + kVoteThreads * kVoteCPT - 1) / (kVoteThreads * kVoteCPT);
+    // one co-resident workgroup per slot: no partial second round of workgroups
+    int per_cu = 0;
+    const void *kfn = lds ? (const void *)k_vote<10, true, kVoteCPT, true> : (const void *)k_vote<10, false, kVoteCPT, true>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kVoteThreads, shm) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t gridn = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)num_cus() * per_cu));
     dim3 grid((unsigned)gridn), blk(kVoteThreads);
-#define ARGS freq, n_total, set_off, p.F, p.L, p.d, p.d_lat, p.d_z32, p.d_z64, p.d_kb, bitmap, vote_min, \
-             cap, n_det, det_idx, votes
     switch (p.d) {
         MR1L_VOTE_DISPATCH(1)
         MR1L_VOTE_DISPATCH(2)
@@ -217,7 +330,6 @@ int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *fr
     default:
         MR1L_VOTE_DISPATCH(0)
     }
-#undef ARGS
     MR1L_LAUNCH_CHECK();
     return MR1L_OK;
 }

@@ -61,6 +61,8 @@ struct Plan {
     int32_t *d_z32 = nullptr;        // [F*L*d] z as int32
     int64_t *d_z64 = nullptr;        // [F*L*d] z as int64
     int32_t *d_kb = nullptr;         // [F]
+    uint32_t *d_z16 = nullptr;       // [F*L][ceil(d/2)] z as packed int16 pairs (M <= 2^15)
+    bool dot2 = false;               // every M <= 2^15: 16-bit packed dot products
     void *d_spec = nullptr;          // kernel spectra (dtype complex)
     void *d_chirp = nullptr;         // chirp tables (dtype complex)
     void *d_tw = nullptr;            // twiddle tables (dtype complex)
@@ -167,6 +169,7 @@ int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap,
 int fft_prepare_spectra(Plan &p);
 void fft_init_attrs();
 void extract_init_attrs();
+void vote_init_attrs();
 
 int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
              const uint32_t *bitmap, int32_t vote_min, int64_t cap, int64_t *n_det,
