@@ -238,6 +238,35 @@ static int build_tables(Plan &p)
     return MR1L_OK;
 }
 
+// Records of the vote pass (see Plan::d_vrec).
+static int build_vote_records(Plan &p, std::vector<uint32_t> &vr)
+{
+    const int zw = p.dot2 ? (p.d + 1) / 2 : p.d;
+    int rs = 1;
+    while (rs < zw + 4) rs <<= 1;
+    p.vrec_stride = rs;
+    vr.assign((size_t)p.F * (p.L + 1) * rs, 0u);
+    for (int f = 0; f < p.F; ++f) {
+        const int64_t word0 = p.lat[(size_t)f * p.L].node_off >> 5;
+        for (int l = 0; l <= p.L; ++l) {
+            const int ls = l < p.L ? l : p.L - 1;
+            const size_t i = (size_t)f * p.L + ls;
+            const LatDesc &ld = p.lat[i];
+            uint32_t *r = &vr[((size_t)f * (p.L + 1) + l) * rs];
+            for (int u = 0; u < p.d; ++u) {
+                const uint32_t zu = (uint32_t)p.z[i * p.d + u];
+                if (p.dot2) r[u / 2] |= (zu & 0xffffu) << (16 * (u & 1));
+                else r[u] = zu;
+            }
+            r[zw + 0] = ld.off32;
+            r[zw + 1] = (uint32_t)ld.M;
+            std::memcpy(&r[zw + 2], &ld.inv_m, 4);
+            r[zw + 3] = (uint32_t)(ld.node_off - (word0 << 5));
+        }
+    }
+    return MR1L_OK;
+}
+
 static int upload(Plan &p)
 {
     MR1L_HIP(hipMalloc(&p.d_lat, p.lat.size() * sizeof(LatDesc)));
@@ -263,6 +292,13 @@ static int upload(Plan &p)
         MR1L_HIP(hipMemcpy(p.d_z16, z16.data(), z16.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     }
     MR1L_HIP(hipMalloc(&p.d_kb, p.kb.size() * sizeof(int32_t)));
+    {
+        std::vector<uint32_t> vr;
+        int rc = build_vote_records(p, vr);
+        if (rc) return rc;
+        MR1L_HIP(hipMalloc(&p.d_vrec, vr.size() * sizeof(uint32_t)));
+        MR1L_HIP(hipMemcpy(p.d_vrec, vr.data(), vr.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
     MR1L_HIP(hipMemcpy(p.d_kb, p.kb.data(), p.kb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!p.lds_lats.empty()) {
         MR1L_HIP(hipMalloc(&p.d_lds_lats, p.lds_lats.size() * sizeof(int32_t)));
@@ -286,7 +322,7 @@ static int upload(Plan &p)
 
 static void release(Plan *p)
 {
-    void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_spec, p->d_chirp, p->d_tw,
+    void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_vrec, p->d_spec, p->d_chirp, p->d_tw,
                     p->d_lds_lats, p->d_big_lats, p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
                     p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
                     p->d_termoff_default};
@@ -421,6 +457,9 @@ int mr1l_plan_set_z(mr1l_plan p, const int64_t *z)
         MR1L_HIP(hipMemcpyAsync(p->d_z16, z16.data(), z16.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                                 p->stream));
     }
+    std::vector<uint32_t> vr;
+    (void)build_vote_records(*p, vr);
+    MR1L_HIP(hipMemcpyAsync(p->d_vrec, vr.data(), vr.size() * sizeof(uint32_t), hipMemcpyHostToDevice, p->stream));
     MR1L_HIP(hipStreamSynchronize(p->stream));
     return MR1L_OK;
 }

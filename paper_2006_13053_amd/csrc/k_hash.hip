@@ -66,7 +66,7 @@ template <int D, bool LDSB, int CPT, bool DOT2>
 __global__ __launch_bounds__(kVoteThreads) void k_vote(
     const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int F,
     int L, int d_rt, const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32,
-    const int64_t *__restrict__ z64, const uint32_t *__restrict__ z16, const int32_t *__restrict__ kbound,
+    const int64_t *__restrict__ z64, const uint32_t *__restrict__ vrec, int rs, const int32_t *__restrict__ kbound,
     const uint32_t *__restrict__ bitmap, int vote_min, int64_t cap,
     int64_t *__restrict__ det_cnt, int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes, int aligned)
 {
@@ -156,14 +156,15 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
                 act[c] = val[c] && fast[c];
                 any = any || act[c];
             }
-            if (any) {
-                // lattice constants are wave-uniform; the next lattice's are loaded while
-                // the current one is hashed
-                constexpr int ZW = DOT2 ? (DM + 1) / 2 : DM;     // z words per lattice
+            if (__any(any)) {   // wave-uniform, so the record loads stay scalar
+                // one contiguous record per lattice (wave-uniform); the next record is
+                // loaded while the current lattice is hashed (record L is a padding copy)
+                constexpr int ZW = DOT2 ? (DM + 1) / 2 : DM;
                 const int zw = DOT2 ? (d + 1) / 2 : d;
-                const int32_t *zf = DOT2 ? reinterpret_cast<const int32_t *>(z16) + (int64_t)f * L * zw
-                                         : z32 + (int64_t)f * L * d;
-                // k as packed 16-bit pairs for the dot2 path
+                // constant address space: uniform loads of the read-only records go through
+                // the scalar cache
+                typedef const __attribute__((address_space(4))) uint32_t *crec_t;
+                crec_t rec = (crec_t)(uintptr_t)(vrec + (int64_t)f * (L + 1) * rs);
                 uint32_t kp[CPT][(DM + 1) / 2];
                 if constexpr (DOT2) {
 #pragma unroll
@@ -175,21 +176,23 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
                             kp[c][j] = a | b;
                         }
                 }
-                LatDesc ld = lf[0];
-                int32_t zc[ZW];
+                uint32_t zc[ZW + 4];
 #pragma unroll
-                for (int u = 0; u < ZW; ++u) zc[u] = (u < zw) ? zf[u] : 0;
-                const int64_t fbit0 = word0 << 5;
+                for (int u = 0; u < ZW; ++u) zc[u] = (u < zw) ? rec[u] : 0u;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) zc[ZW + u] = rec[zw + u];
                 for (int l = 0; l < L; ++l) {
-                    const int ln = (l + 1 < L) ? l + 1 : l;
-                    const LatDesc ldn = lf[ln];
-                    int32_t zn[ZW];
+                    rec += rs;
+                    uint32_t zn[ZW + 4];
 #pragma unroll
-                    for (int u = 0; u < ZW; ++u) zn[u] = (u < zw) ? zf[ln * zw + u] : 0;
-                    const uint32_t bbase = (uint32_t)(ld.node_off - fbit0);   // bit of bucket 0 in the function
+                    for (int u = 0; u < ZW; ++u) zn[u] = (u < zw) ? rec[u] : 0u;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) zn[ZW + u] = rec[zw + u];
+                    const uint32_t off32 = zc[ZW], Mm = zc[ZW + 1], bbase = zc[ZW + 3];
+                    const float inv_m = __uint_as_float(zc[ZW + 2]);
 #pragma unroll
                     for (int c = 0; c < CPT; ++c) {
-                        uint32_t s = ld.off32;
+                        uint32_t s = off32;
                         if constexpr (DOT2) {
                             typedef short v2s __attribute__((ext_vector_type(2)));
 #pragma unroll
@@ -201,19 +204,20 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
                         } else {
 #pragma unroll
                             for (int u = 0; u < DM; ++u)
-                                if (u < d) s += (uint32_t)__mul24(lo[c][u], zc[u]);
+                                if (u < d) s += (uint32_t)__mul24(lo[c][u], (int32_t)zc[u]);
                         }
-                        const uint32_t g = bbase + fast_mod(s, (uint32_t)ld.M, ld.inv_m);
+                        const uint32_t g = bbase + fast_mod(s, Mm, inv_m);
                         uint32_t word;
                         if constexpr (LDSB) word = bits[g >> 5];
                         else word = bitmap[word0 + (g >> 5)];
-                        v[c] += act[c] ? (int)((word >> (g & 31)) & 1u) : 0;
+                        // bit g mod 32 (the extract uses the low five bits of the offset)
+                        v[c] += act[c] ? (int)__builtin_amdgcn_ubfe(word, g, 1) : 0;
                     }
-                    ld = ldn;
 #pragma unroll
-                    for (int u = 0; u < ZW; ++u) zc[u] = zn[u];
-                    if (!want_votes) {
+                    for (int u = 0; u < ZW + 4; ++u) zc[u] = zn[u];
+                    if (!want_votes && l >= L - vote_min) {
                         // leave once every candidate of the wave has reached vote_min or can no longer
+                        // (no candidate can be hopeless before lattice L - vote_min)
                         const int rest = L - 1 - l;
                         bool decided = true;
 #pragma unroll
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
 
 #define MR1L_VOTE_LAUNCH(Dv, LD, D2)                                                                 \
     hipLaunchKernelGGL((k_vote<Dv, LD, kVoteCPT, D2>), grid, blk, LD ? shm : 0, p.stream, freq, n_total,  \
-                       set_off, p.F, p.L, p.d, p.d_lat, p.d_z32, p.d_z64, p.d_z16, p.d_kb, bitmap,         \
+                       set_off, p.F, p.L, p.d, p.d_lat, p.d_z32, p.d_z64, p.d_vrec, p.vrec_stride, p.d_kb, bitmap,         \
                        vote_min, cap, n_det, det_idx, votes, aligned)
 #define MR1L_VOTE_DISPATCH(Dv)                                          \
     case Dv:                                                            \
