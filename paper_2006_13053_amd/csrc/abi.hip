@@ -167,26 +167,27 @@ static int build_tables(Plan &p)
         const int32_t mid = (int32_t)p.mdesc.size();
         mid_of[M] = mid;
         MDesc md{};
-        const int64_t N = next_smooth(std::max<int64_t>(2 * M - 1, 2));
+        int64_t N = next_smooth(std::max<int64_t>(2 * M - 1, 2));
         int64_t N1 = N, N2 = 1;
         if (N > NMAX) {
-            // most balanced split with both factors in LDS
-            int64_t best = -1;
-            for (int64_t a = 2; a <= NMAX; ++a)
-                if (N % a == 0 && N / a <= NMAX) {
-                    if (best < 0 || std::llabs(a - N / a) < std::llabs(best - N / best)) best = a;
-                }
-            if (best < 0) return fail(MR1L_E_OVERFLOW, "lattice size too large for the DFT");
-            N1 = best;
-            N2 = N / best;
+            // beyond one LDS transform: power-of-two N = N1 N2 (four-step, both halves in LDS)
+            int k = 0;
+            while ((int64_t(1) << k) < 2 * M - 1) ++k;
+            N = int64_t(1) << k;
+            N1 = int64_t(1) << ((k + 1) / 2);
+            N2 = N / N1;
+            if (N1 > (sizeof(T) == 8 ? 4096 : 8192)) return fail(MR1L_E_OVERFLOW, "lattice size too large for the DFT");
+            // the sub-transform twiddles (max(N1, N2) <= 256 entries) and the chirp table
+            // (<= 384 entries) go to LDS when every large lattice allows it (M <= 32768)
+            if (N1 > 256 || M > 32768) p.big_ltab = false;
         }
         md.spec_off = spec_len;
         spec_len += N;
         md.chirp_off = (int64_t)ch.size() / 2;
         push_chirp(ch, M, md.chirp_shift, md.chirp_nlo);
-        md.tw_N = twoff(N);
-        md.tw_N1 = N2 > 1 ? twoff(N1) : md.tw_N;
-        md.tw_N2 = N2 > 1 ? twoff(N2) : md.tw_N;
+        md.tw_N = twoff(N);          // sub-transforms of the four-step path index this table
+        md.tw_N1 = md.tw_N;
+        md.tw_N2 = md.tw_N;
         p.mdesc.push_back(md);
         mN.push_back({(int32_t)N, (int32_t)N1, (int32_t)N2});
     }
@@ -310,7 +311,7 @@ static int upload(Plan &p)
         MR1L_HIP(hipMalloc(&p.d_big_lats, p.big_lats.size() * sizeof(int32_t)));
         MR1L_HIP(hipMemcpy(p.d_big_lats, p.big_lats.data(), p.big_lats.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice));
-        p.fft_slots = std::min<int>((int)p.big_lats.size(), num_cus());
+        p.fft_slots = std::min<int>((int)p.big_lats.size(), 2 * num_cus());
         MR1L_HIP(hipMalloc(&p.d_fft_scratch, (size_t)p.fft_slots * 2 * (size_t)p.big_maxN * esz));
     }
     MR1L_HIP(hipMalloc(&p.d_nodes_scratch, (size_t)std::max<int64_t>(p.nodes, 1) * esz));

@@ -77,6 +77,7 @@ struct Plan {
     std::vector<int32_t> lds_lats, big_lats;
     int32_t *d_lds_lats = nullptr, *d_big_lats = nullptr;
     int32_t big_maxN = 0;
+    bool big_ltab = true;            // four-step twiddle/chirp tables fit the LDS
     // scratch
     void *d_fft_scratch = nullptr;   // [slots][big_maxN] complex (four-step)
     int32_t fft_slots = 0;

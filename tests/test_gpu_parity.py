@@ -150,7 +150,8 @@ def test_hash_count_batched_functions(m):
 
 # ------------------------------------------------------------------ DFT
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-@pytest.mark.parametrize("Ms", [[2, 3, 5, 7], [163, 211, 317], [1009, 4133], [5113, 5119], [16001], [15991, 12007]])
+@pytest.mark.parametrize("Ms", [[2, 3, 5, 7], [163, 211, 317], [1009, 4133], [5113, 5119], [16001], [15991, 12007],
+                                [40009], [131071]])
 def test_fft_matches_direct_dft(m, Ms, dtype):
     say("fft", Ms, dtype)
     rng = np.random.default_rng(sum(Ms))
