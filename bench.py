@@ -236,6 +236,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-function loop")
     ap.add_argument("--graph", action="store_true", help="time a captured HIP graph of the step")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the steps, copy 2 GiB once (a plain copy kernel of known size, used to scale "
+                         "the FETCH_SIZE / WRITE_SIZE counters of profiled runs)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -341,6 +344,12 @@ def main():
         cpu, ro, g_exact = cpu_baseline_large(w, n_sample)
         out["cpu_baseline"] = cpu
         out["parity"] = parity_large(m, torch, w, ex, ghat, ro, g_exact, n_sample)
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = int(a.numel() * 8)
     print(json.dumps(out), flush=True)
 
 
