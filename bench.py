@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-function loop")
     ap.add_argument("--graph", action="store_true", help="time a captured HIP graph of the step")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default DFT schedules instead of autotuning them before the timed steps")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the steps, copy 2 GiB once (a plain copy kernel of known size, used to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of profiled runs)")
@@ -269,9 +271,16 @@ def main():
                    functions=F, candidates_total=int(w["gam"].shape[1]), lattices=8, d=10)
         dtype = "c64" if args.c64 else "c128"
 
+    plan = w["plan"]
+    tune = None
+    if not args.no_tune and len(np.unique(plan.M)) <= 64:
+        tune = plan.fft_tune(reps=3)
+        log("DFT schedules (ms per batched DFT): " + json.dumps(tune))
+        for pf in w["plans"]:   # the per-function loop runs the same schedules
+            for M in np.unique(pf.M):
+                pf.fft_schedule(int(M), plan.fft_schedule(int(M)))
     log("setup done; warming up")
     step, ex, ghat = make_step(m, w)
-    plan = w["plan"]
     n_total = int(w["gam"].shape[1])
     L = w["L"]
     for _ in range(args.warmup):
@@ -312,6 +321,10 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": cfg}
     out["functions_per_s_batched"] = F / (elapsed / args.steps)
+    names = m.fft_schedule_names()
+    out["fft_schedules"] = {str(int(M)): names[plan.fft_schedule(int(M))] for M in np.unique(plan.M)[:8]}
+    if tune is not None:
+        out["fft_tune_ms"] = {str(k): v for k, v in list(tune.items())[:8]}
     if stages:
         out["stages_ms"] = {k: (v[0] / v[1] if v[1] else None) for k, v in stages.items()}
         vote_ms = out["stages_ms"]["vote"]

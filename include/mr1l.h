@@ -233,6 +233,36 @@ int mr1l_graph_end(mr1l_plan p, mr1l_graph *g);
 int mr1l_graph_launch(mr1l_graph g, void *stream);
 int mr1l_graph_destroy(mr1l_graph g);
 
+/*
+ * DFT schedules and their autotuner.  The lattice DFT of one size M runs under
+ * one schedule: 0 = the whole Bluestein transform (5-smooth length) in one
+ * workgroup's LDS, valid while that length fits; 1.. = power-of-two four-step
+ * transforms differing in workgroup size, LDS batch, workgroups per CU and the
+ * split N = N1 N2 (names from mr1l_fft_schedule_name).  Every schedule computes
+ * the same transform to within rounding.  A new plan starts each size on the
+ * schedule the autotuner chose for (dtype, M) earlier in the process, else on
+ * 0 where it applies, else on the default four-step schedule.
+ *
+ * mr1l_plan_fft_schedule: sched < 0 returns the schedule of size M in the
+ * plan; otherwise sets it (MR1L_E_ARG if M is not a size of the plan or the
+ * schedule does not apply to it) and returns it.  Synchronises the plan's
+ * stream and may grow the plan's scratch; graphs recorded earlier must be
+ * recorded again.
+ *
+ * mr1l_fft_tune: for every distinct size of the plan, times each applicable
+ * schedule on the plan's own lattices of that size (one warm-up run, then the
+ * mean of reps runs, HIP events on the plan's stream), keeps the fastest and
+ * records it for later plans of this process.  sizes (host [max_sizes] or
+ * NULL) receives the distinct sizes in the order used; times_ms (host
+ * [max_sizes][mr1l_fft_schedule_count()] or NULL) the mean milliseconds per
+ * run, -1 where a schedule does not apply.  Allocates and frees two
+ * node-sized buffers; synchronises the plan's stream.
+ */
+int mr1l_fft_schedule_count(void);
+const char *mr1l_fft_schedule_name(int32_t sched);
+int mr1l_plan_fft_schedule(mr1l_plan p, int64_t M, int32_t sched);
+int mr1l_fft_tune(mr1l_plan p, int32_t reps, int32_t max_sizes, int64_t *sizes, float *times_ms);
+
 /* Parameters of the dimension-incremental driver. */
 typedef struct {
     int32_t d;         /* spatial dimension of the function                */

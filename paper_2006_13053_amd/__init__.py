@@ -76,6 +76,10 @@ SIGNATURES = {
     "mr1l_profile": ([_P, _I32], C.c_int),
     "mr1l_profile_read": ([_P, _P, _P], C.c_int),
     "mr1l_num_lattices": ([_I64, _D, _D], _I32),
+    "mr1l_fft_schedule_count": ([], C.c_int),
+    "mr1l_fft_schedule_name": ([_I32], C.c_char_p),
+    "mr1l_plan_fft_schedule": ([_P, _I64, _I32], C.c_int),
+    "mr1l_fft_tune": ([_P, _I32, _I32, _P, _P], C.c_int),
 }
 
 STAGES = ("fft", "vote", "tail", "sample")
@@ -164,6 +168,25 @@ class Plan:
                "mr1l_profile_read")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(STAGES)}
 
+    def fft_schedule(self, M: int, sched: int | None = None) -> int:
+        """DFT schedule of lattice size M (set it when sched is given)."""
+        rc = lib().mr1l_plan_fft_schedule(self.handle, int(M), -1 if sched is None else int(sched))
+        if rc < 0:
+            _check(rc, "mr1l_plan_fft_schedule")
+        return int(rc)
+
+    def fft_tune(self, reps: int = 5):
+        """Autotune the DFT schedule of every distinct size -> {M: {schedule name: ms}}."""
+        nm = len(np.unique(self.M))
+        ns = fft_schedule_count()
+        sizes = np.zeros(nm, np.int64)
+        times = np.zeros((nm, ns), np.float32)
+        _check(lib().mr1l_fft_tune(self.handle, int(reps), nm, sizes.ctypes.data_as(_P), times.ctypes.data_as(_P)),
+               "mr1l_fft_tune")
+        names = fft_schedule_names()
+        return {int(sizes[i]): {names[j]: float(times[i, j]) for j in range(ns) if times[i, j] >= 0}
+                for i in range(nm)}
+
     def close(self):
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.mr1l_plan_destroy(self.handle)
@@ -174,6 +197,14 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def fft_schedule_count() -> int:
+    return int(lib().mr1l_fft_schedule_count())
+
+
+def fft_schedule_names():
+    return [lib().mr1l_fft_schedule_name(i).decode() for i in range(fft_schedule_count())]
 
 
 def _dev():

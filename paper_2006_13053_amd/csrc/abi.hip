@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 
 namespace mr1l {
@@ -160,42 +161,42 @@ static int build_tables(Plan &p)
         tw_of[n] = off;
         return off;
     };
-    std::vector<std::array<int32_t, 3>> mN;   // per mid: N, N1, N2
     for (int64_t i = 0; i < (int64_t)p.M.size(); ++i) {
         const int64_t M = p.M[i];
         if (mid_of.count(M)) continue;
         const int32_t mid = (int32_t)p.mdesc.size();
         mid_of[M] = mid;
         MDesc md{};
-        int64_t N = next_smooth(std::max<int64_t>(2 * M - 1, 2));
-        int64_t N1 = N, N2 = 1;
-        if (N > NMAX) {
-            // beyond one LDS transform: power-of-two N = N1 N2 (four-step, both halves in LDS)
-            int k = 0;
-            while ((int64_t(1) << k) < 2 * M - 1) ++k;
-            N = int64_t(1) << k;
-            N1 = int64_t(1) << ((k + 1) / 2);
-            N2 = N / N1;
-            if (N1 > (sizeof(T) == 8 ? 4096 : 8192)) return fail(MR1L_E_OVERFLOW, "lattice size too large for the DFT");
-            // the sub-transform twiddles (max(N1, N2) <= 256 entries) and the chirp table
-            // (<= 384 entries) go to LDS when every large lattice allows it (M <= 32768)
-            if (N1 > 256 || M > 32768) p.big_ltab = false;
+        MInfo mi;
+        mi.M = M;
+        // layout of the whole-LDS schedule: 5-smooth N >= 2M - 1 when it fits one workgroup
+        const int64_t Ns = next_smooth(std::max<int64_t>(2 * M - 1, 2));
+        if (Ns <= NMAX) {
+            mi.Ns = (int32_t)Ns;
+            mi.spec_s = spec_len;
+            spec_len += Ns;
+            mi.tw_s = twoff(Ns);
         }
-        md.spec_off = spec_len;
-        spec_len += N;
+        // layout of the four-step schedules: power-of-two N >= 2M - 1 (at least 4)
+        int k = 2;
+        while ((int64_t(1) << k) < 2 * M - 1) ++k;
+        mi.Np = 1 << k;
+        mi.spec_p = spec_len;
+        spec_len += mi.Np;
+        mi.tw_p = twoff(mi.Np);
         md.chirp_off = (int64_t)ch.size() / 2;
         push_chirp(ch, M, md.chirp_shift, md.chirp_nlo);
-        md.tw_N = twoff(N);          // sub-transforms of the four-step path index this table
-        md.tw_N1 = md.tw_N;
-        md.tw_N2 = md.tw_N;
+        // the sub-transform twiddles (max(N1, N2) entries) and the two-level chirp
+        // table go to LDS when they fit their LDS tables
+        const int64_t nch = md.chirp_nlo + (2 * M + md.chirp_nlo - 1) / md.chirp_nlo;
+        mi.ltab = mi.Np <= kTabTw * kTabTw && nch <= kTabCh;
+        mi.sched = tuned_schedule(p.dtype, M);
+        if (mi.sched < 0 || (mi.sched == 0 && mi.Ns == 0)) mi.sched = mi.Ns ? 0 : kDefaultFourStep;
         p.mdesc.push_back(md);
-        mN.push_back({(int32_t)N, (int32_t)N1, (int32_t)N2});
+        p.minfo.push_back(mi);
     }
     p.lat.resize(p.M.size());
     int64_t off = 0;
-    p.lds_lats.clear();
-    p.big_lats.clear();
-    p.big_maxN = 0;
     bool all16 = true;
     for (auto m : p.M) all16 = all16 && m <= (int64_t(1) << 15);
     for (int f = 0; f < p.F; ++f) {
@@ -209,9 +210,6 @@ static int build_tables(Plan &p)
             ld.node_off = off;
             ld.M = (int32_t)M;
             ld.mid = mid_of[M];
-            ld.N = mN[ld.mid][0];
-            ld.N1 = mN[ld.mid][1];
-            ld.N2 = mN[ld.mid][2];
             ld.func = f;
             ld.inv_m = inv_m_down(M);
             const int64_t S = (int64_t)p.d * kb * (M - 1);
@@ -219,11 +217,6 @@ static int build_tables(Plan &p)
             ld.z_off = i * p.d;
             p.lat[i] = ld;
             off += M;
-            if (ld.N2 == 1) p.lds_lats.push_back((int32_t)i);
-            else {
-                p.big_lats.push_back((int32_t)i);
-                p.big_maxN = std::max(p.big_maxN, ld.N);
-            }
         }
     }
     p.nodes = off;
@@ -301,19 +294,7 @@ static int upload(Plan &p)
         MR1L_HIP(hipMemcpy(p.d_vrec, vr.data(), vr.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     }
     MR1L_HIP(hipMemcpy(p.d_kb, p.kb.data(), p.kb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    if (!p.lds_lats.empty()) {
-        MR1L_HIP(hipMalloc(&p.d_lds_lats, p.lds_lats.size() * sizeof(int32_t)));
-        MR1L_HIP(hipMemcpy(p.d_lds_lats, p.lds_lats.data(), p.lds_lats.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice));
-    }
     const size_t esz = p.dtype == MR1L_C128 ? 16 : 8;
-    if (!p.big_lats.empty()) {
-        MR1L_HIP(hipMalloc(&p.d_big_lats, p.big_lats.size() * sizeof(int32_t)));
-        MR1L_HIP(hipMemcpy(p.d_big_lats, p.big_lats.data(), p.big_lats.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice));
-        p.fft_slots = std::min<int>((int)p.big_lats.size(), 2 * num_cus());
-        MR1L_HIP(hipMalloc(&p.d_fft_scratch, (size_t)p.fft_slots * 2 * (size_t)p.big_maxN * esz));
-    }
     MR1L_HIP(hipMalloc(&p.d_nodes_scratch, (size_t)std::max<int64_t>(p.nodes, 1) * esz));
     MR1L_HIP(hipMalloc(&p.d_det_tmp, sizeof(int64_t) * (size_t)p.F));
     MR1L_HIP(hipMalloc(&p.d_setoff_default, 2 * sizeof(int64_t)));
@@ -324,11 +305,13 @@ static int upload(Plan &p)
 static void release(Plan *p)
 {
     void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_vrec, p->d_spec, p->d_chirp, p->d_tw,
-                    p->d_lds_lats, p->d_big_lats, p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
+                    p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
                     p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
                     p->d_termoff_default};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    for (int s = 0; s < kNumSched; ++s)
+        if (p->d_grp_lats[s]) (void)hipFree(p->d_grp_lats[s]);
     delete p;
 }
 
@@ -353,6 +336,24 @@ static int grow(Plan &p, void **ptr, int64_t bytes, int64_t &have)
     MR1L_HIP(hipMalloc(ptr, (size_t)std::max<int64_t>(bytes, 16)));
     have = bytes;
     return MR1L_OK;
+}
+
+// Schedules chosen by the autotuner in this process, per (dtype, M); later plans
+// start from them.
+static std::mutex g_tuned_mu;
+static std::map<std::pair<int32_t, int64_t>, int32_t> g_tuned;
+
+int tuned_schedule(int32_t dtype, int64_t M)
+{
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto it = g_tuned.find({dtype, M});
+    return it == g_tuned.end() ? -1 : it->second;
+}
+
+static void record_tuned(int32_t dtype, int64_t M, int32_t s)
+{
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned[{dtype, M}] = s;
 }
 
 }  // namespace mr1l
@@ -408,6 +409,7 @@ int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int6
     int rc = dtype == MR1L_C128 ? build_tables<double>(*p) : build_tables<float>(*p);
     if (rc == MR1L_OK) rc = upload(*p);
     if (rc == MR1L_OK) rc = fft_prepare_spectra(*p);
+    if (rc == MR1L_OK) rc = fft_apply_schedules(*p);
     if (rc != MR1L_OK) {
         std::string keep = g_err;
         release(p);
@@ -644,6 +646,88 @@ int32_t mr1l_num_lattices(int64_t nJ, double c, double delta)
     if (L < 1) L = 1;
     if ((L & 1) == 0) ++L;
     return L;
+}
+
+int mr1l_fft_schedule_count(void) { return kNumSched; }
+
+const char *mr1l_fft_schedule_name(int32_t s) { return (s >= 0 && s < kNumSched) ? kSched[s].name : ""; }
+
+int mr1l_plan_fft_schedule(mr1l_plan p, int64_t M, int32_t sched)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    int mid = -1;
+    for (size_t i = 0; i < p->minfo.size(); ++i)
+        if (p->minfo[i].M == M) mid = (int)i;
+    if (mid < 0) return fail(MR1L_E_ARG, "no lattice of this size in the plan");
+    if (sched < 0) return p->minfo[mid].sched;
+    if (sched >= kNumSched) return fail(MR1L_E_ARG, "unknown DFT schedule");
+    if (!kSched[sched].four_step && p->minfo[mid].Ns == 0)
+        return fail(MR1L_E_ARG, "this lattice size does not fit one workgroup's LDS");
+    p->minfo[mid].sched = sched;
+    const int rc = fft_apply_schedules(*p);
+    return rc ? rc : sched;
+}
+
+int mr1l_fft_tune(mr1l_plan p, int32_t reps, int32_t max_sizes, int64_t *sizes, float *times_ms)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (reps < 1 || reps > 1000) return fail(MR1L_E_ARG, "reps must be in [1, 1000]");
+    if ((sizes || times_ms) && max_sizes < (int32_t)p->minfo.size())
+        return fail(MR1L_E_ARG, "max_sizes is smaller than the number of distinct lattice sizes");
+    const size_t esz = p->dtype == MR1L_C128 ? 16 : 8;
+    void *in = nullptr, *out = nullptr;
+    MDesc *d_md = nullptr;
+    int32_t *d_list = nullptr;
+    int rc = MR1L_OK;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(p->stream);
+        if (in) (void)hipFree(in);
+        if (out) (void)hipFree(out);
+        if (d_md) (void)hipFree(d_md);
+        if (d_list) (void)hipFree(d_list);
+    };
+    if (hipMalloc(&in, (size_t)std::max<int64_t>(p->nodes, 1) * esz) != hipSuccess ||
+        hipMalloc(&out, (size_t)std::max<int64_t>(p->nodes, 1) * esz) != hipSuccess ||
+        hipMalloc(&d_md, p->mdesc.size() * sizeof(MDesc)) != hipSuccess ||
+        hipMalloc(&d_list, p->lat.size() * sizeof(int32_t)) != hipSuccess) {
+        cleanup();
+        return fail(MR1L_E_NOMEM, "allocation of the tuning buffers failed");
+    }
+    rc = launch_fill_bytes(in, p->nodes * (int64_t)esz, p->stream);
+    for (size_t mid = 0; mid < p->minfo.size() && rc == MR1L_OK; ++mid) {
+        MInfo &mi = p->minfo[mid];
+        std::vector<int32_t> lst;
+        for (size_t i = 0; i < p->lat.size(); ++i)
+            if (p->lat[i].mid == (int32_t)mid) lst.push_back((int32_t)i);
+        if (hipMemcpy(d_list, lst.data(), lst.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(MR1L_E_HIP, "copy of the tuning list failed");
+            break;
+        }
+        if (sizes) sizes[mid] = mi.M;
+        int best = mi.sched;
+        float best_ms = 0.f;
+        for (int s = 0; s < kNumSched && rc == MR1L_OK; ++s) {
+            float ms = -1.f;
+            const bool ok = kSched[s].four_step ? mi.Np > 0 : mi.Ns > 0;
+            if (ok) {
+                std::vector<MDesc> md(p->mdesc);
+                md[mid] = fft_layout(*p, (int)mid, s);
+                if (hipMemcpy(d_md, md.data(), md.size() * sizeof(MDesc), hipMemcpyHostToDevice) != hipSuccess) {
+                    rc = fail(MR1L_E_HIP, "copy of the tuning layout failed");
+                    break;
+                }
+                rc = fft_time_group(*p, s, d_list, (int)lst.size(), d_md, mi.ltab, in, out, reps, &ms);
+                if (rc) break;
+                if (best_ms == 0.f || ms < best_ms) { best_ms = ms; best = s; }
+            }
+            if (times_ms) times_ms[mid * kNumSched + s] = ms;
+        }
+        mi.sched = best;
+        record_tuned(p->dtype, mi.M, best);
+    }
+    cleanup();
+    if (rc) return rc;
+    return fft_apply_schedules(*p);
 }
 
 }  // extern "C"

@@ -19,6 +19,9 @@
 // twiddle, N1 rows of length N2, with the intermediate in a per-workgroup
 // global scratch slot (it stays in L2/MALL) and the chirp and spectrum
 // products fused into the column load and the row store.
+#include <algorithm>
+#include <initializer_list>
+
 #include "mr1l_internal.h"
 
 namespace mr1l {
@@ -240,32 +243,34 @@ __device__ __forceinline__ void dft16(T *xr, T *xi)
     }
 }
 
-// LDS planes of the power-of-two path hold NMAXP elements with one pad element
-// after every 16, which breaks the power-of-two strides of the column accesses
-// and of the early Stockham passes (bank conflicts).
-constexpr int kFft4Threads = 512;   // two four-step workgroups per CU
-constexpr int kTabTw = 256;         // LDS twiddles of the four-step sub-transforms
-constexpr int kTabCh = 384;         // LDS two-level chirp table entries
-template <typename T> constexpr int p2_max_n() { return sizeof(T) == 8 ? 4096 : 8192; }
+// LDS planes of the power-of-two path hold P elements (the workgroup's LDS
+// batch) with one pad element after every 16, which breaks the power-of-two
+// strides of the column accesses and of the early Stockham passes (bank
+// conflicts).
 __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
-template <typename T> constexpr int p2_plane() { return p2_max_n<T>() + p2_max_n<T>() / 16; }
+// The thread index laundered through an empty asm: index arithmetic derived from
+// it cannot be hoisted out of the batch loops, where it would stay live through
+// every Stockham pass and spill.
+__device__ __forceinline__ int opaque(int x) { asm volatile("" : "+v"(x)); return x; }
+constexpr int p2_plane(int P) { return P + P / 16; }
 
-// One Stockham pass of radix 2^LR over 2^logb transforms of length 2^logn; the
-// twiddle e^{-2 pi i r k / (Ns R)} is entry (r k) << (logN - logNs - LR) of a
-// table e^{-2 pi i j / 2^logN} (logN >= logn; in LDS for the lengths used here).
-template <typename T, int LR, typename TW>
+// One Stockham pass of radix 2^LR over 2^logb transforms of length 2^logn held
+// in planes of P elements, by NT threads; the twiddle e^{-2 pi i r k / (Ns R)}
+// is entry (r k) << (logN - logNs - LR) of a table e^{-2 pi i j / 2^logN}.
+template <typename T, int LR, int NT, int P, typename TW>
 __device__ void stockham_p2(T *re, T *im, int logn, int logb, int logNs, TW tw, int logN)
 {
     constexpr int R = 1 << LR;
-    constexpr int BPT = (p2_max_n<T>() / R + kFft4Threads - 1) / kFft4Threads;
+    constexpr int BPT = (P / R + NT - 1) / NT;
     const int lognR = logn - LR;
     const int total = 1 << (logb + lognR);
     const int tsh = logN - logNs - LR;
+    const int tid0 = opaque((int)threadIdx.x);
     T vr[BPT][R], vi[BPT][R];
     int ob[BPT];
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
-        const int j = threadIdx.x + i * kFft4Threads;
+        const int j = tid0 + i * NT;
         ob[i] = -1;
         if (j < total) {
             const int b = j >> lognR;
@@ -306,18 +311,17 @@ __device__ void stockham_p2(T *re, T *im, int logn, int logb, int logNs, TW tw, 
     __syncthreads();
 }
 
-template <typename T, typename TW>
+// Radix 16 for float; radix 8 at most for double (a 16-point double butterfly
+// does not fit the register budget of the two-per-CU schedules).
+template <typename T, int NT, int P, typename TW>
 __device__ void lds_fft_p2(T *re, T *im, int logn, int logb, TW tw, int logN)
 {
     int logNs = 0, rem = logn;
     while (rem > 0) {
-        // radix 16 for float; radix 8 at most for double, whose 16-point butterfly
-        // would not fit the register budget of two workgroups per CU
-        if (sizeof(T) == 4 && rem >= 4) { stockham_p2<T, 4, TW>(re, im, logn, logb, logNs, tw, logN); logNs += 4; rem -= 4; }
-        else if (sizeof(T) == 8 && rem >= 3) { stockham_p2<T, 3, TW>(re, im, logn, logb, logNs, tw, logN); logNs += 3; rem -= 3; }
-        else if (rem == 3) { stockham_p2<T, 3, TW>(re, im, logn, logb, logNs, tw, logN); logNs += 3; rem -= 3; }
-        else if (rem == 2) { stockham_p2<T, 2, TW>(re, im, logn, logb, logNs, tw, logN); logNs += 2; rem -= 2; }
-        else { stockham_p2<T, 1, TW>(re, im, logn, logb, logNs, tw, logN); logNs += 1; rem -= 1; }
+        if (sizeof(T) == 4 && rem >= 4) { stockham_p2<T, 4, NT, P, TW>(re, im, logn, logb, logNs, tw, logN); logNs += 4; rem -= 4; }
+        else if (rem >= 3) { stockham_p2<T, 3, NT, P, TW>(re, im, logn, logb, logNs, tw, logN); logNs += 3; rem -= 3; }
+        else if (rem == 2) { stockham_p2<T, 2, NT, P, TW>(re, im, logn, logb, logNs, tw, logN); logNs += 2; rem -= 2; }
+        else { stockham_p2<T, 1, NT, P, TW>(re, im, logn, logb, logNs, tw, logN); logNs += 1; rem -= 1; }
     }
 }
 
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(kFftThreads) void k_bluestein_lds(
     T *im = re + lds_max_n<T>();
     const LatDesc ld = lat[lats[blockIdx.x]];
     const MDesc m = md[ld.mid];
-    const int N = ld.N, M = ld.M;
+    const int N = m.N, M = ld.M;
     const double inv2m = 1.0 / (2.0 * (double)M);
     const V *ctab = chirp_tab + m.chirp_off;
     const V *tw = tw_tab + m.tw_N;
@@ -456,21 +460,30 @@ __global__ __launch_bounds__(kFftThreads) void k_bluestein_lds(
     }
 }
 
+
 // ------------------------------------------------------------------ four-step kernel
-// Power-of-two N = N1 N2 (N1, N2 <= NMAXP), three phases per lattice:
-//   A  length-N1 DFTs over n1 of x[N2 n1 + n2] (x = chirped input), twiddle
-//      W_N^{n2 k1}, stored Y[k1][n2];
-//   B  for a batch of k1: length-N2 DFTs over n2 give X[k1 + N1 k2]; times the
-//      kernel spectrum; inverse length-N2 DFTs over k2; twiddle W_N^{-b k1};
-//      stored U[b][k1] -- the forward row stage and the first stage of the
-//      inverse transform share the LDS, so the product never leaves the chip;
-//   C  for a batch of b: inverse length-N1 DFTs over k1 give the convolution at
-//      N2 a + b; times the chirp and 1/M (folded into the spectrum); output.
-// Inverse DFTs are conj(DFT(conj(.))).  SPEC mode runs A and the forward half of B
-// on the chirp sequence and stores the scaled spectrum.  Persistent: workgroup w
-// owns scratch slot w (2 maxN complex) and handles lattices w, w + grid, ...
-template <typename T, bool LTAB>
-__global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
+// Power-of-two N = N1 N2 (N1, N2 <= P, the LDS batch), three phases per lattice
+// on one slot of N complex in global scratch (it stays in L2/MALL), in place:
+//   A  for a batch of columns n2: length-N1 DFTs over n1 of x[N2 n1 + n2]
+//      (x = chirped input), twiddle W_N^{n2 k1}, stored Y[k1][n2];
+//   B  for a batch of rows k1: length-N2 DFTs over n2 give X[k1 + N1 k2]; times
+//      the kernel spectrum; inverse length-N2 DFTs over k2; twiddle W_N^{-b k1};
+//      stored back over the same rows as U[k1][b] -- the forward row stage and
+//      the first stage of the inverse transform share the LDS, so the product
+//      never leaves the chip;
+//   C  for a batch of columns b: inverse length-N1 DFTs over k1 give the
+//      convolution at N2 a + b; times the chirp and 1/M (folded into the
+//      spectrum); output.
+// Inverse DFTs are conj(DFT(conj(.))).  SPEC mode runs A and the forward half of
+// B on the chirp sequence and stores the scaled spectrum.  Loads are issued for
+// every lane from a clamped, always valid index (the value is discarded where
+// the element does not exist), which keeps the partially filled load arrays from
+// being carried across loop iterations.  Persistent: workgroup
+// w owns scratch slot w and handles lattices w, w + grid, ...  Every phase-C
+// load of a lattice completes before the barrier that precedes its last DFT, so
+// the next lattice's phase A may overwrite the slot.
+template <typename T, bool LTAB, int NT, int LOGP, int WAVES>
+__global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
     const int32_t *__restrict__ lats, int nlats, const LatDesc *__restrict__ lat,
     const MDesc *__restrict__ md, const typename cvec<T>::type *__restrict__ in,
     typename cvec<T>::type *__restrict__ out, typename cvec<T>::type *__restrict__ spec_tab,
@@ -479,28 +492,27 @@ __global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
     typename cvec<T>::type *__restrict__ scratch, int64_t slot_len)
 {
     using V = typename cvec<T>::type;
-    constexpr int NMAXP = p2_max_n<T>();
-    constexpr int LOGNMAXP = sizeof(T) == 8 ? 12 : 13;
-    constexpr int NT = kFft4Threads;
+    constexpr int P = 1 << LOGP;
+    constexpr int EPT = P / NT;     // elements per thread of a full batch
+    constexpr int CH = 4;           // loads issued together per thread
+    static_assert(EPT % CH == 0, "the LDS batch must hold a multiple of CH elements per thread");
     extern __shared__ __align__(16) unsigned char smem[];
     T *re = reinterpret_cast<T *>(smem);
-    T *im = re + p2_plane<T>();
+    T *im = re + p2_plane(P);
     // small tables next to the planes: twiddles of the sub-transforms (W_nt^j, nt =
     // max(N1, N2) <= kTabTw) and the two-level chirp table (<= kTabCh entries)
-    V *ltw = reinterpret_cast<V *>(im + p2_plane<T>());
+    V *ltw = reinterpret_cast<V *>(im + p2_plane(P));
     V *lch = ltw + kTabTw;
-    V *bufY = scratch + (int64_t)blockIdx.x * slot_len;
-    V *bufU = bufY + slot_len / 2;
+    V *buf = scratch + (int64_t)blockIdx.x * slot_len;
     const int tid = threadIdx.x;
     const T cj = (mode == FFT_INV) ? T(-1) : T(1);
-    (void)NMAXP;
 
     for (int li = blockIdx.x; li < nlats; li += gridDim.x) {
         const LatDesc ld = lat[lats[li]];
         const MDesc m = md[ld.mid];
-        const int N = ld.N, M = ld.M;
+        const int N = m.N, M = ld.M;
         const double inv2m = 1.0 / (2.0 * (double)M);
-        const int logN = 31 - __clz(N), logN1 = 31 - __clz(ld.N1), logN2 = 31 - __clz(ld.N2);
+        const int logN = 31 - __clz(N), logN1 = 31 - __clz(m.N1), logN2 = 31 - __clz(m.N2);
         const V *twN = tw_tab + m.tw_N;
         const V *x = in + ld.node_off;
         const V *sp = spec_tab + m.spec_off;
@@ -520,14 +532,12 @@ __global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
             ctab = chirp_tab + m.chirp_off;
             tsub = twN;
         }
-        const int logB2 = min(logN2, LOGNMAXP - logN1);
-        const int logB1 = min(logN1, LOGNMAXP - logN2);
+        const int logB2 = min(logN2, LOGP - logN1);
+        const int logB1 = min(logN1, LOGP - logN2);
         const int B2 = 1 << logB2, B1 = 1 << logB1;
 
         // ---- phase A: columns.  The raw inputs of a batch are loaded together into
         // LDS, then each thread chirps its own elements (no barrier in between).
-        constexpr int EPT = p2_max_n<T>() / NT;   // elements per thread of a full batch
-        constexpr int CH = 4;                     // loads issued together per thread
         for (int c0 = 0; c0 < (1 << logN2); c0 += B2) {
             const int tot = B2 << logN1;
             if (mode != FFT_SPEC) {
@@ -535,13 +545,13 @@ __global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
                     V v[CH];
 #pragma unroll
                     for (int i = 0; i < CH; ++i) {
-                        const int e = tid + (i0 + i) * NT;
+                        const int e = opaque(tid) + (i0 + i) * NT;
                         const int nn = ((e >> logB2) << logN2) + c0 + (e & (B2 - 1));
-                        if (e < tot && nn < M) v[i] = x[nn];
+                        v[i] = x[(e < tot && nn < M) ? nn : 0];
                     }
 #pragma unroll
                     for (int i = 0; i < CH; ++i) {
-                        const int e = tid + (i0 + i) * NT;
+                        const int e = opaque(tid) + (i0 + i) * NT;
                         if (e < tot) {
                             const int nn = ((e >> logB2) << logN2) + c0 + (e & (B2 - 1));
                             const int q = pad16(((e & (B2 - 1)) << logN1) + (e >> logB2));
@@ -553,7 +563,7 @@ __global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
             }
 #pragma unroll 4
             for (int i = 0; i < EPT; ++i) {
-                const int e = tid + i * NT;
+                const int e = opaque(tid) + i * NT;
                 if (e < tot) {
                     const int b = e & (B2 - 1), n1 = e >> logB2;
                     const int nn = (n1 << logN2) + c0 + b;
@@ -577,48 +587,49 @@ __global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
                 }
             }
             __syncthreads();
-            lds_fft_p2<T>(re, im, logN1, logB2, tsub, logNT);
+            lds_fft_p2<T, NT, P>(re, im, logN1, logB2, tsub, logNT);
             _Pragma("unroll 1") for (int i0 = 0; i0 < EPT; i0 += CH) {
                 V w[CH];
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;
-                    if (e < tot) w[i] = twN[(c0 + (e & (B2 - 1))) * (e >> logB2)];   // e^{-2 pi i n2 k1 / N}
+                    const int e = opaque(tid) + (i0 + i) * NT;
+                    w[i] = twN[e < tot ? (c0 + (e & (B2 - 1))) * (e >> logB2) : 0];   // e^{-2 pi i n2 k1 / N}
                 }
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;
+                    const int e = opaque(tid) + (i0 + i) * NT;
                     if (e < tot) {
                         const int b = e & (B2 - 1), k1 = e >> logB2;
                         const T a = re[pad16((b << logN1) + k1)], bb = im[pad16((b << logN1) + k1)];
                         V o; o.x = a * w[i].x - bb * w[i].y; o.y = a * w[i].y + bb * w[i].x;
-                        bufY[((int64_t)k1 << logN2) + c0 + b] = o;
+                        buf[((int64_t)k1 << logN2) + c0 + b] = o;
                     }
                 }
             }
             __syncthreads();
         }
-        // ---- phase B: rows (forward), spectrum, rows (inverse), twiddle
+        // ---- phase B: rows (forward), spectrum, rows (inverse), twiddle, in place
         for (int r0 = 0; r0 < (1 << logN1); r0 += B1) {
             const int tot = B1 << logN2;
+            V *row = buf + ((int64_t)r0 << logN2);
             _Pragma("unroll 1") for (int i0 = 0; i0 < EPT; i0 += CH) {
                 V v[CH];
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;
-                    if (e < tot) v[i] = bufY[((int64_t)r0 << logN2) + e];
+                    const int e = opaque(tid) + (i0 + i) * NT;
+                    v[i] = row[e < tot ? e : 0];
                 }
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;
+                    const int e = opaque(tid) + (i0 + i) * NT;
                     if (e < tot) { re[pad16(e)] = v[i].x; im[pad16(e)] = v[i].y; }
                 }
             }
             __syncthreads();
-            lds_fft_p2<T>(re, im, logN2, logB1, tsub, logNT);
+            lds_fft_p2<T, NT, P>(re, im, logN2, logB1, tsub, logNT);
             if (mode == FFT_SPEC) {
                 const T s = T(1) / ((T)N * (T)M);
-                for (int e = tid; e < tot; e += NT) {
+                for (int e = opaque(tid); e < tot; e += NT) {
                     const int b = e & (B1 - 1), k2 = e >> logB1;
                     const int k = r0 + b + (k2 << logN1);
                     V o; o.x = re[pad16((b << logN2) + k2)] * s; o.y = im[pad16((b << logN2) + k2)] * s;
@@ -632,12 +643,12 @@ __global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
                 V sv[CH];
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;   // b = e mod B1 (fast), k2 = e / B1
-                    if (e < tot) sv[i] = sp[r0 + (e & (B1 - 1)) + ((e >> logB1) << logN1)];
+                    const int e = opaque(tid) + (i0 + i) * NT;   // b = e mod B1 (fast), k2 = e / B1
+                    sv[i] = sp[e < tot ? r0 + (e & (B1 - 1)) + ((e >> logB1) << logN1) : 0];
                 }
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;
+                    const int e = opaque(tid) + (i0 + i) * NT;
                     if (e < tot) {
                         const int q = pad16(((e & (B1 - 1)) << logN2) + (e >> logB1));
                         const T a = re[q], bb = im[q];
@@ -647,24 +658,23 @@ __global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
                 }
             }
             __syncthreads();
-            lds_fft_p2<T>(re, im, logN2, logB1, tsub, logNT);
-            // undo the conjugation, twiddle e^{+2 pi i b' k1 / N} (b' = output column), store U[b'][k1]
+            lds_fft_p2<T, NT, P>(re, im, logN2, logB1, tsub, logNT);
+            // undo the conjugation, twiddle e^{+2 pi i b' k1 / N} (b' = output column), store
+            // U[k1][b'] over the rows just read: element e is row b = e / N2, column b' = e mod N2
             _Pragma("unroll 1") for (int i0 = 0; i0 < EPT; i0 += CH) {
                 V w[CH];
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;
-                    if (e < tot) w[i] = twN[(e >> logB1) * (r0 + (e & (B1 - 1)))];   // b' k1 < N
+                    const int e = opaque(tid) + (i0 + i) * NT;
+                    w[i] = twN[e < tot ? (e & ((1 << logN2) - 1)) * (r0 + (e >> logN2)) : 0];   // b' k1 < N
                 }
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;
+                    const int e = opaque(tid) + (i0 + i) * NT;
                     if (e < tot) {
-                        const int b = e & (B1 - 1), bp = e >> logB1;   // k1 = r0 + b
-                        const int q = pad16((b << logN2) + bp);
-                        const T a = re[q], bb = -im[q];
+                        const T a = re[pad16(e)], bb = -im[pad16(e)];
                         V o; o.x = a * w[i].x + bb * w[i].y; o.y = bb * w[i].x - a * w[i].y;   // times conj(w)
-                        bufU[((int64_t)bp << logN1) + r0 + b] = o;
+                        row[e] = o;
                     }
                 }
             }
@@ -678,20 +688,23 @@ __global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
                 V v[CH];
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;
-                    if (e < tot) v[i] = bufU[((int64_t)c0 << logN1) + e];
+                    const int e = opaque(tid) + (i0 + i) * NT;
+                    v[i] = buf[e < tot ? ((int64_t)(e >> logB2) << logN2) + c0 + (e & (B2 - 1)) : 0];
                 }
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const int e = tid + (i0 + i) * NT;
-                    if (e < tot) { re[pad16(e)] = v[i].x; im[pad16(e)] = -v[i].y; }
+                    const int e = opaque(tid) + (i0 + i) * NT;
+                    if (e < tot) {
+                        const int q = pad16(((e & (B2 - 1)) << logN1) + (e >> logB2));
+                        re[q] = v[i].x; im[q] = -v[i].y;
+                    }
                 }
             }
             __syncthreads();
-            lds_fft_p2<T>(re, im, logN1, logB2, tsub, logNT);
+            lds_fft_p2<T, NT, P>(re, im, logN1, logB2, tsub, logNT);
             const T sc = scale_by_m ? scale * (T)M : scale;
 #pragma unroll 4
-            for (int e = tid; e < tot; e += NT) {
+            for (int e = opaque(tid); e < tot; e += NT) {
                 const int b = e & (B2 - 1), a = e >> logB2;   // output n = N2 a + (c0 + b)
                 const int h = (a << logN2) + c0 + b;
                 if (h < M) {
@@ -712,48 +725,101 @@ __global__ __launch_bounds__(kFft4Threads, 4) void k_bluestein_4step(
 }
 
 // ------------------------------------------------------------------ host side
-template <typename T>
-static int fft_launch(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap, int mode,
-                      double scale, int scale_by_m)
+const FftSched kSched[kNumSched] = {
+    {"lds", 0, kFftThreads, 0, 1, 0},
+    {"4step-512x2-ceil", 1, 512, 12, 2, 0},
+    {"4step-512x2-floor", 1, 512, 12, 2, 1},
+    {"4step-512x1-ceil", 1, 512, 13, 1, 0},
+    {"4step-512x1-floor", 1, 512, 13, 1, 1},
+    {"4step-1024x1-ceil", 1, 1024, 13, 1, 0},
+    {"4step-1024x1-floor", 1, 1024, 13, 1, 1},
+    {"4step-256x2-ceil", 1, 256, 12, 2, 0},
+    {"4step-256x2-floor", 1, 256, 12, 2, 1},
+};
+
+template <typename T, int LOGP, bool LTAB>
+constexpr size_t lds_4step()
+{
+    return 2 * sizeof(T) * p2_plane(1 << LOGP) + (LTAB ? (kTabTw + kTabCh) * 2 * sizeof(T) : 0);
+}
+
+template <typename T, bool LTAB, int NT, int LOGP, int WAVES>
+static int launch4(Plan &p, const int32_t *d_lats, int nl, const MDesc *d_md, const void *in, void *out,
+                   T th2, uint32_t *bitmap, int mode, T scale, int by_m, int per_cu)
 {
     using V = typename cvec<T>::type;
-    const T th2 = (T)(theta * theta);
-    const size_t shm = kLdsBytes;
-    if (!p.lds_lats.empty()) {
-        hipLaunchKernelGGL(k_bluestein_lds<T>, dim3((unsigned)p.lds_lats.size()), dim3(kFftThreads), shm,
-                           p.stream, p.d_lds_lats, p.d_lat, p.d_mdesc, (const V *)in, (V *)out,
-                           (V *)p.d_spec, (const V *)p.d_chirp, (const V *)p.d_tw, bitmap, th2, mode,
-                           (T)scale, scale_by_m);
-        MR1L_LAUNCH_CHECK();
-    }
-    if (!p.big_lats.empty()) {
-        const int nl = (int)p.big_lats.size();
-        const int grid = std::min(nl, p.fft_slots);   // slots: two per CU
-        const bool ltab = p.big_ltab;
-        const size_t shm4 = 2 * sizeof(T) * p2_plane<T>() + (ltab ? (kTabTw + kTabCh) * 2 * sizeof(T) : 0);
-        if (ltab)
-            hipLaunchKernelGGL((k_bluestein_4step<T, true>), dim3(grid), dim3(kFft4Threads), shm4, p.stream,
-                               p.d_big_lats, nl, p.d_lat, p.d_mdesc, (const V *)in, (V *)out, (V *)p.d_spec,
-                               (const V *)p.d_chirp, (const V *)p.d_tw, bitmap, th2, mode, (T)scale, scale_by_m,
-                               (V *)p.d_fft_scratch, (int64_t)2 * p.big_maxN);
-        else
-            hipLaunchKernelGGL((k_bluestein_4step<T, false>), dim3(grid), dim3(kFft4Threads), shm4, p.stream,
-                               p.d_big_lats, nl, p.d_lat, p.d_mdesc, (const V *)in, (V *)out, (V *)p.d_spec,
-                               (const V *)p.d_chirp, (const V *)p.d_tw, bitmap, th2, mode, (T)scale, scale_by_m,
-                               (V *)p.d_fft_scratch, (int64_t)2 * p.big_maxN);
-        MR1L_LAUNCH_CHECK();
-    }
+    static_assert(lds_4step<T, LOGP, LTAB>() <= (size_t)kLdsBytes, "four-step LDS budget");
+    const int grid = std::min(nl, std::min(p.fft_slots, per_cu * num_cus()));
+    if (grid < 1) return fail(MR1L_E_ARG, "four-step DFT without a scratch slot");
+    constexpr size_t shm = lds_4step<T, LOGP, LTAB>();
+    hipLaunchKernelGGL((k_bluestein_4step<T, LTAB, NT, LOGP, WAVES>), dim3(grid), dim3(NT), shm, p.stream, d_lats, nl, p.d_lat, d_md, (const V *)in, (V *)out,
+                       (V *)p.d_spec, (const V *)p.d_chirp, (const V *)p.d_tw, bitmap, th2, mode, scale, by_m,
+                       (V *)p.d_fft_scratch, p.fft_slot_len);
+    MR1L_LAUNCH_CHECK();
     return MR1L_OK;
+}
+
+// One launch of schedule s over the lattices d_lats (their sizes' tables in d_md).
+template <typename T>
+static int launch_sched(Plan &p, int s, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
+                        const void *in, void *out, double theta, uint32_t *bitmap, int mode, double scale,
+                        int by_m)
+{
+    using V = typename cvec<T>::type;
+    constexpr int LS = sizeof(T) == 8 ? 12 : 13;   // log2 LDS batch of the two-per-CU schedules
+    const T th2 = (T)(theta * theta);
+    const T sc = (T)scale;
+    const int pc = kSched[s].per_cu;
+    if (nl <= 0) return MR1L_OK;
+    switch (s) {
+    case 0:
+        hipLaunchKernelGGL(k_bluestein_lds<T>, dim3((unsigned)nl), dim3(kFftThreads), (size_t)kLdsBytes, p.stream,
+                           d_lats, p.d_lat, d_md, (const V *)in, (V *)out, (V *)p.d_spec, (const V *)p.d_chirp,
+                           (const V *)p.d_tw, bitmap, th2, mode, sc, by_m);
+        MR1L_LAUNCH_CHECK();
+        return MR1L_OK;
+    case 1: case 2:
+        return ltab ? launch4<T, true, 512, LS, 4>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc)
+                    : launch4<T, false, 512, LS, 4>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc);
+    case 3: case 4:
+        return ltab ? launch4<T, true, 512, LS + 1, 2>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc)
+                    : launch4<T, false, 512, LS + 1, 2>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc);
+    case 5: case 6:
+        return ltab ? launch4<T, true, 1024, LS + 1, 4>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc)
+                    : launch4<T, false, 1024, LS + 1, 4>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc);
+    case 7: case 8:
+        return ltab ? launch4<T, true, 256, LS, 2>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc)
+                    : launch4<T, false, 256, LS, 2>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc);
+    default:
+        return fail(MR1L_E_ARG, "unknown DFT schedule");
+    }
+}
+
+static int launch_any(Plan &p, int s, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab, const void *in,
+                      void *out, double theta, uint32_t *bitmap, int mode, double scale, int by_m)
+{
+    return p.dtype == MR1L_C128
+               ? launch_sched<double>(p, s, d_lats, nl, d_md, ltab, in, out, theta, bitmap, mode, scale, by_m)
+               : launch_sched<float>(p, s, d_lats, nl, d_md, ltab, in, out, theta, bitmap, mode, scale, by_m);
+}
+
+template <typename K> static void allow_lds_one(K k)
+{
+    (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
 }
 
 template <typename T> static void allow_lds()
 {
-    (void)hipFuncSetAttribute((const void *)k_bluestein_lds<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        kLdsBytes);
-    (void)hipFuncSetAttribute((const void *)k_bluestein_4step<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kLdsBytes);
-    (void)hipFuncSetAttribute((const void *)k_bluestein_4step<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kLdsBytes);
+    constexpr int LS = sizeof(T) == 8 ? 12 : 13;
+    allow_lds_one(k_bluestein_lds<T>);
+    allow_lds_one(k_bluestein_4step<T, true, 512, LS, 4>);
+    allow_lds_one(k_bluestein_4step<T, false, 512, LS, 4>);
+    allow_lds_one(k_bluestein_4step<T, true, 512, LS + 1, 2>);
+    allow_lds_one(k_bluestein_4step<T, false, 512, LS + 1, 2>);
+    allow_lds_one(k_bluestein_4step<T, true, 1024, LS + 1, 4>);
+    allow_lds_one(k_bluestein_4step<T, false, 1024, LS + 1, 4>);
+    allow_lds_one(k_bluestein_4step<T, true, 256, LS, 2>);
+    allow_lds_one(k_bluestein_4step<T, false, 256, LS, 2>);
 }
 
 int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap, int mode, double scale)
@@ -765,8 +831,13 @@ int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap, 
         int rc = launch_fill_u32(bitmap, (p.nodes + 31) / 32, 0u, p.stream);
         if (rc) return rc;
     }
-    if (p.dtype == MR1L_C128) return fft_launch<double>(p, in, out, theta, bitmap, mode, scale, by_m);
-    return fft_launch<float>(p, in, out, theta, bitmap, mode, scale, by_m);
+    for (int s = 0; s < kNumSched; ++s) {
+        if (p.grp_lats[s].empty()) continue;
+        int rc = launch_any(p, s, p.d_grp_lats[s], (int)p.grp_lats[s].size(), p.d_mdesc, p.grp_ltab[s], in, out,
+                            theta, bitmap, mode, scale, by_m);
+        if (rc) return rc;
+    }
+    return MR1L_OK;
 }
 
 void fft_init_attrs()
@@ -775,34 +846,153 @@ void fft_init_attrs()
     allow_lds<float>();
 }
 
+// Table entry of size `mid` for the layout of schedule s.
+MDesc fft_layout(const Plan &p, int mid, int s)
+{
+    MDesc m = p.mdesc[mid];
+    const MInfo &mi = p.minfo[mid];
+    if (!kSched[s].four_step) {
+        m.spec_off = mi.spec_s; m.tw_N = mi.tw_s; m.N = mi.Ns; m.N1 = mi.Ns; m.N2 = 1;
+    } else {
+        int k = 0;
+        while ((1 << k) < mi.Np) ++k;
+        const int kc = (k + 1) / 2, kf = k / 2;
+        m.spec_off = mi.spec_p; m.tw_N = mi.tw_p; m.N = mi.Np;
+        m.N1 = 1 << (kSched[s].split_floor ? kf : kc);
+        m.N2 = mi.Np / m.N1;
+    }
+    return m;
+}
+
+static bool applies(const MInfo &mi, int s) { return kSched[s].four_step ? mi.Np > 0 : mi.Ns > 0; }
+
+// Grow the four-step scratch to `slots` slots of `len` complex (capped at 8 GiB in
+// total, at least one slot).  Synchronises the plan's stream before freeing.
+static int ensure_scratch(Plan &p, int64_t len, int64_t slots)
+{
+    const int64_t esz = p.dtype == MR1L_C128 ? 16 : 8;
+    len = std::max(len, p.fft_slot_len);
+    const int64_t cap = std::max<int64_t>(1, (int64_t(8) << 30) / (len * esz));
+    slots = std::min(std::max<int64_t>({slots, (int64_t)p.fft_slots, 1}), cap);
+    if (p.d_fft_scratch && len == p.fft_slot_len && slots == p.fft_slots) return MR1L_OK;
+    MR1L_HIP(hipStreamSynchronize(p.stream));
+    if (p.d_fft_scratch) (void)hipFree(p.d_fft_scratch);
+    p.d_fft_scratch = nullptr;
+    p.fft_slots = 0;
+    MR1L_HIP(hipMalloc(&p.d_fft_scratch, (size_t)(slots * len * esz)));
+    p.fft_slot_len = len;
+    p.fft_slots = (int32_t)slots;
+    return MR1L_OK;
+}
+
+static int upload_list(int32_t **dst, const std::vector<int32_t> &v)
+{
+    if (*dst) (void)hipFree(*dst);
+    *dst = nullptr;
+    if (v.empty()) return MR1L_OK;
+    MR1L_HIP(hipMalloc(dst, v.size() * sizeof(int32_t)));
+    MR1L_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return MR1L_OK;
+}
+
+int fft_apply_schedules(Plan &p)
+{
+    MR1L_HIP(hipStreamSynchronize(p.stream));
+    for (size_t mid = 0; mid < p.minfo.size(); ++mid) p.mdesc[mid] = fft_layout(p, (int)mid, p.minfo[mid].sched);
+    MR1L_HIP(hipMemcpy(p.d_mdesc, p.mdesc.data(), p.mdesc.size() * sizeof(MDesc), hipMemcpyHostToDevice));
+    int64_t len = 0, slots = 0;
+    for (int s = 0; s < kNumSched; ++s) {
+        p.grp_lats[s].clear();
+        p.grp_ltab[s] = true;
+    }
+    for (size_t i = 0; i < p.lat.size(); ++i) {
+        const MInfo &mi = p.minfo[p.lat[i].mid];
+        p.grp_lats[mi.sched].push_back((int32_t)i);
+        p.grp_ltab[mi.sched] = p.grp_ltab[mi.sched] && mi.ltab;
+        if (kSched[mi.sched].four_step) len = std::max<int64_t>(len, mi.Np);
+    }
+    for (int s = 0; s < kNumSched; ++s) {
+        int rc = upload_list(&p.d_grp_lats[s], p.grp_lats[s]);
+        if (rc) return rc;
+        if (kSched[s].four_step && !p.grp_lats[s].empty())
+            slots = std::max<int64_t>(slots, std::min<int64_t>((int64_t)p.grp_lats[s].size(),
+                                                               (int64_t)kSched[s].per_cu * num_cus()));
+    }
+    if (len > 0) return ensure_scratch(p, len, slots);
+    return MR1L_OK;
+}
+
+int fft_time_group(Plan &p, int s, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab, const void *in,
+                   void *out, int reps, float *ms)
+{
+    if (kSched[s].four_step) {
+        int64_t len = 0;
+        for (const MInfo &mi : p.minfo) len = std::max<int64_t>(len, mi.Np);
+        int rc = ensure_scratch(p, len, std::min<int64_t>(nl, (int64_t)kSched[s].per_cu * num_cus()));
+        if (rc) return rc;
+    }
+    int rc = launch_any(p, s, d_lats, nl, d_md, ltab, in, out, 0.0, nullptr, FFT_FWD, 1.0, 0);
+    if (rc) return rc;
+    hipEvent_t a, b;
+    MR1L_HIP(hipEventCreate(&a));
+    MR1L_HIP(hipEventCreate(&b));
+    MR1L_HIP(hipEventRecord(a, p.stream));
+    for (int r = 0; r < reps && rc == MR1L_OK; ++r)
+        rc = launch_any(p, s, d_lats, nl, d_md, ltab, in, out, 0.0, nullptr, FFT_FWD, 1.0, 0);
+    MR1L_HIP(hipEventRecord(b, p.stream));
+    MR1L_HIP(hipEventSynchronize(b));
+    float t = 0.f;
+    MR1L_HIP(hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = t / (float)std::max(reps, 1);
+    return rc;
+}
+
+// Kernel spectra of both layouts of every size: the LDS layout where it applies
+// and the power-of-two layout, computed by the DFT kernels themselves (SPEC mode)
+// on one representative lattice per size.
 int fft_prepare_spectra(Plan &p)
 {
-    // one lattice per distinct size: run the SPEC mode on representative lattices
-    std::vector<int32_t> rep_lds, rep_big;
-    std::vector<char> seen(p.mdesc.size(), 0);
-    for (size_t i = 0; i < p.lat.size(); ++i) {
-        const LatDesc &ld = p.lat[i];
-        if (seen[ld.mid]) continue;
-        seen[ld.mid] = 1;
-        (ld.N2 == 1 ? rep_lds : rep_big).push_back((int32_t)i);
+    std::vector<int32_t> rep(p.minfo.size(), -1);
+    for (size_t i = 0; i < p.lat.size(); ++i)
+        if (rep[p.lat[i].mid] < 0) rep[p.lat[i].mid] = (int32_t)i;
+    MDesc *d_md = nullptr;
+    int32_t *d_rep = nullptr;
+    MR1L_HIP(hipMalloc(&d_md, p.mdesc.size() * sizeof(MDesc)));
+    int rc = MR1L_OK;
+    for (int s : {0, kDefaultFourStep}) {
+        std::vector<MDesc> md(p.mdesc);
+        std::vector<int32_t> reps;
+        bool ltab = true;
+        int64_t len = 0;
+        for (size_t mid = 0; mid < p.minfo.size(); ++mid) {
+            if (!applies(p.minfo[mid], s) || rep[mid] < 0) continue;
+            md[mid] = fft_layout(p, (int)mid, s);
+            reps.push_back(rep[mid]);
+            ltab = ltab && p.minfo[mid].ltab;
+            len = std::max<int64_t>(len, p.minfo[mid].Np);
+        }
+        if (reps.empty()) continue;
+        if (kSched[s].four_step) {
+            rc = ensure_scratch(p, len, std::min<int64_t>((int64_t)reps.size(), (int64_t)kSched[s].per_cu * num_cus()));
+            if (rc) break;
+        }
+        rc = upload_list(&d_rep, reps);
+        if (rc) break;
+        if (hipMemcpy(d_md, md.data(), md.size() * sizeof(MDesc), hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(MR1L_E_HIP, "copy of the spectrum layouts failed");
+            break;
+        }
+        rc = launch_any(p, s, d_rep, (int)reps.size(), d_md, ltab, nullptr, nullptr, 0.0, nullptr, FFT_SPEC, 1.0, 0);
+        if (rc) break;
+        if (hipStreamSynchronize(p.stream) != hipSuccess) {
+            rc = fail(MR1L_E_HIP, "spectrum computation failed");
+            break;
+        }
     }
-    std::vector<int32_t> save_lds = p.lds_lats, save_big = p.big_lats;
-    int32_t *dl = nullptr, *db = nullptr;
-    if (!rep_lds.empty()) {
-        MR1L_HIP(hipMalloc(&dl, rep_lds.size() * sizeof(int32_t)));
-        MR1L_HIP(hipMemcpy(dl, rep_lds.data(), rep_lds.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
-    if (!rep_big.empty()) {
-        MR1L_HIP(hipMalloc(&db, rep_big.size() * sizeof(int32_t)));
-        MR1L_HIP(hipMemcpy(db, rep_big.data(), rep_big.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
-    int32_t *sl = p.d_lds_lats, *sb = p.d_big_lats;
-    p.lds_lats = rep_lds; p.big_lats = rep_big; p.d_lds_lats = dl; p.d_big_lats = db;
-    int rc = fft_run(p, nullptr, nullptr, 0.0, nullptr, FFT_SPEC, 1.0);
-    p.lds_lats = save_lds; p.big_lats = save_big; p.d_lds_lats = sl; p.d_big_lats = sb;
-    if (rc == MR1L_OK) MR1L_HIP(hipStreamSynchronize(p.stream));
-    if (dl) (void)hipFree(dl);
-    if (db) (void)hipFree(db);
+    if (d_rep) (void)hipFree(d_rep);
+    (void)hipFree(d_md);
     return rc;
 }
 

@@ -18,6 +18,8 @@ constexpr int kMaxD = 64;          // lattice dimensions
 constexpr int kMaxCap = 8192;      // detected-list capacity per function
 constexpr int kFftThreads = 1024;  // threads of a DFT workgroup
 constexpr int kLdsBytes = 163840;  // LDS of one gfx950 workgroup
+constexpr int kTabTw = 256;        // LDS twiddles of the four-step sub-transforms
+constexpr int kTabCh = 384;        // LDS two-level chirp table entries of the four-step
 
 // Largest transform held whole in LDS (re and im planes).
 template <typename T> constexpr int lds_max_n() { return kLdsBytes / (2 * (int)sizeof(T)); }
@@ -27,8 +29,6 @@ template <typename T> constexpr int lds_max_n() { return kLdsBytes / (2 * (int)s
 struct LatDesc {
     int64_t node_off;   // O_{f,l}
     int32_t M;          // prime lattice size
-    int32_t N;          // Bluestein length, 5-smooth, >= 2M - 1
-    int32_t N1, N2;     // N = N1 * N2; N2 == 1 when the transform fits LDS
     int32_t mid;        // index of the distinct-size tables (MDesc)
     int32_t func;       // function f
     float inv_m;        // 1/M rounded down (fast modulo)
@@ -36,13 +36,45 @@ struct LatDesc {
     int64_t z_off;      // offset of z_{f,l} in the z tables
 };
 
-// Tables shared by every lattice of one size M.
+// Tables shared by every lattice of one size M, for the DFT schedule in use.
 struct MDesc {
     int64_t spec_off;   // kernel spectrum (N complex) in the spectrum table
     int64_t chirp_off;  // two-level chirp table e^{-pi i r / M}, r < 2M
     int32_t chirp_shift;// log2 of the low table size S
     int32_t chirp_nlo;  // S
-    int64_t tw_N, tw_N1, tw_N2; // twiddle tables e^{-2 pi i m / n}
+    int64_t tw_N;       // twiddle table e^{-2 pi i m / N}, m < N
+    int32_t N;          // Bluestein length >= 2M - 1
+    int32_t N1, N2;     // four-step split N = N1 N2 (N2 == 1: whole transform in LDS)
+};
+
+// ---------------------------------------------------------------- DFT schedules
+// How the Bluestein transform of one lattice runs.  Schedule 0 holds the whole
+// 5-smooth-length transform in one workgroup's LDS; the others are power-of-two
+// four-step transforms that differ in workgroup size, LDS batch (elements per
+// LDS-resident sub-problem), resident workgroups per CU (which sets the register
+// budget) and the split N1 = 2^ceil(k/2) or 2^floor(k/2) of N = 2^k.
+struct FftSched {
+    const char *name;
+    int32_t four_step;
+    int32_t threads;
+    int32_t batch_log2;   // complex128; complex64 uses one more
+    int32_t per_cu;
+    int32_t split_floor;
+};
+constexpr int kNumSched = 9;
+extern const FftSched kSched[kNumSched];
+constexpr int kDefaultFourStep = 1;
+
+// Per distinct lattice size: both possible layouts of its transform.
+struct MInfo {
+    int64_t M = 0;
+    int32_t Ns = 0;           // 5-smooth length (0: too large for one workgroup's LDS)
+    int64_t spec_s = -1, tw_s = -1;
+    int32_t Np = 0;           // power-of-two length
+    int64_t spec_p = -1, tw_p = -1;
+    bool ltab = true;         // four-step tables fit the LDS (M <= 32768, N <= 2^16)
+    int32_t sched = 0;
+    int32_t nlat = 0;
 };
 
 // ---------------------------------------------------------------- plan
@@ -73,13 +105,14 @@ struct Plan {
     void *d_chirp = nullptr;         // chirp tables (dtype complex)
     void *d_tw = nullptr;            // twiddle tables (dtype complex)
     int64_t spec_len = 0, chirp_len = 0, tw_len = 0;
-    // lattice lists per DFT path
-    std::vector<int32_t> lds_lats, big_lats;
-    int32_t *d_lds_lats = nullptr, *d_big_lats = nullptr;
-    int32_t big_maxN = 0;
-    bool big_ltab = true;            // four-step twiddle/chirp tables fit the LDS
-    // scratch
-    void *d_fft_scratch = nullptr;   // [slots][big_maxN] complex (four-step)
+    // DFT schedule per distinct size, lattice lists per schedule
+    std::vector<MInfo> minfo;
+    std::vector<int32_t> grp_lats[kNumSched];
+    int32_t *d_grp_lats[kNumSched] = {};
+    bool grp_ltab[kNumSched] = {};
+    // four-step scratch: one in-place slot of slot_len complex per resident workgroup
+    void *d_fft_scratch = nullptr;
+    int64_t fft_slot_len = 0;
     int32_t fft_slots = 0;
     void *d_nodes_scratch = nullptr; // [nodes] complex (sampler, adjoint)
     int64_t *d_det_tmp = nullptr;    // [F] detected counters
@@ -174,6 +207,11 @@ int launch_fill_bytes(void *p, int64_t nbytes, hipStream_t s);  // zero fill
 int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap,
             int mode, double scale);
 int fft_prepare_spectra(Plan &p);
+int fft_apply_schedules(Plan &p);
+int tuned_schedule(int32_t dtype, int64_t M);
+MDesc fft_layout(const Plan &p, int mid, int s);   // table entry of size mid under schedule s
+int fft_time_group(Plan &p, int sched, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
+                   const void *in, void *out, int reps, float *ms);
 void fft_init_attrs();
 void extract_init_attrs();
 void vote_init_attrs();

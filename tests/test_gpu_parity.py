@@ -177,6 +177,64 @@ def test_fft_matches_direct_dft(m, Ms, dtype):
         off += mm
 
 
+def _fft_check(m, plan, f, dtype, rng):
+    g, _ = m.mr1l_fft(plan, T(f.astype(np.complex128)).to(dtype), theta=0.05)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.complex128)
+    off = 0
+    for mm in plan.M:
+        mm = int(mm)
+        if mm <= 5200:
+            go = oracle.dft(f[off:off + mm], np.array([mm]))
+            bins = np.arange(mm)
+        else:
+            bins = np.unique(np.concatenate([[0, 1, mm - 1], rng.integers(0, mm, 300)]))
+            go = oracle.dft_bins(f[off:off + mm], mm, bins)
+        err = np.abs(g[off + bins] - go).max() / np.abs(go).max()
+        assert err <= TOL[dtype], f"M={mm} err {err:.2e}"
+        off += mm
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("Ms", [[2, 3, 5, 7, 163], [1009, 4133], [16001], [20011, 32749], [40009]])
+def test_fft_every_schedule(m, Ms, dtype):
+    """Every DFT schedule that applies to a size computes the same transform (the
+    sizes 20011 and 32749 sit where the two-level chirp table outgrows its LDS copy)."""
+    rng = np.random.default_rng(7 + sum(Ms))
+    M = np.array(Ms, np.int64)
+    f = rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum()))
+    plan = m.Plan(1, M, np.ones((len(Ms), 1), np.int64), dtype=dtype)
+    names = m.fft_schedule_names()
+    for s, name in enumerate(names):
+        if s == 0 and max(Ms) > 5000:
+            with pytest.raises(m.Mr1lError):
+                plan.fft_schedule(int(M[0]), s)
+            continue
+        for mm in np.unique(M):
+            assert plan.fft_schedule(int(mm), s) == s
+        say("fft schedule", name, Ms, dtype)
+        _fft_check(m, plan, f, dtype, rng)
+
+
+def test_fft_tuner_picks_fastest_and_stays_exact(m):
+    rng = np.random.default_rng(99)
+    M = np.array([211] * 8 + [4133] * 8 + [16001] * 8, np.int64)
+    z = rng.integers(1, 200, size=(len(M), 2)).astype(np.int64)
+    plan = m.Plan(2, M, z)
+    say("fft tune")
+    res = plan.fft_tune(reps=2)
+    assert sorted(res) == [211, 4133, 16001]
+    for mm, times in res.items():
+        assert times and all(t > 0 for t in times.values())
+        assert ("lds" in times) == (mm != 16001)
+        best = min(times, key=times.get)
+        assert m.fft_schedule_names()[plan.fft_schedule(mm)] == best
+        # a later plan of the same size starts on the tuned schedule
+        assert m.Plan(2, np.array([mm]), z[:1]).fft_schedule(mm) == plan.fft_schedule(mm)
+    f = rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum()))
+    _fft_check(m, plan, f, torch.complex128, rng)
+
+
 def test_fft_bitmap_and_aliasing_formula(m):
     """Sample -> DFT on a sparse polynomial equals the bucket sums (eq. (2.4)); the
     bitmap is exactly the set of occupied buckets."""
