@@ -168,6 +168,55 @@ def plain_pass(m, torch, w, reps=2):
     return best, bufs
 
 
+# ----------------------------------------------------------------------------- dimincr
+def bench_dimincr(m, torch, args):
+    """Algorithm 3 Step 2 driver on the dimension-incremental workload: d = 25, s = 200
+    frequencies uniform in [-32, 32]^25 with complex N(0,1) coefficients, r = 5,
+    s_local = 400, one lattice size M = 4133, L by eq. (4.2), theta = 1e-12.  Each
+    step is one full driver run on a new polynomial (seeds 0, 1, ...); the samples are
+    taken inside the driver by the library's sampler."""
+    import synth
+    d, s, N, r, Mlat = 25, 200, 32, 5, 4133
+    dev = torch.device("cuda", 0)
+    runs = []
+    for i in range(args.warmup + args.steps):
+        seed = i % 5
+        freq, coef = synth.sparse_poly_box(seed, d=d, s=s, box=N)
+        pf = torch.from_numpy(freq).to(dev)
+        pc = torch.from_numpy(coef).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gf, gc, ns = m.mr1l_dimincr(d, N, s, 2 * s, r, 1e-12, Mlat, 1000 + seed, poly_freq=pf, poly_coef=pc)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
+        ok = [tuple(x) for x in gf.tolist()] == [t[0] for t in truth]
+        err = (float(np.linalg.norm(gc - np.array([t[1] for t in truth])) / np.linalg.norm(coef))
+               if ok else None)
+        log(f"driver run {i} (seed {seed}): {dt:.3f} s, {ns} samples, support exact {ok}, rel err {err}")
+        if i >= args.warmup:
+            runs.append(dict(seed=seed, s=dt, samples=ns, support_exact=ok, rel_err=err))
+    wall = float(np.median([x["s"] for x in runs]))
+    out = {"metric": "dimension-incremental driver wall time", "value": wall, "unit": "s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * wall,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+           "data": "synthetic",
+           "config": {"workload": "dimension-incremental: d=25, s=200 in [-32,32]^25, r=5, s_local=400, "
+                                  "M=4133, L by eq. (4.2), theta=1e-12, Algorithm 3 Step 2"},
+           "runs": runs}
+    if not args.no_cpu:
+        import oracle
+        freq, coef = synth.sparse_poly_box(0, d=d, s=s, box=N)
+        t0 = time.perf_counter()
+        of, oc, ns = oracle.dimincr(freq, coef, N=N, s=s, s_local=2 * s, r=r, theta=1e-12, c=10.33,
+                                    delta=0.9, Mlat=Mlat, seed=1000)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": dt, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": "one full driver run (seed 0) of the oracle: direct DFTs, "
+                                         "long-double arithmetic"}
+    print(json.dumps(out), flush=True)
+
+
 # ----------------------------------------------------------------------------- oracle legs
 def cpu_baseline_large(w, n_sample, budget_s=10.0):
     """Oracle on one function of the batch, repeated until ~budget_s of CPU time: direct
@@ -229,7 +278,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("large", "batch"), default="large")
+    ap.add_argument("--workload", choices=("large", "batch", "dimincr"), default="large")
     ap.add_argument("--functions", type=int, default=None)
     ap.add_argument("--candidates", type=int, default=10_000_000)
     ap.add_argument("--c64", action="store_true")
@@ -254,6 +303,8 @@ def main():
     import paper_2006_13053_amd as m
     torch.cuda.set_device(0)
     m.lib()
+    if args.workload == "dimincr":
+        return bench_dimincr(m, torch, args)
 
     if args.workload == "large":
         F = args.functions or 64

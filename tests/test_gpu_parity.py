@@ -556,3 +556,25 @@ def test_dimincr_matches_oracle_driver(m, seed):
     close(gc, oc, 1e-11, "driver coefficients")
     truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
     assert [tuple(r) for r in gf.tolist()] == [t[0] for t in truth]
+
+
+def test_dimincr_full_size_matches_oracle_and_truth(m):
+    """The dimension-incremental workload at full size: d = 25, s = 200 frequencies
+    uniform in [-32, 32]^25, r = 5, s_local = 400, M = 4133, theta = 1e-12.  The
+    driver's result equals the oracle driver's (same lattices from the same
+    SplitMix64 streams), recovers the support exactly, and its coefficients are
+    exact to 1e-11 (relative l2)."""
+    d, s, N, r, Mlat, seed = 25, 200, 32, 5, 4133, 1000
+    freq, coef = synth.sparse_poly_box(0, d=d, s=s, box=N)
+    say("dimincr full size: oracle")
+    of, oc, ns = oracle.dimincr(freq, coef, N=N, s=s, s_local=2 * s, r=r, theta=1e-12, c=10.33, delta=0.9,
+                                Mlat=Mlat, seed=seed)
+    say("dimincr full size: gpu")
+    gf, gc, gs = m.mr1l_dimincr(d, N, s, 2 * s, r, 1e-12, Mlat, seed, poly_freq=T(freq), poly_coef=T(coef))
+    assert gs == ns
+    assert np.array_equal(gf, of)
+    close(gc, oc, 1e-11, "driver coefficients")
+    truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
+    assert [tuple(x) for x in gf.tolist()] == [t[0] for t in truth]
+    c_truth = np.array([t[1] for t in truth])
+    assert np.linalg.norm(gc - c_truth) / np.linalg.norm(c_truth) < 1e-11
