@@ -310,8 +310,8 @@ static void release(Plan *p)
                     p->d_termoff_default};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
-    for (int s = 0; s < kNumSched; ++s)
-        if (p->d_grp_lats[s]) (void)hipFree(p->d_grp_lats[s]);
+    for (FftGroup &g : p->fft_groups)
+        if (g.d_lats) (void)hipFree(g.d_lats);
     delete p;
 }
 
@@ -716,7 +716,8 @@ int mr1l_fft_tune(mr1l_plan p, int32_t reps, int32_t max_sizes, int64_t *sizes, 
                     rc = fail(MR1L_E_HIP, "copy of the tuning layout failed");
                     break;
                 }
-                rc = fft_time_group(*p, s, d_list, (int)lst.size(), d_md, mi.ltab, in, out, reps, &ms);
+                const int cls = kSched[s].four_step ? 0 : lds_class(mi.Ns);
+                rc = fft_time_group(*p, s, cls, d_list, (int)lst.size(), d_md, mi.ltab, in, out, reps, &ms);
                 if (rc) break;
                 if (best_ms == 0.f || ms < best_ms) { best_ms = ms; best = s; }
             }

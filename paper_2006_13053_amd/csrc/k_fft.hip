@@ -21,10 +21,16 @@
 // products fused into the column load and the row store.
 #include <algorithm>
 #include <initializer_list>
+#include <map>
 
 #include "mr1l_internal.h"
 
 namespace mr1l {
+
+// The thread index laundered through an empty asm: index arithmetic derived from
+// it cannot be hoisted out of the batch loops, where it would stay live through
+// every Stockham pass and spill.
+__device__ __forceinline__ int opaque(int x) { asm volatile("" : "+v"(x)); return x; }
 
 // ------------------------------------------------------------------ radix DFTs
 template <typename T>
@@ -131,20 +137,20 @@ __device__ __forceinline__ int next_radix(int rem)
 // x[b n + jj + r n/R] (jj = j mod n/R), multiplies by e^{-2 pi i r k/(Ns R)}
 // (k = jj mod Ns), applies the radix-R DFT and writes
 // x[b n + (jj / Ns) Ns R + k + r Ns].
-template <typename T, int R>
+template <typename T, int R, int NT, int NMAXT>
 __device__ void stockham_pass(T *re, T *im, int n, int batch, int Ns,
                               const typename cvec<T>::type *__restrict__ tw)
 {
-    constexpr int NMAX = lds_max_n<T>();
-    constexpr int BPT = (NMAX / R + kFftThreads - 1) / kFftThreads;
+    constexpr int BPT = (NMAXT / R + NT - 1) / NT;
     const int nR = n / R;
     const int total = batch * nR;
     const int tstride = n / (Ns * R);
+    const int tid0 = opaque((int)threadIdx.x);
     T vr[BPT][R], vi[BPT][R];
     int ob[BPT];
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
-        const int j = threadIdx.x + i * kFftThreads;
+        const int j = tid0 + i * NT;
         ob[i] = -1;
         if (j < total) {
             const int b = j / nR;
@@ -184,20 +190,21 @@ __device__ void stockham_pass(T *re, T *im, int n, int batch, int Ns,
     __syncthreads();
 }
 
-// Forward FFT (e^{-2 pi i}) of `batch` contiguous length-n transforms in LDS;
-// tw = table e^{-2 pi i m / n}, m < n.  Output in natural order.
-template <typename T>
+// Forward FFT (e^{-2 pi i}) of `batch` contiguous length-n transforms in LDS
+// (batch * n <= NMAXT) by NT threads; tw = table e^{-2 pi i m / n}, m < n.
+// Output in natural order.
+template <typename T, int NT, int NMAXT>
 __device__ void lds_fft(T *re, T *im, int n, int batch, const typename cvec<T>::type *tw)
 {
     int Ns = 1, rem = n;
     while (rem > 1) {
         const int R = next_radix(rem);
         switch (R) {
-        case 8: stockham_pass<T, 8>(re, im, n, batch, Ns, tw); break;
-        case 4: stockham_pass<T, 4>(re, im, n, batch, Ns, tw); break;
-        case 2: stockham_pass<T, 2>(re, im, n, batch, Ns, tw); break;
-        case 5: stockham_pass<T, 5>(re, im, n, batch, Ns, tw); break;
-        default: stockham_pass<T, 3>(re, im, n, batch, Ns, tw); break;
+        case 8: stockham_pass<T, 8, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
+        case 4: stockham_pass<T, 4, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
+        case 2: stockham_pass<T, 2, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
+        case 5: stockham_pass<T, 5, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
+        default: stockham_pass<T, 3, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
         }
         Ns *= R;
         rem /= R;
@@ -248,10 +255,6 @@ __device__ __forceinline__ void dft16(T *xr, T *xi)
 // strides of the column accesses and of the early Stockham passes (bank
 // conflicts).
 __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
-// The thread index laundered through an empty asm: index arithmetic derived from
-// it cannot be hoisted out of the batch loops, where it would stay live through
-// every Stockham pass and spill.
-__device__ __forceinline__ int opaque(int x) { asm volatile("" : "+v"(x)); return x; }
 constexpr int p2_plane(int P) { return P + P / 16; }
 
 // One Stockham pass of radix 2^LR over 2^logb transforms of length 2^logn held
@@ -354,11 +357,13 @@ __device__ __forceinline__ void set_bit_if(uint32_t *bitmap, int64_t g, T re, T 
 }
 
 // ------------------------------------------------------------------ LDS kernel
-// One workgroup per lattice with N <= NMAX.  mode: FFT_FWD (f -> ghat, bitmap),
+// One workgroup of NT threads per lattice with N <= NMAXT, the whole transform in
+// the workgroup's LDS (2 NMAXT elements).  mode: FFT_FWD (f -> ghat, bitmap),
 // FFT_INV (g -> (1/M) sum g e^{+}) times scale (times M when scale_by_m),
 // FFT_SPEC (kernel spectrum of the lattice size, written to the spectrum table).
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_bluestein_lds(
+// Size classes (NT, NMAXT) keep small transforms from holding a whole CU's LDS.
+template <typename T, int NT, int NMAXT>
+__global__ __launch_bounds__(NT) void k_bluestein_lds(
     const int32_t *__restrict__ lats, const LatDesc *__restrict__ lat, const MDesc *__restrict__ md,
     const typename cvec<T>::type *__restrict__ in, typename cvec<T>::type *__restrict__ out,
     typename cvec<T>::type *__restrict__ spec_tab, const typename cvec<T>::type *__restrict__ chirp_tab,
@@ -368,7 +373,7 @@ __global__ __launch_bounds__(kFftThreads) void k_bluestein_lds(
     using V = typename cvec<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     T *re = reinterpret_cast<T *>(smem);
-    T *im = re + lds_max_n<T>();
+    T *im = re + NMAXT;
     const LatDesc ld = lat[lats[blockIdx.x]];
     const MDesc m = md[ld.mid];
     const int N = m.N, M = ld.M;
@@ -379,7 +384,7 @@ __global__ __launch_bounds__(kFftThreads) void k_bluestein_lds(
 
     if (mode == FFT_SPEC) {
         // B[n] = conj(w[n]) for n < M, B[N - n] = conj(w[n]) for 0 < n < M
-        for (int i = tid; i < N; i += kFftThreads) {
+        for (int i = tid; i < N; i += NT) {
             int src = -1;
             if (i < M) src = i;
             else if (i > N - M) src = N - i;
@@ -391,10 +396,10 @@ __global__ __launch_bounds__(kFftThreads) void k_bluestein_lds(
             re[i] = xr; im[i] = xi;
         }
         __syncthreads();
-        lds_fft<T>(re, im, N, 1, tw);
+        lds_fft<T, NT, NMAXT>(re, im, N, 1, tw);
         const T s = T(1) / ((T)N * (T)M);
         V *dst = spec_tab + m.spec_off;
-        for (int i = tid; i < N; i += kFftThreads) {
+        for (int i = tid; i < N; i += NT) {
             V o; o.x = re[i] * s; o.y = im[i] * s;
             dst[i] = o;
         }
@@ -403,40 +408,37 @@ __global__ __launch_bounds__(kFftThreads) void k_bluestein_lds(
 
     const T cj = (mode == FFT_INV) ? T(-1) : T(1);
     const V *x = in + ld.node_off;
-    constexpr int EPT = (lds_max_n<T>() + kFftThreads - 1) / kFftThreads;
+    constexpr int EPT = (NMAXT + NT - 1) / NT;
     {
         T xr[EPT], xi[EPT];
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
-            const int i = tid + k * kFftThreads;
-            xr[k] = 0; xi[k] = 0;
-            if (i < M) {
-                V v = x[i];
-                V w = chirp<T>(ctab, m.chirp_shift, m.chirp_nlo, i, M, inv2m);
-                const T vi = cj * v.y;
-                xr[k] = v.x * w.x - vi * w.y;
-                xi[k] = v.x * w.y + vi * w.x;
-            }
+            const int i = opaque(tid) + k * NT;
+            const V v = x[i < M ? i : 0];
+            const V w = chirp<T>(ctab, m.chirp_shift, m.chirp_nlo, i < M ? i : 0, M, inv2m);
+            const T vi = cj * v.y;
+            xr[k] = i < M ? v.x * w.x - vi * w.y : T(0);
+            xi[k] = i < M ? v.x * w.y + vi * w.x : T(0);
         }
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
-            const int i = tid + k * kFftThreads;
+            const int i = opaque(tid) + k * NT;
             if (i < N) { re[i] = xr[k]; im[i] = xi[k]; }
         }
     }
     __syncthreads();
-    lds_fft<T>(re, im, N, 1, tw);
+    lds_fft<T, NT, NMAXT>(re, im, N, 1, tw);
     const V *sp = spec_tab + m.spec_off;
     {
         V sv[EPT];
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
-            const int i = tid + k * kFftThreads;
-            if (i < N) sv[k] = sp[i];
+            const int i = opaque(tid) + k * NT;
+            sv[k] = sp[i < N ? i : 0];
         }
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
-            const int i = tid + k * kFftThreads;
+            const int i = opaque(tid) + k * NT;
             if (i < N) {
                 T a = re[i], b = im[i];
                 re[i] = a * sv[k].x - b * sv[k].y;
@@ -445,10 +447,10 @@ __global__ __launch_bounds__(kFftThreads) void k_bluestein_lds(
         }
     }
     __syncthreads();
-    lds_fft<T>(re, im, N, 1, tw);
+    lds_fft<T, NT, NMAXT>(re, im, N, 1, tw);
     const T sc = scale_by_m ? scale * (T)M : scale;
     V *y = out + ld.node_off;
-    for (int i = tid; i < M; i += kFftThreads) {
+    for (int i = tid; i < M; i += NT) {
         V w = chirp<T>(ctab, m.chirp_shift, m.chirp_nlo, i, M, inv2m);
         const T cr = re[i], ci = -im[i];     // undo the conjugation
         T gr = (cr * w.x - ci * w.y) * sc;
@@ -459,7 +461,6 @@ __global__ __launch_bounds__(kFftThreads) void k_bluestein_lds(
         if (mode == FFT_FWD && bitmap) set_bit_if<T>(bitmap, ld.node_off + i, gr, gi, th2);
     }
 }
-
 
 // ------------------------------------------------------------------ four-step kernel
 // Power-of-two N = N1 N2 (N1, N2 <= P, the LDS batch), three phases per lattice
@@ -760,12 +761,25 @@ static int launch4(Plan &p, const int32_t *d_lats, int nl, const MDesc *d_md, co
 }
 
 // One launch of schedule s over the lattices d_lats (their sizes' tables in d_md).
+template <typename T, int NT, int NMAXT>
+static int launch_lds(Plan &p, const int32_t *d_lats, int nl, const MDesc *d_md, const void *in, void *out,
+                      T th2, uint32_t *bitmap, int mode, T sc, int by_m)
+{
+    using V = typename cvec<T>::type;
+    constexpr size_t shm = 2 * sizeof(T) * (size_t)NMAXT;
+    static_assert(shm <= (size_t)kLdsBytes, "LDS transform budget");
+    hipLaunchKernelGGL((k_bluestein_lds<T, NT, NMAXT>), dim3((unsigned)nl), dim3(NT), shm, p.stream, d_lats, p.d_lat,
+                       d_md, (const V *)in, (V *)out, (V *)p.d_spec, (const V *)p.d_chirp, (const V *)p.d_tw, bitmap,
+                       th2, mode, sc, by_m);
+    MR1L_LAUNCH_CHECK();
+    return MR1L_OK;
+}
+
 template <typename T>
-static int launch_sched(Plan &p, int s, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
+static int launch_sched(Plan &p, int s, int cls, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
                         const void *in, void *out, double theta, uint32_t *bitmap, int mode, double scale,
                         int by_m)
 {
-    using V = typename cvec<T>::type;
     constexpr int LS = sizeof(T) == 8 ? 12 : 13;   // log2 LDS batch of the two-per-CU schedules
     const T th2 = (T)(theta * theta);
     const T sc = (T)scale;
@@ -773,11 +787,9 @@ static int launch_sched(Plan &p, int s, const int32_t *d_lats, int nl, const MDe
     if (nl <= 0) return MR1L_OK;
     switch (s) {
     case 0:
-        hipLaunchKernelGGL(k_bluestein_lds<T>, dim3((unsigned)nl), dim3(kFftThreads), (size_t)kLdsBytes, p.stream,
-                           d_lats, p.d_lat, d_md, (const V *)in, (V *)out, (V *)p.d_spec, (const V *)p.d_chirp,
-                           (const V *)p.d_tw, bitmap, th2, mode, sc, by_m);
-        MR1L_LAUNCH_CHECK();
-        return MR1L_OK;
+        if (cls == 0) return launch_lds<T, 128, 1024>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m);
+        if (cls == 1) return launch_lds<T, 512, 4096>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m);
+        return launch_lds<T, kFftThreads, lds_max_n<T>()>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m);
     case 1: case 2:
         return ltab ? launch4<T, true, 512, LS, 4>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc)
                     : launch4<T, false, 512, LS, 4>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc);
@@ -795,12 +807,12 @@ static int launch_sched(Plan &p, int s, const int32_t *d_lats, int nl, const MDe
     }
 }
 
-static int launch_any(Plan &p, int s, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab, const void *in,
-                      void *out, double theta, uint32_t *bitmap, int mode, double scale, int by_m)
+static int launch_any(Plan &p, int s, int cls, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
+                      const void *in, void *out, double theta, uint32_t *bitmap, int mode, double scale, int by_m)
 {
     return p.dtype == MR1L_C128
-               ? launch_sched<double>(p, s, d_lats, nl, d_md, ltab, in, out, theta, bitmap, mode, scale, by_m)
-               : launch_sched<float>(p, s, d_lats, nl, d_md, ltab, in, out, theta, bitmap, mode, scale, by_m);
+               ? launch_sched<double>(p, s, cls, d_lats, nl, d_md, ltab, in, out, theta, bitmap, mode, scale, by_m)
+               : launch_sched<float>(p, s, cls, d_lats, nl, d_md, ltab, in, out, theta, bitmap, mode, scale, by_m);
 }
 
 template <typename K> static void allow_lds_one(K k)
@@ -811,7 +823,9 @@ template <typename K> static void allow_lds_one(K k)
 template <typename T> static void allow_lds()
 {
     constexpr int LS = sizeof(T) == 8 ? 12 : 13;
-    allow_lds_one(k_bluestein_lds<T>);
+    allow_lds_one(k_bluestein_lds<T, 128, 1024>);
+    allow_lds_one(k_bluestein_lds<T, 512, 4096>);
+    allow_lds_one(k_bluestein_lds<T, kFftThreads, lds_max_n<T>()>);
     allow_lds_one(k_bluestein_4step<T, true, 512, LS, 4>);
     allow_lds_one(k_bluestein_4step<T, false, 512, LS, 4>);
     allow_lds_one(k_bluestein_4step<T, true, 512, LS + 1, 2>);
@@ -831,10 +845,9 @@ int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap, 
         int rc = launch_fill_u32(bitmap, (p.nodes + 31) / 32, 0u, p.stream);
         if (rc) return rc;
     }
-    for (int s = 0; s < kNumSched; ++s) {
-        if (p.grp_lats[s].empty()) continue;
-        int rc = launch_any(p, s, p.d_grp_lats[s], (int)p.grp_lats[s].size(), p.d_mdesc, p.grp_ltab[s], in, out,
-                            theta, bitmap, mode, scale, by_m);
+    for (const FftGroup &g : p.fft_groups) {
+        int rc = launch_any(p, g.sched, g.cls, g.d_lats, (int)g.lats.size(), p.d_mdesc, g.ltab, in, out, theta,
+                            bitmap, mode, scale, by_m);
         if (rc) return rc;
     }
     return MR1L_OK;
@@ -900,30 +913,39 @@ int fft_apply_schedules(Plan &p)
     MR1L_HIP(hipStreamSynchronize(p.stream));
     for (size_t mid = 0; mid < p.minfo.size(); ++mid) p.mdesc[mid] = fft_layout(p, (int)mid, p.minfo[mid].sched);
     MR1L_HIP(hipMemcpy(p.d_mdesc, p.mdesc.data(), p.mdesc.size() * sizeof(MDesc), hipMemcpyHostToDevice));
+    for (FftGroup &g : p.fft_groups)
+        if (g.d_lats) (void)hipFree(g.d_lats);
+    p.fft_groups.clear();
+    std::map<std::pair<int, int>, size_t> gi;   // (schedule, class) -> group
     int64_t len = 0, slots = 0;
-    for (int s = 0; s < kNumSched; ++s) {
-        p.grp_lats[s].clear();
-        p.grp_ltab[s] = true;
-    }
     for (size_t i = 0; i < p.lat.size(); ++i) {
         const MInfo &mi = p.minfo[p.lat[i].mid];
-        p.grp_lats[mi.sched].push_back((int32_t)i);
-        p.grp_ltab[mi.sched] = p.grp_ltab[mi.sched] && mi.ltab;
+        const int cls = kSched[mi.sched].four_step ? 0 : lds_class(mi.Ns);
+        auto it = gi.find({mi.sched, cls});
+        if (it == gi.end()) {
+            it = gi.emplace(std::make_pair(mi.sched, cls), p.fft_groups.size()).first;
+            p.fft_groups.emplace_back();
+            p.fft_groups.back().sched = mi.sched;
+            p.fft_groups.back().cls = cls;
+        }
+        FftGroup &g = p.fft_groups[it->second];
+        g.lats.push_back((int32_t)i);
+        g.ltab = g.ltab && mi.ltab;
         if (kSched[mi.sched].four_step) len = std::max<int64_t>(len, mi.Np);
     }
-    for (int s = 0; s < kNumSched; ++s) {
-        int rc = upload_list(&p.d_grp_lats[s], p.grp_lats[s]);
+    for (FftGroup &g : p.fft_groups) {
+        int rc = upload_list(&g.d_lats, g.lats);
         if (rc) return rc;
-        if (kSched[s].four_step && !p.grp_lats[s].empty())
-            slots = std::max<int64_t>(slots, std::min<int64_t>((int64_t)p.grp_lats[s].size(),
-                                                               (int64_t)kSched[s].per_cu * num_cus()));
+        if (kSched[g.sched].four_step)
+            slots = std::max<int64_t>(slots, std::min<int64_t>((int64_t)g.lats.size(),
+                                                               (int64_t)kSched[g.sched].per_cu * num_cus()));
     }
     if (len > 0) return ensure_scratch(p, len, slots);
     return MR1L_OK;
 }
 
-int fft_time_group(Plan &p, int s, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab, const void *in,
-                   void *out, int reps, float *ms)
+int fft_time_group(Plan &p, int s, int cls, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
+                   const void *in, void *out, int reps, float *ms)
 {
     if (kSched[s].four_step) {
         int64_t len = 0;
@@ -931,14 +953,14 @@ int fft_time_group(Plan &p, int s, const int32_t *d_lats, int nl, const MDesc *d
         int rc = ensure_scratch(p, len, std::min<int64_t>(nl, (int64_t)kSched[s].per_cu * num_cus()));
         if (rc) return rc;
     }
-    int rc = launch_any(p, s, d_lats, nl, d_md, ltab, in, out, 0.0, nullptr, FFT_FWD, 1.0, 0);
+    int rc = launch_any(p, s, cls, d_lats, nl, d_md, ltab, in, out, 0.0, nullptr, FFT_FWD, 1.0, 0);
     if (rc) return rc;
     hipEvent_t a, b;
     MR1L_HIP(hipEventCreate(&a));
     MR1L_HIP(hipEventCreate(&b));
     MR1L_HIP(hipEventRecord(a, p.stream));
     for (int r = 0; r < reps && rc == MR1L_OK; ++r)
-        rc = launch_any(p, s, d_lats, nl, d_md, ltab, in, out, 0.0, nullptr, FFT_FWD, 1.0, 0);
+        rc = launch_any(p, s, cls, d_lats, nl, d_md, ltab, in, out, 0.0, nullptr, FFT_FWD, 1.0, 0);
     MR1L_HIP(hipEventRecord(b, p.stream));
     MR1L_HIP(hipEventSynchronize(b));
     float t = 0.f;
@@ -984,7 +1006,9 @@ int fft_prepare_spectra(Plan &p)
             rc = fail(MR1L_E_HIP, "copy of the spectrum layouts failed");
             break;
         }
-        rc = launch_any(p, s, d_rep, (int)reps.size(), d_md, ltab, nullptr, nullptr, 0.0, nullptr, FFT_SPEC, 1.0, 0);
+        // the largest LDS class holds every whole-LDS size
+        rc = launch_any(p, s, kLdsClasses - 1, d_rep, (int)reps.size(), d_md, ltab, nullptr, nullptr, 0.0, nullptr,
+                        FFT_SPEC, 1.0, 0);
         if (rc) break;
         if (hipStreamSynchronize(p.stream) != hipSuccess) {
             rc = fail(MR1L_E_HIP, "spectrum computation failed");

@@ -65,6 +65,17 @@ constexpr int kNumSched = 9;
 extern const FftSched kSched[kNumSched];
 constexpr int kDefaultFourStep = 1;
 
+// Lattices launched together: schedule, LDS size class (schedule 0), whether the
+// four-step tables fit the LDS, and the lattice list (host and device).
+struct FftGroup {
+    int32_t sched = 0, cls = 0;
+    bool ltab = true;
+    std::vector<int32_t> lats;
+    int32_t *d_lats = nullptr;
+};
+constexpr int kLdsClasses = 3;     // whole-LDS transforms: N <= 1024, <= 4096, <= NMAX
+inline int lds_class(int64_t N) { return N <= 1024 ? 0 : (N <= 4096 ? 1 : 2); }
+
 // Per distinct lattice size: both possible layouts of its transform.
 struct MInfo {
     int64_t M = 0;
@@ -105,11 +116,10 @@ struct Plan {
     void *d_chirp = nullptr;         // chirp tables (dtype complex)
     void *d_tw = nullptr;            // twiddle tables (dtype complex)
     int64_t spec_len = 0, chirp_len = 0, tw_len = 0;
-    // DFT schedule per distinct size, lattice lists per schedule
+    // DFT schedule per distinct size; one launch per group of lattices with the
+    // same schedule (and, for schedule 0, the same LDS size class)
     std::vector<MInfo> minfo;
-    std::vector<int32_t> grp_lats[kNumSched];
-    int32_t *d_grp_lats[kNumSched] = {};
-    bool grp_ltab[kNumSched] = {};
+    std::vector<FftGroup> fft_groups;
     // four-step scratch: one in-place slot of slot_len complex per resident workgroup
     void *d_fft_scratch = nullptr;
     int64_t fft_slot_len = 0;
@@ -210,7 +220,7 @@ int fft_prepare_spectra(Plan &p);
 int fft_apply_schedules(Plan &p);
 int tuned_schedule(int32_t dtype, int64_t M);
 MDesc fft_layout(const Plan &p, int mid, int s);   // table entry of size mid under schedule s
-int fft_time_group(Plan &p, int sched, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
+int fft_time_group(Plan &p, int sched, int cls, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
                    const void *in, void *out, int reps, float *ms);
 void fft_init_attrs();
 void extract_init_attrs();
