@@ -393,13 +393,17 @@ int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int6
             if (v < 0 || v >= M[i]) return fail(MR1L_E_ARG, "generating vector entry outside [0, M)");
         }
     }
-    static bool attrs_done = false;
-    if (!attrs_done) {
-        fft_init_attrs();
-        extract_init_attrs();
-        vote_init_attrs();
-        attrs_done = true;
-    }
+    // LDS limits of the kernels, once per process (the first plan's device)
+    static std::once_flag attrs_once;
+    static int attrs_rc = MR1L_OK;
+    static std::string attrs_err;
+    std::call_once(attrs_once, [] {
+        attrs_rc = fft_init_attrs();
+        if (!attrs_rc) attrs_rc = extract_init_attrs();
+        if (!attrs_rc) attrs_rc = vote_init_attrs();
+        if (attrs_rc) attrs_err = g_err;
+    });
+    if (attrs_rc) return fail(attrs_rc, "kernel attribute setup failed: " + attrs_err);
     mr1l_plan_s *p = new (std::nothrow) mr1l_plan_s();
     if (!p) return fail(MR1L_E_NOMEM, "host allocation failed");
     p->d = d; p->F = F; p->L = L; p->dtype = dtype;

@@ -4,10 +4,10 @@
 //  k_sort_det    detected set of each function in ascending candidate order
 //                (one workgroup per function, bitonic sort in LDS).
 //  k_det_hash    buckets h_l(k) of every detected candidate.
-//  k_singleton   occupancy of each bucket by the detected set, one workgroup
-//                per lattice with an LDS histogram; bit l of mask[q] is set
-//                when candidate q is alone in its bucket (the sets of
-//                Remark 2.9).
+//  k_singleton   whether each bucket holds one or several detected candidates,
+//                one workgroup per lattice with two LDS bitmaps; bit l of
+//                mask[q] is set when candidate q is alone in its bucket (the
+//                sets of Remark 2.9).
 //  k_combine     medians of the real and imaginary parts of the L lattice
 //                values (eq. (2.10); even L: mean of the two middle order
 //                statistics; order by value, ties by lattice index) and the
@@ -17,6 +17,8 @@
 //                ascending candidate index, first s~ (bitonic sort in LDS).
 //  k_adjoint_scatter  transpose of the gather/combination: coefficient
 //                gradients into buckets (the inverse lattice DFT follows).
+#include <algorithm>
+
 #include "mr1l_internal.h"
 
 namespace mr1l {
@@ -30,10 +32,12 @@ __device__ __forceinline__ int64_t n_of(const int64_t *n_det, int f, int64_t cap
 }
 
 // ------------------------------------------------------------------ sort detected
+// Dynamic LDS: pow2ceil(cap) keys.
 __global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__restrict__ n_det, int64_t cap,
                                                            int64_t *__restrict__ det_idx)
 {
-    __shared__ int64_t key[kMaxCap];
+    extern __shared__ __align__(16) unsigned char smem[];
+    int64_t *key = reinterpret_cast<int64_t *>(smem);
     const int f = blockIdx.x;
     const int n = (int)n_of(n_det, f, cap);
     if (n <= 1) return;
@@ -92,32 +96,47 @@ __global__ __launch_bounds__(256) void k_det_hash(
 }
 
 // ------------------------------------------------------------------ singletons
-constexpr int kHistBins = 40960;   // 160 KiB of int32 counters
+// One workgroup per lattice (f, l).  Two LDS bitmaps over the buckets: the first
+// atomicOr of a bucket's bit in `once` returns it clear, every later one sets the
+// bit in `twice`; a detected candidate is alone in its bucket exactly when the
+// bucket's `twice` bit stays clear.  Buckets beyond one LDS span are handled in
+// further passes over the detected set.
+constexpr int kSingleWords = 20480;   // words per bitmap: 2 x 80 KiB of LDS at most
 
-__global__ __launch_bounds__(1024) void k_singleton(const LatDesc *__restrict__ lat, int L,
-                                                    const int64_t *__restrict__ n_det, int64_t cap,
-                                                    const int32_t *__restrict__ det_hash,
-                                                    uint32_t *__restrict__ mask)
+__global__ __launch_bounds__(256) void k_singleton(const LatDesc *__restrict__ lat, int L,
+                                                   const int64_t *__restrict__ n_det, int64_t cap,
+                                                   const int32_t *__restrict__ det_hash,
+                                                   uint32_t *__restrict__ mask, int words)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    int32_t *hist = reinterpret_cast<int32_t *>(smem);
+    uint32_t *once = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *twice = once + words;
     const int l = blockIdx.x, f = blockIdx.y;
     const int n = (int)n_of(n_det, f, cap);
     if (n == 0) return;
     const int M = lat[f * L + l].M;
     const int32_t *hh = det_hash + (int64_t)f * cap * L;
-    for (int c0 = 0; c0 < M; c0 += kHistBins) {
-        const int c1 = min(M, c0 + kHistBins);
-        for (int i = threadIdx.x; i < c1 - c0; i += blockDim.x) hist[i] = 0;
+    const int span = words * 32;
+    for (int c0 = 0; c0 < M; c0 += span) {
+        const int c1 = min(M, c0 + span);
+        const int nw = (c1 - c0 + 31) >> 5;
+        for (int i = threadIdx.x; i < nw; i += blockDim.x) { once[i] = 0u; twice[i] = 0u; }
         __syncthreads();
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
             const int h = hh[(int64_t)q * L + l];
-            if (h >= c0 && h < c1) atomicAdd(hist + (h - c0), 1);
+            if (h >= c0 && h < c1) {
+                const int r = h - c0;
+                const uint32_t bit = 1u << (r & 31);
+                if (atomicOr(once + (r >> 5), bit) & bit) atomicOr(twice + (r >> 5), bit);
+            }
         }
         __syncthreads();
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
             const int h = hh[(int64_t)q * L + l];
-            if (h >= c0 && h < c1 && hist[h - c0] == 1) atomicOr(mask + (int64_t)f * cap + q, 1u << l);
+            if (h >= c0 && h < c1) {
+                const int r = h - c0;
+                if (!((twice[r >> 5] >> (r & 31)) & 1u)) atomicOr(mask + (int64_t)f * cap + q, 1u << l);
+            }
         }
         __syncthreads();
     }
@@ -211,6 +230,7 @@ __global__ __launch_bounds__(256) void k_combine(
 }
 
 // ------------------------------------------------------------------ limit (Algorithm 4)
+// Dynamic LDS: pow2ceil(cap) keys and positions.
 template <typename T>
 __global__ __launch_bounds__(kSortThreads) void k_limit(
     const int64_t *__restrict__ n_det, int64_t cap, const int64_t *__restrict__ det_idx,
@@ -218,9 +238,12 @@ __global__ __launch_bounds__(kSortThreads) void k_limit(
     int64_t *__restrict__ out_idx, typename cvec<T>::type *__restrict__ out_coef, int32_t *__restrict__ out_pos)
 {
     using V = typename cvec<T>::type;
-    __shared__ uint64_t key[kMaxCap];
-    __shared__ int32_t pos[kMaxCap];
+    extern __shared__ __align__(16) unsigned char smem[];   // pow2ceil(cap) keys, then positions
     __shared__ int npass;
+    int Pc = 1;
+    while (Pc < cap) Pc <<= 1;
+    uint64_t *key = reinterpret_cast<uint64_t *>(smem);
+    int32_t *pos = reinterpret_cast<int32_t *>(key + Pc);
     const int f = blockIdx.x;
     const int n = (int)n_of(n_det, f, cap);
     if (threadIdx.x == 0) npass = 0;
@@ -313,10 +336,23 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, const int3
     return MR1L_OK;
 }
 
-void extract_init_attrs()
+int extract_init_attrs()
 {
-    (void)hipFuncSetAttribute((const void *)k_singleton, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kHistBins * (int)sizeof(int32_t));
+    // dynamic LDS at the largest capacity (static LDS comes on top of it)
+    const std::pair<const void *, int> ks[] = {
+        {(const void *)k_singleton, 2 * kSingleWords * (int)sizeof(uint32_t)},
+        {(const void *)k_sort_det, kMaxCap * (int)sizeof(int64_t)},
+        {(const void *)k_limit<double>, kMaxCap * 12},
+        {(const void *)k_limit<float>, kMaxCap * 12}};
+    for (const auto &k : ks) MR1L_HIP(hipFuncSetAttribute(k.first, hipFuncAttributeMaxDynamicSharedMemorySize, k.second));
+    return MR1L_OK;
+}
+
+static int64_t pow2ceil(int64_t n)
+{
+    int64_t P = 1;
+    while (P < n) P <<= 1;
+    return P;
 }
 
 int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, const void *ghat,
@@ -324,7 +360,9 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
                      uint32_t *det_mask, void *det_med, int32_t *out_pos)
 {
     const int64_t cap = o.cap;
-    hipLaunchKernelGGL(k_sort_det, dim3(p.F), dim3(kSortThreads), 0, p.stream, out.n_det, cap, out.det_idx);
+    const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
+    hipLaunchKernelGGL(k_sort_det, dim3(p.F), dim3(kSortThreads), pc * sizeof(int64_t), p.stream, out.n_det, cap,
+                       out.det_idx);
     MR1L_LAUNCH_CHECK();
     dim3 gq((unsigned)((cap + 255) / 256), (unsigned)p.F);
     hipLaunchKernelGGL(k_det_hash, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat, p.d_z32,
@@ -332,8 +370,11 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     MR1L_LAUNCH_CHECK();
     int rc = launch_fill_u32(det_mask, (int64_t)p.F * cap, 0u, p.stream);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_singleton, dim3(p.L, p.F), dim3(1024), kHistBins * sizeof(int32_t), p.stream, p.d_lat,
-                       p.L, out.n_det, cap, det_hash, det_mask);
+    int64_t maxM = 1;
+    for (int64_t m : p.M) maxM = std::max(maxM, m);
+    const int words = (int)std::min<int64_t>(kSingleWords, (maxM + 31) / 32);
+    hipLaunchKernelGGL(k_singleton, dim3(p.L, p.F), dim3(256), 2 * (size_t)words * sizeof(uint32_t), p.stream,
+                       p.d_lat, p.L, out.n_det, cap, det_hash, det_mask, words);
     MR1L_LAUNCH_CHECK();
     if (p.dtype == MR1L_C128)
         rc = combine_launch<double>(p, out.n_det, cap, det_hash, det_mask, ghat, o.postproc, out.det_coef,
@@ -343,11 +384,11 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
                                    det_med, det_w);
     if (rc) return rc;
     if (p.dtype == MR1L_C128) {
-        hipLaunchKernelGGL(k_limit<double>, dim3(p.F), dim3(kSortThreads), 0, p.stream, out.n_det, cap,
+        hipLaunchKernelGGL(k_limit<double>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap,
                            out.det_idx, (const double2 *)out.det_coef, o.theta * o.theta, o.s_cap, out.n_out,
                            out.out_idx, (double2 *)out.out_coef, out_pos);
     } else {
-        hipLaunchKernelGGL(k_limit<float>, dim3(p.F), dim3(kSortThreads), 0, p.stream, out.n_det, cap,
+        hipLaunchKernelGGL(k_limit<float>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap,
                            out.det_idx, (const float2 *)out.det_coef, (float)(o.theta * o.theta), o.s_cap,
                            out.n_out, out.out_idx, (float2 *)out.out_coef, out_pos);
     }

@@ -815,25 +815,29 @@ static int launch_any(Plan &p, int s, int cls, const int32_t *d_lats, int nl, co
                : launch_sched<float>(p, s, cls, d_lats, nl, d_md, ltab, in, out, theta, bitmap, mode, scale, by_m);
 }
 
-template <typename K> static void allow_lds_one(K k)
+template <typename K> static int allow_lds_one(K k, size_t bytes)
 {
-    (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    MR1L_HIP(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return MR1L_OK;
 }
 
-template <typename T> static void allow_lds()
+template <typename T> static int allow_lds()
 {
     constexpr int LS = sizeof(T) == 8 ? 12 : 13;
-    allow_lds_one(k_bluestein_lds<T, 128, 1024>);
-    allow_lds_one(k_bluestein_lds<T, 512, 4096>);
-    allow_lds_one(k_bluestein_lds<T, kFftThreads, lds_max_n<T>()>);
-    allow_lds_one(k_bluestein_4step<T, true, 512, LS, 4>);
-    allow_lds_one(k_bluestein_4step<T, false, 512, LS, 4>);
-    allow_lds_one(k_bluestein_4step<T, true, 512, LS + 1, 2>);
-    allow_lds_one(k_bluestein_4step<T, false, 512, LS + 1, 2>);
-    allow_lds_one(k_bluestein_4step<T, true, 1024, LS + 1, 4>);
-    allow_lds_one(k_bluestein_4step<T, false, 1024, LS + 1, 4>);
-    allow_lds_one(k_bluestein_4step<T, true, 256, LS, 2>);
-    allow_lds_one(k_bluestein_4step<T, false, 256, LS, 2>);
+    constexpr size_t e = sizeof(T);
+    int rc = MR1L_OK;
+    if (!rc) rc = allow_lds_one(k_bluestein_lds<T, 128, 1024>, 2 * e * 1024);
+    if (!rc) rc = allow_lds_one(k_bluestein_lds<T, 512, 4096>, 2 * e * 4096);
+    if (!rc) rc = allow_lds_one(k_bluestein_lds<T, kFftThreads, lds_max_n<T>()>, 2 * e * lds_max_n<T>());
+    if (!rc) rc = allow_lds_one(k_bluestein_4step<T, true, 512, LS, 4>, lds_4step<T, LS, true>());
+    if (!rc) rc = allow_lds_one(k_bluestein_4step<T, false, 512, LS, 4>, lds_4step<T, LS, false>());
+    if (!rc) rc = allow_lds_one(k_bluestein_4step<T, true, 512, LS + 1, 2>, lds_4step<T, LS + 1, true>());
+    if (!rc) rc = allow_lds_one(k_bluestein_4step<T, false, 512, LS + 1, 2>, lds_4step<T, LS + 1, false>());
+    if (!rc) rc = allow_lds_one(k_bluestein_4step<T, true, 1024, LS + 1, 4>, lds_4step<T, LS + 1, true>());
+    if (!rc) rc = allow_lds_one(k_bluestein_4step<T, false, 1024, LS + 1, 4>, lds_4step<T, LS + 1, false>());
+    if (!rc) rc = allow_lds_one(k_bluestein_4step<T, true, 256, LS, 2>, lds_4step<T, LS, true>());
+    if (!rc) rc = allow_lds_one(k_bluestein_4step<T, false, 256, LS, 2>, lds_4step<T, LS, false>());
+    return rc;
 }
 
 int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap, int mode, double scale)
@@ -853,10 +857,10 @@ int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap, 
     return MR1L_OK;
 }
 
-void fft_init_attrs()
+int fft_init_attrs()
 {
-    allow_lds<double>();
-    allow_lds<float>();
+    const int rc = allow_lds<double>();
+    return rc ? rc : allow_lds<float>();
 }
 
 // Table entry of size `mid` for the layout of schedule s.

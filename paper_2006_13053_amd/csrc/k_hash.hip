@@ -278,18 +278,19 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
         }                                                               \
         break;
 
-void vote_init_attrs()
+int vote_init_attrs()
 {
 #define MR1L_VOTE_ATTR(Dv)                                                                        \
-    (void)hipFuncSetAttribute((const void *)k_vote<Dv, true, kVoteCPT, true>,                          \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsWords * 4);          \
-    (void)hipFuncSetAttribute((const void *)k_vote<Dv, true, kVoteCPT, false>,                         \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsWords * 4);
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_vote<Dv, true, kVoteCPT, true>,                       \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsWords * 4));      \
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_vote<Dv, true, kVoteCPT, false>,                      \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsWords * 4));
     MR1L_VOTE_ATTR(0) MR1L_VOTE_ATTR(1) MR1L_VOTE_ATTR(2) MR1L_VOTE_ATTR(3) MR1L_VOTE_ATTR(4)
     MR1L_VOTE_ATTR(5) MR1L_VOTE_ATTR(6) MR1L_VOTE_ATTR(7) MR1L_VOTE_ATTR(8) MR1L_VOTE_ATTR(9)
     MR1L_VOTE_ATTR(10) MR1L_VOTE_ATTR(12) MR1L_VOTE_ATTR(16) MR1L_VOTE_ATTR(20) MR1L_VOTE_ATTR(25)
     MR1L_VOTE_ATTR(30)
 #undef MR1L_VOTE_ATTR
+    return MR1L_OK;
 }
 
 int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,

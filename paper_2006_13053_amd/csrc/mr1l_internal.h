@@ -63,7 +63,7 @@ struct FftSched {
 };
 constexpr int kNumSched = 9;
 extern const FftSched kSched[kNumSched];
-constexpr int kDefaultFourStep = 1;
+constexpr int kDefaultFourStep = 2;
 
 // Lattices launched together: schedule, LDS size class (schedule 0), whether the
 // four-step tables fit the LDS, and the lattice list (host and device).
@@ -222,9 +222,9 @@ int tuned_schedule(int32_t dtype, int64_t M);
 MDesc fft_layout(const Plan &p, int mid, int s);   // table entry of size mid under schedule s
 int fft_time_group(Plan &p, int sched, int cls, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
                    const void *in, void *out, int reps, float *ms);
-void fft_init_attrs();
-void extract_init_attrs();
-void vote_init_attrs();
+int fft_init_attrs();
+int extract_init_attrs();
+int vote_init_attrs();
 
 int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
              const uint32_t *bitmap, int32_t vote_min, int64_t cap, int64_t *n_det,
