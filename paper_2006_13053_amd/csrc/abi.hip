@@ -236,7 +236,7 @@ static int build_tables(Plan &p)
 static int build_vote_records(Plan &p, std::vector<uint32_t> &vr)
 {
     const int zw = p.dot2 ? (p.d + 1) / 2 : p.d;
-    int rs = 1;
+    int rs = 4;
     while (rs < zw + 4) rs <<= 1;
     p.vrec_stride = rs;
     vr.assign((size_t)p.F * (p.L + 1) * rs, 0u);
@@ -247,15 +247,15 @@ static int build_vote_records(Plan &p, std::vector<uint32_t> &vr)
             const size_t i = (size_t)f * p.L + ls;
             const LatDesc &ld = p.lat[i];
             uint32_t *r = &vr[((size_t)f * (p.L + 1) + l) * rs];
+            r[0] = ld.off32;
+            r[1] = (uint32_t)(-(int32_t)ld.M);
+            std::memcpy(&r[2], &ld.inv_m, 4);
+            r[3] = (uint32_t)(ld.node_off - (word0 << 5));
             for (int u = 0; u < p.d; ++u) {
                 const uint32_t zu = (uint32_t)p.z[i * p.d + u];
-                if (p.dot2) r[u / 2] |= (zu & 0xffffu) << (16 * (u & 1));
-                else r[u] = zu;
+                if (p.dot2) r[4 + u / 2] |= (zu & 0xffffu) << (16 * (u & 1));
+                else r[4 + u] = zu;
             }
-            r[zw + 0] = ld.off32;
-            r[zw + 1] = (uint32_t)ld.M;
-            std::memcpy(&r[zw + 2], &ld.inv_m, 4);
-            r[zw + 3] = (uint32_t)(ld.node_off - (word0 << 5));
         }
     }
     return MR1L_OK;

@@ -56,217 +56,190 @@ __device__ __forceinline__ int func_of(const int64_t *set_off, int F, int64_t i)
 
 // ------------------------------------------------------------------ vote
 constexpr int kVoteThreads = 512;
-constexpr int kVoteCPT = 1;                   // candidates per thread
-constexpr int kVoteLdsWords = 20480;          // 80 KiB: two workgroups per CU
+constexpr int kVoteLdsWords = 20480;          // 80 KiB: lattice records + bitmap, two or more workgroups per CU
 
 // Each workgroup owns a contiguous, tile-aligned range of the concatenated
-// candidate sets; the current function's bitmap words sit in LDS (reloaded at
-// function boundaries).  Thread t of a tile handles candidates 2t and 2t + 1.
-template <int D, bool LDSB, int CPT, bool DOT2>
+// candidate sets (one candidate per thread and tile).  When they fit, the
+// current function's bitmap words sit in LDS (reloaded at function
+// boundaries).  The lattice records (offset, -M, reciprocal, bit base, z
+// words) are wave-uniform and come through the scalar cache; the record of
+// lattice l + 1 is loaded while lattice l is hashed (record L is a padding
+// copy).  Lanes without a fast-path candidate start their count far below
+// zero, which makes them count as decided in the early exit.
+template <int D, bool LDSB, bool DOT2>
 __global__ __launch_bounds__(kVoteThreads) void k_vote(
     const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int F,
-    int L, int d_rt, const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32,
-    const int64_t *__restrict__ z64, const uint32_t *__restrict__ vrec, int rs, const int32_t *__restrict__ kbound,
+    int L, int d_rt, const LatDesc *__restrict__ lat, const int64_t *__restrict__ z64,
+    const uint32_t *__restrict__ vrec, int rs, const int32_t *__restrict__ kbound,
     const uint32_t *__restrict__ bitmap, int vote_min, int64_t cap,
-    int64_t *__restrict__ det_cnt, int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes, int aligned)
+    int64_t *__restrict__ det_cnt, int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes)
 {
     const int d = D > 0 ? D : d_rt;
     constexpr int DM = D > 0 ? D : kMaxD;
-    extern __shared__ __align__(16) uint32_t bits[];
-    __shared__ int s_f;
+    constexpr int ZW = DOT2 ? (DM + 1) / 2 : DM;   // z words of a record
+    const int zw = DOT2 ? (d + 1) / 2 : d;
+    extern __shared__ __align__(16) uint32_t lds[];
+    const int recw = (L + 1) * rs;                  // rs is a multiple of 4
+    uint32_t *bits = lds;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    constexpr int TILE = kVoteThreads * CPT;
-    const int64_t ntiles = (n_total + TILE - 1) / TILE;
+    const int64_t ntiles = (n_total + kVoteThreads - 1) / kVoteThreads;
     const int64_t tper = (ntiles + gridDim.x - 1) / gridDim.x;
-    const int64_t beg = (int64_t)blockIdx.x * tper * TILE;
-    const int64_t end = min(n_total, beg + tper * TILE);
+    const int64_t beg = (int64_t)blockIdx.x * tper * kVoteThreads;
+    const int64_t end = min(n_total, beg + tper * kVoteThreads);
     const bool want_votes = votes != nullptr;
-    int cur_f = -1;
-    int64_t f_lo = 0, f_hi = 0;
-    int64_t word0 = 0;
+    // no candidate can be hopeless before lattice L - vote_min
+    const int L1 = want_votes ? L : max(0, min(L, L - vote_min));
+    int f = 0;
+    int64_t f_lo = 0, f_hi = 0, word0 = 0;
+    int32_t kb = 0;
 
-    for (int64_t t0 = beg; t0 < end; t0 += TILE) {
-        const int64_t tend = min(end, t0 + TILE);
+    for (int64_t t0 = beg; t0 < end; t0 += kVoteThreads) {
+        const int64_t tend = min(end, t0 + kVoteThreads);
         int64_t seg = t0;
         while (seg < tend) {
             if (!(seg >= f_lo && seg < f_hi)) {
-                if (tid == 0) s_f = func_of(set_off, F, seg);
-                __syncthreads();
-                cur_f = s_f;
-                __syncthreads();   // s_f is rewritten at the next function change
-                f_lo = set_off[cur_f];
-                f_hi = set_off[cur_f + 1];
-                const LatDesc l0 = lat[cur_f * L];
-                const LatDesc lL = lat[cur_f * L + L - 1];
+                // every lane searches the same offsets, so f is uniform
+                f = __builtin_amdgcn_readfirstlane(func_of(set_off, F, seg));
+                f_lo = set_off[f];
+                f_hi = set_off[f + 1];
+                kb = kbound[f];
+                const LatDesc l0 = lat[f * L];
+                const LatDesc lL = lat[f * L + L - 1];
                 word0 = l0.node_off >> 5;
+                __syncthreads();   // every wave is done with the previous function's tables
                 if (LDSB) {
                     const int64_t wN = ((lL.node_off + lL.M - 1) >> 5) - word0 + 1;
                     for (int64_t w = tid; w < wN; w += kVoteThreads) bits[w] = bitmap[word0 + w];
-                    __syncthreads();
                 }
+                __syncthreads();
             }
             if (f_hi <= seg) break;   // inconsistent offsets: stop instead of spinning
             const int64_t sEnd = min(tend, f_hi);
-            const int f = __builtin_amdgcn_readfirstlane(cur_f);
-            const int64_t c0 = t0 + CPT * tid;
-            bool val[CPT];
-            int32_t lo[CPT][DM];
-            bool fast[CPT];
-            const int32_t kb = kbound[f];
+            const int64_t c = t0 + tid;
+            const bool val = (c >= seg) && (c < sEnd);
+            const int64_t cc = val ? c : seg;   // every lane loads a valid candidate
+            // coalesced loads, one column per coordinate, all issued before the first use
+            int64_t kk[DM];
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                val[c] = (c0 + c >= seg) && (c0 + c < sEnd);
-                fast[c] = true;
-            }
-            // coalesced loads of the thread's candidates, one column per coordinate
+            for (int u = 0; u < DM; ++u)
+                if (u < d) kk[u] = __builtin_nontemporal_load(freq + (int64_t)u * n_total + cc);
+            int32_t lo[DM];
+            bool fast = true;
 #pragma unroll
             for (int u = 0; u < DM; ++u) {
                 if (u < d) {
-                    const int64_t *row = freq + (int64_t)u * n_total;
-                    int64_t k[CPT];
-                    if constexpr (CPT == 2) {
-                        if (aligned && val[0] && val[1]) {
-                            const longlong2 vv = *reinterpret_cast<const longlong2 *>(row + c0);
-                            k[0] = vv.x;
-                            k[1] = vv.y;
-                        } else {
-                            k[0] = val[0] ? row[c0] : 0;
-                            k[1] = val[1] ? row[c0 + 1] : 0;
-                        }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < CPT; ++c) k[c] = val[c] ? __builtin_nontemporal_load(row + c0 + c) : 0;
-                    }
-#pragma unroll
-                    for (int c = 0; c < CPT; ++c) {
-                        lo[c][u] = (int32_t)k[c];
-                        fast[c] = fast[c] && (k[c] >= -kb) && (k[c] <= kb);
-                    }
+                    lo[u] = (int32_t)kk[u];
+                    fast = fast & (kk[u] >= -kb) & (kk[u] <= kb);   // no short circuit: no waits between loads
                 }
             }
-            int v[CPT];
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) v[c] = 0;
-            const LatDesc *lf = lat + f * L;
-            // fast path for candidates within the 24-bit bound (all but adversarial inputs)
-            bool act[CPT], any = false;
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                act[c] = val[c] && fast[c];
-                any = any || act[c];
-            }
-            if (__any(any)) {   // wave-uniform, so the record loads stay scalar
-                // one contiguous record per lattice (wave-uniform); the next record is
-                // loaded while the current lattice is hashed (record L is a padding copy)
-                constexpr int ZW = DOT2 ? (DM + 1) / 2 : DM;
-                const int zw = DOT2 ? (d + 1) / 2 : d;
-                // constant address space: uniform loads of the read-only records go through
-                // the scalar cache
-                typedef const __attribute__((address_space(4))) uint32_t *crec_t;
-                crec_t rec = (crec_t)(uintptr_t)(vrec + (int64_t)f * (L + 1) * rs);
-                uint32_t kp[CPT][(DM + 1) / 2];
+            const bool act = val && fast;
+            int v = act ? 0 : -(1 << 20);
+            if (__any(act)) {
+                uint32_t kp[ZW];
                 if constexpr (DOT2) {
 #pragma unroll
-                    for (int c = 0; c < CPT; ++c)
-#pragma unroll
-                        for (int j = 0; j < (DM + 1) / 2; ++j) {
-                            const uint32_t a = (2 * j < d) ? ((uint32_t)lo[c][2 * j] & 0xffffu) : 0u;
-                            const uint32_t b = (2 * j + 1 < d) ? ((uint32_t)lo[c][2 * j + 1] << 16) : 0u;
-                            kp[c][j] = a | b;
-                        }
+                    for (int j = 0; j < ZW; ++j) {
+                        const uint32_t a0 = (2 * j < d) ? ((uint32_t)lo[2 * j] & 0xffffu) : 0u;
+                        const uint32_t a1 = (2 * j + 1 < d) ? ((uint32_t)lo[2 * j + 1] << 16) : 0u;
+                        kp[j] = a0 | a1;
+                    }
                 }
-                uint32_t zc[ZW + 4];
+                // uniform records through the scalar cache (constant address space)
+                typedef const __attribute__((address_space(4))) uint32_t *crec_t;
+                const crec_t rp = (crec_t)(uintptr_t)(vrec + (int64_t)f * recw);
+                constexpr int RW = 4 + ZW;
+                uint32_t ra[RW], rb[RW];
 #pragma unroll
-                for (int u = 0; u < ZW; ++u) zc[u] = (u < zw) ? rec[u] : 0u;
+                for (int j = 0; j < RW; ++j) ra[j] = (j < 4 + zw) ? rp[j] : 0u;
+                // hash lattice l with record `cur` while record l + 1 is loaded into `nxt`
+                auto step = [&](const uint32_t (&r)[RW], uint32_t (&nxt)[RW], int l) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) zc[ZW + u] = rec[zw + u];
-                for (int l = 0; l < L; ++l) {
-                    rec += rs;
-                    uint32_t zn[ZW + 4];
+                    for (int j = 0; j < RW; ++j) nxt[j] = (j < 4 + zw) ? rp[(l + 1) * rs + j] : 0u;
+                    uint32_t s = r[0];
+                    if constexpr (DOT2) {
+                        typedef short v2s __attribute__((ext_vector_type(2)));
 #pragma unroll
-                    for (int u = 0; u < ZW; ++u) zn[u] = (u < zw) ? rec[u] : 0u;
+                        for (int j = 0; j < ZW; ++j)
+                            if (j < zw)
+                                s = (uint32_t)__builtin_amdgcn_sdot2(__builtin_bit_cast(v2s, kp[j]),
+                                                                     __builtin_bit_cast(v2s, r[4 + j]), (int)s, false);
+                    } else {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) zn[ZW + u] = rec[zw + u];
-                    const uint32_t off32 = zc[ZW], Mm = zc[ZW + 1], bbase = zc[ZW + 3];
-                    const float inv_m = __uint_as_float(zc[ZW + 2]);
-#pragma unroll
-                    for (int c = 0; c < CPT; ++c) {
-                        uint32_t s = off32;
-                        if constexpr (DOT2) {
-                            typedef short v2s __attribute__((ext_vector_type(2)));
-#pragma unroll
-                            for (int j = 0; j < ZW; ++j)
-                                if (j < zw)
-                                    s = (uint32_t)__builtin_amdgcn_sdot2(__builtin_bit_cast(v2s, kp[c][j]),
-                                                                         __builtin_bit_cast(v2s, zc[j]), (int)s,
-                                                                         false);
-                        } else {
-#pragma unroll
-                            for (int u = 0; u < DM; ++u)
-                                if (u < d) s += (uint32_t)__mul24(lo[c][u], (int32_t)zc[u]);
-                        }
-                        const uint32_t g = bbase + fast_mod(s, Mm, inv_m);
-                        uint32_t word;
-                        if constexpr (LDSB) word = bits[g >> 5];
-                        else word = bitmap[word0 + (g >> 5)];
-                        // bit g mod 32 (the extract uses the low five bits of the offset)
-                        v[c] += act[c] ? (int)__builtin_amdgcn_ubfe(word, g, 1) : 0;
+                        for (int u = 0; u < DM; ++u)
+                            if (u < d) s += (uint32_t)__mul24(lo[u], (int32_t)r[4 + u]);
                     }
+                    // s < 2^32 and s / M < 2^20: the float quotient is exact or one too small
+                    const int32_t negM = (int32_t)r[1];
+                    const uint32_t q = (uint32_t)((float)s * __uint_as_float(r[2]));
+                    uint32_t h = (uint32_t)(__mul24((int32_t)q, negM) + (int32_t)s);   // in [0, 2M)
+                    h = min(h, h + (uint32_t)negM);
+                    const uint32_t g = r[3] + h;
+                    uint32_t word;
+                    if constexpr (LDSB) word = bits[g >> 5];
+                    else word = bitmap[word0 + (g >> 5)];
+                    v += (int)__builtin_amdgcn_ubfe(word, g, 1);   // bit g mod 32
+                };
+                // undecided after lattice l: vote_min - rest <= v < vote_min
+                auto decided = [&](int l) {
+                    const int rest = L - 1 - l;
+                    return __all((uint32_t)(v - vote_min + rest) >= (uint32_t)rest);
+                };
+                // two lattices per iteration, so the record buffers alternate without copies
+                int l = 0;
+                for (; l + 1 < L1; l += 2) {
+                    step(ra, rb, l);
+                    step(rb, ra, l + 1);
+                }
+                if (l < L1) {
+                    step(ra, rb, l);
 #pragma unroll
-                    for (int u = 0; u < ZW + 4; ++u) zc[u] = zn[u];
-                    if (!want_votes && l >= L - vote_min) {
-                        // leave once every candidate of the wave has reached vote_min or can no longer
-                        // (no candidate can be hopeless before lattice L - vote_min)
-                        const int rest = L - 1 - l;
-                        bool decided = true;
-#pragma unroll
-                        for (int c = 0; c < CPT; ++c)
-                            decided = decided && (!act[c] || v[c] >= vote_min || v[c] + rest < vote_min);
-                        if (__all(decided)) break;
-                    }
+                    for (int j = 0; j < RW; ++j) ra[j] = rb[j];
+                    ++l;
+                }
+                while (l < L) {
+                    step(ra, rb, l);
+                    if (decided(l) || ++l == L) break;
+                    step(rb, ra, l);
+                    if (decided(l)) break;
+                    ++l;
                 }
             }
             // exact 64-bit path for candidates beyond the bound (rare, divergent)
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                if (val[c] && !fast[c]) {
-                    for (int l = 0; l < L; ++l) {
-                        const LatDesc ld = lf[l];
-                        const int32_t h = exact_bucket(freq + c0 + c, n_total, d, z64 + ld.z_off, ld.M);
-                        const int64_t g = ld.node_off + h;
-                        uint32_t word;
-                        if constexpr (LDSB) word = bits[(g >> 5) - word0];
-                        else word = bitmap[g >> 5];
-                        v[c] += (word >> (g & 31)) & 1u;
-                    }
+            if (val && !fast) {
+                v = 0;
+                const LatDesc *lf = lat + f * L;
+                for (int l = 0; l < L; ++l) {
+                    const LatDesc ld = lf[l];
+                    const int32_t h = exact_bucket(freq + c, n_total, d, z64 + ld.z_off, ld.M);
+                    const int64_t g = ld.node_off + h;
+                    uint32_t word;
+                    if constexpr (LDSB) word = bits[(g >> 5) - word0];
+                    else word = bitmap[g >> 5];
+                    v += (word >> (g & 31)) & 1u;
                 }
             }
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                if (want_votes && val[c]) votes[c0 + c] = (uint8_t)v[c];
-                const bool det = val[c] && v[c] >= vote_min;
-                const uint64_t bal = __ballot(det);
-                if (bal) {
-                    const int cnt = __popcll(bal);
-                    const int first = __ffsll((unsigned long long)bal) - 1;
-                    const int rank = __popcll(bal & ((1ull << lane) - 1ull));
-                    unsigned long long base = 0;
-                    if (lane == first)
-                        base = atomicAdd((unsigned long long *)(det_cnt + f), (unsigned long long)cnt);
-                    base = __shfl(base, first);
-                    if (det && (int64_t)(base + rank) < cap) det_idx[f * cap + base + rank] = c0 + c - f_lo;
-                }
+            if (want_votes && val) votes[c] = (uint8_t)max(v, 0);
+            const bool det = val && v >= vote_min;
+            const uint64_t bal = __ballot(det);
+            if (bal) {
+                const int cnt = __popcll(bal);
+                const int first = __ffsll((unsigned long long)bal) - 1;
+                const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+                unsigned long long base = 0;
+                if (lane == first) base = atomicAdd((unsigned long long *)(det_cnt + f), (unsigned long long)cnt);
+                base = __shfl(base, first);
+                if (det && (int64_t)(base + rank) < cap) det_idx[f * cap + base + rank] = c - f_lo;
             }
             seg = sEnd;
         }
     }
 }
 
-#define MR1L_VOTE_LAUNCH(Dv, LD, D2)                                                                 \
-    hipLaunchKernelGGL((k_vote<Dv, LD, kVoteCPT, D2>), grid, blk, LD ? shm : 0, p.stream, freq, n_total,  \
-                       set_off, p.F, p.L, p.d, p.d_lat, p.d_z32, p.d_z64, p.d_vrec, p.vrec_stride, p.d_kb, bitmap,         \
-                       vote_min, cap, n_det, det_idx, votes, aligned)
+#define MR1L_VOTE_LAUNCH(Dv, LD, D2)                                                                       \
+    hipLaunchKernelGGL((k_vote<Dv, LD, D2>), grid, blk, shm, p.stream, freq, n_total, set_off, p.F, p.L, p.d, \
+                       p.d_lat, p.d_z64, p.d_vrec, p.vrec_stride, p.d_kb, bitmap, vote_min, cap, n_det,             \
+                       det_idx, votes)
 #define MR1L_VOTE_DISPATCH(Dv)                                          \
     case Dv:                                                            \
         if (lds) {                                                      \
@@ -280,10 +253,10 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
 
 int vote_init_attrs()
 {
-#define MR1L_VOTE_ATTR(Dv)                                                                        \
-    MR1L_HIP(hipFuncSetAttribute((const void *)k_vote<Dv, true, kVoteCPT, true>,                       \
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsWords * 4));      \
-    MR1L_HIP(hipFuncSetAttribute((const void *)k_vote<Dv, true, kVoteCPT, false>,                      \
+#define MR1L_VOTE_ATTR(Dv)                                                                              \
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_vote<Dv, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                 kVoteLdsWords * 4));                                                    \
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_vote<Dv, true, false>,                                  \
                                  hipFuncAttributeMaxDynamicSharedMemorySize, kVoteLdsWords * 4));
     MR1L_VOTE_ATTR(0) MR1L_VOTE_ATTR(1) MR1L_VOTE_ATTR(2) MR1L_VOTE_ATTR(3) MR1L_VOTE_ATTR(4)
     MR1L_VOTE_ATTR(5) MR1L_VOTE_ATTR(6) MR1L_VOTE_ATTR(7) MR1L_VOTE_ATTR(8) MR1L_VOTE_ATTR(9)
@@ -307,11 +280,10 @@ int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *fr
     }
     const bool lds = maxw <= kVoteLdsWords;
     const size_t shm = lds ? (size_t)maxw * 4 : 0;
-    const int aligned = ((reinterpret_cast<uintptr_t>(freq) & 15) == 0 && (n_total & 1) == 0) ? 1 : 0;
-    const int64_t tiles = (n_total + kVoteThreads * kVoteCPT - 1) / (kVoteThreads * kVoteCPT);
+    const int64_t tiles = (n_total + kVoteThreads - 1) / kVoteThreads;
     // one co-resident workgroup per slot: no partial second round of workgroups
     int per_cu = 0;
-    const void *kfn = lds ? (const void *)k_vote<10, true, kVoteCPT, true> : (const void *)k_vote<10, false, kVoteCPT, true>;
+    const void *kfn = lds ? (const void *)k_vote<10, true, true> : (const void *)k_vote<10, false, true>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kVoteThreads, shm) != hipSuccess || per_cu < 1)
         per_cu = 1;
     const int64_t gridn = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)num_cus() * per_cu));
