@@ -70,7 +70,7 @@ template <int D, bool LDSB, bool DOT2>
 __global__ __launch_bounds__(kVoteThreads) void k_vote(
     const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int F,
     int L, int d_rt, const LatDesc *__restrict__ lat, const int64_t *__restrict__ z64,
-    const uint32_t *__restrict__ vrec, int rs, const int32_t *__restrict__ kbound,
+    const uint32_t *__restrict__ vrec, int rs, int32_t kb_min,
     const uint32_t *__restrict__ bitmap, int vote_min, int64_t cap,
     int64_t *__restrict__ det_cnt, int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes)
 {
@@ -92,9 +92,38 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
     const int L1 = want_votes ? L : max(0, min(L, L - vote_min));
     int f = 0;
     int64_t f_lo = 0, f_hi = 0, word0 = 0;
-    int32_t kb = 0;
 
+    // the coordinates of the next tile are loaded while the current one is hashed
+    int64_t kn[DM];
+    auto load_tile = [&](int64_t t) {
+        const int64_t ci = min(t + tid, n_total - 1);
+#pragma unroll
+        for (int u = 0; u < DM; ++u)
+            if (u < d) kn[u] = __builtin_nontemporal_load(freq + (int64_t)u * n_total + ci);
+    };
+    if (beg < end) load_tile(beg);
     for (int64_t t0 = beg; t0 < end; t0 += kVoteThreads) {
+        // this tile's candidate: within the fast bound of every function of the batch
+        // (kb_min; beyond it the exact path decides), low words, packed pairs
+        int32_t lo[DM];
+        bool fast = true;
+#pragma unroll
+        for (int u = 0; u < DM; ++u) {
+            if (u < d) {
+                lo[u] = (int32_t)kn[u];
+                fast = fast & (kn[u] >= -kb_min) & (kn[u] <= kb_min);   // no short circuit
+            }
+        }
+        uint32_t kp[ZW];
+        if constexpr (DOT2) {
+#pragma unroll
+            for (int j = 0; j < ZW; ++j) {
+                const uint32_t a0 = (2 * j < d) ? ((uint32_t)lo[2 * j] & 0xffffu) : 0u;
+                const uint32_t a1 = (2 * j + 1 < d) ? ((uint32_t)lo[2 * j + 1] << 16) : 0u;
+                kp[j] = a0 | a1;
+            }
+        }
+        if (t0 + kVoteThreads < end) load_tile(t0 + kVoteThreads);
         const int64_t tend = min(end, t0 + kVoteThreads);
         int64_t seg = t0;
         while (seg < tend) {
@@ -103,7 +132,6 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
                 f = __builtin_amdgcn_readfirstlane(func_of(set_off, F, seg));
                 f_lo = set_off[f];
                 f_hi = set_off[f + 1];
-                kb = kbound[f];
                 const LatDesc l0 = lat[f * L];
                 const LatDesc lL = lat[f * L + L - 1];
                 word0 = l0.node_off >> 5;
@@ -118,33 +146,9 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
             const int64_t sEnd = min(tend, f_hi);
             const int64_t c = t0 + tid;
             const bool val = (c >= seg) && (c < sEnd);
-            const int64_t cc = val ? c : seg;   // every lane loads a valid candidate
-            // coalesced loads, one column per coordinate, all issued before the first use
-            int64_t kk[DM];
-#pragma unroll
-            for (int u = 0; u < DM; ++u)
-                if (u < d) kk[u] = __builtin_nontemporal_load(freq + (int64_t)u * n_total + cc);
-            int32_t lo[DM];
-            bool fast = true;
-#pragma unroll
-            for (int u = 0; u < DM; ++u) {
-                if (u < d) {
-                    lo[u] = (int32_t)kk[u];
-                    fast = fast & (kk[u] >= -kb) & (kk[u] <= kb);   // no short circuit: no waits between loads
-                }
-            }
             const bool act = val && fast;
             int v = act ? 0 : -(1 << 20);
             if (__any(act)) {
-                uint32_t kp[ZW];
-                if constexpr (DOT2) {
-#pragma unroll
-                    for (int j = 0; j < ZW; ++j) {
-                        const uint32_t a0 = (2 * j < d) ? ((uint32_t)lo[2 * j] & 0xffffu) : 0u;
-                        const uint32_t a1 = (2 * j + 1 < d) ? ((uint32_t)lo[2 * j + 1] << 16) : 0u;
-                        kp[j] = a0 | a1;
-                    }
-                }
                 // uniform records through the scalar cache (constant address space)
                 typedef const __attribute__((address_space(4))) uint32_t *crec_t;
                 const crec_t rp = (crec_t)(uintptr_t)(vrec + (int64_t)f * recw);
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
 
 #define MR1L_VOTE_LAUNCH(Dv, LD, D2)                                                                       \
     hipLaunchKernelGGL((k_vote<Dv, LD, D2>), grid, blk, shm, p.stream, freq, n_total, set_off, p.F, p.L, p.d, \
-                       p.d_lat, p.d_z64, p.d_vrec, p.vrec_stride, p.d_kb, bitmap, vote_min, cap, n_det,             \
+                       p.d_lat, p.d_z64, p.d_vrec, p.vrec_stride, kb_min, bitmap, vote_min, cap, n_det,             \
                        det_idx, votes)
 #define MR1L_VOTE_DISPATCH(Dv)                                          \
     case Dv:                                                            \
@@ -280,6 +284,8 @@ int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *fr
     }
     const bool lds = maxw <= kVoteLdsWords;
     const size_t shm = lds ? (size_t)maxw * 4 : 0;
+    int32_t kb_min = INT32_MAX;
+    for (int32_t k : p.kb) kb_min = std::min(kb_min, k);
     const int64_t tiles = (n_total + kVoteThreads - 1) / kVoteThreads;
     // one co-resident workgroup per slot: no partial second round of workgroups
     int per_cu = 0;
