@@ -63,6 +63,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__rest
 }
 
 // ------------------------------------------------------------------ hashes of detected
+// One thread per (detected candidate, lattice): the L threads of a candidate read
+// the same coordinates (cache hits after the first) and write adjacent buckets.
 __global__ __launch_bounds__(256) void k_det_hash(
     const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int L, int d,
     const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32, const int64_t *__restrict__ z64,
@@ -70,29 +72,23 @@ __global__ __launch_bounds__(256) void k_det_hash(
     const int64_t *__restrict__ det_idx, int32_t *__restrict__ det_hash)
 {
     const int f = blockIdx.y;
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t q = t / L;
+    const int l = (int)(t - q * L);
     if (q >= n_of(n_det, f, cap)) return;
     const int64_t ci = set_off[f] + det_idx[(int64_t)f * cap + q];
     const int32_t kb = kbound[f];
-    int32_t lo[kMaxD];
+    const LatDesc ld = lat[f * L + l];
+    uint32_t s = ld.off32;
     bool fast = true;
     for (int u = 0; u < d; ++u) {
         const int64_t k = freq[(int64_t)u * n_total + ci];
-        lo[u] = (int32_t)k;
-        fast = fast && (k >= -kb) && (k <= kb);
+        fast = fast & (k >= -kb) & (k <= kb);
+        s += (uint32_t)__mul24((int32_t)k, z32[ld.z_off + u]);
     }
-    for (int l = 0; l < L; ++l) {
-        const LatDesc ld = lat[f * L + l];
-        int32_t h;
-        if (fast) {
-            uint32_t s = ld.off32;
-            for (int u = 0; u < d; ++u) s += (uint32_t)__mul24(lo[u], z32[ld.z_off + u]);
-            h = (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m);
-        } else {
-            h = exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
-        }
-        det_hash[((int64_t)f * cap + q) * L + l] = h;
-    }
+    const int32_t h = fast ? (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m)
+                           : exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
+    det_hash[((int64_t)f * cap + q) * L + l] = h;
 }
 
 // ------------------------------------------------------------------ singletons
@@ -143,7 +139,9 @@ __global__ __launch_bounds__(256) void k_singleton(const LatDesc *__restrict__ l
 }
 
 // ------------------------------------------------------------------ combine
-// Median position(s) by rank: rank_l = #{m : (v_m, m) < (v_l, l)}.
+// Median position(s) by rank: rank_l = #{m : (v_m, m) < (v_l, l)}.  Entries
+// L..LMAX-1 hold +infinity, which never ranks below a lattice value, so the
+// counting needs no bounds tests.
 template <typename T, int LMAX>
 __device__ __forceinline__ void median_sel(const T *v, int L, T &med, int &s0, int &s1)
 {
@@ -151,11 +149,13 @@ __device__ __forceinline__ void median_sel(const T *v, int L, T &med, int &s0, i
     s0 = 0; s1 = 0;
 #pragma unroll
     for (int l = 0; l < LMAX; ++l) {
-        if (l < L) {
-            int rank = 0;
+        int rank = 0;
 #pragma unroll
-            for (int m = 0; m < LMAX; ++m)
-                if (m < L) rank += (v[m] < v[l]) || (v[m] == v[l] && m < l);
+        for (int m = 0; m < LMAX; ++m) {
+            if (m < l) rank += v[m] <= v[l];
+            else if (m > l) rank += v[m] < v[l];
+        }
+        if (l < L) {
             if (rank == want0) s0 = l;
             if (rank == want1) s1 = l;
         }
@@ -183,9 +183,10 @@ __global__ __launch_bounds__(256) void k_combine(
     if (q >= n_of(n_det, f, cap)) return;
     const int64_t e = (int64_t)f * cap + q;
     T vr[LMAX], vi[LMAX];
+    const T inf = __builtin_inf();
 #pragma unroll
     for (int l = 0; l < LMAX; ++l) {
-        vr[l] = 0; vi[l] = 0;
+        vr[l] = inf; vi[l] = inf;
         if (l < L) {
             const V g = ghat[lat[f * L + l].node_off + det_hash[e * L + l]];
             vr[l] = g.x; vi[l] = g.y;
@@ -329,7 +330,10 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, const int3
     hipLaunchKernelGGL((k_combine<T, LM>), grid, blk, 0, p.stream, p.d_lat, p.L, n_det, cap, det_hash, mask, \
                        (const V *)ghat, postproc, (V *)det_coef, (V *)det_med, det_w)
     if (p.L <= 8) MR1L_COMB(8);
+    else if (p.L <= 12) MR1L_COMB(12);
     else if (p.L <= 16) MR1L_COMB(16);
+    else if (p.L <= 20) MR1L_COMB(20);
+    else if (p.L <= 24) MR1L_COMB(24);
     else MR1L_COMB(32);
 #undef MR1L_COMB
     MR1L_LAUNCH_CHECK();
@@ -364,7 +368,7 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     hipLaunchKernelGGL(k_sort_det, dim3(p.F), dim3(kSortThreads), pc * sizeof(int64_t), p.stream, out.n_det, cap,
                        out.det_idx);
     MR1L_LAUNCH_CHECK();
-    dim3 gq((unsigned)((cap + 255) / 256), (unsigned)p.F);
+    dim3 gq((unsigned)((cap * p.L + 255) / 256), (unsigned)p.F);
     hipLaunchKernelGGL(k_det_hash, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat, p.d_z32,
                        p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
     MR1L_LAUNCH_CHECK();
