@@ -168,6 +168,37 @@ def plain_pass(m, torch, w, reps=2):
     return best, bufs
 
 
+# ----------------------------------------------------------------------------- autograd
+def autograd_timing(m, torch, w, reps=10):
+    """Coefficients of Algorithm 4 as a differentiable function of the samples
+    (LatticeCoefficients): forward alone (which also records the adjoint weights) vs
+    forward + backward (the adjoint scatter and the inverse lattice DFTs) over the batch."""
+    plan, f0, gam, so = w["plan"], w["f"], w["gam"], w["set_off"]
+    f = f0.clone().requires_grad_(True)
+    gen = torch.Generator(device=f.device).manual_seed(5)
+    wv = torch.randn((w["F"], w["s_cap"]), dtype=f.dtype, device=f.device, generator=gen)
+
+    def fwd():
+        return m.LatticeCoefficients.apply(f, plan, gam, w["theta"], w["s_cap"], w["cap"], True, so)[0]
+
+    def fwd_bwd():
+        out = fwd()
+        torch.real(torch.sum(torch.conj(wv) * out)).backward()
+        f.grad = None
+    res = {}
+    for name, fn in (("forward_ms", lambda: fwd()), ("forward_backward_ms", fwd_bwd)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = 1000.0 * (time.perf_counter() - t0) / reps
+    res["backward_over_forward"] = res["forward_backward_ms"] / res["forward_ms"] - 1.0
+    log(f"autograd: forward {res['forward_ms']:.3f} ms, forward+backward {res['forward_backward_ms']:.3f} ms")
+    return res
+
+
 # ----------------------------------------------------------------------------- dimincr
 def bench_dimincr(m, torch, args):
     """Algorithm 3 Step 2 driver on the dimension-incremental workload: d = 25, s = 200
@@ -402,6 +433,8 @@ def main():
         log(f"plain per-function loop: {1000 * t_plain:.3f} ms")
         out["functions_per_s_plain"] = F / t_plain
         out["plain_ms_per_pass"] = 1000.0 * t_plain
+    if args.workload == "batch":
+        out["autograd"] = autograd_timing(m, torch, w)
     if not args.no_cpu and args.workload == "large":
         n_sample = min(1_000_000, w["n"])
         log("oracle leg (CPU) ...")

@@ -321,7 +321,7 @@ def compare_pass(r, ro, go, theta, tol, s_cap, eps=EPS[torch.complex128]):
     assert np.array_equal(r["det_idx"][r["out_pos"]], r["out_idx"])
 
 
-@pytest.mark.parametrize("seed", list(range(10)))
+@pytest.mark.parametrize("seed", list(range(100)))
 def test_small_config_full_pass(m, seed):
     """d = 5, 2000 candidates, s = 20, L = 5, noise-free complex128 (the small plain case)."""
     say("small full pass seed", seed)
@@ -346,10 +346,11 @@ def test_small_config_complex64(m, postproc):
     compare_pass(r, ro, go, p.theta, 1e-5, 40, eps=EPS[torch.complex64])
 
 
-def test_mid_config_full_pass_with_noise(m):
+@pytest.mark.parametrize("seed", list(range(20)))
+def test_mid_config_full_pass_with_noise(m, seed):
     """d = 10, 1e5 candidates in [-64,64]^10, s = 100, L = 10, 40 dB noise, theta = 1/3."""
-    say("mid full pass")
-    p = synth.mid_config(0)
+    say("mid full pass seed", seed)
+    p = synth.mid_config(seed)
     fo = oracle.sample(p.supp, p.coef, p.M, p.z)
     f = fo + synth.noise_for(fo, p.M, 40.0, p.meta["noise_seed"])
     r, *_ = gpu_pass(m, p, f_np=f, s_cap=200, cap=4096)
@@ -512,6 +513,59 @@ def test_batched_plan_equals_plain_calls(m):
         go = oracle.dft(oracle.sample(q.supp, q.coef, q.M, q.z), q.M)
         ro = oracle.extract(q.cand, q.M, q.z, go, 1e-12, s_cap=512, cap=2048)
         assert np.array_equal(r["out_idx"], ro["out_idx"])
+
+
+def test_batched_autograd_finite_differences_and_dot_product(m):
+    """Backward of the batched coefficient map (8 functions of the batched workload,
+    reduced |Gamma|, 40 dB noise, theta = 0.05): central differences with h = 1e-6 on 16
+    sample coordinates per function, and the dot-product identity over all samples."""
+    say("batched autograd")
+    probs = synth.batch_config(3, nfunc=8, scale=0.004, shi=200)
+    d = probs[0].d
+    F = len(probs)
+    Ms = np.concatenate([q.M for q in probs])
+    zs = np.concatenate([q.z for q in probs])
+    plan = m.Plan(d, Ms, zs, F=F)
+    soff = T(np.concatenate([[0], np.cumsum([q.n for q in probs])]).astype(np.int64))
+    cand = T(np.concatenate([q.cand for q in probs], axis=1))
+    parts = []
+    for i, q in enumerate(probs):
+        fo = oracle.sample(q.supp, q.coef, q.M, q.z)
+        parts.append(fo + synth.noise_for(fo, q.M, 40.0, 100 + i))
+    f0 = np.concatenate(parts)
+    theta, s_cap, cap = 0.05, 256, 1024
+    f = T(f0).requires_grad_(True)
+    out, n_out, idx = m.LatticeCoefficients.apply(f, plan, cand, theta, s_cap, cap, True, soff)
+    rng = np.random.default_rng(4)
+    wv = T(rng.standard_normal((F, s_cap)) + 1j * rng.standard_normal((F, s_cap)))
+    loss = torch.real(torch.sum(torch.conj(wv) * out))
+    loss.backward()
+    g = f.grad.cpu().numpy()
+
+    def coefs(ff):
+        o, _, ii = m.LatticeCoefficients.apply(T(ff), plan, cand, theta, s_cap, cap, True, soff)
+        assert torch.equal(ii, idx)
+        return o
+
+    def L_of(ff):
+        return float(torch.real(torch.sum(torch.conj(wv) * coefs(ff))).item())
+    h = 1e-6
+    node_off = np.concatenate([[0], np.cumsum([q.M.sum() for q in probs])])
+    for fi in range(F):
+        for j in rng.integers(node_off[fi], node_off[fi + 1], 16):
+            for unit in (1.0, 1j):
+                e = np.zeros_like(f0)
+                e[j] = unit
+                fd = (L_of(f0 + h * e) - L_of(f0 - h * e)) / (2 * h)
+                an = g[j].real if unit == 1.0 else g[j].imag
+                assert fd == pytest.approx(an, rel=1e-5, abs=1e-8), (fi, int(j), unit)
+    # dot-product identity over every sample of the batch
+    x = rng.standard_normal(f0.shape[0]) + 1j * rng.standard_normal(f0.shape[0])
+    eps = 1e-4
+    lin = (coefs(f0 + eps * x) - coefs(f0 - eps * x)) / (2 * eps)
+    lhs = float(torch.real(torch.sum(torch.conj(wv) * lin)).item())
+    rhs = float(np.real(np.vdot(g, x)))
+    assert abs(lhs - rhs) <= 1e-7 * max(1.0, abs(rhs))
 
 
 def test_graph_replay_matches_eager(m):
