@@ -54,18 +54,26 @@ def vote_source_hash() -> str:
 
 
 # ----------------------------------------------------------------------------- large
-def setup_large(m, torch, F, n, seed=2026):
+def setup_large(m, torch, F, n, seed=2026, distinct_m=False):
+    import synth
     import synth.counter as sc
     d, L, M, box = 10, 20, 16001, 512
     dev = torch.device("cuda", 0)
     rng = np.random.default_rng(seed)
-    Ms = np.full(F * L, M, np.int64)
-    zs = rng.integers(0, M, size=(F, L, d), dtype=np.int64)
-    nodes_f = L * M
+    if distinct_m:   # 20 distinct primes uniform in [15500, 16500] per function
+        pr = synth.primes_in(15500, 16500)
+        Ms = np.concatenate([rng.choice(pr, size=L, replace=False) for _ in range(F)]).astype(np.int64)
+        zs = np.stack([np.stack([rng.integers(0, Ms[f * L + l], size=d, dtype=np.int64) for l in range(L)])
+                       for f in range(F)])
+    else:            # one size for every lattice: the smallest prime above 16000
+        Ms = np.full(F * L, M, np.int64)
+        zs = rng.integers(0, M, size=(F, L, d), dtype=np.int64)
+    node_off = np.concatenate([[0], np.cumsum(Ms.reshape(F, L).sum(axis=1))]).astype(np.int64)
+    nodes_f = int(node_off[1])
     t0 = time.time()
     gam = torch.empty((d, F * n), dtype=torch.int64, device=dev)      # batched SoA
     per = []                                                           # per-function SoA
-    f_all = torch.empty(F * nodes_f, dtype=torch.complex128, device=dev)
+    f_all = torch.empty(int(node_off[-1]), dtype=torch.complex128, device=dev)
     table = sc.phase_table(dev)
     plans = []
     for f in range(F):
@@ -76,7 +84,7 @@ def setup_large(m, torch, F, n, seed=2026):
         dom = torch.from_numpy(sc.dominant_indices(seed, f, n, 1000)).to(dev)
         c[dom] = 10.0 * torch.from_numpy(sc.dominant_phases(seed, f, 1000)).to(dev)
         pf = m.Plan(d, Ms[f * L:(f + 1) * L], zs[f])
-        m.mr1l_sample(pf, g, c, f=f_all[f * nodes_f:(f + 1) * nodes_f], mode=2)
+        m.mr1l_sample(pf, g, c, f=f_all[node_off[f]:node_off[f + 1]], mode=2)
         plans.append(pf)
         del c
         if f % 8 == 7:
@@ -86,7 +94,7 @@ def setup_large(m, torch, F, n, seed=2026):
     log(f"generated {F} functions x {n} candidates and their samples in {time.time() - t0:.1f}s")
     plan = m.Plan(d, Ms, zs.reshape(-1), F=F)
     set_off = torch.arange(0, (F + 1) * n, n, dtype=torch.int64, device=dev)
-    return dict(d=d, L=L, M=M, F=F, n=n, gam=gam, per=per, f=f_all, plan=plan, plans=plans,
+    return dict(d=d, L=L, M=M, Ms=Ms.reshape(F, L), F=F, n=n, gam=gam, per=per, f=f_all, plan=plan, plans=plans,
                 set_off=set_off, theta=1.0, zs=zs, seed=seed, box=box, nodes_f=nodes_f,
                 cap=4096, s_cap=2048)
 
@@ -257,11 +265,12 @@ def cpu_baseline_large(w, n_sample, budget_s=10.0):
     import oracle
     import synth.counter as sc
     import torch
-    d, L, M, n, seed = w["d"], w["L"], w["M"], w["n"], w["seed"]
-    Ms = np.full(L, M, np.int64)
+    d, L, n, seed = w["d"], w["L"], w["n"], w["seed"]
+    Ms = np.ascontiguousarray(w["Ms"][0])
     z = w["zs"][0]
     rng = np.random.default_rng(7)
-    fs = rng.standard_normal(L * M) + 1j * rng.standard_normal(L * M)
+    nf = int(Ms.sum())
+    fs = rng.standard_normal(nf) + 1j * rng.standard_normal(nf)
     # the oracle's own coefficients of function 0 (eq. (2.4): bucket sums of the polynomial)
     cand = sc.candidates(seed, 0, d, n, w["box"], device="cpu")
     coef = sc.compressible_coefs(seed, 0, cand, sc.phase_table("cpu"))
@@ -283,6 +292,7 @@ def cpu_baseline_large(w, n_sample, budget_s=10.0):
     sub = np.ascontiguousarray(cand_np[:, :n_sample])
     ro_sub = oracle.extract(sub, Ms, z, g_exact, w["theta"], s_cap=w["s_cap"], cap=w["cap"])
     return dict(value=value, unit="candidates\u00b7lattices/s", cores=oracle.num_threads(), kind="oracle",
+                dft_s_per_rep=t_dft / reps, extract_s_per_rep=t_ex / reps,
                 sample=(f"function 0 of the batch, {reps} repetitions: direct O(M^2) DFTs of its {L} lattices "
                         f"({t_dft / reps:.2f}s each) + Algorithm 2/Remark 2.9/Algorithm 4 over all {n} "
                         f"candidates ({t_ex / reps:.2f}s each)")), ro_sub, g_exact
@@ -313,6 +323,8 @@ def main():
     ap.add_argument("--functions", type=int, default=None)
     ap.add_argument("--candidates", type=int, default=10_000_000)
     ap.add_argument("--c64", action="store_true")
+    ap.add_argument("--distinct-m", action="store_true",
+                    help="large workload with 20 distinct primes in [15500, 16500] per function instead of M = 16001")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-function loop")
     ap.add_argument("--graph", action="store_true", help="time a captured HIP graph of the step")
@@ -339,11 +351,12 @@ def main():
 
     if args.workload == "large":
         F = args.functions or 64
-        w = setup_large(m, torch, F, args.candidates)
+        w = setup_large(m, torch, F, args.candidates, distinct_m=args.distinct_m)
+        msz = "20 distinct primes in [15500,16500] per function" if args.distinct_m else "M=16001"
         cfg = dict(workload="large compressible: d=10, |I|=1e7 per function in [-512,512]^10, "
                             "c_k=(1+|k|_1)^-2 x unit phase + 1000 dominants of modulus 10, L=20, "
-                            "M=16001, complex128, theta=1", functions=F, candidates_per_function=args.candidates,
-                   lattices=20, M=16001, d=10)
+                            f"{msz}, complex128, theta=1", functions=F, candidates_per_function=args.candidates,
+                   lattices=20, M="15500..16500" if args.distinct_m else 16001, d=10)
         dtype = "c128"
     else:
         F = args.functions or 512
@@ -355,9 +368,10 @@ def main():
 
     plan = w["plan"]
     tune = None
-    if not args.no_tune and len(np.unique(plan.M)) <= 64:
+    if not args.no_tune:
         tune = plan.fft_tune(reps=3)
-        log("DFT schedules (ms per batched DFT): " + json.dumps(tune))
+        log("DFT schedules (ms per batched DFT of each size's group): "
+            + json.dumps({k: tune[k] for k in list(tune)[:4]}))
         for pf in w["plans"]:   # the per-function loop runs the same schedules
             for M in np.unique(pf.M):
                 pf.fft_schedule(int(M), plan.fft_schedule(int(M)))
@@ -386,12 +400,16 @@ def main():
         runner = step
 
     plan.profile(not args.graph)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         runner()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     stages = plan.profile_read() if not args.graph else {}
     plan.profile(False)
     ms_step = 1000.0 * elapsed / args.steps
@@ -403,6 +421,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": cfg}
     out["functions_per_s_batched"] = F / (elapsed / args.steps)
+    out["step_ms_median"] = float(np.median(step_ms))
     names = m.fft_schedule_names()
     out["fft_schedules"] = {str(int(M)): names[plan.fft_schedule(int(M))] for M in np.unique(plan.M)[:8]}
     if tune is not None:
@@ -417,7 +436,8 @@ def main():
         if os.path.exists(PMC_FILE):
             with open(PMC_FILE) as fh:
                 pmc = json.load(fh)
-            if pmc.get("source_hash") == vote_source_hash() and pmc.get("workload") == args.workload:
+            wl = args.workload + ("-distinct-m" if args.distinct_m else "")
+            if pmc.get("source_hash") == vote_source_hash() and pmc.get("workload") == wl:
                 traffic = pmc.get("bytes_per_launch")
         out["roofline"] = {"bound": "hbm", "kernel": "k_vote (hash + vote + compaction)", "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -249,14 +249,17 @@ int mr1l_graph_destroy(mr1l_graph g);
  * stream and may grow the plan's scratch; graphs recorded earlier must be
  * recorded again.
  *
- * mr1l_fft_tune: for every distinct size of the plan, times each applicable
- * schedule on the plan's own lattices of that size (one warm-up run, then the
- * mean of reps runs, HIP events on the plan's stream), keeps the fastest and
- * records it for later plans of this process.  sizes (host [max_sizes] or
- * NULL) receives the distinct sizes in the order used; times_ms (host
- * [max_sizes][mr1l_fft_schedule_count()] or NULL) the mean milliseconds per
- * run, -1 where a schedule does not apply.  Allocates and frees two
- * node-sized buffers; synchronises the plan's stream.
+ * mr1l_fft_tune: groups the plan's distinct sizes whose transforms run
+ * alike (same power-of-two length and same LDS size class of the 5-smooth
+ * length, or none), times each schedule that applies to a group on all of the
+ * plan's lattices of that group in one launch (one warm-up run, then the mean
+ * of reps runs, HIP events on the plan's stream), keeps the fastest for every
+ * size of the group and records it for later plans of this process.  sizes
+ * (host [max_sizes] or NULL) receives the distinct sizes in the order used;
+ * times_ms (host [max_sizes][mr1l_fft_schedule_count()] or NULL) the mean
+ * milliseconds per run of each size's group, -1 where a schedule does not
+ * apply.  Allocates and frees two node-sized buffers; synchronises the plan's
+ * stream.
  */
 int mr1l_fft_schedule_count(void);
 const char *mr1l_fft_schedule_name(int32_t sched);

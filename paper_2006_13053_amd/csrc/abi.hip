@@ -210,6 +210,7 @@ static int build_tables(Plan &p)
             ld.node_off = off;
             ld.M = (int32_t)M;
             ld.mid = mid_of[M];
+            p.minfo[ld.mid].nlat += 1;
             ld.func = f;
             ld.inv_m = inv_m_down(M);
             const int64_t S = (int64_t)p.d * kb * (M - 1);
@@ -680,55 +681,63 @@ int mr1l_fft_tune(mr1l_plan p, int32_t reps, int32_t max_sizes, int64_t *sizes, 
         return fail(MR1L_E_ARG, "max_sizes is smaller than the number of distinct lattice sizes");
     const size_t esz = p->dtype == MR1L_C128 ? 16 : 8;
     void *in = nullptr, *out = nullptr;
-    MDesc *d_md = nullptr;
-    int32_t *d_list = nullptr;
     int rc = MR1L_OK;
     auto cleanup = [&]() {
         (void)hipStreamSynchronize(p->stream);
         if (in) (void)hipFree(in);
         if (out) (void)hipFree(out);
-        if (d_md) (void)hipFree(d_md);
-        if (d_list) (void)hipFree(d_list);
     };
     if (hipMalloc(&in, (size_t)std::max<int64_t>(p->nodes, 1) * esz) != hipSuccess ||
-        hipMalloc(&out, (size_t)std::max<int64_t>(p->nodes, 1) * esz) != hipSuccess ||
-        hipMalloc(&d_md, p->mdesc.size() * sizeof(MDesc)) != hipSuccess ||
-        hipMalloc(&d_list, p->lat.size() * sizeof(int32_t)) != hipSuccess) {
+        hipMalloc(&out, (size_t)std::max<int64_t>(p->nodes, 1) * esz) != hipSuccess) {
         cleanup();
         return fail(MR1L_E_NOMEM, "allocation of the tuning buffers failed");
     }
     rc = launch_fill_bytes(in, p->nodes * (int64_t)esz, p->stream);
-    for (size_t mid = 0; mid < p->minfo.size() && rc == MR1L_OK; ++mid) {
-        MInfo &mi = p->minfo[mid];
-        std::vector<int32_t> lst;
-        for (size_t i = 0; i < p->lat.size(); ++i)
-            if (p->lat[i].mid == (int32_t)mid) lst.push_back((int32_t)i);
-        if (hipMemcpy(d_list, lst.data(), lst.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
-            rc = fail(MR1L_E_HIP, "copy of the tuning list failed");
-            break;
-        }
+    // Sizes whose transforms run alike (same LDS class of the 5-smooth length, or
+    // none, and the same power-of-two length) form a group and get one schedule.
+    // Coordinate descent over the groups, largest first: each schedule of a group is
+    // timed on the whole plan's DFT (every group launched as it runs afterwards),
+    // the others held at their current schedules.
+    std::map<std::pair<int, int32_t>, std::vector<int>> gmap;
+    for (size_t mid = 0; mid < p->minfo.size(); ++mid) {
+        const MInfo &mi = p->minfo[mid];
+        gmap[{mi.Ns ? lds_class(mi.Ns) : kLdsClasses, mi.Np}].push_back((int)mid);
         if (sizes) sizes[mid] = mi.M;
-        int best = mi.sched;
-        float best_ms = 0.f;
+    }
+    std::vector<std::pair<int64_t, std::vector<int>>> groups;   // (lattice count, sizes)
+    for (auto &g : gmap) {
+        int64_t nl = 0;
+        for (int mid : g.second) nl += p->minfo[mid].nlat;
+        groups.push_back({nl, g.second});
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    auto set_group = [&](const std::vector<int> &mids, int s) {
+        for (int mid : mids) p->minfo[mid].sched = s;
+        return fft_apply_schedules(*p);
+    };
+    float cur_ms = 0.f;
+    if (rc == MR1L_OK) rc = fft_time_plan(*p, in, out, reps, &cur_ms);
+    for (size_t gi = 0; gi < groups.size() && rc == MR1L_OK; ++gi) {
+        const std::vector<int> &mids = groups[gi].second;
+        const bool lds_ok = p->minfo[mids[0]].Ns > 0;
+        const int start = p->minfo[mids[0]].sched;
+        int best = start;
+        float best_ms = cur_ms;
         for (int s = 0; s < kNumSched && rc == MR1L_OK; ++s) {
             float ms = -1.f;
-            const bool ok = kSched[s].four_step ? mi.Np > 0 : mi.Ns > 0;
-            if (ok) {
-                std::vector<MDesc> md(p->mdesc);
-                md[mid] = fft_layout(*p, (int)mid, s);
-                if (hipMemcpy(d_md, md.data(), md.size() * sizeof(MDesc), hipMemcpyHostToDevice) != hipSuccess) {
-                    rc = fail(MR1L_E_HIP, "copy of the tuning layout failed");
-                    break;
-                }
-                const int cls = kSched[s].four_step ? 0 : lds_class(mi.Ns);
-                rc = fft_time_group(*p, s, cls, d_list, (int)lst.size(), d_md, mi.ltab, in, out, reps, &ms);
-                if (rc) break;
-                if (best_ms == 0.f || ms < best_ms) { best_ms = ms; best = s; }
+            if (s == start) {
+                ms = cur_ms;
+            } else if (kSched[s].four_step || lds_ok) {
+                rc = set_group(mids, s);
+                if (rc == MR1L_OK) rc = fft_time_plan(*p, in, out, reps, &ms);
+                if (rc == MR1L_OK && ms < best_ms) { best_ms = ms; best = s; }
             }
-            if (times_ms) times_ms[mid * kNumSched + s] = ms;
+            if (times_ms)
+                for (int mid : mids) times_ms[mid * kNumSched + s] = ms;
         }
-        mi.sched = best;
-        record_tuned(p->dtype, mi.M, best);
+        if (rc == MR1L_OK) rc = set_group(mids, best);
+        cur_ms = best_ms;
+        for (int mid : mids) record_tuned(p->dtype, p->minfo[mid].M, best);
     }
     cleanup();
     if (rc) return rc;

@@ -948,23 +948,15 @@ int fft_apply_schedules(Plan &p)
     return MR1L_OK;
 }
 
-int fft_time_group(Plan &p, int s, int cls, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
-                   const void *in, void *out, int reps, float *ms)
+int fft_time_plan(Plan &p, const void *in, void *out, int reps, float *ms)
 {
-    if (kSched[s].four_step) {
-        int64_t len = 0;
-        for (const MInfo &mi : p.minfo) len = std::max<int64_t>(len, mi.Np);
-        int rc = ensure_scratch(p, len, std::min<int64_t>(nl, (int64_t)kSched[s].per_cu * num_cus()));
-        if (rc) return rc;
-    }
-    int rc = launch_any(p, s, cls, d_lats, nl, d_md, ltab, in, out, 0.0, nullptr, FFT_FWD, 1.0, 0);
+    int rc = fft_run(p, in, out, 0.0, nullptr, FFT_FWD, 1.0);
     if (rc) return rc;
     hipEvent_t a, b;
     MR1L_HIP(hipEventCreate(&a));
     MR1L_HIP(hipEventCreate(&b));
     MR1L_HIP(hipEventRecord(a, p.stream));
-    for (int r = 0; r < reps && rc == MR1L_OK; ++r)
-        rc = launch_any(p, s, cls, d_lats, nl, d_md, ltab, in, out, 0.0, nullptr, FFT_FWD, 1.0, 0);
+    for (int r = 0; r < reps && rc == MR1L_OK; ++r) rc = fft_run(p, in, out, 0.0, nullptr, FFT_FWD, 1.0);
     MR1L_HIP(hipEventRecord(b, p.stream));
     MR1L_HIP(hipEventSynchronize(b));
     float t = 0.f;

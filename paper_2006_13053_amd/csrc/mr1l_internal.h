@@ -220,8 +220,7 @@ int fft_prepare_spectra(Plan &p);
 int fft_apply_schedules(Plan &p);
 int tuned_schedule(int32_t dtype, int64_t M);
 MDesc fft_layout(const Plan &p, int mid, int s);   // table entry of size mid under schedule s
-int fft_time_group(Plan &p, int sched, int cls, const int32_t *d_lats, int nl, const MDesc *d_md, bool ltab,
-                   const void *in, void *out, int reps, float *ms);
+int fft_time_plan(Plan &p, const void *in, void *out, int reps, float *ms);   // whole-plan forward DFT
 int fft_init_attrs();
 int extract_init_attrs();
 int vote_init_attrs();
