@@ -234,6 +234,21 @@ int mr1l_graph_launch(mr1l_graph g, void *stream);
 int mr1l_graph_destroy(mr1l_graph g);
 
 /*
+ * Check that every function's candidate set stays injective modulo each of its
+ * lattice sizes (the sizes must lie in P^Gamma, Section 2.1).  Every prime
+ * above the set's expansion N_Gamma (largest coordinate range) qualifies; for
+ * smaller sizes the reduced vectors k mod M are compared exactly.
+ *   freq, set_off  as for mr1l_extract;
+ *   ok             host [F] or NULL: 1 if function f's set is injective
+ *                  modulo all of its sizes, else 0.
+ * Returns MR1L_E_NOT_INJECTIVE when some function fails (ok is filled for all
+ * functions).  Allocates a temporary table of 4 * pow2ceil(2 |Gamma_f|) bytes
+ * when a size needs the exact comparison; synchronises the plan's stream.
+ */
+int mr1l_check_injective(mr1l_plan p, int64_t n_total, const int64_t *set_off,
+                         const int64_t *freq, int32_t *ok);
+
+/*
  * DFT schedules and their autotuner.  The lattice DFT of one size M runs under
  * one schedule: 0 = the whole Bluestein transform (5-smooth length) in one
  * workgroup's LDS, valid while that length fits; 1.. = power-of-two four-step

@@ -76,6 +76,7 @@ SIGNATURES = {
     "mr1l_profile": ([_P, _I32], C.c_int),
     "mr1l_profile_read": ([_P, _P, _P], C.c_int),
     "mr1l_num_lattices": ([_I64, _D, _D], _I32),
+    "mr1l_check_injective": ([_P, _I64, _P, _P, _P], C.c_int),
     "mr1l_fft_schedule_count": ([], C.c_int),
     "mr1l_fft_schedule_name": ([_I32], C.c_char_p),
     "mr1l_plan_fft_schedule": ([_P, _I64, _I32], C.c_int),
@@ -197,6 +198,17 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def mr1l_check_injective(plan: Plan, freq, set_off=None):
+    """Whether each function's candidates stay distinct modulo each of its lattice
+    sizes (M in P^Gamma) -> (all injective, per-function flags)."""
+    ok = np.zeros(plan.F, np.int32)
+    rc = lib().mr1l_check_injective(plan.handle, int(freq.shape[1]), _ptr(set_off), _ptr(freq),
+                                    ok.ctypes.data_as(_P))
+    if rc not in (0, -4):   # -4: MR1L_E_NOT_INJECTIVE
+        _check(rc, "mr1l_check_injective")
+    return rc == 0, ok.astype(bool)
 
 
 def fft_schedule_count() -> int:

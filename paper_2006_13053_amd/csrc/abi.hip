@@ -653,6 +653,14 @@ int32_t mr1l_num_lattices(int64_t nJ, double c, double delta)
     return L;
 }
 
+int mr1l_check_injective(mr1l_plan p, int64_t n_total, const int64_t *set_off, const int64_t *freq, int32_t *ok)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (n_total < 0 || (n_total > 0 && !freq)) return fail(MR1L_E_ARG, "invalid candidate buffer");
+    if (!set_off && p->F != 1) return fail(MR1L_E_ARG, "set_off required when F > 1");
+    return check_injective_run(*p, n_total, set_off, freq, ok);
+}
+
 int mr1l_fft_schedule_count(void) { return kNumSched; }
 
 const char *mr1l_fft_schedule_name(int32_t s) { return (s >= 0 && s < kNumSched) ? kSched[s].name : ""; }

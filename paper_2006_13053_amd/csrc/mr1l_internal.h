@@ -221,6 +221,7 @@ int fft_apply_schedules(Plan &p);
 int tuned_schedule(int32_t dtype, int64_t M);
 MDesc fft_layout(const Plan &p, int mid, int s);   // table entry of size mid under schedule s
 int fft_time_plan(Plan &p, const void *in, void *out, int reps, float *ms);   // whole-plan forward DFT
+int check_injective_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, int32_t *ok);
 int fft_init_attrs();
 int extract_init_attrs();
 int vote_init_attrs();

@@ -385,6 +385,37 @@ def test_dirichlet_counting_polynomial(m):
     compare_pass(r, ro, go, p.theta, 1e-11, 2000)
 
 
+def test_injectivity_check_matches_definition(m):
+    """|Gamma mod M| = |Gamma| (Section 2.1), for sizes above and below the expansion
+    of the set, single and batched."""
+    rng = np.random.default_rng(11)
+    d = 3
+    cases = []
+    for n, box, Ms in [(400, 20, [41, 43]), (30, 20, [7, 11]), (60, 20, [13, 17]), (200, 3, [5, 7]),
+                       (1000, 40, [83, 89, 97]), (30, 20, [31, 37])]:
+        cand = synth.distinct_uniform_points(rng, n, d, -box, box)
+        M = np.array(Ms, np.int64)
+        z = rng.integers(0, M.min(), size=(len(Ms), d)).astype(np.int64)
+        want = all(np.unique(np.mod(cand, int(mm)), axis=1).shape[1] == n for mm in M)
+        plan = m.Plan(d, M, z)
+        ok_all, ok = m.mr1l_check_injective(plan, T(cand))
+        say("injective", n, box, Ms, want)
+        assert ok_all == want and bool(ok[0]) == want
+        cases.append((cand, M, z, want))
+    # a duplicate modulo M planted in a set whose range exceeds M
+    cand = synth.distinct_uniform_points(rng, 50, d, -20, 20)
+    cand[:, 7] = cand[:, 3] + np.array([13, -26, 0])
+    if np.unique(cand, axis=1).shape[1] == 50:
+        ok_all, _ = m.mr1l_check_injective(m.Plan(d, np.array([13]), np.ones((1, d), np.int64)), T(cand))
+        assert not ok_all
+    # batched: one plan over all cases with the same number of lattices
+    sel = [c for c in cases if len(c[1]) == 2]
+    plan = m.Plan(d, np.concatenate([c[1] for c in sel]), np.concatenate([c[2] for c in sel]), F=len(sel))
+    soff = np.concatenate([[0], np.cumsum([c[0].shape[1] for c in sel])]).astype(np.int64)
+    ok_all, ok = m.mr1l_check_injective(plan, T(np.concatenate([c[0] for c in sel], axis=1)), T(soff))
+    assert list(ok) == [c[3] for c in sel] and ok_all == all(c[3] for c in sel)
+
+
 def test_empty_and_ragged_inputs(m):
     say("empty/ragged")
     p = synth.small_config(8)
