@@ -251,10 +251,11 @@ __device__ __forceinline__ void dft16(T *xr, T *xi)
 }
 
 // LDS planes of the power-of-two path hold P elements (the workgroup's LDS
-// batch) with one pad element after every 16, which breaks the power-of-two
-// strides of the column accesses and of the early Stockham passes (bank
-// conflicts).
-__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+// batch) of rows of length 2^logn: element i sits at i + i/32 + i/2^lr, lr =
+// max(logn, 5), one pad element after every 32 and one more after every row.
+// The row stride becomes odd (column accesses by consecutive lanes fall in
+// distinct banks) and the strided Stockham accesses spread over the banks.
+__device__ __forceinline__ int padr(int i, int lr) { return i + (i >> 5) + (i >> lr); }
 constexpr int p2_plane(int P) { return P + P / 16; }
 
 // One Stockham pass of radix 2^LR over 2^logb transforms of length 2^logn held
@@ -268,6 +269,7 @@ __device__ void stockham_p2(T *re, T *im, int logn, int logb, int logNs, TW tw, 
     const int lognR = logn - LR;
     const int total = 1 << (logb + lognR);
     const int tsh = logN - logNs - LR;
+    const int lr = max(logn, 5);
     const int tid0 = opaque((int)threadIdx.x);
     T vr[BPT][R], vi[BPT][R];
     int ob[BPT];
@@ -283,8 +285,8 @@ __device__ void stockham_p2(T *re, T *im, int logn, int logb, int logNs, TW tw, 
             const int base = (b << logn) + jj;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                vr[i][r] = re[pad16(base + (r << lognR))];
-                vi[i][r] = im[pad16(base + (r << lognR))];
+                vr[i][r] = re[padr(base + (r << lognR), lr)];
+                vi[i][r] = im[padr(base + (r << lognR), lr)];
             }
             if (logNs > 0) {
 #pragma unroll
@@ -306,8 +308,8 @@ __device__ void stockham_p2(T *re, T *im, int logn, int logb, int logNs, TW tw, 
         if (ob[i] >= 0) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                re[pad16(ob[i] + (r << logNs))] = vr[i][r];
-                im[pad16(ob[i] + (r << logNs))] = vi[i][r];
+                re[padr(ob[i] + (r << logNs), lr)] = vr[i][r];
+                im[padr(ob[i] + (r << logNs), lr)] = vi[i][r];
             }
         }
     }
@@ -536,6 +538,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
         const int logB2 = min(logN2, LOGP - logN1);
         const int logB1 = min(logN1, LOGP - logN2);
         const int B2 = 1 << logB2, B1 = 1 << logB1;
+        const int lrA = max(logN1, 5), lrB = max(logN2, 5);   // LDS rows of phases A/C and B
 
         // ---- phase A: columns.  The raw inputs of a batch are loaded together into
         // LDS, then each thread chirps its own elements (no barrier in between).
@@ -555,7 +558,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
                         const int e = opaque(tid) + (i0 + i) * NT;
                         if (e < tot) {
                             const int nn = ((e >> logB2) << logN2) + c0 + (e & (B2 - 1));
-                            const int q = pad16(((e & (B2 - 1)) << logN1) + (e >> logB2));
+                            const int q = padr(((e & (B2 - 1)) << logN1) + (e >> logB2), lrA);
                             re[q] = nn < M ? v[i].x : T(0);
                             im[q] = nn < M ? cj * v[i].y : T(0);
                         }
@@ -568,7 +571,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
                 if (e < tot) {
                     const int b = e & (B2 - 1), n1 = e >> logB2;
                     const int nn = (n1 << logN2) + c0 + b;
-                    const int q = pad16((b << logN1) + n1);
+                    const int q = padr((b << logN1) + n1, lrA);
                     if (mode == FFT_SPEC) {
                         int src = -1;
                         if (nn < M) src = nn;
@@ -601,7 +604,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
                     const int e = opaque(tid) + (i0 + i) * NT;
                     if (e < tot) {
                         const int b = e & (B2 - 1), k1 = e >> logB2;
-                        const T a = re[pad16((b << logN1) + k1)], bb = im[pad16((b << logN1) + k1)];
+                        const T a = re[padr((b << logN1) + k1, lrA)], bb = im[padr((b << logN1) + k1, lrA)];
                         V o; o.x = a * w[i].x - bb * w[i].y; o.y = a * w[i].y + bb * w[i].x;
                         buf[((int64_t)k1 << logN2) + c0 + b] = o;
                     }
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
                     const int e = opaque(tid) + (i0 + i) * NT;
-                    if (e < tot) { re[pad16(e)] = v[i].x; im[pad16(e)] = v[i].y; }
+                    if (e < tot) { re[padr(e, lrB)] = v[i].x; im[padr(e, lrB)] = v[i].y; }
                 }
             }
             __syncthreads();
@@ -633,7 +636,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
                 for (int e = opaque(tid); e < tot; e += NT) {
                     const int b = e & (B1 - 1), k2 = e >> logB1;
                     const int k = r0 + b + (k2 << logN1);
-                    V o; o.x = re[pad16((b << logN2) + k2)] * s; o.y = im[pad16((b << logN2) + k2)] * s;
+                    V o; o.x = re[padr((b << logN2) + k2, lrB)] * s; o.y = im[padr((b << logN2) + k2, lrB)] * s;
                     spec_tab[m.spec_off + k] = o;
                 }
                 __syncthreads();
@@ -651,7 +654,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
                 for (int i = 0; i < CH; ++i) {
                     const int e = opaque(tid) + (i0 + i) * NT;
                     if (e < tot) {
-                        const int q = pad16(((e & (B1 - 1)) << logN2) + (e >> logB1));
+                        const int q = padr(((e & (B1 - 1)) << logN2) + (e >> logB1), lrB);
                         const T a = re[q], bb = im[q];
                         re[q] = a * sv[i].x - bb * sv[i].y;
                         im[q] = -(a * sv[i].y + bb * sv[i].x);
@@ -673,7 +676,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
                 for (int i = 0; i < CH; ++i) {
                     const int e = opaque(tid) + (i0 + i) * NT;
                     if (e < tot) {
-                        const T a = re[pad16(e)], bb = -im[pad16(e)];
+                        const T a = re[padr(e, lrB)], bb = -im[padr(e, lrB)];
                         V o; o.x = a * w[i].x + bb * w[i].y; o.y = bb * w[i].x - a * w[i].y;   // times conj(w)
                         row[e] = o;
                     }
@@ -696,7 +699,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
                 for (int i = 0; i < CH; ++i) {
                     const int e = opaque(tid) + (i0 + i) * NT;
                     if (e < tot) {
-                        const int q = pad16(((e & (B2 - 1)) << logN1) + (e >> logB2));
+                        const int q = padr(((e & (B2 - 1)) << logN1) + (e >> logB2), lrA);
                         re[q] = v[i].x; im[q] = -v[i].y;
                     }
                 }
@@ -709,7 +712,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
                 const int b = e & (B2 - 1), a = e >> logB2;   // output n = N2 a + (c0 + b)
                 const int h = (a << logN2) + c0 + b;
                 if (h < M) {
-                    const int q = pad16((b << logN1) + a);
+                    const int q = padr((b << logN1) + a, lrA);
                     const T cr = re[q], ci = -im[q];
                     const V w = chirp<T>(ctab, m.chirp_shift, m.chirp_nlo, h, M, inv2m);
                     T gr = (cr * w.x - ci * w.y) * sc;
