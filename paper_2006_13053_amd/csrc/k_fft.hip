@@ -137,7 +137,13 @@ __device__ __forceinline__ int next_radix(int rem)
 // x[b n + jj + r n/R] (jj = j mod n/R), multiplies by e^{-2 pi i r k/(Ns R)}
 // (k = jj mod Ns), applies the radix-R DFT and writes
 // x[b n + (jj / Ns) Ns R + k + r Ns].
-template <typename T, int R, int NT, int NMAXT>
+// LDS index of element i of the mixed-radix planes: one pad element after every
+// 32 when the planes have room for it (PAD), which spreads the strided Stockham
+// writes of the early passes over the banks.
+template <bool PAD> __device__ __forceinline__ int pidx(int i) { return PAD ? i + (i >> 5) : i; }
+template <int NMAXT, bool PAD> constexpr int mr_plane() { return PAD ? NMAXT + NMAXT / 32 : NMAXT; }
+
+template <typename T, int R, int NT, int NMAXT, bool PAD>
 __device__ void stockham_pass(T *re, T *im, int n, int batch, int Ns,
                               const typename cvec<T>::type *__restrict__ tw)
 {
@@ -160,8 +166,8 @@ __device__ void stockham_pass(T *re, T *im, int n, int batch, int Ns,
             const int base = b * n + jj;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                vr[i][r] = re[base + r * nR];
-                vi[i][r] = im[base + r * nR];
+                vr[i][r] = re[pidx<PAD>(base + r * nR)];
+                vi[i][r] = im[pidx<PAD>(base + r * nR)];
             }
             if (Ns > 1) {
 #pragma unroll
@@ -182,8 +188,8 @@ __device__ void stockham_pass(T *re, T *im, int n, int batch, int Ns,
         if (ob[i] >= 0) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                re[ob[i] + r * Ns] = vr[i][r];
-                im[ob[i] + r * Ns] = vi[i][r];
+                re[pidx<PAD>(ob[i] + r * Ns)] = vr[i][r];
+                im[pidx<PAD>(ob[i] + r * Ns)] = vi[i][r];
             }
         }
     }
@@ -193,18 +199,18 @@ __device__ void stockham_pass(T *re, T *im, int n, int batch, int Ns,
 // Forward FFT (e^{-2 pi i}) of `batch` contiguous length-n transforms in LDS
 // (batch * n <= NMAXT) by NT threads; tw = table e^{-2 pi i m / n}, m < n.
 // Output in natural order.
-template <typename T, int NT, int NMAXT>
+template <typename T, int NT, int NMAXT, bool PAD>
 __device__ void lds_fft(T *re, T *im, int n, int batch, const typename cvec<T>::type *tw)
 {
     int Ns = 1, rem = n;
     while (rem > 1) {
         const int R = next_radix(rem);
         switch (R) {
-        case 8: stockham_pass<T, 8, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
-        case 4: stockham_pass<T, 4, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
-        case 2: stockham_pass<T, 2, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
-        case 5: stockham_pass<T, 5, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
-        default: stockham_pass<T, 3, NT, NMAXT>(re, im, n, batch, Ns, tw); break;
+        case 8: stockham_pass<T, 8, NT, NMAXT, PAD>(re, im, n, batch, Ns, tw); break;
+        case 4: stockham_pass<T, 4, NT, NMAXT, PAD>(re, im, n, batch, Ns, tw); break;
+        case 2: stockham_pass<T, 2, NT, NMAXT, PAD>(re, im, n, batch, Ns, tw); break;
+        case 5: stockham_pass<T, 5, NT, NMAXT, PAD>(re, im, n, batch, Ns, tw); break;
+        default: stockham_pass<T, 3, NT, NMAXT, PAD>(re, im, n, batch, Ns, tw); break;
         }
         Ns *= R;
         rem /= R;
@@ -364,7 +370,7 @@ __device__ __forceinline__ void set_bit_if(uint32_t *bitmap, int64_t g, T re, T 
 // FFT_INV (g -> (1/M) sum g e^{+}) times scale (times M when scale_by_m),
 // FFT_SPEC (kernel spectrum of the lattice size, written to the spectrum table).
 // Size classes (NT, NMAXT) keep small transforms from holding a whole CU's LDS.
-template <typename T, int NT, int NMAXT>
+template <typename T, int NT, int NMAXT, bool PAD>
 __global__ __launch_bounds__(NT) void k_bluestein_lds(
     const int32_t *__restrict__ lats, const LatDesc *__restrict__ lat, const MDesc *__restrict__ md,
     const typename cvec<T>::type *__restrict__ in, typename cvec<T>::type *__restrict__ out,
@@ -375,7 +381,7 @@ __global__ __launch_bounds__(NT) void k_bluestein_lds(
     using V = typename cvec<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     T *re = reinterpret_cast<T *>(smem);
-    T *im = re + NMAXT;
+    T *im = re + mr_plane<NMAXT, PAD>();
     const LatDesc ld = lat[lats[blockIdx.x]];
     const MDesc m = md[ld.mid];
     const int N = m.N, M = ld.M;
@@ -395,14 +401,14 @@ __global__ __launch_bounds__(NT) void k_bluestein_lds(
                 V w = chirp<T>(ctab, m.chirp_shift, m.chirp_nlo, src, M, inv2m);
                 xr = w.x; xi = -w.y;
             }
-            re[i] = xr; im[i] = xi;
+            re[pidx<PAD>(i)] = xr; im[pidx<PAD>(i)] = xi;
         }
         __syncthreads();
-        lds_fft<T, NT, NMAXT>(re, im, N, 1, tw);
+        lds_fft<T, NT, NMAXT, PAD>(re, im, N, 1, tw);
         const T s = T(1) / ((T)N * (T)M);
         V *dst = spec_tab + m.spec_off;
         for (int i = tid; i < N; i += NT) {
-            V o; o.x = re[i] * s; o.y = im[i] * s;
+            V o; o.x = re[pidx<PAD>(i)] * s; o.y = im[pidx<PAD>(i)] * s;
             dst[i] = o;
         }
         return;
@@ -425,11 +431,11 @@ __global__ __launch_bounds__(NT) void k_bluestein_lds(
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
             const int i = opaque(tid) + k * NT;
-            if (i < N) { re[i] = xr[k]; im[i] = xi[k]; }
+            if (i < N) { re[pidx<PAD>(i)] = xr[k]; im[pidx<PAD>(i)] = xi[k]; }
         }
     }
     __syncthreads();
-    lds_fft<T, NT, NMAXT>(re, im, N, 1, tw);
+    lds_fft<T, NT, NMAXT, PAD>(re, im, N, 1, tw);
     const V *sp = spec_tab + m.spec_off;
     {
         V sv[EPT];
@@ -442,19 +448,19 @@ __global__ __launch_bounds__(NT) void k_bluestein_lds(
         for (int k = 0; k < EPT; ++k) {
             const int i = opaque(tid) + k * NT;
             if (i < N) {
-                T a = re[i], b = im[i];
-                re[i] = a * sv[k].x - b * sv[k].y;
-                im[i] = -(a * sv[k].y + b * sv[k].x);   // conjugate: the next FFT is an inverse one
+                T a = re[pidx<PAD>(i)], b = im[pidx<PAD>(i)];
+                re[pidx<PAD>(i)] = a * sv[k].x - b * sv[k].y;
+                im[pidx<PAD>(i)] = -(a * sv[k].y + b * sv[k].x);   // conjugate: the next FFT is an inverse one
             }
         }
     }
     __syncthreads();
-    lds_fft<T, NT, NMAXT>(re, im, N, 1, tw);
+    lds_fft<T, NT, NMAXT, PAD>(re, im, N, 1, tw);
     const T sc = scale_by_m ? scale * (T)M : scale;
     V *y = out + ld.node_off;
     for (int i = tid; i < M; i += NT) {
         V w = chirp<T>(ctab, m.chirp_shift, m.chirp_nlo, i, M, inv2m);
-        const T cr = re[i], ci = -im[i];     // undo the conjugation
+        const T cr = re[pidx<PAD>(i)], ci = -im[pidx<PAD>(i)];     // undo the conjugation
         T gr = (cr * w.x - ci * w.y) * sc;
         T gi = (cr * w.y + ci * w.x) * sc;
         if (mode == FFT_INV) gi = -gi;
@@ -764,14 +770,14 @@ static int launch4(Plan &p, const int32_t *d_lats, int nl, const MDesc *d_md, co
 }
 
 // One launch of schedule s over the lattices d_lats (their sizes' tables in d_md).
-template <typename T, int NT, int NMAXT>
+template <typename T, int NT, int NMAXT, bool PAD>
 static int launch_lds(Plan &p, const int32_t *d_lats, int nl, const MDesc *d_md, const void *in, void *out,
                       T th2, uint32_t *bitmap, int mode, T sc, int by_m)
 {
     using V = typename cvec<T>::type;
-    constexpr size_t shm = 2 * sizeof(T) * (size_t)NMAXT;
+    constexpr size_t shm = 2 * sizeof(T) * (size_t)mr_plane<NMAXT, PAD>();
     static_assert(shm <= (size_t)kLdsBytes, "LDS transform budget");
-    hipLaunchKernelGGL((k_bluestein_lds<T, NT, NMAXT>), dim3((unsigned)nl), dim3(NT), shm, p.stream, d_lats, p.d_lat,
+    hipLaunchKernelGGL((k_bluestein_lds<T, NT, NMAXT, PAD>), dim3((unsigned)nl), dim3(NT), shm, p.stream, d_lats, p.d_lat,
                        d_md, (const V *)in, (V *)out, (V *)p.d_spec, (const V *)p.d_chirp, (const V *)p.d_tw, bitmap,
                        th2, mode, sc, by_m);
     MR1L_LAUNCH_CHECK();
@@ -790,9 +796,10 @@ static int launch_sched(Plan &p, int s, int cls, const int32_t *d_lats, int nl, 
     if (nl <= 0) return MR1L_OK;
     switch (s) {
     case 0:
-        if (cls == 0) return launch_lds<T, 128, 1024>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m);
-        if (cls == 1) return launch_lds<T, 512, 4096>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m);
-        return launch_lds<T, kFftThreads, lds_max_n<T>()>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m);
+        if (cls == 0) return launch_lds<T, 128, 1024, true>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m);
+        if (cls == 1) return launch_lds<T, 512, 4096, true>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m);
+        return launch_lds<T, kFftThreads, lds_max_n<T>(), false>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc,
+                                                                 by_m);
     case 1: case 2:
         return ltab ? launch4<T, true, 512, LS, 4>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc)
                     : launch4<T, false, 512, LS, 4>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc);
@@ -829,9 +836,9 @@ template <typename T> static int allow_lds()
     constexpr int LS = sizeof(T) == 8 ? 12 : 13;
     constexpr size_t e = sizeof(T);
     int rc = MR1L_OK;
-    if (!rc) rc = allow_lds_one(k_bluestein_lds<T, 128, 1024>, 2 * e * 1024);
-    if (!rc) rc = allow_lds_one(k_bluestein_lds<T, 512, 4096>, 2 * e * 4096);
-    if (!rc) rc = allow_lds_one(k_bluestein_lds<T, kFftThreads, lds_max_n<T>()>, 2 * e * lds_max_n<T>());
+    if (!rc) rc = allow_lds_one(k_bluestein_lds<T, 128, 1024, true>, 2 * e * mr_plane<1024, true>());
+    if (!rc) rc = allow_lds_one(k_bluestein_lds<T, 512, 4096, true>, 2 * e * mr_plane<4096, true>());
+    if (!rc) rc = allow_lds_one(k_bluestein_lds<T, kFftThreads, lds_max_n<T>(), false>, 2 * e * lds_max_n<T>());
     if (!rc) rc = allow_lds_one(k_bluestein_4step<T, true, 512, LS, 4>, lds_4step<T, LS, true>());
     if (!rc) rc = allow_lds_one(k_bluestein_4step<T, false, 512, LS, 4>, lds_4step<T, LS, false>());
     if (!rc) rc = allow_lds_one(k_bluestein_4step<T, true, 512, LS + 1, 2>, lds_4step<T, LS + 1, true>());
