@@ -225,7 +225,8 @@ def bench_dimincr(m, torch, args):
         pc = torch.from_numpy(coef).to(dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        gf, gc, ns = m.mr1l_dimincr(d, N, s, 2 * s, r, 1e-12, Mlat, 1000 + seed, poly_freq=pf, poly_coef=pc)
+        gf, gc, ns = m.mr1l_dimincr(d, N, s, 2 * s, r, 1e-12, Mlat, 1000 + seed, poly_freq=pf, poly_coef=pc,
+                                    step1=args.step1)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
@@ -241,14 +242,15 @@ def bench_dimincr(m, torch, args):
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
            "data": "synthetic",
            "config": {"workload": "dimension-incremental: d=25, s=200 in [-32,32]^25, r=5, s_local=400, "
-                                  "M=4133, L by eq. (4.2), theta=1e-12, Algorithm 3 Step 2"},
+                                  "M=4133, L by eq. (4.2), theta=1e-12, Algorithm 3 "
+                                  + ("Steps 1 and 2" if args.step1 else "Step 2 (full single-coordinate range)")},
            "runs": runs}
     if not args.no_cpu:
         import oracle
         freq, coef = synth.sparse_poly_box(0, d=d, s=s, box=N)
         t0 = time.perf_counter()
         of, oc, ns = oracle.dimincr(freq, coef, N=N, s=s, s_local=2 * s, r=r, theta=1e-12, c=10.33,
-                                    delta=0.9, Mlat=Mlat, seed=1000)
+                                    delta=0.9, Mlat=Mlat, seed=1000, step1=args.step1)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": dt, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": "one full driver run (seed 0) of the oracle: direct DFTs, "
@@ -323,6 +325,8 @@ def main():
     ap.add_argument("--functions", type=int, default=None)
     ap.add_argument("--candidates", type=int, default=10_000_000)
     ap.add_argument("--c64", action="store_true")
+    ap.add_argument("--step1", action="store_true",
+                    help="dimincr workload: single-coordinate sets from Algorithm 3 Step 1 instead of the full range")
     ap.add_argument("--distinct-m", action="store_true",
                     help="large workload with 20 distinct primes in [15500, 16500] per function instead of M = 16001")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")

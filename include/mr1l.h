@@ -295,6 +295,7 @@ typedef struct {
     int32_t postproc;  /* Remark 2.9 averaging on/off                      */
     uint64_t seed;     /* SplitMix64 seed of all random draws               */
     int32_t dtype;     /* MR1L_C128 or MR1L_C64                            */
+    int32_t step1;     /* 1: single-coordinate sets from Step 1; 0: [-N, N] */
 } mr1l_dimincr_params;
 
 /*
@@ -309,10 +310,17 @@ typedef int (*mr1l_sample_fn)(void *user, int32_t t, int32_t L,
                               void *stream);
 
 /*
- * Step 2 of Algorithm 3 with Algorithm 4 as the detection method
- * (Section 3.2.2), the single-coordinate sets being the full range [-N, N]:
- * for t = 2..d and i = 1..r~ (r~ = r for t < d, 1 for t = d), candidates
- * J_t = I^(1..t-1) x [-N, N] in lexicographic order, L lattices by
+ * Steps 1 and 2 of Algorithm 3 with Algorithm 4 as the detection method
+ * (Section 3.2.2).
+ * Step 1 (step1 = 1; built-in sampler only; 2N + 1 <= 8192): for every
+ * coordinate t = 1..d and i = 1..r, anchors x'_j = a_j / 2^32 for j != t
+ * (ascending j) from the SplitMix64 stream n = 2^62 + ((t*64 + i) << 24)
+ * + c + 1, samples at x_t = l / (2N+1), l <= 2N, the normalised length-(2N+1)
+ * DFT, and the frequencies k_t in [-N, N] among the s_local largest moduli
+ * with |value| >= theta (ties: smaller k_t first); I^(t) is the union over i.
+ * With step1 = 0 every I^(t) is the full range [-N, N].
+ * Step 2: for t = 2..d and i = 1..r~ (r~ = r for t < d, 1 for t = d),
+ * candidates J_t = I^(1..t-1) x I^(t) in lexicographic order, L lattices by
  * eq. (4.2) on |J_t| (smallest odd L >= (c/((c-2) ln(c-1))) (ln|J_t| -
  * ln delta)), every lattice of size M, random anchors and generating
  * vectors drawn from SplitMix64 outputs of the stream (seed, t, i)
@@ -329,7 +337,8 @@ typedef int (*mr1l_sample_fn)(void *user, int32_t t, int32_t L,
  *   n_out     host: number of recovered frequencies.
  *   freq_out  host [cap][d] int64, lexicographically sorted;
  *   coef_out  host [cap] complex (dtype of the params).
- *   total_samples host (may be NULL): sum over calls of L*M.
+ *   total_samples host (may be NULL): sum over Step 2 calls of L*M, plus
+ *             d*r*(2N+1) with Step 1.
  * Synchronises the stream.  MR1L_E_CAPACITY if a union exceeds cap.
  */
 int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn,

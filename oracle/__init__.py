@@ -75,7 +75,7 @@ def _declare(L):
     L.orc_num_lattices_eq42.argtypes = [_i64, _d, _d]
     L.orc_num_lattices_eq42.restype = _i32
     L.orc_dimincr.argtypes = [_i32, _i64, _i64, _p, _p, _i64, _i64, _i32, _d, _d, _d, _i64,
-                              _i32, _u64, _i64, _p, _p, _p]
+                              _i32, _u64, _i64, _i32, _p, _p, _p]
     L.orc_dimincr.restype = _i64
 
 
@@ -244,8 +244,9 @@ def num_lattices_eq42(nJ: int, c: float = 10.33, delta: float = 0.9) -> int:
 
 
 def dimincr(poly_freq, poly_coef, N, s, s_local, r, theta, c, delta, Mlat, seed,
-            postproc=True, cap_set=1 << 20):
-    """Algorithm 3 Step 2 (full-range single-coordinate sets) with Algorithm 4.
+            postproc=True, cap_set=1 << 20, step1=False):
+    """Algorithm 3 Step 2 with Algorithm 4; the single-coordinate sets come from Step 1
+    (step1) or are the full range [-N, N].
 
     Returns (freq [n, d] int64 lexicographically sorted, coef [n] complex, samples).
     """
@@ -257,8 +258,8 @@ def dimincr(poly_freq, poly_coef, N, s, s_local, r, theta, c, delta, Mlat, seed,
     tot = C.c_int64(0)
     n = lib().orc_dimincr(d, int(N), sp, _ptr(pf), _ptr(pc), int(s), int(s_local), int(r),
                           float(theta), float(c), float(delta), int(Mlat), int(bool(postproc)),
-                          C.c_uint64(seed & (2**64 - 1)), int(cap_set), _ptr(out_f), _ptr(out_c),
-                          C.byref(tot))
+                          C.c_uint64(seed & (2**64 - 1)), int(cap_set), int(bool(step1)), _ptr(out_f),
+                          _ptr(out_c), C.byref(tot))
     if n < 0:
         raise RuntimeError("oracle dimincr: capacity exceeded")
     return out_f[:n], out_c.view(np.complex128)[:n], int(tot.value)

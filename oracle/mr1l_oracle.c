@@ -571,6 +571,71 @@ static uint64_t stream_draw(uint64_t seed, int32_t t, int32_t i, uint64_t c)
     return orc_splitmix64(seed, n);
 }
 
+/* Step 1 of the driver draws from a second family of streams:          */
+/*   n = 2^62 + ((t * 64 + i) << 24) + c + 1 (t = coordinate, 1-based).  */
+static uint64_t stream1_draw(uint64_t seed, int32_t t, int32_t i, uint64_t c)
+{
+    uint64_t n = (1ULL << 62) + ((((uint64_t)t * 64u) + (uint64_t)i) << 24) + c + 1u;
+    return orc_splitmix64(seed, n);
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 3, Step 1 (single frequency component identification) for  */
+/* coordinate t (1-based) over the range [-N, N] (K = 2N + 1):           */
+/* r times: anchors x'_j = a_j / 2^32 for j != t (drawn in ascending j  */
+/* from stream1 (t, i)), samples p at x_t = l / K, l < K, the           */
+/* normalised length-K DFT, and the frequencies k_t in [-N, N] among   */
+/* the s_local largest |p~_{t,k_t}| with |p~| >= theta (ties: smaller  */
+/* k_t first); I^(t) is the union, returned sorted in set[], size      */
+/* returned.  *samples grows by r K.                                   */
+/* ------------------------------------------------------------------ */
+static int64_t step1_set(int32_t d, int32_t t, int64_t N, int64_t s_poly, const int64_t *poly_freq,
+                         const double *poly_coef, int64_t s_local, int32_t r, double theta,
+                         uint64_t seed, int64_t *set, int64_t *samples)
+{
+    const int64_t K = 2 * N + 1;
+    /* the polynomial's coordinates with t moved to the front */
+    int64_t *pf = (int64_t *)malloc(sizeof(int64_t) * (size_t)d * (size_t)(s_poly > 0 ? s_poly : 1));
+    for (int64_t q = 0; q < s_poly; ++q) {
+        pf[q] = poly_freq[(int64_t)(t - 1) * s_poly + q];
+        int32_t row = 1;
+        for (int32_t u = 0; u < d; ++u)
+            if (u != t - 1) pf[(int64_t)(row++) * s_poly + q] = poly_freq[(int64_t)u * s_poly + q];
+    }
+    char *in = (char *)calloc((size_t)K, 1);
+    double *f = (double *)malloc(sizeof(double) * 2 * (size_t)K);
+    double *g = (double *)malloc(sizeof(double) * 2 * (size_t)K);
+    struct key { double m2; int64_t idx; } *keys = malloc(sizeof(struct key) * (size_t)K);
+    uint32_t *anc = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)d);
+    const int64_t one = 1;
+    for (int32_t i = 1; i <= r; ++i) {
+        uint64_t cnt = 0;
+        for (int32_t j = 0; j < d - 1; ++j) anc[j] = (uint32_t)(stream1_draw(seed, t, i, cnt++) >> 32);
+        orc_sample(d, 1, s_poly, pf, poly_coef, anc, 1, &K, &one, f);
+        *samples += K;
+        orc_dft(1, &K, f, g, -1);
+        int64_t nk = 0;
+        for (int64_t k = -N; k <= N; ++k) {
+            const int64_t h = ((k % K) + K) % K;
+            const double m2 = g[2 * h] * g[2 * h] + g[2 * h + 1] * g[2 * h + 1];
+            if (m2 >= theta * theta) { keys[nk].m2 = m2; keys[nk].idx = k + N; nk++; }
+        }
+        /* the s_local largest moduli, ties by smaller frequency (selection by repeated maxima) */
+        for (int64_t q = 0; q < s_local && q < nk; ++q) {
+            int64_t b = q;
+            for (int64_t x = q + 1; x < nk; ++x)
+                if (keys[x].m2 > keys[b].m2 || (keys[x].m2 == keys[b].m2 && keys[x].idx < keys[b].idx)) b = x;
+            struct key tmp = keys[q]; keys[q] = keys[b]; keys[b] = tmp;
+            in[keys[q].idx] = 1;
+        }
+    }
+    int64_t n = 0;
+    for (int64_t a = 0; a < K; ++a)
+        if (in[a]) set[n++] = a - N;
+    free(anc); free(keys); free(g); free(f); free(in); free(pf);
+    return n;
+}
+
 static int64_t uniform_below(uint64_t x, int64_t m)
 {
     return (int64_t)(((unsigned __int128)x * (unsigned __int128)(uint64_t)m) >> 64);
@@ -603,14 +668,13 @@ static int cmp_tuple(const void *a, const void *b)
 /* Algorithm 3, Step 2 (coupling of frequency components), with         */
 /* Algorithm 4 in the role of Algorithm A, for a sparse trigonometric   */
 /* polynomial given by its d x s frequencies and coefficients.           */
-/* Step 1 is replaced by the full one-dimensional range [-N, N] in      */
-/* every coordinate (the single-coordinate sets of Step 1 are taken as  */
-/* the whole range), and the output of the t = d call is the result    */
-/* (the external Step 3 is not part of this method).                    */
+/* The single-coordinate sets I^(t) come from Step 1 (step1 != 0) or   */
+/* are the full one-dimensional range [-N, N]; the output of the t = d  */
+/* call is the result (the external Step 3 is not part of this method). */
 /*                                                                     */
 /* For t = 2..d and i = 1..r~ (r~ = r for t < d, 1 for t = d;           */
 /* s~ = s_local for t < d, s for t = d):                                 */
-/*   J_t  = I^(1..t-1) x [-N, N] (lexicographic order),                 */
+/*   J_t  = I^(1..t-1) x I^(t) (lexicographic order),                   */
 /*   L    = eq. (4.2) on |J_t|, every lattice of size Mlat,             */
 /*   draws: anchors a_u (u = t..d-1), then z_{l,u} (l < L, u < t),       */
 /*   samples at the t-dimensional lattice nodes with anchors,           */
@@ -622,28 +686,43 @@ static int cmp_tuple(const void *a, const void *b)
 int64_t orc_dimincr(int32_t d, int64_t N, int64_t s_poly, const int64_t *poly_freq,
                     const double *poly_coef, int64_t s, int64_t s_local, int32_t r,
                     double theta, double c, double delta, int64_t Mlat,
-                    int32_t postproc, uint64_t seed, int64_t cap_set,
+                    int32_t postproc, uint64_t seed, int64_t cap_set, int32_t step1,
                     int64_t *out_freq, double *out_coef, int64_t *total_samples)
 {
     const int64_t K = 2 * N + 1;
-    int64_t nprev = K;                   /* |I^(1..t-1)| */
+    int64_t samples = 0;
+    /* single-coordinate sets I^(t): Step 1, or the whole range [-N, N] */
+    int64_t *I1 = (int64_t *)malloc(sizeof(int64_t) * (size_t)d * (size_t)K);
+    int64_t *n1 = (int64_t *)malloc(sizeof(int64_t) * (size_t)d);
+    for (int32_t t = 1; t <= d; ++t) {
+        if (step1) {
+            n1[t - 1] = step1_set(d, t, N, s_poly, poly_freq, poly_coef, s_local, r, theta, seed,
+                                  I1 + (int64_t)(t - 1) * K, &samples);
+        } else {
+            for (int64_t a = 0; a < K; ++a) I1[(int64_t)(t - 1) * K + a] = a - N;
+            n1[t - 1] = K;
+        }
+    }
+    int64_t nprev = n1[0];               /* |I^(1..t-1)| */
     int64_t *prev = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap_set * (size_t)d);
-    for (int64_t a = 0; a < K; ++a) prev[a] = a - N; /* I^(1) = [-N, N] */
+    for (int64_t a = 0; a < nprev; ++a) prev[a] = I1[a]; /* I^(1) */
     int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap_set * (size_t)d);
     int64_t nout_final = 0;
-    int64_t samples = 0;
 
-    for (int32_t t = 2; t <= d; ++t) {
+    for (int32_t t = 2; t <= d && nprev > 0; ++t) {
         const int32_t rt = (t < d) ? r : 1;
         const int64_t st = (t < d) ? s_local : s;
-        const int64_t nJ = nprev * K;
-        /* J_t as SoA [t][nJ] */
+        const int64_t Kt = n1[t - 1];
+        const int64_t *It = I1 + (int64_t)(t - 1) * K;
+        const int64_t nJ = nprev * Kt;
+        if (nJ == 0) { nprev = 0; break; }
+        /* J_t = I^(1..t-1) x I^(t) as SoA [t][nJ], lexicographic */
         int64_t *J = (int64_t *)malloc(sizeof(int64_t) * (size_t)nJ * (size_t)t);
         for (int64_t a = 0; a < nprev; ++a)
-            for (int64_t b = 0; b < K; ++b) {
-                int64_t q = a * K + b;
+            for (int64_t b = 0; b < Kt; ++b) {
+                int64_t q = a * Kt + b;
                 for (int32_t u = 0; u < t - 1; ++u) J[(int64_t)u * nJ + q] = prev[a * (t - 1) + u];
-                J[(int64_t)(t - 1) * nJ + q] = b - N;
+                J[(int64_t)(t - 1) * nJ + q] = It[b];
             }
         const int32_t L = orc_num_lattices_eq42(nJ, c, delta);
         int64_t *Ms = (int64_t *)malloc(sizeof(int64_t) * (size_t)L);
@@ -696,7 +775,7 @@ int64_t orc_dimincr(int32_t d, int64_t N, int64_t s_poly, const int64_t *poly_fr
         }
         free(Ms);
         free(J);
-        if (ncur < 0) { free(prev); free(cur); return -1; }
+        if (ncur < 0) { free(prev); free(cur); free(I1); free(n1); return -1; }
 
         if (t == d) {
             /* sort final tuples (with their coefficients) lexicographically */
@@ -735,6 +814,8 @@ int64_t orc_dimincr(int32_t d, int64_t N, int64_t s_poly, const int64_t *poly_fr
     }
     free(prev);
     free(cur);
+    free(I1);
+    free(n1);
     if (total_samples) *total_samples = samples;
     return nout_final;
 }

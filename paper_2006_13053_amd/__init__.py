@@ -45,7 +45,8 @@ class ExtractOut(C.Structure):
 class DimincrParams(C.Structure):
     _fields_ = [("d", C.c_int32), ("N", C.c_int64), ("s", C.c_int64), ("s_local", C.c_int64),
                 ("r", C.c_int32), ("theta", C.c_double), ("c", C.c_double), ("delta", C.c_double),
-                ("M", C.c_int64), ("postproc", C.c_int32), ("seed", C.c_uint64), ("dtype", C.c_int32)]
+                ("M", C.c_int64), ("postproc", C.c_int32), ("seed", C.c_uint64), ("dtype", C.c_int32),
+                ("step1", C.c_int32)]
 
 
 SAMPLE_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
@@ -341,10 +342,12 @@ def mr1l_num_lattices(nJ: int, c: float = 10.33, delta: float = 0.9) -> int:
 
 def mr1l_dimincr(d: int, N: int, s: int, s_local: int, r: int, theta: float, M: int, seed: int,
                  poly_freq=None, poly_coef=None, c: float = 10.33, delta: float = 0.9,
-                 postproc: bool = True, dtype=torch.complex128, cap: int = 1 << 16, sample_fn=None):
-    """Algorithm 3 Step 2 driver -> (freq [n, d] int64 numpy, coef [n] numpy, total samples)."""
+                 postproc: bool = True, dtype=torch.complex128, cap: int = 1 << 16, sample_fn=None,
+                 step1: bool = False):
+    """Algorithm 3 driver (Step 2, and Step 1 when step1) -> (freq [n, d] int64 numpy,
+    coef [n] numpy, total samples)."""
     prm = DimincrParams(int(d), int(N), int(s), int(s_local), int(r), float(theta), float(c), float(delta),
-                        int(M), int(bool(postproc)), int(seed) & (2**64 - 1), _ctype(dtype))
+                        int(M), int(bool(postproc)), int(seed) & (2**64 - 1), _ctype(dtype), int(bool(step1)))
     fo = np.zeros((cap, d), np.int64)
     co = np.zeros(cap, np.complex128 if dtype == torch.complex128 else np.complex64)
     n_out, tot = C.c_int64(0), C.c_int64(0)

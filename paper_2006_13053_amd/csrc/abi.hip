@@ -376,6 +376,18 @@ const char *mr1l_last_error(void) { return g_err.c_str(); }
 int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int64_t *M, const int64_t *z,
                      int32_t dtype, void *stream)
 {
+    return plan_create_impl(out, d, F, L, M, z, dtype, stream, true);
+}
+
+}  // extern "C"
+
+mr1l::Plan &mr1l::plan_of(mr1l_plan p) { return *p; }
+
+// Plan creation; need_prime = false admits composite sizes (the one-dimensional
+// DFT grids of the driver's Step 1; the Bluestein transform holds for any size).
+int mr1l::plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int64_t *M, const int64_t *z,
+                           int32_t dtype, void *stream, bool need_prime)
+{
     if (!out) return fail(MR1L_E_ARG, "out is NULL");
     *out = nullptr;
     if (d < 1 || d > kMaxD) return fail(MR1L_E_ARG, "d must be in [1, 64]");
@@ -387,7 +399,7 @@ int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int6
     for (int64_t i = 0; i < nl; ++i) {
         if (M[i] < 2 || M[i] >= (int64_t(1) << 23))
             return fail(MR1L_E_ARG, "lattice size out of range [2, 2^23): " + std::to_string(M[i]));
-        if (!is_prime_u64((uint64_t)M[i]))
+        if (need_prime && !is_prime_u64((uint64_t)M[i]))
             return fail(MR1L_E_NOT_PRIME, "lattice size is not prime: " + std::to_string(M[i]));
         for (int u = 0; u < d; ++u) {
             const int64_t v = z[i * d + u];
@@ -424,6 +436,8 @@ int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int6
     *out = p;
     return MR1L_OK;
 }
+
+extern "C" {
 
 int mr1l_plan_destroy(mr1l_plan p)
 {

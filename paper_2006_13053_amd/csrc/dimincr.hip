@@ -1,9 +1,15 @@
-// Dimension-incremental driver: Step 2 of Algorithm 3 with Algorithm 4 as
-// the detection method (Section 3.2.2), the single-coordinate candidate sets
-// being the whole range [-N, N].
+// Dimension-incremental driver: Algorithm 3 with Algorithm 4 as the detection
+// method (Section 3.2.2).
+//
+// Step 1 (optional; otherwise every I^(t) is the whole range [-N, N]): all
+// d x r one-dimensional problems run as one batched plan of composite size
+// K = 2N + 1 -- the polynomial with coordinate t moved first, anchors for the
+// others, samples on the grid l / K, the normalised DFT, and Algorithm 4 over
+// the K frequencies [-N, N] keeping the s_local largest; I^(t) is the union
+// over the r repetitions.
 //
 // Per step t = 2..d and repetition i = 1..r~:
-//   J_t = I^(1..t-1) x [-N, N]                (k_cartesian, lexicographic)
+//   J_t = I^(1..t-1) x I^(t)                  (k_cartesian, lexicographic)
 //   L   = eq. (4.2) on |J_t|, every lattice of size M
 //   draws from SplitMix64 stream (seed, t, i): anchors, then generating vectors
 //   samples on the t-dimensional lattices with the anchors fixed (Step 2b)
@@ -29,22 +35,40 @@ static uint64_t splitmix(uint64_t seed, uint64_t n)
     return x ^ (x >> 31);
 }
 
+// Step 2 streams: n = ((t*64 + i) << 24) + c + 1; Step 1 streams add 2^62.
 struct Stream {
     uint64_t seed, base, c = 0;
-    Stream(uint64_t s, int t, int i) : seed(s), base(((uint64_t)t * 64u + (uint64_t)i) << 24) {}
+    Stream(uint64_t s, int t, int i, bool step1 = false)
+        : seed(s), base((step1 ? (uint64_t(1) << 62) : 0u) + (((uint64_t)t * 64u + (uint64_t)i) << 24)) {}
     uint64_t next() { return splitmix(seed, base + (c++) + 1u); }
     int64_t below(int64_t m) { return (int64_t)(((unsigned __int128)next() * (uint64_t)m) >> 64); }
 };
 
-__global__ void k_cartesian(const int64_t *__restrict__ prev, int64_t nprev, int tm1, int64_t N,
-                            int64_t *__restrict__ J)
+// J = prev x set, lexicographic: J[u][a * K + b] = prev[u][a] (u < tm1), set[b].
+__global__ void k_cartesian(const int64_t *__restrict__ prev, int64_t nprev, int tm1,
+                            const int64_t *__restrict__ set, int64_t K, int64_t *__restrict__ J)
 {
-    const int64_t K = 2 * N + 1;
     const int64_t nJ = nprev * K;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nJ; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t a = q / K, b = q - a * K;
         for (int u = 0; u < tm1; ++u) J[(int64_t)u * nJ + q] = prev[(int64_t)u * nprev + a];
-        J[(int64_t)tm1 * nJ + q] = b - N;
+        J[(int64_t)tm1 * nJ + q] = set[b];
+    }
+}
+
+// Step 1 lists for Algorithm 4: entry q of problem f is the frequency q - N with
+// the DFT value at index (q - N) mod K.
+template <typename T>
+__global__ void k_line_gather(int F, int64_t K, int64_t N, const typename cvec<T>::type *__restrict__ ghat,
+                              int64_t *__restrict__ det_idx, typename cvec<T>::type *__restrict__ det_coef,
+                              int64_t *__restrict__ n_det)
+{
+    const int f = blockIdx.y;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < K; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t h = (q + N + 1) % K;   // (q - N) mod K
+        det_idx[(int64_t)f * K + q] = q;
+        det_coef[(int64_t)f * K + q] = ghat[(int64_t)f * K + h];
+        if (q == 0) n_det[f] = K;
     }
 }
 
@@ -91,21 +115,114 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
     *n_out = 0;
     int64_t samples = 0;
 
-    // I^(1) = [-N, N], row-major tuples
-    std::vector<int64_t> prev(K);
-    for (int64_t a = 0; a < K; ++a) prev[a] = a - P.N;
-    int64_t nprev = K;
-    DevBuf<int64_t> dprev, dJ, n_det, det_idx, n_o, out_idx;
+    DevBuf<int64_t> dprev, dJ, n_det, det_idx, n_o, out_idx, dset;
     DevBuf<unsigned char> fbuf, gbuf, det_coef, out_coef;
     DevBuf<uint32_t> bitmap, danc;
+    int rc;
+
+    // single-coordinate sets I^(t), t = 1..d
+    std::vector<std::vector<int64_t>> I1(d);
+    if (!P.step1) {
+        for (int t = 0; t < d; ++t)
+            for (int64_t a = 0; a < K; ++a) I1[t].push_back(a - P.N);
+    } else {
+        if (fn) return fail(MR1L_E_ARG, "Step 1 needs the built-in sampler");
+        if (K > kMaxCap) return fail(MR1L_E_ARG, "Step 1 needs 2N + 1 <= 8192");
+        if (poly_s < 1) return fail(MR1L_E_ARG, "Step 1 needs a non-empty polynomial");
+        // the polynomial on the host, then one copy per (t, i) with coordinate t first
+        std::vector<int64_t> hf((size_t)d * poly_s);
+        std::vector<unsigned char> hc((size_t)poly_s * esz);
+        MR1L_HIP(hipMemcpyAsync(hf.data(), poly_freq, hf.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        MR1L_HIP(hipMemcpyAsync(hc.data(), poly_coef, hc.size(), hipMemcpyDeviceToHost, st));
+        MR1L_HIP(hipStreamSynchronize(st));
+        const int F1 = d * P.r;
+        const int64_t T1 = (int64_t)F1 * poly_s;
+        std::vector<int64_t> rf((size_t)d * T1), toff(F1 + 1);
+        std::vector<unsigned char> rcf((size_t)T1 * esz);
+        std::vector<uint32_t> anc1((size_t)F1 * (d - 1));
+        for (int f = 0; f < F1; ++f) {
+            const int t = f / P.r + 1, i = f % P.r + 1;
+            toff[f] = (int64_t)f * poly_s;
+            for (int64_t q = 0; q < poly_s; ++q) {
+                const int64_t col = (int64_t)f * poly_s + q;
+                rf[col] = hf[(size_t)(t - 1) * poly_s + q];
+                int row = 1;
+                for (int u = 0; u < d; ++u)
+                    if (u != t - 1) rf[(size_t)(row++) * T1 + col] = hf[(size_t)u * poly_s + q];
+            }
+            std::memcpy(rcf.data() + (size_t)f * poly_s * esz, hc.data(), (size_t)poly_s * esz);
+            Stream rs(P.seed, t, i, true);
+            for (int j = 0; j < d - 1; ++j) anc1[(size_t)f * (d - 1) + j] = (uint32_t)(rs.next() >> 32);
+        }
+        toff[F1] = T1;
+        DevBuf<int64_t> drf, dtoff;
+        DevBuf<unsigned char> drc;
+        DevBuf<uint32_t> danc1;
+        if ((rc = drf.need((int64_t)rf.size())) || (rc = dtoff.need(F1 + 1)) || (rc = drc.need((int64_t)rcf.size())) ||
+            (rc = danc1.need((int64_t)anc1.size())))
+            return rc;
+        MR1L_HIP(hipMemcpyAsync(drf.p, rf.data(), rf.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        MR1L_HIP(hipMemcpyAsync(dtoff.p, toff.data(), toff.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        MR1L_HIP(hipMemcpyAsync(drc.p, rcf.data(), rcf.size(), hipMemcpyHostToDevice, st));
+        MR1L_HIP(hipMemcpyAsync(danc1.p, anc1.data(), anc1.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        std::vector<int64_t> M1(F1, K), z1(F1, 1);
+        PlanHolder p1;
+        if ((rc = plan_create_impl(&p1.p, 1, F1, 1, M1.data(), z1.data(), P.dtype, stream, false))) return rc;
+        const int64_t nodes1 = (int64_t)F1 * K;
+        if ((rc = fbuf.need(nodes1 * esz)) || (rc = gbuf.need(nodes1 * esz)) || (rc = n_det.need(F1)) ||
+            (rc = det_idx.need(nodes1)) || (rc = det_coef.need(nodes1 * esz)) || (rc = n_o.need(F1)) ||
+            (rc = out_idx.need((int64_t)F1 * P.s_local)) || (rc = out_coef.need((int64_t)F1 * P.s_local * esz)))
+            return rc;
+        if ((rc = mr1l_sample(p1.p, d, dtoff.p, T1, drf.p, drc.p, danc1.p, fbuf.p, 1))) return rc;
+        if ((rc = mr1l_fft(p1.p, fbuf.p, gbuf.p, P.theta, nullptr))) return rc;
+        const dim3 gg((unsigned)std::min<int64_t>((K + 255) / 256, 64), (unsigned)F1);
+        if (P.dtype == MR1L_C128)
+            hipLaunchKernelGGL(k_line_gather<double>, gg, dim3(256), 0, st, F1, K, P.N, (const double2 *)gbuf.p,
+                               det_idx.p, (double2 *)det_coef.p, n_det.p);
+        else
+            hipLaunchKernelGGL(k_line_gather<float>, gg, dim3(256), 0, st, F1, K, P.N, (const float2 *)gbuf.p,
+                               det_idx.p, (float2 *)det_coef.p, n_det.p);
+        MR1L_LAUNCH_CHECK();
+        if ((rc = limit_run(plan_of(p1.p), n_det.p, K, det_idx.p, det_coef.p, P.theta, P.s_local, n_o.p, out_idx.p,
+                            out_coef.p)))
+            return rc;
+        std::vector<int64_t> hn(F1), hi((size_t)F1 * P.s_local);
+        MR1L_HIP(hipMemcpyAsync(hn.data(), n_o.p, F1 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        MR1L_HIP(hipMemcpyAsync(hi.data(), out_idx.p, hi.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        MR1L_HIP(hipStreamSynchronize(st));
+        samples += nodes1;
+        for (int t = 0; t < d; ++t) {
+            std::vector<char> in(K, 0);
+            for (int i = 0; i < P.r; ++i) {
+                const int f = t * P.r + i;
+                for (int64_t q = 0; q < hn[f]; ++q) in[hi[(size_t)f * P.s_local + q]] = 1;
+            }
+            for (int64_t a = 0; a < K; ++a)
+                if (in[a]) I1[t].push_back(a - P.N);
+        }
+    }
+
+    // I^(1), row-major tuples
+    std::vector<int64_t> prev = I1[0];
+    int64_t nprev = (int64_t)prev.size();
+    if (nprev == 0) {
+        if (total_samples) *total_samples = samples;
+        return MR1L_OK;   // nothing detected: the result is empty
+    }
 
     for (int t = 2; t <= d; ++t) {
         const int rt = (t < d) ? P.r : 1;
         const int64_t s_t = (t < d) ? P.s_local : P.s;
-        const int64_t nJ = nprev * K;
+        const std::vector<int64_t> &It = I1[t - 1];
+        const int64_t Kt = (int64_t)It.size();
+        const int64_t nJ = nprev * Kt;
+        if (nJ == 0) {
+            *n_out = 0;
+            if (total_samples) *total_samples = samples;
+            return MR1L_OK;
+        }
         const int32_t L = mr1l_num_lattices(nJ, P.c, P.delta);
         if (L < 1 || L > kMaxL) return fail(MR1L_E_ARG, "eq. (4.2) lattice count out of range");
-        int rc;
         // previous tuples as SoA [t-1][nprev]
         std::vector<int64_t> soa((size_t)(t - 1) * nprev);
         for (int64_t a = 0; a < nprev; ++a)
@@ -114,7 +231,10 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
         MR1L_HIP(hipMemcpyAsync(dprev.p, soa.data(), soa.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
         if ((rc = dJ.need(nJ * t))) return rc;
         const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((nJ + 255) / 256, 4096));
-        hipLaunchKernelGGL(k_cartesian, dim3((unsigned)blocks), dim3(256), 0, st, dprev.p, nprev, t - 1, P.N, dJ.p);
+        if ((rc = dset.need(Kt))) return rc;
+        MR1L_HIP(hipMemcpyAsync(dset.p, It.data(), Kt * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_cartesian, dim3((unsigned)blocks), dim3(256), 0, st, dprev.p, nprev, t - 1, dset.p, Kt,
+                           dJ.p);
         MR1L_LAUNCH_CHECK();
 
         std::vector<int64_t> Ms(L, P.M);
@@ -169,9 +289,9 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
                 MR1L_HIP(hipMemcpy(oc.data(), out_coef.p, h_nout * esz, hipMemcpyDeviceToHost));
             }
             for (int64_t q = 0; q < h_nout; ++q) {
-                const int64_t a = oi[q] / K, b = oi[q] - a * K;
+                const int64_t a = oi[q] / Kt, b = oi[q] - a * Kt;
                 for (int u = 0; u < t - 1; ++u) cur.push_back(prev[(size_t)a * (t - 1) + u]);
-                cur.push_back(b - P.N);
+                cur.push_back(It[b]);
             }
             if (t == d) cur_coef = oc;
             if ((int64_t)(cur.size() / t) > cap) return fail(MR1L_E_CAPACITY, "union exceeds cap");

@@ -400,6 +400,25 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     return MR1L_OK;
 }
 
+// Algorithm 4 alone over given lists (det_idx [F][cap] in candidate order,
+// det_coef [F][cap], n_det [F] on the device).
+int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef, double theta,
+              int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef)
+{
+    if (cap < 1 || cap > kMaxCap) return fail(MR1L_E_ARG, "capacity must be in [1, 8192]");
+    const size_t pc = (size_t)pow2ceil(cap);
+    if (p.dtype == MR1L_C128)
+        hipLaunchKernelGGL(k_limit<double>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, n_det, cap, det_idx,
+                           (const double2 *)det_coef, theta * theta, s_cap, n_out, out_idx, (double2 *)out_coef,
+                           (int32_t *)nullptr);
+    else
+        hipLaunchKernelGGL(k_limit<float>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, n_det, cap, det_idx,
+                           (const float2 *)det_coef, (float)(theta * theta), s_cap, n_out, out_idx,
+                           (float2 *)out_coef, (int32_t *)nullptr);
+    MR1L_LAUNCH_CHECK();
+    return MR1L_OK;
+}
+
 int adjoint_run(Plan &p, int64_t cap, int64_t s_cap, const int64_t *n_out, const int32_t *out_pos,
                 const int32_t *det_hash, const double *det_w, const void *grad_out, void *grad_f)
 {

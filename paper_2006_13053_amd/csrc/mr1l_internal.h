@@ -221,6 +221,11 @@ int fft_apply_schedules(Plan &p);
 int tuned_schedule(int32_t dtype, int64_t M);
 MDesc fft_layout(const Plan &p, int mid, int s);   // table entry of size mid under schedule s
 int fft_time_plan(Plan &p, const void *in, void *out, int reps, float *ms);   // whole-plan forward DFT
+Plan &plan_of(mr1l_plan p);   // the plan behind an ABI handle
+int plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int64_t *M, const int64_t *z,
+                     int32_t dtype, void *stream, bool need_prime);
+int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef, double theta,
+              int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef);
 int check_injective_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, int32_t *ok);
 int fft_init_attrs();
 int extract_init_attrs();

@@ -643,19 +643,39 @@ def test_dimincr_matches_oracle_driver(m, seed):
     assert [tuple(r) for r in gf.tolist()] == [t[0] for t in truth]
 
 
-def test_dimincr_full_size_matches_oracle_and_truth(m):
+@pytest.mark.parametrize("d,s,N", [(4, 8, 60), (6, 12, 6)])
+def test_dimincr_step1_matches_oracle_driver(m, d, s, N):
+    """Algorithm 3 with Step 1: same single-coordinate sets, lattices and output as the
+    oracle driver, and the true support."""
+    say("dimincr step1", d, s, N)
+    freq, coef = synth.sparse_poly_box(5, d=d, s=s, box=N)
+    Mlat = synth.next_prime_above(10.33 * 2 * s)
+    of, oc, ns = oracle.dimincr(freq, coef, N=N, s=s, s_local=2 * s, r=2, theta=1e-12, c=10.33, delta=0.9,
+                                Mlat=Mlat, seed=91, step1=True)
+    gf, gc, gs = m.mr1l_dimincr(d, N, s, 2 * s, 2, 1e-12, Mlat, 91, poly_freq=T(freq), poly_coef=T(coef),
+                                step1=True)
+    assert ns == gs
+    assert np.array_equal(gf, of)
+    close(gc, oc, 1e-11, "driver coefficients")
+    truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
+    assert [tuple(r) for r in gf.tolist()] == [t[0] for t in truth]
+
+
+@pytest.mark.parametrize("step1", [False, True])
+def test_dimincr_full_size_matches_oracle_and_truth(m, step1):
     """The dimension-incremental workload at full size: d = 25, s = 200 frequencies
-    uniform in [-32, 32]^25, r = 5, s_local = 400, M = 4133, theta = 1e-12.  The
-    driver's result equals the oracle driver's (same lattices from the same
-    SplitMix64 streams), recovers the support exactly, and its coefficients are
-    exact to 1e-11 (relative l2)."""
+    uniform in [-32, 32]^25, r = 5, s_local = 400, M = 4133, theta = 1e-12, with the
+    full single-coordinate range or with Step 1.  The driver's result equals the oracle
+    driver's (same lattices from the same SplitMix64 streams), recovers the support
+    exactly, and its coefficients are exact to 1e-11 (relative l2)."""
     d, s, N, r, Mlat, seed = 25, 200, 32, 5, 4133, 1000
     freq, coef = synth.sparse_poly_box(0, d=d, s=s, box=N)
-    say("dimincr full size: oracle")
+    say("dimincr full size: oracle", step1)
     of, oc, ns = oracle.dimincr(freq, coef, N=N, s=s, s_local=2 * s, r=r, theta=1e-12, c=10.33, delta=0.9,
-                                Mlat=Mlat, seed=seed)
-    say("dimincr full size: gpu")
-    gf, gc, gs = m.mr1l_dimincr(d, N, s, 2 * s, r, 1e-12, Mlat, seed, poly_freq=T(freq), poly_coef=T(coef))
+                                Mlat=Mlat, seed=seed, step1=step1)
+    say("dimincr full size: gpu", step1)
+    gf, gc, gs = m.mr1l_dimincr(d, N, s, 2 * s, r, 1e-12, Mlat, seed, poly_freq=T(freq), poly_coef=T(coef),
+                                step1=step1)
     assert gs == ns
     assert np.array_equal(gf, of)
     close(gc, oc, 1e-11, "driver coefficients")

@@ -36,7 +36,9 @@ MUTANTS = {
     "eq42_factor": ("double bound = 0.25 *", "double bound = 0.5 *"),
     "bucket_sum_conjugate": ("acc[2 * h + 1] += (ld)coef[2 * i + 1];", "acc[2 * h + 1] -= (ld)coef[2 * i + 1];"),
     "threshold_not_squared": ("return m2 >= theta * theta;", "return m2 >= theta;"),
-    "driver_range": ("J[(int64_t)(t - 1) * nJ + q] = b - N;", "J[(int64_t)(t - 1) * nJ + q] = b - N + 1;"),
+    "driver_range": ("I1[(int64_t)(t - 1) * K + a] = a - N;", "I1[(int64_t)(t - 1) * K + a] = a - N + 1;"),
+    "step1_threshold": ("if (m2 >= theta * theta) { keys[nk].m2", "if (m2 < theta * theta) { keys[nk].m2"),
+    "step1_coordinate": ("pf[q] = poly_freq[(int64_t)(t - 1) * s_poly + q];", "pf[q] = poly_freq[(int64_t)t % d * s_poly + q];"),
     "median_weight_even": ("wq[2 * vs[L / 2].l + part] = 1.0;", "wq[2 * vs[0].l + part] = 1.0;"),
 }
 

@@ -401,6 +401,26 @@ def test_dimincr_recovers_random_sparse_polynomial(seed):
     assert nsamp > 0
 
 
+@pytest.mark.parametrize("d,s,N", [(4, 8, 60), (5, 10, 6)])
+def test_dimincr_with_step1_recovers_sparse_polynomial(d, s, N):
+    """Algorithm 3 with Step 1 (single-coordinate detection on one-dimensional grids of
+    size 2N + 1 with random anchors): the sets I^(t) and then the support are recovered and
+    the coefficients are exact to rounding; with N = 60 Step 1 narrows each coordinate
+    from 121 values to at most s."""
+    freq, coef = synth.sparse_poly_box(5, d=d, s=s, box=N)
+    out_f, out_c, nsamp = oracle.dimincr(freq, coef, N=N, s=s, s_local=2 * s, r=2,
+                                         theta=1e-12, c=10.33, delta=0.9,
+                                         Mlat=synth.next_prime_above(10.33 * 2 * s), seed=91, step1=True)
+    truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
+    assert [tuple(r) for r in out_f.tolist()] == [t[0] for t in truth]
+    err = np.linalg.norm(out_c - np.array([t[1] for t in truth])) / np.linalg.norm(coef)
+    assert err < 1e-13
+    # Step 1 samples: d coordinates x r repetitions x (2N + 1) nodes on top of Step 2's
+    _, _, nfull = oracle.dimincr(freq, coef, N=N, s=s, s_local=2 * s, r=2, theta=1e-12, c=10.33,
+                                 delta=0.9, Mlat=synth.next_prime_above(10.33 * 2 * s), seed=91)
+    assert nsamp != nfull and nsamp > d * 2 * (2 * N + 1)
+
+
 def test_threshold_boundary_is_inclusive_on_modulus():
     """Remark 2.3 / Algorithm 4: a bucket counts as non-zero iff |ghat| >= theta, and the
     output keeps |p| >= theta.  Buckets are set directly around the boundary."""
