@@ -258,6 +258,195 @@ def bench_dimincr(m, torch, args):
     print(json.dumps(out), flush=True)
 
 
+# ----------------------------------------------------------------------------- worst case (Section 4.1)
+RANDOM_3D = dict(d=3, box=1000, n_gamma=10_000_000, n_active=1000, M=10331)
+CROSS_8D = dict(d=8, bound=32, weight_exp=1.08, M=11047)
+L_RANGE = tuple(range(9, 38, 2))
+
+
+def _event_timer(torch):
+    class T:
+        def __init__(self):
+            self.ms = 0.0
+
+        def __enter__(self):
+            self.a = torch.cuda.Event(enable_timing=True)
+            self.b = torch.cuda.Event(enable_timing=True)
+            self.a.record()
+            return self
+
+        def __exit__(self, *e):
+            self.b.record()
+            self.b.synchronize()
+            self.ms += self.a.elapsed_time(self.b)
+    return T()
+
+
+def _add_stages(acc, plan):
+    for k, (ms, cnt) in plan.profile_read().items():
+        a = acc.setdefault(k, [0.0, 0])
+        a[0] += ms
+        a[1] += cnt
+
+
+def worst_case_random_3d(m, torch, Ls=L_RANGE, reps=1000, batch=16, seed=41, n_gamma=None, cfg=RANDOM_3D,
+                         stages=None):
+    """Section 4.1.2: Gamma of n_gamma distinct points uniform in [-1000, 1000]^3 and I
+    of 1000 points uniform in Gamma, new for each repetition (the same draw serves all
+    L); for each L one random lattice configuration of size M = 10331, fixed over the
+    repetitions.  Returns ({L: counts int64 [reps, 4]}, generation ms, method ms)."""
+    import synth.counter as sc
+    from paper_2006_13053_amd import worst_case as wc
+    dev = torch.device("cuda", 0)
+    d, box, na, M = cfg["d"], cfg["box"], cfg["n_active"], cfg["M"]
+    n = n_gamma or cfg["n_gamma"]
+    rng = np.random.default_rng(seed)
+    runs = {L: wc.CountingRun(d, batch, L, M, np.tile(rng.integers(0, M, size=(L, d)), (batch, 1)),
+                              profile=stages is not None) for L in Ls}
+    set_off = torch.arange(batch + 1, dtype=torch.int64, device=dev) * n
+    term_off = torch.arange(batch + 1, dtype=torch.int64, device=dev) * na
+    n_act = torch.full((batch,), na, dtype=torch.int64, device=dev)
+    cand = torch.empty((d, batch * n), dtype=torch.int64, device=dev)
+    out = {L: [] for L in Ls}
+    t_gen, t_run = _event_timer(torch), _event_timer(torch)
+    nb = (reps + batch - 1) // batch
+    for b in range(nb):
+        with t_gen:
+            for f in range(batch):
+                rep = b * batch + f
+                cand[:, f * n:(f + 1) * n] = sc.distinct_grid_points(seed * 1_000_003 + rep, n, d, box, device=dev)
+            terms = cand.view(d, batch, n)[:, :, :na].reshape(d, batch * na).contiguous()
+        with t_run:
+            for L in Ls:
+                out[L].append(runs[L].run(cand, set_off, n_act, terms, term_off).clone())
+        if b % 8 == 7 or b == nb - 1:
+            log(f"random 3d: {min(reps, (b + 1) * batch)}/{reps} repetitions")
+    for r in runs.values():
+        if stages is not None:
+            _add_stages(stages, r.plan)
+        r.close()
+    res = {L: torch.cat(v).cpu().numpy()[:reps] for L, v in out.items()}
+    return res, t_gen.ms, t_run.ms
+
+
+def cross_8d_set(cfg=CROSS_8D):
+    """Section 4.1.3: the unweighted hyperbolic cross Gamma (d = 8, bound 32) with the
+    weighted cross I (weights t^1.08) listed first -> (Gamma [8, n] int64, |I|)."""
+    import synth
+    g = synth.hyperbolic_cross(cfg["d"], cfg["bound"])
+    return synth.support_first(g, synth.weighted_cross_member(g, cfg["bound"], cfg["weight_exp"]))
+
+
+def worst_case_cross_8d(m, torch, Ls=L_RANGE, reps=1000, batch=8, seed=43, cfg=CROSS_8D, gamma=None,
+                        stages=None):
+    """Section 4.1.3: Gamma and I fixed, a new random lattice configuration of size
+    M = 11047 for every repetition.  Returns ({L: counts [reps, 4]}, setup ms, method ms)."""
+    from paper_2006_13053_amd import worst_case as wc
+    dev = torch.device("cuda", 0)
+    d, M = cfg["d"], cfg["M"]
+    t_gen, t_run = _event_timer(torch), _event_timer(torch)
+    with t_gen:
+        g, na = gamma if gamma is not None else cross_8d_set(cfg)
+        n = g.shape[1]
+        g = torch.from_numpy(g).to(dev)
+        cand = g.repeat(1, batch)
+        terms = g[:, :na].repeat(1, batch)
+        del g
+    set_off = torch.arange(batch + 1, dtype=torch.int64, device=dev) * n
+    term_off = torch.arange(batch + 1, dtype=torch.int64, device=dev) * na
+    n_act = torch.full((batch,), na, dtype=torch.int64, device=dev)
+    rng = np.random.default_rng(seed)
+    out = {L: [] for L in Ls}
+    nb = (reps + batch - 1) // batch
+    for L in Ls:
+        run = wc.CountingRun(d, batch, L, M, rng.integers(0, M, size=(batch * L, d)), profile=stages is not None)
+        with t_run:
+            for b in range(nb):
+                if b:
+                    run.set_z(rng.integers(0, M, size=(batch * L, d)))
+                out[L].append(run.run(cand, set_off, n_act, terms, term_off).clone())
+        if stages is not None:
+            _add_stages(stages, run.plan)
+        run.close()
+        log(f"cross 8d: L = {L} done")
+    del cand, terms
+    res = {L: torch.cat(v).cpu().numpy()[:reps] for L, v in out.items()}
+    return res, t_gen.ms, t_run.ms
+
+
+def bench_worst_case(m, torch, args):
+    """Both experiments of Section 4.1 over L = 9, 11, ..., 37 with args.reps repetitions;
+    success rates next to the printed ones, and the classification throughput."""
+    from paper_2006_13053_amd import worst_case as wc
+    gold = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "worst_case_success_rates.json")
+    if os.path.exists(gpath):
+        with open(gpath) as fh:
+            gold = json.load(fh)
+    exps, cl, run_ms, gen_ms, stages, vote_bytes = {}, 0.0, 0.0, 0.0, {}, 0.0
+    todo = ("random_3d", "hyperbolic_cross_8d") if args.experiment == "both" else (args.experiment,)
+    for name in todo:
+        st = {}
+        if name == "random_3d":
+            res, g_ms, r_ms = worst_case_random_3d(m, torch, reps=args.reps, batch=16, stages=st)
+            n_gamma, na, M, c, d, batch = RANDOM_3D["n_gamma"], RANDOM_3D["n_active"], RANDOM_3D["M"], 10.33, 3, 16
+        else:
+            res, g_ms, r_ms = worst_case_cross_8d(m, torch, reps=args.reps, batch=8, stages=st)
+            n_gamma, na, M, c, d, batch = 10_665_297, 1069, CROSS_8D["M"], 10.33, 8, 8
+        table = {}
+        for L in sorted(res):
+            sm = wc.summarize(res[L])
+            sm["cor27_failure_bound"] = round(wc.cor27_failure_bound(n_gamma, c, L), 6)
+            g = gold.get(name, {})
+            sm["paper"] = {k: g[k][str(L)] for k in ("median", "median_r1l", "pfp_le10", "pfp_le100",
+                                                      "max_pfn", "max_pfp") if str(L) in g.get(k, {})}
+            table[str(L)] = sm
+            cl += float(args.reps) * n_gamma * L
+        exps[name] = {"reps": args.reps, "n_gamma": n_gamma, "n_active": na, "M": M, "method_ms": r_ms,
+                      "input_ms": g_ms, "by_L": table}
+        run_ms += r_ms
+        gen_ms += g_ms
+        vb = batch * n_gamma * d * 8.0
+        for k, (ms, cnt) in st.items():
+            a = stages.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += cnt
+        vote_bytes += vb * st.get("vote", (0.0, 0))[1]
+        log(name, f"method {r_ms:.0f} ms, inputs {g_ms:.0f} ms")
+    vote_ms, vote_n = stages.get("vote", (0.0, 0))
+    roof = None
+    if vote_n:
+        ach = vote_bytes / (vote_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None, "kernel": "k_vote", "launches": vote_n,
+                "bytes_per_launch_note": "candidates x d x 8 bytes of one batched launch (average over both "
+                                         "experiments' launches)"}
+    out = {"metric": "worst-case classifications (candidates x lattices) per second", "value": cl / (run_ms / 1e3),
+           "unit": "candidate-lattices/s", "n_gpus": 1, "steps": args.reps, "warmup": 0,
+           "ms_per_step": run_ms / (args.reps * len(todo)), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+           "config": {"workload": "worst-case aliasing of Section 4.1 (Table 4.1): random Gamma of 1e7 points "
+                                  "in [-1000,1000]^3 with |I| = 1000, M = 10331; 8-d hyperbolic cross "
+                                  "(10,665,297) with the weighted cross I (1069), M = 11047; L = 9..37 odd; "
+                                  "one step = one repetition over all L", "experiments": list(todo)},
+           "stage_ms": {k: v[0] for k, v in stages.items()}, "input_generation_ms": gen_ms,
+           "experiments": exps, "roofline": roof}
+    if not args.no_cpu:
+        import oracle
+        import synth.counter as sc
+        L = 21
+        g = sc.distinct_grid_points(12345, RANDOM_3D["n_gamma"], 3, RANDOM_3D["box"]).numpy()
+        z = np.random.default_rng(1).integers(0, RANDOM_3D["M"], size=(L, 3))
+        t0 = time.perf_counter()
+        oracle.pfpn(g, RANDOM_3D["n_active"], np.full(L, RANDOM_3D["M"]), z)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": RANDOM_3D["n_gamma"] * L / dt, "unit": "candidate-lattices/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"one repetition of the random 3-d experiment at L = {L} "
+                                         f"(1e7 candidates), classification by direct alias counting: {dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 # ----------------------------------------------------------------------------- oracle legs
 def cpu_baseline_large(w, n_sample, budget_s=10.0):
     """Oracle on one function of the batch, repeated until ~budget_s of CPU time: direct
@@ -321,7 +510,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("large", "batch", "dimincr"), default="large")
+    ap.add_argument("--workload", choices=("large", "batch", "dimincr", "worst-case"), default="large")
+    ap.add_argument("--reps", type=int, default=1000, help="worst-case workload: repetitions per L")
+    ap.add_argument("--experiment", choices=("both", "random_3d", "hyperbolic_cross_8d"), default="both",
+                    help="worst-case workload: which experiment of Section 4.1")
     ap.add_argument("--functions", type=int, default=None)
     ap.add_argument("--candidates", type=int, default=10_000_000)
     ap.add_argument("--c64", action="store_true")
@@ -352,6 +544,8 @@ def main():
     m.lib()
     if args.workload == "dimincr":
         return bench_dimincr(m, torch, args)
+    if args.workload == "worst-case":
+        return bench_worst_case(m, torch, args)
 
     if args.workload == "large":
         F = args.functions or 64

@@ -75,7 +75,8 @@ const char *mr1l_last_error(void);
 
 /*
  * Create a plan for F functions of d lattice dimensions with L lattices each
- * (the multiple rank-1 lattice configuration of Section 2.1).
+ * (the multiple rank-1 lattice configuration of Section 2.1); 1 <= d <= 64,
+ * F >= 1, 1 <= L <= 64.
  *   M     host [F*L]   lattice sizes; each must be a prime (checked with a
  *                      deterministic Miller-Rabin test) with 2 <= M < 2^23.
  *   z     host [F*L*d] generating vectors, 0 <= z < M (checked).
@@ -161,14 +162,16 @@ typedef struct {
 
 /* Outputs of mr1l_extract (all dev; optional ones may be NULL). */
 typedef struct {
-    int64_t *n_det;     /* [F] |detected set| (may exceed cap: then only cap
-                           entries are kept and the call's later stages see
-                           the first cap in ascending order)               */
+    int64_t *n_det;     /* [F] |detected set| (may exceed cap: then cap of
+                           the detected candidates, a subset that depends
+                           on the order of the vote pass, are kept, sorted
+                           ascending, and the later stages see only them)  */
     int64_t *det_idx;   /* [F][cap] detected candidates, ascending          */
     void *det_coef;     /* [F][cap] coefficient: singleton average, else
                            median (postproc = 1); median (postproc = 0)    */
     void *det_med;      /* [F][cap] median coefficient, eq. (2.10) | NULL   */
-    uint32_t *det_mask; /* [F][cap] bit l set iff the candidate is alone
+    uint32_t *det_mask; /* [F][cap][W], W = ceil(L/32) words: bit l % 32 of
+                           word l / 32 set iff the candidate is alone
                            among the detected set in its bucket of lattice
                            l (Remark 2.9) | NULL                           */
     int32_t *det_hash;  /* [F][cap][L] buckets of the detected set | NULL   */
@@ -247,6 +250,34 @@ int mr1l_graph_destroy(mr1l_graph g);
  */
 int mr1l_check_injective(mr1l_plan p, int64_t n_total, const int64_t *set_off,
                          const int64_t *freq, int32_t *ok);
+
+/*
+ * Worst-case aliasing counts of Section 4.1.1 (Table 4.1).  Run mr1l_sample,
+ * mr1l_fft and mr1l_extract (Remark 2.9 post-processing on, vote_min 0) on the
+ * counting polynomial of eq. (4.1), all-ones coefficients on the support I,
+ * over candidate sets that list I first: candidates [0, n_active[f]) of
+ * function f are I, the rest are Gamma \ I.  Every lattice value at a bucket
+ * of k then counts the members of I in that bucket, and per function
+ *   counts[4f+0] = #PFP: candidates outside I that are detected
+ *                  (n_det - n_active, exact also beyond cap),
+ *   counts[4f+1] = #PFN: members of I whose median (eq. (2.10)) exceeds 1,
+ *   counts[4f+2] = #PFP left after Remark 2.9: detected candidates outside I
+ *                  whose post-processed coefficient keeps |p| >= theta,
+ *   counts[4f+3] = flags: bit 0 the detected list was truncated (n_det > cap;
+ *                  counts[4f+1] and counts[4f+2] then cover the kept
+ *                  entries only); bit 1 I was not detected whole in front
+ *                  of a complete list, or |I| > cap (a threshold outside
+ *                  (0, 1) or a set not listing I first).
+ *   cap, n_det, det_idx, det_med, det_coef  the extract call's cap and dev
+ *            outputs (det_med required); n_active dev int64 [F];
+ *   theta    the extract call's threshold; counts dev int64 [F][4].
+ * Asynchronous on the plan's stream; MR1L_E_ARG for NULL buffers or an
+ * invalid cap.
+ */
+int mr1l_pfpn_count(mr1l_plan p, int64_t cap, const int64_t *n_active,
+                    const int64_t *n_det, const int64_t *det_idx,
+                    const void *det_med, const void *det_coef, double theta,
+                    int64_t *counts);
 
 /*
  * DFT schedules and their autotuner.  The lattice DFT of one size M runs under

@@ -77,6 +77,7 @@ def _declare(L):
     L.orc_dimincr.argtypes = [_i32, _i64, _i64, _p, _p, _i64, _i64, _i32, _d, _d, _d, _i64,
                               _i32, _u64, _i64, _i32, _p, _p, _p]
     L.orc_dimincr.restype = _i64
+    L.orc_pfpn.argtypes = [_i32, _i64, _p, _i64, _i32, _p, _p, _p]
 
 
 def _ptr(a):
@@ -189,7 +190,7 @@ def extract(freq, M, z, ghat, theta, s_cap, vote_min=None, postproc=True, cap=No
     votes = np.zeros(n, np.uint8)
     det_idx = np.zeros(max(cap, 1), np.int64)
     det_med = np.zeros(2 * max(cap, 1), np.float64)
-    det_mask = np.zeros(max(cap, 1), np.uint32)
+    det_mask = np.zeros(max(cap, 1), np.uint64)
     det_coef = np.zeros(2 * max(cap, 1), np.float64)
     sc = max(int(s_cap), 1)
     out_idx = np.zeros(sc, np.int64)
@@ -213,7 +214,7 @@ def weights(freq, M, z, ghat, det_idx, det_mask, postproc=True):
     freq, M, z = _c(freq, np.int64), _c(M, np.int64), _c(z, np.int64)
     d, n = freq.shape
     L = M.shape[0]
-    di, dm = _c(det_idx, np.int64), _c(det_mask, np.uint32)
+    di, dm = _c(det_idx, np.int64), _c(det_mask, np.uint64)
     nd = di.shape[0]
     w = np.zeros((max(nd, 1), L, 2), np.float64)
     lib().orc_weights(d, n, _ptr(freq), L, _ptr(M), _ptr(z), _ptr(_cplx(ghat)), nd, _ptr(di),
@@ -263,3 +264,22 @@ def dimincr(poly_freq, poly_coef, N, s, s_local, r, theta, c, delta, Mlat, seed,
     if n < 0:
         raise RuntimeError("oracle dimincr: capacity exceeded")
     return out_f[:n], out_c.view(np.complex128)[:n], int(tot.value)
+
+
+def pfpn(freq, n_active, M, z):
+    """Table 4.1 classification for the counting polynomial eq. (4.1) with support
+    freq[:, :n_active] -> uint8 [n]: bit 0 PFP, bit 1 PFN, bit 2 PFP kept by the
+    Remark 2.9 post-processing (see the C file)."""
+    freq = _c(freq, np.int64)
+    d, n = freq.shape
+    M = _c(M, np.int64)
+    z = _c(z, np.int64).reshape(len(M), d)
+    cls = np.zeros(n, np.uint8)
+    lib().orc_pfpn(d, n, _ptr(freq), int(n_active), len(M), _ptr(M), _ptr(z), _ptr(cls))
+    return cls
+
+
+def pfpn_counts(cls):
+    """(#PFP, #PFN, #PFP kept by post-processing) of a pfpn classification."""
+    cls = np.asarray(cls)
+    return int(((cls & 1) != 0).sum()), int(((cls & 2) != 0).sum()), int(((cls & 4) != 0).sum())

@@ -336,7 +336,7 @@ int64_t orc_extract(int32_t d, int64_t n, const int64_t *freq, int32_t L,
                     double theta, int32_t vote_min, int32_t postproc,
                     int64_t s_cap, int64_t cap,
                     uint8_t *votes, int64_t *det_idx, double *det_med,
-                    uint32_t *det_mask, double *det_coef,
+                    uint64_t *det_mask, double *det_coef,
                     int64_t *n_out, int64_t *out_idx, double *out_coef,
                     int64_t *out_pos)
 {
@@ -387,12 +387,12 @@ int64_t orc_extract(int32_t d, int64_t n, const int64_t *freq, int32_t L,
     for (int64_t q = 0; q < nd; ++q)
         for (int32_t l = 0; l < L; ++l) cnt[off[l] + hh[q * L + l]]++;
     for (int64_t q = 0; q < nd; ++q) {
-        uint32_t mask = 0;
+        uint64_t mask = 0;
         ld sr = 0.0L, si = 0.0L;
         int32_t na = 0;
         for (int32_t l = 0; l < L; ++l) {
             if (cnt[off[l] + hh[q * L + l]] == 1) {
-                mask |= 1u << l;
+                mask |= 1ull << l;
                 sr += vals[(q * L + l) * 2];
                 si += vals[(q * L + l) * 2 + 1];
                 na++;
@@ -469,7 +469,7 @@ static int cmp_vl(const void *a, const void *b)
 
 void orc_weights(int32_t d, int64_t n, const int64_t *freq, int32_t L,
                  const int64_t *M, const int64_t *z, const double *ghat,
-                 int64_t nd, const int64_t *det_idx, const uint32_t *det_mask,
+                 int64_t nd, const int64_t *det_idx, const uint64_t *det_mask,
                  int32_t postproc, double *w /* [nd][L][2] */)
 {
     int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(L + 1));
@@ -478,9 +478,9 @@ void orc_weights(int32_t d, int64_t n, const int64_t *freq, int32_t L,
     for (int64_t q = 0; q < nd; ++q) {
         double *wq = w + q * L * 2;
         for (int32_t l = 0; l < 2 * L; ++l) wq[l] = 0.0;
-        uint32_t mask = det_mask[q];
+        uint64_t mask = det_mask[q];
         int32_t na = 0;
-        for (int32_t l = 0; l < L; ++l) na += (mask >> l) & 1u;
+        for (int32_t l = 0; l < L; ++l) na += (int32_t)((mask >> l) & 1u);
         if (postproc && na > 0) {
             for (int32_t l = 0; l < L; ++l)
                 if ((mask >> l) & 1u) {
@@ -748,7 +748,7 @@ int64_t orc_dimincr(int32_t d, int64_t N, int64_t s_poly, const int64_t *poly_fr
             const int64_t cap = nJ;
             int64_t *det_idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
             double *det_med = (double *)malloc(sizeof(double) * 2 * (size_t)cap);
-            uint32_t *det_mask = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)cap);
+            uint64_t *det_mask = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)cap);
             double *det_coef = (double *)malloc(sizeof(double) * 2 * (size_t)cap);
             int64_t *out_idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(st > 0 ? st : 1));
             int64_t *out_pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(st > 0 ? st : 1));
@@ -818,4 +818,61 @@ int64_t orc_dimincr(int32_t d, int64_t N, int64_t s_poly, const int64_t *poly_fr
     free(n1);
     if (total_samples) *total_samples = samples;
     return nout_final;
+}
+
+/* ------------------------------------------------------------------ */
+/* Worst-case aliasing classification of Section 4.1.1 (Table 4.1).   */
+/* The method is applied to the counting polynomial of eq. (4.1):     */
+/* all-ones coefficients on the support I.  By the aliasing formula   */
+/* eq. (2.4) the lattice-l value at k's bucket is the number of       */
+/* members of I in that bucket; its median over the lattices          */
+/* (eq. (2.10)) classifies k:                                         */
+/*   k in I:      median > 1  ->  potential false negative (PFN);     */
+/*   k not in I:  median > 0  ->  potential false positive (PFP).     */
+/* The candidates [0, n_active) are I.  The detected set of the       */
+/* method is then I together with the PFPs.  In the post-processing   */
+/* of Remark 2.9 a PFP is removed iff some lattice puts it alone      */
+/* among the detected set in its bucket: such a bucket holds no       */
+/* member of I, so the recovered coefficient is zero.                 */
+/* cls[i]: bit 0 PFP, bit 1 PFN, bit 2 PFP kept by post-processing.   */
+/* ------------------------------------------------------------------ */
+void orc_pfpn(int32_t d, int64_t n, const int64_t *freq, int64_t n_active, int32_t L,
+              const int64_t *M, const int64_t *z, uint8_t *cls)
+{
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(L + 1));
+    off[0] = 0;
+    for (int32_t l = 0; l < L; ++l) off[l + 1] = off[l] + M[l];
+    int32_t *cnt = (int32_t *)calloc((size_t)off[L], sizeof(int32_t));
+    for (int32_t l = 0; l < L; ++l)
+        for (int64_t i = 0; i < n_active; ++i)
+            cnt[off[l] + orc_hash_one(d, freq + i, n, z + (int64_t)l * d, M[l])]++;
+#pragma omp parallel
+    {
+        double *v = (double *)malloc(sizeof(double) * (size_t)L);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            for (int32_t l = 0; l < L; ++l)
+                v[l] = (double)cnt[off[l] + orc_hash_one(d, freq + i, n, z + (int64_t)l * d, M[l])];
+            const double med = median_of(v, L);
+            cls[i] = (uint8_t)(i < n_active ? (med > 1.0 ? 2 : 0) : (med > 0.0 ? 1 : 0));
+        }
+        free(v);
+    }
+    /* occupancy by the detected set I u PFP */
+    int32_t *cd = (int32_t *)calloc((size_t)off[L], sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) {
+        if (i >= n_active && !(cls[i] & 1)) continue;
+        for (int32_t l = 0; l < L; ++l)
+            cd[off[l] + orc_hash_one(d, freq + i, n, z + (int64_t)l * d, M[l])]++;
+    }
+    for (int64_t i = n_active; i < n; ++i) {
+        if (!(cls[i] & 1)) continue;
+        int alone = 0;
+        for (int32_t l = 0; l < L && !alone; ++l)
+            alone = cd[off[l] + orc_hash_one(d, freq + i, n, z + (int64_t)l * d, M[l])] == 1;
+        if (!alone) cls[i] |= 4;
+    }
+    free(cd);
+    free(cnt);
+    free(off);
 }

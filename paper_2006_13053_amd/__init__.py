@@ -82,6 +82,7 @@ SIGNATURES = {
     "mr1l_fft_schedule_name": ([_I32], C.c_char_p),
     "mr1l_plan_fft_schedule": ([_P, _I64, _I32], C.c_int),
     "mr1l_fft_tune": ([_P, _I32, _I32, _P, _P], C.c_int),
+    "mr1l_pfpn_count": ([_P, _I64, _P, _P, _P, _P, _P, C.c_double, _P], C.c_int),
 }
 
 STAGES = ("fft", "vote", "tail", "sample")
@@ -212,6 +213,18 @@ def mr1l_check_injective(plan: Plan, freq, set_off=None):
     return rc == 0, ok.astype(bool)
 
 
+def mr1l_pfpn_count(plan: Plan, ex: "Extracted", n_active, counts=None):
+    """Per-function worst-case counts of one extract pass over the counting polynomial
+    (support listed first in each set) -> int64 [F, 4]: #PFP, #PFN, #PFP left after
+    the singleton post-processing, flags."""
+    if counts is None:
+        counts = torch.empty((plan.F, 4), dtype=torch.int64, device=_dev())
+    _check(lib().mr1l_pfpn_count(plan.handle, ex.cap, _ptr(n_active), _ptr(ex["n_det"]), _ptr(ex["det_idx"]),
+                                 _ptr(ex["det_med"]), _ptr(ex["det_coef"]), float(ex.theta), _ptr(counts)),
+           "mr1l_pfpn_count")
+    return counts
+
+
 def fft_schedule_count() -> int:
     return int(lib().mr1l_fft_schedule_count())
 
@@ -267,7 +280,7 @@ def extract_buffers(plan: Plan, cap: int, s_cap: int, n_total: int, want_votes=F
         det_idx=torch.zeros((F, cap), dtype=torch.int64, device=dev),
         det_coef=torch.zeros((F, cap), dtype=plan.dtype, device=dev),
         det_med=torch.zeros((F, cap), dtype=plan.dtype, device=dev),
-        det_mask=torch.zeros((F, cap), dtype=torch.int32, device=dev),
+        det_mask=torch.zeros((F, cap) if L <= 32 else (F, cap, (L + 31) // 32), dtype=torch.int32, device=dev),
         det_hash=torch.zeros((F, cap, L), dtype=torch.int32, device=dev),
         det_w=torch.zeros((F, cap, L, 2), dtype=torch.float64, device=dev) if want_w else None,
         n_out=torch.zeros(F, dtype=torch.int64, device=dev),

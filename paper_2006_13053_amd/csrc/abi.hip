@@ -392,7 +392,7 @@ int mr1l::plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, cons
     *out = nullptr;
     if (d < 1 || d > kMaxD) return fail(MR1L_E_ARG, "d must be in [1, 64]");
     if (F < 1) return fail(MR1L_E_ARG, "F must be >= 1");
-    if (L < 1 || L > kMaxL) return fail(MR1L_E_ARG, "L must be in [1, 32]");
+    if (L < 1 || L > kMaxL) return fail(MR1L_E_ARG, "L must be in [1, 64]");
     if (dtype != MR1L_C128 && dtype != MR1L_C64) return fail(MR1L_E_ARG, "dtype must be MR1L_C128 or MR1L_C64");
     if (!M || !z) return fail(MR1L_E_ARG, "M or z is NULL");
     const int64_t nl = (int64_t)F * L;
@@ -558,7 +558,7 @@ int mr1l_extract(mr1l_plan p, int64_t n_total, const int64_t *set_off, const int
     int rc = MR1L_OK;
     if (!dh && (rc = grow(*p, (void **)&p->d_ex_hash, F * cap * L * 4, p->h_bytes))) return rc;
     if (!dh) dh = p->d_ex_hash;
-    if (!dm && (rc = grow(*p, (void **)&p->d_ex_mask, F * cap * 4, p->m_bytes))) return rc;
+    if (!dm && (rc = grow(*p, (void **)&p->d_ex_mask, F * cap * 4 * mask_words(p->L), p->m_bytes))) return rc;
     if (!dm) dm = p->d_ex_mask;
     if (!dpos && (rc = grow(*p, (void **)&p->d_ex_pos, F * o->s_cap * 4, p->pos_bytes))) return rc;
     if (!dpos) dpos = p->d_ex_pos;
@@ -665,6 +665,17 @@ int32_t mr1l_num_lattices(int64_t nJ, double c, double delta)
     if (L < 1) L = 1;
     if ((L & 1) == 0) ++L;
     return L;
+}
+
+int mr1l_pfpn_count(mr1l_plan p, int64_t cap, const int64_t *n_active, const int64_t *n_det, const int64_t *det_idx,
+                    const void *det_med, const void *det_coef, double theta, int64_t *counts)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (cap < 1 || cap > kMaxCap) return fail(MR1L_E_ARG, "cap must be in [1, 8192]");
+    if (!(theta >= 0.0)) return fail(MR1L_E_ARG, "theta must be >= 0");
+    if (!n_active || !n_det || !det_idx || !det_med || !det_coef || !counts)
+        return fail(MR1L_E_ARG, "null buffer");
+    return pfpn_run(*p, cap, n_active, n_det, det_idx, det_med, det_coef, theta, counts);
 }
 
 int mr1l_check_injective(mr1l_plan p, int64_t n_total, const int64_t *set_off, const int64_t *freq, int32_t *ok)

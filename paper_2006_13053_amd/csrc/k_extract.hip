@@ -131,7 +131,8 @@ __global__ __launch_bounds__(256) void k_singleton(const LatDesc *__restrict__ l
             const int h = hh[(int64_t)q * L + l];
             if (h >= c0 && h < c1) {
                 const int r = h - c0;
-                if (!((twice[r >> 5] >> (r & 31)) & 1u)) atomicOr(mask + (int64_t)f * cap + q, 1u << l);
+                if (!((twice[r >> 5] >> (r & 31)) & 1u))
+                    atomicOr(mask + ((int64_t)f * cap + q) * mask_words(L) + (l >> 5), 1u << (l & 31));
             }
         }
         __syncthreads();
@@ -169,6 +170,56 @@ __device__ __forceinline__ void median_sel(const T *v, int L, T &med, int &s0, i
     med = (L & 1) ? a : T(0.5) * (a + b);
 }
 
+// Writes the median, the post-processed coefficient (mean of the lattice values
+// over the singleton lattices of mask mk, when post-processing is on and there
+// is one) and the real weights of the coefficient as a linear map of the
+// lattice values.
+template <typename T>
+__device__ __forceinline__ void combine_store(int L, int64_t e, uint64_t mk, T mr, T mi, T sum_r, T sum_i,
+                                              int r0, int r1, int i0, int i1, int postproc,
+                                              typename cvec<T>::type *__restrict__ det_coef,
+                                              typename cvec<T>::type *__restrict__ det_med,
+                                              double *__restrict__ det_w)
+{
+    using V = typename cvec<T>::type;
+    const int na = __popcll(mk);
+    V med; med.x = mr; med.y = mi;
+    if (det_med) det_med[e] = med;
+    V out = med;
+    const bool avg = postproc && na > 0;
+    if (avg) {
+        out.x = sum_r / (T)na;
+        out.y = sum_i / (T)na;
+    }
+    det_coef[e] = out;
+    if (det_w) {
+        double *w = det_w + e * L * 2;
+        for (int l = 0; l < L; ++l) {
+            double wr = 0.0, wi = 0.0;
+            if (avg) {
+                if ((mk >> l) & 1ull) { wr = 1.0 / na; wi = 1.0 / na; }
+            } else if (L & 1) {
+                wr = (l == r0) ? 1.0 : 0.0;
+                wi = (l == i0) ? 1.0 : 0.0;
+            } else {
+                wr = 0.5 * ((l == r0) + (l == r1));
+                wi = 0.5 * ((l == i0) + (l == i1));
+            }
+            w[2 * l] = wr;
+            w[2 * l + 1] = wi;
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t load_mask(const uint32_t *__restrict__ mask, int64_t e, int L)
+{
+    const int W = mask_words(L);
+    uint64_t mk = mask[e * W];
+    if (W > 1) mk |= (uint64_t)mask[e * W + 1] << 32;
+    return mk;
+}
+
+// Up to LMAX <= 40 lattices: the values stay in registers.
 template <typename T, int LMAX>
 __global__ __launch_bounds__(256) void k_combine(
     const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ n_det, int64_t cap,
@@ -196,38 +247,58 @@ __global__ __launch_bounds__(256) void k_combine(
     int r0, r1, i0, i1;
     median_sel<T, LMAX>(vr, L, mr, r0, r1);
     median_sel<T, LMAX>(vi, L, mi, i0, i1);
-    const uint32_t mk = mask[e];
-    const int na = __popc(mk);
-    V med; med.x = mr; med.y = mi;
-    if (det_med) det_med[e] = med;
-    V out = med;
-    const bool avg = postproc && na > 0;
-    if (avg) {
-        T sr = 0, si = 0;
+    const uint64_t mk = load_mask(mask, e, L);
+    T sr = 0, si = 0;
 #pragma unroll
-        for (int l = 0; l < LMAX; ++l)
-            if (l < L && ((mk >> l) & 1u)) { sr += vr[l]; si += vi[l]; }
-        out.x = sr / (T)na;
-        out.y = si / (T)na;
+    for (int l = 0; l < LMAX; ++l)
+        if (l < L && ((mk >> l) & 1ull)) { sr += vr[l]; si += vi[l]; }
+    combine_store<T>(L, e, mk, mr, mi, sr, si, r0, r1, i0, i1, postproc, det_coef, det_med, det_w);
+}
+
+// 41..64 lattices: each lane keeps its values in its own column of an LDS array
+// ([lattice][lane], one wavefront per block) and indexes it freely; no lane reads
+// another lane's column, so no barrier is needed.  Same ranks as median_sel.
+template <typename T>
+__global__ __launch_bounds__(64) void k_combine_wide(
+    const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ n_det, int64_t cap,
+    const int32_t *__restrict__ det_hash, const uint32_t *__restrict__ mask,
+    const typename cvec<T>::type *__restrict__ ghat, int postproc,
+    typename cvec<T>::type *__restrict__ det_coef, typename cvec<T>::type *__restrict__ det_med,
+    double *__restrict__ det_w)
+{
+    using V = typename cvec<T>::type;
+    __shared__ T cr[kMaxL][64], ci[kMaxL][64];
+    const int f = blockIdx.y, t = threadIdx.x;
+    const int64_t q = blockIdx.x * (int64_t)64 + t;
+    if (q >= n_of(n_det, f, cap)) return;
+    const int64_t e = (int64_t)f * cap + q;
+    for (int l = 0; l < L; ++l) {
+        const V g = ghat[lat[f * L + l].node_off + det_hash[e * L + l]];
+        cr[l][t] = g.x;
+        ci[l][t] = g.y;
     }
-    det_coef[e] = out;
-    if (det_w) {
-        double *w = det_w + e * L * 2;
-        for (int l = 0; l < L; ++l) {
-            double wr = 0.0, wi = 0.0;
-            if (avg) {
-                if ((mk >> l) & 1u) { wr = 1.0 / na; wi = 1.0 / na; }
-            } else if (L & 1) {
-                wr = (l == r0) ? 1.0 : 0.0;
-                wi = (l == i0) ? 1.0 : 0.0;
-            } else {
-                wr = 0.5 * ((l == r0) + (l == r1));
-                wi = 0.5 * ((l == i0) + (l == i1));
-            }
-            w[2 * l] = wr;
-            w[2 * l + 1] = wi;
+    const int w0 = (L - 1) / 2, w1 = L / 2;
+    int r0 = 0, r1 = 0, i0 = 0, i1 = 0;
+    for (int l = 0; l < L; ++l) {
+        const T a = cr[l][t], b = ci[l][t];
+        int rr = 0, ri = 0;
+        for (int m = 0; m < L; ++m) {
+            const T am = cr[m][t], bm = ci[m][t];
+            rr += (am < a) || (am == a && m < l);
+            ri += (bm < b) || (bm == b && m < l);
         }
+        if (rr == w0) r0 = l;
+        if (rr == w1) r1 = l;
+        if (ri == w0) i0 = l;
+        if (ri == w1) i1 = l;
     }
+    const T mr = (L & 1) ? cr[r0][t] : T(0.5) * (cr[r0][t] + cr[r1][t]);
+    const T mi = (L & 1) ? ci[i0][t] : T(0.5) * (ci[i0][t] + ci[i1][t]);
+    const uint64_t mk = load_mask(mask, e, L);
+    T sr = 0, si = 0;
+    for (int l = 0; l < L; ++l)
+        if ((mk >> l) & 1ull) { sr += cr[l][t]; si += ci[l][t]; }
+    combine_store<T>(L, e, mk, mr, mi, sr, si, r0, r1, i0, i1, postproc, det_coef, det_med, det_w);
 }
 
 // ------------------------------------------------------------------ limit (Algorithm 4)
@@ -334,7 +405,12 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, const int3
     else if (p.L <= 16) MR1L_COMB(16);
     else if (p.L <= 20) MR1L_COMB(20);
     else if (p.L <= 24) MR1L_COMB(24);
-    else MR1L_COMB(32);
+    else if (p.L <= 32) MR1L_COMB(32);
+    else if (p.L <= 40) MR1L_COMB(40);
+    else
+        hipLaunchKernelGGL(k_combine_wide<T>, dim3((unsigned)((cap + 63) / 64), (unsigned)p.F), dim3(64), 0, p.stream,
+                           p.d_lat, p.L, n_det, cap, det_hash, mask, (const V *)ghat, postproc, (V *)det_coef,
+                           (V *)det_med, det_w);
 #undef MR1L_COMB
     MR1L_LAUNCH_CHECK();
     return MR1L_OK;
@@ -372,7 +448,7 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     hipLaunchKernelGGL(k_det_hash, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat, p.d_z32,
                        p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
     MR1L_LAUNCH_CHECK();
-    int rc = launch_fill_u32(det_mask, (int64_t)p.F * cap, 0u, p.stream);
+    int rc = launch_fill_u32(det_mask, (int64_t)p.F * cap * mask_words(p.L), 0u, p.stream);
     if (rc) return rc;
     int64_t maxM = 1;
     for (int64_t m : p.M) maxM = std::max(maxM, m);

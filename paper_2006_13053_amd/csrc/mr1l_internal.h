@@ -13,8 +13,9 @@
 namespace mr1l {
 
 // ---------------------------------------------------------------- limits
-constexpr int kMaxL = 32;          // lattices per function (masks are uint32)
+constexpr int kMaxL = 64;          // lattices per function (singleton masks: two uint32 words)
 constexpr int kMaxD = 64;          // lattice dimensions
+__host__ __device__ constexpr int mask_words(int L) { return (L + 31) >> 5; }   // uint32 words per mask
 constexpr int kMaxCap = 8192;      // detected-list capacity per function
 constexpr int kFftThreads = 1024;  // threads of a DFT workgroup
 constexpr int kLdsBytes = 163840;  // LDS of one gfx950 workgroup
@@ -227,6 +228,8 @@ int plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int6
 int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef, double theta,
               int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef);
 int check_injective_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, int32_t *ok);
+int pfpn_run(Plan &p, int64_t cap, const int64_t *n_active, const int64_t *n_det, const int64_t *det_idx,
+             const void *det_med, const void *det_coef, double theta, int64_t *counts);
 int fft_init_attrs();
 int extract_init_attrs();
 int vote_init_attrs();

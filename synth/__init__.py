@@ -182,3 +182,44 @@ def dirichlet(problem: Problem) -> Problem:
     return Problem(problem.d, problem.cand, problem.supp_idx,
                    np.ones(problem.supp_idx.shape[0], np.complex128), problem.M, problem.z,
                    theta=0.5, meta=dict(problem.meta, dirichlet=True))
+
+
+# ----------------------------------------------------------------------------- Section 4.1 sets
+def hyperbolic_cross(d: int, bound: float, weight_exp: float | None = None) -> np.ndarray:
+    """{k in Z^d : prod_t max(1, w_t |k_t|) <= bound} as SoA int64 [d, n], with
+    w_t = t^weight_exp (t = 1..d) for the weighted cross and w_t = 1 without
+    weights (the sets of Section 4.1.3).  The product is accumulated left to
+    right in float64; every factor is >= 1, so a partial product above the bound
+    can be pruned."""
+    prod = np.ones(1)
+    rows = np.zeros((1, 0), np.int64)
+    for t in range(1, d + 1):
+        w = 1.0 if weight_exp is None else float(t) ** weight_exp
+        # a superset of the admissible |k_t| per partial product, filtered exactly below
+        kmax = np.floor(bound / (prod * w)).astype(np.int64) + 1
+        nopt = 2 * kmax + 1
+        rep = np.repeat(np.arange(prod.shape[0]), nopt)
+        start = np.repeat(np.cumsum(nopt) - nopt, nopt)
+        k = np.arange(rep.shape[0], dtype=np.int64) - start - np.repeat(kmax, nopt)
+        p = prod[rep] * np.maximum(1.0, w * np.abs(k))
+        ok = p <= bound
+        rep, k, prod = rep[ok], k[ok], p[ok]
+        rows = np.concatenate([rows[rep], k[:, None]], axis=1)
+    return np.ascontiguousarray(rows.T)
+
+
+def support_first(gamma: np.ndarray, member: np.ndarray) -> tuple[np.ndarray, int]:
+    """Reorder a candidate set so that the members of the support come first (in their
+    original order) -> (reordered set, support size)."""
+    member = np.asarray(member, bool)
+    order = np.concatenate([np.nonzero(member)[0], np.nonzero(~member)[0]])
+    return np.ascontiguousarray(gamma[:, order]), int(member.sum())
+
+
+def weighted_cross_member(gamma: np.ndarray, bound: float, weight_exp: float) -> np.ndarray:
+    """Membership of the columns of gamma in the weighted hyperbolic cross (same product
+    order as hyperbolic_cross)."""
+    prod = np.ones(gamma.shape[1])
+    for t in range(1, gamma.shape[0] + 1):
+        prod = prod * np.maximum(1.0, float(t) ** weight_exp * np.abs(gamma[t - 1]))
+    return prod <= bound

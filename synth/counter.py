@@ -104,3 +104,41 @@ def dominant_phases(seed: int, func: int, count: int) -> np.ndarray:
     m = rng.integers(0, 1 << _PHASE_BITS, size=count)
     ang = 2.0 * math.pi * m.astype(np.float64) / float(1 << _PHASE_BITS)
     return np.cos(ang) + 1j * np.sin(ang)
+
+
+# ----------------------------------------------------------------------------- distinct points
+def _feistel(x: torch.Tensor, keys, h: int) -> torch.Tensor:
+    """Balanced Feistel network on 2h-bit integers (a bijection of [0, 2^(2h)))."""
+    mask = (1 << h) - 1
+    lo, hi = x & mask, _lsr(x, h) & mask
+    for k in keys:
+        lo, hi = hi ^ (splitmix64(k, lo + 1) & mask), lo
+    return (hi << h) | lo
+
+
+def distinct_grid_points(seed: int, n: int, d: int, box: int, device="cpu") -> torch.Tensor:
+    """n distinct points of {-box..box}^d, uniformly at random and in random order (so
+    the first s of them are a uniform s-subset), SoA int64 [d, n].  Point i is the
+    image of i under a keyed Feistel permutation of [0, 2^(2h)) (cycle-walked into
+    [0, (2 box + 1)^d)), written in base 2 box + 1."""
+    base = 2 * box + 1
+    D = base ** d
+    if n > D:
+        raise ValueError("more points than the grid holds")
+    h = 1
+    while (1 << (2 * h)) < D:
+        h += 1
+    if 2 * h > 62:
+        raise ValueError("grid too large for the 62-bit permutation")
+    keys = [splitmix64_py(seed, 1000 + r) & ((1 << 63) - 1) for r in range(4)]
+    y = _feistel(torch.arange(n, dtype=torch.int64, device=device), keys, h)
+    idx = torch.nonzero(y >= D).squeeze(1)
+    while idx.numel():   # cycle-walking: iterate the permutation until the value is in range
+        v = _feistel(y[idx], keys, h)
+        y[idx] = v
+        idx = idx[v >= D]
+    rows = []
+    for _ in range(d):
+        rows.append(y % base - box)
+        y = y // base
+    return torch.stack(rows[::-1])

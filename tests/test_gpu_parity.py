@@ -278,6 +278,12 @@ def test_sample_with_anchors(m):
 
 
 # ------------------------------------------------------------------ full pass
+def mask64(dm):
+    """Singleton masks ([n] or [n][2] uint32 words) as uint64 values."""
+    w = dm.cpu().numpy().view(np.uint32).astype(np.uint64)
+    return w if w.ndim == 1 else w[:, 0] | (w[:, 1] << np.uint64(32))
+
+
 def gpu_pass(m, p, f_np=None, dtype=torch.complex128, s_cap=None, cap=4096, postproc=True, vote_min=0,
              want_votes=True):
     plan = m.Plan(p.d, p.M, p.z, dtype=dtype)
@@ -294,7 +300,7 @@ def gpu_pass(m, p, f_np=None, dtype=torch.complex128, s_cap=None, cap=4096, post
     k = min(nd, cap)
     no = int(ex["n_out"][0])
     r = dict(n_det=nd, ghat=g.cpu().numpy(), bitmap=unpack_bits(bm.cpu().numpy(), plan.nodes),
-             det_idx=ex["det_idx"][0, :k].cpu().numpy(), det_mask=ex["det_mask"][0, :k].cpu().numpy().view(np.uint32),
+             det_idx=ex["det_idx"][0, :k].cpu().numpy(), det_mask=mask64(ex["det_mask"][0, :k]),
              det_coef=ex["det_coef"][0, :k].cpu().numpy(), det_med=ex["det_med"][0, :k].cpu().numpy(),
              out_idx=ex["out_idx"][0, :no].cpu().numpy(), out_coef=ex["out_coef"][0, :no].cpu().numpy(),
              out_pos=ex["out_pos"][0, :no].cpu().numpy())
@@ -319,6 +325,25 @@ def compare_pass(r, ro, go, theta, tol, s_cap, eps=EPS[torch.complex128]):
     check_limit(r, ro, eps, tol)
     # out_pos points into the detected list at the output's candidate
     assert np.array_equal(r["det_idx"][r["out_pos"]], r["out_idx"])
+
+
+@pytest.mark.parametrize("L,seed", [(33, 1), (37, 2), (40, 3), (48, 4), (64, 5)])
+def test_full_pass_beyond_32_lattices(m, L, seed):
+    """More than 32 lattices per function: two-word singleton masks, wider median
+    selection (odd and even L); plus the Dirichlet counts of eq. (4.1)."""
+    say("full pass L", L, "seed", seed)
+    p = synth.small_config(seed, L=L, mlo=200, mhi=900)
+    r, *_ = gpu_pass(m, p, s_cap=40, cap=2000)
+    fo = oracle.sample(p.supp, p.coef, p.M, p.z)
+    go = oracle.dft(fo, p.M)
+    ro = oracle.extract(p.cand, p.M, p.z, go, p.theta, s_cap=40, cap=2000)
+    compare_pass(r, ro, go, p.theta, 1e-11, 40)
+    pd = synth.dirichlet(synth.small_config(seed, L=L, mlo=31, mhi=400))
+    r, *_ = gpu_pass(m, pd, s_cap=2000, cap=2000)
+    god = oracle.dft(oracle.sample(pd.supp, pd.coef, pd.M, pd.z), pd.M)
+    rod = oracle.extract(pd.cand, pd.M, pd.z, god, pd.theta, s_cap=2000, cap=2000)
+    assert np.any(rod["det_mask"] >> np.uint64(32))   # masks use the second word
+    compare_pass(r, rod, god, pd.theta, 1e-11, 2000)
 
 
 @pytest.mark.parametrize("seed", list(range(100)))

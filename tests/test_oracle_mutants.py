@@ -40,6 +40,13 @@ MUTANTS = {
     "step1_threshold": ("if (m2 >= theta * theta) { keys[nk].m2", "if (m2 < theta * theta) { keys[nk].m2"),
     "step1_coordinate": ("pf[q] = poly_freq[(int64_t)(t - 1) * s_poly + q];", "pf[q] = poly_freq[(int64_t)t % d * s_poly + q];"),
     "median_weight_even": ("wq[2 * vs[L / 2].l + part] = 1.0;", "wq[2 * vs[0].l + part] = 1.0;"),
+    "mask_32_bits": ("mask |= 1ull << l;", "mask |= 1u << (l & 31);"),
+    "pfpn_pfn_threshold": ("(med > 1.0 ? 2 : 0)", "(med >= 1.0 ? 2 : 0)"),
+    "pfpn_pfp_threshold": ("(med > 0.0 ? 1 : 0)", "(med > 0.5 ? 1 : 0)"),
+    "pfpn_alone": ("M[l])] == 1;\n        if", "M[l])] <= 2;\n        if"),
+    "pfpn_support_counted": ("for (int64_t i = 0; i < n_active; ++i)\n            cnt[",
+                             "for (int64_t i = 0; i <= n_active; ++i)\n            cnt["),
+    "pfpn_detected_set": ("if (i >= n_active && !(cls[i] & 1)) continue;", "if (!(cls[i] & 1)) continue;"),
 }
 
 

@@ -322,6 +322,37 @@ def test_postprocessing_repairs_median_failure():
         assert r["det_mask"][q] == m
 
 
+@pytest.mark.parametrize("L", [37, 64])
+def test_singleton_masks_and_average_beyond_32_lattices(L):
+    """Remark 2.9 with more than 32 lattices: bit l of the singleton mask (now 64-bit)
+    is set iff the detected candidate is alone in its bucket of lattice l (brute force
+    over pairs of buckets), and the post-processed coefficient is the mean of the
+    lattice values over those lattices (the median where there are none)."""
+    rng = np.random.default_rng(L)
+    d, n, s = 2, 400, 40
+    cand = synth.distinct_uniform_points(rng, n, d, -30, 30)
+    supp = np.sort(rng.choice(n, size=s, replace=False))
+    coef = rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    M, z = synth.draw_lattices(rng, L, d, 61, 400)
+    g = oracle.dft(oracle.sample(cand[:, supp], coef, M, z), M)
+    r = oracle.extract(cand, M, z, g, 1e-9, s_cap=n, postproc=True)
+    det = r["det_idx"]
+    h = oracle.hash_buckets(cand[:, det], M, z)
+    offs = np.concatenate([[0], np.cumsum(M)])
+    high = 0
+    for q in range(len(det)):
+        want, vals = 0, []
+        for l in range(L):
+            if np.sum(h[l] == h[l, q]) == 1:
+                want |= 1 << l
+                vals.append(g[offs[l] + h[l, q]])
+        assert int(r["det_mask"][q]) == want
+        high += want >> 32 != 0
+        ref = np.mean(vals) if vals else r["det_med"][q]
+        assert abs(r["det_coef"][q] - ref) < 1e-12
+    assert high > 0
+
+
 def test_limit_matches_python_sort_and_threshold():
     """Algorithm 4: threshold theta, modulus descending (ties by index), first s~."""
     p = synth.mid_config(0, n=3000, s=30, L=7)
@@ -445,3 +476,128 @@ def test_threshold_boundary_is_inclusive_on_modulus():
     assert not set(np.nonzero(expect)[0]) & {0, 1, 2, 7}
     # median of three equal-modulus but rotated values; output ordered by modulus
     assert list(r["out_idx"][:2]) == [8, 6]
+
+
+# ------------------------------------------------------------------ Table 4.1 classification
+def _pfpn_brute(cand, na, M, z):
+    """Table 4.1 from the definitions, pair by pair: the value for k in lattice l is the
+    number of j in I with (k - j) . z_l = 0 mod M_l; PFN: k in I with median > 1; PFP:
+    k outside I with median > 0; a PFP is removed by the Remark 2.9 post-processing
+    iff some lattice has no other detected candidate in its bucket."""
+    import statistics
+    d, n = cand.shape
+    cls = np.zeros(n, np.uint8)
+    for i in range(n):
+        per_l = []
+        for l, m in enumerate(M):
+            dots = ((cand[:, i:i + 1] - cand[:, :na]) * z[l][:, None]).sum(axis=0)
+            per_l.append(int(np.count_nonzero(dots % int(m) == 0)))
+        med = statistics.median(per_l)
+        if i < na and med > 1:
+            cls[i] = 2
+        if i >= na and med > 0:
+            cls[i] = 1
+    det = np.array([i for i in range(n) if i < na or cls[i] & 1])
+    for i in range(na, n):
+        if not cls[i] & 1:
+            continue
+        alone = False
+        for l, m in enumerate(M):
+            dots = ((cand[:, det] - cand[:, i:i + 1]) * z[l][:, None]).sum(axis=0) % int(m)
+            alone = alone or int(np.count_nonzero(dots == 0)) == 1   # only k itself
+        if not alone:
+            cls[i] |= 4
+    return cls
+
+
+@pytest.mark.parametrize("seed,L", [(1, 5), (2, 6), (3, 7), (4, 4), (5, 9)])
+def test_pfpn_classification_brute_force(seed, L):
+    """Section 4.1.1 (Table 4.1, Remark 2.9) on small lattices with heavy aliasing;
+    odd and even L (even L: median of the two middle values)."""
+    rng = np.random.default_rng(seed)
+    d, n, na = 3, 300, 24
+    cand = synth.distinct_uniform_points(rng, n, d, -20, 20)
+    M = rng.choice(synth.primes_in(41, 79), size=L)
+    z = rng.integers(0, 1 << 20, size=(L, d)) % M[:, None]
+    cls = oracle.pfpn(cand, na, M, z)
+    want = _pfpn_brute(cand, na, M, z)
+    assert np.array_equal(cls, want)
+    pfp, pfn, post = oracle.pfpn_counts(cls)
+    assert pfp > 0 and post <= pfp   # heavy aliasing: the case is not vacuous
+
+
+def test_pfpn_even_lattice_count_half_median():
+    """Even L: a median of 1/2 (k outside I) is a PFP and a median of 3/2 (k in I) a
+    PFN; found for this configuration by the pairwise count."""
+    rng = np.random.default_rng(9)
+    d, n, na = 2, 200, 30
+    cand = synth.distinct_uniform_points(rng, n, d, -15, 15)
+    M = np.array([31, 37, 41, 43], np.int64)
+    z = rng.integers(1, 31, size=(4, d))
+    cls = oracle.pfpn(cand, na, M, z)
+    assert np.array_equal(cls, _pfpn_brute(cand, na, M, z))
+    offs = np.concatenate([[0], np.cumsum(M)])
+    cnt = oracle.counts(cand[:, :na], M, z)
+    h = oracle.hash_buckets(cand, M, z)
+    vals = np.stack([cnt[offs[l] + h[l]] for l in range(4)])
+    med = np.median(vals, axis=0)
+    assert np.any(med[na:] == 0.5) and np.all((cls[na:][med[na:] == 0.5] & 1) == 1)
+    half_pfn = (med[:na] == 1.5)
+    assert np.all((cls[:na][half_pfn] & 2) == 2)
+
+
+def test_pfpn_injective_lattice_has_no_potential_false_detection():
+    """A lattice that maps the box [-b, b]^3 injectively (z = (1, 2b+1, (2b+1)^2),
+    M prime >= (2b+1)^3) aliases nothing: no PFP, no PFN (Section 4.1.1)."""
+    rng = np.random.default_rng(4)
+    b = 6
+    cand = synth.distinct_uniform_points(rng, 500, 3, -b, b)
+    M = np.array([synth.next_prime_above((2 * b + 1) ** 3)] * 3, np.int64)
+    z = np.array([[1, 2 * b + 1, (2 * b + 1) ** 2]] * 3, np.int64)
+    cls = oracle.pfpn(cand, 40, M, z)
+    assert not cls.any()
+
+
+def test_pfpn_planted_collisions():
+    """Candidates that differ by a multiple of M e_1 share a bucket in every lattice
+    of size M: two such support members are both PFNs, and a third candidate on the
+    same line outside I is a PFP that the post-processing cannot remove."""
+    rng = np.random.default_rng(6)
+    M = np.array([101] * 5, np.int64)
+    z = rng.integers(0, 101, size=(5, 3))
+    z[:, 0] = rng.integers(1, 101, size=5)
+    base = synth.distinct_uniform_points(rng, 60, 3, -40, 40)
+    cand = base.copy()
+    cand[:, 1] = cand[:, 0] + np.array([101, 0, 0])     # support member aliasing member 0
+    cand[:, 50] = cand[:, 0] + np.array([202, 0, 0])    # outside I, aliasing both
+    assert np.unique(cand, axis=1).shape[1] == 60
+    cls = oracle.pfpn(cand, 10, M, z)
+    assert cls[0] & 2 and cls[1] & 2
+    assert cls[50] & 1 and cls[50] & 4
+    assert np.array_equal(cls, _pfpn_brute(cand, 10, M, z))
+
+
+def test_cor27_failure_bound_reproduces_printed_lines():
+    """Corollary 2.7 solved for delta, |Gamma| (c-1)^(-(c-2) L/(4c)) with c = 10.33,
+    reproduces the dashed failure-rate lines of Figures 4.1 and 4.3."""
+    from paper_2006_13053_amd.worst_case import cor27_failure_bound
+    g = _gold("cor27_failure_bound.json")
+    for st in g["sets"]:
+        for L, b in st["points"]:
+            assert cor27_failure_bound(st["Gamma"], g["c"], L) == pytest.approx(b, abs=6e-4)
+
+
+def test_hyperbolic_cross_sizes_printed_in_paper():
+    """Section 4.1.3: |Gamma| = 10,665,297 for the unweighted cross (d = 8, bound 32) and
+    |I| = 1069 for the weighted one (weights t^1.08); small cases by brute force."""
+    g = synth.hyperbolic_cross(8, 32)
+    assert g.shape == (8, 10_665_297)
+    assert np.abs(g).max() == 32
+    w = synth.hyperbolic_cross(8, 32, 1.08)
+    assert w.shape == (8, 1069)
+    assert synth.weighted_cross_member(g, 32, 1.08).sum() == 1069
+    for d, N in [(1, 7), (2, 9), (3, 6)]:
+        h = synth.hyperbolic_cross(d, N)
+        brute = [k for k in itertools.product(range(-N, N + 1), repeat=d)
+                 if math.prod(max(1, abs(v)) for v in k) <= N]
+        assert sorted(map(tuple, h.T.tolist())) == sorted(brute)
