@@ -252,6 +252,40 @@ int mr1l_check_injective(mr1l_plan p, int64_t n_total, const int64_t *set_off,
                          const int64_t *freq, int32_t *ok);
 
 /*
+ * Least-squares coefficients on the detected set (Remark 2.9: with the
+ * detected set I~ taken as the frequencies of the polynomial, its
+ * coefficients are computed from the samples already taken on the fixed
+ * lattices by a least-squares method).  Minimises over c in C^{|I~|}
+ *   sum_l sum_{j<M_l} |sum_{k in I~} c_k e^{2 pi i j k.z_l / M_l} - f_l[j]|^2
+ *   = sum_l M_l sum_h |sum_{k in I~, h_l(k) = h} c_k - ghat_l[h]|^2
+ * (Parseval on each lattice and eq. (2.4)) by conjugate gradients on the
+ * normal equations, per function, then applies Algorithm 4 to c.  When the
+ * lattices discretise the polynomials on I~ and I~ contains the support, the
+ * solution is exact and zero on the false positives.
+ *   cap, n_det, det_idx, det_hash, det_mask  dev outputs of the extract call
+ *            that found I~ (det_hash and det_mask required; only the first
+ *            min(n_det, cap) entries take part); ghat  dev lattice values of
+ *            mr1l_fft (the same samples).
+ *   max_iter >= 0 CG iterations at most; tol >= 0: stop once the normal-
+ *            equation residual is <= tol times the right-hand side.
+ *   coef     dev [F][cap] complex, in: the start (e.g. the extract call's
+ *            det_coef), out: the least-squares coefficients.
+ *   resid    dev double [F] final relative residual | NULL;
+ *   iters    dev int32 [F] iterations taken | NULL.
+ *   theta, s_cap, n_out, out_idx, out_coef  Algorithm 4 on the solution, as
+ *            in mr1l_extract; n_out == NULL skips it.
+ * Asynchronous on the plan's stream; grows plan scratch of
+ * F*cap*(4L + 3*sizeof(complex)) bytes on first use (not during graph
+ * capture); MR1L_E_ARG for invalid arguments.
+ */
+int mr1l_lsq(mr1l_plan p, int64_t cap, const int64_t *n_det,
+             const int64_t *det_idx, const int32_t *det_hash,
+             const uint32_t *det_mask, const void *ghat, int32_t max_iter,
+             double tol, void *coef, double *resid, int32_t *iters,
+             double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx,
+             void *out_coef);
+
+/*
  * Worst-case aliasing counts of Section 4.1.1 (Table 4.1).  Run mr1l_sample,
  * mr1l_fft and mr1l_extract (Remark 2.9 post-processing on, vote_min 0) on the
  * counting polynomial of eq. (4.1), all-ones coefficients on the support I,

@@ -283,3 +283,26 @@ def pfpn_counts(cls):
     """(#PFP, #PFN, #PFP kept by post-processing) of a pfpn classification."""
     cls = np.asarray(cls)
     return int(((cls & 1) != 0).sum()), int(((cls & 2) != 0).sum()), int(((cls & 4) != 0).sum())
+
+
+def lsq_matrix(freq, M, z):
+    """Sampling matrix of the trigonometric polynomials with frequencies freq on the
+    concatenated lattice nodes: A[(l, j), q] = e^{2 pi i j h_l(k_q) / M_l}, since
+    k . x_j = j (k . z_l) / M_l mod 1 (eq. (2.1)); the phase j h mod M is reduced in
+    integers.  Dense, for small cases."""
+    h = hash_buckets(freq, M, z)
+    rows = []
+    for l, m in enumerate(np.asarray(M, np.int64)):
+        j = np.arange(int(m), dtype=np.int64)[:, None]
+        ph = (j * h[l][None, :]) % int(m)
+        rows.append(np.exp(2j * np.pi * ph / float(m)))
+    return np.vstack(rows)
+
+
+def lsq(freq, M, z, f, det_idx):
+    """Remark 2.9, least-squares variant: coefficients on the candidates det_idx that
+    minimise the sum over all lattice nodes of |sum_k c_k e^{2 pi i k.x_j} - f(x_j)|^2
+    (numpy's least squares on the dense sampling matrix; minimum norm if singular)."""
+    A = lsq_matrix(np.asarray(freq)[:, np.asarray(det_idx, np.int64)], M, z)
+    c, *_ = np.linalg.lstsq(A, np.asarray(f, np.complex128), rcond=None)
+    return c

@@ -82,6 +82,8 @@ SIGNATURES = {
     "mr1l_fft_schedule_name": ([_I32], C.c_char_p),
     "mr1l_plan_fft_schedule": ([_P, _I64, _I32], C.c_int),
     "mr1l_fft_tune": ([_P, _I32, _I32, _P, _P], C.c_int),
+    "mr1l_lsq": ([_P, _I64, _P, _P, _P, _P, _P, _I32, C.c_double, _P, _P, _P, C.c_double, _I64, _P, _P, _P],
+                 C.c_int),
     "mr1l_pfpn_count": ([_P, _I64, _P, _P, _P, _P, _P, C.c_double, _P], C.c_int),
 }
 
@@ -211,6 +213,30 @@ def mr1l_check_injective(plan: Plan, freq, set_off=None):
     if rc not in (0, -4):   # -4: MR1L_E_NOT_INJECTIVE
         _check(rc, "mr1l_check_injective")
     return rc == 0, ok.astype(bool)
+
+
+def mr1l_lsq(plan: Plan, ex: "Extracted", ghat, max_iter: int = 100, tol: float = 1e-14, theta: float | None = None,
+             s_cap: int | None = None, coef=None):
+    """Least-squares coefficients on the detected set of an extract call (Remark 2.9)
+    and Algorithm 4 on them -> dict(coef, resid, iters, n_out, out_idx, out_coef).
+    The extract call must have kept det_hash and det_mask."""
+    if ex.get("det_hash") is None or ex.get("det_mask") is None:
+        raise Mr1lError("mr1l_lsq needs the extract call's det_hash and det_mask")
+    dev = _dev()
+    F = plan.F
+    s_cap = ex.s_cap if s_cap is None else int(s_cap)
+    theta = ex.theta if theta is None else float(theta)
+    coef = ex["det_coef"].clone() if coef is None else coef
+    out = dict(coef=coef, resid=torch.zeros(F, dtype=torch.float64, device=dev),
+               iters=torch.zeros(F, dtype=torch.int32, device=dev),
+               n_out=torch.zeros(F, dtype=torch.int64, device=dev),
+               out_idx=torch.zeros((F, s_cap), dtype=torch.int64, device=dev),
+               out_coef=torch.zeros((F, s_cap), dtype=plan.dtype, device=dev))
+    _check(lib().mr1l_lsq(plan.handle, ex.cap, _ptr(ex["n_det"]), _ptr(ex["det_idx"]), _ptr(ex["det_hash"]),
+                          _ptr(ex["det_mask"]), _ptr(ghat), int(max_iter), float(tol), _ptr(coef),
+                          _ptr(out["resid"]), _ptr(out["iters"]), theta, s_cap, _ptr(out["n_out"]),
+                          _ptr(out["out_idx"]), _ptr(out["out_coef"])), "mr1l_lsq")
+    return out
 
 
 def mr1l_pfpn_count(plan: Plan, ex: "Extracted", n_active, counts=None):

@@ -308,7 +308,7 @@ static void release(Plan *p)
     void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_vrec, p->d_spec, p->d_chirp, p->d_tw,
                     p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
                     p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
-                    p->d_termoff_default};
+                    p->d_termoff_default, p->d_ls};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (FftGroup &g : p->fft_groups)
@@ -414,6 +414,7 @@ int mr1l::plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, cons
         attrs_rc = fft_init_attrs();
         if (!attrs_rc) attrs_rc = extract_init_attrs();
         if (!attrs_rc) attrs_rc = vote_init_attrs();
+        if (!attrs_rc) attrs_rc = lsq_init_attrs();
         if (attrs_rc) attrs_err = g_err;
     });
     if (attrs_rc) return fail(attrs_rc, "kernel attribute setup failed: " + attrs_err);
@@ -665,6 +666,29 @@ int32_t mr1l_num_lattices(int64_t nJ, double c, double delta)
     if (L < 1) L = 1;
     if ((L & 1) == 0) ++L;
     return L;
+}
+
+int mr1l_lsq(mr1l_plan p, int64_t cap, const int64_t *n_det, const int64_t *det_idx, const int32_t *det_hash,
+             const uint32_t *det_mask, const void *ghat, int32_t max_iter, double tol, void *coef, double *resid,
+             int32_t *iters, double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (cap < 1 || cap > kMaxCap) return fail(MR1L_E_ARG, "cap must be in [1, 8192]");
+    if (!n_det || !det_hash || !det_mask || !ghat || !coef) return fail(MR1L_E_ARG, "null input buffer");
+    if (max_iter < 0 || !(tol >= 0.0)) return fail(MR1L_E_ARG, "max_iter and tol must be >= 0");
+    if (n_out) {
+        if (!det_idx || !out_idx || !out_coef) return fail(MR1L_E_ARG, "Algorithm 4 outputs need det_idx, out_idx, out_coef");
+        if (s_cap < 1 || s_cap > cap) return fail(MR1L_E_ARG, "s_cap must be in [1, cap]");
+        if (!(theta >= 0.0)) return fail(MR1L_E_ARG, "theta must be >= 0");
+    }
+    const int64_t esz = p->dtype == MR1L_C128 ? 16 : 8;
+    const int64_t rep_bytes = ((int64_t)p->F * cap * p->L * 4 + 255) / 256 * 256;
+    int rc = grow(*p, &p->d_ls, rep_bytes + 3 * (int64_t)p->F * cap * esz, p->ls_bytes);
+    if (rc) return rc;
+    rc = lsq_run(*p, cap, n_det, det_hash, det_mask, ghat, max_iter, tol, coef, resid, iters, (int32_t *)p->d_ls,
+                 (char *)p->d_ls + rep_bytes);
+    if (rc || !n_out) return rc;
+    return limit_run(*p, n_det, cap, det_idx, coef, theta, s_cap, n_out, out_idx, out_coef);
 }
 
 int mr1l_pfpn_count(mr1l_plan p, int64_t cap, const int64_t *n_active, const int64_t *n_det, const int64_t *det_idx,

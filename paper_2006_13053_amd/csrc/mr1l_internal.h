@@ -131,10 +131,12 @@ struct Plan {
     int64_t ex_cap = 0;
     int32_t *d_ex_hash = nullptr;    // [F][cap][L]
     double *d_ex_w = nullptr;        // [F][cap][L][2]
-    uint32_t *d_ex_mask = nullptr;   // [F][cap]
+    uint32_t *d_ex_mask = nullptr;   // [F][cap][mask_words(L)]
     void *d_ex_med = nullptr;        // [F][cap] complex
     int32_t *d_ex_pos = nullptr;     // [F][s_cap]
     int64_t ex_scap = 0;
+    void *d_ls = nullptr;            // least squares: [F][cap][L] int32 representatives + 3 [F][cap] complex
+    int64_t ls_bytes = 0;
     int64_t *d_setoff_default = nullptr; // [2] = {0, n} for F == 1 calls
     int64_t setoff_n = -1;
     int64_t *d_termoff_default = nullptr;
@@ -228,6 +230,10 @@ int plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int6
 int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef, double theta,
               int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef);
 int check_injective_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, int32_t *ok);
+int lsq_init_attrs();
+int lsq_run(Plan &p, int64_t cap, const int64_t *n_det, const int32_t *det_hash, const uint32_t *det_mask,
+            const void *ghat, int32_t max_iter, double tol, void *coef, double *resid, int32_t *iters,
+            int32_t *rep, void *vecs);
 int pfpn_run(Plan &p, int64_t cap, const int64_t *n_active, const int64_t *n_det, const int64_t *det_idx,
              const void *det_med, const void *det_coef, double theta, int64_t *counts);
 int fft_init_attrs();

@@ -601,3 +601,53 @@ def test_hyperbolic_cross_sizes_printed_in_paper():
         brute = [k for k in itertools.product(range(-N, N + 1), repeat=d)
                  if math.prod(max(1, abs(v)) for v in k) <= N]
         assert sorted(map(tuple, h.T.tolist())) == sorted(brute)
+
+
+# ------------------------------------------------------------------ Remark 2.9, least squares
+def test_lsq_matrix_is_the_sampler():
+    """The least-squares design matrix applied to coefficients gives the samples of
+    the polynomial on the lattice nodes (eq. (2.1), (2.2))."""
+    rng = np.random.default_rng(3)
+    cand = synth.distinct_uniform_points(rng, 40, 4, -50, 50)
+    M, z = synth.draw_lattices(rng, 3, 4, 30, 90)
+    c = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    A = oracle.lsq_matrix(cand, M, z)
+    assert A.shape == (int(M.sum()), 40)
+    assert np.abs(A @ c - oracle.sample(cand, c, M, z)).max() < 1e-12
+
+
+def test_lsq_all_singletons_is_weighted_mean():
+    """Every candidate alone in its bucket of every lattice: the normal equations are
+    diagonal, so c_k = sum_l M_l ghat_l[h_l(k)] / sum_l M_l."""
+    rng = np.random.default_rng(4)
+    while True:
+        cand = synth.distinct_uniform_points(rng, 6, 3, -40, 40)
+        M, z = synth.draw_lattices(rng, 4, 3, 200, 400)
+        h = oracle.hash_buckets(cand, M, z)
+        if all(len(set(h[l].tolist())) == 6 for l in range(4)):
+            break
+    f = rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum()))
+    g = oracle.dft(f, M)
+    offs = np.concatenate([[0], np.cumsum(M)])
+    want = sum(M[l] * g[offs[l] + h[l]] for l in range(4)) / M.sum()
+    assert np.abs(oracle.lsq(cand, M, z, f, np.arange(6)) - want).max() < 1e-12
+
+
+def test_lsq_exact_with_false_positives():
+    """Remark 2.9 and the end of Sec. 4.1.2: with the support inside the detected set and
+    enough samples, least squares recovers the coefficients exactly and gives zero
+    on the false positives."""
+    rng = np.random.default_rng(5)
+    cand = synth.distinct_uniform_points(rng, 400, 5, -30, 30)
+    supp = np.sort(rng.choice(400, size=25, replace=False))
+    coef = rng.standard_normal(25) + 1j * rng.standard_normal(25)
+    M, z = synth.draw_lattices(rng, 4, 5, 60, 120)   # heavy aliasing per lattice
+    f = oracle.sample(cand[:, supp], coef, M, z)
+    extra = np.setdiff1d(np.arange(400), supp)[:35]
+    det = np.sort(np.concatenate([supp, extra]))
+    A = oracle.lsq_matrix(cand[:, det], M, z)
+    assert np.linalg.matrix_rank(A) == len(det)
+    c = oracle.lsq(cand, M, z, f, det)
+    want = np.zeros(len(det), np.complex128)
+    want[np.searchsorted(det, supp)] = coef
+    assert np.abs(c - want).max() < 1e-10
