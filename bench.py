@@ -47,7 +47,7 @@ def log(*a):
 
 def vote_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("k_hash.hip", "mr1l_internal.h"):
+    for f in ("k_hash.hip", "mr1l_device.h"):
         with open(os.path.join(ROOT, "paper_2006_13053_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def vote_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("k_hash.hip", "mr1l_internal.h"):
+    for f in ("k_hash.hip", "mr1l_device.h"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
