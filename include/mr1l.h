@@ -127,6 +127,27 @@ int mr1l_sample(mr1l_plan p, int32_t d_poly, const int64_t *term_off,
                 const uint32_t *anchor, void *f, int32_t mode);
 
 /*
+ * Samples of a sum of tensor products of periodic B-splines, the kind of test
+ * function of eq. (4.3) (Section 4.2.3):
+ *   f(x) = sum_{j < n_prod} prod_{u in S_j} N_{m_j}(x_u),
+ *   N_m(x) = C_m sum_k sinc(pi k / m)^m (-1)^k e^{2 pi i k x},  ||N_m||_2 = 1,
+ * at the plan's lattice nodes, coordinates u < d from the lattice and
+ * u >= d fixed anchors x'_u = anchor[f*(d_poly-d) + u-d] / 2^32, as in
+ * mr1l_sample.  On [0, 1), N_m(x) = C_m m B_m(m x) with the cardinal B-spline
+ * B_m of order m (knots 0..m) and C_m = (m B_2m(m))^{-1/2}.
+ *   d_poly   coordinates of the function, d <= d_poly <= 64;
+ *   n_prod   1..16 products; order host int32 [n_prod], 1 <= m_j <= 16;
+ *   dims     host uint64 [F][n_prod]: bit u set iff coordinate u (in the
+ *            order above) belongs to S_j for function f;
+ *   anchor   dev uint32 [F][d_poly-d] (NULL when d_poly == d);
+ *   f        dev [nodes] complex output (imaginary parts zero).
+ * Synchronises the plan's stream before returning (the masks are copied).
+ */
+int mr1l_sample_bspline(mr1l_plan p, int32_t d_poly, int32_t n_prod,
+                        const int32_t *order, const uint64_t *dims,
+                        const uint32_t *anchor, void *f);
+
+/*
  * Normalised lattice DFT of Algorithm 2 (first loop):
  *   ghat[O + h] = (1/M) sum_{j<M} f[O + j] exp(-2 pi i j h / M), h < M,
  * for every lattice (Bluestein's chirp transform with LDS-staged Stockham
@@ -157,7 +178,9 @@ typedef struct {
     int32_t postproc;  /* 1: singleton averaging of Remark 2.9, median as
                           fall-back; 0: medians of eq. (2.10) only           */
     int64_t s_cap;     /* Algorithm 4 sparsity s~ per function (>= 1)         */
-    int64_t cap;       /* detected-list capacity per function, 1..8192       */
+    int64_t cap;       /* detected-list capacity per function, 1..2^24; above
+                          8192 the call synchronises its stream once (to size
+                          global-memory sorts) and cannot be graph-captured */
 } mr1l_extract_opts;
 
 /* Outputs of mr1l_extract (all dev; optional ones may be NULL). */
@@ -264,7 +287,7 @@ int mr1l_check_injective(mr1l_plan p, int64_t n_total, const int64_t *set_off,
  * solution is exact and zero on the false positives.
  *   cap, n_det, det_idx, det_hash, det_mask  dev outputs of the extract call
  *            that found I~ (det_hash and det_mask required; only the first
- *            min(n_det, cap) entries take part); ghat  dev lattice values of
+ *            min(n_det, cap) entries take part; cap <= 8192); ghat  dev lattice values of
  *            mr1l_fft (the same samples).
  *   max_iter >= 0 CG iterations at most; tol >= 0: stop once the normal-
  *            equation residual is <= tol times the right-hand side.
@@ -361,6 +384,12 @@ typedef struct {
     uint64_t seed;     /* SplitMix64 seed of all random draws               */
     int32_t dtype;     /* MR1L_C128 or MR1L_C64                            */
     int32_t step1;     /* 1: single-coordinate sets from Step 1; 0: [-N, N] */
+    int32_t bs_n;      /* > 0: the function is the built-in B-spline test
+                          function of mr1l_sample_bspline with bs_n products
+                          (orders bs_order, coordinate masks bs_dims over the
+                          d coordinates); 0: the sparse polynomial           */
+    int32_t bs_order[16];
+    uint64_t bs_dims[16];
 } mr1l_dimincr_params;
 
 /*
@@ -395,8 +424,9 @@ typedef int (*mr1l_sample_fn)(void *user, int32_t t, int32_t L,
  * detected tuples (sorted, without repeats).  The output of the t = d call
  * is the result.
  *   fn/user   sampling callback; if fn is NULL the built-in sampler of the
- *             sparse polynomial (poly_freq dev [d][poly_s] int64,
- *             poly_coef dev [poly_s] complex) is used.
+ *             B-spline test function (bs_n > 0) or of the sparse polynomial
+ *             (poly_freq dev [d][poly_s] int64, poly_coef dev [poly_s]
+ *             complex) is used.
  *   cap       capacity of freq_out / coef_out and of every intermediate
  *             union (entries).
  *   n_out     host: number of recovered frequencies.

@@ -74,8 +74,11 @@ def _declare(L):
     L.orc_splitmix64.restype = _u64
     L.orc_num_lattices_eq42.argtypes = [_i64, _d, _d]
     L.orc_num_lattices_eq42.restype = _i32
-    L.orc_dimincr.argtypes = [_i32, _i64, _i64, _p, _p, _i64, _i64, _i32, _d, _d, _d, _i64,
+    L.orc_dimincr.argtypes = [_i32, _i64, _i64, _p, _p, _i32, _p, _p, _i64, _i64, _i32, _d, _d, _d, _i64,
                               _i32, _u64, _i64, _i32, _p, _p, _p]
+    L.orc_sample_bspline.argtypes = [_i32, _i32, _i32, _p, _p, _p, _i32, _p, _p, _p]
+    L.orc_bspline_periodic.argtypes = [_i32, C.c_longdouble]
+    L.orc_bspline_periodic.restype = C.c_longdouble
     L.orc_dimincr.restype = _i64
     L.orc_pfpn.argtypes = [_i32, _i64, _p, _i64, _i32, _p, _p, _p]
 
@@ -245,25 +248,55 @@ def num_lattices_eq42(nJ: int, c: float = 10.33, delta: float = 0.9) -> int:
 
 
 def dimincr(poly_freq, poly_coef, N, s, s_local, r, theta, c, delta, Mlat, seed,
-            postproc=True, cap_set=1 << 20, step1=False):
+            postproc=True, cap_set=1 << 20, step1=False, bspline=None, d=None):
     """Algorithm 3 Step 2 with Algorithm 4; the single-coordinate sets come from Step 1
-    (step1) or are the full range [-N, N].
+    (step1) or are the full range [-N, N].  The function is the sparse polynomial
+    (poly_freq, poly_coef), or with bspline = (orders, coordinate masks) the test
+    function of eq. (4.3) in d coordinates.
 
     Returns (freq [n, d] int64 lexicographically sorted, coef [n] complex, samples).
     """
-    pf = _c(poly_freq, np.int64)
-    d, sp = pf.shape
-    pc = _cplx(poly_coef)
+    if bspline is None:
+        pf = _c(poly_freq, np.int64)
+        d, sp = pf.shape
+        pc = _cplx(poly_coef)
+        bn, bo, bd = 0, None, None
+    else:
+        pf, pc, sp = None, None, 0
+        bo = _c(bspline[0], np.int32)
+        bd = _c(bspline[1], np.uint64)
+        bn = int(bo.shape[0])
     out_f = np.zeros((max(int(s), 1), d), np.int64)
     out_c = np.zeros(2 * max(int(s), 1), np.float64)
     tot = C.c_int64(0)
-    n = lib().orc_dimincr(d, int(N), sp, _ptr(pf), _ptr(pc), int(s), int(s_local), int(r),
-                          float(theta), float(c), float(delta), int(Mlat), int(bool(postproc)),
+    n = lib().orc_dimincr(d, int(N), sp, _ptr(pf), _ptr(pc), bn, _ptr(bo), _ptr(bd), int(s), int(s_local),
+                          int(r), float(theta), float(c), float(delta), int(Mlat), int(bool(postproc)),
                           C.c_uint64(seed & (2**64 - 1)), int(cap_set), int(bool(step1)), _ptr(out_f),
                           _ptr(out_c), C.byref(tot))
     if n < 0:
         raise RuntimeError("oracle dimincr: capacity exceeded")
     return out_f[:n], out_c.view(np.complex128)[:n], int(tot.value)
+
+
+def bspline_periodic(m, x):
+    """N_m(x) of eq. (4.3) (unit L2 norm, period 1), long double, returned as float."""
+    return float(lib().orc_bspline_periodic(int(m), C.c_longdouble(float(x))))
+
+
+def sample_bspline(order, dims, M, z, anchor=None, t=None):
+    """Samples of sum_j prod_{u in S_j} N_{m_j}(x_u) at the lattice nodes (coordinates
+    u < t from the lattices, u >= t anchors a_u / 2^32); dims[j] = bit mask of S_j."""
+    order = _c(order, np.int32)
+    dims = _c(dims, np.uint64)
+    M = _c(M, np.int64)
+    z = _c(z, np.int64).reshape(len(M), -1)
+    t = z.shape[1] if t is None else int(t)
+    d_poly = t + (0 if anchor is None else len(anchor))
+    anc = None if anchor is None else _c(anchor, np.uint32)
+    f = np.zeros(2 * int(M.sum()), np.float64)
+    lib().orc_sample_bspline(t, d_poly, len(order), _ptr(order), _ptr(dims), _ptr(anc), len(M), _ptr(M), _ptr(z),
+                             _ptr(f))
+    return f.view(np.complex128)
 
 
 def pfpn(freq, n_active, M, z):

@@ -580,6 +580,90 @@ static uint64_t stream1_draw(uint64_t seed, int32_t t, int32_t i, uint64_t c)
 }
 
 /* ------------------------------------------------------------------ */
+/* The test function of eq. (4.3) (Sec. 4.2.3): sums of tensor products */
+/* of the periodic B-splines                                            */
+/*   N_m(x) = C_m sum_k sinc(pi k / m)^m (-1)^k e^{2 pi i k x}.          */
+/* The series equals C_m m B_m(m x) on [0, 1), B_m the cardinal         */
+/* B-spline of order m with knots 0..m, evaluated here by its           */
+/* truncated-power form                                                 */
+/*   B_m(y) = (1/(m-1)!) sum_{j=0}^{m} (-1)^j binom(m, j) (y - j)_+^{m-1}. */
+/* C_m makes ||N_m||_2 = 1; by Parseval C_m^-2 = sum_k sinc(pi k/m)^{2m}, */
+/* summed directly (terms decay like k^{-2m}).                         */
+/* ------------------------------------------------------------------ */
+static ld trunc_power_bspline(int32_t m, ld y)
+{
+    if (y < 0 || y >= m) return 0;
+    ld s = 0, binom = 1, fact = 1;
+    for (int32_t j = 2; j < m; ++j) fact *= j;
+    for (int32_t j = 0; j <= m; ++j) {
+        if (y >= j) {
+            ld pw = 1;
+            for (int32_t e = 0; e < m - 1; ++e) pw *= (y - j);
+            s += ((j & 1) ? -binom : binom) * pw;
+        }
+        binom = binom * (m - j) / (j + 1);
+    }
+    return s / fact;
+}
+
+static ld bspline_norm_const(int32_t m)
+{
+    static ld cache[33];
+    if (m >= 1 && m <= 32 && cache[m] > 0) return cache[m];
+    ld acc = 1;   /* k = 0 */
+    for (int64_t k = 1; k <= 200000; ++k) {
+        const ld x = (ld)3.14159265358979323846264338327950288L * (ld)k / (ld)m;
+        const ld sc = sinl(x) / x;
+        ld p = 1;
+        for (int32_t e = 0; e < 2 * m; ++e) p *= sc;
+        acc += 2 * p;
+    }
+    const ld c = 1 / sqrtl(acc);
+    if (m >= 1 && m <= 32) cache[m] = c;
+    return c;
+}
+
+/* N_m(x) for any real x (period 1). */
+ld orc_bspline_periodic(int32_t m, ld x)
+{
+    x = x - floorl(x);
+    return bspline_norm_const(m) * (ld)m * trunc_power_bspline(m, (ld)m * x);
+}
+
+/* Samples of f(x) = sum_j prod_{u in S_j} N_{m_j}(x_u) at the nodes of L   */
+/* lattices in t coordinates (x_u = j z_u / M mod 1, u < t) with anchors   */
+/* x_u = anchor[u - t] / 2^32 (u = t..d_poly-1); dims[j] has bit u set iff */
+/* u is in S_j.  f: complex [sum M] (imaginary parts zero).                 */
+void orc_sample_bspline(int32_t t, int32_t d_poly, int32_t n_prod, const int32_t *order,
+                        const uint64_t *dims, const uint32_t *anchor, int32_t L, const int64_t *M,
+                        const int64_t *z, double *f)
+{
+    for (int32_t q = 0; q < n_prod; ++q) (void)bspline_norm_const(order[q]);   /* fill the cache serially */
+    int64_t off = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        const int64_t Ml = M[l];
+#pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < Ml; ++j) {
+            ld acc = 0;
+            for (int32_t q = 0; q < n_prod; ++q) {
+                ld prod = 1;
+                for (int32_t u = 0; u < d_poly; ++u) {
+                    if (!((dims[q] >> u) & 1u)) continue;
+                    ld x;
+                    if (u < t) x = (ld)floor_mod_i128((__int128)j * z[(int64_t)l * t + u], Ml) / (ld)Ml;
+                    else x = (ld)anchor[u - t] / 4294967296.0L;
+                    prod *= orc_bspline_periodic(order[q], x);
+                }
+                acc += prod;
+            }
+            f[2 * (off + j)] = (double)acc;
+            f[2 * (off + j) + 1] = 0.0;
+        }
+        off += Ml;
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Algorithm 3, Step 1 (single frequency component identification) for  */
 /* coordinate t (1-based) over the range [-N, N] (K = 2N + 1):           */
 /* r times: anchors x'_j = a_j / 2^32 for j != t (drawn in ascending j  */
@@ -590,7 +674,8 @@ static uint64_t stream1_draw(uint64_t seed, int32_t t, int32_t i, uint64_t c)
 /* returned.  *samples grows by r K.                                   */
 /* ------------------------------------------------------------------ */
 static int64_t step1_set(int32_t d, int32_t t, int64_t N, int64_t s_poly, const int64_t *poly_freq,
-                         const double *poly_coef, int64_t s_local, int32_t r, double theta,
+                         const double *poly_coef, int32_t bs_n, const int32_t *bs_order,
+                         const uint64_t *bs_dims, int64_t s_local, int32_t r, double theta,
                          uint64_t seed, int64_t *set, int64_t *samples)
 {
     const int64_t K = 2 * N + 1;
@@ -608,10 +693,31 @@ static int64_t step1_set(int32_t d, int32_t t, int64_t N, int64_t s_poly, const 
     struct key { double m2; int64_t idx; } *keys = malloc(sizeof(struct key) * (size_t)K);
     uint32_t *anc = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)d);
     const int64_t one = 1;
+
     for (int32_t i = 1; i <= r; ++i) {
         uint64_t cnt = 0;
         for (int32_t j = 0; j < d - 1; ++j) anc[j] = (uint32_t)(stream1_draw(seed, t, i, cnt++) >> 32);
-        orc_sample(d, 1, s_poly, pf, poly_coef, anc, 1, &K, &one, f);
+        if (bs_n > 0) {
+            /* the test function on the line: x_t = l / K, the other coordinates anchored */
+            for (int32_t q = 0; q < bs_n; ++q) (void)bspline_norm_const(bs_order[q]);
+            for (int64_t l = 0; l < K; ++l) {
+                ld acc = 0;
+                for (int32_t q = 0; q < bs_n; ++q) {
+                    ld prod = 1;
+                    for (int32_t u = 0; u < d; ++u) {
+                        if (!((bs_dims[q] >> u) & 1u)) continue;
+                        const ld x = (u == t - 1) ? (ld)l / (ld)K
+                                                  : (ld)anc[u < t - 1 ? u : u - 1] / 4294967296.0L;
+                        prod *= orc_bspline_periodic(bs_order[q], x);
+                    }
+                    acc += prod;
+                }
+                f[2 * l] = (double)acc;
+                f[2 * l + 1] = 0.0;
+            }
+        } else {
+            orc_sample(d, 1, s_poly, pf, poly_coef, anc, 1, &K, &one, f);
+        }
         *samples += K;
         orc_dft(1, &K, f, g, -1);
         int64_t nk = 0;
@@ -667,7 +773,8 @@ static int cmp_tuple(const void *a, const void *b)
 /* ------------------------------------------------------------------ */
 /* Algorithm 3, Step 2 (coupling of frequency components), with         */
 /* Algorithm 4 in the role of Algorithm A, for a sparse trigonometric   */
-/* polynomial given by its d x s frequencies and coefficients.           */
+/* polynomial given by its d x s frequencies and coefficients, or       */
+/* (bs_n > 0) the test function of eq. (4.3) given by its products.     */
 /* The single-coordinate sets I^(t) come from Step 1 (step1 != 0) or   */
 /* are the full one-dimensional range [-N, N]; the output of the t = d  */
 /* call is the result (the external Step 3 is not part of this method). */
@@ -684,7 +791,8 @@ static int cmp_tuple(const void *a, const void *b)
 /* capacity is exceeded.  *total_samples gets sum over calls of L*Mlat.  */
 /* ------------------------------------------------------------------ */
 int64_t orc_dimincr(int32_t d, int64_t N, int64_t s_poly, const int64_t *poly_freq,
-                    const double *poly_coef, int64_t s, int64_t s_local, int32_t r,
+                    const double *poly_coef, int32_t bs_n, const int32_t *bs_order,
+                    const uint64_t *bs_dims, int64_t s, int64_t s_local, int32_t r,
                     double theta, double c, double delta, int64_t Mlat,
                     int32_t postproc, uint64_t seed, int64_t cap_set, int32_t step1,
                     int64_t *out_freq, double *out_coef, int64_t *total_samples)
@@ -696,7 +804,8 @@ int64_t orc_dimincr(int32_t d, int64_t N, int64_t s_poly, const int64_t *poly_fr
     int64_t *n1 = (int64_t *)malloc(sizeof(int64_t) * (size_t)d);
     for (int32_t t = 1; t <= d; ++t) {
         if (step1) {
-            n1[t - 1] = step1_set(d, t, N, s_poly, poly_freq, poly_coef, s_local, r, theta, seed,
+            n1[t - 1] = step1_set(d, t, N, s_poly, poly_freq, poly_coef, bs_n, bs_order, bs_dims, s_local, r,
+                                  theta, seed,
                                   I1 + (int64_t)(t - 1) * K, &samples);
         } else {
             for (int64_t a = 0; a < K; ++a) I1[(int64_t)(t - 1) * K + a] = a - N;
@@ -741,7 +850,8 @@ int64_t orc_dimincr(int32_t d, int64_t N, int64_t s_poly, const int64_t *poly_fr
 
             double *f = (double *)malloc(sizeof(double) * 2 * (size_t)SM);
             double *g = (double *)malloc(sizeof(double) * 2 * (size_t)SM);
-            orc_sample(d, t, s_poly, poly_freq, poly_coef, anc, L, Ms, zz, f);
+            if (bs_n > 0) orc_sample_bspline(t, d, bs_n, bs_order, bs_dims, anc, L, Ms, zz, f);
+            else orc_sample(d, t, s_poly, poly_freq, poly_coef, anc, L, Ms, zz, f);
             samples += SM;
             orc_dft(L, Ms, f, g, -1);
 

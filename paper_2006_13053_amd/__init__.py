@@ -46,7 +46,8 @@ class DimincrParams(C.Structure):
     _fields_ = [("d", C.c_int32), ("N", C.c_int64), ("s", C.c_int64), ("s_local", C.c_int64),
                 ("r", C.c_int32), ("theta", C.c_double), ("c", C.c_double), ("delta", C.c_double),
                 ("M", C.c_int64), ("postproc", C.c_int32), ("seed", C.c_uint64), ("dtype", C.c_int32),
-                ("step1", C.c_int32)]
+                ("step1", C.c_int32), ("bs_n", C.c_int32), ("bs_order", C.c_int32 * 16),
+                ("bs_dims", C.c_uint64 * 16)]
 
 
 SAMPLE_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
@@ -82,6 +83,7 @@ SIGNATURES = {
     "mr1l_fft_schedule_name": ([_I32], C.c_char_p),
     "mr1l_plan_fft_schedule": ([_P, _I64, _I32], C.c_int),
     "mr1l_fft_tune": ([_P, _I32, _I32, _P, _P], C.c_int),
+    "mr1l_sample_bspline": ([_P, _I32, _I32, _P, _P, _P, _P], C.c_int),
     "mr1l_lsq": ([_P, _I64, _P, _P, _P, _P, _P, _I32, C.c_double, _P, _P, _P, C.c_double, _I64, _P, _P, _P],
                  C.c_int),
     "mr1l_pfpn_count": ([_P, _I64, _P, _P, _P, _P, _P, C.c_double, _P], C.c_int),
@@ -274,6 +276,22 @@ def mr1l_sample(plan: Plan, freq, coef, f=None, term_off=None, anchor=None, mode
     return f
 
 
+def mr1l_sample_bspline(plan: Plan, d_poly: int, order, dims, anchor=None, f=None):
+    """Samples of sum_j prod_{u in S_j} N_{m_j}(x_u) (eq. (4.3)) at the plan's nodes.
+    order: [n_prod] ints; dims: [F, n_prod] (or [n_prod], all functions alike) bit masks
+    of the coordinates of each product."""
+    order = np.ascontiguousarray(np.asarray(order, dtype=np.int32).reshape(-1))
+    dims = np.asarray(dims, dtype=np.uint64)
+    if dims.ndim == 1:
+        dims = np.tile(dims, (plan.F, 1))
+    dims = np.ascontiguousarray(dims.reshape(plan.F, order.shape[0]))
+    if f is None:
+        f = torch.empty(plan.nodes, dtype=plan.dtype, device=_dev())
+    _check(lib().mr1l_sample_bspline(plan.handle, int(d_poly), int(order.shape[0]), order.ctypes.data_as(_P),
+                                     dims.ctypes.data_as(_P), _ptr(anchor), _ptr(f)), "mr1l_sample_bspline")
+    return f
+
+
 def mr1l_fft(plan: Plan, f, theta: float, ghat=None, bitmap=None, want_bitmap: bool = True):
     """Normalised lattice DFTs and the non-zero bitmap -> (ghat, bitmap)."""
     if ghat is None:
@@ -382,11 +400,18 @@ def mr1l_num_lattices(nJ: int, c: float = 10.33, delta: float = 0.9) -> int:
 def mr1l_dimincr(d: int, N: int, s: int, s_local: int, r: int, theta: float, M: int, seed: int,
                  poly_freq=None, poly_coef=None, c: float = 10.33, delta: float = 0.9,
                  postproc: bool = True, dtype=torch.complex128, cap: int = 1 << 16, sample_fn=None,
-                 step1: bool = False):
+                 step1: bool = False, bspline=None):
     """Algorithm 3 driver (Step 2, and Step 1 when step1) -> (freq [n, d] int64 numpy,
-    coef [n] numpy, total samples)."""
+    coef [n] numpy, total samples).  bspline = (orders, coordinate masks) selects the
+    built-in B-spline test function (eq. (4.3)) instead of the polynomial."""
     prm = DimincrParams(int(d), int(N), int(s), int(s_local), int(r), float(theta), float(c), float(delta),
                         int(M), int(bool(postproc)), int(seed) & (2**64 - 1), _ctype(dtype), int(bool(step1)))
+    if bspline is not None:
+        orders, masks = list(bspline[0]), list(bspline[1])
+        prm.bs_n = len(orders)
+        for q, (mq, dq) in enumerate(zip(orders, masks)):
+            prm.bs_order[q] = int(mq)
+            prm.bs_dims[q] = int(dq)
     fo = np.zeros((cap, d), np.int64)
     co = np.zeros(cap, np.complex128 if dtype == torch.complex128 else np.complex64)
     n_out, tot = C.c_int64(0), C.c_int64(0)

@@ -308,7 +308,7 @@ static void release(Plan *p)
     void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_vrec, p->d_spec, p->d_chirp, p->d_tw,
                     p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
                     p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
-                    p->d_termoff_default, p->d_ls};
+                    p->d_termoff_default, p->d_ls, p->d_gsort, p->d_bs_dims};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (FftGroup &g : p->fft_groups)
@@ -536,7 +536,7 @@ int mr1l_extract(mr1l_plan p, int64_t n_total, const int64_t *set_off, const int
 {
     if (!p || !o || !out) return fail(MR1L_E_ARG, "plan, options or outputs NULL");
     if (n_total < 0 || (n_total > 0 && !freq) || !ghat || !nz_bitmap) return fail(MR1L_E_ARG, "null input buffer");
-    if (o->cap < 1 || o->cap > kMaxCap) return fail(MR1L_E_ARG, "cap must be in [1, 8192]");
+    if (o->cap < 1 || o->cap > kMaxCapLarge) return fail(MR1L_E_ARG, "cap must be in [1, 2^24]");
     if (o->s_cap < 1 || o->s_cap > o->cap) return fail(MR1L_E_ARG, "s_cap must be in [1, cap]");
     if (!(o->theta >= 0.0)) return fail(MR1L_E_ARG, "theta must be >= 0");
     if (o->vote_min < 0 || o->vote_min > p->L) return fail(MR1L_E_ARG, "vote_min must be in [0, L]");
@@ -579,7 +579,7 @@ int mr1l_adjoint(mr1l_plan p, int64_t cap, int64_t s_cap, const int64_t *n_out, 
                  const int32_t *det_hash, const double *det_w, const void *grad_out, void *grad_f)
 {
     if (!p) return fail(MR1L_E_ARG, "plan is NULL");
-    if (cap < 1 || cap > kMaxCap || s_cap < 1 || s_cap > cap) return fail(MR1L_E_ARG, "invalid cap/s_cap");
+    if (cap < 1 || cap > kMaxCapLarge || s_cap < 1 || s_cap > cap) return fail(MR1L_E_ARG, "invalid cap/s_cap");
     if (!n_out || !out_pos || !det_hash || !det_w || !grad_out || !grad_f)
         return fail(MR1L_E_ARG, "null buffer (out_pos, det_hash and det_w of the extract call are required)");
     return adjoint_run(*p, cap, s_cap, n_out, out_pos, det_hash, det_w, grad_out, grad_f);
@@ -668,12 +668,20 @@ int32_t mr1l_num_lattices(int64_t nJ, double c, double delta)
     return L;
 }
 
+int mr1l_sample_bspline(mr1l_plan p, int32_t d_poly, int32_t n_prod, const int32_t *order, const uint64_t *dims,
+                        const uint32_t *anchor, void *f)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    StageTimer tm(*p, MR1L_STAGE_SAMPLE);
+    return bspline_sample_run(*p, d_poly, n_prod, order, dims, anchor, f);
+}
+
 int mr1l_lsq(mr1l_plan p, int64_t cap, const int64_t *n_det, const int64_t *det_idx, const int32_t *det_hash,
              const uint32_t *det_mask, const void *ghat, int32_t max_iter, double tol, void *coef, double *resid,
              int32_t *iters, double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef)
 {
     if (!p) return fail(MR1L_E_ARG, "plan is NULL");
-    if (cap < 1 || cap > kMaxCap) return fail(MR1L_E_ARG, "cap must be in [1, 8192]");
+    if (cap < 1 || cap > kMaxCap) return fail(MR1L_E_ARG, "least squares needs cap in [1, 8192]");
     if (!n_det || !det_hash || !det_mask || !ghat || !coef) return fail(MR1L_E_ARG, "null input buffer");
     if (max_iter < 0 || !(tol >= 0.0)) return fail(MR1L_E_ARG, "max_iter and tol must be >= 0");
     if (n_out) {
@@ -695,7 +703,7 @@ int mr1l_pfpn_count(mr1l_plan p, int64_t cap, const int64_t *n_active, const int
                     const void *det_med, const void *det_coef, double theta, int64_t *counts)
 {
     if (!p) return fail(MR1L_E_ARG, "plan is NULL");
-    if (cap < 1 || cap > kMaxCap) return fail(MR1L_E_ARG, "cap must be in [1, 8192]");
+    if (cap < 1 || cap > kMaxCapLarge) return fail(MR1L_E_ARG, "cap must be in [1, 2^24]");
     if (!(theta >= 0.0)) return fail(MR1L_E_ARG, "theta must be >= 0");
     if (!n_active || !n_det || !det_idx || !det_med || !det_coef || !counts)
         return fail(MR1L_E_ARG, "null buffer");

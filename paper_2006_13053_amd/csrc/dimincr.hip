@@ -105,7 +105,9 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
     if (P.d < 2 || P.d > kMaxD) return fail(MR1L_E_ARG, "d must be in [2, 64]");
     if (P.N < 0 || P.s < 1 || P.s_local < P.s || P.r < 1) return fail(MR1L_E_ARG, "invalid N, s, s_local or r");
     if (P.dtype != MR1L_C128 && P.dtype != MR1L_C64) return fail(MR1L_E_ARG, "invalid dtype");
-    if (!fn && (poly_s < 0 || (poly_s > 0 && (!poly_freq || !poly_coef))))
+    const bool bsp = !fn && P.bs_n > 0;
+    if (P.bs_n < 0 || P.bs_n > 16) return fail(MR1L_E_ARG, "bs_n must be in [0, 16]");
+    if (!fn && !bsp && (poly_s < 0 || (poly_s > 0 && (!poly_freq || !poly_coef))))
         return fail(MR1L_E_ARG, "built-in sampler needs the polynomial");
     if (cap < P.s) return fail(MR1L_E_CAPACITY, "cap below s");
     const hipStream_t st = (hipStream_t)stream;
@@ -128,22 +130,34 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
     } else {
         if (fn) return fail(MR1L_E_ARG, "Step 1 needs the built-in sampler");
         if (K > kMaxCap) return fail(MR1L_E_ARG, "Step 1 needs 2N + 1 <= 8192");
-        if (poly_s < 1) return fail(MR1L_E_ARG, "Step 1 needs a non-empty polynomial");
+        if (!bsp && poly_s < 1) return fail(MR1L_E_ARG, "Step 1 needs a non-empty polynomial");
         // the polynomial on the host, then one copy per (t, i) with coordinate t first
-        std::vector<int64_t> hf((size_t)d * poly_s);
-        std::vector<unsigned char> hc((size_t)poly_s * esz);
-        MR1L_HIP(hipMemcpyAsync(hf.data(), poly_freq, hf.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        MR1L_HIP(hipMemcpyAsync(hc.data(), poly_coef, hc.size(), hipMemcpyDeviceToHost, st));
-        MR1L_HIP(hipStreamSynchronize(st));
+        // (for the B-spline function: its coordinate masks with bit t moved to bit 0)
+        const int64_t ps = bsp ? 0 : poly_s;
+        std::vector<int64_t> hf((size_t)d * ps);
+        std::vector<unsigned char> hc((size_t)ps * esz);
+        if (ps > 0) {
+            MR1L_HIP(hipMemcpyAsync(hf.data(), poly_freq, hf.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            MR1L_HIP(hipMemcpyAsync(hc.data(), poly_coef, hc.size(), hipMemcpyDeviceToHost, st));
+            MR1L_HIP(hipStreamSynchronize(st));
+        }
         const int F1 = d * P.r;
-        const int64_t T1 = (int64_t)F1 * poly_s;
+        const int64_t T1 = (int64_t)F1 * ps;
         std::vector<int64_t> rf((size_t)d * T1), toff(F1 + 1);
         std::vector<unsigned char> rcf((size_t)T1 * esz);
         std::vector<uint32_t> anc1((size_t)F1 * (d - 1));
+        std::vector<uint64_t> bdims((size_t)F1 * std::max(1, P.bs_n));
         for (int f = 0; f < F1; ++f) {
             const int t = f / P.r + 1, i = f % P.r + 1;
-            toff[f] = (int64_t)f * poly_s;
-            for (int64_t q = 0; q < poly_s; ++q) {
+            toff[f] = (int64_t)f * ps;
+            for (int q = 0; q < (bsp ? P.bs_n : 0); ++q) {
+                uint64_t m = (P.bs_dims[q] >> (t - 1)) & 1u;
+                int row = 1;
+                for (int u = 0; u < d; ++u)
+                    if (u != t - 1) m |= ((P.bs_dims[q] >> u) & 1u) << (row++);
+                bdims[(size_t)f * P.bs_n + q] = m;
+            }
+            for (int64_t q = 0; q < ps; ++q) {
                 const int64_t col = (int64_t)f * poly_s + q;
                 rf[col] = hf[(size_t)(t - 1) * poly_s + q];
                 int row = 1;
@@ -158,12 +172,14 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
         DevBuf<int64_t> drf, dtoff;
         DevBuf<unsigned char> drc;
         DevBuf<uint32_t> danc1;
-        if ((rc = drf.need((int64_t)rf.size())) || (rc = dtoff.need(F1 + 1)) || (rc = drc.need((int64_t)rcf.size())) ||
-            (rc = danc1.need((int64_t)anc1.size())))
+        if ((rc = drf.need(std::max<int64_t>(1, (int64_t)rf.size()))) || (rc = dtoff.need(F1 + 1)) ||
+            (rc = drc.need(std::max<int64_t>(1, (int64_t)rcf.size()))) || (rc = danc1.need((int64_t)anc1.size())))
             return rc;
-        MR1L_HIP(hipMemcpyAsync(drf.p, rf.data(), rf.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        if (ps > 0) {
+            MR1L_HIP(hipMemcpyAsync(drf.p, rf.data(), rf.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            MR1L_HIP(hipMemcpyAsync(drc.p, rcf.data(), rcf.size(), hipMemcpyHostToDevice, st));
+        }
         MR1L_HIP(hipMemcpyAsync(dtoff.p, toff.data(), toff.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        MR1L_HIP(hipMemcpyAsync(drc.p, rcf.data(), rcf.size(), hipMemcpyHostToDevice, st));
         MR1L_HIP(hipMemcpyAsync(danc1.p, anc1.data(), anc1.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
         std::vector<int64_t> M1(F1, K), z1(F1, 1);
         PlanHolder p1;
@@ -173,7 +189,12 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
             (rc = det_idx.need(nodes1)) || (rc = det_coef.need(nodes1 * esz)) || (rc = n_o.need(F1)) ||
             (rc = out_idx.need((int64_t)F1 * P.s_local)) || (rc = out_coef.need((int64_t)F1 * P.s_local * esz)))
             return rc;
-        if ((rc = mr1l_sample(p1.p, d, dtoff.p, T1, drf.p, drc.p, danc1.p, fbuf.p, 1))) return rc;
+        if (bsp) {
+            if ((rc = bspline_sample_run(plan_of(p1.p), d, P.bs_n, P.bs_order, bdims.data(), danc1.p, fbuf.p)))
+                return rc;
+        } else if ((rc = mr1l_sample(p1.p, d, dtoff.p, T1, drf.p, drc.p, danc1.p, fbuf.p, 1))) {
+            return rc;
+        }
         if ((rc = mr1l_fft(p1.p, fbuf.p, gbuf.p, P.theta, nullptr))) return rc;
         const dim3 gg((unsigned)std::min<int64_t>((K + 255) / 256, 64), (unsigned)F1);
         if (P.dtype == MR1L_C128)
@@ -241,7 +262,8 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
         const int64_t nodes = (int64_t)L * P.M;
         if ((rc = fbuf.need(nodes * esz)) || (rc = gbuf.need(nodes * esz)) || (rc = bitmap.need((nodes + 31) / 32)))
             return rc;
-        const int64_t ecap = kMaxCap;
+        // detected-list capacity: the LDS path while every candidate fits it, else the whole set
+        const int64_t ecap = std::min<int64_t>(kMaxCapLarge, std::max<int64_t>(nJ <= kMaxCap ? kMaxCap : nJ, s_t));
         if ((rc = n_det.need(1)) || (rc = det_idx.need(ecap)) || (rc = det_coef.need(ecap * esz)) ||
             (rc = n_o.need(1)) || (rc = out_idx.need(s_t)) || (rc = out_coef.need(s_t * esz)) ||
             (rc = danc.need(std::max(1, d - t))))
@@ -266,6 +288,10 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
             if (fn) {
                 if (fn(user, t, L, Ms.data(), z.data(), anc.data(), fbuf.p, stream) != 0)
                     return fail(MR1L_E_ARG, "sampling callback failed");
+            } else if (bsp) {
+                if ((rc = bspline_sample_run(plan_of(plan.p), d, P.bs_n, P.bs_order, P.bs_dims,
+                                             d > t ? danc.p : nullptr, fbuf.p)))
+                    return rc;
             } else if ((rc = mr1l_sample(plan.p, d, nullptr, poly_s, poly_freq, poly_coef, d > t ? danc.p : nullptr,
                                          fbuf.p, 1))) {
                 return rc;
@@ -281,7 +307,7 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
             MR1L_HIP(hipMemcpyAsync(&h_ndet, n_det.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
             MR1L_HIP(hipMemcpyAsync(&h_nout, n_o.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
             MR1L_HIP(hipStreamSynchronize(st));
-            if (h_ndet > ecap) return fail(MR1L_E_CAPACITY, "detected set exceeds 8192 entries in one step");
+            if (h_ndet > ecap) return fail(MR1L_E_CAPACITY, "detected set exceeds the capacity of one step");
             std::vector<int64_t> oi(h_nout);
             std::vector<unsigned char> oc(h_nout * esz);
             if (h_nout > 0) {

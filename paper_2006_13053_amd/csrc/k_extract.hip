@@ -368,6 +368,154 @@ __global__ __launch_bounds__(kSortThreads) void k_limit(
     }
 }
 
+// ------------------------------------------------------------------ global sort (large lists)
+// Detected lists longer than one workgroup's LDS sort (cap > 8192) are ordered by a
+// bitonic sort of (key, position) pairs in global memory, one segment of P = 2^e
+// pairs per function, ascending by (key, position).  Stages with a partner
+// distance of at most kGsortLocal / 2 run inside one workgroup's LDS.
+constexpr int kGsortLocal = 2048;   // pairs per workgroup in the LDS stages
+
+__device__ __forceinline__ void gs_cmpswap(uint64_t &ka, int32_t &pa, uint64_t &kb, int32_t &pb, bool asc)
+{
+    const bool gt = (ka > kb) || (ka == kb && pa > pb);
+    if (gt == asc) {
+        const uint64_t tk = ka; ka = kb; kb = tk;
+        const int32_t tp = pa; pa = pb; pb = tp;
+    }
+}
+
+// One stage (k, j) with j >= kGsortLocal / 2 over every segment.
+__global__ __launch_bounds__(256) void k_gsort_global(uint64_t *__restrict__ key, int32_t *__restrict__ pos,
+                                                      int64_t P, int64_t k, int64_t j)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= P / 2) return;
+    const int64_t base = (int64_t)blockIdx.y * P;
+    const int64_t i = 2 * t - (t & (j - 1));   // lower element of the pair
+    const int64_t x = base + i, y = x + j;
+    uint64_t ka = key[x], kb = key[y];
+    int32_t pa = pos[x], pb = pos[y];
+    gs_cmpswap(ka, pa, kb, pb, (i & k) == 0);
+    key[x] = ka; key[y] = kb;
+    pos[x] = pa; pos[y] = pb;
+}
+
+// All stages of merge size k with j < kGsortLocal, or (k0 == 0) the whole sort
+// up to merge size kGsortLocal, on blocks of kGsortLocal pairs in LDS.
+__global__ __launch_bounds__(kGsortLocal / 2) void k_gsort_local(uint64_t *__restrict__ key,
+                                                                 int32_t *__restrict__ pos, int64_t P, int64_t k0)
+{
+    __shared__ uint64_t sk[kGsortLocal];
+    __shared__ int32_t sp[kGsortLocal];
+    const int64_t base = (int64_t)blockIdx.y * P + (int64_t)blockIdx.x * kGsortLocal;
+    const int n = (int)min((int64_t)kGsortLocal, P);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) { sk[i] = key[base + i]; sp[i] = pos[base + i]; }
+    __syncthreads();
+    const int64_t off = (int64_t)blockIdx.x * kGsortLocal;   // position of the block in its segment
+    const int64_t kfirst = k0 ? k0 : 2;
+    const int64_t klast = k0 ? k0 : (int64_t)n;
+    for (int64_t k = kfirst; k <= klast; k <<= 1) {
+        for (int64_t j = (k0 ? min(k0, (int64_t)n) : k) >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+                const int i = 2 * t - (t & ((int)j - 1));
+                gs_cmpswap(sk[i], sp[i], sk[i + j], sp[i + j], ((off + i) & k) == 0);
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) { key[base + i] = sk[i]; pos[base + i] = sp[i]; }
+}
+
+// Sorts F segments of P (a power of two) pairs.
+int gsort_run(Plan &p, uint64_t *key, int32_t *pos, int64_t P)
+{
+    if (P <= 1) return MR1L_OK;
+    const int64_t lb = std::min<int64_t>(P, kGsortLocal);
+    const dim3 gl((unsigned)(P / lb), (unsigned)p.F);
+    hipLaunchKernelGGL(k_gsort_local, gl, dim3(kGsortLocal / 2), 0, p.stream, key, pos, P, (int64_t)0);
+    MR1L_LAUNCH_CHECK();
+    for (int64_t k = 2 * kGsortLocal; k <= P; k <<= 1) {
+        for (int64_t j = k >> 1; j >= kGsortLocal; j >>= 1) {
+            const dim3 g((unsigned)((P / 2 + 255) / 256), (unsigned)p.F);
+            hipLaunchKernelGGL(k_gsort_global, g, dim3(256), 0, p.stream, key, pos, P, k, j);
+            MR1L_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_gsort_local, gl, dim3(kGsortLocal / 2), 0, p.stream, key, pos, P, k);
+        MR1L_LAUNCH_CHECK();
+    }
+    return MR1L_OK;
+}
+
+// Detected indices into sort pairs (padding sorts last), and back.
+__global__ __launch_bounds__(256) void k_det_to_pairs(const int64_t *__restrict__ n_det, int64_t cap,
+                                                      const int64_t *__restrict__ det_idx, int64_t P,
+                                                      uint64_t *__restrict__ key, int32_t *__restrict__ pos)
+{
+    const int f = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const bool in = i < n_of(n_det, f, cap);
+    key[(int64_t)f * P + i] = in ? (uint64_t)det_idx[(int64_t)f * cap + i] : ~0ull;
+    pos[(int64_t)f * P + i] = in ? (int32_t)i : INT32_MAX;
+}
+
+__global__ __launch_bounds__(256) void k_pairs_to_det(const int64_t *__restrict__ n_det, int64_t cap, int64_t P,
+                                                      const uint64_t *__restrict__ key, int64_t *__restrict__ det_idx)
+{
+    const int f = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_of(n_det, f, cap)) return;
+    det_idx[(int64_t)f * cap + i] = (int64_t)key[(int64_t)f * P + i];
+}
+
+// Algorithm 4 keys of a long list: ~bits(|p|^2) for |p|^2 >= theta^2 (ascending key =
+// descending modulus), the position as tie-break; others sort last.
+template <typename T>
+__global__ __launch_bounds__(256) void k_limit_keys(const int64_t *__restrict__ n_det, int64_t cap,
+                                                    const typename cvec<T>::type *__restrict__ det_coef, T th2,
+                                                    int64_t P, uint64_t *__restrict__ key, int32_t *__restrict__ pos,
+                                                    int64_t *__restrict__ npass)
+{
+    using V = typename cvec<T>::type;
+    const int f = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    uint64_t k = ~0ull;
+    int32_t ps = INT32_MAX;
+    if (i < n_of(n_det, f, cap)) {
+        const V c = det_coef[(int64_t)f * cap + i];
+        const T m2 = c.x * c.x + c.y * c.y;
+        if (m2 >= th2) {
+            k = ~(uint64_t)__double_as_longlong((double)m2);
+            ps = (int32_t)i;
+        }
+    }
+    const uint64_t bal = __ballot(ps != INT32_MAX);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd((unsigned long long *)(npass + f), (unsigned long long)__popcll(bal));
+    key[(int64_t)f * P + i] = k;
+    pos[(int64_t)f * P + i] = ps;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_limit_emit(const int64_t *__restrict__ npass, int64_t cap,
+                                                    const int64_t *__restrict__ det_idx,
+                                                    const typename cvec<T>::type *__restrict__ det_coef, int64_t P,
+                                                    const int32_t *__restrict__ pos, int64_t s_cap,
+                                                    int64_t *__restrict__ n_out, int64_t *__restrict__ out_idx,
+                                                    typename cvec<T>::type *__restrict__ out_coef,
+                                                    int32_t *__restrict__ out_pos)
+{
+    const int f = blockIdx.y;
+    const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t no = min(npass[f], s_cap);
+    if (o == 0) n_out[f] = no;
+    if (o >= no) return;
+    const int32_t q = pos[(int64_t)f * P + o];
+    out_idx[(int64_t)f * s_cap + o] = det_idx[(int64_t)f * cap + q];
+    out_coef[(int64_t)f * s_cap + o] = det_coef[(int64_t)f * cap + q];
+    if (out_pos) out_pos[(int64_t)f * s_cap + o] = q;
+}
+
 // ------------------------------------------------------------------ adjoint scatter
 template <typename T>
 __global__ __launch_bounds__(256) void k_adjoint_scatter(
@@ -391,12 +539,12 @@ __global__ __launch_bounds__(256) void k_adjoint_scatter(
 
 // ------------------------------------------------------------------ host
 template <typename T>
-static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, const int32_t *det_hash,
+static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, int64_t nmax, const int32_t *det_hash,
                           const uint32_t *mask, const void *ghat, int postproc, void *det_coef, void *det_med,
                           double *det_w)
 {
     using V = typename cvec<T>::type;
-    dim3 grid((unsigned)((cap + 255) / 256), (unsigned)p.F), blk(256);
+    dim3 grid((unsigned)((nmax + 255) / 256), (unsigned)p.F), blk(256);
 #define MR1L_COMB(LM)                                                                                       \
     hipLaunchKernelGGL((k_combine<T, LM>), grid, blk, 0, p.stream, p.d_lat, p.L, n_det, cap, det_hash, mask, \
                        (const V *)ghat, postproc, (V *)det_coef, (V *)det_med, det_w)
@@ -408,7 +556,7 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, const int3
     else if (p.L <= 32) MR1L_COMB(32);
     else if (p.L <= 40) MR1L_COMB(40);
     else
-        hipLaunchKernelGGL(k_combine_wide<T>, dim3((unsigned)((cap + 63) / 64), (unsigned)p.F), dim3(64), 0, p.stream,
+        hipLaunchKernelGGL(k_combine_wide<T>, dim3((unsigned)((nmax + 63) / 64), (unsigned)p.F), dim3(64), 0, p.stream,
                            p.d_lat, p.L, n_det, cap, det_hash, mask, (const V *)ghat, postproc, (V *)det_coef,
                            (V *)det_med, det_w);
 #undef MR1L_COMB
@@ -435,20 +583,60 @@ static int64_t pow2ceil(int64_t n)
     return P;
 }
 
+static int grow_sort(Plan &p, int64_t P)
+{
+    const int64_t bytes = p.F * P * 12;
+    if (p.gsort_bytes >= bytes && p.d_gsort) return MR1L_OK;
+    if (p.capturing) return fail(MR1L_E_ARG, "lists longer than 8192 cannot be recorded in a graph");
+    if (p.d_gsort) (void)hipFree(p.d_gsort);
+    p.d_gsort = nullptr;
+    p.gsort_bytes = 0;
+    MR1L_HIP(hipMalloc(&p.d_gsort, (size_t)bytes));
+    p.gsort_bytes = bytes;
+    return MR1L_OK;
+}
+
 int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, const void *ghat,
                      const mr1l_extract_opts &o, const mr1l_extract_out &out, int32_t *det_hash, double *det_w,
                      uint32_t *det_mask, void *det_med, int32_t *out_pos)
 {
     const int64_t cap = o.cap;
-    const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
-    hipLaunchKernelGGL(k_sort_det, dim3(p.F), dim3(kSortThreads), pc * sizeof(int64_t), p.stream, out.n_det, cap,
-                       out.det_idx);
-    MR1L_LAUNCH_CHECK();
-    dim3 gq((unsigned)((cap * p.L + 255) / 256), (unsigned)p.F);
-    hipLaunchKernelGGL(k_det_hash, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat, p.d_z32,
-                       p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
-    MR1L_LAUNCH_CHECK();
-    int rc = launch_fill_u32(det_mask, (int64_t)p.F * cap * mask_words(p.L), 0u, p.stream);
+    const bool large = cap > kMaxCap;
+    int64_t nmax = cap, P = 1;
+    int rc = MR1L_OK;
+    uint64_t *skey = nullptr;
+    int32_t *spos = nullptr;
+    if (!large) {
+        const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
+        hipLaunchKernelGGL(k_sort_det, dim3(p.F), dim3(kSortThreads), pc * sizeof(int64_t), p.stream, out.n_det, cap,
+                           out.det_idx);
+        MR1L_LAUNCH_CHECK();
+    } else {
+        // the sort sizes come from the detected counts: one synchronisation
+        if (p.capturing) return fail(MR1L_E_ARG, "lists longer than 8192 cannot be recorded in a graph");
+        std::vector<int64_t> nd((size_t)p.F);
+        MR1L_HIP(hipMemcpyAsync(nd.data(), out.n_det, nd.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p.stream));
+        MR1L_HIP(hipStreamSynchronize(p.stream));
+        nmax = 0;
+        for (int64_t v : nd) nmax = std::max(nmax, std::min(v, cap));
+        P = pow2ceil(std::max<int64_t>(nmax, 1));
+        if ((rc = grow_sort(p, P))) return rc;
+        skey = (uint64_t *)p.d_gsort;
+        spos = (int32_t *)(skey + p.F * P);
+        const dim3 gp((unsigned)((P + 255) / 256), (unsigned)p.F);
+        hipLaunchKernelGGL(k_det_to_pairs, gp, dim3(256), 0, p.stream, out.n_det, cap, out.det_idx, P, skey, spos);
+        MR1L_LAUNCH_CHECK();
+        if ((rc = gsort_run(p, skey, spos, P))) return rc;
+        hipLaunchKernelGGL(k_pairs_to_det, gp, dim3(256), 0, p.stream, out.n_det, cap, P, skey, out.det_idx);
+        MR1L_LAUNCH_CHECK();
+    }
+    if (nmax > 0) {
+        dim3 gq((unsigned)((nmax * p.L + 255) / 256), (unsigned)p.F);
+        hipLaunchKernelGGL(k_det_hash, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat, p.d_z32,
+                           p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
+        MR1L_LAUNCH_CHECK();
+    }
+    rc = launch_fill_u32(det_mask, (int64_t)p.F * cap * mask_words(p.L), 0u, p.stream);
     if (rc) return rc;
     int64_t maxM = 1;
     for (int64_t m : p.M) maxM = std::max(maxM, m);
@@ -456,28 +644,53 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     hipLaunchKernelGGL(k_singleton, dim3(p.L, p.F), dim3(256), 2 * (size_t)words * sizeof(uint32_t), p.stream,
                        p.d_lat, p.L, out.n_det, cap, det_hash, det_mask, words);
     MR1L_LAUNCH_CHECK();
+    const int64_t ncomb = std::max<int64_t>(nmax, 1);
     if (p.dtype == MR1L_C128)
-        rc = combine_launch<double>(p, out.n_det, cap, det_hash, det_mask, ghat, o.postproc, out.det_coef,
+        rc = combine_launch<double>(p, out.n_det, cap, ncomb, det_hash, det_mask, ghat, o.postproc, out.det_coef,
                                     det_med, det_w);
     else
-        rc = combine_launch<float>(p, out.n_det, cap, det_hash, det_mask, ghat, o.postproc, out.det_coef,
+        rc = combine_launch<float>(p, out.n_det, cap, ncomb, det_hash, det_mask, ghat, o.postproc, out.det_coef,
                                    det_med, det_w);
     if (rc) return rc;
-    if (p.dtype == MR1L_C128) {
-        hipLaunchKernelGGL(k_limit<double>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap,
-                           out.det_idx, (const double2 *)out.det_coef, o.theta * o.theta, o.s_cap, out.n_out,
-                           out.out_idx, (double2 *)out.out_coef, out_pos);
-    } else {
-        hipLaunchKernelGGL(k_limit<float>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap,
-                           out.det_idx, (const float2 *)out.det_coef, (float)(o.theta * o.theta), o.s_cap,
-                           out.n_out, out.out_idx, (float2 *)out.out_coef, out_pos);
+    if (!large) {
+        const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
+        if (p.dtype == MR1L_C128) {
+            hipLaunchKernelGGL(k_limit<double>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap,
+                               out.det_idx, (const double2 *)out.det_coef, o.theta * o.theta, o.s_cap, out.n_out,
+                               out.out_idx, (double2 *)out.out_coef, out_pos);
+        } else {
+            hipLaunchKernelGGL(k_limit<float>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap,
+                               out.det_idx, (const float2 *)out.det_coef, (float)(o.theta * o.theta), o.s_cap,
+                               out.n_out, out.out_idx, (float2 *)out.out_coef, out_pos);
+        }
+        MR1L_LAUNCH_CHECK();
+        return MR1L_OK;
     }
+    // Algorithm 4 on a long list: keys, global sort, first s~
+    int64_t *npass = p.d_det_tmp;
+    if ((rc = launch_fill_bytes(npass, p.F * (int64_t)sizeof(int64_t), p.stream))) return rc;
+    const dim3 gp((unsigned)((P + 255) / 256), (unsigned)p.F);
+    if (p.dtype == MR1L_C128)
+        hipLaunchKernelGGL(k_limit_keys<double>, gp, dim3(256), 0, p.stream, out.n_det, cap,
+                           (const double2 *)out.det_coef, o.theta * o.theta, P, skey, spos, npass);
+    else
+        hipLaunchKernelGGL(k_limit_keys<float>, gp, dim3(256), 0, p.stream, out.n_det, cap,
+                           (const float2 *)out.det_coef, (float)(o.theta * o.theta), P, skey, spos, npass);
+    MR1L_LAUNCH_CHECK();
+    if ((rc = gsort_run(p, skey, spos, P))) return rc;
+    const dim3 ge((unsigned)((o.s_cap + 255) / 256), (unsigned)p.F);
+    if (p.dtype == MR1L_C128)
+        hipLaunchKernelGGL(k_limit_emit<double>, ge, dim3(256), 0, p.stream, npass, cap, out.det_idx,
+                           (const double2 *)out.det_coef, P, spos, o.s_cap, out.n_out, out.out_idx,
+                           (double2 *)out.out_coef, out_pos);
+    else
+        hipLaunchKernelGGL(k_limit_emit<float>, ge, dim3(256), 0, p.stream, npass, cap, out.det_idx,
+                           (const float2 *)out.det_coef, P, spos, o.s_cap, out.n_out, out.out_idx,
+                           (float2 *)out.out_coef, out_pos);
     MR1L_LAUNCH_CHECK();
     return MR1L_OK;
 }
 
-// Algorithm 4 alone over given lists (det_idx [F][cap] in candidate order,
-// det_coef [F][cap], n_det [F] on the device).
 int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef, double theta,
               int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef)
 {

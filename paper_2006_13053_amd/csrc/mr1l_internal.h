@@ -13,6 +13,9 @@
 
 namespace mr1l {
 
+// detected lists longer than kMaxCap are sorted in global memory (one stream synchronisation)
+constexpr int64_t kMaxCapLarge = int64_t(1) << 24;
+
 // ---------------------------------------------------------------- DFT schedules
 // How the Bluestein transform of one lattice runs.  Schedule 0 holds the whole
 // 5-smooth-length transform in one workgroup's LDS; the others are power-of-two
@@ -100,6 +103,10 @@ struct Plan {
     void *d_ex_med = nullptr;        // [F][cap] complex
     int32_t *d_ex_pos = nullptr;     // [F][s_cap]
     int64_t ex_scap = 0;
+    void *d_gsort = nullptr;         // global sort pairs of long detected lists: [F][P] uint64 + [F][P] int32
+    int64_t gsort_bytes = 0;
+    void *d_bs_dims = nullptr;       // B-spline sampler: [F][n_prod] coordinate masks
+    int64_t bs_bytes = 0;
     void *d_ls = nullptr;            // least squares: [F][cap][L] int32 representatives + 3 [F][cap] complex
     int64_t ls_bytes = 0;
     int64_t *d_setoff_default = nullptr; // [2] = {0, n} for F == 1 calls
@@ -165,6 +172,8 @@ int plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, const int6
 int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef, double theta,
               int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef);
 int check_injective_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, int32_t *ok);
+int bspline_sample_run(Plan &p, int32_t d_poly, int32_t n_prod, const int32_t *order, const uint64_t *dims,
+                       const uint32_t *anchor, void *f);
 int lsq_init_attrs();
 int lsq_run(Plan &p, int64_t cap, const int64_t *n_det, const int32_t *det_hash, const uint32_t *det_mask,
             const void *ghat, int32_t max_iter, double tol, void *coef, double *resid, int32_t *iters,

@@ -223,3 +223,68 @@ def weighted_cross_member(gamma: np.ndarray, bound: float, weight_exp: float) ->
     for t in range(1, gamma.shape[0] + 1):
         prod = prod * np.maximum(1.0, float(t) ** weight_exp * np.abs(gamma[t - 1]))
     return prod <= bound
+
+
+# ----------------------------------------------------------------------------- Section 4.2.3
+# eq. (4.3): products over the coordinates {1,3,8}, {2,5,6,10}, {4,7,9} (1-based) of the
+# B-splines N_2, N_4, N_6.
+EQ43_ORDERS = (2, 4, 6)
+EQ43_SETS = ((1, 3, 8), (2, 5, 6, 10), (4, 7, 9))
+
+
+def eq43_function():
+    """(orders, coordinate bit masks) of the test function eq. (4.3), d = 10."""
+    masks = [sum(1 << (u - 1) for u in S) for S in EQ43_SETS]
+    return list(EQ43_ORDERS), masks
+
+
+def bspline_const(m: int) -> float:
+    """C_m of N_m(x) = C_m sum_k sinc(pi k/m)^m (-1)^k e^{2 pi i k x} with unit L2 norm:
+    C_m^-2 = sum_k sinc(pi k/m)^{2m} (Parseval), summed to |k| <= 2*10^5."""
+    k = np.arange(1, 200001, dtype=np.float64)
+    x = np.pi * k / m
+    return float(1.0 / math.sqrt(1.0 + 2.0 * np.sum((np.sin(x) / x) ** (2 * m))))
+
+
+def bspline_coefficients(freq, orders, masks) -> np.ndarray:
+    """Fourier coefficients of sum_j prod_{u in S_j} N_{m_j}(x_u) at the frequencies
+    freq [n, d]: product j contributes prod_{u in S_j} C_m sinc(pi k_u/m)^m (-1)^{k_u}
+    when k_u = 0 outside S_j."""
+    freq = np.asarray(freq, np.int64)
+    n, d = freq.shape
+    out = np.zeros(n, np.float64)
+    for m, mask in zip(orders, masks):
+        inside = np.array([(mask >> u) & 1 for u in range(d)], bool)
+        ok = np.all(freq[:, ~inside] == 0, axis=1)
+        c = bspline_const(m)
+        val = np.ones(n)
+        for u in np.nonzero(inside)[0]:
+            k = freq[:, u].astype(np.float64)
+            x = np.pi * k / m
+            sinc = np.where(k == 0, 1.0, np.sin(x) / np.where(k == 0, 1.0, x))
+            val = val * c * sinc ** m * np.where(freq[:, u] % 2 == 0, 1.0, -1.0)
+        out += np.where(ok, val, 0.0)
+    return out.astype(np.complex128)
+
+
+def bspline_norm2(orders, masks) -> float:
+    """||f||_2^2 for products on pairwise disjoint coordinate sets: each product has
+    unit norm, and two products on disjoint sets overlap only through their means
+    C_m^{|S|}."""
+    sets = [int(mk) for mk in masks]
+    for a in range(len(sets)):
+        for b in range(a + 1, len(sets)):
+            if sets[a] & sets[b]:
+                raise ValueError("coordinate sets must be disjoint")
+    means = [bspline_const(m) ** bin(mk).count("1") for m, mk in zip(orders, sets)]
+    return float(len(sets) + 2 * sum(means[a] * means[b] for a in range(len(sets)) for b in range(a + 1, len(sets))))
+
+
+def bspline_rel_l2_error(freq, coef, orders, masks) -> float:
+    """Relative L2 error of the trigonometric polynomial (freq, coef) as an
+    approximation of the test function (Section 4.2.3): sqrt(||f||^2 - sum_I |f_k|^2 +
+    sum_I |p_k - f_k|^2) / ||f||."""
+    fk = bspline_coefficients(freq, orders, masks)
+    nf2 = bspline_norm2(orders, masks)
+    e2 = nf2 - float(np.sum(np.abs(fk) ** 2)) + float(np.sum(np.abs(np.asarray(coef) - fk) ** 2))
+    return math.sqrt(max(e2, 0.0) / nf2)

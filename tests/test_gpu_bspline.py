@@ -1,0 +1,93 @@
+"""The test function of eq. (4.3) (Section 4.2.3): the library's B-spline sampler and
+the dimension-incremental driver on it, against the oracle and against the relative
+L2 errors the paper prints (Table 4.4)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def m():
+    import paper_2006_13053_amd as mod
+    mod.lib()
+    torch.cuda.set_device(0)
+    return mod
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+@pytest.mark.parametrize("t", [1, 3, 10])
+def test_sampler_matches_oracle(m, t):
+    """eq. (4.3) in d = 10 at lattice nodes in t coordinates with 10 - t anchors;
+    two functions with different coordinate masks."""
+    say("bspline sampler t", t)
+    rng = np.random.default_rng(t)
+    orders, masks = synth.eq43_function()
+    masks2 = [masks[1], masks[2], masks[0]]
+    M, z = synth.draw_lattices(rng, 6, t, 100, 600)
+    anc = rng.integers(0, 2**32, size=(2, 10 - t), dtype=np.uint64).astype(np.uint32)
+    plan = m.Plan(t, np.concatenate([M, M]), np.concatenate([z, z]), F=2)
+    f = m.mr1l_sample_bspline(plan, 10, orders, np.array([masks, masks2], np.uint64),
+                              anchor=T(anc.view(np.int32)) if t < 10 else None)
+    torch.cuda.synchronize()
+    got = f.cpu().numpy()
+    n = int(M.sum())
+    for fi, mk in enumerate((masks, masks2)):
+        want = oracle.sample_bspline(orders, mk, M, z, anchor=anc[fi] if t < 10 else None, t=t)
+        err = np.abs(got[fi * n:(fi + 1) * n] - want).max() / np.abs(want).max()
+        assert err < 1e-13, (fi, err)
+
+
+@pytest.mark.parametrize("step1", [False, True])
+def test_driver_matches_oracle_without_truncation(m, step1):
+    """Small case where every step keeps all its candidates (s_local >= |J_t|, s = |J_d|):
+    the same frequencies and coefficients as the oracle's driver on the same draws."""
+    say("bspline driver parity step1", step1)
+    orders, masks = [2, 4, 6], [0b001, 0b010, 0b100]
+    d, N, s = 3, 4, 729
+    Mlat = 1009
+    fg, cg, ng = m.mr1l_dimincr(d, N, s, s, 2, 1e-12, Mlat, 31, cap=1 << 14, step1=step1,
+                                bspline=(orders, masks))
+    fo, co, no = oracle.dimincr(None, None, N=N, s=s, s_local=s, r=2, theta=1e-12, c=10.33, delta=0.9,
+                                Mlat=Mlat, seed=31, step1=step1, bspline=(orders, masks), d=d)
+    say("n", len(fg), len(fo), "samples", ng, no)
+    assert ng == no and len(fg) == len(fo) == 729
+    assert np.array_equal(fg, fo)
+    assert np.abs(cg - co).max() < 1e-11 * np.abs(co).max()
+
+
+@pytest.mark.parametrize("N,s,printed", [(16, 1000, 1.2e-2), (16, 2000, 4.1e-3)])
+def test_relative_error_matches_table_4_4(m, N, s, printed):
+    """Table 4.4 (Algorithm 3 with random lattices): the maximum relative L2 error over
+    three runs stays within 1.5 times the printed maximum over ten runs (the lattice
+    sizes of the paper's runs are not given; here M = nextprime(10.33 s_local))."""
+    orders, masks = synth.eq43_function()
+    Mlat = synth.next_prime_above(10.33 * 2 * s)
+    errs = []
+    for seed in range(3):
+        fr, co, ns = m.mr1l_dimincr(10, N, s, 2 * s, 5, 1e-12, Mlat, 1000 + seed, delta=0.999, cap=1 << 20,
+                                    step1=True, bspline=(orders, masks))
+        err = synth.bspline_rel_l2_error(fr, co, orders, masks)
+        say("N", N, "s", s, "seed", seed, "n", len(fr), "samples", ns, "rel L2 error", err)
+        errs.append(err)
+        assert len(fr) == s
+    assert max(errs) < 1.5 * printed

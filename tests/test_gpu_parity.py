@@ -441,6 +441,57 @@ def test_injectivity_check_matches_definition(m):
     assert list(ok) == [c[3] for c in sel] and ok_all == all(c[3] for c in sel)
 
 
+@pytest.mark.parametrize("seed,F", [(1, 1), (2, 2)])
+def test_long_detected_lists_match_oracle(m, seed, F):
+    """Detected lists longer than 8192 (global-memory sorts): noise samples make every
+    bucket non-zero, so every candidate is detected; Algorithm 4 keeps the 10000
+    largest medians.  Against the oracle per function, and against the LDS path on
+    the same pass truncated to fit."""
+    say("long lists", seed, F)
+    rng = np.random.default_rng(100 + seed)
+    d, L = 4, 7
+    sets, Ms, zs, fs = [], [], [], []
+    for fi in range(F):
+        n = 30000 - 7000 * fi
+        sets.append(synth.distinct_uniform_points(rng, n, d, -60, 60))
+        M, z = synth.draw_lattices(rng, L, d, 1500, 2500)
+        Ms.append(M)
+        zs.append(z)
+        fs.append(rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum())))
+    plan = m.Plan(d, np.concatenate(Ms), np.concatenate(zs), F=F)
+    g, bm = m.mr1l_fft(plan, T(np.concatenate(fs)), 1e-9)
+    off = np.concatenate([[0], np.cumsum([x.shape[1] for x in sets])]).astype(np.int64)
+    cand = T(np.concatenate(sets, axis=1))
+    ex = m.mr1l_extract(plan, cand, g, bm, 1e-9, s_cap=10000, cap=32768, set_off=T(off), want_w=False)
+    torch.cuda.synchronize()
+    for fi in range(F):
+        go = oracle.dft(fs[fi], Ms[fi])
+        ro = oracle.extract(sets[fi], Ms[fi], zs[fi], go, 1e-9, s_cap=10000, cap=32768)
+        nd = int(ex["n_det"][fi])
+        assert nd == ro["n_det"] == sets[fi].shape[1]
+        assert np.array_equal(ex["det_idx"][fi, :nd].cpu().numpy(), ro["det_idx"])
+        assert np.array_equal(mask64(ex["det_mask"][fi, :nd]), ro["det_mask"])
+        close(ex["det_coef"][fi, :nd].cpu().numpy(), ro["det_coef"], 1e-11, "coefficients")
+        no = int(ex["n_out"][fi])
+        r = dict(out_idx=ex["out_idx"][fi, :no].cpu().numpy(), out_coef=ex["out_coef"][fi, :no].cpu().numpy())
+        check_limit(r, ro, EPS[torch.complex128], 1e-11)
+        assert np.array_equal(ex["det_idx"][fi, ex["out_pos"][fi, :no].long()].cpu().numpy(), r["out_idx"])
+    # a list that fits one workgroup's sort: the LDS path (cap 8192) and the global
+    # path (cap 9000) give identical results
+    sub = [x[:, :6000] for x in sets]
+    off2 = T(np.arange(F + 1, dtype=np.int64) * 6000)
+    cs = T(np.concatenate(sub, axis=1))
+    outs = [m.mr1l_extract(plan, cs, g, bm, 1e-9, s_cap=3000, cap=c, set_off=off2, want_w=False) for c in (8192, 9000)]
+    torch.cuda.synchronize()
+    a, b = outs
+    for fi in range(F):
+        assert int(a["n_det"][fi]) == int(b["n_det"][fi]) == 6000
+        assert torch.equal(a["det_idx"][fi, :6000], b["det_idx"][fi, :6000])
+        assert torch.equal(a["det_coef"][fi, :6000], b["det_coef"][fi, :6000])
+        assert int(a["n_out"][fi]) == int(b["n_out"][fi])
+        assert torch.equal(a["out_idx"][fi], b["out_idx"][fi]) and torch.equal(a["out_coef"][fi], b["out_coef"][fi])
+
+
 def test_empty_and_ragged_inputs(m):
     say("empty/ragged")
     p = synth.small_config(8)

@@ -41,6 +41,11 @@ MUTANTS = {
     "step1_coordinate": ("pf[q] = poly_freq[(int64_t)(t - 1) * s_poly + q];", "pf[q] = poly_freq[(int64_t)t % d * s_poly + q];"),
     "median_weight_even": ("wq[2 * vs[L / 2].l + part] = 1.0;", "wq[2 * vs[0].l + part] = 1.0;"),
     "mask_32_bits": ("mask |= 1ull << l;", "mask |= 1u << (l & 31);"),
+    "bspline_sign": ("s += ((j & 1) ? -binom : binom) * pw;", "s += binom * pw;"),
+    "bspline_norm_power": ("for (int32_t e = 0; e < 2 * m; ++e) p *= sc;", "for (int32_t e = 0; e < m; ++e) p *= sc;"),
+    "bspline_scale": ("return bspline_norm_const(m) * (ld)m * trunc_power_bspline(m, (ld)m * x);",
+                      "return bspline_norm_const(m) * trunc_power_bspline(m, (ld)m * x);"),
+    "bspline_anchor": ("else x = (ld)anchor[u - t] / 4294967296.0L;", "else x = (ld)anchor[0] / 4294967296.0L;"),
     "pfpn_pfn_threshold": ("(med > 1.0 ? 2 : 0)", "(med >= 1.0 ? 2 : 0)"),
     "pfpn_pfp_threshold": ("(med > 0.0 ? 1 : 0)", "(med > 0.5 ? 1 : 0)"),
     "pfpn_alone": ("M[l])] == 1;\n        if", "M[l])] <= 2;\n        if"),

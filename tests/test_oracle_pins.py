@@ -651,3 +651,78 @@ def test_lsq_exact_with_false_positives():
     want = np.zeros(len(det), np.complex128)
     want[np.searchsorted(det, supp)] = coef
     assert np.abs(c - want).max() < 1e-10
+
+
+# ------------------------------------------------------------------ eq. (4.3) test function
+@pytest.mark.parametrize("m,tol", [(2, 2e-6), (4, 1e-12), (6, 1e-14)])
+def test_bspline_fourier_series(m, tol):
+    """Sec. 4.2.3: the lattice DFT of the oracle's N_m samples on 1201 equispaced points
+    equals the printed series C_m sinc(pi k/m)^m (-1)^k up to aliasing (about the
+    coefficient size at k ~ 1201)."""
+    G = 1201
+    f = oracle.sample_bspline([m], [1], np.array([G]), np.array([[1]]))
+    g = oracle.dft(f, np.array([G]))
+    k = np.arange(-20, 21)
+    want = synth.bspline_coefficients(k[:, None], [m], [1])
+    assert np.abs(g[k % G] - want).max() < tol
+    assert abs(np.mean(np.abs(f) ** 2) - 1.0) < 10 * tol      # unit L2 norm (Parseval)
+
+
+def test_bspline_symmetry_and_partition_of_unity():
+    """B_m is symmetric about m/2 and its integer shifts sum to one, so
+    N_m(x) = N_m(1 - x) and sum_i N_m((y + i)/m) = C_m m."""
+    rng = np.random.default_rng(2)
+    for m in (1, 2, 3, 4, 6):
+        c = synth.bspline_const(m)
+        for y in rng.uniform(0, 1, 8):
+            assert abs(oracle.bspline_periodic(m, y) - oracle.bspline_periodic(m, 1 - y)) < 1e-12
+            s = sum(oracle.bspline_periodic(m, (y + i) / m) for i in range(m))
+            assert abs(s - c * m) < 1e-12
+
+
+def test_bspline_tensor_products_at_lattice_nodes():
+    """Sums of tensor products at lattice nodes with anchors: each node's value is the
+    product formula evaluated at x_u = j z_u / M mod 1 (u < t) and a_u / 2^32."""
+    rng = np.random.default_rng(3)
+    orders, masks = [2, 4], [0b00101, 0b11010]
+    M = np.array([97, 101])
+    z = rng.integers(0, 97, size=(2, 2))
+    anc = rng.integers(0, 2**32, size=3, dtype=np.uint64).astype(np.uint32)
+    f = oracle.sample_bspline(orders, masks, M, z, anchor=anc, t=2)
+    off = 0
+    for l in range(2):
+        for j in range(0, int(M[l]), 7):
+            x = [(j * int(z[l, u]) % int(M[l])) / int(M[l]) for u in range(2)] + [int(a) / 2**32 for a in anc]
+            want = sum(math.prod(oracle.bspline_periodic(mq, x[u]) for u in range(5) if (mk >> u) & 1)
+                       for mq, mk in zip(orders, masks))
+            assert abs(f[off + j] - want) < 1e-12
+        off += int(M[l])
+
+
+def test_bspline_norm_of_sum_closed_form():
+    """||f||^2 of a sum of products on disjoint coordinate sets (the form of eq. (4.3)),
+    against the sum of squared coefficients over a large grid (d = 3)."""
+    orders, masks = [4, 6], [0b011, 0b100]
+    K = 40
+    grid = np.stack(np.meshgrid(*[np.arange(-K, K + 1)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    c = synth.bspline_coefficients(grid, orders, masks)
+    assert abs(np.sum(np.abs(c) ** 2) - synth.bspline_norm2(orders, masks)) < 1e-8
+
+
+def test_dimincr_bspline_close_to_best_s_term():
+    """Algorithm 3 on a compressible function (eq. (4.3) type, d = 4, N = 8): the
+    driver's relative L2 error is within a factor 1.5 of the best s-term error over
+    [-8, 8]^4 (closed-form coefficients), with and without Step 1."""
+    orders, masks = [4, 2], [0b0011, 0b1100]
+    d, N, s = 4, 8, 40
+    grid = np.stack(np.meshgrid(*[np.arange(-N, N + 1)] * d, indexing="ij"), -1).reshape(-1, d)
+    c = np.abs(synth.bspline_coefficients(grid, orders, masks))
+    top = np.sort(c)[::-1]
+    nf2 = synth.bspline_norm2(orders, masks)
+    best = math.sqrt((nf2 - float(np.sum(top[:s] ** 2))) / nf2)
+    Mlat = synth.next_prime_above(10.33 * 2 * s)
+    for step1 in (False, True):
+        fr, co, ns = oracle.dimincr(None, None, N=N, s=s, s_local=2 * s, r=3, theta=1e-12, c=10.33, delta=0.9,
+                                    Mlat=Mlat, seed=4, step1=step1, bspline=(orders, masks), d=d)
+        err = synth.bspline_rel_l2_error(fr, co, orders, masks)
+        assert len(fr) == s and err < 1.5 * best, (step1, err, best)
