@@ -447,6 +447,60 @@ def bench_worst_case(m, torch, args):
     print(json.dumps(out), flush=True)
 
 
+# ----------------------------------------------------------------------------- Table 4.4
+def bench_bspline(m, torch, args):
+    """Algorithm 3 (Steps 1 and 2, Algorithm 4 as the detection method) on the test
+    function eq. (4.3) in d = 10 over the (N, s) grid of Table 4.4: r = 5, s_local = 2s,
+    delta = 0.999, theta = 1e-12, every lattice of size nextprime(10.33 s_local);
+    args.reps runs per row (seeds 0, 1, ...).  Reports the largest relative L2 error
+    and sample count per row next to the printed ones, and the wall time per run."""
+    import synth
+    gpath = os.path.join(ROOT, "tests", "golden", "table_4_4_bspline.json")
+    with open(gpath) as fh:
+        rows = json.load(fh)["rows"]
+    if args.rows:
+        rows = [r for r in rows if f"{r['N']}:{r['s']}" in args.rows.split(",")]
+    orders, masks = synth.eq43_function()
+    out_rows, times = [], []
+    for row in rows:
+        N, s = row["N"], row["s"]
+        Mlat = synth.next_prime_above(10.33 * (s if args.m_of == "s" else 2 * s))
+        errs, errs_ls, samp, ts = [], [], [], []
+        for seed in range(args.reps):
+            for lsq in (0, args.lsq_iters):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fr, co, ns = m.mr1l_dimincr(10, N, s, 2 * s, 5, 1e-12, Mlat, 1000 + seed, delta=0.999,
+                                            cap=1 << 20, step1=True, bspline=(orders, masks), lsq_iters=lsq)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                e = synth.bspline_rel_l2_error(fr, co, orders, masks)
+                if lsq:
+                    errs_ls.append(e)
+                else:
+                    errs.append(e)
+                    ts.append(dt)
+                    samp.append(ns)
+        log(f"N {N} s {s}: max rel L2 error {max(errs):.3e}, with least squares {max(errs_ls):.3e} "
+            f"(printed {row['max_rel_l2_error']:.1e}), max samples {max(samp)} (printed {row['max_samples']}), "
+            f"{np.mean(ts):.2f} s per run")
+        out_rows.append(dict(N=N, s=s, M=Mlat, runs=args.reps, max_rel_l2_error=max(errs),
+                             max_rel_l2_error_least_squares=max(errs_ls),
+                             printed_max_rel_l2_error=row["max_rel_l2_error"], max_samples=max(samp),
+                             printed_max_samples=row["max_samples"], s_per_run=float(np.mean(ts))))
+        times += ts
+    out = {"metric": "dimension-incremental run time on the eq. (4.3) function (mean over the Table 4.4 grid)",
+           "value": float(np.mean(times)), "unit": "s", "n_gpus": 1, "steps": len(times), "warmup": 0,
+           "ms_per_step": 1000.0 * float(np.mean(times)), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+           "config": {"workload": "Table 4.4: f of eq. (4.3), d = 10, r = 5, s_local = 2s, delta = 0.999, "
+                                  f"theta = 1e-12, Steps 1 and 2, M = nextprime(10.33 {args.m_of}); each run "
+                                  "also with the least-squares final step",
+                      "rows": [f"{r['N']}:{r['s']}" for r in out_rows]},
+           "rows": out_rows}
+    print(json.dumps(out), flush=True)
+
+
 # ----------------------------------------------------------------------------- oracle legs
 def cpu_baseline_large(w, n_sample, budget_s=10.0):
     """Oracle on one function of the batch, repeated until ~budget_s of CPU time: direct
@@ -510,8 +564,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("large", "batch", "dimincr", "worst-case"), default="large")
-    ap.add_argument("--reps", type=int, default=1000, help="worst-case workload: repetitions per L")
+    ap.add_argument("--workload", choices=("large", "batch", "dimincr", "worst-case", "bspline"), default="large")
+    ap.add_argument("--lsq-iters", type=int, default=200,
+                    help="bspline workload: CG iterations of the least-squares final step (second run per seed)")
+    ap.add_argument("--m-of", choices=("s", "s_local"), default="s",
+                    help="bspline workload: lattice size nextprime(10.33 s) or nextprime(10.33 s_local)")
+    ap.add_argument("--rows", default="", help="bspline workload: comma-separated N:s rows of Table 4.4 (default all)")
+    ap.add_argument("--reps", type=int, default=None,
+                    help="worst-case workload: repetitions per L (1000); bspline workload: runs per row (3)")
     ap.add_argument("--experiment", choices=("both", "random_3d", "hyperbolic_cross_8d"), default="both",
                     help="worst-case workload: which experiment of Section 4.1")
     ap.add_argument("--functions", type=int, default=None)
@@ -545,7 +605,11 @@ def main():
     if args.workload == "dimincr":
         return bench_dimincr(m, torch, args)
     if args.workload == "worst-case":
+        args.reps = args.reps or 1000
         return bench_worst_case(m, torch, args)
+    if args.workload == "bspline":
+        args.reps = args.reps or 3
+        return bench_bspline(m, torch, args)
 
     if args.workload == "large":
         F = args.functions or 64

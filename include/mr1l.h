@@ -287,7 +287,7 @@ int mr1l_check_injective(mr1l_plan p, int64_t n_total, const int64_t *set_off,
  * solution is exact and zero on the false positives.
  *   cap, n_det, det_idx, det_hash, det_mask  dev outputs of the extract call
  *            that found I~ (det_hash and det_mask required; only the first
- *            min(n_det, cap) entries take part; cap <= 8192); ghat  dev lattice values of
+ *            min(n_det, cap) entries take part); ghat  dev lattice values of
  *            mr1l_fft (the same samples).
  *   max_iter >= 0 CG iterations at most; tol >= 0: stop once the normal-
  *            equation residual is <= tol times the right-hand side.
@@ -298,7 +298,7 @@ int mr1l_check_injective(mr1l_plan p, int64_t n_total, const int64_t *set_off,
  *   theta, s_cap, n_out, out_idx, out_coef  Algorithm 4 on the solution, as
  *            in mr1l_extract; n_out == NULL skips it.
  * Asynchronous on the plan's stream; grows plan scratch of
- * F*cap*(4L + 3*sizeof(complex)) bytes on first use (not during graph
+ * F*cap*(4L + 4*sizeof(complex)) bytes on first use (not during graph
  * capture); MR1L_E_ARG for invalid arguments.
  */
 int mr1l_lsq(mr1l_plan p, int64_t cap, const int64_t *n_det,
@@ -390,6 +390,11 @@ typedef struct {
                           d coordinates); 0: the sparse polynomial           */
     int32_t bs_order[16];
     uint64_t bs_dims[16];
+    int32_t lsq_iters; /* > 0: the final coefficients are the least-squares
+                          fit (mr1l_lsq, at most lsq_iters CG iterations) of
+                          the output frequencies to the samples of the t = d
+                          step's lattices (Remark 2.9, in place of the
+                          external Step 3); 0: Algorithm 4's estimates       */
 } mr1l_dimincr_params;
 
 /*

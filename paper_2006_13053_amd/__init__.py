@@ -47,7 +47,7 @@ class DimincrParams(C.Structure):
                 ("r", C.c_int32), ("theta", C.c_double), ("c", C.c_double), ("delta", C.c_double),
                 ("M", C.c_int64), ("postproc", C.c_int32), ("seed", C.c_uint64), ("dtype", C.c_int32),
                 ("step1", C.c_int32), ("bs_n", C.c_int32), ("bs_order", C.c_int32 * 16),
-                ("bs_dims", C.c_uint64 * 16)]
+                ("bs_dims", C.c_uint64 * 16), ("lsq_iters", C.c_int32)]
 
 
 SAMPLE_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
@@ -400,12 +400,13 @@ def mr1l_num_lattices(nJ: int, c: float = 10.33, delta: float = 0.9) -> int:
 def mr1l_dimincr(d: int, N: int, s: int, s_local: int, r: int, theta: float, M: int, seed: int,
                  poly_freq=None, poly_coef=None, c: float = 10.33, delta: float = 0.9,
                  postproc: bool = True, dtype=torch.complex128, cap: int = 1 << 16, sample_fn=None,
-                 step1: bool = False, bspline=None):
+                 step1: bool = False, bspline=None, lsq_iters: int = 0):
     """Algorithm 3 driver (Step 2, and Step 1 when step1) -> (freq [n, d] int64 numpy,
     coef [n] numpy, total samples).  bspline = (orders, coordinate masks) selects the
     built-in B-spline test function (eq. (4.3)) instead of the polynomial."""
     prm = DimincrParams(int(d), int(N), int(s), int(s_local), int(r), float(theta), float(c), float(delta),
                         int(M), int(bool(postproc)), int(seed) & (2**64 - 1), _ctype(dtype), int(bool(step1)))
+    prm.lsq_iters = int(lsq_iters)
     if bspline is not None:
         orders, masks = list(bspline[0]), list(bspline[1])
         prm.bs_n = len(orders)

@@ -681,7 +681,7 @@ int mr1l_lsq(mr1l_plan p, int64_t cap, const int64_t *n_det, const int64_t *det_
              int32_t *iters, double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef)
 {
     if (!p) return fail(MR1L_E_ARG, "plan is NULL");
-    if (cap < 1 || cap > kMaxCap) return fail(MR1L_E_ARG, "least squares needs cap in [1, 8192]");
+    if (cap < 1 || cap > kMaxCapLarge) return fail(MR1L_E_ARG, "cap must be in [1, 2^24]");
     if (!n_det || !det_hash || !det_mask || !ghat || !coef) return fail(MR1L_E_ARG, "null input buffer");
     if (max_iter < 0 || !(tol >= 0.0)) return fail(MR1L_E_ARG, "max_iter and tol must be >= 0");
     if (n_out) {
@@ -691,7 +691,7 @@ int mr1l_lsq(mr1l_plan p, int64_t cap, const int64_t *n_det, const int64_t *det_
     }
     const int64_t esz = p->dtype == MR1L_C128 ? 16 : 8;
     const int64_t rep_bytes = ((int64_t)p->F * cap * p->L * 4 + 255) / 256 * 256;
-    int rc = grow(*p, &p->d_ls, rep_bytes + 3 * (int64_t)p->F * cap * esz, p->ls_bytes);
+    int rc = grow(*p, &p->d_ls, rep_bytes + 4 * (int64_t)p->F * cap * esz, p->ls_bytes);
     if (rc) return rc;
     rc = lsq_run(*p, cap, n_det, det_hash, det_mask, ghat, max_iter, tol, coef, resid, iters, (int32_t *)p->d_ls,
                  (char *)p->d_ls + rep_bytes);

@@ -320,6 +320,39 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
                 cur.push_back(It[b]);
             }
             if (t == d) cur_coef = oc;
+            if (t == d && P.lsq_iters > 0 && h_nout > 0) {
+                // least squares on the output frequencies with this step's samples (Remark 2.9):
+                // every output is kept (theta 0, one vote), then CG on the normal equations
+                std::vector<int64_t> soa2((size_t)d * h_nout);
+                for (int64_t q = 0; q < h_nout; ++q)
+                    for (int u = 0; u < d; ++u) soa2[(size_t)u * h_nout + q] = cur[(size_t)q * d + u];
+                DevBuf<int64_t> dsel, n2, i2, o2n, o2i;
+                DevBuf<unsigned char> c2, o2c;
+                DevBuf<double> res;
+                if ((rc = dsel.need((int64_t)soa2.size())) || (rc = n2.need(1)) || (rc = i2.need(h_nout)) ||
+                    (rc = c2.need(h_nout * esz)) || (rc = o2n.need(1)) || (rc = o2i.need(h_nout)) ||
+                    (rc = o2c.need(h_nout * esz)) || (rc = res.need(1)))
+                    return rc;
+                MR1L_HIP(hipMemcpyAsync(dsel.p, soa2.data(), soa2.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+                if ((rc = launch_fill_u32(bitmap.p, (nodes + 31) / 32, 0xffffffffu, st))) return rc;
+                mr1l_extract_opts o2{0.0, 1, P.postproc, h_nout, h_nout};
+                mr1l_extract_out ex2{};
+                ex2.n_det = n2.p; ex2.det_idx = i2.p; ex2.det_coef = c2.p;
+                ex2.n_out = o2n.p; ex2.out_idx = o2i.p; ex2.out_coef = o2c.p;
+                if ((rc = mr1l_extract(plan.p, h_nout, nullptr, dsel.p, gbuf.p, bitmap.p, &o2, &ex2))) return rc;
+                Plan &pp = plan_of(plan.p);
+                if ((rc = mr1l_lsq(plan.p, h_nout, n2.p, i2.p, pp.d_ex_hash, pp.d_ex_mask, gbuf.p, P.lsq_iters,
+                                   1e-14, c2.p, res.p, nullptr, 0.0, 1, nullptr, nullptr, nullptr)))
+                    return rc;
+                // the detected list is every output in ascending position: coefficient q belongs to row q
+                std::vector<int64_t> hi2(h_nout);
+                MR1L_HIP(hipMemcpyAsync(hi2.data(), i2.p, h_nout * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+                std::vector<unsigned char> hc2(h_nout * esz);
+                MR1L_HIP(hipMemcpyAsync(hc2.data(), c2.p, h_nout * esz, hipMemcpyDeviceToHost, st));
+                MR1L_HIP(hipStreamSynchronize(st));
+                for (int64_t q = 0; q < h_nout; ++q)
+                    std::memcpy(cur_coef.data() + hi2[q] * esz, hc2.data() + q * esz, esz);
+            }
             if ((int64_t)(cur.size() / t) > cap) return fail(MR1L_E_CAPACITY, "union exceeds cap");
         }
         const int64_t ncur = (int64_t)(cur.size() / t);

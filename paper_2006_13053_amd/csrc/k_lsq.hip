@@ -92,9 +92,25 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *red)
     __syncthreads();
 }
 
+// Group sums of one lattice: in LDS (GS = false) or, for lists longer than the
+// LDS holds, in global memory, where every access is an atomic at device scope
+// so that the workgroup's threads see each other's sums after a barrier.
+template <bool GS, typename T>
+__device__ __forceinline__ void gsum_zero(T *a)
+{
+    if (GS) __hip_atomic_store(a, (T)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *a = (T)0;
+}
+template <bool GS, typename T>
+__device__ __forceinline__ T gsum_load(const T *a)
+{
+    if (GS) return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *a;
+}
+
 // out = G v over the function's n detected candidates (entries owned by thread
-// q mod blockDim).  s: LDS group sums of one lattice, indexed by representative.
-template <typename T>
+// q mod blockDim).  s: group sums of one lattice, indexed by representative.
+template <typename T, bool GS>
 __device__ void apply_g(const LatDesc *__restrict__ lf, int L, int n, int64_t base,
                         const int32_t *__restrict__ rep, const typename cvec<T>::type *v,
                         typename cvec<T>::type *out, typename cvec<T>::type *s)
@@ -105,7 +121,7 @@ __device__ void apply_g(const LatDesc *__restrict__ lf, int L, int n, int64_t ba
         const T w = (T)lf[l].M;
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
             const int rp = rep[(base + q) * L + l];
-            if (rp >= 0) { s[rp].x = 0; s[rp].y = 0; }
+            if (rp >= 0) { gsum_zero<GS>(&s[rp].x); gsum_zero<GS>(&s[rp].y); }
         }
         __syncthreads();
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -119,7 +135,9 @@ __device__ void apply_g(const LatDesc *__restrict__ lf, int L, int n, int64_t ba
         __syncthreads();
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
             const int rp = rep[(base + q) * L + l];
-            const V a = rp >= 0 ? s[rp] : v[base + q];
+            V a;
+            if (rp >= 0) { a.x = gsum_load<GS>(&s[rp].x); a.y = gsum_load<GS>(&s[rp].y); }
+            else a = v[base + q];
             V o = out[base + q];
             o.x += w * a.x;
             o.y += w * a.y;
@@ -129,17 +147,17 @@ __device__ void apply_g(const LatDesc *__restrict__ lf, int L, int n, int64_t ba
     }
 }
 
-template <typename T>
+template <typename T, bool GS>
 __global__ __launch_bounds__(kLsqThreads) void k_lsq_cg(
     const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ n_det, int64_t cap,
     const int32_t *__restrict__ det_hash, const int32_t *__restrict__ rep,
     const typename cvec<T>::type *__restrict__ ghat, int max_iter, double tol2, typename cvec<T>::type *x,
-    typename cvec<T>::type *r, typename cvec<T>::type *pv, typename cvec<T>::type *ap, double *__restrict__ resid,
-    int32_t *__restrict__ iters)
+    typename cvec<T>::type *r, typename cvec<T>::type *pv, typename cvec<T>::type *ap,
+    typename cvec<T>::type *gsums, double *__restrict__ resid, int32_t *__restrict__ iters)
 {
     using V = typename cvec<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    V *s = reinterpret_cast<V *>(smem);
+    V *s = GS ? gsums + (int64_t)blockIdx.x * cap : reinterpret_cast<V *>(smem);
     __shared__ double red[2 * (kLsqThreads / 64)];
     const int f = blockIdx.x;
     const int n = (int)n_kept(n_det, f, cap);
@@ -156,7 +174,7 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq_cg(
         r[base + q].x = (T)br;
         r[base + q].y = (T)bi;
     }
-    apply_g<T>(lf, L, n, base, rep, x, ap, s);
+    apply_g<T, GS>(lf, L, n, base, rep, x, ap, s);
     double bb = 0.0, rr = 0.0;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
         V b = r[base + q];
@@ -171,7 +189,7 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq_cg(
     block_sum2(bb, rr, red);
     int it = 0;
     while (it < max_iter && rr > tol2 * bb) {
-        apply_g<T>(lf, L, n, base, rep, pv, ap, s);
+        apply_g<T, GS>(lf, L, n, base, rep, pv, ap, s);
         double pap = 0.0, unused = 0.0;
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
             const V p = pv[base + q], a = ap[base + q];
@@ -212,9 +230,9 @@ __global__ __launch_bounds__(kLsqThreads) void k_lsq_cg(
 
 int lsq_init_attrs()
 {
-    MR1L_HIP(hipFuncSetAttribute((const void *)k_lsq_cg<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_lsq_cg<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  kMaxCap * 16));
-    MR1L_HIP(hipFuncSetAttribute((const void *)k_lsq_cg<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_lsq_cg<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  kMaxCap * 8));
     return MR1L_OK;
 }
@@ -233,18 +251,30 @@ int lsq_run(Plan &p, int64_t cap, const int64_t *n_det, const int32_t *det_hash,
     MR1L_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_lsq_rep, g, b, 0, p.stream, p.d_lat, L, n_det, cap, det_hash, det_mask, owner, rep);
     MR1L_LAUNCH_CHECK();
-    const size_t shm = (size_t)cap * esz;
+    const bool gs = cap > kMaxCap;   // group sums in global memory
+    const size_t shm = gs ? 0 : (size_t)cap * esz;
     const int64_t stride = p.F * cap;
+    const dim3 grid((unsigned)p.F), blk(kLsqThreads);
     if (p.dtype == MR1L_C128) {
         double2 *v = (double2 *)vecs;
-        hipLaunchKernelGGL(k_lsq_cg<double>, dim3((unsigned)p.F), dim3(kLsqThreads), shm, p.stream, p.d_lat, L,
-                           n_det, cap, det_hash, rep, (const double2 *)ghat, max_iter, tol * tol, (double2 *)coef, v,
-                           v + stride, v + 2 * stride, resid, iters);
+        if (gs)
+            hipLaunchKernelGGL((k_lsq_cg<double, true>), grid, blk, 0, p.stream, p.d_lat, L, n_det, cap, det_hash,
+                               rep, (const double2 *)ghat, max_iter, tol * tol, (double2 *)coef, v, v + stride,
+                               v + 2 * stride, v + 3 * stride, resid, iters);
+        else
+            hipLaunchKernelGGL((k_lsq_cg<double, false>), grid, blk, shm, p.stream, p.d_lat, L, n_det, cap, det_hash,
+                               rep, (const double2 *)ghat, max_iter, tol * tol, (double2 *)coef, v, v + stride,
+                               v + 2 * stride, v + 3 * stride, resid, iters);
     } else {
         float2 *v = (float2 *)vecs;
-        hipLaunchKernelGGL(k_lsq_cg<float>, dim3((unsigned)p.F), dim3(kLsqThreads), shm, p.stream, p.d_lat, L,
-                           n_det, cap, det_hash, rep, (const float2 *)ghat, max_iter, tol * tol, (float2 *)coef, v,
-                           v + stride, v + 2 * stride, resid, iters);
+        if (gs)
+            hipLaunchKernelGGL((k_lsq_cg<float, true>), grid, blk, 0, p.stream, p.d_lat, L, n_det, cap, det_hash,
+                               rep, (const float2 *)ghat, max_iter, tol * tol, (float2 *)coef, v, v + stride,
+                               v + 2 * stride, v + 3 * stride, resid, iters);
+        else
+            hipLaunchKernelGGL((k_lsq_cg<float, false>), grid, blk, shm, p.stream, p.d_lat, L, n_det, cap, det_hash,
+                               rep, (const float2 *)ghat, max_iter, tol * tol, (float2 *)coef, v, v + stride,
+                               v + 2 * stride, v + 3 * stride, resid, iters);
     }
     MR1L_LAUNCH_CHECK();
     return MR1L_OK;

@@ -107,7 +107,7 @@ struct Plan {
     int64_t gsort_bytes = 0;
     void *d_bs_dims = nullptr;       // B-spline sampler: [F][n_prod] coordinate masks
     int64_t bs_bytes = 0;
-    void *d_ls = nullptr;            // least squares: [F][cap][L] int32 representatives + 3 [F][cap] complex
+    void *d_ls = nullptr;            // least squares: [F][cap][L] int32 representatives + 4 [F][cap] complex
     int64_t ls_bytes = 0;
     int64_t *d_setoff_default = nullptr; // [2] = {0, n} for F == 1 calls
     int64_t setoff_n = -1;

@@ -737,6 +737,22 @@ def test_dimincr_step1_matches_oracle_driver(m, d, s, N):
     assert [tuple(r) for r in gf.tolist()] == [t[0] for t in truth]
 
 
+def test_dimincr_least_squares_final_step_exact(m):
+    """The least-squares final step (Remark 2.9) on a noise-free sparse polynomial: the
+    same support as without it and coefficients exact to 1e-12 (relative)."""
+    say("dimincr least squares")
+    d, s, N = 6, 12, 6
+    freq, coef = synth.sparse_poly_box(7, d=d, s=s, box=N)
+    Mlat = synth.next_prime_above(10.33 * 2 * s)
+    g0, c0, n0 = m.mr1l_dimincr(d, N, s, 2 * s, 2, 1e-12, Mlat, 5, poly_freq=T(freq), poly_coef=T(coef))
+    g1, c1, n1 = m.mr1l_dimincr(d, N, s, 2 * s, 2, 1e-12, Mlat, 5, poly_freq=T(freq), poly_coef=T(coef),
+                                lsq_iters=100)
+    assert np.array_equal(g0, g1) and n0 == n1
+    truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
+    assert [tuple(r) for r in g1.tolist()] == [t[0] for t in truth]
+    close(c1, np.array([t[1] for t in truth]), 1e-12, "least-squares coefficients")
+
+
 @pytest.mark.parametrize("step1", [False, True])
 def test_dimincr_full_size_matches_oracle_and_truth(m, step1):
     """The dimension-incremental workload at full size: d = 25, s = 200 frequencies
