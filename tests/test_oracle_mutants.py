@@ -6,6 +6,7 @@ a strict instead of inclusive comparison, a wrong transpose, a wrong constant). 
 compiled on the CPU and the pin suite is run against it in a subprocess; the suite
 must fail for every mutant.
 """
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -55,18 +56,39 @@ MUTANTS = {
 }
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_mutant_is_caught(name, tmp_path):
+def _run_mutant(name, workdir):
+    """Compile one mutant and run the pin suite against it -> (return code, output tail)."""
     old, new = MUTANTS[name]
     src = open(SRC).read()
-    assert src.count(old) == 1, f"mutation site not unique/found: {name}"
-    msrc = tmp_path / "mutant.c"
-    msrc.write_text(src.replace(old, new))
-    mlib = str(tmp_path / "libmutant.so")
-    oracle.build_from(str(msrc), mlib)
-    env = dict(os.environ, MR1L_ORACLE_LIB=mlib)
+    if src.count(old) != 1:
+        return None, f"mutation site not unique/found: {name}"
+    d = os.path.join(workdir, name)
+    os.makedirs(d, exist_ok=True)
+    msrc = os.path.join(d, "mutant.c")
+    with open(msrc, "w") as fh:
+        fh.write(src.replace(old, new))
+    mlib = os.path.join(d, "libmutant.so")
+    oracle.build_from(msrc, mlib)
+    env = dict(os.environ, MR1L_ORACLE_LIB=mlib, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
-                       env=env, capture_output=True, text=True, timeout=600, cwd=ROOT)
-    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+                       env=env, capture_output=True, text=True, timeout=900, cwd=ROOT)
+    return r.returncode, r.stdout[-2000:]
+
+
+@pytest.fixture(scope="module")
+def mutant_results(tmp_path_factory):
+    """Every mutant's pin run, several at a time (each is its own process)."""
+    workdir = str(tmp_path_factory.mktemp("mutants"))
+    workers = max(1, min(8, (os.cpu_count() or 2) // 2))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = {name: ex.submit(_run_mutant, name, workdir) for name in sorted(MUTANTS)}
+        return {name: f.result() for name, f in futs.items()}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, mutant_results):
+    rc, out = mutant_results[name]
+    assert rc is not None, out
+    assert rc != 0, f"mutant {name} survived the pins:\n{out}"

@@ -587,22 +587,6 @@ def test_cor27_failure_bound_reproduces_printed_lines():
             assert cor27_failure_bound(st["Gamma"], g["c"], L) == pytest.approx(b, abs=6e-4)
 
 
-def test_hyperbolic_cross_sizes_printed_in_paper():
-    """Section 4.1.3: |Gamma| = 10,665,297 for the unweighted cross (d = 8, bound 32) and
-    |I| = 1069 for the weighted one (weights t^1.08); small cases by brute force."""
-    g = synth.hyperbolic_cross(8, 32)
-    assert g.shape == (8, 10_665_297)
-    assert np.abs(g).max() == 32
-    w = synth.hyperbolic_cross(8, 32, 1.08)
-    assert w.shape == (8, 1069)
-    assert synth.weighted_cross_member(g, 32, 1.08).sum() == 1069
-    for d, N in [(1, 7), (2, 9), (3, 6)]:
-        h = synth.hyperbolic_cross(d, N)
-        brute = [k for k in itertools.product(range(-N, N + 1), repeat=d)
-                 if math.prod(max(1, abs(v)) for v in k) <= N]
-        assert sorted(map(tuple, h.T.tolist())) == sorted(brute)
-
-
 # ------------------------------------------------------------------ Remark 2.9, least squares
 def test_lsq_matrix_is_the_sampler():
     """The least-squares design matrix applied to coefficients gives the samples of
