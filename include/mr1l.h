@@ -339,12 +339,15 @@ int mr1l_pfpn_count(mr1l_plan p, int64_t cap, const int64_t *n_active,
 /*
  * DFT schedules and their autotuner.  The lattice DFT of one size M runs under
  * one schedule: 0 = the whole Bluestein transform (5-smooth length) in one
- * workgroup's LDS, valid while that length fits; 1.. = power-of-two four-step
- * transforms differing in workgroup size, LDS batch, workgroups per CU and the
- * split N = N1 N2 (names from mr1l_fft_schedule_name).  Every schedule computes
- * the same transform to within rounding.  A new plan starts each size on the
- * schedule the autotuner chose for (dtype, M) earlier in the process, else on
- * 0 where it applies, else on the default four-step schedule.
+ * workgroup's LDS, valid while that length fits; 1..8 = power-of-two four-step
+ * Bluestein transforms differing in workgroup size, LDS batch, workgroups per
+ * CU and the split N = N1 N2; 9 = Rader's algorithm with the length-(M-1)
+ * convolution in registers, for prime M with M - 1 = 2^a 5^b, a >= 2, b >= 1,
+ * (M - 1)/20 <= 1024 and M - 1 reals fitting the LDS (names from
+ * mr1l_fft_schedule_name).  Every schedule computes the same transform to
+ * within rounding.  A new plan starts each size on the schedule the autotuner
+ * chose for (dtype, M) earlier in the process, else on 0 where it applies,
+ * else on 9 where it applies, else on the default four-step schedule.
  *
  * mr1l_plan_fft_schedule: sched < 0 returns the schedule of size M in the
  * plan; otherwise sets it (MR1L_E_ARG if M is not a size of the plan or the

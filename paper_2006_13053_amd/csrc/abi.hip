@@ -152,6 +152,8 @@ static int build_tables(Plan &p)
     std::map<int64_t, int32_t> mid_of;
     std::map<int64_t, int64_t> tw_of;
     std::vector<T> tw, ch;
+    std::vector<int32_t> ritab;
+    std::vector<T> rctab;
     int64_t spec_len = 0;
     auto twoff = [&](int64_t n) -> int64_t {
         auto it = tw_of.find(n);
@@ -190,10 +192,20 @@ static int build_tables(Plan &p)
         // table go to LDS when they fit their LDS tables
         const int64_t nch = md.chirp_nlo + (2 * M + md.chirp_nlo - 1) / md.chirp_nlo;
         mi.ltab = mi.Np <= kTabTw * kTabTw && nch <= kTabCh;
+        // Rader's algorithm in registers for prime M with M - 1 = 2^a 5^b
+        RaderDesc rd{};
+        if (rader_applies(M, sizeof(T))) {
+            mi.rader = true;
+            rader_tables<T>(M, rd, ritab, rctab);
+        }
         mi.sched = tuned_schedule(p.dtype, M);
-        if (mi.sched < 0 || (mi.sched == 0 && mi.Ns == 0)) mi.sched = mi.Ns ? 0 : kDefaultFourStep;
+        if (mi.sched >= 0 && !fft_schedule_applies(mi, mi.sched)) mi.sched = -1;
+        // untuned: the whole-LDS transform where it fits, else Rader where it applies
+        // (faster than the four-step on such sizes), else the default four-step
+        if (mi.sched < 0) mi.sched = mi.Ns ? 0 : (mi.rader ? kRaderSched : kDefaultFourStep);
         p.mdesc.push_back(md);
         p.minfo.push_back(mi);
+        p.rdesc.push_back(rd);
     }
     p.lat.resize(p.M.size());
     int64_t off = 0;
@@ -225,6 +237,14 @@ static int build_tables(Plan &p)
     p.tw_len = (int64_t)tw.size() / 2;
     p.chirp_len = (int64_t)ch.size() / 2;
     const size_t esz = 2 * sizeof(T);
+    MR1L_HIP(hipMalloc(&p.d_rdesc, p.rdesc.size() * sizeof(RaderDesc)));
+    MR1L_HIP(hipMemcpy(p.d_rdesc, p.rdesc.data(), p.rdesc.size() * sizeof(RaderDesc), hipMemcpyHostToDevice));
+    if (!ritab.empty()) {
+        MR1L_HIP(hipMalloc(&p.d_ritab, ritab.size() * sizeof(int32_t)));
+        MR1L_HIP(hipMemcpy(p.d_ritab, ritab.data(), ritab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        MR1L_HIP(hipMalloc(&p.d_rctab, rctab.size() * sizeof(T)));
+        MR1L_HIP(hipMemcpy(p.d_rctab, rctab.data(), rctab.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
     MR1L_HIP(hipMalloc(&p.d_spec, (size_t)spec_len * esz));
     MR1L_HIP(hipMalloc(&p.d_tw, tw.size() * sizeof(T)));
     MR1L_HIP(hipMemcpy(p.d_tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -308,7 +328,7 @@ static void release(Plan *p)
     void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_vrec, p->d_spec, p->d_chirp, p->d_tw,
                     p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
                     p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
-                    p->d_termoff_default, p->d_ls, p->d_gsort, p->d_bs_dims};
+                    p->d_termoff_default, p->d_ls, p->d_gsort, p->d_bs_dims, p->d_rdesc, p->d_ritab, p->d_rctab};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (FftGroup &g : p->fft_groups)
@@ -415,6 +435,7 @@ int mr1l::plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, cons
         if (!attrs_rc) attrs_rc = extract_init_attrs();
         if (!attrs_rc) attrs_rc = vote_init_attrs();
         if (!attrs_rc) attrs_rc = lsq_init_attrs();
+        if (!attrs_rc) attrs_rc = rader_init_attrs();
         if (attrs_rc) attrs_err = g_err;
     });
     if (attrs_rc) return fail(attrs_rc, "kernel attribute setup failed: " + attrs_err);
@@ -731,8 +752,9 @@ int mr1l_plan_fft_schedule(mr1l_plan p, int64_t M, int32_t sched)
     if (mid < 0) return fail(MR1L_E_ARG, "no lattice of this size in the plan");
     if (sched < 0) return p->minfo[mid].sched;
     if (sched >= kNumSched) return fail(MR1L_E_ARG, "unknown DFT schedule");
-    if (!kSched[sched].four_step && p->minfo[mid].Ns == 0)
-        return fail(MR1L_E_ARG, "this lattice size does not fit one workgroup's LDS");
+    if (!fft_schedule_applies(p->minfo[mid], sched))
+        return fail(MR1L_E_ARG, kSched[sched].rader ? "the Rader schedule needs a prime M with M - 1 = 2^a 5^b"
+                                                    : "this lattice size does not fit one workgroup's LDS");
     p->minfo[mid].sched = sched;
     const int rc = fft_apply_schedules(*p);
     return rc ? rc : sched;
@@ -766,7 +788,7 @@ int mr1l_fft_tune(mr1l_plan p, int32_t reps, int32_t max_sizes, int64_t *sizes, 
     std::map<std::pair<int, int32_t>, std::vector<int>> gmap;
     for (size_t mid = 0; mid < p->minfo.size(); ++mid) {
         const MInfo &mi = p->minfo[mid];
-        gmap[{mi.Ns ? lds_class(mi.Ns) : kLdsClasses, mi.Np}].push_back((int)mid);
+        gmap[{(mi.Ns ? lds_class(mi.Ns) : kLdsClasses) + (mi.rader ? 16 : 0), mi.Np}].push_back((int)mid);
         if (sizes) sizes[mid] = mi.M;
     }
     std::vector<std::pair<int64_t, std::vector<int>>> groups;   // (lattice count, sizes)
@@ -784,7 +806,6 @@ int mr1l_fft_tune(mr1l_plan p, int32_t reps, int32_t max_sizes, int64_t *sizes, 
     if (rc == MR1L_OK) rc = fft_time_plan(*p, in, out, reps, &cur_ms);
     for (size_t gi = 0; gi < groups.size() && rc == MR1L_OK; ++gi) {
         const std::vector<int> &mids = groups[gi].second;
-        const bool lds_ok = p->minfo[mids[0]].Ns > 0;
         const int start = p->minfo[mids[0]].sched;
         int best = start;
         float best_ms = cur_ms;
@@ -792,7 +813,7 @@ int mr1l_fft_tune(mr1l_plan p, int32_t reps, int32_t max_sizes, int64_t *sizes, 
             float ms = -1.f;
             if (s == start) {
                 ms = cur_ms;
-            } else if (kSched[s].four_step || lds_ok) {
+            } else if (fft_schedule_applies(p->minfo[mids[0]], s)) {
                 rc = set_group(mids, s);
                 if (rc == MR1L_OK) rc = fft_time_plan(*p, in, out, reps, &ms);
                 if (rc == MR1L_OK && ms < best_ms) { best_ms = ms; best = s; }

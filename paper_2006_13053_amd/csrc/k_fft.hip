@@ -736,15 +736,16 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
 
 // ------------------------------------------------------------------ host side
 const FftSched kSched[kNumSched] = {
-    {"lds", 0, kFftThreads, 0, 1, 0},
-    {"4step-512x2-ceil", 1, 512, 12, 2, 0},
-    {"4step-512x2-floor", 1, 512, 12, 2, 1},
-    {"4step-512x1-ceil", 1, 512, 13, 1, 0},
-    {"4step-512x1-floor", 1, 512, 13, 1, 1},
-    {"4step-1024x1-ceil", 1, 1024, 13, 1, 0},
-    {"4step-1024x1-floor", 1, 1024, 13, 1, 1},
-    {"4step-256x2-ceil", 1, 256, 12, 2, 0},
-    {"4step-256x2-floor", 1, 256, 12, 2, 1},
+    {"lds", 0, kFftThreads, 0, 1, 0, 0},
+    {"4step-512x2-ceil", 1, 512, 12, 2, 0, 0},
+    {"4step-512x2-floor", 1, 512, 12, 2, 1, 0},
+    {"4step-512x1-ceil", 1, 512, 13, 1, 0, 0},
+    {"4step-512x1-floor", 1, 512, 13, 1, 1, 0},
+    {"4step-1024x1-ceil", 1, 1024, 13, 1, 0, 0},
+    {"4step-1024x1-floor", 1, 1024, 13, 1, 1, 0},
+    {"4step-256x2-ceil", 1, 256, 12, 2, 0, 0},
+    {"4step-256x2-floor", 1, 256, 12, 2, 1, 0},
+    {"rader-20", 0, 1024, 0, 1, 0, 1},
 };
 
 template <typename T, int LOGP, bool LTAB>
@@ -812,6 +813,8 @@ static int launch_sched(Plan &p, int s, int cls, const int32_t *d_lats, int nl, 
     case 7: case 8:
         return ltab ? launch4<T, true, 256, LS, 2>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc)
                     : launch4<T, false, 256, LS, 2>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc);
+    case 9:
+        return rader_launch(p, d_lats, nl, in, out, theta, bitmap, mode, scale, by_m);
     default:
         return fail(MR1L_E_ARG, "unknown DFT schedule");
     }
@@ -878,7 +881,7 @@ MDesc fft_layout(const Plan &p, int mid, int s)
 {
     MDesc m = p.mdesc[mid];
     const MInfo &mi = p.minfo[mid];
-    if (!kSched[s].four_step) {
+    if (!kSched[s].four_step && !kSched[s].rader) {
         m.spec_off = mi.spec_s; m.tw_N = mi.tw_s; m.N = mi.Ns; m.N1 = mi.Ns; m.N2 = 1;
     } else {
         int k = 0;
@@ -891,7 +894,12 @@ MDesc fft_layout(const Plan &p, int mid, int s)
     return m;
 }
 
-static bool applies(const MInfo &mi, int s) { return kSched[s].four_step ? mi.Np > 0 : mi.Ns > 0; }
+static bool applies(const MInfo &mi, int s)
+{
+    if (kSched[s].rader) return mi.rader;
+    return kSched[s].four_step ? mi.Np > 0 : mi.Ns > 0;
+}
+bool fft_schedule_applies(const MInfo &mi, int s) { return s >= 0 && s < kNumSched && applies(mi, s); }
 
 // Grow the four-step scratch to `slots` slots of `len` complex (capped at 8 GiB in
 // total, at least one slot).  Synchronises the plan's stream before freeing.
@@ -934,7 +942,7 @@ int fft_apply_schedules(Plan &p)
     int64_t len = 0, slots = 0;
     for (size_t i = 0; i < p.lat.size(); ++i) {
         const MInfo &mi = p.minfo[p.lat[i].mid];
-        const int cls = kSched[mi.sched].four_step ? 0 : lds_class(mi.Ns);
+        const int cls = (kSched[mi.sched].four_step || kSched[mi.sched].rader) ? 0 : lds_class(mi.Ns);
         auto it = gi.find({mi.sched, cls});
         if (it == gi.end()) {
             it = gi.emplace(std::make_pair(mi.sched, cls), p.fft_groups.size()).first;

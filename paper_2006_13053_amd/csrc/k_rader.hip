@@ -1,0 +1,431 @@
+// Lattice DFTs of prime size M with M - 1 = 2^a 5^b (a >= 2, b >= 1) by Rader's
+// algorithm, the whole transform in registers: for h != 0,
+//   ghat[g^-p] = (1/M) (f[0] + sum_q f[g^q] w^(-g^(q-p))),   w = e^{2 pi i / M},
+// a cyclic convolution of length P = M - 1 of a[q] = f[g^q] with
+// b[n] = w^(-g^-n) (g a primitive root mod M), done as a length-P DFT of a, a
+// product with the precomputed DFT of b (1/P folded in), and a second length-P
+// DFT of the conjugate (an inverse DFT is conj(DFT(conj(.)))).  ghat[0] is the
+// mean of f.  One workgroup per lattice: each of the P/20 active threads holds
+// 20 values in registers through mixed-radix (4, 2, 5) Stockham passes; between
+// passes the values move through one LDS plane (P reals), real and imaginary
+// parts in turn.  Nothing goes through global scratch.
+#include <complex>
+#include <vector>
+
+#include "mr1l_internal.h"
+
+namespace mr1l {
+
+// values per thread (20) and the largest workgroup: P <= 20480 (and the LDS plane
+// bounds P further in double).  40 values in 512 threads (256 registers each) was
+// slower in double: fewer waves to hide the LDS and barrier latency.
+template <typename T> constexpr int rader_e() { return 20; }
+template <typename T> constexpr int rader_threads() { return 1024; }
+
+// Hides a value from the optimiser so that per-pass index arithmetic is not hoisted
+// out of the pass loop (which would hold all passes' indices in registers).
+__device__ __forceinline__ int rader_opaque(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(T *xr, T *xi)
+{
+    if constexpr (R == 2) {
+        const T ar = xr[0], ai = xi[0];
+        xr[0] = ar + xr[1]; xi[0] = ai + xi[1];
+        xr[1] = ar - xr[1]; xi[1] = ai - xi[1];
+    } else if constexpr (R == 4) {
+        const T s0r = xr[0] + xr[2], s0i = xi[0] + xi[2], d0r = xr[0] - xr[2], d0i = xi[0] - xi[2];
+        const T s1r = xr[1] + xr[3], s1i = xi[1] + xi[3], d1r = xr[1] - xr[3], d1i = xi[1] - xi[3];
+        xr[0] = s0r + s1r; xi[0] = s0i + s1i;
+        xr[2] = s0r - s1r; xi[2] = s0i - s1i;
+        xr[1] = d0r + d1i; xi[1] = d0i - d1r;   // d0 - i d1
+        xr[3] = d0r - d1i; xi[3] = d0i + d1r;   // d0 + i d1
+    } else {
+        static_assert(R == 5, "radix 2, 4 or 5");
+        const T c1 = (T)0.30901699437494742410229341718281906, c2 = (T)-0.80901699437494742410229341718281906;
+        const T s1 = (T)0.95105651629515357211643933337938214, s2 = (T)0.58778525229247312916870595463907277;
+        const T t1r = xr[1] + xr[4], t1i = xi[1] + xi[4], t3r = xr[1] - xr[4], t3i = xi[1] - xi[4];
+        const T t2r = xr[2] + xr[3], t2i = xi[2] + xi[3], t4r = xr[2] - xr[3], t4i = xi[2] - xi[3];
+        const T a1r = xr[0] + c1 * t1r + c2 * t2r, a1i = xi[0] + c1 * t1i + c2 * t2i;
+        const T a2r = xr[0] + c2 * t1r + c1 * t2r, a2i = xi[0] + c2 * t1i + c1 * t2i;
+        const T b1r = s1 * t3r + s2 * t4r, b1i = s1 * t3i + s2 * t4i;
+        const T b2r = s2 * t3r - s1 * t4r, b2i = s2 * t3i - s1 * t4i;
+        xr[0] = xr[0] + t1r + t2r; xi[0] = xi[0] + t1i + t2i;
+        xr[1] = a1r + b1i; xi[1] = a1i - b1r;   // a1 - i b1
+        xr[4] = a1r - b1i; xi[4] = a1i + b1r;   // a1 + i b1
+        xr[2] = a2r + b2i; xi[2] = a2i - b2r;   // a2 - i b2
+        xr[3] = a2r - b2i; xi[3] = a2i + b2r;   // a2 + i b2
+    }
+}
+
+// One Stockham pass of radix R: butterfly j = tid + Tn c (c < E/R) takes the inputs
+// j + m P/R, twiddles them by W_{LR}^{k m} (k = j mod L) and leaves the outputs for
+// positions (j / L) L R + k + p L.
+template <typename T, int R, int E>
+__device__ __forceinline__ void rader_pass(T (&xr)[E], T (&xi)[E], int tid, int Tn, int P, int L,
+                                           const typename cvec<T>::type *__restrict__ tw)
+{
+    using V = typename cvec<T>::type;
+    const int step = P / (L * R);
+#pragma unroll
+    for (int c = 0; c < E / R; ++c) {
+        const int j = tid + Tn * c;
+        const int k = j % L;
+        const V w1 = tw[k * step];
+        T wr = 1, wi = 0;
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+            const T nr = wr * w1.x - wi * w1.y;
+            wi = wr * w1.y + wi * w1.x;
+            wr = nr;
+            const T ar = xr[c * R + m], ai = xi[c * R + m];
+            xr[c * R + m] = ar * wr - ai * wi;
+            xi[c * R + m] = ar * wi + ai * wr;
+        }
+        dft_small<T, R>(xr + c * R, xi + c * R);
+    }
+}
+
+// Output position of value (c, p) of a pass of radix R with sub-length L.
+__device__ __forceinline__ int out_pos(int tid, int Tn, int c, int p, int R, int L)
+{
+    const int j = tid + Tn * c;
+    return (j / L) * L * R + (j % L) + p * L;
+}
+
+template <typename T, int R, int E>
+__device__ __forceinline__ void put_plane(T *pl, const T (&x)[E], int tid, int Tn, int L)
+{
+#pragma unroll
+    for (int c = 0; c < E / R; ++c)
+#pragma unroll
+        for (int p = 0; p < R; ++p) pl[out_pos(tid, Tn, c, p, R, L)] = x[c * R + p];
+}
+
+template <typename T, int R, int E>
+__device__ __forceinline__ void get_plane(const T *pl, T (&x)[E], int tid, int Tn, int P)
+{
+#pragma unroll
+    for (int c = 0; c < E / R; ++c)
+#pragma unroll
+        for (int m = 0; m < R; ++m) x[c * R + m] = pl[tid + Tn * c + m * (P / R)];
+}
+
+// Values leave the layout of a pass (radix RO, sub-length Lo) for the input layout
+// of a pass of radix RI, through the LDS plane, real and imaginary parts in turn.
+// Inactive threads (tid >= Tn) take part in the barriers only.
+template <typename T, int E, int RO, int RI>
+__device__ __forceinline__ void exchange(T *pl, T (&xr)[E], T (&xi)[E], bool act, int tid, int Tn, int P, int Lo)
+{
+    // each call gets its own opaque copy of tid, so the addresses are recomputed
+    // instead of being held across the barriers
+    if (act) put_plane<T, RO, E>(pl, xr, rader_opaque(tid), Tn, Lo);
+    __syncthreads();
+    if (act) get_plane<T, RI, E>(pl, xr, rader_opaque(tid), Tn, P);
+    __syncthreads();
+    if (act) put_plane<T, RO, E>(pl, xi, rader_opaque(tid), Tn, Lo);
+    __syncthreads();
+    if (act) get_plane<T, RI, E>(pl, xi, rader_opaque(tid), Tn, P);
+    __syncthreads();
+}
+
+// A length-P DFT (forward sign) on values already in the input layout of the first
+// pass: n4 passes of radix 4, n2 (0 or 1) of radix 2, n5 of radix 5, in this order.
+// Returns the sub-length of the last pass (its outputs are in radix-5 layout).
+template <typename T, int E>
+__device__ __forceinline__ int dft_passes(T *pl, T (&xr)[E], T (&xi)[E], bool act, int t, int tid, int Tn, int P,
+                                          int n4, int n2, int n5, const typename cvec<T>::type *__restrict__ tw)
+{
+    int L = 1, Lprev = 1;
+    for (int i = 0; i < n4; ++i) {
+        if (i > 0) exchange<T, E, 4, 4>(pl, xr, xi, act, tid, Tn, P, Lprev);
+        if (act) rader_pass<T, 4, E>(xr, xi, rader_opaque(t), Tn, P, L, tw);
+        Lprev = L; L *= 4;
+    }
+    if (n2) {
+        exchange<T, E, 4, 2>(pl, xr, xi, act, tid, Tn, P, Lprev);
+        if (act) rader_pass<T, 2, E>(xr, xi, rader_opaque(t), Tn, P, L, tw);
+        Lprev = L; L *= 2;
+    }
+    for (int i = 0; i < n5; ++i) {
+        if (i == 0) {
+            if (n2) exchange<T, E, 2, 5>(pl, xr, xi, act, tid, Tn, P, Lprev);
+            else exchange<T, E, 4, 5>(pl, xr, xi, act, tid, Tn, P, Lprev);
+        } else {
+            exchange<T, E, 5, 5>(pl, xr, xi, act, tid, Tn, P, Lprev);
+        }
+        if (act) rader_pass<T, 5, E>(xr, xi, rader_opaque(t), Tn, P, L, tw);
+        Lprev = L; L *= 5;
+    }
+    return Lprev;
+}
+
+// mode: FFT_FWD (ghat = (1/M) sum f w^{-jh} times scale, and the non-zero bitmap) or
+// FFT_INV (scale (1/M) sum g w^{+jh}, times M when scale_by_m).
+template <typename T>
+__global__ __launch_bounds__(rader_threads<T>()) void k_rader(
+    const int32_t *__restrict__ lats, const LatDesc *__restrict__ lat, const RaderDesc *__restrict__ rdesc,
+    const int32_t *__restrict__ itab, const typename cvec<T>::type *__restrict__ ctab,
+    const typename cvec<T>::type *__restrict__ in, typename cvec<T>::type *__restrict__ out,
+    uint32_t *__restrict__ bitmap, T th2, int mode, T scale, int scale_by_m)
+{
+    using V = typename cvec<T>::type;
+    constexpr int E = rader_e<T>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *pl = reinterpret_cast<T *>(smem);
+    __shared__ double red[2 * (rader_threads<T>() / 64)];
+    const LatDesc ld = lat[lats[blockIdx.x]];
+    const RaderDesc *rd = rdesc + ld.mid;
+    const int P = rd->P, Tn = rd->nthreads, M = ld.M;
+    const int n4 = rd->n4, n2 = rd->n2, n5 = rd->n5;
+    const int tid = threadIdx.x;
+    const bool act = tid < Tn;
+    const int t = act ? tid : 0;   // inactive threads mirror thread 0 (in range), results unused
+    const int32_t *pin = itab + rd->perm_in;
+    const int32_t *pout = itab + rd->perm_out;
+    const V *tw = ctab + rd->tw;
+    const V *sp = ctab + rd->spec;
+    const T cj = (mode == FFT_INV) ? T(-1) : T(1);
+    const V *x = in + ld.node_off;
+    T xr[E], xi[E];
+
+    // a[q] = f[g^q]: f[1..M) through the plane in natural order, gathered in the
+    // input order of the first pass
+    // (the radix list starts with 4 and ends with 5: M - 1 = 2^a 5^b with a >= 2, b >= 1)
+    for (int i = tid; i < P; i += blockDim.x) pl[i] = x[1 + i].x;
+    __syncthreads();
+    int gidx[E];
+    // first-pass input index of register e = 4 c + m: q = t + Tn c + m P / 4
+#pragma unroll
+    for (int e = 0; e < E; ++e) gidx[e] = pin[t + Tn * (e / 4) + (e % 4) * (P / 4)] - 1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) xr[e] = pl[gidx[e]];
+    __syncthreads();
+    for (int i = tid; i < P; i += blockDim.x) pl[i] = cj * x[1 + i].y;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xi[e] = pl[gidx[e]];
+    __syncthreads();
+
+    // ghat[0]: the sum of f
+    V f0 = x[0];
+    f0.y *= cj;
+    {
+        double sr = 0.0, si = 0.0;
+        if (act)
+#pragma unroll
+            for (int e = 0; e < E; ++e) { sr += xr[e]; si += xi[e]; }
+        for (int o = 32; o > 0; o >>= 1) {
+            sr += __shfl_xor(sr, o);
+            si += __shfl_xor(si, o);
+        }
+        if ((tid & 63) == 0) { red[2 * (tid >> 6)] = sr; red[2 * (tid >> 6) + 1] = si; }
+    }
+
+    // forward length-P DFT of a
+    int Ll = dft_passes<T, E>(pl, xr, xi, act, t, tid, Tn, P, n4, n2, n5, tw);
+    // times the spectrum of b (with 1/P), conjugated for the inverse DFT
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const V s = sp[out_pos(t, Tn, e / 5, e % 5, 5, Ll)];
+            const T ar = xr[e], ai = xi[e];
+            xr[e] = ar * s.x - ai * s.y;
+            xi[e] = -(ar * s.y + ai * s.x);
+        }
+    }
+    // inverse length-P DFT (conjugated input): the convolution, conjugated
+    exchange<T, E, 5, 4>(pl, xr, xi, act, tid, Tn, P, Ll);
+    Ll = dft_passes<T, E>(pl, xr, xi, act, t, tid, Tn, P, n4, n2, n5, tw);
+    // ghat[g^-p] = (f[0] + conv[p]) / M at natural index g^-p - 1 of the plane; the
+    // real parts go out first (8-byte stores), then the imaginary parts
+    const T sc = (scale_by_m ? scale * (T)M : scale) / (T)M;
+#pragma unroll
+    for (int e = 0; e < E; ++e) gidx[e] = pout[out_pos(t, Tn, e / 5, e % 5, 5, Ll)] - 1;
+    V *y = out + ld.node_off;
+    T *yr = reinterpret_cast<T *>(y);
+    if (act)
+#pragma unroll
+        for (int e = 0; e < E; ++e) pl[gidx[e]] = (f0.x + xr[e]) * sc;
+    __syncthreads();
+    for (int i = tid; i < P; i += blockDim.x) yr[2 * (1 + i)] = pl[i];
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int e = 0; e < E; ++e) pl[gidx[e]] = cj * (f0.y - xi[e]) * sc;   // undo the conjugation
+    __syncthreads();
+    for (int i = tid; i < P; i += blockDim.x) {
+        const T gi = pl[i];
+        yr[2 * (1 + i) + 1] = gi;
+        if (mode == FFT_FWD && bitmap) {
+            const T gr = yr[2 * (1 + i)];   // written by this thread above
+            if (gr * gr + gi * gi >= th2)
+                atomicOr(bitmap + ((ld.node_off + 1 + i) >> 5), 1u << ((ld.node_off + 1 + i) & 31));
+        }
+    }
+    if (tid == 0) {
+        double sr = 0.0, si = 0.0;
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) { sr += red[2 * w]; si += red[2 * w + 1]; }
+        V o;
+        o.x = (T)(((double)f0.x + sr) * (double)sc);
+        o.y = (T)(cj * ((double)f0.y + si) * (double)sc);
+        y[0] = o;
+        if (mode == FFT_FWD && bitmap && o.x * o.x + o.y * o.y >= th2)
+            atomicOr(bitmap + (ld.node_off >> 5), 1u << (ld.node_off & 31));
+    }
+}
+
+// ------------------------------------------------------------------ host
+static int64_t powmod(int64_t a, int64_t e, int64_t m)
+{
+    int64_t r = 1 % m;
+    a %= m;
+    while (e > 0) {
+        if (e & 1) r = (int64_t)((__int128)r * a % m);
+        a = (int64_t)((__int128)a * a % m);
+        e >>= 1;
+    }
+    return r;
+}
+
+static bool is_prime_host(int64_t n)
+{
+    if (n < 2) return false;
+    for (int64_t q = 2; q * q <= n; ++q)
+        if (n % q == 0) return false;
+    return true;
+}
+
+// Radix list of P = 2^a 5^b for the register layout (a >= 2, b >= 1), or empty.
+static std::vector<int> rader_radices(int64_t P)
+{
+    int a = 0, b = 0;
+    int64_t Q = P;
+    while (Q % 2 == 0) { Q /= 2; ++a; }
+    while (Q % 5 == 0) { Q /= 5; ++b; }
+    std::vector<int> r;
+    if (Q != 1 || a < 2 || b < 1) return r;
+    for (int i = 0; i < a / 2; ++i) r.push_back(4);
+    if (a % 2) r.push_back(2);
+    for (int i = 0; i < b; ++i) r.push_back(5);
+    return r;
+}
+
+bool rader_applies(int64_t M, size_t real_bytes)
+{
+    const int64_t P = M - 1;
+    const int64_t E = real_bytes == 8 ? rader_e<double>() : rader_e<float>();
+    const int64_t TH = real_bytes == 8 ? rader_threads<double>() : rader_threads<float>();
+    if (P < E || P % E || P / E > TH) return false;
+    if ((int64_t)real_bytes * P + 2048 > kLdsBytes) return false;
+    if (rader_radices(P).empty()) return false;
+    return is_prime_host(M);
+}
+
+// Length-n DFT (n = 2^a 5^b) in long double, by recursive decimation in time.
+static void dft_ld(std::vector<std::complex<long double>> &x)
+{
+    const size_t n = x.size();
+    if (n == 1) return;
+    const size_t r = (n % 2 == 0) ? 2 : 5;
+    const size_t m = n / r;
+    std::vector<std::vector<std::complex<long double>>> sub(r, std::vector<std::complex<long double>>(m));
+    for (size_t s = 0; s < r; ++s)
+        for (size_t j = 0; j < m; ++j) sub[s][j] = x[j * r + s];
+    for (auto &v : sub) dft_ld(v);
+    const long double tp = -6.283185307179586476925286766559005768L / (long double)n;
+    for (size_t k = 0; k < n; ++k) {
+        std::complex<long double> acc = 0;
+        for (size_t s = 0; s < r; ++s) {
+            const size_t e = (s * k) % n;
+            acc += sub[s][k % m] * std::complex<long double>(cosl(tp * e), sinl(tp * e));
+        }
+        x[k] = acc;
+    }
+}
+
+// Appends the tables of size M: permutations (itab) and twiddles and spectrum
+// (ctab, interleaved re/im of T).
+template <typename T>
+int rader_tables(int64_t M, RaderDesc &rd, std::vector<int32_t> &itab, std::vector<T> &ctab)
+{
+    const int64_t P = M - 1;
+    const std::vector<int> rad = rader_radices(P);
+    rd = RaderDesc{};
+    rd.P = (int32_t)P;
+    rd.nthreads = (int32_t)(P / rader_e<T>());
+    for (int r : rad) {
+        if (r == 4) rd.n4++;
+        else if (r == 2) rd.n2++;
+        else rd.n5++;
+    }
+    // primitive root
+    int64_t g = 2;
+    for (;; ++g) {
+        if (powmod(g, P / 2, M) != 1 && powmod(g, P / 5, M) != 1) break;
+    }
+    const int64_t ginv = powmod(g, M - 2, M);
+    rd.perm_in = (int64_t)itab.size();
+    for (int64_t q = 0, v = 1; q < P; ++q, v = v * g % M) itab.push_back((int32_t)v);
+    rd.perm_out = (int64_t)itab.size();
+    for (int64_t q = 0, v = 1; q < P; ++q, v = v * ginv % M) itab.push_back((int32_t)v);
+    rd.tw = (int64_t)ctab.size() / 2;
+    const long double tpP = -6.283185307179586476925286766559005768L / (long double)P;
+    for (int64_t x = 0; x < P; ++x) {
+        ctab.push_back((T)cosl(tpP * x));
+        ctab.push_back((T)sinl(tpP * x));
+    }
+    // spectrum of b[n] = w^(-g^-n), with the 1/P of the inverse DFT
+    std::vector<std::complex<long double>> b((size_t)P);
+    const long double tpM = -6.283185307179586476925286766559005768L / (long double)M;
+    for (int64_t q = 0, v = 1; q < P; ++q, v = v * ginv % M)
+        b[(size_t)q] = std::complex<long double>(cosl(tpM * v), sinl(tpM * v));
+    dft_ld(b);
+    rd.spec = (int64_t)ctab.size() / 2;
+    for (int64_t k = 0; k < P; ++k) {
+        ctab.push_back((T)(b[(size_t)k].real() / (long double)P));
+        ctab.push_back((T)(b[(size_t)k].imag() / (long double)P));
+    }
+    return MR1L_OK;
+}
+template int rader_tables<double>(int64_t, RaderDesc &, std::vector<int32_t> &, std::vector<double> &);
+template int rader_tables<float>(int64_t, RaderDesc &, std::vector<int32_t> &, std::vector<float> &);
+
+int rader_init_attrs()
+{
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_rader<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes - 2048));
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_rader<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes - 2048));
+    return MR1L_OK;
+}
+
+int rader_launch(Plan &p, const int32_t *d_lats, int nl, const void *in, void *out, double theta,
+                 uint32_t *bitmap, int mode, double scale, int by_m)
+{
+    if (nl <= 0) return MR1L_OK;
+    if (mode == FFT_SPEC) return MR1L_OK;   // the Rader spectra are built on the host
+    int Pmax = 0;
+    for (const RaderDesc &r : p.rdesc) Pmax = std::max(Pmax, r.P);
+    if (p.dtype == MR1L_C128) {
+        const int threads = std::max(64, ((Pmax / rader_e<double>()) + 63) / 64 * 64);
+        const size_t shm = (size_t)Pmax * sizeof(double);
+        hipLaunchKernelGGL(k_rader<double>, dim3((unsigned)nl), dim3(threads), shm, p.stream, d_lats, p.d_lat,
+                           p.d_rdesc, p.d_ritab, (const double2 *)p.d_rctab, (const double2 *)in, (double2 *)out,
+                           bitmap, theta * theta, mode, scale, by_m);
+    } else {
+        const int threads = std::max(64, ((Pmax / rader_e<float>()) + 63) / 64 * 64);
+        const size_t shm = (size_t)Pmax * sizeof(float);
+        hipLaunchKernelGGL(k_rader<float>, dim3((unsigned)nl), dim3(threads), shm, p.stream, d_lats, p.d_lat,
+                           p.d_rdesc, p.d_ritab, (const float2 *)p.d_rctab, (const float2 *)in, (float2 *)out,
+                           bitmap, (float)(theta * theta), mode, (float)scale, by_m);
+    }
+    MR1L_LAUNCH_CHECK();
+    return MR1L_OK;
+}
+
+}  // namespace mr1l

@@ -29,10 +29,12 @@ struct FftSched {
     int32_t batch_log2;   // complex128; complex64 uses one more
     int32_t per_cu;
     int32_t split_floor;
+    int32_t rader;        // Rader's algorithm in registers (prime M, M - 1 = 2^a 5^b)
 };
-constexpr int kNumSched = 9;
+constexpr int kNumSched = 10;
 extern const FftSched kSched[kNumSched];
 constexpr int kDefaultFourStep = 2;
+constexpr int kRaderSched = 9;
 
 // Lattices launched together: schedule, LDS size class (schedule 0), whether the
 // four-step tables fit the LDS, and the lattice list (host and device).
@@ -45,6 +47,15 @@ struct FftGroup {
 constexpr int kLdsClasses = 3;     // whole-LDS transforms: N <= 1024, <= 4096, <= NMAX
 inline int lds_class(int64_t N) { return N <= 1024 ? 0 : (N <= 4096 ? 1 : 2); }
 
+// Rader transform of one prime size M (P = M - 1): register passes and table offsets
+// (permutations in the plan's int32 table, twiddles and the spectrum of the
+// convolution kernel in its complex table).
+struct RaderDesc {
+    int32_t P = 0, nthreads = 0;
+    int32_t n4 = 0, n2 = 0, n5 = 0, pad = 0;   // passes of radix 4, 2 and 5, in this order
+    int64_t perm_in = 0, perm_out = 0, tw = 0, spec = 0;
+};
+
 // Per distinct lattice size: both possible layouts of its transform.
 struct MInfo {
     int64_t M = 0;
@@ -53,6 +64,7 @@ struct MInfo {
     int32_t Np = 0;           // power-of-two length
     int64_t spec_p = -1, tw_p = -1;
     bool ltab = true;         // four-step tables fit the LDS (M <= 32768, N <= 2^16)
+    bool rader = false;       // the Rader schedule applies
     int32_t sched = 0;
     int32_t nlat = 0;
 };
@@ -94,6 +106,10 @@ struct Plan {
     int64_t fft_slot_len = 0;
     int32_t fft_slots = 0;
     void *d_nodes_scratch = nullptr; // [nodes] complex (sampler, adjoint)
+    std::vector<RaderDesc> rdesc;    // per distinct size (P = 0 where Rader does not apply)
+    RaderDesc *d_rdesc = nullptr;
+    int32_t *d_ritab = nullptr;      // Rader permutations
+    void *d_rctab = nullptr;         // Rader twiddles and spectra (dtype complex)
     int64_t *d_det_tmp = nullptr;    // [F] detected counters
     // persistent scratch of extract when the caller passes NULL outputs
     int64_t ex_cap = 0;
@@ -163,6 +179,7 @@ int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap,
             int mode, double scale);
 int fft_prepare_spectra(Plan &p);
 int fft_apply_schedules(Plan &p);
+bool fft_schedule_applies(const MInfo &mi, int s);
 int tuned_schedule(int32_t dtype, int64_t M);
 MDesc fft_layout(const Plan &p, int mid, int s);   // table entry of size mid under schedule s
 int fft_time_plan(Plan &p, const void *in, void *out, int reps, float *ms);   // whole-plan forward DFT
@@ -174,6 +191,11 @@ int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx
 int check_injective_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, int32_t *ok);
 int bspline_sample_run(Plan &p, int32_t d_poly, int32_t n_prod, const int32_t *order, const uint64_t *dims,
                        const uint32_t *anchor, void *f);
+bool rader_applies(int64_t M, size_t real_bytes);
+template <typename T> int rader_tables(int64_t M, RaderDesc &rd, std::vector<int32_t> &itab, std::vector<T> &ctab);
+int rader_init_attrs();
+int rader_launch(Plan &p, const int32_t *d_lats, int nl, const void *in, void *out, double theta,
+                 uint32_t *bitmap, int mode, double scale, int by_m);
 int lsq_init_attrs();
 int lsq_run(Plan &p, int64_t cap, const int64_t *n_det, const int32_t *det_hash, const uint32_t *det_mask,
             const void *ghat, int32_t max_iter, double tol, void *coef, double *resid, int32_t *iters,

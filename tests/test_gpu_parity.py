@@ -206,14 +206,65 @@ def test_fft_every_schedule(m, Ms, dtype):
     plan = m.Plan(1, M, np.ones((len(Ms), 1), np.int64), dtype=dtype)
     names = m.fft_schedule_names()
     for s, name in enumerate(names):
-        if s == 0 and max(Ms) > 5000:
+        if name.startswith("rader"):
+            if not any(rader_ok(int(mm), dtype) for mm in M):
+                with pytest.raises(m.Mr1lError):
+                    plan.fft_schedule(int(M[0]), s)
+                continue
+            for mm in np.unique(M):
+                if rader_ok(int(mm), dtype):
+                    assert plan.fft_schedule(int(mm), s) == s
+        elif s == 0 and max(Ms) > 5000:
             with pytest.raises(m.Mr1lError):
                 plan.fft_schedule(int(M[0]), s)
             continue
-        for mm in np.unique(M):
-            assert plan.fft_schedule(int(mm), s) == s
+        else:
+            for mm in np.unique(M):
+                assert plan.fft_schedule(int(mm), s) == s
         say("fft schedule", name, Ms, dtype)
         _fft_check(m, plan, f, dtype, rng)
+
+
+def rader_ok(M, dtype):
+    """Sizes the Rader schedule takes: prime M, M - 1 = 2^a 5^b, a multiple of the
+    20 values per thread, within one workgroup (1024 threads) and its LDS."""
+    P = M - 1
+    if M < 3 or any(M % q == 0 for q in range(2, int(M ** 0.5) + 1)):
+        return False
+    q = P
+    while q % 2 == 0:
+        q //= 2
+    while q % 5 == 0:
+        q //= 5
+    e, th, w = (20, 1024, 8) if dtype == torch.complex128 else (20, 1024, 4)
+    return q == 1 and P % e == 0 and P // e <= th and P * w + 2048 <= 163840
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_rader_schedule_forward_and_inverse(m, dtype):
+    """Prime sizes with M - 1 = 2^a 5^b under the Rader schedule (with sizes of other
+    schedules in the same plan): the forward DFT against the oracle, and the inverse
+    DFT through the bucket sampler (eq. (2.4) then an inverse lattice DFT times M)."""
+    Ms = [41, 101, 641, 1601, 16001, 211, 4133]
+    rng = np.random.default_rng(3)
+    M = np.array(Ms, np.int64)
+    z = rng.integers(1, 40, size=(len(Ms), 2)) % M[:, None]
+    plan = m.Plan(2, M, z, dtype=dtype)
+    rs = m.fft_schedule_names().index("rader-20")
+    took = [mm for mm in Ms if rader_ok(mm, dtype)]
+    assert 16001 in took
+    for mm in took:
+        assert plan.fft_schedule(mm, rs) == rs
+    say("rader", dtype, took)
+    f = rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum()))
+    _fft_check(m, plan, f, dtype, rng)
+    freq = synth.distinct_uniform_points(rng, 300, 2, -500, 500)
+    coef = rng.standard_normal(300) + 1j * rng.standard_normal(300)
+    got = m.mr1l_sample(plan, T(freq), T(coef).to(dtype), mode=2)
+    torch.cuda.synchronize()
+    want = oracle.sample(freq, coef, M, z)
+    err = np.abs(got.cpu().numpy().astype(np.complex128) - want).max() / np.abs(want).max()
+    assert err <= 10 * TOL[dtype], err
 
 
 def test_fft_tuner_picks_fastest_and_stays_exact(m):
