@@ -45,6 +45,17 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def vote_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("k_hash.hip", "mr1l_device.h"):
@@ -255,6 +266,83 @@ def bench_dimincr(m, torch, args):
         out["cpu_baseline"] = {"value": dt, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": "one full driver run (seed 0) of the oracle: direct DFTs, "
                                          "long-double arithmetic"}
+    print(json.dumps(out), flush=True)
+
+
+# ----------------------------------------------------------------------------- small / mid
+def bench_plain(m, torch, args):
+    """The small (d = 5, 2000 candidates, s = 20, L = 5, 100 seeds) and mid (d = 10, 10^5
+    candidates, s = 100, L = 10, 40 dB, 20 seeds) configurations: one DFT + extract pass
+    per function on resident samples, per-function calls (plain) and, for the small
+    configuration, all 100 functions in one batched plan.  Launch-latency bound."""
+    import synth
+    dev = torch.device("cuda", 0)
+    res = {}
+    for name, mk, seeds in (("small", lambda sd: synth.small_config(sd), 100),
+                            ("mid", lambda sd: synth.mid_config(sd), 20)):
+        items = []
+        for sd in range(seeds):
+            p = mk(sd)
+            plan = m.Plan(p.d, p.M, p.z)
+            f = m.mr1l_sample(plan, torch.from_numpy(p.supp).to(dev), torch.from_numpy(p.coef).to(dev))
+            if name == "mid":   # 40 dB complex Gaussian noise per lattice
+                fn = f.cpu().numpy()
+                f = torch.from_numpy(fn + synth.noise_for(fn, p.M, 40.0, sd)).to(dev)
+            cand = torch.from_numpy(p.cand).to(dev)
+            g, bm = m.mr1l_fft(plan, f, p.theta)
+            ex = m.extract_buffers(plan, 4096, 2 * len(p.coef), 0, want_w=False)
+            items.append((p, plan, f, cand, g, bm, ex))
+        def one_pass():
+            for p, plan, f, cand, g, bm, ex in items:
+                m.mr1l_fft(plan, f, p.theta, ghat=g, bitmap=bm)
+                m.mr1l_extract(plan, cand, g, bm, p.theta, s_cap=ex.s_cap, cap=4096, want_w=False, out=ex)
+        for _ in range(args.warmup):
+            one_pass()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            one_pass()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        cl = sum(p.cand.shape[1] * len(p.M) for p, *_ in items)
+        res[name] = {"functions": seeds, "functions_per_s_plain": seeds / dt, "cand_lattices_per_s_plain": cl / dt,
+                     "ms_per_function": 1000.0 * dt / seeds}
+        log(name, f"plain: {seeds / dt:.0f} functions/s, {cl / dt:.3e} cand*lattices/s")
+        for it in items:
+            it[1].close()
+    # small configuration batched: the 100 functions in one plan
+    ps = [synth.small_config(sd) for sd in range(100)]
+    plan = m.Plan(5, np.concatenate([p.M for p in ps]), np.concatenate([p.z for p in ps]), F=100)
+    off = np.concatenate([[0], np.cumsum([p.cand.shape[1] for p in ps])]).astype(np.int64)
+    toff = np.concatenate([[0], np.cumsum([len(p.coef) for p in ps])]).astype(np.int64)
+    f = m.mr1l_sample(plan, torch.from_numpy(np.concatenate([p.supp for p in ps], axis=1)).to(dev),
+                      torch.from_numpy(np.concatenate([p.coef for p in ps])).to(dev),
+                      term_off=torch.from_numpy(toff).to(dev))
+    cand = torch.from_numpy(np.concatenate([p.cand for p in ps], axis=1)).to(dev)
+    so = torch.from_numpy(off).to(dev)
+    g, bm = m.mr1l_fft(plan, f, 1e-12)
+    ex = m.extract_buffers(plan, 4096, 40, 0, want_w=False)
+    def batched():
+        m.mr1l_fft(plan, f, 1e-12, ghat=g, bitmap=bm)
+        m.mr1l_extract(plan, cand, g, bm, 1e-12, s_cap=40, cap=4096, set_off=so, want_w=False, out=ex)
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    res["small"]["functions_per_s_batched"] = 100 / dt
+    log("small", f"batched: {100 / dt:.0f} functions/s")
+    out = {"metric": "functions per second, small configuration, per-function calls", "value":
+           res["small"]["functions_per_s_plain"], "unit": "functions/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["small"]["ms_per_function"] * 100, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+           "config": {"workload": "small: d=5, 2000 candidates in [-32,32]^5, s=20, L=5, 100 seeds; "
+                                  "mid: d=10, 1e5 candidates in [-64,64]^10, s=100, L=10, 40 dB, 20 seeds; "
+                                  "one step = one DFT + extract pass over every function"},
+           "results": res}
     print(json.dumps(out), flush=True)
 
 
@@ -537,6 +625,7 @@ def cpu_baseline_large(w, n_sample, budget_s=10.0):
     sub = np.ascontiguousarray(cand_np[:, :n_sample])
     ro_sub = oracle.extract(sub, Ms, z, g_exact, w["theta"], s_cap=w["s_cap"], cap=w["cap"])
     return dict(value=value, unit="candidates\u00b7lattices/s", cores=oracle.num_threads(), kind="oracle",
+                cpu_model=cpu_model(),
                 dft_s_per_rep=t_dft / reps, extract_s_per_rep=t_ex / reps,
                 sample=(f"function 0 of the batch, {reps} repetitions: direct O(M^2) DFTs of its {L} lattices "
                         f"({t_dft / reps:.2f}s each) + Algorithm 2/Remark 2.9/Algorithm 4 over all {n} "
@@ -563,8 +652,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("large", "batch", "dimincr", "worst-case", "bspline"), default="large")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=("large", "batch", "dimincr", "worst-case", "bspline", "plain"),
+                    default="large")
     ap.add_argument("--lsq-iters", type=int, default=200,
                     help="bspline workload: CG iterations of the least-squares final step (second run per seed)")
     ap.add_argument("--m-of", choices=("s", "s_local"), default="s",
@@ -610,6 +700,8 @@ def main():
     if args.workload == "bspline":
         args.reps = args.reps or 3
         return bench_bspline(m, torch, args)
+    if args.workload == "plain":
+        return bench_plain(m, torch, args)
 
     if args.workload == "large":
         F = args.functions or 64
