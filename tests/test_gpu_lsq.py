@@ -128,3 +128,37 @@ def test_lsq_batched_many_lattices_and_empty(m):
         err = np.abs(got - want).max() / np.abs(want).max()
         say("function", fi, "n_det", nd, "iters", int(ls["iters"][fi]), "err", err)
         assert err < 1e-9
+
+
+def test_lsq_long_list_global_sums_match_lds_sums(m):
+    """A 9,000-entry detected list (cap > 8192: the CG's group sums in global memory):
+    the solution satisfies the normal equations G c = b rebuilt on the host from the
+    oracle's buckets and the lattice values (the DFT itself is checked elsewhere)."""
+    say("lsq long list")
+    rng = np.random.default_rng(23)
+    d, n, L = 3, 9000, 5
+    cand = synth.distinct_uniform_points(rng, n, d, -400, 400)
+    M, z = synth.draw_lattices(rng, L, d, 40000, 60000)
+    f = rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum()))
+    plan = m.Plan(d, M, z)
+    g, bm = m.mr1l_fft(plan, T(f), 1e-9)
+    ex = m.mr1l_extract(plan, T(cand), g, bm, 1e-9, s_cap=100, cap=n, want_w=False)
+    torch.cuda.synchronize()
+    assert int(ex["n_det"][0]) == n
+    ls = m.mr1l_lsq(plan, ex, g, max_iter=300, tol=1e-13)
+    torch.cuda.synchronize()
+    say("iters", int(ls["iters"][0]), "resid", float(ls["resid"][0]))
+    assert float(ls["resid"][0]) <= 1e-13
+    # normal equations checked on the host: G c = b, G and b from the bucket structure
+    c = ls["coef"][0, :n].cpu().numpy()
+    h = oracle.hash_buckets(cand, M, z)
+    go = g.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum(M)])
+    Gc = np.zeros(n, np.complex128)
+    b = np.zeros(n, np.complex128)
+    for l in range(L):
+        sums = np.zeros(int(M[l]), np.complex128)
+        np.add.at(sums, h[l], c)
+        Gc += M[l] * sums[h[l]]
+        b += M[l] * go[offs[l] + h[l]]
+    assert np.linalg.norm(Gc - b) <= 1e-10 * np.linalg.norm(b)
