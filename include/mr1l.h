@@ -297,7 +297,9 @@ int mr1l_check_injective(mr1l_plan p, int64_t n_total, const int64_t *set_off,
  *   iters    dev int32 [F] iterations taken | NULL.
  *   theta, s_cap, n_out, out_idx, out_coef  Algorithm 4 on the solution, as
  *            in mr1l_extract; n_out == NULL skips it.
- * Asynchronous on the plan's stream; grows plan scratch of
+ * Asynchronous on the plan's stream, except that with cap > 8192 and
+ * n_out != NULL it synchronises once (to size the global-memory sort of
+ * Algorithm 4, as mr1l_extract does); grows plan scratch of
  * F*cap*(4L + 4*sizeof(complex)) bytes on first use (not during graph
  * capture); MR1L_E_ARG for invalid arguments.
  */

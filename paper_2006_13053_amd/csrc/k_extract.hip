@@ -596,6 +596,51 @@ static int grow_sort(Plan &p, int64_t P)
     return MR1L_OK;
 }
 
+// Algorithm 4 on a long list (sort buffers sized for P >= every function's count):
+// keys, global sort, first s~
+static int limit_long(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef,
+                      double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef,
+                      int32_t *out_pos, int64_t P)
+{
+    uint64_t *skey = (uint64_t *)p.d_gsort;
+    int32_t *spos = (int32_t *)(skey + p.F * P);
+    int64_t *npass = p.d_det_tmp;
+    int rc = launch_fill_bytes(npass, p.F * (int64_t)sizeof(int64_t), p.stream);
+    if (rc) return rc;
+    const dim3 gp((unsigned)((P + 255) / 256), (unsigned)p.F);
+    if (p.dtype == MR1L_C128)
+        hipLaunchKernelGGL(k_limit_keys<double>, gp, dim3(256), 0, p.stream, n_det, cap, (const double2 *)det_coef,
+                           theta * theta, P, skey, spos, npass);
+    else
+        hipLaunchKernelGGL(k_limit_keys<float>, gp, dim3(256), 0, p.stream, n_det, cap, (const float2 *)det_coef,
+                           (float)(theta * theta), P, skey, spos, npass);
+    MR1L_LAUNCH_CHECK();
+    if ((rc = gsort_run(p, skey, spos, P))) return rc;
+    const dim3 ge((unsigned)((s_cap + 255) / 256), (unsigned)p.F);
+    if (p.dtype == MR1L_C128)
+        hipLaunchKernelGGL(k_limit_emit<double>, ge, dim3(256), 0, p.stream, npass, cap, det_idx,
+                           (const double2 *)det_coef, P, spos, s_cap, n_out, out_idx, (double2 *)out_coef, out_pos);
+    else
+        hipLaunchKernelGGL(k_limit_emit<float>, ge, dim3(256), 0, p.stream, npass, cap, det_idx,
+                           (const float2 *)det_coef, P, spos, s_cap, n_out, out_idx, (float2 *)out_coef, out_pos);
+    MR1L_LAUNCH_CHECK();
+    return MR1L_OK;
+}
+
+// the longest of the F detected lists (one synchronisation) and sort buffers of its
+// power-of-two size
+static int long_list_size(Plan &p, const int64_t *n_det, int64_t cap, int64_t &nmax, int64_t &P)
+{
+    if (p.capturing) return fail(MR1L_E_ARG, "lists longer than 8192 cannot be recorded in a graph");
+    std::vector<int64_t> nd((size_t)p.F);
+    MR1L_HIP(hipMemcpyAsync(nd.data(), n_det, nd.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p.stream));
+    MR1L_HIP(hipStreamSynchronize(p.stream));
+    nmax = 0;
+    for (int64_t v : nd) nmax = std::max(nmax, std::min(v, cap));
+    P = pow2ceil(std::max<int64_t>(nmax, 1));
+    return grow_sort(p, P);
+}
+
 int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, const void *ghat,
                      const mr1l_extract_opts &o, const mr1l_extract_out &out, int32_t *det_hash, double *det_w,
                      uint32_t *det_mask, void *det_med, int32_t *out_pos)
@@ -612,15 +657,8 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
                            out.det_idx);
         MR1L_LAUNCH_CHECK();
     } else {
-        // the sort sizes come from the detected counts: one synchronisation
-        if (p.capturing) return fail(MR1L_E_ARG, "lists longer than 8192 cannot be recorded in a graph");
-        std::vector<int64_t> nd((size_t)p.F);
-        MR1L_HIP(hipMemcpyAsync(nd.data(), out.n_det, nd.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p.stream));
-        MR1L_HIP(hipStreamSynchronize(p.stream));
-        nmax = 0;
-        for (int64_t v : nd) nmax = std::max(nmax, std::min(v, cap));
-        P = pow2ceil(std::max<int64_t>(nmax, 1));
-        if ((rc = grow_sort(p, P))) return rc;
+        // the sort sizes come from the detected counts
+        if ((rc = long_list_size(p, out.n_det, cap, nmax, P))) return rc;
         skey = (uint64_t *)p.d_gsort;
         spos = (int32_t *)(skey + p.F * P);
         const dim3 gp((unsigned)((P + 255) / 256), (unsigned)p.F);
@@ -666,35 +704,19 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
         MR1L_LAUNCH_CHECK();
         return MR1L_OK;
     }
-    // Algorithm 4 on a long list: keys, global sort, first s~
-    int64_t *npass = p.d_det_tmp;
-    if ((rc = launch_fill_bytes(npass, p.F * (int64_t)sizeof(int64_t), p.stream))) return rc;
-    const dim3 gp((unsigned)((P + 255) / 256), (unsigned)p.F);
-    if (p.dtype == MR1L_C128)
-        hipLaunchKernelGGL(k_limit_keys<double>, gp, dim3(256), 0, p.stream, out.n_det, cap,
-                           (const double2 *)out.det_coef, o.theta * o.theta, P, skey, spos, npass);
-    else
-        hipLaunchKernelGGL(k_limit_keys<float>, gp, dim3(256), 0, p.stream, out.n_det, cap,
-                           (const float2 *)out.det_coef, (float)(o.theta * o.theta), P, skey, spos, npass);
-    MR1L_LAUNCH_CHECK();
-    if ((rc = gsort_run(p, skey, spos, P))) return rc;
-    const dim3 ge((unsigned)((o.s_cap + 255) / 256), (unsigned)p.F);
-    if (p.dtype == MR1L_C128)
-        hipLaunchKernelGGL(k_limit_emit<double>, ge, dim3(256), 0, p.stream, npass, cap, out.det_idx,
-                           (const double2 *)out.det_coef, P, spos, o.s_cap, out.n_out, out.out_idx,
-                           (double2 *)out.out_coef, out_pos);
-    else
-        hipLaunchKernelGGL(k_limit_emit<float>, ge, dim3(256), 0, p.stream, npass, cap, out.det_idx,
-                           (const float2 *)out.det_coef, P, spos, o.s_cap, out.n_out, out.out_idx,
-                           (float2 *)out.out_coef, out_pos);
-    MR1L_LAUNCH_CHECK();
-    return MR1L_OK;
+    return limit_long(p, out.n_det, cap, out.det_idx, out.det_coef, o.theta, o.s_cap, out.n_out, out.out_idx,
+                      out.out_coef, out_pos, P);
 }
 
 int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef, double theta,
               int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef)
 {
-    if (cap < 1 || cap > kMaxCap) return fail(MR1L_E_ARG, "capacity must be in [1, 8192]");
+    if (cap < 1 || cap > kMaxCapLarge) return fail(MR1L_E_ARG, "capacity must be in [1, 2^24]");
+    if (cap > kMaxCap) {
+        int64_t nmax = 0, P = 1;
+        const int rc = long_list_size(p, n_det, cap, nmax, P);
+        return rc ? rc : limit_long(p, n_det, cap, det_idx, det_coef, theta, s_cap, n_out, out_idx, out_coef, nullptr, P);
+    }
     const size_t pc = (size_t)pow2ceil(cap);
     if (p.dtype == MR1L_C128)
         hipLaunchKernelGGL(k_limit<double>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, n_det, cap, det_idx,

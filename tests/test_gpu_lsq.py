@@ -130,10 +130,11 @@ def test_lsq_batched_many_lattices_and_empty(m):
         assert err < 1e-9
 
 
-def test_lsq_long_list_global_sums_match_lds_sums(m):
-    """A 9,000-entry detected list (cap > 8192: the CG's group sums in global memory):
-    the solution satisfies the normal equations G c = b rebuilt on the host from the
-    oracle's buckets and the lattice values (the DFT itself is checked elsewhere)."""
+def test_lsq_long_list_normal_equations(m):
+    """A 9,000-entry detected list (cap > 8192: the CG's group sums in global memory,
+    Algorithm 4 by the global sort): the solution satisfies the normal equations
+    G c = b rebuilt on the host from the oracle's buckets and the lattice values (the
+    DFT itself is checked elsewhere), and the kept s~ = 100 are its largest entries."""
     say("lsq long list")
     rng = np.random.default_rng(23)
     d, n, L = 3, 9000, 5
@@ -162,3 +163,8 @@ def test_lsq_long_list_global_sums_match_lds_sums(m):
         Gc += M[l] * sums[h[l]]
         b += M[l] * go[offs[l] + h[l]]
     assert np.linalg.norm(Gc - b) <= 1e-10 * np.linalg.norm(b)
+    # Algorithm 4 on the solution: the 100 largest magnitudes (theta is far below them)
+    c_dev = ls["coef"][0, :n].cpu().numpy()
+    want = set(cand_idx for cand_idx in np.asarray(ex["det_idx"][0, :n].cpu())[np.argsort(-np.abs(c_dev))[:100]])
+    assert int(ls["n_out"][0]) == 100
+    assert set(ls["out_idx"][0].cpu().numpy().tolist()) == want
