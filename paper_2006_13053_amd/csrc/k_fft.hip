@@ -814,7 +814,7 @@ static int launch_sched(Plan &p, int s, int cls, const int32_t *d_lats, int nl, 
         return ltab ? launch4<T, true, 256, LS, 2>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc)
                     : launch4<T, false, 256, LS, 2>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc);
     case 9:
-        return rader_launch(p, d_lats, nl, in, out, theta, bitmap, mode, scale, by_m);
+        return rader_launch(p, cls, d_lats, nl, in, out, theta, bitmap, mode, scale, by_m);   // cls = M - 1
     default:
         return fail(MR1L_E_ARG, "unknown DFT schedule");
     }
@@ -942,7 +942,8 @@ int fft_apply_schedules(Plan &p)
     int64_t len = 0, slots = 0;
     for (size_t i = 0; i < p.lat.size(); ++i) {
         const MInfo &mi = p.minfo[p.lat[i].mid];
-        const int cls = (kSched[mi.sched].four_step || kSched[mi.sched].rader) ? 0 : lds_class(mi.Ns);
+        // one group per size for the Rader kernels (compiled per length M - 1)
+        const int cls = kSched[mi.sched].rader ? (int)(mi.M - 1) : kSched[mi.sched].four_step ? 0 : lds_class(mi.Ns);
         auto it = gi.find({mi.sched, cls});
         if (it == gi.end()) {
             it = gi.emplace(std::make_pair(mi.sched, cls), p.fft_groups.size()).first;

@@ -16,14 +16,42 @@
 
 namespace mr1l {
 
-// values per thread (20) and the largest workgroup: P <= 20480 (and the LDS plane
-// bounds P further in double).  40 values in 512 threads (256 registers each) was
-// slower in double: fewer waves to hide the LDS and barrier latency.
-template <typename T> constexpr int rader_e() { return 20; }
-template <typename T> constexpr int rader_threads() { return 1024; }
+// Values per thread.  Every supported length P = M - 1 (the prime lattice sizes
+// M = 20 2^i 5^j + 1 up to P = 20480) gets its own kernel, so that the pass sequence,
+// the sub-lengths and all index arithmetic are compile-time constants.  40 values in
+// half the threads was slower in double: fewer waves to hide the LDS and barrier
+// latency.
+constexpr int kRaderE = 20;
+constexpr int kRaderSizes[] = {40, 100, 400, 640, 1600, 4000, 16000};
+
+constexpr int rader_log(int P, int b)
+{
+    int n = 0;
+    while (P % b == 0) { P /= b; ++n; }
+    return n;
+}
+
+// The transform of length P: 20 values in each of P/20 threads, passes of radix 4
+// (a/2 of them), 2 (a mod 2) and 5 (b), in this order, for P = 2^a 5^b.
+template <int P> struct RShape {
+    static constexpr int E = kRaderE;
+    static constexpr int Tn = P / E;
+    static constexpr int threads = (Tn + 63) / 64 * 64;
+    static constexpr int n4 = rader_log(P, 2) / 2, n2 = rader_log(P, 2) % 2, n5 = rader_log(P, 5);
+    static constexpr int NP = n4 + n2 + n5;
+    static constexpr int radix(int i) { return i < n4 ? 4 : (i < n4 + n2 ? 2 : 5); }
+    static constexpr int sub(int i)   // sub-length before pass i
+    {
+        int L = 1;
+        for (int k = 0; k < i; ++k) L *= radix(k);
+        return L;
+    }
+    static constexpr int Llast = sub(NP - 1);
+    static_assert(P % E == 0 && n4 >= 1 && n5 >= 1 && Tn <= 1024, "P = 20 2^i 5^j <= 20480");
+};
 
 // Hides a value from the optimiser so that per-pass index arithmetic is not hoisted
-// out of the pass loop (which would hold all passes' indices in registers).
+// out of the pass sequence (which would hold all passes' indices in registers).
 __device__ __forceinline__ int rader_opaque(int x)
 {
     asm volatile("" : "+v"(x));
@@ -62,126 +90,113 @@ __device__ __forceinline__ void dft_small(T *xr, T *xi)
     }
 }
 
-// One Stockham pass of radix R: butterfly j = tid + Tn c (c < E/R) takes the inputs
-// j + m P/R, twiddles them by W_{LR}^{k m} (k = j mod L) and leaves the outputs for
-// positions (j / L) L R + k + p L.
-template <typename T, int R, int E>
-__device__ __forceinline__ void rader_pass(T (&xr)[E], T (&xi)[E], int tid, int Tn, int P, int L,
+// One Stockham pass of radix R on sub-length L: butterfly j = tid + Tn c
+// (c < E/R) takes the inputs j + m P/R, twiddles them by W_{LR}^{k m} (k = j mod L)
+// and leaves the outputs for positions (j / L) L R + k + p L.
+template <typename T, int P, int R, int L>
+__device__ __forceinline__ void rader_pass(T (&xr)[kRaderE], T (&xi)[kRaderE], int tid,
                                            const typename cvec<T>::type *__restrict__ tw)
 {
     using V = typename cvec<T>::type;
-    const int step = P / (L * R);
+    constexpr int E = kRaderE, Tn = P / E, step = P / (L * R);
 #pragma unroll
     for (int c = 0; c < E / R; ++c) {
-        const int j = tid + Tn * c;
-        const int k = j % L;
-        const V w1 = tw[k * step];
-        T wr = 1, wi = 0;
+        if constexpr (L > 1) {   // the first pass has no twiddles
+            const int k = (tid + Tn * c) % L;
+            const V w1 = tw[k * step];
+            T wr = w1.x, wi = w1.y;
 #pragma unroll
-        for (int m = 1; m < R; ++m) {
-            const T nr = wr * w1.x - wi * w1.y;
-            wi = wr * w1.y + wi * w1.x;
-            wr = nr;
-            const T ar = xr[c * R + m], ai = xi[c * R + m];
-            xr[c * R + m] = ar * wr - ai * wi;
-            xi[c * R + m] = ar * wi + ai * wr;
+            for (int m = 1; m < R; ++m) {
+                if (m > 1) {
+                    const T nr = wr * w1.x - wi * w1.y;
+                    wi = wr * w1.y + wi * w1.x;
+                    wr = nr;
+                }
+                const T ar = xr[c * R + m], ai = xi[c * R + m];
+                xr[c * R + m] = ar * wr - ai * wi;
+                xi[c * R + m] = ar * wi + ai * wr;
+            }
         }
         dft_small<T, R>(xr + c * R, xi + c * R);
     }
 }
 
 // Output position of value (c, p) of a pass of radix R with sub-length L.
-__device__ __forceinline__ int out_pos(int tid, int Tn, int c, int p, int R, int L)
+template <int P, int R, int L>
+__device__ __forceinline__ int out_pos(int tid, int c, int p)
 {
-    const int j = tid + Tn * c;
+    const int j = tid + (P / kRaderE) * c;
     return (j / L) * L * R + (j % L) + p * L;
 }
 
-template <typename T, int R, int E>
-__device__ __forceinline__ void put_plane(T *pl, const T (&x)[E], int tid, int Tn, int L)
+template <typename T, int P, int R, int L>
+__device__ __forceinline__ void put_plane(T *pl, const T (&x)[kRaderE], int tid)
 {
 #pragma unroll
-    for (int c = 0; c < E / R; ++c)
+    for (int c = 0; c < kRaderE / R; ++c)
 #pragma unroll
-        for (int p = 0; p < R; ++p) pl[out_pos(tid, Tn, c, p, R, L)] = x[c * R + p];
+        for (int p = 0; p < R; ++p) pl[out_pos<P, R, L>(tid, c, p)] = x[c * R + p];
 }
 
-template <typename T, int R, int E>
-__device__ __forceinline__ void get_plane(const T *pl, T (&x)[E], int tid, int Tn, int P)
+template <typename T, int P, int R>
+__device__ __forceinline__ void get_plane(const T *pl, T (&x)[kRaderE], int tid)
 {
 #pragma unroll
-    for (int c = 0; c < E / R; ++c)
+    for (int c = 0; c < kRaderE / R; ++c)
 #pragma unroll
-        for (int m = 0; m < R; ++m) x[c * R + m] = pl[tid + Tn * c + m * (P / R)];
+        for (int m = 0; m < R; ++m) x[c * R + m] = pl[tid + (P / kRaderE) * c + m * (P / R)];
 }
 
-// Values leave the layout of a pass (radix RO, sub-length Lo) for the input layout
+// Values leave the layout of a pass (radix RO, sub-length LO) for the input layout
 // of a pass of radix RI, through the LDS plane, real and imaginary parts in turn.
 // Inactive threads (tid >= Tn) take part in the barriers only.
-template <typename T, int E, int RO, int RI>
-__device__ __forceinline__ void exchange(T *pl, T (&xr)[E], T (&xi)[E], bool act, int tid, int Tn, int P, int Lo)
+template <typename T, int P, int RO, int LO, int RI>
+__device__ __forceinline__ void exchange(T *pl, T (&xr)[kRaderE], T (&xi)[kRaderE], bool act, int tid)
 {
-    // each call gets its own opaque copy of tid, so the addresses are recomputed
+    // each access gets its own opaque copy of tid, so the addresses are recomputed
     // instead of being held across the barriers
-    if (act) put_plane<T, RO, E>(pl, xr, rader_opaque(tid), Tn, Lo);
+    if (act) put_plane<T, P, RO, LO>(pl, xr, rader_opaque(tid));
     __syncthreads();
-    if (act) get_plane<T, RI, E>(pl, xr, rader_opaque(tid), Tn, P);
+    if (act) get_plane<T, P, RI>(pl, xr, rader_opaque(tid));
     __syncthreads();
-    if (act) put_plane<T, RO, E>(pl, xi, rader_opaque(tid), Tn, Lo);
+    if (act) put_plane<T, P, RO, LO>(pl, xi, rader_opaque(tid));
     __syncthreads();
-    if (act) get_plane<T, RI, E>(pl, xi, rader_opaque(tid), Tn, P);
+    if (act) get_plane<T, P, RI>(pl, xi, rader_opaque(tid));
     __syncthreads();
 }
 
-// A length-P DFT (forward sign) on values already in the input layout of the first
-// pass: n4 passes of radix 4, n2 (0 or 1) of radix 2, n5 of radix 5, in this order.
-// Returns the sub-length of the last pass (its outputs are in radix-5 layout).
-template <typename T, int E>
-__device__ __forceinline__ int dft_passes(T *pl, T (&xr)[E], T (&xi)[E], bool act, int t, int tid, int Tn, int P,
-                                          int n4, int n2, int n5, const typename cvec<T>::type *__restrict__ tw)
+// Passes I, I + 1, ... of a length-P DFT (forward sign), the values in the input
+// layout of pass I; the outputs end in the layout of the last (radix-5) pass.
+template <typename T, int P, int I>
+__device__ __forceinline__ void dft_passes(T *pl, T (&xr)[kRaderE], T (&xi)[kRaderE], bool act, int t, int tid,
+                                           const typename cvec<T>::type *__restrict__ tw)
 {
-    int L = 1, Lprev = 1;
-    for (int i = 0; i < n4; ++i) {
-        if (i > 0) exchange<T, E, 4, 4>(pl, xr, xi, act, tid, Tn, P, Lprev);
-        if (act) rader_pass<T, 4, E>(xr, xi, rader_opaque(t), Tn, P, L, tw);
-        Lprev = L; L *= 4;
+    using S = RShape<P>;
+    if constexpr (I < S::NP) {
+        if constexpr (I > 0) exchange<T, P, S::radix(I - 1), S::sub(I - 1), S::radix(I)>(pl, xr, xi, act, tid);
+        if (act) rader_pass<T, P, S::radix(I), S::sub(I)>(xr, xi, rader_opaque(t), tw);
+        dft_passes<T, P, I + 1>(pl, xr, xi, act, t, tid, tw);
     }
-    if (n2) {
-        exchange<T, E, 4, 2>(pl, xr, xi, act, tid, Tn, P, Lprev);
-        if (act) rader_pass<T, 2, E>(xr, xi, rader_opaque(t), Tn, P, L, tw);
-        Lprev = L; L *= 2;
-    }
-    for (int i = 0; i < n5; ++i) {
-        if (i == 0) {
-            if (n2) exchange<T, E, 2, 5>(pl, xr, xi, act, tid, Tn, P, Lprev);
-            else exchange<T, E, 4, 5>(pl, xr, xi, act, tid, Tn, P, Lprev);
-        } else {
-            exchange<T, E, 5, 5>(pl, xr, xi, act, tid, Tn, P, Lprev);
-        }
-        if (act) rader_pass<T, 5, E>(xr, xi, rader_opaque(t), Tn, P, L, tw);
-        Lprev = L; L *= 5;
-    }
-    return Lprev;
 }
 
 // mode: FFT_FWD (ghat = (1/M) sum f w^{-jh} times scale, and the non-zero bitmap) or
 // FFT_INV (scale (1/M) sum g w^{+jh}, times M when scale_by_m).
-template <typename T>
-__global__ __launch_bounds__(rader_threads<T>()) void k_rader(
+template <typename T, int P>
+__global__ __launch_bounds__(RShape<P>::threads) void k_rader(
     const int32_t *__restrict__ lats, const LatDesc *__restrict__ lat, const RaderDesc *__restrict__ rdesc,
     const int32_t *__restrict__ itab, const typename cvec<T>::type *__restrict__ ctab,
     const typename cvec<T>::type *__restrict__ in, typename cvec<T>::type *__restrict__ out,
     uint32_t *__restrict__ bitmap, T th2, int mode, T scale, int scale_by_m)
 {
     using V = typename cvec<T>::type;
-    constexpr int E = rader_e<T>();
+    using S = RShape<P>;
+    constexpr int E = kRaderE, Tn = S::Tn, NT = S::threads, Ll = S::Llast;
     extern __shared__ __align__(16) unsigned char smem[];
     T *pl = reinterpret_cast<T *>(smem);
-    __shared__ double red[2 * (rader_threads<T>() / 64)];
+    __shared__ double red[2 * (NT / 64)];
     const LatDesc ld = lat[lats[blockIdx.x]];
     const RaderDesc *rd = rdesc + ld.mid;
-    const int P = rd->P, Tn = rd->nthreads, M = ld.M;
-    const int n4 = rd->n4, n2 = rd->n2, n5 = rd->n5;
+    const int M = P + 1;
     const int tid = threadIdx.x;
     const bool act = tid < Tn;
     const int t = act ? tid : 0;   // inactive threads mirror thread 0 (in range), results unused
@@ -194,9 +209,8 @@ __global__ __launch_bounds__(rader_threads<T>()) void k_rader(
     T xr[E], xi[E];
 
     // a[q] = f[g^q]: f[1..M) through the plane in natural order, gathered in the
-    // input order of the first pass
-    // (the radix list starts with 4 and ends with 5: M - 1 = 2^a 5^b with a >= 2, b >= 1)
-    for (int i = tid; i < P; i += blockDim.x) pl[i] = x[1 + i].x;
+    // input order of the first (radix-4) pass
+    for (int i = tid; i < P; i += NT) pl[i] = x[1 + i].x;
     __syncthreads();
     int gidx[E];
     // first-pass input index of register e = 4 c + m: q = t + Tn c + m P / 4
@@ -205,7 +219,7 @@ __global__ __launch_bounds__(rader_threads<T>()) void k_rader(
 #pragma unroll
     for (int e = 0; e < E; ++e) xr[e] = pl[gidx[e]];
     __syncthreads();
-    for (int i = tid; i < P; i += blockDim.x) pl[i] = cj * x[1 + i].y;
+    for (int i = tid; i < P; i += NT) pl[i] = cj * x[1 + i].y;
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) xi[e] = pl[gidx[e]];
@@ -227,38 +241,42 @@ __global__ __launch_bounds__(rader_threads<T>()) void k_rader(
     }
 
     // forward length-P DFT of a
-    int Ll = dft_passes<T, E>(pl, xr, xi, act, t, tid, Tn, P, n4, n2, n5, tw);
+    dft_passes<T, P, 0>(pl, xr, xi, act, t, tid, tw);
     // times the spectrum of b (with 1/P), conjugated for the inverse DFT
     if (act) {
+        const int tt = rader_opaque(t);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const V s = sp[out_pos(t, Tn, e / 5, e % 5, 5, Ll)];
+            const V s = sp[out_pos<P, 5, Ll>(tt, e / 5, e % 5)];
             const T ar = xr[e], ai = xi[e];
             xr[e] = ar * s.x - ai * s.y;
             xi[e] = -(ar * s.y + ai * s.x);
         }
     }
     // inverse length-P DFT (conjugated input): the convolution, conjugated
-    exchange<T, E, 5, 4>(pl, xr, xi, act, tid, Tn, P, Ll);
-    Ll = dft_passes<T, E>(pl, xr, xi, act, t, tid, Tn, P, n4, n2, n5, tw);
+    exchange<T, P, 5, Ll, 4>(pl, xr, xi, act, tid);
+    dft_passes<T, P, 0>(pl, xr, xi, act, t, tid, tw);
     // ghat[g^-p] = (f[0] + conv[p]) / M at natural index g^-p - 1 of the plane; the
     // real parts go out first (8-byte stores), then the imaginary parts
     const T sc = (scale_by_m ? scale * (T)M : scale) / (T)M;
+    {
+        const int tt = rader_opaque(t);
 #pragma unroll
-    for (int e = 0; e < E; ++e) gidx[e] = pout[out_pos(t, Tn, e / 5, e % 5, 5, Ll)] - 1;
+        for (int e = 0; e < E; ++e) gidx[e] = pout[out_pos<P, 5, Ll>(tt, e / 5, e % 5)] - 1;
+    }
     V *y = out + ld.node_off;
     T *yr = reinterpret_cast<T *>(y);
     if (act)
 #pragma unroll
         for (int e = 0; e < E; ++e) pl[gidx[e]] = (f0.x + xr[e]) * sc;
     __syncthreads();
-    for (int i = tid; i < P; i += blockDim.x) yr[2 * (1 + i)] = pl[i];
+    for (int i = tid; i < P; i += NT) yr[2 * (1 + i)] = pl[i];
     __syncthreads();
     if (act)
 #pragma unroll
         for (int e = 0; e < E; ++e) pl[gidx[e]] = cj * (f0.y - xi[e]) * sc;   // undo the conjugation
     __syncthreads();
-    for (int i = tid; i < P; i += blockDim.x) {
+    for (int i = tid; i < P; i += NT) {
         const T gi = pl[i];
         yr[2 * (1 + i) + 1] = gi;
         if (mode == FFT_FWD && bitmap) {
@@ -269,7 +287,7 @@ __global__ __launch_bounds__(rader_threads<T>()) void k_rader(
     }
     if (tid == 0) {
         double sr = 0.0, si = 0.0;
-        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) { sr += red[2 * w]; si += red[2 * w + 1]; }
+        for (int w = 0; w < NT / 64; ++w) { sr += red[2 * w]; si += red[2 * w + 1]; }
         V o;
         o.x = (T)(((double)f0.x + sr) * (double)sc);
         o.y = (T)(cj * ((double)f0.y + si) * (double)sc);
@@ -318,9 +336,9 @@ static std::vector<int> rader_radices(int64_t P)
 bool rader_applies(int64_t M, size_t real_bytes)
 {
     const int64_t P = M - 1;
-    const int64_t E = real_bytes == 8 ? rader_e<double>() : rader_e<float>();
-    const int64_t TH = real_bytes == 8 ? rader_threads<double>() : rader_threads<float>();
-    if (P < E || P % E || P / E > TH) return false;
+    bool listed = false;
+    for (int q : kRaderSizes) listed = listed || q == P;
+    if (!listed) return false;
     if ((int64_t)real_bytes * P + 2048 > kLdsBytes) return false;
     if (rader_radices(P).empty()) return false;
     return is_prime_host(M);
@@ -357,7 +375,7 @@ int rader_tables(int64_t M, RaderDesc &rd, std::vector<int32_t> &itab, std::vect
     const std::vector<int> rad = rader_radices(P);
     rd = RaderDesc{};
     rd.P = (int32_t)P;
-    rd.nthreads = (int32_t)(P / rader_e<T>());
+    rd.nthreads = (int32_t)(P / kRaderE);
     for (int r : rad) {
         if (r == 4) rd.n4++;
         else if (r == 2) rd.n2++;
@@ -395,37 +413,62 @@ int rader_tables(int64_t M, RaderDesc &rd, std::vector<int32_t> &itab, std::vect
 template int rader_tables<double>(int64_t, RaderDesc &, std::vector<int32_t> &, std::vector<double> &);
 template int rader_tables<float>(int64_t, RaderDesc &, std::vector<int32_t> &, std::vector<float> &);
 
-int rader_init_attrs()
+template <typename T, int P>
+static int rader_attr()
 {
-    MR1L_HIP(hipFuncSetAttribute((const void *)k_rader<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 kLdsBytes - 2048));
-    MR1L_HIP(hipFuncSetAttribute((const void *)k_rader<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 kLdsBytes - 2048));
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_rader<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 P * (int)sizeof(T)));
     return MR1L_OK;
 }
 
-int rader_launch(Plan &p, const int32_t *d_lats, int nl, const void *in, void *out, double theta,
+template <typename T, int... Ps>
+static int rader_attrs()
+{
+    int rc = MR1L_OK;
+    ((rc = rc ? rc : rader_attr<T, Ps>()), ...);
+    return rc;
+}
+
+int rader_init_attrs()
+{
+    int rc = rader_attrs<double, 40, 100, 400, 640, 1600, 4000, 16000>();
+    return rc ? rc : rader_attrs<float, 40, 100, 400, 640, 1600, 4000, 16000>();
+}
+
+template <typename T, int P>
+static int rader_go(Plan &p, const int32_t *d_lats, int nl, const void *in, void *out, T th2, uint32_t *bitmap,
+                    int mode, T scale, int by_m)
+{
+    using V = typename cvec<T>::type;
+    hipLaunchKernelGGL((k_rader<T, P>), dim3((unsigned)nl), dim3(RShape<P>::threads), (size_t)P * sizeof(T),
+                       p.stream, d_lats, p.d_lat, p.d_rdesc, p.d_ritab, (const V *)p.d_rctab, (const V *)in,
+                       (V *)out, bitmap, th2, mode, scale, by_m);
+    MR1L_LAUNCH_CHECK();
+    return MR1L_OK;
+}
+
+template <typename T>
+static int rader_dispatch(Plan &p, int P, const int32_t *d_lats, int nl, const void *in, void *out, T th2,
+                          uint32_t *bitmap, int mode, T scale, int by_m)
+{
+#define MR1L_RADER(Q) \
+    case Q: return rader_go<T, Q>(p, d_lats, nl, in, out, th2, bitmap, mode, scale, by_m);
+    switch (P) {
+        MR1L_RADER(40) MR1L_RADER(100) MR1L_RADER(400) MR1L_RADER(640) MR1L_RADER(1600) MR1L_RADER(4000)
+        MR1L_RADER(16000)
+    default: return fail(MR1L_E_ARG, "no Rader kernel for this lattice size");
+    }
+#undef MR1L_RADER
+}
+
+int rader_launch(Plan &p, int P, const int32_t *d_lats, int nl, const void *in, void *out, double theta,
                  uint32_t *bitmap, int mode, double scale, int by_m)
 {
     if (nl <= 0) return MR1L_OK;
     if (mode == FFT_SPEC) return MR1L_OK;   // the Rader spectra are built on the host
-    int Pmax = 0;
-    for (const RaderDesc &r : p.rdesc) Pmax = std::max(Pmax, r.P);
-    if (p.dtype == MR1L_C128) {
-        const int threads = std::max(64, ((Pmax / rader_e<double>()) + 63) / 64 * 64);
-        const size_t shm = (size_t)Pmax * sizeof(double);
-        hipLaunchKernelGGL(k_rader<double>, dim3((unsigned)nl), dim3(threads), shm, p.stream, d_lats, p.d_lat,
-                           p.d_rdesc, p.d_ritab, (const double2 *)p.d_rctab, (const double2 *)in, (double2 *)out,
-                           bitmap, theta * theta, mode, scale, by_m);
-    } else {
-        const int threads = std::max(64, ((Pmax / rader_e<float>()) + 63) / 64 * 64);
-        const size_t shm = (size_t)Pmax * sizeof(float);
-        hipLaunchKernelGGL(k_rader<float>, dim3((unsigned)nl), dim3(threads), shm, p.stream, d_lats, p.d_lat,
-                           p.d_rdesc, p.d_ritab, (const float2 *)p.d_rctab, (const float2 *)in, (float2 *)out,
-                           bitmap, (float)(theta * theta), mode, (float)scale, by_m);
-    }
-    MR1L_LAUNCH_CHECK();
-    return MR1L_OK;
+    if (p.dtype == MR1L_C128)
+        return rader_dispatch<double>(p, P, d_lats, nl, in, out, theta * theta, bitmap, mode, scale, by_m);
+    return rader_dispatch<float>(p, P, d_lats, nl, in, out, (float)(theta * theta), bitmap, mode, (float)scale, by_m);
 }
 
 }  // namespace mr1l

@@ -194,7 +194,7 @@ int bspline_sample_run(Plan &p, int32_t d_poly, int32_t n_prod, const int32_t *o
 bool rader_applies(int64_t M, size_t real_bytes);
 template <typename T> int rader_tables(int64_t M, RaderDesc &rd, std::vector<int32_t> &itab, std::vector<T> &ctab);
 int rader_init_attrs();
-int rader_launch(Plan &p, const int32_t *d_lats, int nl, const void *in, void *out, double theta,
+int rader_launch(Plan &p, int P, const int32_t *d_lats, int nl, const void *in, void *out, double theta,
                  uint32_t *bitmap, int mode, double scale, int by_m);
 int lsq_init_attrs();
 int lsq_run(Plan &p, int64_t cap, const int64_t *n_det, const int32_t *det_hash, const uint32_t *det_mask,

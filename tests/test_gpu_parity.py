@@ -245,7 +245,7 @@ def test_rader_schedule_forward_and_inverse(m, dtype):
     """Prime sizes with M - 1 = 2^a 5^b under the Rader schedule (with sizes of other
     schedules in the same plan): the forward DFT against the oracle, and the inverse
     DFT through the bucket sampler (eq. (2.4) then an inverse lattice DFT times M)."""
-    Ms = [41, 101, 641, 1601, 16001, 211, 4133]
+    Ms = [41, 101, 401, 641, 1601, 4001, 16001, 211, 4133]
     rng = np.random.default_rng(3)
     M = np.array(Ms, np.int64)
     z = rng.integers(1, 40, size=(len(Ms), 2)) % M[:, None]
