@@ -6,7 +6,7 @@
 // product with the precomputed DFT of b (1/P folded in), and a second length-P
 // DFT of the conjugate (an inverse DFT is conj(DFT(conj(.)))).  ghat[0] is the
 // mean of f.  One workgroup per lattice: each of the P/20 active threads holds
-// 20 values in registers through mixed-radix (4, 2, 5) Stockham passes; between
+// 20 values in registers through Stockham passes of radix 20 (4 x 5), 10, 5, 4 or 2; between
 // passes the values move through one LDS plane (P reals), real and imaginary
 // parts in turn.  Nothing goes through global scratch.
 #include <complex>
@@ -31,23 +31,45 @@ constexpr int rader_log(int P, int b)
     return n;
 }
 
-// The transform of length P: 20 values in each of P/20 threads, passes of radix 4
-// (a/2 of them), 2 (a mod 2) and 5 (b), in this order, for P = 2^a 5^b.
+// The transform of length P: 20 values in each of P/20 threads, through Stockham
+// passes whose radices divide 20: first the factors of P / 20^k that are left
+// (10, else fours, a five, a two), then k passes of radix 20, k as large as possible.
 template <int P> struct RShape {
     static constexpr int E = kRaderE;
     static constexpr int Tn = P / E;
     static constexpr int threads = (Tn + 63) / 64 * 64;
-    static constexpr int n4 = rader_log(P, 2) / 2, n2 = rader_log(P, 2) % 2, n5 = rader_log(P, 5);
-    static constexpr int NP = n4 + n2 + n5;
-    static constexpr int radix(int i) { return i < n4 ? 4 : (i < n4 + n2 ? 2 : 5); }
+    static constexpr int n20()
+    {
+        int k = 0, q = P;
+        while (q % 20 == 0) { q /= 20; ++k; }
+        return k;
+    }
+    static constexpr int rest() { int q = P; for (int k = 0; k < n20(); ++k) q /= 20; return q; }
+    static constexpr int small_radix(int q) { return q % 10 == 0 ? 10 : q % 4 == 0 ? 4 : q % 5 == 0 ? 5 : 2; }
+    static constexpr int nsmall()
+    {
+        int k = 0;
+        for (int q = rest(); q > 1; q /= small_radix(q)) ++k;
+        return k;
+    }
+    static constexpr int NP = nsmall() + n20();
+    static constexpr int radix(int i)
+    {
+        int q = rest();
+        for (int k = 0; k < nsmall(); ++k) {
+            if (k == i) return small_radix(q);
+            q /= small_radix(q);
+        }
+        return 20;
+    }
     static constexpr int sub(int i)   // sub-length before pass i
     {
         int L = 1;
         for (int k = 0; k < i; ++k) L *= radix(k);
         return L;
     }
-    static constexpr int Llast = sub(NP - 1);
-    static_assert(P % E == 0 && n4 >= 1 && n5 >= 1 && Tn <= 1024, "P = 20 2^i 5^j <= 20480");
+    static constexpr int R0 = radix(0), RL = radix(NP - 1), Llast = sub(NP - 1);
+    static_assert(P % E == 0 && sub(NP) == P && Tn <= 1024, "P = 20 2^i 5^j <= 20480");
 };
 
 // Hides a value from the optimiser so that per-pass index arithmetic is not hoisted
@@ -56,6 +78,59 @@ __device__ __forceinline__ int rader_opaque(int x)
 {
     asm volatile("" : "+v"(x));
     return x;
+}
+
+// cos and sin of 18 m degrees (W_20^m = cos - i sin), from the exact values of the
+// multiples of 18 degrees.
+template <typename T> __device__ __forceinline__ constexpr T cos18(int m)
+{
+    constexpr T c[6] = {(T)1, (T)0.95105651629515357211643933337938214, (T)0.80901699437494742410229341718281906,
+                        (T)0.58778525229247312916870595463907277, (T)0.30901699437494742410229341718281906, (T)0};
+    m = ((m % 20) + 20) % 20;
+    return m <= 5 ? c[m] : m <= 10 ? -c[10 - m] : m <= 15 ? -c[m - 10] : c[20 - m];
+}
+template <typename T> __device__ __forceinline__ constexpr T sin18(int m) { return cos18<T>(m - 5); }
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(T *xr, T *xi);
+
+// DFT of length R = R1 R2 (R2 = 5) by the index split n = R2 n1 + n2, k = k1 + R1 k2:
+// R2 DFTs of length R1, twiddles W_R^{n2 k1}, R1 DFTs of length R2.
+template <typename T, int R1, int R2>
+__device__ __forceinline__ void dft_composite(T *xr, T *xi)
+{
+    constexpr int R = R1 * R2;
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        T ar[R1], ai[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) { ar[n1] = xr[R2 * n1 + n2]; ai[n1] = xi[R2 * n1 + n2]; }
+        dft_small<T, R1>(ar, ai);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            const int m = n2 * k1 * (20 / R);
+            if (m) {
+                const T c = cos18<T>(m), s = sin18<T>(m);   // times c - i s
+                const T r = ar[k1] * c + ai[k1] * s;
+                ai[k1] = ai[k1] * c - ar[k1] * s;
+                ar[k1] = r;
+            }
+            xr[R2 * k1 + n2] = ar[k1];
+            xi[R2 * k1 + n2] = ai[k1];
+        }
+    }
+    T yr[R], yi[R];
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        T br[R2], bi[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) { br[n2] = xr[R2 * k1 + n2]; bi[n2] = xi[R2 * k1 + n2]; }
+        dft_small<T, R2>(br, bi);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) { yr[k1 + R1 * k2] = br[k2]; yi[k1 + R1 * k2] = bi[k2]; }
+    }
+#pragma unroll
+    for (int p = 0; p < R; ++p) { xr[p] = yr[p]; xi[p] = yi[p]; }
 }
 
 template <typename T, int R>
@@ -72,8 +147,7 @@ __device__ __forceinline__ void dft_small(T *xr, T *xi)
         xr[2] = s0r - s1r; xi[2] = s0i - s1i;
         xr[1] = d0r + d1i; xi[1] = d0i - d1r;   // d0 - i d1
         xr[3] = d0r - d1i; xi[3] = d0i + d1r;   // d0 + i d1
-    } else {
-        static_assert(R == 5, "radix 2, 4 or 5");
+    } else if constexpr (R == 5) {
         const T c1 = (T)0.30901699437494742410229341718281906, c2 = (T)-0.80901699437494742410229341718281906;
         const T s1 = (T)0.95105651629515357211643933337938214, s2 = (T)0.58778525229247312916870595463907277;
         const T t1r = xr[1] + xr[4], t1i = xi[1] + xi[4], t3r = xr[1] - xr[4], t3i = xi[1] - xi[4];
@@ -87,6 +161,11 @@ __device__ __forceinline__ void dft_small(T *xr, T *xi)
         xr[4] = a1r - b1i; xi[4] = a1i + b1r;   // a1 + i b1
         xr[2] = a2r + b2i; xi[2] = a2i - b2r;   // a2 - i b2
         xr[3] = a2r - b2i; xi[3] = a2i + b2r;   // a2 + i b2
+    } else if constexpr (R == 10) {
+        dft_composite<T, 2, 5>(xr, xi);
+    } else {
+        static_assert(R == 20, "radix 2, 4, 5, 10 or 20");
+        dft_composite<T, 4, 5>(xr, xi);
     }
 }
 
@@ -102,12 +181,17 @@ __device__ __forceinline__ void rader_pass(T (&xr)[kRaderE], T (&xi)[kRaderE], i
 #pragma unroll
     for (int c = 0; c < E / R; ++c) {
         if constexpr (L > 1) {   // the first pass has no twiddles
+            // W^m by products with W^1, restarted from the table at m = 5, 10, 15
             const int k = (tid + Tn * c) % L;
             const V w1 = tw[k * step];
             T wr = w1.x, wi = w1.y;
 #pragma unroll
             for (int m = 1; m < R; ++m) {
-                if (m > 1) {
+                if (m % 5 == 0) {
+                    const V wm = tw[k * step * m];
+                    wr = wm.x;
+                    wi = wm.y;
+                } else if (m > 1) {
                     const T nr = wr * w1.x - wi * w1.y;
                     wi = wr * w1.y + wi * w1.x;
                     wr = nr;
@@ -166,7 +250,7 @@ __device__ __forceinline__ void exchange(T *pl, T (&xr)[kRaderE], T (&xi)[kRader
 }
 
 // Passes I, I + 1, ... of a length-P DFT (forward sign), the values in the input
-// layout of pass I; the outputs end in the layout of the last (radix-5) pass.
+// layout of pass I; the outputs end in the layout of the last pass.
 template <typename T, int P, int I>
 __device__ __forceinline__ void dft_passes(T *pl, T (&xr)[kRaderE], T (&xi)[kRaderE], bool act, int t, int tid,
                                            const typename cvec<T>::type *__restrict__ tw)
@@ -190,7 +274,7 @@ __global__ __launch_bounds__(RShape<P>::threads) void k_rader(
 {
     using V = typename cvec<T>::type;
     using S = RShape<P>;
-    constexpr int E = kRaderE, Tn = S::Tn, NT = S::threads, Ll = S::Llast;
+    constexpr int E = kRaderE, Tn = S::Tn, NT = S::threads, Ll = S::Llast, RL = S::RL;
     extern __shared__ __align__(16) unsigned char smem[];
     T *pl = reinterpret_cast<T *>(smem);
     __shared__ double red[2 * (NT / 64)];
@@ -209,13 +293,13 @@ __global__ __launch_bounds__(RShape<P>::threads) void k_rader(
     T xr[E], xi[E];
 
     // a[q] = f[g^q]: f[1..M) through the plane in natural order, gathered in the
-    // input order of the first (radix-4) pass
+    // input order of the first pass
     for (int i = tid; i < P; i += NT) pl[i] = x[1 + i].x;
     __syncthreads();
     int gidx[E];
-    // first-pass input index of register e = 4 c + m: q = t + Tn c + m P / 4
+    // first-pass input index of register e = R0 c + m: q = t + Tn c + m P / R0
 #pragma unroll
-    for (int e = 0; e < E; ++e) gidx[e] = pin[t + Tn * (e / 4) + (e % 4) * (P / 4)] - 1;
+    for (int e = 0; e < E; ++e) gidx[e] = pin[t + Tn * (e / S::R0) + (e % S::R0) * (P / S::R0)] - 1;
 #pragma unroll
     for (int e = 0; e < E; ++e) xr[e] = pl[gidx[e]];
     __syncthreads();
@@ -247,14 +331,14 @@ __global__ __launch_bounds__(RShape<P>::threads) void k_rader(
         const int tt = rader_opaque(t);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const V s = sp[out_pos<P, 5, Ll>(tt, e / 5, e % 5)];
+            const V s = sp[out_pos<P, RL, Ll>(tt, e / RL, e % RL)];
             const T ar = xr[e], ai = xi[e];
             xr[e] = ar * s.x - ai * s.y;
             xi[e] = -(ar * s.y + ai * s.x);
         }
     }
     // inverse length-P DFT (conjugated input): the convolution, conjugated
-    exchange<T, P, 5, Ll, 4>(pl, xr, xi, act, tid);
+    exchange<T, P, RL, Ll, S::R0>(pl, xr, xi, act, tid);
     dft_passes<T, P, 0>(pl, xr, xi, act, t, tid, tw);
     // ghat[g^-p] = (f[0] + conv[p]) / M at natural index g^-p - 1 of the plane; the
     // real parts go out first (8-byte stores), then the imaginary parts
@@ -262,7 +346,7 @@ __global__ __launch_bounds__(RShape<P>::threads) void k_rader(
     {
         const int tt = rader_opaque(t);
 #pragma unroll
-        for (int e = 0; e < E; ++e) gidx[e] = pout[out_pos<P, 5, Ll>(tt, e / 5, e % 5)] - 1;
+        for (int e = 0; e < E; ++e) gidx[e] = pout[out_pos<P, RL, Ll>(tt, e / RL, e % RL)] - 1;
     }
     V *y = out + ld.node_off;
     T *yr = reinterpret_cast<T *>(y);
