@@ -436,6 +436,7 @@ int mr1l::plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, cons
         if (!attrs_rc) attrs_rc = vote_init_attrs();
         if (!attrs_rc) attrs_rc = lsq_init_attrs();
         if (!attrs_rc) attrs_rc = rader_init_attrs();
+        if (!attrs_rc) attrs_rc = sample_init_attrs();
         if (attrs_rc) attrs_err = g_err;
     });
     if (attrs_rc) return fail(attrs_rc, "kernel attribute setup failed: " + attrs_err);

@@ -8,8 +8,10 @@
 //   direct  one thread per node sums all terms of its function; the phase
 //           e^{2 pi i r / M} comes from a two-level table (r = hi S + lo) in LDS.
 //   bucket  the aliasing formula eq. (2.4): coefficients are summed into the
-//           buckets h_l(k) (atomics), then f_l[j] = sum_h B[h] e^{2 pi i j h / M}
-//           is an inverse lattice DFT (scaled by M).
+//           buckets h_l(k) (in LDS per lattice, component and chunk of terms when
+//           one lattice's buckets fit, else by global atomics), then
+//           f_l[j] = sum_h B[h] e^{2 pi i j h / M} is an inverse lattice DFT
+//           (scaled by M).
 #include "mr1l_internal.h"
 
 namespace mr1l {
@@ -25,7 +27,12 @@ __device__ __forceinline__ int func_of_terms(const int64_t *off, int F, int64_t 
 }
 
 // Per term: anchored coefficient and buckets in all lattices of its function.
-template <typename T>
+// PLANAR writes the coefficients as a real plane followed by an imaginary plane
+// (for the LDS bucket accumulation), else interleaved.  When all lanes of a wave
+// hold terms of one function (the usual case), its lattice records and generating
+// vectors are wave-uniform and come through scalar loads.  DM bounds d at compile
+// time so that the coordinates stay in registers (DM = 16 covers d <= 16).
+template <typename T, bool PLANAR, int DM>
 __global__ __launch_bounds__(256) void k_term_prep(
     const int64_t *__restrict__ freq, int64_t n_terms, const int64_t *__restrict__ term_off, int F, int L, int d,
     int d_poly, const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32, const int64_t *__restrict__ z64,
@@ -46,27 +53,43 @@ __global__ __launch_bounds__(256) void k_term_prep(
             c.x = (T)(cr * cs - ci * sn);
             c.y = (T)(cr * sn + ci * cs);
         }
-        cterm[t] = c;
+        if constexpr (PLANAR) {
+            T *pl = reinterpret_cast<T *>(cterm);
+            pl[t] = c.x;
+            pl[n_terms + t] = c.y;
+        } else {
+            cterm[t] = c;
+        }
         const int32_t kb = kbound[f];
-        int32_t lo[kMaxD];
+        int32_t lo[DM];
         bool fast = true;
-        for (int u = 0; u < d; ++u) {
-            const int64_t k = freq[(int64_t)u * n_terms + t];
-            lo[u] = (int32_t)k;
-            fast = fast && (k >= -kb) && (k <= kb);
-        }
-        for (int l = 0; l < L; ++l) {
-            const LatDesc ld = lat[f * L + l];
-            int32_t h;
-            if (fast) {
-                uint32_t s = ld.off32;
-                for (int u = 0; u < d; ++u) s += (uint32_t)__mul24(lo[u], z32[ld.z_off + u]);
-                h = (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m);
-            } else {
-                h = exact_bucket(freq + t, n_terms, d, z64 + ld.z_off, ld.M);
+#pragma unroll
+        for (int u = 0; u < DM; ++u) {
+            if (u < d) {
+                const int64_t k = freq[(int64_t)u * n_terms + t];
+                lo[u] = (int32_t)k;
+                fast = fast & (k >= -kb) & (k <= kb);
             }
-            thash[(int64_t)l * n_terms + t] = h;
         }
+        auto hash_all = [&](int ff) {
+            for (int l = 0; l < L; ++l) {
+                const LatDesc ld = lat[ff * L + l];
+                int32_t h;
+                if (fast) {
+                    uint32_t s = ld.off32;
+#pragma unroll
+                    for (int u = 0; u < DM; ++u)
+                        if (u < d) s += (uint32_t)__mul24(lo[u], z32[ld.z_off + u]);
+                    h = (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m);
+                } else {
+                    h = exact_bucket(freq + t, n_terms, d, z64 + ld.z_off, ld.M);
+                }
+                thash[(int64_t)l * n_terms + t] = h;
+            }
+        };
+        const int fu = __builtin_amdgcn_readfirstlane(f);
+        if (__all(f == fu)) hash_all(fu);
+        else hash_all(f);
     }
 }
 
@@ -150,6 +173,64 @@ __global__ __launch_bounds__(256) void k_sample_scatter(
     }
 }
 
+// Bucket sums of one lattice and one component (real or imaginary) in LDS: a
+// workgroup takes one chunk of its function's terms (planar coefficients), adds
+// them into an LDS copy of the M_l buckets, then adds the copy into the global
+// buckets.  Global atomics drop from two per term and lattice to one per bucket
+// and chunk.
+constexpr int kLdsScatterThreads = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kLdsScatterThreads) void k_sample_lds(
+    const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ term_off, int64_t n_terms, int chunks,
+    const T *__restrict__ cplane, const int32_t *__restrict__ thash, T *__restrict__ buckets)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *acc = reinterpret_cast<T *>(smem);
+    const int comp = blockIdx.y & 1;
+    const int li = blockIdx.y >> 1;
+    const int f = li / L, l = li - f * L;
+    const LatDesc ld = lat[li];
+    const int M = ld.M;
+    for (int i = threadIdx.x; i < M; i += blockDim.x) acc[i] = T(0);
+    __syncthreads();
+    const int64_t t0 = term_off[f], t1 = term_off[f + 1];
+    const int64_t per = (t1 - t0 + chunks - 1) / chunks;
+    const int64_t b = min(t1, t0 + (int64_t)blockIdx.x * per), e = min(t1, b + per);
+    const T *cv = cplane + (int64_t)comp * n_terms;
+    const int32_t *hh = thash + (int64_t)l * n_terms;
+    constexpr int U = 4;   // loads in flight per thread
+    int64_t t = b + threadIdx.x;
+    for (; t + (U - 1) * (int64_t)kLdsScatterThreads < e; t += U * (int64_t)kLdsScatterThreads) {
+        int32_t h[U];
+        T v[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            h[q] = __builtin_nontemporal_load(hh + t + q * kLdsScatterThreads);
+            v[q] = __builtin_nontemporal_load(cv + t + q * kLdsScatterThreads);
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) unsafeAtomicAdd(acc + h[q], v[q]);
+    }
+    for (; t < e; t += kLdsScatterThreads) unsafeAtomicAdd(acc + hh[t], cv[t]);
+    __syncthreads();
+    if (b >= e) return;
+    T *out = buckets + 2 * ld.node_off + comp;
+    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+        const T v = acc[i];
+        if (v != T(0)) unsafeAtomicAdd(out + 2 * (int64_t)i, v);
+    }
+}
+
+int sample_init_attrs()
+{
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_sample_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes));
+    MR1L_HIP(hipFuncSetAttribute((const void *)k_sample_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes));
+    return MR1L_OK;
+}
+
 template <typename T>
 static int sample_impl(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms, const int64_t *freq,
                        const void *coef, const uint32_t *anchor, void *f, int32_t mode, void *cterm,
@@ -157,15 +238,30 @@ static int sample_impl(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t
 {
     using V = typename cvec<T>::type;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n_terms + 255) / 256, (int64_t)num_cus() * 16));
+    int32_t maxM = 0;
+    for (auto m : p.M) maxM = std::max<int32_t>(maxM, (int32_t)m);
+    // bucket sums in LDS when one lattice's buckets (one component) fit and the
+    // functions have many terms per bucket chunk
+    const int units = p.F * p.L * 2;
+    const int64_t per_f = n_terms / std::max(1, p.F);
+    const bool lds = mode == 2 && units <= 65535 && (int64_t)maxM * (int64_t)sizeof(T) <= kLdsBytes &&
+                     per_f >= 8 * (int64_t)maxM;
     if (n_terms > 0) {
-        hipLaunchKernelGGL(k_term_prep<T>, dim3((unsigned)blocks), dim3(256), 0, p.stream, freq, n_terms, term_off,
-                           p.F, p.L, p.d, d_poly, p.d_lat, p.d_z32, p.d_z64, p.d_kb, (const V *)coef, anchor,
-                           (V *)cterm, thash);
+#define MR1L_PREP(PL, DM)                                                                                        \
+    hipLaunchKernelGGL((k_term_prep<T, PL, DM>), dim3((unsigned)blocks), dim3(256), 0, p.stream, freq, n_terms, \
+                       term_off, p.F, p.L, p.d, d_poly, p.d_lat, p.d_z32, p.d_z64, p.d_kb, (const V *)coef, anchor, \
+                       (V *)cterm, thash)
+        if (lds) {
+            if (p.d <= 16) MR1L_PREP(true, 16);
+            else MR1L_PREP(true, kMaxD);
+        } else {
+            if (p.d <= 16) MR1L_PREP(false, 16);
+            else MR1L_PREP(false, kMaxD);
+        }
+#undef MR1L_PREP
         MR1L_LAUNCH_CHECK();
     }
     if (mode == 1) {
-        int32_t maxM = 0;
-        for (auto m : p.M) maxM = std::max<int32_t>(maxM, (int32_t)m);
         dim3 grid((unsigned)((maxM + 255) / 256), (unsigned)(p.F * p.L));
         hipLaunchKernelGGL(k_sample_direct<T>, grid, dim3(256), 0, p.stream, p.d_lat, p.L, term_off, n_terms,
                            (const V *)cterm, thash, (V *)f);
@@ -174,7 +270,16 @@ static int sample_impl(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t
     }
     int rc = launch_fill_bytes(p.d_nodes_scratch, p.nodes * (int64_t)sizeof(V), p.stream);
     if (rc) return rc;
-    if (n_terms > 0) {
+    if (n_terms > 0 && lds) {
+        // chunks per (lattice, component): one round of workgroups over the CUs,
+        // at least 2 M terms per chunk
+        const int64_t by_cus = std::max<int64_t>(1, num_cus() / std::max(1, units));
+        const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(by_cus, per_f / (2 * (int64_t)maxM)));
+        hipLaunchKernelGGL(k_sample_lds<T>, dim3((unsigned)chunks, (unsigned)units), dim3(kLdsScatterThreads),
+                           (size_t)maxM * sizeof(T), p.stream, p.d_lat, p.L, term_off, n_terms, chunks,
+                           (const T *)cterm, thash, (T *)p.d_nodes_scratch);
+        MR1L_LAUNCH_CHECK();
+    } else if (n_terms > 0) {
         hipLaunchKernelGGL(k_sample_scatter<T>, dim3((unsigned)blocks), dim3(256), 0, p.stream, p.d_lat, p.L,
                            term_off, p.F, n_terms, (const V *)cterm, thash, (T *)p.d_nodes_scratch);
         MR1L_LAUNCH_CHECK();
@@ -193,7 +298,8 @@ static int ensure(void **ptr, int64_t *have, int64_t want)
     return MR1L_OK;
 }
 
-// plan-owned term scratch (grown outside graph capture only)
+// term scratch shared by the plans used from one host thread (grown outside graph
+// capture only)
 static thread_local void *g_cterm = nullptr;
 static thread_local int64_t g_cterm_n = 0;
 static thread_local void *g_thash = nullptr;

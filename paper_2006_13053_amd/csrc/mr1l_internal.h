@@ -215,6 +215,7 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
                      const void *ghat, const mr1l_extract_opts &o, const mr1l_extract_out &out,
                      int32_t *det_hash, double *det_w, uint32_t *det_mask, void *det_med,
                      int32_t *out_pos);
+int sample_init_attrs();
 int sample_run(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms,
                const int64_t *freq, const void *coef, const uint32_t *anchor, void *f,
                int32_t mode);

@@ -313,6 +313,57 @@ def test_inverse_dft_via_sampler_bucket_mode(m):
     close(fb.cpu().numpy(), fo, 1e-11, "bucket-mode samples")
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("anchored", [False, True])
+def test_sample_bucket_mode_lds_sums(m, dtype, anchored):
+    """Bucket-mode sampling of functions with many terms per bucket (the buckets of a
+    lattice summed in LDS per chunk of terms): three functions of uneven length, against
+    the oracle's direct evaluation of eq. (2.2)."""
+    say("sample bucket mode lds", dtype, anchored)
+    rng = np.random.default_rng(21 + anchored)
+    d_poly, t, F, L = 5, (3 if anchored else 5), 3, 4
+    counts = [5000, 12000, 700]
+    freqs = [rng.integers(-60, 61, size=(d_poly, n), dtype=np.int64) for n in counts]
+    coefs = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in counts]
+    Ms, zs = [], []
+    for f in range(F):
+        M, z = synth.draw_lattices(rng, L, t, 150, 400)
+        Ms.append(M)
+        zs.append(z)
+    anc = rng.integers(0, 2**32, size=(F, d_poly - t), dtype=np.uint64).astype(np.uint32)
+    plan = m.Plan(t, np.concatenate(Ms), np.concatenate(zs), F=F, dtype=dtype)
+    toff = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    kw = dict(anchor=T(anc.reshape(-1).view(np.int32))) if anchored else {}
+    got = m.mr1l_sample(plan, T(np.concatenate(freqs, axis=1)), T(np.concatenate(coefs)).to(dtype),
+                        term_off=T(toff), mode=2, **kw)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.complex128)
+    off = 0
+    for f in range(F):
+        want = oracle.sample(freqs[f], coefs[f], Ms[f], zs[f], anchor=anc[f] if anchored else None,
+                             t=t if anchored else None)
+        n = int(Ms[f].sum())
+        err = np.abs(got[off:off + n] - want).max() / np.abs(want).max()
+        assert err <= TOL[dtype], (f, err)
+        off += n
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_sample_more_than_16_dimensions(m, mode):
+    """Lattices of dimension 20 (beyond the register-held coordinate path of the term
+    preparation), direct and bucket modes, against the oracle."""
+    say("sample d=20", mode)
+    rng = np.random.default_rng(31)
+    d, n = 20, 3000
+    freq = rng.integers(-40, 41, size=(d, n), dtype=np.int64)
+    coef = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    M, z = synth.draw_lattices(rng, 3, d, 200, 300)
+    plan = m.Plan(d, M, z)
+    got = m.mr1l_sample(plan, T(freq), T(coef), mode=mode)
+    torch.cuda.synchronize()
+    close(got.cpu().numpy(), oracle.sample(freq, coef, M, z), 1e-11, f"d=20 mode {mode}")
+
+
 def test_sample_with_anchors(m):
     say("sample anchors")
     rng = np.random.default_rng(8)
