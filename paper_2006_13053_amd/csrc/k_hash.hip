@@ -74,8 +74,9 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
     const uint32_t *__restrict__ bitmap, int vote_min, int64_t cap,
     int64_t *__restrict__ det_cnt, int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes)
 {
+    // D > 0: exactly D coordinates; D < 0: runtime d <= -D; D == 0: runtime d <= kMaxD
     const int d = D > 0 ? D : d_rt;
-    constexpr int DM = D > 0 ? D : kMaxD;
+    constexpr int DM = D > 0 ? D : (D < 0 ? -D : kMaxD);
     constexpr int ZW = DOT2 ? (DM + 1) / 2 : DM;   // z words of a record
     const int zw = DOT2 ? (d + 1) / 2 : d;
     extern __shared__ __align__(16) uint32_t lds[];
@@ -265,7 +266,7 @@ int vote_init_attrs()
     MR1L_VOTE_ATTR(0) MR1L_VOTE_ATTR(1) MR1L_VOTE_ATTR(2) MR1L_VOTE_ATTR(3) MR1L_VOTE_ATTR(4)
     MR1L_VOTE_ATTR(5) MR1L_VOTE_ATTR(6) MR1L_VOTE_ATTR(7) MR1L_VOTE_ATTR(8) MR1L_VOTE_ATTR(9)
     MR1L_VOTE_ATTR(10) MR1L_VOTE_ATTR(12) MR1L_VOTE_ATTR(16) MR1L_VOTE_ATTR(20) MR1L_VOTE_ATTR(25)
-    MR1L_VOTE_ATTR(30)
+    MR1L_VOTE_ATTR(30) MR1L_VOTE_ATTR(-16) MR1L_VOTE_ATTR(-32)
 #undef MR1L_VOTE_ATTR
     return MR1L_OK;
 }
@@ -311,7 +312,13 @@ int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *fr
         MR1L_VOTE_DISPATCH(25)
         MR1L_VOTE_DISPATCH(30)
     default:
-        MR1L_VOTE_DISPATCH(0)
+        // other dimensions: the coordinate registers sized for d <= 16, d <= 32 or any d
+        switch (p.d <= 16 ? -16 : p.d <= 32 ? -32 : 0) {
+            MR1L_VOTE_DISPATCH(-16)
+            MR1L_VOTE_DISPATCH(-32)
+        default:
+            MR1L_VOTE_DISPATCH(0)
+        }
     }
     MR1L_LAUNCH_CHECK();
     return MR1L_OK;
@@ -320,6 +327,7 @@ int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *fr
 // ------------------------------------------------------------------ hash + count
 // hash[l * n_total + i] and counts[O_{f,l} + h] over a candidate set; counts is
 // zero-filled first and accumulated with global atomics (order-independent).
+template <int DM>   // d <= DM: the coordinates stay in registers
 __global__ __launch_bounds__(256) void k_hash_count(
     const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int F, int L,
     int d, const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32, const int64_t *__restrict__ z64,
@@ -329,19 +337,24 @@ __global__ __launch_bounds__(256) void k_hash_count(
          i += (int64_t)gridDim.x * blockDim.x) {
         const int f = func_of(set_off, F, i);
         const int32_t kb = kbound[f];
-        int32_t lo[kMaxD];
+        int32_t lo[DM];
         bool fast = true;
-        for (int u = 0; u < d; ++u) {
-            const int64_t k = freq[(int64_t)u * n_total + i];
-            lo[u] = (int32_t)k;
-            fast = fast && (k >= -kb) && (k <= kb);
+#pragma unroll
+        for (int u = 0; u < DM; ++u) {
+            if (u < d) {
+                const int64_t k = freq[(int64_t)u * n_total + i];
+                lo[u] = (int32_t)k;
+                fast = fast & (k >= -kb) & (k <= kb);
+            }
         }
         for (int l = 0; l < L; ++l) {
             const LatDesc ld = lat[f * L + l];
             int32_t h;
             if (fast) {
                 uint32_t s = ld.off32;
-                for (int u = 0; u < d; ++u) s += (uint32_t)__mul24(lo[u], z32[ld.z_off + u]);
+#pragma unroll
+                for (int u = 0; u < DM; ++u)
+                    if (u < d) s += (uint32_t)__mul24(lo[u], z32[ld.z_off + u]);
                 h = (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m);
             } else {
                 h = exact_bucket(freq + i, n_total, d, z64 + ld.z_off, ld.M);
@@ -361,8 +374,13 @@ int hash_count_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64
     }
     if (n_total <= 0) return MR1L_OK;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n_total + 255) / 256, (int64_t)num_cus() * 16));
-    hipLaunchKernelGGL(k_hash_count, dim3((unsigned)blocks), dim3(256), 0, p.stream, freq, n_total, set_off,
-                       p.F, p.L, p.d, p.d_lat, p.d_z32, p.d_z64, p.d_kb, hash, counts);
+#define MR1L_HC(DM)                                                                                          \
+    hipLaunchKernelGGL(k_hash_count<DM>, dim3((unsigned)blocks), dim3(256), 0, p.stream, freq, n_total, set_off, \
+                       p.F, p.L, p.d, p.d_lat, p.d_z32, p.d_z64, p.d_kb, hash, counts)
+    if (p.d <= 16) MR1L_HC(16);
+    else if (p.d <= 32) MR1L_HC(32);
+    else MR1L_HC(kMaxD);
+#undef MR1L_HC
     MR1L_LAUNCH_CHECK();
     return MR1L_OK;
 }

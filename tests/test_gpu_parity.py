@@ -104,6 +104,9 @@ def check_limit(r, ro, eps, tol):
     (25, 5000, 32, 7, 4133, 4133),
     (3, 3000, 2**40, 6, 10000, 16000),      # beyond the 24-bit bound: exact 64-bit path
     (10, 4000, 512, 20, 16001, 16001),
+    (13, 3000, 40, 6, 500, 900),            # dimensions without a kernel of their own:
+    (23, 3000, 20, 6, 2000, 3000),          # coordinate registers for d <= 16, <= 32
+    (40, 2000, 10, 5, 3000, 4000),          # and any d
 ])
 def test_hash_count_bit_exact(m, d, n, box, L, mlo, mhi):
     say("hash_count", d, n, box, L)
@@ -486,6 +489,18 @@ def test_mid_config_full_pass_with_noise(m, seed):
     compare_pass(r, ro, go, p.theta, 1e-11, 200)
     # the support is found and its coefficients are within the noise of the truth
     assert set(p.supp_idx.tolist()) <= set(r["out_idx"].tolist())
+
+
+@pytest.mark.parametrize("d", [13, 23, 40])
+def test_full_pass_dimensions_without_own_kernel(m, d):
+    """The vote kernel for dimensions that have no instance of their own (registers
+    sized for d <= 16, d <= 32 and any d): full pass against the oracle."""
+    say("full pass d", d)
+    p = synth.small_config(40 + d, d=d, n=3000, box=12, L=7, mlo=300, mhi=600)
+    r, *_ = gpu_pass(m, p, s_cap=40, cap=2000)
+    go = oracle.dft(oracle.sample(p.supp, p.coef, p.M, p.z), p.M)
+    ro = oracle.extract(p.cand, p.M, p.z, go, p.theta, s_cap=40, cap=2000)
+    compare_pass(r, ro, go, p.theta, 1e-11, 40)
 
 
 def test_vote_min_general_nu(m):
