@@ -358,12 +358,6 @@ __device__ __forceinline__ typename cvec<T>::type chirp(TAB tab, int shift, int 
     return o;
 }
 
-template <typename T>
-__device__ __forceinline__ void set_bit_if(uint32_t *bitmap, int64_t g, T re, T im, T th2)
-{
-    if (re * re + im * im >= th2) atomicOr(bitmap + (g >> 5), 1u << (g & 31));
-}
-
 // ------------------------------------------------------------------ LDS kernel
 // One workgroup of NT threads per lattice with N <= NMAXT, the whole transform in
 // the workgroup's LDS (2 NMAXT elements).  mode: FFT_FWD (f -> ghat, bitmap),
@@ -466,7 +460,7 @@ __global__ __launch_bounds__(NT) void k_bluestein_lds(
         if (mode == FFT_INV) gi = -gi;
         V o; o.x = gr; o.y = gi;
         y[i] = o;
-        if (mode == FFT_FWD && bitmap) set_bit_if<T>(bitmap, ld.node_off + i, gr, gi, th2);
+        if (mode == FFT_FWD && bitmap) bitmap_set_run(bitmap, ld.node_off + i, gr * gr + gi * gi >= th2);
     }
 }
 
@@ -717,6 +711,7 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
             for (int e = opaque(tid); e < tot; e += NT) {
                 const int b = e & (B2 - 1), a = e >> logB2;   // output n = N2 a + (c0 + b)
                 const int h = (a << logN2) + c0 + b;
+                bool set = false;
                 if (h < M) {
                     const int q = padr((b << logN1) + a, lrA);
                     const T cr = re[q], ci = -im[q];
@@ -726,8 +721,10 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
                     if (mode == FFT_INV) gi = -gi;
                     V o; o.x = gr; o.y = gi;
                     out[ld.node_off + h] = o;
-                    if (mode == FFT_FWD && bitmap) set_bit_if<T>(bitmap, ld.node_off + h, gr, gi, th2);
+                    set = gr * gr + gi * gi >= th2;
                 }
+                // every lane of the loop takes part (runs of consecutive h per wave)
+                if (mode == FFT_FWD && bitmap) bitmap_set_lanes(bitmap, ld.node_off + h, set);
             }
             __syncthreads();
         }

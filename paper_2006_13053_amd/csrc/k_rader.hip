@@ -365,8 +365,7 @@ __global__ __launch_bounds__(RShape<P>::threads) void k_rader(
         yr[2 * (1 + i) + 1] = gi;
         if (mode == FFT_FWD && bitmap) {
             const T gr = yr[2 * (1 + i)];   // written by this thread above
-            if (gr * gr + gi * gi >= th2)
-                atomicOr(bitmap + ((ld.node_off + 1 + i) >> 5), 1u << ((ld.node_off + 1 + i) & 31));
+            bitmap_set_run(bitmap, ld.node_off + 1 + i, gr * gr + gi * gi >= th2);
         }
     }
     if (tid == 0) {

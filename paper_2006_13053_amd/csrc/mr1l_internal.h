@@ -16,6 +16,42 @@ namespace mr1l {
 // detected lists longer than kMaxCap are sorted in global memory (one stream synchronisation)
 constexpr int64_t kMaxCapLarge = int64_t(1) << 24;
 
+// Non-zero bitmap bits of a wave whose active lanes are a prefix of the wave holding
+// consecutive nodes (lane j: node g of lane 0 plus j, as in a loop i = tid, tid + NT, ...
+// with NT a multiple of 64): the bits are gathered by a ballot and each 32-bit word the
+// wave touches gets one atomicOr, from the lane that starts it.
+__device__ __forceinline__ void bitmap_set_run(uint32_t *bitmap, int64_t g, bool set)
+{
+    const uint64_t b = __ballot(set);
+    if (b == 0) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int bit = (int)(g & 31);
+    if (lane == 0 || bit == 0) {
+        const int len = min(64 - lane, 32 - bit);   // lanes in this word, at most 32
+        const uint64_t seg = (b >> lane) & ((uint64_t(1) << len) - 1);
+        if (seg) atomicOr(bitmap + (g >> 5), (uint32_t)(seg << bit));
+    }
+}
+
+// The same for any node order, as long as the active lanes are a prefix of the wave:
+// lanes whose node follows the previous lane's node within one 32-bit word join that
+// lane's run, and each run's first lane sets the run's bits with one atomicOr.
+__device__ __forceinline__ void bitmap_set_lanes(uint32_t *bitmap, int64_t g, bool set)
+{
+    const uint64_t b = __ballot(set);
+    if (b == 0) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t gp = __shfl_up(g, 1);
+    const bool cont = lane > 0 && gp + 1 == g && (g & 31) != 0;
+    const uint64_t c = __ballot(cont);
+    if (!cont) {
+        const uint64_t next = lane == 63 ? 0 : (c >> (lane + 1));   // continuation flags after this lane
+        const int len = 1 + __builtin_ctzll(~next);                 // at most 32: runs stop at word ends
+        const uint64_t seg = (b >> lane) & ((uint64_t(1) << len) - 1);
+        if (seg) atomicOr(bitmap + (g >> 5), (uint32_t)(seg << (g & 31)));
+    }
+}
+
 // ---------------------------------------------------------------- DFT schedules
 // How the Bluestein transform of one lattice runs.  Schedule 0 holds the whole
 // 5-smooth-length transform in one workgroup's LDS; the others are power-of-two

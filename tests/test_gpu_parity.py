@@ -196,6 +196,16 @@ def _fft_check(m, plan, f, dtype, rng):
         err = np.abs(g[off + bins] - go).max() / np.abs(go).max()
         assert err <= TOL[dtype], f"M={mm} err {err:.2e}"
         off += mm
+    # the non-zero bitmap, dense for the small sizes and about half full for the largest
+    # (|ghat|^2 has mean 2/M here), against the threshold test on the returned values
+    # taken in the kernel's precision
+    th = float(np.sqrt(2.0 / max(int(mm) for mm in plan.M)))
+    g2, bm = m.mr1l_fft(plan, T(f.astype(np.complex128)).to(dtype), theta=th)
+    torch.cuda.synchronize()
+    gv = g2.cpu().numpy()
+    rt = np.float64 if dtype == torch.complex128 else np.float32
+    want = gv.real.astype(rt) * gv.real.astype(rt) + gv.imag.astype(rt) * gv.imag.astype(rt) >= rt(th * th)
+    assert np.array_equal(unpack_bits(bm.cpu().numpy(), plan.nodes), want)
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
