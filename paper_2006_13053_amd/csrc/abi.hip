@@ -328,7 +328,8 @@ static void release(Plan *p)
     void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_vrec, p->d_spec, p->d_chirp, p->d_tw,
                     p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
                     p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
-                    p->d_termoff_default, p->d_ls, p->d_gsort, p->d_bs_dims, p->d_rdesc, p->d_ritab, p->d_rctab};
+                    p->d_termoff_default, p->d_ls, p->d_gsort, p->d_single, p->d_dflag, p->d_bs_dims, p->d_rdesc,
+                    p->d_ritab, p->d_rctab};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (FftGroup &g : p->fft_groups)

@@ -139,6 +139,78 @@ __global__ __launch_bounds__(256) void k_singleton(const LatDesc *__restrict__ l
     }
 }
 
+// Long detected lists (global bitmaps once / twice per lattice, zeroed first):
+// workgroup (chunk, l, f) counts its chunk of the detected set in LDS bitmaps as
+// above, then merges them word by word.  A bucket ends in `twice` when one chunk
+// saw it twice, or when it was already in `once` from another chunk.
+constexpr int kSingleThreads = 1024;
+
+__global__ __launch_bounds__(kSingleThreads) void k_single_count(
+    const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ n_det, int64_t cap,
+    const int32_t *__restrict__ det_hash, int chunks, int64_t wl, uint32_t *__restrict__ g_once,
+    uint32_t *__restrict__ g_twice, int words)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *once = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *twice = once + words;
+    const int l = blockIdx.y, f = blockIdx.z;
+    const int64_t n = n_of(n_det, f, cap);
+    const int64_t per = (n + chunks - 1) / chunks;
+    const int64_t q0 = (int64_t)blockIdx.x * per, q1 = min(n, q0 + per);
+    if (q0 >= q1) return;
+    const int M = lat[f * L + l].M;
+    const int32_t *hh = det_hash + (int64_t)f * cap * L;
+    uint32_t *go = g_once + ((int64_t)f * L + l) * wl;
+    uint32_t *gt = g_twice + ((int64_t)f * L + l) * wl;
+    const int span = words * 32;
+    for (int c0 = 0; c0 < M; c0 += span) {
+        const int c1 = min(M, c0 + span);
+        const int nw = (c1 - c0 + 31) >> 5;
+        for (int i = threadIdx.x; i < nw; i += blockDim.x) { once[i] = 0u; twice[i] = 0u; }
+        __syncthreads();
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+            const int h = hh[q * L + l];
+            if (h >= c0 && h < c1) {
+                const int r = h - c0;
+                const uint32_t bit = 1u << (r & 31);
+                if (atomicOr(once + (r >> 5), bit) & bit) atomicOr(twice + (r >> 5), bit);
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+            const uint32_t o = once[i];
+            if (o) {
+                const uint32_t prev = atomicOr(go + (c0 >> 5) + i, o);
+                const uint32_t t = twice[i] | (prev & o);
+                if (t) atomicOr(gt + (c0 >> 5) + i, t);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One thread per detected candidate: its singleton mask over all lattices from the
+// merged `twice` bitmaps, written whole (no atomics).
+__global__ __launch_bounds__(256) void k_single_mask(const LatDesc *__restrict__ lat, int L,
+                                                     const int64_t *__restrict__ n_det, int64_t cap,
+                                                     const int32_t *__restrict__ det_hash, int64_t wl,
+                                                     const uint32_t *__restrict__ g_twice,
+                                                     uint32_t *__restrict__ mask)
+{
+    const int f = blockIdx.y;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_of(n_det, f, cap)) return;
+    const int32_t *hq = det_hash + ((int64_t)f * cap + q) * L;
+    const uint32_t *gt = g_twice + (int64_t)f * L * wl;
+    uint32_t w[2] = {0u, 0u};
+    for (int l = 0; l < L; ++l) {
+        const int h = hq[l];
+        if (!((gt[(int64_t)l * wl + (h >> 5)] >> (h & 31)) & 1u)) w[l >> 5] |= 1u << (l & 31);
+    }
+    const int W = mask_words(L);
+    for (int k = 0; k < W; ++k) mask[((int64_t)f * cap + q) * W + k] = w[k];
+}
+
 // ------------------------------------------------------------------ combine
 // Median position(s) by rank: rank_l = #{m : (v_m, m) < (v_l, l)}.  Entries
 // L..LMAX-1 hold +infinity, which never ranks below a lattice value, so the
@@ -446,26 +518,101 @@ int gsort_run(Plan &p, uint64_t *key, int32_t *pos, int64_t P)
     return MR1L_OK;
 }
 
-// Detected indices into sort pairs (padding sorts last), and back.
-__global__ __launch_bounds__(256) void k_det_to_pairs(const int64_t *__restrict__ n_det, int64_t cap,
-                                                      const int64_t *__restrict__ det_idx, int64_t P,
-                                                      uint64_t *__restrict__ key, int32_t *__restrict__ pos)
+// Ascending order of a long detected list without a sort: the detected candidates
+// set their bits in a bitmap over the concatenated candidate sets, and an ordered
+// compaction of each function's range of bits writes them back in index order
+// (counts per block of 1024 words, a scan of the counts, then the emission).
+constexpr int kFlagWordsPerBlock = 1024;   // 256 threads x 4 words
+
+__global__ __launch_bounds__(256) void k_flag_det(const int64_t *__restrict__ n_det, int64_t cap,
+                                                  const int64_t *__restrict__ det_idx,
+                                                  const int64_t *__restrict__ set_off, uint32_t *__restrict__ flags)
 {
     const int f = blockIdx.y;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    const bool in = i < n_of(n_det, f, cap);
-    key[(int64_t)f * P + i] = in ? (uint64_t)det_idx[(int64_t)f * cap + i] : ~0ull;
-    pos[(int64_t)f * P + i] = in ? (int32_t)i : INT32_MAX;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_of(n_det, f, cap)) return;
+    const int64_t c = set_off[f] + det_idx[(int64_t)f * cap + q];
+    atomicOr(flags + (c >> 5), 1u << (c & 31));
 }
 
-__global__ __launch_bounds__(256) void k_pairs_to_det(const int64_t *__restrict__ n_det, int64_t cap, int64_t P,
-                                                      const uint64_t *__restrict__ key, int64_t *__restrict__ det_idx)
+// bits of word w that belong to the candidate range [lo, hi)
+__device__ __forceinline__ uint32_t flag_word(const uint32_t *flags, int64_t w, int64_t lo, int64_t hi)
 {
+    const int64_t b0 = w * 32;
+    if (b0 + 32 <= lo || b0 >= hi) return 0u;
+    uint32_t v = flags[w];
+    if (lo > b0) v &= ~0u << (lo - b0);
+    if (hi < b0 + 32) v &= (1u << (hi - b0)) - 1u;
+    return v;
+}
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const int a = tid >= o ? sh[tid - o] : 0;
+        __syncthreads();
+        sh[tid] += a;
+        __syncthreads();
+    }
+    const int incl = sh[tid];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_flag_count(const int64_t *__restrict__ set_off,
+                                                    const uint32_t *__restrict__ flags, int nx,
+                                                    int32_t *__restrict__ cnt)
+{
+    __shared__ int sh[256];
     const int f = blockIdx.y;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n_of(n_det, f, cap)) return;
-    det_idx[(int64_t)f * cap + i] = (int64_t)key[(int64_t)f * P + i];
+    const int64_t lo = set_off[f], hi = set_off[f + 1];
+    const int64_t wb = (lo >> 5) + (int64_t)blockIdx.x * kFlagWordsPerBlock + threadIdx.x * 4;
+    int c = 0;
+    for (int k = 0; k < 4; ++k) c += __popc(flag_word(flags, wb + k, lo, hi));
+    const int before = block_exclusive_scan(c, sh);
+    if (threadIdx.x == blockDim.x - 1) cnt[(int64_t)f * nx + blockIdx.x] = before + c;
+}
+
+__global__ __launch_bounds__(64) void k_flag_scan(int nx, int32_t *__restrict__ cnt)
+{
+    if (threadIdx.x != 0) return;
+    int32_t *c = cnt + (int64_t)blockIdx.x * nx;
+    int acc = 0;
+    for (int x = 0; x < nx; ++x) {
+        const int v = c[x];
+        c[x] = acc;
+        acc += v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_flag_emit(const int64_t *__restrict__ set_off,
+                                                   const uint32_t *__restrict__ flags, int nx,
+                                                   const int32_t *__restrict__ off, int64_t cap,
+                                                   int64_t *__restrict__ det_idx)
+{
+    __shared__ int sh[256];
+    const int f = blockIdx.y;
+    const int64_t lo = set_off[f], hi = set_off[f + 1];
+    const int64_t wb = (lo >> 5) + (int64_t)blockIdx.x * kFlagWordsPerBlock + threadIdx.x * 4;
+    uint32_t v[4];
+    int c = 0;
+    for (int k = 0; k < 4; ++k) {
+        v[k] = flag_word(flags, wb + k, lo, hi);
+        c += __popc(v[k]);
+    }
+    int64_t r = off[(int64_t)f * nx + blockIdx.x] + block_exclusive_scan(c, sh);
+    for (int k = 0; k < 4; ++k) {
+        uint32_t b = v[k];
+        while (b) {
+            const int j = __ffs(b) - 1;
+            b &= b - 1;
+            if (r < cap) det_idx[(int64_t)f * cap + r] = (wb + k) * 32 + j - lo;
+            ++r;
+        }
+    }
 }
 
 // Algorithm 4 keys of a long list: ~bits(|p|^2) for |p|^2 >= theta^2 (ascending key =
@@ -473,8 +620,7 @@ __global__ __launch_bounds__(256) void k_pairs_to_det(const int64_t *__restrict_
 template <typename T>
 __global__ __launch_bounds__(256) void k_limit_keys(const int64_t *__restrict__ n_det, int64_t cap,
                                                     const typename cvec<T>::type *__restrict__ det_coef, T th2,
-                                                    int64_t P, uint64_t *__restrict__ key, int32_t *__restrict__ pos,
-                                                    int64_t *__restrict__ npass)
+                                                    int64_t P, uint64_t *__restrict__ key, int32_t *__restrict__ pos)
 {
     using V = typename cvec<T>::type;
     const int f = blockIdx.y;
@@ -490,14 +636,12 @@ __global__ __launch_bounds__(256) void k_limit_keys(const int64_t *__restrict__ 
             ps = (int32_t)i;
         }
     }
-    const uint64_t bal = __ballot(ps != INT32_MAX);
-    if ((threadIdx.x & 63) == 0 && bal) atomicAdd((unsigned long long *)(npass + f), (unsigned long long)__popcll(bal));
     key[(int64_t)f * P + i] = k;
     pos[(int64_t)f * P + i] = ps;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_limit_emit(const int64_t *__restrict__ npass, int64_t cap,
+__global__ __launch_bounds__(256) void k_limit_emit(int64_t cap,
                                                     const int64_t *__restrict__ det_idx,
                                                     const typename cvec<T>::type *__restrict__ det_coef, int64_t P,
                                                     const int32_t *__restrict__ pos, int64_t s_cap,
@@ -507,10 +651,18 @@ __global__ __launch_bounds__(256) void k_limit_emit(const int64_t *__restrict__ 
 {
     const int f = blockIdx.y;
     const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t no = min(npass[f], s_cap);
+    // the passing entries sort first (their positions are below INT32_MAX): the
+    // output length is the first failing position among the first s~
+    const int32_t *pf = pos + (int64_t)f * P;
+    int64_t lo = 0, hi = min(P, s_cap);
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (pf[mid] != INT32_MAX) lo = mid + 1; else hi = mid;
+    }
+    const int64_t no = lo;
     if (o == 0) n_out[f] = no;
     if (o >= no) return;
-    const int32_t q = pos[(int64_t)f * P + o];
+    const int32_t q = pf[o];
     out_idx[(int64_t)f * s_cap + o] = det_idx[(int64_t)f * cap + q];
     out_coef[(int64_t)f * s_cap + o] = det_coef[(int64_t)f * cap + q];
     if (out_pos) out_pos[(int64_t)f * s_cap + o] = q;
@@ -569,6 +721,7 @@ int extract_init_attrs()
     // dynamic LDS at the largest capacity (static LDS comes on top of it)
     const std::pair<const void *, int> ks[] = {
         {(const void *)k_singleton, 2 * kSingleWords * (int)sizeof(uint32_t)},
+        {(const void *)k_single_count, 2 * kSingleWords * (int)sizeof(uint32_t)},
         {(const void *)k_sort_det, kMaxCap * (int)sizeof(int64_t)},
         {(const void *)k_limit<double>, kMaxCap * 12},
         {(const void *)k_limit<float>, kMaxCap * 12}};
@@ -604,36 +757,39 @@ static int limit_long(Plan &p, const int64_t *n_det, int64_t cap, const int64_t 
 {
     uint64_t *skey = (uint64_t *)p.d_gsort;
     int32_t *spos = (int32_t *)(skey + p.F * P);
-    int64_t *npass = p.d_det_tmp;
-    int rc = launch_fill_bytes(npass, p.F * (int64_t)sizeof(int64_t), p.stream);
-    if (rc) return rc;
+    int rc = MR1L_OK;
     const dim3 gp((unsigned)((P + 255) / 256), (unsigned)p.F);
     if (p.dtype == MR1L_C128)
         hipLaunchKernelGGL(k_limit_keys<double>, gp, dim3(256), 0, p.stream, n_det, cap, (const double2 *)det_coef,
-                           theta * theta, P, skey, spos, npass);
+                           theta * theta, P, skey, spos);
     else
         hipLaunchKernelGGL(k_limit_keys<float>, gp, dim3(256), 0, p.stream, n_det, cap, (const float2 *)det_coef,
-                           (float)(theta * theta), P, skey, spos, npass);
+                           (float)(theta * theta), P, skey, spos);
     MR1L_LAUNCH_CHECK();
     if ((rc = gsort_run(p, skey, spos, P))) return rc;
     const dim3 ge((unsigned)((s_cap + 255) / 256), (unsigned)p.F);
     if (p.dtype == MR1L_C128)
-        hipLaunchKernelGGL(k_limit_emit<double>, ge, dim3(256), 0, p.stream, npass, cap, det_idx,
-                           (const double2 *)det_coef, P, spos, s_cap, n_out, out_idx, (double2 *)out_coef, out_pos);
+        hipLaunchKernelGGL(k_limit_emit<double>, ge, dim3(256), 0, p.stream, cap, det_idx, (const double2 *)det_coef,
+                           P, spos, s_cap, n_out, out_idx, (double2 *)out_coef, out_pos);
     else
-        hipLaunchKernelGGL(k_limit_emit<float>, ge, dim3(256), 0, p.stream, npass, cap, det_idx,
-                           (const float2 *)det_coef, P, spos, s_cap, n_out, out_idx, (float2 *)out_coef, out_pos);
+        hipLaunchKernelGGL(k_limit_emit<float>, ge, dim3(256), 0, p.stream, cap, det_idx, (const float2 *)det_coef,
+                           P, spos, s_cap, n_out, out_idx, (float2 *)out_coef, out_pos);
     MR1L_LAUNCH_CHECK();
     return MR1L_OK;
 }
 
 // the longest of the F detected lists (one synchronisation) and sort buffers of its
 // power-of-two size
-static int long_list_size(Plan &p, const int64_t *n_det, int64_t cap, int64_t &nmax, int64_t &P)
+static int long_list_size(Plan &p, const int64_t *n_det, int64_t cap, int64_t &nmax, int64_t &P,
+                          const int64_t *set_off = nullptr, std::vector<int64_t> *so = nullptr)
 {
     if (p.capturing) return fail(MR1L_E_ARG, "lists longer than 8192 cannot be recorded in a graph");
     std::vector<int64_t> nd((size_t)p.F);
     MR1L_HIP(hipMemcpyAsync(nd.data(), n_det, nd.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p.stream));
+    if (so) {
+        so->resize((size_t)p.F + 1);
+        MR1L_HIP(hipMemcpyAsync(so->data(), set_off, so->size() * sizeof(int64_t), hipMemcpyDeviceToHost, p.stream));
+    }
     MR1L_HIP(hipStreamSynchronize(p.stream));
     nmax = 0;
     for (int64_t v : nd) nmax = std::max(nmax, std::min(v, cap));
@@ -649,24 +805,45 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     const bool large = cap > kMaxCap;
     int64_t nmax = cap, P = 1;
     int rc = MR1L_OK;
-    uint64_t *skey = nullptr;
-    int32_t *spos = nullptr;
     if (!large) {
         const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
         hipLaunchKernelGGL(k_sort_det, dim3(p.F), dim3(kSortThreads), pc * sizeof(int64_t), p.stream, out.n_det, cap,
                            out.det_idx);
         MR1L_LAUNCH_CHECK();
     } else {
-        // the sort sizes come from the detected counts
-        if ((rc = long_list_size(p, out.n_det, cap, nmax, P))) return rc;
-        skey = (uint64_t *)p.d_gsort;
-        spos = (int32_t *)(skey + p.F * P);
-        const dim3 gp((unsigned)((P + 255) / 256), (unsigned)p.F);
-        hipLaunchKernelGGL(k_det_to_pairs, gp, dim3(256), 0, p.stream, out.n_det, cap, out.det_idx, P, skey, spos);
-        MR1L_LAUNCH_CHECK();
-        if ((rc = gsort_run(p, skey, spos, P))) return rc;
-        hipLaunchKernelGGL(k_pairs_to_det, gp, dim3(256), 0, p.stream, out.n_det, cap, P, skey, out.det_idx);
-        MR1L_LAUNCH_CHECK();
+        // the buffer sizes come from the detected counts and the set offsets
+        std::vector<int64_t> so;
+        if ((rc = long_list_size(p, out.n_det, cap, nmax, P, set_off, &so))) return rc;
+        if (nmax > 0) {
+            // ascending order by an ordered compaction of the detected candidates' bits
+            int64_t wmax = 1;
+            for (int f = 0; f < p.F; ++f)
+                wmax = std::max<int64_t>(wmax, ((so[f + 1] + 31) >> 5) - (so[f] >> 5));
+            const int nx = (int)((wmax + kFlagWordsPerBlock - 1) / kFlagWordsPerBlock);
+            const int64_t fwords = (n_total + 31) / 32 + 1;
+            const int64_t bytes = fwords * 4 + (int64_t)p.F * nx * 4;
+            if (p.dflag_bytes < bytes || !p.d_dflag) {
+                if (p.d_dflag) (void)hipFree(p.d_dflag);
+                p.d_dflag = nullptr;
+                p.dflag_bytes = 0;
+                MR1L_HIP(hipMalloc(&p.d_dflag, (size_t)bytes));
+                p.dflag_bytes = bytes;
+            }
+            uint32_t *flags = p.d_dflag;
+            int32_t *cnt = (int32_t *)(p.d_dflag + fwords);
+            if ((rc = launch_fill_u32(flags, fwords, 0u, p.stream))) return rc;
+            hipLaunchKernelGGL(k_flag_det, dim3((unsigned)((nmax + 255) / 256), (unsigned)p.F), dim3(256), 0, p.stream,
+                               out.n_det, cap, out.det_idx, set_off, flags);
+            MR1L_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_flag_count, dim3((unsigned)nx, (unsigned)p.F), dim3(256), 0, p.stream, set_off, flags,
+                               nx, cnt);
+            MR1L_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_flag_scan, dim3((unsigned)p.F), dim3(64), 0, p.stream, nx, cnt);
+            MR1L_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_flag_emit, dim3((unsigned)nx, (unsigned)p.F), dim3(256), 0, p.stream, set_off, flags,
+                               nx, cnt, cap, out.det_idx);
+            MR1L_LAUNCH_CHECK();
+        }
     }
     if (nmax > 0) {
         dim3 gq((unsigned)((nmax * p.L + 255) / 256), (unsigned)p.F);
@@ -679,9 +856,33 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     int64_t maxM = 1;
     for (int64_t m : p.M) maxM = std::max(maxM, m);
     const int words = (int)std::min<int64_t>(kSingleWords, (maxM + 31) / 32);
-    hipLaunchKernelGGL(k_singleton, dim3(p.L, p.F), dim3(256), 2 * (size_t)words * sizeof(uint32_t), p.stream,
-                       p.d_lat, p.L, out.n_det, cap, det_hash, det_mask, words);
-    MR1L_LAUNCH_CHECK();
+    if (!large || nmax <= kMaxCap) {
+        hipLaunchKernelGGL(k_singleton, dim3(p.L, p.F), dim3(256), 2 * (size_t)words * sizeof(uint32_t), p.stream,
+                           p.d_lat, p.L, out.n_det, cap, det_hash, det_mask, words);
+        MR1L_LAUNCH_CHECK();
+    } else {
+        // long lists: chunks of the detected set per lattice, merged in global bitmaps
+        const int64_t wl = (maxM + 31) / 32;
+        const int64_t bytes = 2 * (int64_t)p.F * p.L * wl * (int64_t)sizeof(uint32_t);
+        if (p.single_bytes < bytes || !p.d_single) {
+            if (p.d_single) (void)hipFree(p.d_single);
+            p.d_single = nullptr;
+            p.single_bytes = 0;
+            MR1L_HIP(hipMalloc(&p.d_single, (size_t)bytes));
+            p.single_bytes = bytes;
+        }
+        uint32_t *g_once = p.d_single, *g_twice = p.d_single + (int64_t)p.F * p.L * wl;
+        if ((rc = launch_fill_u32(p.d_single, 2 * (int64_t)p.F * p.L * wl, 0u, p.stream))) return rc;
+        const int64_t by_cus = std::max<int64_t>(1, 2 * (int64_t)num_cus() / std::max<int64_t>(1, (int64_t)p.L * p.F));
+        const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(by_cus, (nmax + 4095) / 4096));
+        hipLaunchKernelGGL(k_single_count, dim3((unsigned)chunks, (unsigned)p.L, (unsigned)p.F), dim3(kSingleThreads),
+                           2 * (size_t)words * sizeof(uint32_t), p.stream, p.d_lat, p.L, out.n_det, cap, det_hash,
+                           chunks, wl, g_once, g_twice, words);
+        MR1L_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_single_mask, dim3((unsigned)((nmax + 255) / 256), (unsigned)p.F), dim3(256), 0, p.stream,
+                           p.d_lat, p.L, out.n_det, cap, det_hash, wl, g_twice, det_mask);
+        MR1L_LAUNCH_CHECK();
+    }
     const int64_t ncomb = std::max<int64_t>(nmax, 1);
     if (p.dtype == MR1L_C128)
         rc = combine_launch<double>(p, out.n_det, cap, ncomb, det_hash, det_mask, ghat, o.postproc, out.det_coef,

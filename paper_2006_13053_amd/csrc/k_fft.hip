@@ -707,7 +707,6 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
             __syncthreads();
             lds_fft_p2<T, NT, P>(re, im, logN1, logB2, tsub, logNT);
             const T sc = scale_by_m ? scale * (T)M : scale;
-#pragma unroll 4
             for (int e = opaque(tid); e < tot; e += NT) {
                 const int b = e & (B2 - 1), a = e >> logB2;   // output n = N2 a + (c0 + b)
                 const int h = (a << logN2) + c0 + b;

@@ -157,6 +157,10 @@ struct Plan {
     int64_t ex_scap = 0;
     void *d_gsort = nullptr;         // global sort pairs of long detected lists: [F][P] uint64 + [F][P] int32
     int64_t gsort_bytes = 0;
+    uint32_t *d_single = nullptr;    // long lists: bucket bitmaps seen once / twice, 2 x [F][L][ceil(maxM/32)]
+    int64_t single_bytes = 0;
+    uint32_t *d_dflag = nullptr;     // long lists: detected-candidate bitmap over all sets + block counts
+    int64_t dflag_bytes = 0;
     void *d_bs_dims = nullptr;       // B-spline sampler: [F][n_prod] coordinate masks
     int64_t bs_bytes = 0;
     void *d_ls = nullptr;            // least squares: [F][cap][L] int32 representatives + 4 [F][cap] complex

@@ -568,15 +568,15 @@ def test_injectivity_check_matches_definition(m):
     assert list(ok) == [c[3] for c in sel] and ok_all == all(c[3] for c in sel)
 
 
-@pytest.mark.parametrize("seed,F", [(1, 1), (2, 2)])
-def test_long_detected_lists_match_oracle(m, seed, F):
+@pytest.mark.parametrize("seed,F,L", [(1, 1, 7), (2, 2, 7), (3, 1, 40)])
+def test_long_detected_lists_match_oracle(m, seed, F, L):
     """Detected lists longer than 8192 (global-memory sorts): noise samples make every
     bucket non-zero, so every candidate is detected; Algorithm 4 keeps the 10000
     largest medians.  Against the oracle per function, and against the LDS path on
     the same pass truncated to fit."""
-    say("long lists", seed, F)
+    say("long lists", seed, F, L)
     rng = np.random.default_rng(100 + seed)
-    d, L = 4, 7
+    d = 4
     sets, Ms, zs, fs = [], [], [], []
     for fi in range(F):
         n = 30000 - 7000 * fi
