@@ -96,11 +96,23 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
 
     // the coordinates of the next tile are loaded while the current one is hashed
     int64_t kn[DM];
+    // buffer loads: one descriptor per coordinate row, based at the tile and bounded by
+    // the row's end (lanes past the last candidate read 0), plus the lane's byte
+    // offset; the descriptors come from scalar adds, not per-lane 64-bit addresses
     auto load_tile = [&](int64_t t) {
-        const int64_t ci = min(t + tid, n_total - 1);
+        const int nrec = (int)min<int64_t>((n_total - t) * 8, (int64_t)0x7ffffff8);
+        const char *b = reinterpret_cast<const char *>(freq + t);
 #pragma unroll
-        for (int u = 0; u < DM; ++u)
-            if (u < d) kn[u] = __builtin_nontemporal_load(freq + (int64_t)u * n_total + ci);
+        for (int u = 0; u < DM; ++u) {
+            if (u < d) {
+                const __amdgpu_buffer_rsrc_t r =
+                    __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(b), (short)0, nrec, 0x00020000);
+                typedef int v2i __attribute__((ext_vector_type(2)));
+                const v2i x = __builtin_amdgcn_raw_buffer_load_b64(r, tid * 8, 0, 2);   // nontemporal
+                kn[u] = (int64_t)(((uint64_t)(uint32_t)x.y << 32) | (uint32_t)x.x);
+            }
+            b += n_total * 8;
+        }
     };
     if (beg < end) load_tile(beg);
     for (int64_t t0 = beg; t0 < end; t0 += kVoteThreads) {
@@ -146,7 +158,8 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(
             if (f_hi <= seg) break;   // inconsistent offsets: stop instead of spinning
             const int64_t sEnd = min(tend, f_hi);
             const int64_t c = t0 + tid;
-            const bool val = (c >= seg) && (c < sEnd);
+            // the lanes of [seg, sEnd), tested on tile offsets (32-bit)
+            const bool val = (tid >= (int)(seg - t0)) && (tid < (int)(sEnd - t0));
             const bool act = val && fast;
             int v = act ? 0 : -(1 << 20);
             if (__any(act)) {
