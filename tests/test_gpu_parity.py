@@ -334,8 +334,8 @@ def test_sample_bucket_mode_lds_sums(m, dtype, anchored):
     the oracle's direct evaluation of eq. (2.2)."""
     say("sample bucket mode lds", dtype, anchored)
     rng = np.random.default_rng(21 + anchored)
-    d_poly, t, F, L = 5, (3 if anchored else 5), 3, 4
-    counts = [5000, 12000, 700]
+    d_poly, t, F, L = 5, (3 if anchored else 5), 4, 4
+    counts = [5000, 12000, 0, 700]   # one function without terms
     freqs = [rng.integers(-60, 61, size=(d_poly, n), dtype=np.int64) for n in counts]
     coefs = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in counts]
     Ms, zs = [], []
@@ -353,9 +353,13 @@ def test_sample_bucket_mode_lds_sums(m, dtype, anchored):
     got = got.cpu().numpy().astype(np.complex128)
     off = 0
     for f in range(F):
+        n = int(Ms[f].sum())
+        if counts[f] == 0:
+            assert np.all(got[off:off + n] == 0), f
+            off += n
+            continue
         want = oracle.sample(freqs[f], coefs[f], Ms[f], zs[f], anchor=anc[f] if anchored else None,
                              t=t if anchored else None)
-        n = int(Ms[f].sum())
         err = np.abs(got[off:off + n] - want).max() / np.abs(want).max()
         assert err <= TOL[dtype], (f, err)
         off += n
@@ -499,6 +503,39 @@ def test_mid_config_full_pass_with_noise(m, seed):
     compare_pass(r, ro, go, p.theta, 1e-11, 200)
     # the support is found and its coefficients are within the noise of the truth
     assert set(p.supp_idx.tolist()) <= set(r["out_idx"].tolist())
+
+
+def test_long_list_mode_with_empty_and_undetected_functions(m):
+    """cap > 8192 (global-memory paths) with a function whose set is empty, one whose
+    lattice values are all zero (nothing detected) and one that detects 12,000
+    candidates: counts, order, masks and coefficients against the oracle."""
+    say("long lists, empty functions")
+    rng = np.random.default_rng(77)
+    d, L = 3, 6
+    sizes = [0, 3000, 12000]
+    sets = [synth.distinct_uniform_points(rng, n, d, -80, 80) if n else np.zeros((d, 0), np.int64) for n in sizes]
+    Ms, zs, fs = [], [], []
+    for fi, n in enumerate(sizes):
+        M, z = synth.draw_lattices(rng, L, d, 1500, 2500)
+        Ms.append(M)
+        zs.append(z)
+        f = rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum()))
+        fs.append(f if fi != 1 else np.zeros_like(f))
+    plan = m.Plan(d, np.concatenate(Ms), np.concatenate(zs), F=3)
+    g, bm = m.mr1l_fft(plan, T(np.concatenate(fs)), 1e-9)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ex = m.mr1l_extract(plan, T(np.concatenate(sets, axis=1)), g, bm, 1e-9, s_cap=5000, cap=16384,
+                        set_off=T(off), want_w=False)
+    torch.cuda.synchronize()
+    assert [int(v) for v in ex["n_det"].cpu()] == [0, 0, 12000]
+    assert [int(v) for v in ex["n_out"].cpu()] == [0, 0, 5000]
+    go = oracle.dft(fs[2], Ms[2])
+    ro = oracle.extract(sets[2], Ms[2], zs[2], go, 1e-9, s_cap=5000, cap=16384)
+    assert np.array_equal(ex["det_idx"][2, :12000].cpu().numpy(), ro["det_idx"])
+    assert np.array_equal(mask64(ex["det_mask"][2, :12000]), ro["det_mask"])
+    close(ex["det_coef"][2, :12000].cpu().numpy(), ro["det_coef"], 1e-11, "coefficients")
+    r = dict(out_idx=ex["out_idx"][2, :5000].cpu().numpy(), out_coef=ex["out_coef"][2, :5000].cpu().numpy())
+    check_limit(r, ro, EPS[torch.complex128], 1e-11)
 
 
 @pytest.mark.parametrize("d", [13, 23, 40])
