@@ -66,8 +66,14 @@ constexpr int kVoteLdsWords = 20480;          // 80 KiB: lattice records + bitma
 // lattice l + 1 is loaded while lattice l is hashed (record L is a padding
 // copy).  Lanes without a fast-path candidate start their count far below
 // zero, which makes them count as decided in the early exit.
+// Waves per SIMD the register allocation aims at: 8 (four 512-thread workgroups per
+// CU, as a 40 KiB LDS bitmap allows; the SGPRs beyond 78 go to VGPR lanes) for the
+// dimensions where that needs no VGPR spills, else whatever the registers give.
+template <int D> constexpr int vote_waves() { return (D >= 1 && D <= 4) || (D >= 7 && D <= 10) ? 8 : 1; }
+
 template <int D, bool LDSB, bool DOT2>
-__global__ __launch_bounds__(kVoteThreads) void k_vote(
+__global__ __launch_bounds__(kVoteThreads) __attribute__((amdgpu_waves_per_eu(vote_waves<D>())))
+void k_vote(
     const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int F,
     int L, int d_rt, const LatDesc *__restrict__ lat, const int64_t *__restrict__ z64,
     const uint32_t *__restrict__ vrec, int rs, int32_t kb_min,
