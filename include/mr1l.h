@@ -180,7 +180,9 @@ typedef struct {
     int64_t s_cap;     /* Algorithm 4 sparsity s~ per function (>= 1)         */
     int64_t cap;       /* detected-list capacity per function, 1..2^24; above
                           8192 the call synchronises its stream once (to size
-                          global-memory sorts) and cannot be graph-captured */
+                          its global-memory buffers: the ordered compaction of
+                          the detected set and Algorithm 4's sort) and cannot
+                          be graph-captured */
 } mr1l_extract_opts;
 
 /* Outputs of mr1l_extract (all dev; optional ones may be NULL). */
