@@ -590,6 +590,24 @@ def bench_bspline(m, torch, args):
 
 
 # ----------------------------------------------------------------------------- oracle legs
+def copy_bandwidth(torch, nbytes=1 << 31):
+    """Measured HBM rate of a plain device copy (torch's copy kernel): bytes read plus
+    written over the best of three copies of nbytes, in GB/s (next to the 8 TB/s peak)."""
+    a = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    best = None
+    for _ in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    del a, b
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
 def cpu_baseline_large(w, n_sample, budget_s=10.0):
     """Oracle on one function of the batch, repeated until ~budget_s of CPU time: direct
     O(M^2) DFTs of its 20 lattices (on synthetic samples of the same size) and Algorithm 2
@@ -796,11 +814,17 @@ def main():
         out["roofline"] = {"bound": "hbm", "kernel": "k_vote (hash + vote + compaction)", "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                            "traffic": traffic, "algorithmic_bytes_per_launch": algo_bytes,
-                           "vote_ms_per_launch": vote_ms}
+                           "vote_ms_per_launch": vote_ms, "copy_GBps": copy_bandwidth(torch)}
         fft_ms = out["stages_ms"]["fft"]
         fft_bytes = 2.0 * 16 * plan.nodes if dtype == "c128" else 2.0 * 8 * plan.nodes
+        # the FLOP roof too, with the nominal 5 M log2 M operations of a length-M DFT
+        fft_flops = float(sum(5.0 * int(mm) * np.log2(int(mm)) for mm in plan.M))
+        flop_peak = 78.6 if dtype == "c128" else 157.3
         out["fft_roofline"] = {"achieved": fft_bytes / (fft_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                               "unit": "GB/s", "algorithmic_bytes_per_launch": fft_bytes}
+                               "unit": "GB/s", "algorithmic_bytes_per_launch": fft_bytes,
+                               "nominal_flops_per_launch": fft_flops,
+                               "achieved_TFLOPs": fft_flops / (fft_ms * 1e-3) / 1e12,
+                               "peak_TFLOPs": flop_peak}
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
     if not args.no_plain:
         t_plain, _ = plain_pass(m, torch, w)
