@@ -88,6 +88,11 @@ void k_vote(
     extern __shared__ __align__(16) uint32_t lds[];
     const int recw = (L + 1) * rs;                  // rs is a multiple of 4
     uint32_t *bits = lds;
+    // LDS byte addresses of the bitmap words come straight from the bit index: the
+    // bitmap's LDS base (a multiple of 32 bits) is folded into each lattice's scalar
+    // bit base, so the per-lane index needs no separate base add
+    typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+    const uint32_t lds_bit0 = LDSB ? (uint32_t)(uintptr_t)(lds_u32 *)bits * 8u : 0u;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int64_t ntiles = (n_total + kVoteThreads - 1) / kVoteThreads;
@@ -198,9 +203,9 @@ void k_vote(
                     const uint32_t q = (uint32_t)((float)s * __uint_as_float(r[2]));
                     uint32_t h = (uint32_t)(__mul24((int32_t)q, negM) + (int32_t)s);   // in [0, 2M)
                     h = min(h, h + (uint32_t)negM);
-                    const uint32_t g = r[3] + h;
+                    const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane(r[3] + lds_bit0) + h;
                     uint32_t word;
-                    if constexpr (LDSB) word = bits[g >> 5];
+                    if constexpr (LDSB) word = *(lds_u32 *)(uintptr_t)((g >> 3) & ~3u);
                     else word = bitmap[word0 + (g >> 5)];
                     v += (int)__builtin_amdgcn_ubfe(word, g, 1);   // bit g mod 32
                 };
