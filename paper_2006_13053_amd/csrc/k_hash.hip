@@ -77,7 +77,7 @@ void k_vote(
     const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int F,
     int L, int d_rt, const LatDesc *__restrict__ lat, const int64_t *__restrict__ z64,
     const uint32_t *__restrict__ vrec, int rs, int32_t kb_min,
-    const uint32_t *__restrict__ bitmap, int vote_min, int64_t cap,
+    const uint32_t *__restrict__ bitmap, int64_t bm_words, int vote_min, int64_t cap,
     int64_t *__restrict__ det_cnt, int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes)
 {
     // D > 0: exactly D coordinates; D < 0: runtime d <= -D; D == 0: runtime d <= kMaxD
@@ -88,11 +88,12 @@ void k_vote(
     extern __shared__ __align__(16) uint32_t lds[];
     const int recw = (L + 1) * rs;                  // rs is a multiple of 4
     uint32_t *bits = lds;
-    // LDS byte addresses of the bitmap words come straight from the bit index: the
-    // bitmap's LDS base (a multiple of 32 bits) is folded into each lattice's scalar
-    // bit base, so the per-lane index needs no separate base add
+    // In LDS each lattice's bits start on a word (re-aligned when the function's bitmap
+    // is loaded), so bucket h of lattice l is bit h mod 32 of the word at byte
+    // base_l + 4 (h >> 5); base_l (record word 4) plus the bitmap's LDS base is a
+    // scalar sum, and the per-lane address needs one shift and one shift-add
     typedef __attribute__((address_space(3))) const uint32_t lds_u32;
-    const uint32_t lds_bit0 = LDSB ? (uint32_t)(uintptr_t)(lds_u32 *)bits * 8u : 0u;
+    const uint32_t lds_byte0 = LDSB ? (uint32_t)(uintptr_t)(lds_u32 *)bits : 0u;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int64_t ntiles = (n_total + kVoteThreads - 1) / kVoteThreads;
@@ -157,12 +158,24 @@ void k_vote(
                 f_lo = set_off[f];
                 f_hi = set_off[f + 1];
                 const LatDesc l0 = lat[f * L];
-                const LatDesc lL = lat[f * L + L - 1];
                 word0 = l0.node_off >> 5;
                 __syncthreads();   // every wave is done with the previous function's tables
                 if (LDSB) {
-                    const int64_t wN = ((lL.node_off + lL.M - 1) >> 5) - word0 + 1;
-                    for (int64_t w = tid; w < wN; w += kVoteThreads) bits[w] = bitmap[word0 + w];
+                    // lattice l's M_l bits from bit node_off of the bitmap, to words from
+                    // sum_{l' < l} ceil(M_l' / 32) on (a funnel shift of two words)
+                    int wbase = 0;
+                    for (int l = 0; l < L; ++l) {
+                        const LatDesc ll = lat[f * L + l];
+                        const int nw = (ll.M + 31) >> 5;
+                        const int64_t g0 = ll.node_off >> 5;
+                        const uint32_t sh = (uint32_t)(ll.node_off & 31);
+                        for (int w = tid; w < nw; w += kVoteThreads) {
+                            const uint32_t lo = bitmap[g0 + w];
+                            const uint32_t hi = g0 + w + 1 < bm_words ? bitmap[g0 + w + 1] : 0u;
+                            bits[wbase + w] = __builtin_amdgcn_alignbit(hi, lo, sh);
+                        }
+                        wbase += nw;
+                    }
                 }
                 __syncthreads();
             }
@@ -177,14 +190,14 @@ void k_vote(
                 // uniform records through the scalar cache (constant address space)
                 typedef const __attribute__((address_space(4))) uint32_t *crec_t;
                 const crec_t rp = (crec_t)(uintptr_t)(vrec + (int64_t)f * recw);
-                constexpr int RW = 4 + ZW;
+                constexpr int RW = 5 + ZW;
                 uint32_t ra[RW], rb[RW];
 #pragma unroll
-                for (int j = 0; j < RW; ++j) ra[j] = (j < 4 + zw) ? rp[j] : 0u;
+                for (int j = 0; j < RW; ++j) ra[j] = (j < 5 + zw) ? rp[j] : 0u;
                 // hash lattice l with record `cur` while record l + 1 is loaded into `nxt`
                 auto step = [&](const uint32_t (&r)[RW], uint32_t (&nxt)[RW], int l) {
 #pragma unroll
-                    for (int j = 0; j < RW; ++j) nxt[j] = (j < 4 + zw) ? rp[(l + 1) * rs + j] : 0u;
+                    for (int j = 0; j < RW; ++j) nxt[j] = (j < 5 + zw) ? rp[(l + 1) * rs + j] : 0u;
                     uint32_t s = r[0];
                     if constexpr (DOT2) {
                         typedef short v2s __attribute__((ext_vector_type(2)));
@@ -192,21 +205,30 @@ void k_vote(
                         for (int j = 0; j < ZW; ++j)
                             if (j < zw)
                                 s = (uint32_t)__builtin_amdgcn_sdot2(__builtin_bit_cast(v2s, kp[j]),
-                                                                     __builtin_bit_cast(v2s, r[4 + j]), (int)s, false);
+                                                                     __builtin_bit_cast(v2s, r[5 + j]), (int)s, false);
                     } else {
 #pragma unroll
                         for (int u = 0; u < DM; ++u)
-                            if (u < d) s += (uint32_t)__mul24(lo[u], (int32_t)r[4 + u]);
+                            if (u < d) s += (uint32_t)__mul24(lo[u], (int32_t)r[5 + u]);
                     }
                     // s < 2^32 and s / M < 2^20: the float quotient is exact or one too small
                     const int32_t negM = (int32_t)r[1];
                     const uint32_t q = (uint32_t)((float)s * __uint_as_float(r[2]));
                     uint32_t h = (uint32_t)(__mul24((int32_t)q, negM) + (int32_t)s);   // in [0, 2M)
                     h = min(h, h + (uint32_t)negM);
-                    const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane(r[3] + lds_bit0) + h;
-                    uint32_t word;
-                    if constexpr (LDSB) word = *(lds_u32 *)(uintptr_t)((g >> 3) & ~3u);
-                    else word = bitmap[word0 + (g >> 5)];
+                    uint32_t word, g;
+                    if constexpr (LDSB) {
+                        const uint32_t wb = (uint32_t)__builtin_amdgcn_readfirstlane(r[4] + lds_byte0);
+                        // the word index hidden from the optimiser, so that the address stays
+                        // one shift-add instead of a shift, a mask and an add
+                        uint32_t hw = h >> 5;
+                        asm("" : "+v"(hw));
+                        word = *(lds_u32 *)(uintptr_t)(wb + (hw << 2));
+                        g = h;
+                    } else {
+                        g = r[3] + h;
+                        word = bitmap[word0 + (g >> 5)];
+                    }
                     v += (int)__builtin_amdgcn_ubfe(word, g, 1);   // bit g mod 32
                 };
                 // undecided after lattice l: vote_min - rest <= v < vote_min
@@ -241,11 +263,17 @@ void k_vote(
                 for (int l = 0; l < L; ++l) {
                     const LatDesc ld = lf[l];
                     const int32_t h = exact_bucket(freq + c, n_total, d, z64 + ld.z_off, ld.M);
-                    const int64_t g = ld.node_off + h;
                     uint32_t word;
-                    if constexpr (LDSB) word = bits[(g >> 5) - word0];
-                    else word = bitmap[g >> 5];
-                    v += (word >> (g & 31)) & 1u;
+                    int bit;
+                    if constexpr (LDSB) {
+                        word = bits[(vrec[(int64_t)f * recw + l * rs + 4] >> 2) + (h >> 5)];
+                        bit = h & 31;
+                    } else {
+                        const int64_t g = ld.node_off + h;
+                        word = bitmap[g >> 5];
+                        bit = (int)(g & 31);
+                    }
+                    v += (word >> bit) & 1u;
                 }
             }
             if (want_votes && val) votes[c] = (uint8_t)max(v, 0);
@@ -267,7 +295,7 @@ void k_vote(
 
 #define MR1L_VOTE_LAUNCH(Dv, LD, D2)                                                                       \
     hipLaunchKernelGGL((k_vote<Dv, LD, D2>), grid, blk, shm, p.stream, freq, n_total, set_off, p.F, p.L, p.d, \
-                       p.d_lat, p.d_z64, p.d_vrec, p.vrec_stride, kb_min, bitmap, vote_min, cap, n_det,             \
+                       p.d_lat, p.d_z64, p.d_vrec, p.vrec_stride, kb_min, bitmap, bm_words, vote_min, cap, n_det,   \
                        det_idx, votes)
 #define MR1L_VOTE_DISPATCH(Dv)                                          \
     case Dv:                                                            \
@@ -301,12 +329,14 @@ int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *fr
 {
     // n_det is zero-filled by the caller (outside the timed vote stage)
     if (n_total <= 0) return MR1L_OK;
-    // LDS bitmap when every function's lattice bits fit
+    // LDS bitmap (each lattice's bits from a word boundary) when every function's fit
     int64_t maxw = 0;
     for (int f = 0; f < p.F; ++f) {
-        const LatDesc &a = p.lat[(size_t)f * p.L], &b = p.lat[(size_t)f * p.L + p.L - 1];
-        maxw = std::max<int64_t>(maxw, ((b.node_off + b.M - 1) >> 5) - (a.node_off >> 5) + 1);
+        int64_t w = 0;
+        for (int l = 0; l < p.L; ++l) w += (p.lat[(size_t)f * p.L + l].M + 31) >> 5;
+        maxw = std::max<int64_t>(maxw, w);
     }
+    const int64_t bm_words = (p.nodes + 31) / 32;
     const bool lds = maxw <= kVoteLdsWords;
     const size_t shm = lds ? (size_t)maxw * 4 : 0;
     int32_t kb_min = INT32_MAX;

@@ -124,9 +124,12 @@ struct Plan {
     uint32_t *d_z16 = nullptr;       // [F*L][ceil(d/2)] z as packed int16 pairs (M <= 2^15)
     bool dot2 = false;               // every M <= 2^15: 16-bit packed dot products
     // vote records: per function L + 1 records of vrec_stride (a power of two >= 4) words
-    //   [off32, -M, inv_m bits, bit base, z words (packed pairs when dot2, else int32)...]
-    // (bit base = bit of bucket 0 relative to the function's first bitmap word;
-    //  record L repeats record L - 1 so the next record can always be loaded)
+    //   [off32, -M, inv_m bits, bit base, LDS byte base, z words (packed pairs when dot2,
+    //    else int32)...]
+    // (bit base = bit of bucket 0 relative to the function's first bitmap word; LDS byte
+    //  base = 4 x the words of the function's earlier lattices, each lattice's bits
+    //  starting on a word in the LDS copy; record L repeats record L - 1 so the next
+    //  record can always be loaded)
     uint32_t *d_vrec = nullptr;
     int32_t vrec_stride = 0;
     void *d_spec = nullptr;          // kernel spectra (dtype complex)
