@@ -112,7 +112,8 @@ void k_vote(
     // the row's end (lanes past the last candidate read 0), plus the lane's byte
     // offset; the descriptors come from scalar adds, not per-lane 64-bit addresses
     auto load_tile = [&](int64_t t) {
-        const int nrec = (int)min<int64_t>((n_total - t) * 8, (int64_t)0x7ffffff8);
+        // (t past the last candidate: an empty range, every lane reads 0)
+        const int nrec = (int)max<int64_t>(0, min<int64_t>((n_total - t) * 8, (int64_t)0x7ffffff8));
         const char *b = reinterpret_cast<const char *>(freq + t);
 #pragma unroll
         for (int u = 0; u < DM; ++u) {
@@ -148,7 +149,9 @@ void k_vote(
                 kp[j] = a0 | a1;
             }
         }
-        if (t0 + kVoteThreads < end) load_tile(t0 + kVoteThreads);
+        // the next tile's loads, issued unconditionally (past the range they read zeros) so
+        // that they can land in the registers of the coordinates used above, no copies
+        load_tile(t0 + kVoteThreads);
         const int64_t tend = min(end, t0 + kVoteThreads);
         int64_t seg = t0;
         while (seg < tend) {
