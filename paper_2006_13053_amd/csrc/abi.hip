@@ -258,8 +258,16 @@ static int build_vote_records(Plan &p, std::vector<uint32_t> &vr)
 {
     const int zw = p.dot2 ? (p.d + 1) / 2 : p.d;
     int rs = 4;
-    while (rs < zw + 5) rs <<= 1;
+    while (rs < zw + 4) rs <<= 1;
     p.vrec_stride = rs;
+    // the LDS copy: each lattice's bits from a word boundary, when every function fits
+    p.vote_lds_words = 0;
+    for (int f = 0; f < p.F; ++f) {
+        int64_t w = 0;
+        for (int l = 0; l < p.L; ++l) w += (p.lat[(size_t)f * p.L + l].M + 31) >> 5;
+        p.vote_lds_words = std::max(p.vote_lds_words, w);
+    }
+    p.vote_lds = p.vote_lds_words <= kVoteLdsWords;
     vr.assign((size_t)p.F * (p.L + 1) * rs, 0u);
     for (int f = 0; f < p.F; ++f) {
         const int64_t word0 = p.lat[(size_t)f * p.L].node_off >> 5;
@@ -272,12 +280,12 @@ static int build_vote_records(Plan &p, std::vector<uint32_t> &vr)
             r[0] = ld.off32;
             r[1] = (uint32_t)(-(int32_t)ld.M);
             std::memcpy(&r[2], &ld.inv_m, 4);
-            r[3] = (uint32_t)(ld.node_off - (word0 << 5));
-            r[4] = 4u * (l < p.L ? wbase : wbase - (uint32_t)((ld.M + 31) >> 5));
+            r[3] = p.vote_lds ? 4u * (l < p.L ? wbase : wbase - (uint32_t)((ld.M + 31) >> 5))
+                              : (uint32_t)(ld.node_off - (word0 << 5));
             for (int u = 0; u < p.d; ++u) {
                 const uint32_t zu = (uint32_t)p.z[i * p.d + u];
-                if (p.dot2) r[5 + u / 2] |= (zu & 0xffffu) << (16 * (u & 1));
-                else r[5 + u] = zu;
+                if (p.dot2) r[4 + u / 2] |= (zu & 0xffffu) << (16 * (u & 1));
+                else r[4 + u] = zu;
             }
             if (l < p.L) wbase += (uint32_t)((ld.M + 31) >> 5);
         }

@@ -56,7 +56,6 @@ __device__ __forceinline__ int func_of(const int64_t *set_off, int F, int64_t i)
 
 // ------------------------------------------------------------------ vote
 constexpr int kVoteThreads = 512;
-constexpr int kVoteLdsWords = 20480;          // 80 KiB: lattice records + bitmap, two or more workgroups per CU
 
 // Each workgroup owns a contiguous, tile-aligned range of the concatenated
 // candidate sets (one candidate per thread and tile).  When they fit, the
@@ -90,7 +89,7 @@ void k_vote(
     uint32_t *bits = lds;
     // In LDS each lattice's bits start on a word (re-aligned when the function's bitmap
     // is loaded), so bucket h of lattice l is bit h mod 32 of the word at byte
-    // base_l + 4 (h >> 5); base_l (record word 4) plus the bitmap's LDS base is a
+    // base_l + 4 (h >> 5); base_l (record word 3) plus the bitmap's LDS base is a
     // scalar sum, and the per-lane address needs one shift and one shift-add
     typedef __attribute__((address_space(3))) const uint32_t lds_u32;
     const uint32_t lds_byte0 = LDSB ? (uint32_t)(uintptr_t)(lds_u32 *)bits : 0u;
@@ -193,14 +192,14 @@ void k_vote(
                 // uniform records through the scalar cache (constant address space)
                 typedef const __attribute__((address_space(4))) uint32_t *crec_t;
                 const crec_t rp = (crec_t)(uintptr_t)(vrec + (int64_t)f * recw);
-                constexpr int RW = 5 + ZW;
+                constexpr int RW = 4 + ZW;
                 uint32_t ra[RW], rb[RW];
 #pragma unroll
-                for (int j = 0; j < RW; ++j) ra[j] = (j < 5 + zw) ? rp[j] : 0u;
+                for (int j = 0; j < RW; ++j) ra[j] = (j < 4 + zw) ? rp[j] : 0u;
                 // hash lattice l with record `cur` while record l + 1 is loaded into `nxt`
                 auto step = [&](const uint32_t (&r)[RW], uint32_t (&nxt)[RW], int l) {
 #pragma unroll
-                    for (int j = 0; j < RW; ++j) nxt[j] = (j < 5 + zw) ? rp[(l + 1) * rs + j] : 0u;
+                    for (int j = 0; j < RW; ++j) nxt[j] = (j < 4 + zw) ? rp[(l + 1) * rs + j] : 0u;
                     uint32_t s = r[0];
                     if constexpr (DOT2) {
                         typedef short v2s __attribute__((ext_vector_type(2)));
@@ -208,11 +207,11 @@ void k_vote(
                         for (int j = 0; j < ZW; ++j)
                             if (j < zw)
                                 s = (uint32_t)__builtin_amdgcn_sdot2(__builtin_bit_cast(v2s, kp[j]),
-                                                                     __builtin_bit_cast(v2s, r[5 + j]), (int)s, false);
+                                                                     __builtin_bit_cast(v2s, r[4 + j]), (int)s, false);
                     } else {
 #pragma unroll
                         for (int u = 0; u < DM; ++u)
-                            if (u < d) s += (uint32_t)__mul24(lo[u], (int32_t)r[5 + u]);
+                            if (u < d) s += (uint32_t)__mul24(lo[u], (int32_t)r[4 + u]);
                     }
                     // s < 2^32 and s / M < 2^20: the float quotient is exact or one too small
                     const int32_t negM = (int32_t)r[1];
@@ -221,7 +220,7 @@ void k_vote(
                     h = min(h, h + (uint32_t)negM);
                     uint32_t word, g;
                     if constexpr (LDSB) {
-                        const uint32_t wb = (uint32_t)__builtin_amdgcn_readfirstlane(r[4] + lds_byte0);
+                        const uint32_t wb = (uint32_t)__builtin_amdgcn_readfirstlane(r[3] + lds_byte0);
                         // the word index hidden from the optimiser, so that the address stays
                         // one shift-add instead of a shift, a mask and an add
                         uint32_t hw = h >> 5;
@@ -269,7 +268,7 @@ void k_vote(
                     uint32_t word;
                     int bit;
                     if constexpr (LDSB) {
-                        word = bits[(vrec[(int64_t)f * recw + l * rs + 4] >> 2) + (h >> 5)];
+                        word = bits[(vrec[(int64_t)f * recw + l * rs + 3] >> 2) + (h >> 5)];
                         bit = h & 31;
                     } else {
                         const int64_t g = ld.node_off + h;
@@ -332,16 +331,11 @@ int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *fr
 {
     // n_det is zero-filled by the caller (outside the timed vote stage)
     if (n_total <= 0) return MR1L_OK;
-    // LDS bitmap (each lattice's bits from a word boundary) when every function's fit
-    int64_t maxw = 0;
-    for (int f = 0; f < p.F; ++f) {
-        int64_t w = 0;
-        for (int l = 0; l < p.L; ++l) w += (p.lat[(size_t)f * p.L + l].M + 31) >> 5;
-        maxw = std::max<int64_t>(maxw, w);
-    }
+    // LDS bitmap copy (each lattice's bits from a word boundary) when every function's
+    // fits; the records were built for the same choice
     const int64_t bm_words = (p.nodes + 31) / 32;
-    const bool lds = maxw <= kVoteLdsWords;
-    const size_t shm = lds ? (size_t)maxw * 4 : 0;
+    const bool lds = p.vote_lds;
+    const size_t shm = lds ? (size_t)p.vote_lds_words * 4 : 0;
     int32_t kb_min = INT32_MAX;
     for (int32_t k : p.kb) kb_min = std::min(kb_min, k);
     const int64_t tiles = (n_total + kVoteThreads - 1) / kVoteThreads;

@@ -16,6 +16,9 @@ namespace mr1l {
 // detected lists longer than kMaxCap are sorted in global memory (one stream synchronisation)
 constexpr int64_t kMaxCapLarge = int64_t(1) << 24;
 
+// LDS words of the vote pass's bitmap copy at most (80 KiB: two or more workgroups per CU)
+constexpr int kVoteLdsWords = 20480;
+
 // Non-zero bitmap bits of a wave whose active lanes are a prefix of the wave holding
 // consecutive nodes (lane j: node g of lane 0 plus j, as in a loop i = tid, tid + NT, ...
 // with NT a multiple of 64): the bits are gathered by a ballot and each 32-bit word the
@@ -124,14 +127,15 @@ struct Plan {
     uint32_t *d_z16 = nullptr;       // [F*L][ceil(d/2)] z as packed int16 pairs (M <= 2^15)
     bool dot2 = false;               // every M <= 2^15: 16-bit packed dot products
     // vote records: per function L + 1 records of vrec_stride (a power of two >= 4) words
-    //   [off32, -M, inv_m bits, bit base, LDS byte base, z words (packed pairs when dot2,
-    //    else int32)...]
-    // (bit base = bit of bucket 0 relative to the function's first bitmap word; LDS byte
-    //  base = 4 x the words of the function's earlier lattices, each lattice's bits
-    //  starting on a word in the LDS copy; record L repeats record L - 1 so the next
-    //  record can always be loaded)
+    //   [off32, -M, inv_m bits, base, z words (packed pairs when dot2, else int32)...]
+    // base: with the LDS bitmap copy (vote_lds), the byte offset of the lattice's words,
+    // 4 x the words of the function's earlier lattices (each lattice's bits start on a
+    // word there); else the bit of bucket 0 relative to the function's first bitmap
+    // word.  Record L repeats record L - 1 so the next record can always be loaded.
     uint32_t *d_vrec = nullptr;
     int32_t vrec_stride = 0;
+    bool vote_lds = false;           // every function's bitmap fits the vote pass's LDS copy
+    int64_t vote_lds_words = 0;      // its words: max over functions of sum_l ceil(M_l / 32)
     void *d_spec = nullptr;          // kernel spectra (dtype complex)
     void *d_chirp = nullptr;         // chirp tables (dtype complex)
     void *d_tw = nullptr;            // twiddle tables (dtype complex)
