@@ -130,15 +130,20 @@ void k_vote(
     for (int64_t t0 = beg; t0 < end; t0 += kVoteThreads) {
         // this tile's candidate: within the fast bound of every function of the batch
         // (kb_min; beyond it the exact path decides), low words, packed pairs
+        // |k_u| <= kb_min for every u, in 32-bit operations (64-bit compares cost more):
+        // the high word is the sign of the low word (bad collects the differences) and
+        // lo_u + kb_min, unsigned, is at most 2 kb_min (big collects the largest)
         int32_t lo[DM];
-        bool fast = true;
+        uint32_t bad = 0u, big = 0u;
 #pragma unroll
         for (int u = 0; u < DM; ++u) {
             if (u < d) {
                 lo[u] = (int32_t)kn[u];
-                fast = fast & (kn[u] >= -kb_min) & (kn[u] <= kb_min);   // no short circuit
+                bad |= (uint32_t)(kn[u] >> 32) ^ (uint32_t)(lo[u] >> 31);
+                big = max(big, (uint32_t)lo[u] + (uint32_t)kb_min);
             }
         }
+        const bool fast = (bad == 0u) & (big <= 2u * (uint32_t)kb_min);
         uint32_t kp[ZW];
         if constexpr (DOT2) {
 #pragma unroll

@@ -550,6 +550,39 @@ def test_full_pass_dimensions_without_own_kernel(m, d):
     compare_pass(r, ro, go, p.theta, 1e-11, 40)
 
 
+def test_vote_exact_path_edge_coordinates(m):
+    """Candidates whose coordinates straddle the fast hash's bound wherever it lies
+    (2^k - 1, 2^k, 2^k + 1 for k = 8..40, both signs) and 64-bit values whose low word
+    alone would pass (2^32 + 5, -2^32 + 5): the vote pass's range test and its exact
+    64-bit path, against the oracle; part of the support sits on such candidates."""
+    say("vote exact path edges")
+    rng = np.random.default_rng(57)
+    d, L = 3, 7
+    small = synth.distinct_uniform_points(rng, 1500, d, -30, 30)
+    special = []
+    for k in range(8, 41):
+        for v in (2**k - 1, 2**k, 2**k + 1):
+            for sgn in (1, -1):
+                special.append([sgn * v, int(rng.integers(-5, 6)), int(rng.integers(-5, 6))])
+    for v in (2**32 + 5, -2**32 + 5, 2**31, -2**31, 2**45 + 3):
+        special.append([int(rng.integers(-5, 6)), v, int(rng.integers(-5, 6))])
+    special = np.unique(np.array(special, np.int64), axis=0).T
+    cand = np.concatenate([small, special], axis=1)
+    cand = np.unique(cand, axis=1)
+    n = cand.shape[1]
+    supp_idx = np.sort(np.concatenate([rng.choice(n, 12, replace=False),
+                                       np.flatnonzero(np.abs(cand).max(axis=0) > 2**20)[:8]]))
+    supp_idx = np.unique(supp_idx)
+    coef = rng.standard_normal(supp_idx.size) + 1j * rng.standard_normal(supp_idx.size)
+    M, z = synth.draw_lattices(rng, L, d, 300, 900)
+    f = oracle.sample(cand[:, supp_idx], coef, M, z)
+    p = synth.Problem(d, cand, supp_idx, coef, M, z, theta=1e-12, meta=dict(workload="edges"))
+    r, *_ = gpu_pass(m, p, f_np=f, s_cap=64, cap=4096)
+    go = oracle.dft(f, M)
+    ro = oracle.extract(cand, M, z, go, 1e-12, s_cap=64, cap=4096)
+    compare_pass(r, ro, go, 1e-12, 1e-11, 64)
+
+
 def test_vote_min_general_nu(m):
     say("vote_min")
     p = synth.small_config(6, mlo=40, mhi=90)
