@@ -148,9 +148,11 @@ void k_vote(
         if constexpr (DOT2) {
 #pragma unroll
             for (int j = 0; j < ZW; ++j) {
-                const uint32_t a0 = (2 * j < d) ? ((uint32_t)lo[2 * j] & 0xffffu) : 0u;
-                const uint32_t a1 = (2 * j + 1 < d) ? ((uint32_t)lo[2 * j + 1] << 16) : 0u;
-                kp[j] = a0 | a1;
+                // the low halves of a pair in one byte permute (bytes 0, 1 of the first,
+                // then bytes 0, 1 of the second); an odd last coordinate pairs with 0
+                const uint32_t a0 = (2 * j < d) ? (uint32_t)lo[2 * j] : 0u;
+                const uint32_t a1 = (2 * j + 1 < d) ? (uint32_t)lo[2 * j + 1] : 0u;
+                kp[j] = __builtin_amdgcn_perm(a1, a0, 0x05040100u);
             }
         }
         // the next tile's loads, issued unconditionally (past the range they read zeros) so
