@@ -92,36 +92,65 @@ static int64_t next_smooth(int64_t n)
 }
 
 // ---------------------------------------------------------------- tables (host, long double)
+// The tables of one size are the same in every plan, and their long-double evaluation
+// dominates plan creation (the driver creates a plan per step): each is computed once
+// per process and kept (entries are never removed, so references stay valid).
+template <typename V> struct TableCache {
+    std::mutex mu;
+    std::map<int64_t, V> map;
+    template <typename F> const V &get(int64_t key, F make)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = map.find(key);
+        if (it == map.end()) it = map.emplace(key, make()).first;
+        return it->second;
+    }
+};
+
 template <typename T>
 static void push_twiddles(std::vector<T> &tab, int64_t n)
 {
-    const long double tp = 6.283185307179586476925286766559005768L;
-    for (int64_t m = 0; m < n; ++m) {
-        long double a = -tp * (long double)m / (long double)n;
-        tab.push_back((T)cosl(a));
-        tab.push_back((T)sinl(a));
-    }
+    static TableCache<std::vector<T>> cache;
+    const std::vector<T> &v = cache.get(n, [n] {
+        std::vector<T> t;
+        t.reserve(2 * (size_t)n);
+        const long double tp = 6.283185307179586476925286766559005768L;
+        for (int64_t m = 0; m < n; ++m) {
+            long double a = -tp * (long double)m / (long double)n;
+            t.push_back((T)cosl(a));
+            t.push_back((T)sinl(a));
+        }
+        return t;
+    });
+    tab.insert(tab.end(), v.begin(), v.end());
 }
 
 // e^{-pi i r / M}: low part r < S, high part r = hi * S
 template <typename T>
 static void push_chirp(std::vector<T> &tab, int64_t M, int32_t &shift, int32_t &nlo)
 {
-    const long double pi = 3.141592653589793238462643383279502884L;
     shift = 0;
     while ((int64_t(1) << (2 * shift)) < 2 * M) ++shift;
     nlo = 1 << shift;
-    const int64_t nhi = (2 * M + nlo - 1) / nlo;
-    for (int64_t r = 0; r < nlo; ++r) {
-        long double a = -pi * (long double)r / (long double)M;
-        tab.push_back((T)cosl(a));
-        tab.push_back((T)sinl(a));
-    }
-    for (int64_t h = 0; h < nhi; ++h) {
-        long double a = -pi * (long double)(h * nlo) / (long double)M;
-        tab.push_back((T)cosl(a));
-        tab.push_back((T)sinl(a));
-    }
+    const int32_t S = nlo;
+    static TableCache<std::vector<T>> cache;
+    const std::vector<T> &v = cache.get(M, [M, S] {
+        std::vector<T> t;
+        const long double pi = 3.141592653589793238462643383279502884L;
+        const int64_t nhi = (2 * M + S - 1) / S;
+        for (int64_t r = 0; r < S; ++r) {
+            long double a = -pi * (long double)r / (long double)M;
+            t.push_back((T)cosl(a));
+            t.push_back((T)sinl(a));
+        }
+        for (int64_t h = 0; h < nhi; ++h) {
+            long double a = -pi * (long double)(h * S) / (long double)M;
+            t.push_back((T)cosl(a));
+            t.push_back((T)sinl(a));
+        }
+        return t;
+    });
+    tab.insert(tab.end(), v.begin(), v.end());
 }
 
 // float reciprocal of M rounded down by at least 2^-21 relative

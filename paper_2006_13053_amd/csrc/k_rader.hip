@@ -10,6 +10,8 @@
 // passes the values move through one LDS plane (P reals), real and imaginary
 // parts in turn.  Nothing goes through global scratch.
 #include <complex>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "mr1l_internal.h"
@@ -452,7 +454,44 @@ static void dft_ld(std::vector<std::complex<long double>> &x)
 // Appends the tables of size M: permutations (itab) and twiddles and spectrum
 // (ctab, interleaved re/im of T).
 template <typename T>
+static int rader_tables_compute(int64_t M, RaderDesc &rd, std::vector<int32_t> &itab, std::vector<T> &ctab);
+
+// The tables of one size, computed once per process (the recursive long-double DFT
+// of the kernel takes tens of milliseconds at M = 16001) and appended to the plan's.
+template <typename T>
 int rader_tables(int64_t M, RaderDesc &rd, std::vector<int32_t> &itab, std::vector<T> &ctab)
+{
+    struct Entry {
+        RaderDesc rd;
+        std::vector<int32_t> itab;
+        std::vector<T> ctab;
+    };
+    static std::mutex mu;
+    static std::map<int64_t, Entry> cache;
+    const Entry *e;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(M);
+        if (it == cache.end()) {
+            Entry n;
+            rader_tables_compute<T>(M, n.rd, n.itab, n.ctab);
+            it = cache.emplace(M, std::move(n)).first;
+        }
+        e = &it->second;
+    }
+    rd = e->rd;
+    const int64_t ioff = (int64_t)itab.size(), coff = (int64_t)ctab.size() / 2;
+    rd.perm_in += ioff;
+    rd.perm_out += ioff;
+    rd.tw += coff;
+    rd.spec += coff;
+    itab.insert(itab.end(), e->itab.begin(), e->itab.end());
+    ctab.insert(ctab.end(), e->ctab.begin(), e->ctab.end());
+    return MR1L_OK;
+}
+
+template <typename T>
+static int rader_tables_compute(int64_t M, RaderDesc &rd, std::vector<int32_t> &itab, std::vector<T> &ctab)
 {
     const int64_t P = M - 1;
     const std::vector<int> rad = rader_radices(P);
