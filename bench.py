@@ -701,8 +701,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); the method's "
-                          "multi-GPU sharding is described in DESIGN.md but not built"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1): the library "
+                          "has no multi-GPU path (sharding by candidates or by functions is not built)"}))
         sys.exit(2)
 
     import torch
