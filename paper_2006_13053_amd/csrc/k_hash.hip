@@ -162,8 +162,18 @@ void k_vote(
         int64_t seg = t0;
         while (seg < tend) {
             if (!(seg >= f_lo && seg < f_hi)) {
+                // the workgroup walks its range in order: past the first lookup, the next
+                // function is f + 1 (or a later one when sets are empty), one scalar load
+                // instead of a binary search, which made many small functions expensive
+                int fn;
+                if (f_hi > 0 && seg >= f_hi) {
+                    fn = f + 1;
+                    while (fn + 1 < F && set_off[fn + 1] <= seg) ++fn;
+                } else {
+                    fn = func_of(set_off, F, seg);
+                }
                 // every lane searches the same offsets, so f is uniform
-                f = __builtin_amdgcn_readfirstlane(func_of(set_off, F, seg));
+                f = __builtin_amdgcn_readfirstlane(fn);
                 f_lo = set_off[f];
                 f_hi = set_off[f + 1];
                 const LatDesc l0 = lat[f * L];
