@@ -24,6 +24,7 @@
 namespace mr1l {
 
 constexpr int kSortThreads = 1024;
+constexpr int64_t kTailBlocks = 4;   // workgroups per function of the per-entry tail kernels
 
 __device__ __forceinline__ int64_t n_of(const int64_t *n_det, int f, int64_t cap)
 {
@@ -72,10 +73,10 @@ __global__ __launch_bounds__(256) void k_det_hash(
     const int64_t *__restrict__ det_idx, int32_t *__restrict__ det_hash)
 {
     const int f = blockIdx.y;
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nl = n_of(n_det, f, cap) * L;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nl; t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q = t / L;
     const int l = (int)(t - q * L);
-    if (q >= n_of(n_det, f, cap)) return;
     const int64_t ci = set_off[f] + det_idx[(int64_t)f * cap + q];
     const int32_t kb = kbound[f];
     const LatDesc ld = lat[f * L + l];
@@ -89,6 +90,7 @@ __global__ __launch_bounds__(256) void k_det_hash(
     const int32_t h = fast ? (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m)
                            : exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
     det_hash[((int64_t)f * cap + q) * L + l] = h;
+    }
 }
 
 // ------------------------------------------------------------------ singletons
@@ -302,8 +304,8 @@ __global__ __launch_bounds__(256) void k_combine(
 {
     using V = typename cvec<T>::type;
     const int f = blockIdx.y;
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= n_of(n_det, f, cap)) return;
+    const int64_t n = n_of(n_det, f, cap);
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = (int64_t)f * cap + q;
     T vr[LMAX], vi[LMAX];
     const T inf = __builtin_inf();
@@ -325,6 +327,7 @@ __global__ __launch_bounds__(256) void k_combine(
     for (int l = 0; l < LMAX; ++l)
         if (l < L && ((mk >> l) & 1ull)) { sr += vr[l]; si += vi[l]; }
     combine_store<T>(L, e, mk, mr, mi, sr, si, r0, r1, i0, i1, postproc, det_coef, det_med, det_w);
+    }
 }
 
 // 41..64 lattices: each lane keeps its values in its own column of an LDS array
@@ -341,8 +344,8 @@ __global__ __launch_bounds__(64) void k_combine_wide(
     using V = typename cvec<T>::type;
     __shared__ T cr[kMaxL][64], ci[kMaxL][64];
     const int f = blockIdx.y, t = threadIdx.x;
-    const int64_t q = blockIdx.x * (int64_t)64 + t;
-    if (q >= n_of(n_det, f, cap)) return;
+    const int64_t n = n_of(n_det, f, cap);
+    for (int64_t q = blockIdx.x * (int64_t)64 + t; q < n; q += (int64_t)gridDim.x * 64) {
     const int64_t e = (int64_t)f * cap + q;
     for (int l = 0; l < L; ++l) {
         const V g = ghat[lat[f * L + l].node_off + det_hash[e * L + l]];
@@ -371,6 +374,7 @@ __global__ __launch_bounds__(64) void k_combine_wide(
     for (int l = 0; l < L; ++l)
         if ((mk >> l) & 1ull) { sr += cr[l][t]; si += ci[l][t]; }
     combine_store<T>(L, e, mk, mr, mi, sr, si, r0, r1, i0, i1, postproc, det_coef, det_med, det_w);
+    }
 }
 
 // ------------------------------------------------------------------ limit (Algorithm 4)
@@ -696,7 +700,10 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, int64_t nm
                           double *det_w)
 {
     using V = typename cvec<T>::type;
-    dim3 grid((unsigned)((nmax + 255) / 256), (unsigned)p.F), blk(256);
+    // a few workgroups per function (the kernels loop): most functions' lists are far
+    // shorter than the capacity, and launching a workgroup per 256 entries of it cost
+    // more than the work
+    dim3 grid((unsigned)std::min<int64_t>((nmax + 255) / 256, kTailBlocks), (unsigned)p.F), blk(256);
 #define MR1L_COMB(LM)                                                                                       \
     hipLaunchKernelGGL((k_combine<T, LM>), grid, blk, 0, p.stream, p.d_lat, p.L, n_det, cap, det_hash, mask, \
                        (const V *)ghat, postproc, (V *)det_coef, (V *)det_med, det_w)
@@ -708,7 +715,8 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, int64_t nm
     else if (p.L <= 32) MR1L_COMB(32);
     else if (p.L <= 40) MR1L_COMB(40);
     else
-        hipLaunchKernelGGL(k_combine_wide<T>, dim3((unsigned)((nmax + 63) / 64), (unsigned)p.F), dim3(64), 0, p.stream,
+        hipLaunchKernelGGL(k_combine_wide<T>, dim3((unsigned)std::min<int64_t>((nmax + 63) / 64, 4 * kTailBlocks),
+                                                   (unsigned)p.F), dim3(64), 0, p.stream,
                            p.d_lat, p.L, n_det, cap, det_hash, mask, (const V *)ghat, postproc, (V *)det_coef,
                            (V *)det_med, det_w);
 #undef MR1L_COMB
@@ -846,7 +854,7 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
         }
     }
     if (nmax > 0) {
-        dim3 gq((unsigned)((nmax * p.L + 255) / 256), (unsigned)p.F);
+        dim3 gq((unsigned)std::min<int64_t>((nmax * p.L + 255) / 256, 4 * kTailBlocks), (unsigned)p.F);
         hipLaunchKernelGGL(k_det_hash, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat, p.d_z32,
                            p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
         MR1L_LAUNCH_CHECK();
