@@ -24,7 +24,17 @@
 namespace mr1l {
 
 constexpr int kSortThreads = 1024;
-constexpr int64_t kTailBlocks = 4;   // workgroups per function of the per-entry tail kernels
+constexpr int64_t kTailBlocks = 4;    // least workgroups per function of the per-entry tail kernels
+constexpr int64_t kTailGrid = 256;    // workgroups the whole grid of such a kernel aims at (one per CU)
+
+// Workgroups per function of a per-entry tail kernel whose lists need `need` workgroups at
+// most: the kernels loop over a function's entries, so a few per function suffice when there
+// are many functions, while a single long list still spreads over the whole chip
+static unsigned tail_blocks(int64_t need, int F, int64_t scale = 1)
+{
+    const int64_t per_f = std::max<int64_t>(kTailBlocks * scale, kTailGrid * scale / std::max(F, 1));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, per_f));
+}
 
 __device__ __forceinline__ int64_t n_of(const int64_t *n_det, int f, int64_t cap)
 {
@@ -700,10 +710,10 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, int64_t nm
                           double *det_w)
 {
     using V = typename cvec<T>::type;
-    // a few workgroups per function (the kernels loop): most functions' lists are far
-    // shorter than the capacity, and launching a workgroup per 256 entries of it cost
-    // more than the work
-    dim3 grid((unsigned)std::min<int64_t>((nmax + 255) / 256, kTailBlocks), (unsigned)p.F), blk(256);
+    // a bounded number of workgroups per function (the kernels loop): most functions' lists
+    // are far shorter than the capacity, and launching a workgroup per 256 entries of it
+    // cost more than the work
+    dim3 grid(tail_blocks((nmax + 255) / 256, p.F), (unsigned)p.F), blk(256);
 #define MR1L_COMB(LM)                                                                                       \
     hipLaunchKernelGGL((k_combine<T, LM>), grid, blk, 0, p.stream, p.d_lat, p.L, n_det, cap, det_hash, mask, \
                        (const V *)ghat, postproc, (V *)det_coef, (V *)det_med, det_w)
@@ -715,8 +725,7 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, int64_t nm
     else if (p.L <= 32) MR1L_COMB(32);
     else if (p.L <= 40) MR1L_COMB(40);
     else
-        hipLaunchKernelGGL(k_combine_wide<T>, dim3((unsigned)std::min<int64_t>((nmax + 63) / 64, 4 * kTailBlocks),
-                                                   (unsigned)p.F), dim3(64), 0, p.stream,
+        hipLaunchKernelGGL(k_combine_wide<T>, dim3(tail_blocks((nmax + 63) / 64, p.F, 4), (unsigned)p.F), dim3(64), 0, p.stream,
                            p.d_lat, p.L, n_det, cap, det_hash, mask, (const V *)ghat, postproc, (V *)det_coef,
                            (V *)det_med, det_w);
 #undef MR1L_COMB
@@ -854,7 +863,7 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
         }
     }
     if (nmax > 0) {
-        dim3 gq((unsigned)std::min<int64_t>((nmax * p.L + 255) / 256, 4 * kTailBlocks), (unsigned)p.F);
+        dim3 gq(tail_blocks((nmax * p.L + 255) / 256, p.F, 4), (unsigned)p.F);
         hipLaunchKernelGGL(k_det_hash, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat, p.d_z32,
                            p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
         MR1L_LAUNCH_CHECK();
