@@ -76,7 +76,7 @@ const char *mr1l_last_error(void);
 /*
  * Create a plan for F functions of d lattice dimensions with L lattices each
  * (the multiple rank-1 lattice configuration of Section 2.1); 1 <= d <= 64,
- * F >= 1, 1 <= L <= 64.
+ * 1 <= F <= 2^20, 1 <= L <= 64.
  *   M     host [F*L]   lattice sizes; each must be a prime (checked with a
  *                      deterministic Miller-Rabin test) with 2 <= M < 2^23.
  *   z     host [F*L*d] generating vectors, 0 <= z < M (checked).

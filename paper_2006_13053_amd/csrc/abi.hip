@@ -452,7 +452,8 @@ int mr1l::plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, cons
     if (!out) return fail(MR1L_E_ARG, "out is NULL");
     *out = nullptr;
     if (d < 1 || d > kMaxD) return fail(MR1L_E_ARG, "d must be in [1, 64]");
-    if (F < 1) return fail(MR1L_E_ARG, "F must be >= 1");
+    // F is a grid dimension of the per-function kernels and f * L an int index
+    if (F < 1 || F > (1 << 20)) return fail(MR1L_E_ARG, "F must be in [1, 2^20]");
     if (L < 1 || L > kMaxL) return fail(MR1L_E_ARG, "L must be in [1, 64]");
     if (dtype != MR1L_C128 && dtype != MR1L_C64) return fail(MR1L_E_ARG, "dtype must be MR1L_C128 or MR1L_C64");
     if (!M || !z) return fail(MR1L_E_ARG, "M or z is NULL");

@@ -972,3 +972,13 @@ def test_dimincr_full_size_matches_oracle_and_truth(m, step1):
     assert [tuple(x) for x in gf.tolist()] == [t[0] for t in truth]
     c_truth = np.array([t[1] for t in truth])
     assert np.linalg.norm(gc - c_truth) / np.linalg.norm(c_truth) < 1e-11
+
+
+@pytest.mark.parametrize("d,F,L", [(0, 1, 1), (65, 1, 1), (1, (1 << 20) + 1, 1), (1, 1, 65)])
+def test_plan_create_rejects_out_of_range_shapes(m, d, F, L):
+    """d, F and L beyond the documented ranges are argument errors (no plan, no launch)."""
+    say("plan shape bounds", d, F, L)
+    M = np.full(F * L, 7, np.int64)
+    z = np.zeros((F * L, max(d, 1)), np.int64)
+    with pytest.raises(m.Mr1lError):
+        m.Plan(d, M, z[:, :d] if d else np.zeros((F * L, 0), np.int64), F=F)
