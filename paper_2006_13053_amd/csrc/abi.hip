@@ -366,7 +366,7 @@ static int upload(Plan &p)
 static void release(Plan *p)
 {
     void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_vrec, p->d_spec, p->d_chirp, p->d_tw,
-                    p->d_fft_scratch, p->d_nodes_scratch, p->d_det_tmp,
+                    p->d_fft_scratch, p->d_nodes_scratch, p->d_cterm, p->d_thash, p->d_det_tmp,
                     p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
                     p->d_termoff_default, p->d_ls, p->d_gsort, p->d_single, p->d_dflag, p->d_bs_dims, p->d_rdesc,
                     p->d_ritab, p->d_rctab};
@@ -389,7 +389,7 @@ static int default_offsets(Plan &p, int64_t *dst, int64_t n)
     return MR1L_OK;
 }
 
-static int grow(Plan &p, void **ptr, int64_t bytes, int64_t &have)
+int grow_scratch(Plan &p, void **ptr, int64_t bytes, int64_t &have)
 {
     if (have >= bytes && *ptr) return MR1L_OK;
     if (p.capturing) return fail(MR1L_E_ARG, "scratch must be sized before graph capture (run the call once)");
@@ -399,6 +399,8 @@ static int grow(Plan &p, void **ptr, int64_t bytes, int64_t &have)
     have = bytes;
     return MR1L_OK;
 }
+
+static int grow(Plan &p, void **ptr, int64_t bytes, int64_t &have) { return grow_scratch(p, ptr, bytes, have); }
 
 // Schedules chosen by the autotuner in this process, per (dtype, M); later plans
 // start from them.

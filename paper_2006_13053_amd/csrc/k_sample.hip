@@ -287,41 +287,33 @@ static int sample_impl(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t
     return fft_run(p, p.d_nodes_scratch, f, 0.0, nullptr, FFT_INV, -1.0);   // times M
 }
 
-static int ensure(void **ptr, int64_t *have, int64_t want)
+static int resolve_mode(const Plan &p, int64_t n_terms, int32_t mode)
 {
-    if (*have >= want) return MR1L_OK;
-    if (*ptr) (void)hipFree(*ptr);
-    *ptr = nullptr;
-    *have = 0;
-    MR1L_HIP(hipMalloc(ptr, (size_t)std::max<int64_t>(want, 16)));
-    *have = want;
-    return MR1L_OK;
+    // direct when a function has few terms per node; buckets otherwise
+    if (mode == 0) mode = (n_terms / std::max(1, p.F) > 2048) ? 2 : 1;
+    return mode;
 }
 
-// term scratch shared by the plans used from one host thread (grown outside graph
-// capture only)
-static thread_local void *g_cterm = nullptr;
-static thread_local int64_t g_cterm_n = 0;
-static thread_local void *g_thash = nullptr;
-static thread_local int64_t g_thash_n = 0;
+int sample_run_with(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms, const int64_t *freq,
+                    const void *coef, const uint32_t *anchor, void *f, int32_t mode, void *cterm, int32_t *thash)
+{
+    mode = resolve_mode(p, n_terms, mode);
+    if (p.dtype == MR1L_C128)
+        return sample_impl<double>(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, cterm, thash);
+    return sample_impl<float>(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, cterm, thash);
+}
 
+// The term scratch (anchored coefficients and buckets) belongs to the plan and grows
+// with the largest call, outside graph capture only.
 int sample_run(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms, const int64_t *freq,
                const void *coef, const uint32_t *anchor, void *f, int32_t mode)
 {
     const int64_t esz = p.dtype == MR1L_C128 ? 16 : 8;
-    if (mode == 0) {
-        // direct when a function has few terms per node; buckets otherwise
-        mode = (n_terms / std::max(1, p.F) > 2048) ? 2 : 1;
-    }
-    int rc = ensure(&g_cterm, &g_cterm_n, std::max<int64_t>(1, n_terms) * esz);
+    int rc = grow_scratch(p, &p.d_cterm, std::max<int64_t>(1, n_terms) * esz, p.cterm_bytes);
     if (rc) return rc;
-    rc = ensure(&g_thash, &g_thash_n, std::max<int64_t>(1, n_terms) * 4 * p.L);
+    rc = grow_scratch(p, (void **)&p.d_thash, std::max<int64_t>(1, n_terms) * 4 * p.L, p.thash_bytes);
     if (rc) return rc;
-    if (p.dtype == MR1L_C128)
-        return sample_impl<double>(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, g_cterm,
-                                   (int32_t *)g_thash);
-    return sample_impl<float>(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, g_cterm,
-                              (int32_t *)g_thash);
+    return sample_run_with(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, p.d_cterm, p.d_thash);
 }
 
 }  // namespace mr1l

@@ -149,6 +149,10 @@ struct Plan {
     int64_t fft_slot_len = 0;
     int32_t fft_slots = 0;
     void *d_nodes_scratch = nullptr; // [nodes] complex (sampler, adjoint)
+    void *d_cterm = nullptr;         // sampler: [n_terms] anchored coefficients (complex)
+    int64_t cterm_bytes = 0;
+    int32_t *d_thash = nullptr;      // sampler: [L][n_terms] buckets of the terms
+    int64_t thash_bytes = 0;
     std::vector<RaderDesc> rdesc;    // per distinct size (P = 0 where Rader does not apply)
     RaderDesc *d_rdesc = nullptr;
     int32_t *d_ritab = nullptr;      // Rader permutations
@@ -222,6 +226,10 @@ int fail(int code, const std::string &msg);
 int launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 int launch_fill_bytes(void *p, int64_t nbytes, hipStream_t s);  // zero fill
 
+// Plan scratch of at least `bytes` bytes in *ptr (capacity in `have`): reallocated when
+// smaller, refused while the plan records a graph (a recorded kernel keeps the pointer).
+int grow_scratch(Plan &p, void **ptr, int64_t bytes, int64_t &have);
+
 int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap,
             int mode, double scale);
 int fft_prepare_spectra(Plan &p);
@@ -266,6 +274,10 @@ int sample_init_attrs();
 int sample_run(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms,
                const int64_t *freq, const void *coef, const uint32_t *anchor, void *f,
                int32_t mode);
+// The sampler with caller-provided term scratch: cterm [n_terms] complex, thash [L][n_terms].
+int sample_run_with(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms,
+                    const int64_t *freq, const void *coef, const uint32_t *anchor, void *f,
+                    int32_t mode, void *cterm, int32_t *thash);
 int adjoint_run(Plan &p, int64_t cap, int64_t s_cap, const int64_t *n_out,
                 const int32_t *out_pos, const int32_t *det_hash, const double *det_w,
                 const void *grad_out, void *grad_f);
