@@ -94,9 +94,12 @@ def setup_large(m, torch, F, n, seed=2026, distinct_m=False):
         c = sc.compressible_coefs(seed, f, g, table)
         dom = torch.from_numpy(sc.dominant_indices(seed, f, n, 1000)).to(dev)
         c[dom] = 10.0 * torch.from_numpy(sc.dominant_phases(seed, f, 1000)).to(dev)
-        pf = m.Plan(d, Ms[f * L:(f + 1) * L], zs[f])
-        m.mr1l_sample(pf, g, c, f=f_all[node_off[f]:node_off[f + 1]], mode=2)
-        plans.append(pf)
+        # sampled through a plan of its own, closed at once: its term scratch (10^7
+        # terms x 96 B) is not kept by the per-function plans of the plain loop
+        ps = m.Plan(d, Ms[f * L:(f + 1) * L], zs[f])
+        m.mr1l_sample(ps, g, c, f=f_all[node_off[f]:node_off[f + 1]], mode=2)
+        ps.close()
+        plans.append(m.Plan(d, Ms[f * L:(f + 1) * L], zs[f]))
         del c
         if f % 8 == 7:
             torch.cuda.synchronize()
@@ -111,44 +114,30 @@ def setup_large(m, torch, F, n, seed=2026, distinct_m=False):
 
 
 # ----------------------------------------------------------------------------- batch
-def setup_batch(m, torch, F, seed=2027, c64=False):
+def setup_batch(m, torch, F, seed=2027, c64=False, wl=None):
     import synth
-    import synth.counter as sc
-    d, L, box = 10, 8, 128
     dev = torch.device("cuda", 0)
     dtype = torch.complex64 if c64 else torch.complex128
-    rng = np.random.default_rng(seed)
-    s = np.rint(np.exp(rng.uniform(math.log(10), math.log(1000), F))).astype(np.int64)
-    n = np.rint(np.exp(rng.uniform(math.log(1e3), math.log(1e6), F))).astype(np.int64)
-    n = np.maximum(n, s)
-    Ms, zs, supp_idx = [], [], []
-    for f in range(F):
-        M, z = synth.draw_lattices(rng, L, d, 8 * int(s[f]), 16 * int(s[f]))
-        Ms.append(M)
-        zs.append(z)
-        supp_idx.append(np.sort(rng.choice(int(n[f]), size=int(s[f]), replace=False)))
-    Ms = np.concatenate(Ms)
-    zs = np.concatenate(zs)
-    off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
-    toff = np.concatenate([[0], np.cumsum(s)]).astype(np.int64)
+    wl = wl or synth.batch_workload(seed, F)
+    d, L = wl.d, wl.L
+    off, toff = wl.set_off, wl.term_off
     gam = torch.empty((d, int(off[-1])), dtype=torch.int64, device=dev)
-    per, supp, coef = [], [], []
+    per, supp = [], []
     for f in range(F):
-        g = sc.candidates(seed, f, d, int(n[f]), box, device=dev)
+        g = wl.candidates(f, device=dev)
         gam[:, off[f]:off[f + 1]] = g
         per.append(g)
-        supp.append(g[:, torch.from_numpy(supp_idx[f]).to(dev)])
-        coef.append(torch.from_numpy(rng.standard_normal(int(s[f])) + 1j * rng.standard_normal(int(s[f]))))
+        supp.append(g[:, torch.from_numpy(wl.supp_idx[f]).to(dev)])
     supp = torch.cat(supp, dim=1).contiguous()
-    coef = torch.cat(coef).to(dev).to(dtype)
-    plan = m.Plan(d, Ms, zs, F=F, dtype=dtype)
+    coef = torch.from_numpy(np.concatenate(wl.coef)).to(dev).to(dtype)
+    plan = m.Plan(d, wl.M, wl.z, F=F, dtype=dtype)
     f_all = m.mr1l_sample(plan, supp, coef, term_off=torch.from_numpy(toff).to(dev), mode=1)
-    plans = [m.Plan(d, Ms[f * L:(f + 1) * L], zs[f * L:(f + 1) * L], dtype=dtype) for f in range(F)]
-    node_off = np.concatenate([[0], np.cumsum([int(Ms[f * L:(f + 1) * L].sum()) for f in range(F)])])
+    plans = [m.Plan(d, wl.M[f * L:(f + 1) * L], wl.z[f * L:(f + 1) * L], dtype=dtype) for f in range(F)]
+    node_off = np.concatenate([[0], np.cumsum([int(wl.M[f * L:(f + 1) * L].sum()) for f in range(F)])])
     torch.cuda.synchronize()
-    return dict(d=d, L=L, F=F, n=n, gam=gam, per=per, f=f_all, plan=plan, plans=plans,
+    return dict(d=d, L=L, F=F, n=wl.n, gam=gam, per=per, f=f_all, plan=plan, plans=plans,
                 set_off=torch.from_numpy(off).to(dev), theta=1e-3 if c64 else 1e-12, cap=4096,
-                s_cap=2048, node_off=node_off, s=s, dtype=dtype)
+                s_cap=2048, node_off=node_off, s=wl.s, dtype=dtype, wl=wl)
 
 
 # ----------------------------------------------------------------------------- steps
@@ -161,7 +150,63 @@ def make_step(m, w):
     def step():
         m.mr1l_fft(plan, f, w["theta"], ghat=ghat, bitmap=bm)
         m.mr1l_extract(plan, gam, ghat, bm, w["theta"], s_cap=w["s_cap"], cap=w["cap"], set_off=so, out=ex)
-    return step, ex, ghat
+    return step, ex, ghat, bm
+
+
+def timed_steps(torch, runner, steps, stream=None):
+    """Run `steps` steps between two synchronisations -> (seconds, per-step ms from events
+    recorded on `stream` (torch's current stream when None))."""
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(steps):
+        runner()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return elapsed, [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+
+
+def graph_runner(m, torch, plan, step):
+    """Capture one step of `plan` into a HIP graph on a stream of its own -> (replay
+    function, stream)."""
+    s = torch.cuda.Stream()
+    plan.set_stream(s)
+    with torch.cuda.stream(s):
+        step()
+        s.synchronize()
+        graph = m.Graph(plan)
+        with graph:
+            step()
+        s.synchronize()
+
+    def run():
+        graph.launch(s)
+    run.graph = graph
+    return run, s
+
+
+def stage_rooflines(w, plan, stages, ex, n_total, dtype):
+    """Per-launch rooflines of the vote pass (8 d bytes per candidate + 8 per detection)
+    and of the DFT stage (2 w bytes per node, nominal 5 M log2 M flops per lattice) from
+    the stage times the library recorded on its stream."""
+    st = {k: (v[0] / v[1] if v[1] else None) for k, v in stages.items()}
+    vote_ms, fft_ms = st["vote"], st["fft"]
+    nd = ex["n_det"].cpu().numpy()
+    vbytes = 8.0 * w["d"] * n_total + 8.0 * float(np.minimum(nd, w["cap"]).sum())
+    wb = 16 if dtype == "c128" else 8
+    fbytes = 2.0 * wb * plan.nodes
+    flops = float(sum(5.0 * int(mm) * np.log2(int(mm)) for mm in plan.M))
+    fpeak = 78.6 if dtype == "c128" else 157.3
+    vote = {"bound": "hbm", "kernel": "k_vote (hash + vote + compaction)", "achieved": vbytes / (vote_ms * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": vbytes / (vote_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": vbytes, "vote_ms_per_launch": vote_ms}
+    fft = {"achieved": fbytes / (fft_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": fbytes / (fft_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms_per_launch": fft_ms,
+           "algorithmic_bytes_per_launch": fbytes, "nominal_flops_per_launch": flops,
+           "achieved_TFLOPs": flops / (fft_ms * 1e-3) / 1e12, "peak_TFLOPs": fpeak}
+    return st, vote, fft
 
 
 def plain_pass(m, torch, w, reps=2):
@@ -608,7 +653,7 @@ def copy_bandwidth(torch, nbytes=1 << 31):
     return 2.0 * nbytes / (best * 1e-3) / 1e9
 
 
-def cpu_baseline_large(w, n_sample, budget_s=10.0):
+def cpu_baseline_large(w, budget_s=10.0):
     """Oracle on one function of the batch, repeated until ~budget_s of CPU time: direct
     O(M^2) DFTs of its 20 lattices (on synthetic samples of the same size) and Algorithm 2
     + Remark 2.9 + Algorithm 4 over all of its candidates; value = candidates x lattices
@@ -640,29 +685,98 @@ def cpu_baseline_large(w, n_sample, budget_s=10.0):
         t_ex += t2 - t1
         reps += 1
     value = reps * n * L / (t_dft + t_ex)
-    sub = np.ascontiguousarray(cand_np[:, :n_sample])
-    ro_sub = oracle.extract(sub, Ms, z, g_exact, w["theta"], s_cap=w["s_cap"], cap=w["cap"])
     return dict(value=value, unit="candidates\u00b7lattices/s", cores=oracle.num_threads(), kind="oracle",
                 cpu_model=cpu_model(),
                 dft_s_per_rep=t_dft / reps, extract_s_per_rep=t_ex / reps,
                 sample=(f"function 0 of the batch, {reps} repetitions: direct O(M^2) DFTs of its {L} lattices "
                         f"({t_dft / reps:.2f}s each) + Algorithm 2/Remark 2.9/Algorithm 4 over all {n} "
-                        f"candidates ({t_ex / reps:.2f}s each)")), ro_sub, g_exact
+                        f"candidates ({t_ex / reps:.2f}s each)")), ro, g_exact
 
 
-def parity_large(m, torch, w, ex, ghat, ro, g_exact, n_sample):
-    """Function 0 of the batched pass vs the oracle on the candidate sample: detected
-    sets bit-exact, median coefficients (eq. (2.10), which depend on the candidate alone)
-    within 1e-11, and the lattice DFT values within 1e-11 of the bucket sums (eq. (2.4))."""
-    k = min(int(ex["n_det"][0]), w["cap"])
-    di = ex["det_idx"][0, :k].cpu().numpy()
-    dc = ex["det_med"][0, :k].cpu().numpy()
-    sel = di < n_sample
-    same = np.array_equal(di[sel], ro["det_idx"])
-    err = float(np.abs(dc[sel] - ro["det_med"]).max() / np.abs(ro["det_med"]).max()) if sel.any() else 0.0
-    gerr = float(np.abs(ghat[: w["nodes_f"]].cpu().numpy() - g_exact).max() / np.abs(g_exact).max())
-    return dict(sampled_candidates=n_sample, detected_in_sample=int(sel.sum()), detected_equal=bool(same),
-                coef_max_rel_err=err, ghat_max_rel_err=gerr, ok=bool(same and err <= 1e-11 and gerr <= 1e-11))
+def unpack_bitmap(words, nodes):
+    w = np.asarray(words).view(np.uint32)
+    bits = ((w[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).reshape(-1)
+    return bits[:nodes].astype(bool)
+
+
+def masks_u64(dm):
+    w = np.asarray(dm).view(np.uint32).astype(np.uint64)
+    return w if w.ndim == 1 else w[:, 0] | (w[:, 1] << np.uint64(32))
+
+
+def compare_function(r, ro, go, theta, eps, tol):
+    """One function's GPU pass (host arrays r) against the oracle's (ro) on the oracle's
+    lattice values go: lattice values within tol of the largest modulus, the non-zero
+    bitmap, detected count and indices and singleton masks bit-exact, median and
+    post-processed coefficients within tol, Algorithm 4's entries and order equal up to
+    moduli that tie within rounding.  Threshold decisions whose oracle modulus lies
+    within the rounding band of theta are counted and left out (expected: none)."""
+    res = {}
+    gs = max(1e-300, float(np.abs(go).max()))
+    res["ghat_rel_err"] = float(np.abs(r["ghat"] - go).max() / gs)
+    band = np.abs(np.abs(go) - theta) <= 256 * eps * gs
+    res["threshold_band"] = int(band.sum())
+    res["bitmap_equal"] = bool(np.array_equal(r["bitmap"][~band], ((go.real ** 2 + go.imag ** 2)
+                                                                   >= theta * theta)[~band]))
+    res["n_det"] = int(r["n_det"])
+    res["n_det_equal"] = res["n_det"] == int(ro["n_det"])
+    res["det_idx_equal"] = bool(np.array_equal(r["det_idx"], ro["det_idx"]))
+    res["det_mask_equal"] = bool(np.array_equal(r["det_mask"], ro["det_mask"]))
+    same = res["det_idx_equal"]
+    cs = max(1e-300, float(np.abs(ro["det_coef"]).max())) if ro["det_coef"].size else 1.0
+    ms = max(1e-300, float(np.abs(ro["det_med"]).max())) if ro["det_med"].size else 1.0
+    res["median_rel_err"] = float(np.abs(r["det_med"] - ro["det_med"]).max() / ms) if same and r["det_med"].size else 0.0
+    res["coef_rel_err"] = float(np.abs(r["det_coef"] - ro["det_coef"]).max() / cs) if same and r["det_coef"].size else 0.0
+    # Algorithm 4: same entries except ties at the smallest kept modulus, order by modulus
+    oi, oc, gi, gc = ro["out_idx"], ro["out_coef"], r["out_idx"], r["out_coef"]
+    lim_ok = gi.shape == oi.shape
+    out_err = 0.0
+    if lim_ok and oi.size:
+        sc = max(1e-300, float(np.abs(oc).max()))
+        delta = 256 * eps * sc
+        omag = dict(zip(oi.tolist(), np.abs(oc).tolist()))
+        mmin = float(np.abs(oc).min())
+        boundary = {i for i, mg in omag.items() if abs(mg - mmin) <= delta}
+        lim_ok = (set(oi.tolist()) - set(gi.tolist())) <= boundary
+        seq = [omag.get(i, mmin) for i in gi.tolist()]
+        lim_ok = lim_ok and all(seq[o] >= seq[o + 1] - delta for o in range(len(seq) - 1))
+        ocd = dict(zip(oi.tolist(), oc.tolist()))
+        out_err = max([abs(c - ocd[i]) / sc for i, c in zip(gi.tolist(), gc.tolist()) if i in ocd] or [0.0])
+    res["limit_equal_up_to_ties"] = bool(lim_ok)
+    res["out_coef_rel_err"] = float(out_err)
+    res["ok"] = bool(res["threshold_band"] == 0 and res["bitmap_equal"] and res["n_det_equal"] and same
+                     and res["det_mask_equal"] and res["ghat_rel_err"] <= tol and res["median_rel_err"] <= tol
+                     and res["coef_rel_err"] <= tol and lim_ok and out_err <= tol)
+    return res
+
+
+def gpu_function(ex, ghat, bits, nodes_off, fi, cap):
+    """Host copies of function fi's outputs of a batched pass (ghat and the unpacked
+    bitmap of its nodes [nodes_off[fi], nodes_off[fi + 1]))."""
+    a, b = int(nodes_off[fi]), int(nodes_off[fi + 1])
+    nd = int(ex["n_det"][fi])
+    k = min(nd, cap)
+    no = int(ex["n_out"][fi])
+    bits = bits[a:b]
+    return dict(n_det=nd, ghat=ghat[a:b], bitmap=bits, det_idx=ex["det_idx"][fi, :k],
+                det_mask=masks_u64(ex["det_mask"][fi, :k]), det_med=ex["det_med"][fi, :k],
+                det_coef=ex["det_coef"][fi, :k], out_idx=ex["out_idx"][fi, :no], out_coef=ex["out_coef"][fi, :no])
+
+
+def host_outputs(ex):
+    return {k: (v.cpu().numpy() if v is not None and hasattr(v, "cpu") else v) for k, v in ex.items()}
+
+
+def parity_large(m, torch, w, ex, ghat, bm, ro, g_exact):
+    """Function 0 of the batched pass against the oracle over all of its candidates."""
+    h = host_outputs(ex)
+    gh = ghat[: w["nodes_f"]].cpu().numpy()
+    bits = unpack_bitmap(bm[: (w["nodes_f"] + 31) // 32].cpu().numpy(), w["nodes_f"])
+    r = gpu_function(h, gh, bits, [0, w["nodes_f"]], 0, w["cap"])
+    res = compare_function(r, ro, g_exact, w["theta"], 2.0 ** -53, 1e-11)
+    res["function"] = 0
+    res["candidates"] = int(w["n"])
+    return res
 
 
 # ----------------------------------------------------------------------------- main
@@ -691,6 +805,11 @@ def main():
                     help="large workload with 20 distinct primes in [15500, 16500] per function instead of M = 16001")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-function loop")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="large workload: skip the batched-workload leg (512 functions, graph vs per-function loop, "
+                         "autograd)")
+    ap.add_argument("--no-distinct-m", action="store_true",
+                    help="large workload: skip the leg with 20 distinct lattice sizes per function")
     ap.add_argument("--graph", action="store_true", help="time a captured HIP graph of the step")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default DFT schedules instead of autotuning them before the timed steps")
@@ -738,50 +857,67 @@ def main():
                    functions=F, candidates_total=int(w["gam"].shape[1]), lattices=8, d=10)
         dtype = "c64" if args.c64 else "c128"
 
+    out = headline(m, torch, args, w, cfg, dtype, F)
+    if args.workload == "large":
+        if not args.no_cpu:
+            log("oracle leg (CPU) ...")
+            cpu, ro, g_exact = cpu_baseline_large(w)
+            out["cpu_baseline"] = cpu
+            out["parity"] = parity_large(m, torch, w, out.pop("_ex"), out.pop("_ghat"), out.pop("_bm"), ro, g_exact)
+            log(f"parity of function 0 (all {w['n']} candidates): {out['parity']['ok']}")
+        if not args.no_distinct_m and not args.distinct_m:
+            out["distinct_m"] = distinct_m_leg(m, torch, args, w)
+        for k in ("_ex", "_ghat", "_bm"):
+            out.pop(k, None)
+        w["plans"].clear()
+        w["per"].clear()
+        del w
+        torch.cuda.empty_cache()
+        if not args.no_batch:
+            out["batch"] = batch_leg(m, torch, args)
+    for k in ("_ex", "_ghat", "_bm"):
+        out.pop(k, None)
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = int(a.numel() * 8)
+    print(json.dumps(out), flush=True)
+
+
+def tune_schedules(w):
+    """Autotune the batched plan's DFT schedules; the per-function plans take the same."""
+    plan = w["plan"]
+    tune = plan.fft_tune(reps=3)
+    for pf in w["plans"]:
+        for M in np.unique(pf.M):
+            pf.fft_schedule(int(M), plan.fft_schedule(int(M)))
+    return tune
+
+
+def headline(m, torch, args, w, cfg, dtype, F):
+    """The timed steps of the chosen workload -> the JSON line's fields."""
     plan = w["plan"]
     tune = None
     if not args.no_tune:
-        tune = plan.fft_tune(reps=3)
+        tune = tune_schedules(w)
         log("DFT schedules (ms per batched DFT of each size's group): "
             + json.dumps({k: tune[k] for k in list(tune)[:4]}))
-        for pf in w["plans"]:   # the per-function loop runs the same schedules
-            for M in np.unique(pf.M):
-                pf.fft_schedule(int(M), plan.fft_schedule(int(M)))
     log("setup done; warming up")
-    step, ex, ghat = make_step(m, w)
+    step, ex, ghat, bm = make_step(m, w)
     n_total = int(w["gam"].shape[1])
     L = w["L"]
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    stream = None
     if args.graph:
-        s = torch.cuda.Stream()
-        plan.set_stream(s)
-        with torch.cuda.stream(s):
-            step()
-            s.synchronize()
-            graph = m.Graph(plan)
-            with graph:
-                step()
-            s.synchronize()
-
-            def run():
-                graph.launch(s)
-        runner = run
+        runner, stream = graph_runner(m, torch, plan, step)
     else:
         runner = step
-
     plan.profile(not args.graph)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    evs[0].record()
-    for i in range(args.steps):
-        runner()
-        evs[i + 1].record()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
+    elapsed, step_ms = timed_steps(torch, runner, args.steps, stream)
     stages = plan.profile_read() if not args.graph else {}
     plan.profile(False)
     ms_step = 1000.0 * elapsed / args.steps
@@ -799,11 +935,8 @@ def main():
     if tune is not None:
         out["fft_tune_ms"] = {str(k): v for k, v in list(tune.items())[:8]}
     if stages:
-        out["stages_ms"] = {k: (v[0] / v[1] if v[1] else None) for k, v in stages.items()}
-        vote_ms = out["stages_ms"]["vote"]
-        nd = ex["n_det"].cpu().numpy()
-        algo_bytes = 8.0 * w["d"] * n_total + 8.0 * float(np.minimum(nd, w["cap"]).sum())
-        achieved = algo_bytes / (vote_ms * 1e-3) / 1e9
+        st, vote, fft = stage_rooflines(w, plan, stages, ex, n_total, dtype)
+        out["stages_ms"] = st
         traffic = None
         if os.path.exists(PMC_FILE):
             with open(PMC_FILE) as fh:
@@ -811,20 +944,11 @@ def main():
             wl = args.workload + ("-distinct-m" if args.distinct_m else "")
             if pmc.get("source_hash") == vote_source_hash() and pmc.get("workload") == wl:
                 traffic = pmc.get("bytes_per_launch")
-        out["roofline"] = {"bound": "hbm", "kernel": "k_vote (hash + vote + compaction)", "achieved": achieved,
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": traffic, "algorithmic_bytes_per_launch": algo_bytes,
-                           "vote_ms_per_launch": vote_ms, "copy_GBps": copy_bandwidth(torch)}
-        fft_ms = out["stages_ms"]["fft"]
-        fft_bytes = 2.0 * 16 * plan.nodes if dtype == "c128" else 2.0 * 8 * plan.nodes
-        # the FLOP roof too, with the nominal 5 M log2 M operations of a length-M DFT
-        fft_flops = float(sum(5.0 * int(mm) * np.log2(int(mm)) for mm in plan.M))
-        flop_peak = 78.6 if dtype == "c128" else 157.3
-        out["fft_roofline"] = {"achieved": fft_bytes / (fft_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                               "unit": "GB/s", "algorithmic_bytes_per_launch": fft_bytes,
-                               "nominal_flops_per_launch": fft_flops,
-                               "achieved_TFLOPs": fft_flops / (fft_ms * 1e-3) / 1e12,
-                               "peak_TFLOPs": flop_peak}
+        vote["traffic"] = traffic
+        vote["copy_GBps"] = copy_bandwidth(torch)
+        out["roofline"] = {k: vote[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
+        out["roofline"].update({k: v for k, v in vote.items() if k not in out["roofline"]})
+        out["fft_roofline"] = fft
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
     if not args.no_plain:
         t_plain, _ = plain_pass(m, torch, w)
@@ -833,19 +957,170 @@ def main():
         out["plain_ms_per_pass"] = 1000.0 * t_plain
     if args.workload == "batch":
         out["autograd"] = autograd_timing(m, torch, w)
-    if not args.no_cpu and args.workload == "large":
-        n_sample = min(1_000_000, w["n"])
-        log("oracle leg (CPU) ...")
-        cpu, ro, g_exact = cpu_baseline_large(w, n_sample)
-        out["cpu_baseline"] = cpu
-        out["parity"] = parity_large(m, torch, w, ex, ghat, ro, g_exact, n_sample)
-    if args.copy_probe:
-        a = torch.ones(1 << 28, dtype=torch.int64, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        out["copy_probe_bytes"] = int(a.numel() * 8)
-    print(json.dumps(out), flush=True)
+    out["_ex"], out["_ghat"], out["_bm"] = ex, ghat, bm
+    return out
+
+
+def oracle_function(w, fi):
+    """The oracle's lattice values (eq. (2.4) bucket sums of the polynomial) and its
+    Algorithm 2 + Remark 2.9 + Algorithm 4 over every candidate of function fi of the
+    large workload."""
+    import oracle
+    import synth.counter as sc
+    import torch
+    d, n, seed = w["d"], w["n"], w["seed"]
+    Ms = np.ascontiguousarray(w["Ms"][fi])
+    z = w["zs"][fi]
+    cand = sc.candidates(seed, fi, d, n, w["box"], device="cpu")
+    coef = sc.compressible_coefs(seed, fi, cand, sc.phase_table("cpu"))
+    dom = torch.from_numpy(sc.dominant_indices(seed, fi, n, 1000))
+    coef[dom] = 10.0 * torch.from_numpy(sc.dominant_phases(seed, fi, 1000))
+    cand_np = np.ascontiguousarray(cand.numpy())
+    g_exact = oracle.bucket_sums(cand_np, coef.numpy(), Ms, z)
+    ro = oracle.extract(cand_np, Ms, z, g_exact, w["theta"], s_cap=w["s_cap"], cap=w["cap"])
+    return ro, g_exact
+
+
+def distinct_m_leg(m, torch, args, w):
+    """The large workload (same candidates and coefficients) with 20 distinct primes
+    uniform among the primes in [15500, 16500] per function: the DFT stage (every size
+    has its own tables), the whole step, and function 0 against the oracle."""
+    import synth
+    import synth.counter as sc
+    F, d, L, n, seed = w["F"], w["d"], w["L"], w["n"], w["seed"]
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(seed + 1)
+    pr = synth.primes_in(15500, 16500)
+    Ms = np.concatenate([rng.choice(pr, size=L, replace=False) for _ in range(F)]).astype(np.int64)
+    zs = np.stack([np.stack([rng.integers(0, Ms[f * L + l], size=d, dtype=np.int64) for l in range(L)])
+                   for f in range(F)])
+    node_off = np.concatenate([[0], np.cumsum(Ms.reshape(F, L).sum(axis=1))]).astype(np.int64)
+    f_all = torch.empty(int(node_off[-1]), dtype=torch.complex128, device=dev)
+    table = sc.phase_table(dev)
+    t0 = time.time()
+    for f in range(F):
+        c = sc.compressible_coefs(seed, f, w["per"][f], table)
+        dom = torch.from_numpy(sc.dominant_indices(seed, f, n, 1000)).to(dev)
+        c[dom] = 10.0 * torch.from_numpy(sc.dominant_phases(seed, f, 1000)).to(dev)
+        ps = m.Plan(d, Ms[f * L:(f + 1) * L], zs[f])
+        m.mr1l_sample(ps, w["per"][f], c, f=f_all[node_off[f]:node_off[f + 1]], mode=2)
+        ps.close()
+        del c
+    torch.cuda.synchronize()
+    log(f"distinct sizes: samples of {F} functions in {time.time() - t0:.1f}s")
+    plan = m.Plan(d, Ms, zs.reshape(-1), F=F)
+    w2 = dict(w, plan=plan, plans=[], f=f_all, Ms=Ms.reshape(F, L), zs=zs, nodes_f=int(node_off[1]))
+    res = {"workload": "the large workload with 20 distinct primes uniform in [15500, 16500] per function",
+           "distinct_sizes": int(np.unique(Ms).shape[0])}
+    if not args.no_tune:
+        tune_schedules(w2)
+    names = m.fft_schedule_names()
+    scheds = {}
+    for M in np.unique(Ms):
+        k = names[plan.fft_schedule(int(M))]
+        scheds[k] = scheds.get(k, 0) + 1
+    res["fft_schedules"] = scheds
+    step, ex, ghat, bm = make_step(m, w2)
+    for _ in range(args.warmup):
+        step()
+    plan.profile(True)
+    elapsed, step_ms = timed_steps(torch, step, args.steps)
+    stages = plan.profile_read()
+    plan.profile(False)
+    st, vote, fft = stage_rooflines(w2, plan, stages, ex, int(w["gam"].shape[1]), "c128")
+    res.update(ms_per_step=1000.0 * elapsed / args.steps, step_ms_median=float(np.median(step_ms)),
+               stages_ms=st, fft_roofline=fft, vote_roofline=vote)
+    log(f"distinct sizes: {res['ms_per_step']:.3f} ms/step, DFT {st['fft']:.3f} ms")
+    if not args.no_cpu:
+        ro, g_exact = oracle_function(w2, 0)
+        res["parity"] = parity_large(m, torch, w2, ex, ghat, bm, ro, g_exact)
+        log(f"distinct sizes: parity of function 0: {res['parity']['ok']}")
+    plan.close()
+    return res
+
+
+def batch_leg(m, torch, args):
+    """The batched workload (512 functions, complex128) as extra keys of the line:
+    functions/s of one pass replayed from a captured HIP graph, eagerly, and as the
+    per-function loop; autograd forward vs forward + backward; the vote and DFT
+    rooflines; every function against the oracle."""
+    F = 512
+    t0 = time.time()
+    w = setup_batch(m, torch, F)
+    log(f"batched workload: {F} functions, {int(w['gam'].shape[1])} candidates, set up in {time.time() - t0:.1f}s")
+    plan = w["plan"]
+    if not args.no_tune:
+        tune_schedules(w)
+    step, ex, ghat, bm = make_step(m, w)
+    n_total = int(w["gam"].shape[1])
+    steps = max(args.steps, 10)
+    for _ in range(args.warmup):
+        step()
+    plan.profile(True)
+    timed_steps(torch, step, steps)
+    stages = plan.profile_read()
+    plan.profile(False)
+    st, vote, fft = stage_rooflines(w, plan, stages, ex, n_total, "c128")
+    el_e, ms_e = timed_steps(torch, step, steps)
+    run, s = graph_runner(m, torch, plan, step)
+    for _ in range(args.warmup):
+        run()
+    el_g, ms_g = timed_steps(torch, run, steps, stream=s)
+    plan.set_stream(torch.cuda.current_stream())
+    t_plain, _ = plain_pass(m, torch, w)
+    res = {"workload": "batched: 512 functions, d=10, s log-uniform [10,1000], |I| log-uniform [1e3,1e6] from "
+                       "[-128,128]^10, L=8, M distinct primes in [8s,16s], noise-free, complex128, theta=1e-12",
+           "functions": F, "candidates": n_total, "nodes": int(plan.nodes),
+           "ms_per_pass_graph": 1000.0 * el_g / steps, "ms_per_pass_eager": 1000.0 * el_e / steps,
+           "ms_per_pass_plain": 1000.0 * t_plain,
+           "functions_per_s_graph": F * steps / el_g, "functions_per_s_eager": F * steps / el_e,
+           "functions_per_s_plain": F / t_plain,
+           "graph_over_plain": (F * steps / el_g) / (F / t_plain),
+           "stages_ms": st, "vote_roofline": vote, "fft_roofline": fft}
+    log(f"batched: graph {res['ms_per_pass_graph']:.3f} ms, eager {res['ms_per_pass_eager']:.3f} ms, "
+        f"per-function loop {res['ms_per_pass_plain']:.3f} ms per pass")
+    ag = autograd_timing(m, torch, w)
+    ag["functions_per_s_forward"] = F / (ag["forward_ms"] * 1e-3)
+    ag["functions_per_s_forward_backward"] = F / (ag["forward_backward_ms"] * 1e-3)
+    res["autograd"] = ag
+    if not args.no_cpu:
+        res["parity"] = parity_batch(w, ex, ghat, bm)
+        log(f"batched: parity over all {F} functions: {res['parity']['ok']}")
+    return res
+
+
+def parity_batch(w, ex, ghat, bm):
+    """Every function of the batched pass (here: the buffers the graph replays wrote)
+    against the oracle over all of its candidates, with the oracle's lattice values the
+    eq. (2.4) bucket sums of the function's support."""
+    import oracle
+    wl = w["wl"]
+    F, L = wl.F, wl.L
+    t0 = time.perf_counter()
+    cand = w["gam"].cpu().numpy()
+    h = host_outputs(ex)
+    gh = ghat.cpu().numpy()
+    bits = unpack_bitmap(bm.cpu().numpy(), int(gh.shape[0]))
+    node_off = np.concatenate([[0], np.cumsum(wl.M)]).astype(np.int64)[::L]
+    soff = wl.set_off
+    worst = {"ghat_rel_err": 0.0, "median_rel_err": 0.0, "coef_rel_err": 0.0, "out_coef_rel_err": 0.0}
+    bad, band, ndet = [], 0, 0
+    for fi in range(F):
+        Mf, zf = wl.M[fi * L:(fi + 1) * L], wl.z[fi * L:(fi + 1) * L]
+        cf = np.ascontiguousarray(cand[:, soff[fi]:soff[fi + 1]])
+        go = oracle.bucket_sums(np.ascontiguousarray(cf[:, wl.supp_idx[fi]]), wl.coef[fi], Mf, zf)
+        ro = oracle.extract(cf, Mf, zf, go, w["theta"], s_cap=w["s_cap"], cap=w["cap"])
+        r = gpu_function(h, gh, bits, node_off, fi, w["cap"])
+        c = compare_function(r, ro, go, w["theta"], 2.0 ** -53, 1e-11)
+        for k in worst:
+            worst[k] = max(worst[k], c[k])
+        band += c["threshold_band"]
+        ndet += c["n_det"]
+        if not c["ok"]:
+            bad.append(fi)
+    return dict(functions=F, candidates=int(cand.shape[1]), functions_equal=F - len(bad), failed=bad[:20],
+                detected=ndet, threshold_band=band, worst=worst, oracle_s=time.perf_counter() - t0,
+                ok=not bad and band == 0)
 
 
 if __name__ == "__main__":

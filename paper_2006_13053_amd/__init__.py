@@ -127,6 +127,40 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+class _PlanStream:
+    """Orders one library call with torch's current stream when the plan runs on another
+    stream: the plan's stream first waits for the work queued so far on the current
+    stream (which made the inputs), every tensor passed to ``keep`` is marked as used on
+    the plan's stream (so the caching allocator does not hand its memory out again
+    before the library has finished with it), and afterwards the current stream waits
+    for the plan's stream (which makes the outputs).  Nothing is done while the plan
+    records a graph, or when both streams are the same."""
+
+    def __init__(self, plan):
+        self.plan = plan
+        self.ps = None
+        self.held = []
+
+    def __enter__(self):
+        ps = self.plan._stream
+        cur = torch.cuda.current_stream()
+        if ps is not None and ps != cur and not self.plan._capturing:
+            ps.wait_stream(cur)
+            self.ps, self.cur = ps, cur
+        return self.keep
+
+    def keep(self, *ts):
+        if self.ps is not None:
+            self.held.extend(t for t in ts if isinstance(t, torch.Tensor) and t.is_cuda)
+
+    def __exit__(self, et, ev, tb):
+        if self.ps is not None:
+            for t in self.held:
+                t.record_stream(self.ps)
+            self.cur.wait_stream(self.ps)
+        return False
+
+
 def _ctype(dtype):
     if dtype == torch.complex128:
         return MR1L_C128
@@ -146,7 +180,9 @@ class Plan:
         z = np.ascontiguousarray(np.asarray(z, dtype=np.int64).reshape(F * L * d))
         self.d, self.F, self.L, self.dtype = int(d), int(F), int(L), dtype
         self.M = M.copy()
-        self._stream = stream
+        # the stream the library orders this plan's calls on
+        self._stream = torch.cuda.current_stream() if stream is None else stream
+        self._capturing = False
         h = _P()
         _check(lib().mr1l_plan_create(C.byref(h), self.d, self.F, self.L, M.ctypes.data_as(_P),
                                       z.ctypes.data_as(_P), _ctype(dtype), _stream_handle(stream)),
@@ -156,7 +192,7 @@ class Plan:
         self.offsets = np.concatenate([[0], np.cumsum(M)]).astype(np.int64)
 
     def set_stream(self, stream=None):
-        self._stream = stream
+        self._stream = torch.cuda.current_stream() if stream is None else stream
         _check(lib().mr1l_plan_set_stream(self.handle, _stream_handle(stream)), "mr1l_plan_set_stream")
 
     def set_z(self, z):
@@ -234,10 +270,12 @@ def mr1l_lsq(plan: Plan, ex: "Extracted", ghat, max_iter: int = 100, tol: float 
                n_out=torch.zeros(F, dtype=torch.int64, device=dev),
                out_idx=torch.zeros((F, s_cap), dtype=torch.int64, device=dev),
                out_coef=torch.zeros((F, s_cap), dtype=plan.dtype, device=dev))
-    _check(lib().mr1l_lsq(plan.handle, ex.cap, _ptr(ex["n_det"]), _ptr(ex["det_idx"]), _ptr(ex["det_hash"]),
-                          _ptr(ex["det_mask"]), _ptr(ghat), int(max_iter), float(tol), _ptr(coef),
-                          _ptr(out["resid"]), _ptr(out["iters"]), theta, s_cap, _ptr(out["n_out"]),
-                          _ptr(out["out_idx"]), _ptr(out["out_coef"])), "mr1l_lsq")
+    with _PlanStream(plan) as keep:
+        _check(lib().mr1l_lsq(plan.handle, ex.cap, _ptr(ex["n_det"]), _ptr(ex["det_idx"]), _ptr(ex["det_hash"]),
+                              _ptr(ex["det_mask"]), _ptr(ghat), int(max_iter), float(tol), _ptr(coef),
+                              _ptr(out["resid"]), _ptr(out["iters"]), theta, s_cap, _ptr(out["n_out"]),
+                              _ptr(out["out_idx"]), _ptr(out["out_coef"])), "mr1l_lsq")
+        keep(ghat, *out.values(), *[v for v in ex.values() if v is not None])
     return out
 
 
@@ -247,9 +285,11 @@ def mr1l_pfpn_count(plan: Plan, ex: "Extracted", n_active, counts=None):
     the singleton post-processing, flags."""
     if counts is None:
         counts = torch.empty((plan.F, 4), dtype=torch.int64, device=_dev())
-    _check(lib().mr1l_pfpn_count(plan.handle, ex.cap, _ptr(n_active), _ptr(ex["n_det"]), _ptr(ex["det_idx"]),
-                                 _ptr(ex["det_med"]), _ptr(ex["det_coef"]), float(ex.theta), _ptr(counts)),
-           "mr1l_pfpn_count")
+    with _PlanStream(plan) as keep:
+        _check(lib().mr1l_pfpn_count(plan.handle, ex.cap, _ptr(n_active), _ptr(ex["n_det"]), _ptr(ex["det_idx"]),
+                                     _ptr(ex["det_med"]), _ptr(ex["det_coef"]), float(ex.theta), _ptr(counts)),
+               "mr1l_pfpn_count")
+        keep(n_active, counts, ex["n_det"], ex["det_idx"], ex["det_med"], ex["det_coef"])
     return counts
 
 
@@ -271,8 +311,10 @@ def mr1l_sample(plan: Plan, freq, coef, f=None, term_off=None, anchor=None, mode
     n_terms = int(freq.shape[1])
     if f is None:
         f = torch.empty(plan.nodes, dtype=plan.dtype, device=_dev())
-    _check(lib().mr1l_sample(plan.handle, d_poly, _ptr(term_off), n_terms, _ptr(freq), _ptr(coef),
-                             _ptr(anchor), _ptr(f), int(mode)), "mr1l_sample")
+    with _PlanStream(plan) as keep:
+        _check(lib().mr1l_sample(plan.handle, d_poly, _ptr(term_off), n_terms, _ptr(freq), _ptr(coef),
+                                 _ptr(anchor), _ptr(f), int(mode)), "mr1l_sample")
+        keep(term_off, freq, coef, anchor, f)
     return f
 
 
@@ -287,8 +329,10 @@ def mr1l_sample_bspline(plan: Plan, d_poly: int, order, dims, anchor=None, f=Non
     dims = np.ascontiguousarray(dims.reshape(plan.F, order.shape[0]))
     if f is None:
         f = torch.empty(plan.nodes, dtype=plan.dtype, device=_dev())
-    _check(lib().mr1l_sample_bspline(plan.handle, int(d_poly), int(order.shape[0]), order.ctypes.data_as(_P),
-                                     dims.ctypes.data_as(_P), _ptr(anchor), _ptr(f)), "mr1l_sample_bspline")
+    with _PlanStream(plan) as keep:
+        _check(lib().mr1l_sample_bspline(plan.handle, int(d_poly), int(order.shape[0]), order.ctypes.data_as(_P),
+                                         dims.ctypes.data_as(_P), _ptr(anchor), _ptr(f)), "mr1l_sample_bspline")
+        keep(anchor, f)
     return f
 
 
@@ -298,7 +342,9 @@ def mr1l_fft(plan: Plan, f, theta: float, ghat=None, bitmap=None, want_bitmap: b
         ghat = torch.empty(plan.nodes, dtype=plan.dtype, device=_dev())
     if bitmap is None and want_bitmap:
         bitmap = torch.empty((plan.nodes + 31) // 32, dtype=torch.int32, device=_dev())
-    _check(lib().mr1l_fft(plan.handle, _ptr(f), _ptr(ghat), float(theta), _ptr(bitmap)), "mr1l_fft")
+    with _PlanStream(plan) as keep:
+        _check(lib().mr1l_fft(plan.handle, _ptr(f), _ptr(ghat), float(theta), _ptr(bitmap)), "mr1l_fft")
+        keep(f, ghat, bitmap)
     return ghat, bitmap
 
 
@@ -307,8 +353,10 @@ def mr1l_hash_count(plan: Plan, freq, set_off=None, want_hash: bool = True, want
     n = int(freq.shape[1])
     h = torch.empty((plan.L, n), dtype=torch.int32, device=_dev()) if want_hash else None
     c = torch.empty(plan.nodes, dtype=torch.int32, device=_dev()) if want_counts else None
-    _check(lib().mr1l_hash_count(plan.handle, n, _ptr(set_off), _ptr(freq), _ptr(h), _ptr(c)),
-           "mr1l_hash_count")
+    with _PlanStream(plan) as keep:
+        _check(lib().mr1l_hash_count(plan.handle, n, _ptr(set_off), _ptr(freq), _ptr(h), _ptr(c)),
+               "mr1l_hash_count")
+        keep(set_off, freq, h, c)
     return h, c
 
 
@@ -347,8 +395,10 @@ def mr1l_extract(plan: Plan, freq, ghat, bitmap, theta: float, s_cap: int, cap: 
         out = extract_buffers(plan, cap, s_cap, n, want_votes, want_w)
     o = ExtractOpts(float(theta), int(vote_min), int(bool(postproc)), int(s_cap), int(cap))
     x = ExtractOut(*[None if out.get(k) is None else out[k].data_ptr() for k, _ in ExtractOut._fields_])
-    _check(lib().mr1l_extract(plan.handle, n, _ptr(set_off), _ptr(freq), _ptr(ghat), _ptr(bitmap),
-                              C.byref(o), C.byref(x)), "mr1l_extract")
+    with _PlanStream(plan) as keep:
+        _check(lib().mr1l_extract(plan.handle, n, _ptr(set_off), _ptr(freq), _ptr(ghat), _ptr(bitmap),
+                                  C.byref(o), C.byref(x)), "mr1l_extract")
+        keep(set_off, freq, ghat, bitmap, *[v for v in out.values() if v is not None])
     out.theta, out.postproc = float(theta), bool(postproc)
     return out
 
@@ -358,9 +408,11 @@ def mr1l_adjoint(plan: Plan, ex: Extracted, grad_out, grad_f=None):
     if grad_f is None:
         grad_f = torch.empty(plan.nodes, dtype=plan.dtype, device=_dev())
     g = grad_out.contiguous().to(plan.dtype)
-    _check(lib().mr1l_adjoint(plan.handle, ex.cap, ex.s_cap, _ptr(ex["n_out"]), _ptr(ex["out_pos"]),
-                              _ptr(ex["det_hash"]), _ptr(ex["det_w"]), _ptr(g), _ptr(grad_f)),
-           "mr1l_adjoint")
+    with _PlanStream(plan) as keep:
+        _check(lib().mr1l_adjoint(plan.handle, ex.cap, ex.s_cap, _ptr(ex["n_out"]), _ptr(ex["out_pos"]),
+                                  _ptr(ex["det_hash"]), _ptr(ex["det_w"]), _ptr(g), _ptr(grad_f)),
+               "mr1l_adjoint")
+        keep(g, grad_f, ex["n_out"], ex["out_pos"], ex["det_hash"], ex["det_w"])
     return grad_f
 
 
@@ -372,10 +424,12 @@ class Graph:
 
     def __enter__(self):
         _check(lib().mr1l_graph_begin(self.plan.handle), "mr1l_graph_begin")
+        self.plan._capturing = True
         return self
 
     def __exit__(self, et, ev, tb):
         h = _P()
+        self.plan._capturing = False
         rc = lib().mr1l_graph_end(self.plan.handle, C.byref(h))
         if et is None:
             _check(rc, "mr1l_graph_end")

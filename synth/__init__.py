@@ -167,6 +167,60 @@ def batch_config(seed: int, nfunc=512, d=10, box=128, L=8, slo=10, shi=1000, nlo
     return probs
 
 
+@dataclass
+class BatchWorkload:
+    """The batched workload at full size: F functions, function f with s[f] support
+    terms among n[f] candidates (``candidates(f)``), L lattices of distinct primes in
+    [8 s, 16 s].  Candidates come from the counter generator (uniform in the box, no
+    de-duplication: two equal candidates in one set have probability < 1e-13)."""
+    seed: int
+    d: int
+    L: int
+    box: int
+    s: np.ndarray             # [F] support sizes
+    n: np.ndarray             # [F] candidate-set sizes
+    M: np.ndarray             # [F*L] lattice sizes
+    z: np.ndarray             # [F*L, d] generating vectors
+    supp_idx: list            # F arrays of support positions inside each candidate set
+    coef: list                # F complex128 coefficient arrays
+
+    @property
+    def F(self) -> int:
+        return int(self.s.shape[0])
+
+    @property
+    def set_off(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.n)]).astype(np.int64)
+
+    @property
+    def term_off(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.s)]).astype(np.int64)
+
+    def candidates(self, f: int, device="cpu"):
+        """Candidate set of function f, SoA int64 [d, n[f]] (a torch tensor)."""
+        return counter.candidates(self.seed, f, self.d, int(self.n[f]), self.box, device=device)
+
+
+def batch_workload(seed: int = 2027, F: int = 512, d: int = 10, L: int = 8, box: int = 128,
+                   slo: int = 10, shi: int = 1000, nlo: int = 1000, nhi: int = 1_000_000) -> BatchWorkload:
+    """Batched workload: F functions, s log-uniform in [10, 1000], |Gamma| log-uniform in
+    [1e3, 1e6] uniform in [-128, 128]^10, support at uniform random positions of the
+    set, L = 8 distinct primes uniform in [8 s, 16 s] with uniform generating vectors,
+    complex N(0,1) coefficients (noise-free)."""
+    rng = np.random.default_rng(seed)
+    s = np.rint(np.exp(rng.uniform(math.log(slo), math.log(shi), F))).astype(np.int64)
+    n = np.rint(np.exp(rng.uniform(math.log(nlo), math.log(nhi), F))).astype(np.int64)
+    n = np.maximum(n, s)
+    Ms, zs, supp_idx = [], [], []
+    for f in range(F):
+        M, z = draw_lattices(rng, L, d, 8 * int(s[f]), 16 * int(s[f]))
+        Ms.append(M)
+        zs.append(z)
+        supp_idx.append(np.sort(rng.choice(int(n[f]), size=int(s[f]), replace=False)))
+    coef = [rng.standard_normal(int(s[f])) + 1j * rng.standard_normal(int(s[f])) for f in range(F)]
+    return BatchWorkload(seed, d, L, box, s, n, np.concatenate(Ms), np.concatenate(zs), supp_idx, coef)
+
+
 def sparse_poly_box(seed: int, d=25, s=200, box=32):
     """Random sparse polynomial on [-N, N]^d: s distinct frequencies uniform in the box,
     complex N(0,1) coefficients (the dimension-incremental workload; the box is never

@@ -899,6 +899,61 @@ def test_graph_replay_matches_eager(m):
             assert torch.equal(ex["out_coef"], ref[0])
 
 
+def test_sample_graph_replay_keeps_its_scratch(m):
+    """A graph that recorded mr1l_sample on plan A replays the same samples after a
+    larger sample call on plan B on the same host thread and stream (each plan owns its
+    term scratch, so B's growth cannot free or overwrite what A's graph uses)."""
+    say("sample graph vs another plan's scratch")
+    pa, pb = synth.small_config(4), synth.mid_config(1)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        A = m.Plan(pa.d, pa.M, pa.z, stream=s)
+        B = m.Plan(pb.d, pb.M, pb.z, stream=s)
+        supp, coef = T(pa.supp), T(pa.coef)
+        fa = m.mr1l_sample(A, supp, coef, mode=1)          # sizes A's scratch
+        s.synchronize()
+        ref = fa.clone()
+        graph = m.Graph(A)
+        with graph:
+            m.mr1l_sample(A, supp, coef, f=fa, mode=1)
+        rng = np.random.default_rng(9)
+        big = T(pb.cand)                                    # 10^5 terms: 50x A's
+        bc = T(rng.standard_normal(pb.n) + 1j * rng.standard_normal(pb.n))
+        for mode in (1, 2):
+            fb = m.mr1l_sample(B, big, bc, mode=mode)
+            for rep in range(3):
+                fa.zero_()
+                s.synchronize()
+                graph.launch(s)
+                s.synchronize()
+                assert torch.equal(fa, ref), (mode, rep)
+        s.synchronize()
+    close(ref.cpu().numpy(), oracle.sample(pa.supp, pa.coef, pa.M, pa.z), 1e-11, "samples of A")
+    fo = oracle.sample_nodes(pb.cand, bc.cpu().numpy(), pb.z[0], int(pb.M[0]), np.arange(0, int(pb.M[0]), 97))
+    close(fb.cpu().numpy()[:int(pb.M[0])][::97], fo, 1e-11, "samples of B (bucket mode)")
+
+
+def test_calls_on_a_plan_stream_other_than_the_current_one(m):
+    """A plan bound to its own stream, called from torch's default stream: inputs made on
+    the current stream are ready before the library reads them, and the results equal
+    those of a plan on the current stream (the adjoint's temporary included)."""
+    say("plan stream vs current stream")
+    p = synth.mid_config(2)
+    s = torch.cuda.Stream()
+    P1 = m.Plan(p.d, p.M, p.z)
+    P2 = m.Plan(p.d, p.M, p.z, stream=s)
+    outs = []
+    for plan in (P1, P2):
+        f = m.mr1l_sample(plan, T(p.supp) * 1, T(p.coef) * 1)     # inputs made just now on the current stream
+        g, bm = m.mr1l_fft(plan, f, p.theta)
+        ex = m.mr1l_extract(plan, T(p.cand) + 0, g, bm, p.theta, s_cap=200, cap=4096)
+        gf = m.mr1l_adjoint(plan, ex, torch.ones((1, 200), dtype=torch.complex64, device=dev()) * 0.5)
+        outs.append((ex["out_idx"].cpu(), ex["out_coef"].cpu(), gf.cpu()))
+    assert torch.equal(outs[0][0], outs[1][0])
+    close(outs[1][1].numpy(), outs[0][1].numpy(), 1e-11, "coefficients")
+    close(outs[1][2].numpy(), outs[0][2].numpy(), 1e-11, "adjoint")
+
+
 # ------------------------------------------------------------------ driver
 @pytest.mark.parametrize("seed", [0, 1])
 def test_dimincr_matches_oracle_driver(m, seed):
