@@ -119,6 +119,9 @@ def _ptr(t):
         return None
     if not t.is_cuda:
         raise Mr1lError("device tensor expected")
+    if not t.is_contiguous():
+        # the library reads row-major arrays through a raw pointer
+        raise Mr1lError("contiguous (row-major) tensor expected")
     return C.c_void_p(t.data_ptr())
 
 

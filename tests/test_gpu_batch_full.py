@@ -42,7 +42,7 @@ def workload():
     for f in range(wl.F):
         cand_dev[:, off[f]:off[f + 1]] = wl.candidates(f, device=dev)
     cand = cand_dev.cpu().numpy()
-    supp = np.concatenate([cand[:, off[f] + wl.supp_idx[f]] for f in range(wl.F)], axis=1)
+    supp = np.ascontiguousarray(np.concatenate([cand[:, off[f] + wl.supp_idx[f]] for f in range(wl.F)], axis=1))
     yield wl, cand_dev, cand, supp
     del cand_dev
 

@@ -954,6 +954,22 @@ def test_calls_on_a_plan_stream_other_than_the_current_one(m):
     close(outs[1][2].numpy(), outs[0][2].numpy(), 1e-11, "adjoint")
 
 
+def test_non_contiguous_arguments_are_refused(m):
+    """The library reads row-major arrays through raw pointers: a transposed view (numpy
+    fancy indexing along the second axis returns one) is refused, not read in the wrong
+    order."""
+    say("non-contiguous arguments")
+    p = synth.small_config(0)
+    plan = m.Plan(p.d, p.M, p.z)
+    supp_f = torch.from_numpy(np.asfortranarray(p.supp)).to(dev())
+    assert not supp_f.is_contiguous()
+    with pytest.raises(m.Mr1lError):
+        m.mr1l_sample(plan, supp_f, T(p.coef))
+    f = m.mr1l_sample(plan, supp_f.contiguous(), T(p.coef))
+    torch.cuda.synchronize()
+    close(f.cpu().numpy(), oracle.sample(p.supp, p.coef, p.M, p.z), 1e-11, "samples")
+
+
 # ------------------------------------------------------------------ driver
 @pytest.mark.parametrize("seed", [0, 1])
 def test_dimincr_matches_oracle_driver(m, seed):
