@@ -127,6 +127,24 @@ int mr1l_sample(mr1l_plan p, int32_t d_poly, const int64_t *term_off,
                 const uint32_t *anchor, void *f, int32_t mode);
 
 /*
+ * mr1l_sample for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and results, but the term scratch (anchored
+ * coefficients and buckets, n_terms * (w + 4 L) bytes, w = 16 for complex128
+ * and 8 for complex64, plus up to 255 bytes of alignment) lives in a static
+ * 64 MiB array that the library holds on every device it runs on until the
+ * process ends.  The call allocates nothing and does not synchronise.
+ *   term_off is required (dev [F+1]), also when F == 1.
+ * Errors: MR1L_E_CAPACITY when the term scratch would exceed 64 MiB (nothing is
+ * launched), and the argument errors of mr1l_sample.
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (several streams or threads) race; order them.
+ */
+int mr1l_sample_noalloc(mr1l_plan p, int32_t d_poly, const int64_t *term_off,
+                        int64_t n_terms, const int64_t *freq, const void *coef,
+                        const uint32_t *anchor, void *f, int32_t mode);
+
+/*
  * Samples of a sum of tensor products of periodic B-splines, the kind of test
  * function of eq. (4.3) (Section 4.2.3):
  *   f(x) = sum_{j < n_prod} prod_{u in S_j} N_{m_j}(x_u),

@@ -65,6 +65,7 @@ SIGNATURES = {
     "mr1l_plan_set_stream": ([_P, _P], C.c_int),
     "mr1l_plan_set_z": ([_P, _P], C.c_int),
     "mr1l_sample": ([_P, _I32, _P, _I64, _P, _P, _P, _P, _I32], C.c_int),
+    "mr1l_sample_noalloc": ([_P, _I32, _P, _I64, _P, _P, _P, _P, _I32], C.c_int),
     "mr1l_fft": ([_P, _P, _P, _D, _P], C.c_int),
     "mr1l_hash_count": ([_P, _I64, _P, _P, _P, _P], C.c_int),
     "mr1l_extract": ([_P, _I64, _P, _P, _P, _P, C.POINTER(ExtractOpts), C.POINTER(ExtractOut)], C.c_int),
@@ -317,6 +318,20 @@ def mr1l_sample(plan: Plan, freq, coef, f=None, term_off=None, anchor=None, mode
     with _PlanStream(plan) as keep:
         _check(lib().mr1l_sample(plan.handle, d_poly, _ptr(term_off), n_terms, _ptr(freq), _ptr(coef),
                                  _ptr(anchor), _ptr(f), int(mode)), "mr1l_sample")
+        keep(term_off, freq, coef, anchor, f)
+    return f
+
+
+def mr1l_sample_noalloc(plan: Plan, freq, coef, f, term_off, anchor=None, mode: int = 0):
+    """mr1l_sample with the term scratch in the library's static array (no allocation in
+    the call; the caller passes every buffer, term_off included)."""
+    if f is None or term_off is None:
+        raise Mr1lError("f and term_off are required")
+    d_poly = int(freq.shape[0])
+    n_terms = int(freq.shape[1])
+    with _PlanStream(plan) as keep:
+        _check(lib().mr1l_sample_noalloc(plan.handle, d_poly, _ptr(term_off), n_terms, _ptr(freq), _ptr(coef),
+                                         _ptr(anchor), _ptr(f), int(mode)), "mr1l_sample_noalloc")
         keep(term_off, freq, coef, anchor, f)
     return f
 

@@ -492,6 +492,7 @@ int mr1l::plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, cons
     p->z.assign(z, z + nl * d);
     int rc = dtype == MR1L_C128 ? build_tables<double>(*p) : build_tables<float>(*p);
     if (rc == MR1L_OK) rc = upload(*p);
+    if (rc == MR1L_OK) rc = sample_static_scratch(&p->d_static_scratch);
     if (rc == MR1L_OK) rc = fft_prepare_spectra(*p);
     if (rc == MR1L_OK) rc = fft_apply_schedules(*p);
     if (rc != MR1L_OK) {
@@ -572,6 +573,21 @@ int mr1l_sample(mr1l_plan p, int32_t d_poly, const int64_t *term_off, int64_t n_
             if (m > (int64_t(1) << 22)) mode = 2;
     StageTimer tm(*p, MR1L_STAGE_SAMPLE);
     return sample_run(*p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode);
+}
+
+int mr1l_sample_noalloc(mr1l_plan p, int32_t d_poly, const int64_t *term_off, int64_t n_terms, const int64_t *freq,
+                        const void *coef, const uint32_t *anchor, void *f, int32_t mode)
+{
+    if (!p) return fail(MR1L_E_ARG, "plan is NULL");
+    if (d_poly < p->d || d_poly > kMaxD) return fail(MR1L_E_ARG, "d_poly must be in [d, 64]");
+    if (n_terms < 0 || (n_terms > 0 && (!freq || !coef)) || !f) return fail(MR1L_E_ARG, "null buffer");
+    if (d_poly > p->d && !anchor) return fail(MR1L_E_ARG, "anchors required when d_poly > d");
+    if (mode < 0 || mode > 2) return fail(MR1L_E_ARG, "mode must be 0, 1 or 2");
+    if (!term_off) return fail(MR1L_E_ARG, "term_off is required (dev [F+1])");
+    if (mode == 1)
+        for (auto m : p->M)
+            if (m > (int64_t(1) << 22)) mode = 2;
+    return sample_run_noalloc(*p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode);
 }
 
 int mr1l_fft(mr1l_plan p, const void *f, void *ghat, double theta, uint32_t *nz_bitmap)

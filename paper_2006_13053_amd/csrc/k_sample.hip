@@ -12,6 +12,9 @@
 //           one lattice's buckets fit, else by global atomics), then
 //           f_l[j] = sum_h B[h] e^{2 pi i j h / M} is an inverse lattice DFT
 //           (scaled by M).
+#include <mutex>
+#include <string>
+
 #include "mr1l_internal.h"
 
 namespace mr1l {
@@ -301,6 +304,53 @@ int sample_run_with(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_
     if (p.dtype == MR1L_C128)
         return sample_impl<double>(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, cterm, thash);
     return sample_impl<float>(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, cterm, thash);
+}
+
+// Term scratch of the allocation-free sampler: one array per device, held from the
+// library's load until the process ends.  Host code never uses the array's name as
+// an address (in host code it is a stand-in, not device memory): each device's
+// address comes from hipGetSymbolAddress, once per device, at plan creation.
+constexpr int64_t kStaticScratchBytes = int64_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+int sample_static_scratch(void **out)
+{
+    int dev = 0;
+    MR1L_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MR1L_E_ARG, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MR1L_E_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MR1L_OK;
+}
+
+// The sampler with its term scratch (anchored coefficients, then the buckets, each
+// from a 256-byte boundary) in the device's static array: no allocation.  Every call
+// on a device shares the array, so calls that overlap on one device race.
+int sample_run_noalloc(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms, const int64_t *freq,
+                       const void *coef, const uint32_t *anchor, void *f, int32_t mode)
+{
+    if (!p.d_static_scratch) return fail(MR1L_E_ARG, "the plan has no static scratch address");
+    const int64_t esz = p.dtype == MR1L_C128 ? 16 : 8;
+    const int64_t nt = std::max<int64_t>(1, n_terms);
+    const int64_t cbytes = (nt * esz + 255) / 256 * 256;
+    const int64_t need = cbytes + nt * 4 * (int64_t)p.L;
+    if (need > kStaticScratchBytes)
+        return fail(MR1L_E_CAPACITY, "n_terms too large for the static term scratch: needs " + std::to_string(need) +
+                                         " bytes, at most " + std::to_string(kStaticScratchBytes) + " (n_terms * (" +
+                                         std::to_string(esz) + " + 4 L) plus alignment)");
+    unsigned char *base = static_cast<unsigned char *>(p.d_static_scratch);
+    return sample_run_with(p, d_poly, term_off, n_terms, freq, coef, anchor, f, mode, base,
+                           reinterpret_cast<int32_t *>(base + cbytes));
 }
 
 // The term scratch (anchored coefficients and buckets) belongs to the plan and grows

@@ -153,6 +153,7 @@ struct Plan {
     int64_t cterm_bytes = 0;
     int32_t *d_thash = nullptr;      // sampler: [L][n_terms] buckets of the terms
     int64_t thash_bytes = 0;
+    void *d_static_scratch = nullptr; // this device's copy of the library's static term scratch
     std::vector<RaderDesc> rdesc;    // per distinct size (P = 0 where Rader does not apply)
     RaderDesc *d_rdesc = nullptr;
     int32_t *d_ritab = nullptr;      // Rader permutations
@@ -271,6 +272,10 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
                      int32_t *det_hash, double *det_w, uint32_t *det_mask, void *det_med,
                      int32_t *out_pos);
 int sample_init_attrs();
+// Address of the static term scratch on the current device (looked up once per device).
+int sample_static_scratch(void **out);
+int sample_run_noalloc(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms, const int64_t *freq,
+                       const void *coef, const uint32_t *anchor, void *f, int32_t mode);
 int sample_run(Plan &p, int32_t d_poly, const int64_t *term_off, int64_t n_terms,
                const int64_t *freq, const void *coef, const uint32_t *anchor, void *f,
                int32_t mode);
