@@ -221,6 +221,28 @@ static int build_tables(Plan &p)
         // table go to LDS when they fit their LDS tables
         const int64_t nch = md.chirp_nlo + (2 * M + md.chirp_nlo - 1) / md.chirp_nlo;
         mi.ltab = mi.Np <= kTabTw * kTabTw && nch <= kTabCh;
+        // reg: one register-resident transform pair of the power of two N >= 2M - 1
+        {
+            const int64_t nmax = sizeof(T) == 8 ? 16384 : 32768;
+            int64_t n = kRegMinN;
+            while (n < 2 * M - 1) n <<= 1;
+            if (n <= nmax) {
+                mi.Nr = (int32_t)n;
+                mi.spec_r = spec_len;
+                spec_len += n;
+                mi.tw_r = twoff(n);
+            }
+        }
+        // split (complex128, M too large for reg): K blocks of B <= kSplitLen / 2
+        if (!mi.Nr && sizeof(T) == 8 && M <= (int64_t)kSplitMaxK * (kSplitLen / 2)) {
+            const int64_t K = (M + kSplitLen / 2 - 1) / (kSplitLen / 2);
+            mi.Nq = kSplitLen;
+            mi.Kq = (int32_t)K;
+            mi.Bq = (int32_t)((M + K - 1) / K);
+            mi.spec_q = spec_len;
+            spec_len += (2 * K - 1) * kSplitLen;
+            mi.tw_q = twoff(kSplitLen);
+        }
         // Rader's algorithm in registers for prime M with M - 1 = 2^a 5^b
         RaderDesc rd{};
         if (rader_applies(M, sizeof(T))) {
@@ -229,9 +251,10 @@ static int build_tables(Plan &p)
         }
         mi.sched = tuned_schedule(p.dtype, M);
         if (mi.sched >= 0 && !fft_schedule_applies(mi, mi.sched)) mi.sched = -1;
-        // untuned: the whole-LDS transform where it fits, else Rader where it applies
-        // (faster than the four-step on such sizes), else the default four-step
-        if (mi.sched < 0) mi.sched = mi.Ns ? 0 : (mi.rader ? kRaderSched : kDefaultFourStep);
+        // untuned: Rader where it applies (half the transform length of Bluestein),
+        // else the register transforms, else the whole-LDS transform, else the four-step
+        if (mi.sched < 0)
+            mi.sched = mi.rader ? kRaderSched : mi.Nr ? kRegSched : mi.Nq ? kSplitSched : mi.Ns ? 0 : kDefaultFourStep;
         p.mdesc.push_back(md);
         p.minfo.push_back(mi);
         p.rdesc.push_back(rd);
@@ -374,6 +397,10 @@ static void release(Plan *p)
         if (q) (void)hipFree(q);
     for (FftGroup &g : p->fft_groups)
         if (g.d_lats) (void)hipFree(g.d_lats);
+    for (auto &st : p->fft_aux)
+        if (st) (void)hipStreamDestroy(st);
+    for (auto &ev : p->fft_ev)
+        if (ev) (void)hipEventDestroy(ev);
     delete p;
 }
 
@@ -493,6 +520,12 @@ int mr1l::plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, cons
     int rc = dtype == MR1L_C128 ? build_tables<double>(*p) : build_tables<float>(*p);
     if (rc == MR1L_OK) rc = upload(*p);
     if (rc == MR1L_OK) rc = sample_static_scratch(&p->d_static_scratch);
+    for (int i = 0; rc == MR1L_OK && i < Plan::kFftAux; ++i)
+        if (hipStreamCreateWithFlags(&p->fft_aux[i], hipStreamNonBlocking) != hipSuccess)
+            rc = fail(MR1L_E_HIP, "DFT stream creation failed");
+    for (int i = 0; rc == MR1L_OK && i <= Plan::kFftAux; ++i)
+        if (hipEventCreateWithFlags(&p->fft_ev[i], hipEventDisableTiming) != hipSuccess)
+            rc = fail(MR1L_E_HIP, "DFT event creation failed");
     if (rc == MR1L_OK) rc = fft_prepare_spectra(*p);
     if (rc == MR1L_OK) rc = fft_apply_schedules(*p);
     if (rc != MR1L_OK) {
@@ -814,8 +847,10 @@ int mr1l_plan_fft_schedule(mr1l_plan p, int64_t M, int32_t sched)
     if (sched < 0) return p->minfo[mid].sched;
     if (sched >= kNumSched) return fail(MR1L_E_ARG, "unknown DFT schedule");
     if (!fft_schedule_applies(p->minfo[mid], sched))
-        return fail(MR1L_E_ARG, kSched[sched].rader ? "the Rader schedule needs a prime M with M - 1 = 2^a 5^b"
-                                                    : "this lattice size does not fit one workgroup's LDS");
+        return fail(MR1L_E_ARG, kSched[sched].rader         ? "the Rader schedule needs a prime M with M - 1 = 2^a 5^b"
+                                : kSched[sched].engine == 1 ? "the reg schedule needs 2M - 1 <= 16384 (complex128) or 32768"
+                                : kSched[sched].engine == 2 ? "the split schedule needs complex128 and 8192 < M <= 32768"
+                                                            : "this lattice size does not fit one workgroup's LDS");
     p->minfo[mid].sched = sched;
     const int rc = fft_apply_schedules(*p);
     return rc ? rc : sched;
@@ -849,7 +884,8 @@ int mr1l_fft_tune(mr1l_plan p, int32_t reps, int32_t max_sizes, int64_t *sizes, 
     std::map<std::pair<int, int32_t>, std::vector<int>> gmap;
     for (size_t mid = 0; mid < p->minfo.size(); ++mid) {
         const MInfo &mi = p->minfo[mid];
-        gmap[{(mi.Ns ? lds_class(mi.Ns) : kLdsClasses) + (mi.rader ? 16 : 0), mi.Np}].push_back((int)mid);
+        gmap[{(mi.Ns ? lds_class(mi.Ns) : kLdsClasses) + (mi.rader ? 16 : 0) + (mi.Nq ? 64 * mi.Kq : 0), mi.Np}]
+            .push_back((int)mid);
         if (sizes) sizes[mid] = mi.M;
     }
     std::vector<std::pair<int64_t, std::vector<int>>> groups;   // (lattice count, sizes)

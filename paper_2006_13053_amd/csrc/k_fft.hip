@@ -20,6 +20,7 @@
 // global scratch slot (it stays in L2/MALL) and the chirp and spectrum
 // products fused into the column load and the row store.
 #include <algorithm>
+#include <cmath>
 #include <initializer_list>
 #include <map>
 
@@ -732,16 +733,18 @@ __global__ __launch_bounds__(NT, WAVES) void k_bluestein_4step(
 
 // ------------------------------------------------------------------ host side
 const FftSched kSched[kNumSched] = {
-    {"lds", 0, kFftThreads, 0, 1, 0, 0},
-    {"4step-512x2-ceil", 1, 512, 12, 2, 0, 0},
-    {"4step-512x2-floor", 1, 512, 12, 2, 1, 0},
-    {"4step-512x1-ceil", 1, 512, 13, 1, 0, 0},
-    {"4step-512x1-floor", 1, 512, 13, 1, 1, 0},
-    {"4step-1024x1-ceil", 1, 1024, 13, 1, 0, 0},
-    {"4step-1024x1-floor", 1, 1024, 13, 1, 1, 0},
-    {"4step-256x2-ceil", 1, 256, 12, 2, 0, 0},
-    {"4step-256x2-floor", 1, 256, 12, 2, 1, 0},
-    {"rader-20", 0, 1024, 0, 1, 0, 1},
+    {"lds", 0, kFftThreads, 0, 1, 0, 0, 0},
+    {"4step-512x2-ceil", 1, 512, 12, 2, 0, 0, 0},
+    {"4step-512x2-floor", 1, 512, 12, 2, 1, 0, 0},
+    {"4step-512x1-ceil", 1, 512, 13, 1, 0, 0, 0},
+    {"4step-512x1-floor", 1, 512, 13, 1, 1, 0, 0},
+    {"4step-1024x1-ceil", 1, 1024, 13, 1, 0, 0, 0},
+    {"4step-1024x1-floor", 1, 1024, 13, 1, 1, 0, 0},
+    {"4step-256x2-ceil", 1, 256, 12, 2, 0, 0, 0},
+    {"4step-256x2-floor", 1, 256, 12, 2, 1, 0, 0},
+    {"rader-20", 0, 1024, 0, 1, 0, 1, 0},
+    {"reg", 0, 0, 0, 1, 0, 0, 1},
+    {"split", 0, kSplitLen / 16, 0, 1, 0, 0, 2},
 };
 
 template <typename T, int LOGP, bool LTAB>
@@ -811,6 +814,12 @@ static int launch_sched(Plan &p, int s, int cls, const int32_t *d_lats, int nl, 
                     : launch4<T, false, 256, LS, 2>(p, d_lats, nl, d_md, in, out, th2, bitmap, mode, sc, by_m, pc);
     case 9:
         return rader_launch(p, cls, d_lats, nl, in, out, theta, bitmap, mode, scale, by_m);   // cls = M - 1
+    case 10:   // cls = transform length
+        return sizeof(T) == 8 ? reg_launch_d(p, cls, d_lats, nl, d_md, in, out, theta, bitmap, mode, scale, by_m)
+                              : reg_launch_f(p, cls, d_lats, nl, d_md, in, out, theta, bitmap, mode, scale, by_m);
+    case 11:
+        if (sizeof(T) != 8) return fail(MR1L_E_ARG, "the split DFT schedule is complex128 only");
+        return split_launch_d(p, cls, d_lats, nl, d_md, in, out, theta, bitmap, mode, scale, by_m);   // cls = K
     default:
         return fail(MR1L_E_ARG, "unknown DFT schedule");
     }
@@ -858,18 +867,57 @@ int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap, 
         int rc = launch_fill_u32(bitmap, (p.nodes + 31) / 32, 0u, p.stream);
         if (rc) return rc;
     }
-    for (const FftGroup &g : p.fft_groups) {
+    // Groups that use the scratch slots (four-step, split) run in turn on the plan's
+    // stream, the largest first; the others are spread over the auxiliary streams
+    // (forked from the plan's stream after the bitmap fill, joined back at the end),
+    // so that the tail of one group's launch overlaps the next group's work.
+    std::vector<int> order(p.fft_groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    auto uses_scratch = [&](int i) {
+        const int s = p.fft_groups[i].sched;
+        return kSched[s].four_step || kSched[s].engine == 2;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (uses_scratch(a) != uses_scratch(b)) return uses_scratch(a);
+        return p.fft_groups[a].work > p.fft_groups[b].work;
+    });
+    int nfork = 0;
+    for (int i : order) nfork += !uses_scratch(i);
+    const bool fork = nfork > 1 && p.fft_aux[0] != nullptr;
+    if (fork) MR1L_HIP(hipEventRecord(p.fft_ev[Plan::kFftAux], p.stream));
+    bool used[Plan::kFftAux] = {};
+    int next = 0;
+    for (int i : order) {
+        const FftGroup &g = p.fft_groups[i];
+        hipStream_t st = p.stream;
+        if (fork && !uses_scratch(i)) {
+            const int a = next++ % Plan::kFftAux;
+            if (!used[a]) MR1L_HIP(hipStreamWaitEvent(p.fft_aux[a], p.fft_ev[Plan::kFftAux], 0));
+            used[a] = true;
+            st = p.fft_aux[a];
+        }
+        const hipStream_t keep = p.stream;
+        p.stream = st;
         int rc = launch_any(p, g.sched, g.cls, g.d_lats, (int)g.lats.size(), p.d_mdesc, g.ltab, in, out, theta,
                             bitmap, mode, scale, by_m);
+        p.stream = keep;
         if (rc) return rc;
     }
+    for (int a = 0; a < Plan::kFftAux; ++a)
+        if (used[a]) {
+            MR1L_HIP(hipEventRecord(p.fft_ev[a], p.fft_aux[a]));
+            MR1L_HIP(hipStreamWaitEvent(p.stream, p.fft_ev[a], 0));
+        }
     return MR1L_OK;
 }
 
 int fft_init_attrs()
 {
-    const int rc = allow_lds<double>();
-    return rc ? rc : allow_lds<float>();
+    int rc = allow_lds<double>();
+    if (!rc) rc = allow_lds<float>();
+    if (!rc) rc = lfft_attrs_d();
+    if (!rc) rc = lfft_attrs_f();
+    return rc;
 }
 
 // Table entry of size `mid` for the layout of schedule s.
@@ -877,7 +925,11 @@ MDesc fft_layout(const Plan &p, int mid, int s)
 {
     MDesc m = p.mdesc[mid];
     const MInfo &mi = p.minfo[mid];
-    if (!kSched[s].four_step && !kSched[s].rader) {
+    if (kSched[s].engine == 1) {
+        m.spec_off = mi.spec_r; m.tw_N = mi.tw_r; m.N = mi.Nr; m.N1 = mi.Nr; m.N2 = 1;
+    } else if (kSched[s].engine == 2) {
+        m.spec_off = mi.spec_q; m.tw_N = mi.tw_q; m.N = mi.Nq; m.N1 = mi.Bq; m.N2 = mi.Kq;
+    } else if (!kSched[s].four_step && !kSched[s].rader) {
         m.spec_off = mi.spec_s; m.tw_N = mi.tw_s; m.N = mi.Ns; m.N1 = mi.Ns; m.N2 = 1;
     } else {
         int k = 0;
@@ -892,6 +944,8 @@ MDesc fft_layout(const Plan &p, int mid, int s)
 
 static bool applies(const MInfo &mi, int s)
 {
+    if (kSched[s].engine == 1) return mi.Nr > 0;
+    if (kSched[s].engine == 2) return mi.Nq > 0;
     if (kSched[s].rader) return mi.rader;
     return kSched[s].four_step ? mi.Np > 0 : mi.Ns > 0;
 }
@@ -938,8 +992,13 @@ int fft_apply_schedules(Plan &p)
     int64_t len = 0, slots = 0;
     for (size_t i = 0; i < p.lat.size(); ++i) {
         const MInfo &mi = p.minfo[p.lat[i].mid];
-        // one group per size for the Rader kernels (compiled per length M - 1)
-        const int cls = kSched[mi.sched].rader ? (int)(mi.M - 1) : kSched[mi.sched].four_step ? 0 : lds_class(mi.Ns);
+        // one group per size for the Rader kernels (compiled per length M - 1), per
+        // transform length for reg
+        const int cls = kSched[mi.sched].rader          ? (int)(mi.M - 1)
+                        : kSched[mi.sched].engine == 1 ? mi.Nr
+                        : kSched[mi.sched].engine == 2 ? mi.Kq
+                        : kSched[mi.sched].four_step   ? 0
+                                                       : lds_class(mi.Ns);
         auto it = gi.find({mi.sched, cls});
         if (it == gi.end()) {
             it = gi.emplace(std::make_pair(mi.sched, cls), p.fft_groups.size()).first;
@@ -949,13 +1008,15 @@ int fft_apply_schedules(Plan &p)
         }
         FftGroup &g = p.fft_groups[it->second];
         g.lats.push_back((int32_t)i);
+        g.work += (double)mi.M * std::log2((double)mi.M + 1.0);
         g.ltab = g.ltab && mi.ltab;
         if (kSched[mi.sched].four_step) len = std::max<int64_t>(len, mi.Np);
+        if (kSched[mi.sched].engine == 2) len = std::max<int64_t>(len, (int64_t)(mi.Kq - 1) * mi.Nq);
     }
     for (FftGroup &g : p.fft_groups) {
         int rc = upload_list(&g.d_lats, g.lats);
         if (rc) return rc;
-        if (kSched[g.sched].four_step)
+        if (kSched[g.sched].four_step || kSched[g.sched].engine == 2)
             slots = std::max<int64_t>(slots, std::min<int64_t>((int64_t)g.lats.size(),
                                                                (int64_t)kSched[g.sched].per_cu * num_cus()));
     }
@@ -994,20 +1055,31 @@ int fft_prepare_spectra(Plan &p)
     int32_t *d_rep = nullptr;
     MR1L_HIP(hipMalloc(&d_md, p.mdesc.size() * sizeof(MDesc)));
     int rc = MR1L_OK;
-    for (int s : {0, kDefaultFourStep}) {
+    // (schedule, class): the reg schedule runs one launch per transform length
+    std::vector<std::pair<int, int>> passes = {{0, kLdsClasses - 1}, {kDefaultFourStep, 0}, {kSplitSched, 0}};
+    {
+        std::vector<int> lens;
+        for (const MInfo &mi : p.minfo)
+            if (mi.Nr && std::find(lens.begin(), lens.end(), mi.Nr) == lens.end()) lens.push_back(mi.Nr);
+        for (int n : lens) passes.push_back({kRegSched, n});
+    }
+    for (const auto &sc : passes) {
+        const int s = sc.first;
         std::vector<MDesc> md(p.mdesc);
         std::vector<int32_t> reps;
         bool ltab = true;
         int64_t len = 0;
         for (size_t mid = 0; mid < p.minfo.size(); ++mid) {
             if (!applies(p.minfo[mid], s) || rep[mid] < 0) continue;
+            if (s == kRegSched && p.minfo[mid].Nr != sc.second) continue;
             md[mid] = fft_layout(p, (int)mid, s);
             reps.push_back(rep[mid]);
             ltab = ltab && p.minfo[mid].ltab;
-            len = std::max<int64_t>(len, p.minfo[mid].Np);
+            len = std::max<int64_t>(len, s == kSplitSched ? (int64_t)(p.minfo[mid].Kq - 1) * p.minfo[mid].Nq
+                                                          : (int64_t)p.minfo[mid].Np);
         }
         if (reps.empty()) continue;
-        if (kSched[s].four_step) {
+        if (kSched[s].four_step || kSched[s].engine == 2) {
             rc = ensure_scratch(p, len, std::min<int64_t>((int64_t)reps.size(), (int64_t)kSched[s].per_cu * num_cus()));
             if (rc) break;
         }
@@ -1018,7 +1090,7 @@ int fft_prepare_spectra(Plan &p)
             break;
         }
         // the largest LDS class holds every whole-LDS size
-        rc = launch_any(p, s, kLdsClasses - 1, d_rep, (int)reps.size(), d_md, ltab, nullptr, nullptr, 0.0, nullptr,
+        rc = launch_any(p, s, sc.second, d_rep, (int)reps.size(), d_md, ltab, nullptr, nullptr, 0.0, nullptr,
                         FFT_SPEC, 1.0, 0);
         if (rc) break;
         if (hipStreamSynchronize(p.stream) != hipSuccess) {

@@ -69,17 +69,27 @@ struct FftSched {
     int32_t per_cu;
     int32_t split_floor;
     int32_t rader;        // Rader's algorithm in registers (prime M, M - 1 = 2^a 5^b)
+    int32_t engine;       // 1: reg (whole transform in registers), 2: split (blocks of one workgroup)
 };
-constexpr int kNumSched = 10;
+constexpr int kNumSched = 12;
 extern const FftSched kSched[kNumSched];
 constexpr int kDefaultFourStep = 2;
 constexpr int kRaderSched = 9;
+constexpr int kRegSched = 10;
+constexpr int kSplitSched = 11;
+// Register-engine lengths: reg takes N = the smallest power of two >= 2M - 1 in
+// [64, 16384] (complex128) or [64, 32768] (complex64); split (complex128) cuts M into
+// K = ceil(M / 8192) <= 4 blocks transformed at length 16384.
+constexpr int kRegMinN = 64;
+constexpr int kSplitLen = 16384;
+constexpr int kSplitMaxK = 4;
 
 // Lattices launched together: schedule, LDS size class (schedule 0), whether the
 // four-step tables fit the LDS, and the lattice list (host and device).
 struct FftGroup {
     int32_t sched = 0, cls = 0;
     bool ltab = true;
+    double work = 0.0;   // sum of M log M over the group (launch order)
     std::vector<int32_t> lats;
     int32_t *d_lats = nullptr;
 };
@@ -104,6 +114,10 @@ struct MInfo {
     int64_t spec_p = -1, tw_p = -1;
     bool ltab = true;         // four-step tables fit the LDS (M <= 32768, N <= 2^16)
     bool rader = false;       // the Rader schedule applies
+    int32_t Nr = 0;           // reg schedule: transform length (0: does not apply)
+    int64_t spec_r = -1, tw_r = -1;
+    int32_t Nq = 0, Bq = 0, Kq = 0;   // split schedule: transform length, block, blocks (Nq 0: does not apply)
+    int64_t spec_q = -1, tw_q = -1;
     int32_t sched = 0;
     int32_t nlat = 0;
 };
@@ -112,6 +126,11 @@ struct MInfo {
 struct Plan {
     int32_t d = 0, F = 0, L = 0, dtype = MR1L_C128;
     hipStream_t stream = nullptr;
+    // DFT groups without scratch run concurrently on these (default priority) streams,
+    // forked from and joined back into the plan's stream with the events
+    static constexpr int kFftAux = 3;
+    hipStream_t fft_aux[kFftAux] = {};
+    hipEvent_t fft_ev[kFftAux + 1] = {};
     int64_t nodes = 0;
     std::vector<int64_t> M;          // host [F*L]
     std::vector<int64_t> z;          // host [F*L*d]
@@ -288,6 +307,16 @@ int adjoint_run(Plan &p, int64_t cap, int64_t s_cap, const int64_t *n_out,
                 const void *grad_out, void *grad_f);
 
 enum { FFT_FWD = 0, FFT_INV = 1, FFT_SPEC = 2 };
+
+// reg and split DFT schedules (k_lfft_d.hip, k_lfft_f.hip)
+int reg_launch_d(Plan &p, int N, const int32_t *d_lats, int nl, const MDesc *d_md, const void *in, void *out,
+                 double theta, uint32_t *bitmap, int mode, double scale, int by_m);
+int reg_launch_f(Plan &p, int N, const int32_t *d_lats, int nl, const MDesc *d_md, const void *in, void *out,
+                 double theta, uint32_t *bitmap, int mode, double scale, int by_m);
+int split_launch_d(Plan &p, int K, const int32_t *d_lats, int nl, const MDesc *d_md, const void *in, void *out,
+                   double theta, uint32_t *bitmap, int mode, double scale, int by_m);
+int lfft_attrs_d();
+int lfft_attrs_f();
 
 // Number of compute units of the current device.
 int num_cus();
