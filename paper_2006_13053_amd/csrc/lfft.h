@@ -283,22 +283,23 @@ __device__ __forceinline__ int in_pos(int t, int c, int m)
 // LDS index of plane entry q: one pad entry after every 16 doubles (32 floats), so
 // that the first pass's outputs (stride E entries across the lanes) fall in distinct
 // banks; runs of 16 or more consecutive lanes stay conflict-free.
-template <typename T> constexpr int pad_shift() { return sizeof(T) == 8 ? 4 : 5; }
-template <typename T> __device__ __forceinline__ int padq(int q) { return q + (q >> pad_shift<T>()); }
+// With E values per thread not a multiple of 16 (the radix-20 transforms) the stride
+// of the first pass is not a power of two and the plane is left unpadded.
+template <typename T, int E = 16> constexpr int pad_shift() { return E % 16 ? 30 : (sizeof(T) == 8 ? 4 : 5); }
+template <typename T, int E = 16> __device__ __forceinline__ int padq(int q) { return q + (q >> pad_shift<T, E>()); }
 // Entries of one padded plane of length N.
-template <typename T> constexpr int plane_len(int N) { return N + (N >> pad_shift<T>()); }
+template <typename T, int E = 16> constexpr int plane_len(int N) { return N + (N >> pad_shift<T, E>()); }
 
 // Plane stores of a pass's outputs and loads of the next pass's inputs.  Every index
 // is base(t) + K with K a constant of the unrolled loops (t + NT c splits this way
 // because NT and the sub-length are powers of two, one dividing the other); where K
 // is a multiple of the pad period the padded index is padq(base) + K + the pad of K,
 // so the address is one register plus an immediate offset.
-template <typename T> constexpr int pad_period() { return 1 << pad_shift<T>(); }
-
-template <typename T>
+template <typename T, int E>
 __device__ __forceinline__ int padded(int base, int pbase, int K)
 {
-    return (K % pad_period<T>() == 0) ? pbase + K + (K >> pad_shift<T>()) : padq<T>(base + K);
+    constexpr int sh = pad_shift<T, E>();
+    return (sh >= 30 || K % (1 << sh) == 0) ? pbase + K + (K >> sh) : padq<T, E>(base + K);
 }
 
 template <typename T, int N, int E, int RO, int LO>
@@ -307,7 +308,7 @@ __device__ __forceinline__ void put_plane(T *pl, const T (&x)[E], int t)
     constexpr int NT = N / E;
     constexpr bool A = NT % LO == 0, B = LO % NT == 0;
     const int base = A ? (t / LO) * LO * RO + (t % LO) : t;
-    const int pb = padq<T>(base);
+    const int pb = padq<T, E>(base);
 #pragma unroll
     for (int c = 0; c < E / RO; ++c)
 #pragma unroll
@@ -315,9 +316,9 @@ __device__ __forceinline__ void put_plane(T *pl, const T (&x)[E], int t)
             if constexpr (A || B) {
                 const int qc = (NT * c) / LO, rc = (NT * c) % LO;   // B: NT c = qc LO + rc, rc + t < LO
                 const int K = A ? NT * c * RO + p * LO : qc * LO * RO + rc + p * LO;
-                pl[padded<T>(base, pb, K)] = x[c * RO + p];
+                pl[padded<T, E>(base, pb, K)] = x[c * RO + p];
             } else {
-                pl[padq<T>(out_pos<N, E, RO, LO>(t, c, p))] = x[c * RO + p];
+                pl[padq<T, E>(out_pos<N, E, RO, LO>(t, c, p))] = x[c * RO + p];
             }
         }
 }
@@ -325,11 +326,11 @@ __device__ __forceinline__ void put_plane(T *pl, const T (&x)[E], int t)
 template <typename T, int N, int E, int RI>
 __device__ __forceinline__ void get_plane(const T *pl, T (&x)[E], int t)
 {
-    const int pb = padq<T>(t);
+    const int pb = padq<T, E>(t);
 #pragma unroll
     for (int c = 0; c < E / RI; ++c)
 #pragma unroll
-        for (int m = 0; m < RI; ++m) x[c * RI + m] = pl[padded<T>(t, pb, (N / E) * c + m * (N / RI))];
+        for (int m = 0; m < RI; ++m) x[c * RI + m] = pl[padded<T, E>(t, pb, (N / E) * c + m * (N / RI))];
 }
 
 // Values leave the layout of a pass (radix RO, sub-length LO) for the input layout of
