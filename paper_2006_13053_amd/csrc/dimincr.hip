@@ -14,7 +14,10 @@
 //   draws from SplitMix64 stream (seed, t, i): anchors, then generating vectors
 //   samples on the t-dimensional lattices with the anchors fixed (Step 2b)
 //   mr1l_fft + mr1l_extract with s~ (Step 2c)
-//   union of the detected tuples (Step 2d, sorted without repeats on the host)
+//   union of the detected tuples (Step 2d): a bitmap over J compacted in ascending
+//   order (J is lexicographic, so the union is sorted and has no repeats)
+// The rt repetitions of a step are the rt functions of one batched plan; J, the
+// union and the next step's tuples stay on the device (one transfer per step).
 #include "mr1l_internal.h"
 
 #include <algorithm>
@@ -69,6 +72,114 @@ __global__ void k_line_gather(int F, int64_t K, int64_t N, const typename cvec<T
         det_idx[(int64_t)f * K + q] = q;
         det_coef[(int64_t)f * K + q] = ghat[(int64_t)f * K + h];
         if (q == 0) n_det[f] = K;
+    }
+}
+
+// J = prev x set, lexicographic, written rt times (one copy per repetition's
+// function): J[u][f nJ + a K + b] = prev[u][a] (u < tm1), set[b].
+__global__ void k_cartesian_rep(const int64_t *__restrict__ prev, int64_t nprev, int64_t prev_stride, int tm1,
+                                const int64_t *__restrict__ set, int64_t K, int rt, int64_t *__restrict__ J)
+{
+    const int64_t nJ = nprev * K, tot = nJ * rt;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < tot; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = g % nJ;
+        const int64_t a = q / K, b = q - a * K;
+        for (int u = 0; u < tm1; ++u) J[(int64_t)u * tot + g] = prev[(int64_t)u * prev_stride + a];
+        J[(int64_t)tm1 * tot + g] = set[b];
+    }
+}
+
+// rows x n int64 values, each row written rt times side by side: dst[r][f n + j] = src[r][j].
+__global__ void k_replicate(const int64_t *__restrict__ src, int rows, int64_t n, int rt, int64_t *__restrict__ dst)
+{
+    const int64_t tot = (int64_t)rows * n * rt;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < tot; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = g / (n * rt), rem = g - r * n * rt, j = rem % n;
+        dst[g] = src[r * n + j];
+    }
+}
+
+// Step 2d union: the output lists of the rt repetitions (indices into the same J) set
+// bits of one bitmap over J; the bitmap's set bits in ascending order are the union,
+// already lexicographic and without repeats (J is built in lexicographic order).
+__global__ void k_union_mark(const int64_t *__restrict__ n_out, const int64_t *__restrict__ out_idx, int64_t s_cap,
+                             int rt, uint32_t *__restrict__ bits)
+{
+    const int f = blockIdx.y;
+    const int64_t n = min(n_out[f], s_cap);
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = out_idx[(int64_t)f * s_cap + q];
+        atomicOr(bits + (j >> 5), 1u << (j & 31));
+    }
+}
+
+constexpr int kUnionWords = 1024;   // bitmap words per counting block (256 threads x 4)
+
+__device__ __forceinline__ int union_block_scan(int v, int *sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        const int a = tid >= o ? sh[tid - o] : 0;
+        __syncthreads();
+        sh[tid] += a;
+        __syncthreads();
+    }
+    return sh[tid] - v;
+}
+
+__global__ __launch_bounds__(256) void k_union_count(const uint32_t *__restrict__ bits, int64_t nwords,
+                                                     int32_t *__restrict__ cnt)
+{
+    __shared__ int sh[256];
+    const int64_t w0 = (int64_t)blockIdx.x * kUnionWords + threadIdx.x * 4;
+    int c = 0;
+    for (int k = 0; k < 4; ++k)
+        if (w0 + k < nwords) c += __popc(bits[w0 + k]);
+    const int before = union_block_scan(c, sh);
+    if (threadIdx.x == blockDim.x - 1) cnt[blockIdx.x] = before + c;
+}
+
+// exclusive offsets of the counting blocks; stat[0] = the union's size
+__global__ void k_union_scan(int nb, int32_t *__restrict__ cnt, int64_t *__restrict__ stat)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int x = 0; x < nb; ++x) {
+        const int v = cnt[x];
+        cnt[x] = (int32_t)acc;
+        acc += v;
+    }
+    stat[0] = acc;
+}
+
+// the union's tuples: column u of J at each set bit, in ascending order, to prev_out
+// (SoA [t][cap_prev]; entries beyond cap_prev are counted but not written)
+__global__ __launch_bounds__(256) void k_union_emit(const uint32_t *__restrict__ bits, int64_t nwords,
+                                                    const int32_t *__restrict__ off, const int64_t *__restrict__ J,
+                                                    int64_t Jstride, int t, int64_t cap_prev,
+                                                    int64_t *__restrict__ prev_out)
+{
+    __shared__ int sh[256];
+    const int64_t w0 = (int64_t)blockIdx.x * kUnionWords + threadIdx.x * 4;
+    uint32_t v[4];
+    int c = 0;
+    for (int k = 0; k < 4; ++k) {
+        v[k] = (w0 + k < nwords) ? bits[w0 + k] : 0u;
+        c += __popc(v[k]);
+    }
+    int64_t r = off[blockIdx.x] + union_block_scan(c, sh);
+    for (int k = 0; k < 4; ++k) {
+        uint32_t b = v[k];
+        while (b) {
+            const int j = __ffs(b) - 1;
+            b &= b - 1;
+            const int64_t q = (w0 + k) * 32 + j;
+            if (r < cap_prev)
+                for (int u = 0; u < t; ++u) prev_out[(int64_t)u * cap_prev + r] = J[(int64_t)u * Jstride + q];
+            ++r;
+        }
     }
 }
 
@@ -223,13 +334,24 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
         }
     }
 
-    // I^(1), row-major tuples
-    std::vector<int64_t> prev = I1[0];
-    int64_t nprev = (int64_t)prev.size();
+    // Step 2 on the device: per step t, the rt repetitions are the rt functions of one
+    // batched plan (their own lattices and anchors, the same candidate set J in rt
+    // copies), sampled, transformed and detected together; their union and the next
+    // step's tuples stay on the device, and one transfer per step brings the union's
+    // size and the detected counts to the host.
+    int64_t nprev = (int64_t)I1[0].size();
     if (nprev == 0) {
         if (total_samples) *total_samples = samples;
         return MR1L_OK;   // nothing detected: the result is empty
     }
+    int64_t prev_stride = nprev;   // columns of the SoA tuples in dprev
+    if ((rc = dprev.need(nprev))) return rc;
+    MR1L_HIP(hipMemcpyAsync(dprev.p, I1[0].data(), nprev * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    DevBuf<int64_t> dnext, dstat, dsetoff, dtoff, drf;
+    DevBuf<unsigned char> drc;
+    DevBuf<uint32_t> dbits;
+    DevBuf<int32_t> dcnt;
+    bool long_lists = false;   // a step overflowed the short-list capacity: later steps take the long path
 
     for (int t = 2; t <= d; ++t) {
         const int rt = (t < d) ? P.r : 1;
@@ -244,149 +366,216 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
         }
         const int32_t L = mr1l_num_lattices(nJ, P.c, P.delta);
         if (L < 1 || L > kMaxL) return fail(MR1L_E_ARG, "eq. (4.2) lattice count out of range");
-        // previous tuples as SoA [t-1][nprev]
-        std::vector<int64_t> soa((size_t)(t - 1) * nprev);
-        for (int64_t a = 0; a < nprev; ++a)
-            for (int u = 0; u < t - 1; ++u) soa[(size_t)u * nprev + a] = prev[(size_t)a * (t - 1) + u];
-        if ((rc = dprev.need((int64_t)soa.size()))) return rc;
-        MR1L_HIP(hipMemcpyAsync(dprev.p, soa.data(), soa.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        if ((rc = dJ.need(nJ * t))) return rc;
-        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((nJ + 255) / 256, 4096));
-        if ((rc = dset.need(Kt))) return rc;
-        MR1L_HIP(hipMemcpyAsync(dset.p, It.data(), Kt * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_cartesian, dim3((unsigned)blocks), dim3(256), 0, st, dprev.p, nprev, t - 1, dset.p, Kt,
-                           dJ.p);
-        MR1L_LAUNCH_CHECK();
-
-        std::vector<int64_t> Ms(L, P.M);
-        const int64_t nodes = (int64_t)L * P.M;
-        if ((rc = fbuf.need(nodes * esz)) || (rc = gbuf.need(nodes * esz)) || (rc = bitmap.need((nodes + 31) / 32)))
-            return rc;
-        // detected-list capacity: the LDS path while every candidate fits it, else the whole set
-        const int64_t ecap = std::min<int64_t>(kMaxCapLarge, std::max<int64_t>(nJ <= kMaxCap ? kMaxCap : nJ, s_t));
-        if ((rc = n_det.need(1)) || (rc = det_idx.need(ecap)) || (rc = det_coef.need(ecap * esz)) ||
-            (rc = n_o.need(1)) || (rc = out_idx.need(s_t)) || (rc = out_coef.need(s_t * esz)) ||
-            (rc = danc.need(std::max(1, d - t))))
-            return rc;
-
-        std::vector<int64_t> cur;   // row-major t-tuples
-        std::vector<unsigned char> cur_coef;
-        PlanHolder plan;
+        const int64_t nJr = nJ * rt;
+        // draws of every repetition: anchors, then generating vectors
+        std::vector<uint32_t> anc((size_t)rt * std::max(1, d - t), 0u);
+        std::vector<int64_t> z((size_t)rt * L * t);
         for (int i = 1; i <= rt; ++i) {
             Stream rs(P.seed, t, i);
-            std::vector<uint32_t> anc(std::max(1, d - t), 0u);
-            for (int u = t; u < d; ++u) anc[u - t] = (uint32_t)(rs.next() >> 32);
-            std::vector<int64_t> z((size_t)L * t);
+            for (int u = t; u < d; ++u) anc[(size_t)(i - 1) * (d - t) + (u - t)] = (uint32_t)(rs.next() >> 32);
             for (int l = 0; l < L; ++l)
-                for (int u = 0; u < t; ++u) z[(size_t)l * t + u] = rs.below(P.M);
-            if (!plan.p) {
-                if ((rc = mr1l_plan_create(&plan.p, t, 1, L, Ms.data(), z.data(), P.dtype, stream))) return rc;
-            } else if ((rc = mr1l_plan_set_z(plan.p, z.data()))) {
-                return rc;
-            }
-            MR1L_HIP(hipMemcpyAsync(danc.p, anc.data(), anc.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-            if (fn) {
-                if (fn(user, t, L, Ms.data(), z.data(), anc.data(), fbuf.p, stream) != 0)
+                for (int u = 0; u < t; ++u) z[((size_t)(i - 1) * L + l) * t + u] = rs.below(P.M);
+        }
+        std::vector<int64_t> Ms((size_t)rt * L, P.M);
+        PlanHolder plan;
+        if ((rc = mr1l_plan_create(&plan.p, t, rt, L, Ms.data(), z.data(), P.dtype, stream))) return rc;
+        // J in rt copies, and the sets' offsets
+        if ((rc = dJ.need(nJr * t)) || (rc = dset.need(Kt)) || (rc = dsetoff.need(rt + 1)) ||
+            (rc = danc.need((int64_t)anc.size())))
+            return rc;
+        std::vector<int64_t> so(rt + 1);
+        for (int f = 0; f <= rt; ++f) so[f] = (int64_t)f * nJ;
+        MR1L_HIP(hipMemcpyAsync(dset.p, It.data(), Kt * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        MR1L_HIP(hipMemcpyAsync(dsetoff.p, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        MR1L_HIP(hipMemcpyAsync(danc.p, anc.data(), anc.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((nJr + 255) / 256, 4096));
+        hipLaunchKernelGGL(k_cartesian_rep, dim3((unsigned)blocks), dim3(256), 0, st, dprev.p, nprev, prev_stride,
+                           t - 1, dset.p, Kt, rt, dJ.p);
+        MR1L_LAUNCH_CHECK();
+
+        // samples of every repetition (Step 2b)
+        const int64_t nodes_f = (int64_t)L * P.M, nodes = nodes_f * rt;
+        if ((rc = fbuf.need(nodes * esz)) || (rc = gbuf.need(nodes * esz)) || (rc = bitmap.need((nodes + 31) / 32)))
+            return rc;
+        std::vector<uint64_t> bdims;
+        std::vector<int64_t> toff(rt + 1);
+        if (fn) {
+            for (int i = 0; i < rt; ++i)
+                if (fn(user, t, L, Ms.data() + (size_t)i * L, z.data() + (size_t)i * L * t, anc.data() + (size_t)i * std::max(1, d - t),
+                       fbuf.p + (size_t)i * nodes_f * esz, stream) != 0)
                     return fail(MR1L_E_ARG, "sampling callback failed");
-            } else if (bsp) {
-                if ((rc = bspline_sample_run(plan_of(plan.p), d, P.bs_n, P.bs_order, P.bs_dims,
-                                             d > t ? danc.p : nullptr, fbuf.p)))
-                    return rc;
-            } else if ((rc = mr1l_sample(plan.p, d, nullptr, poly_s, poly_freq, poly_coef, d > t ? danc.p : nullptr,
-                                         fbuf.p, 1))) {
+        } else if (bsp) {
+            bdims.resize((size_t)rt * P.bs_n);
+            for (int i = 0; i < rt; ++i)
+                for (int q = 0; q < P.bs_n; ++q) bdims[(size_t)i * P.bs_n + q] = P.bs_dims[q];
+            if ((rc = bspline_sample_run(plan_of(plan.p), d, P.bs_n, P.bs_order, bdims.data(), d > t ? danc.p : nullptr,
+                                         fbuf.p)))
                 return rc;
+        } else {
+            // the polynomial's terms once per repetition
+            const int64_t cw = (int64_t)esz / 8;   // int64 words per coefficient
+            if ((rc = drf.need(std::max<int64_t>(1, (int64_t)d * poly_s * rt))) ||
+                (rc = drc.need(std::max<int64_t>(1, poly_s * rt) * (int64_t)esz)) || (rc = dtoff.need(rt + 1)))
+                return rc;
+            for (int f = 0; f <= rt; ++f) toff[f] = (int64_t)f * poly_s;
+            MR1L_HIP(hipMemcpyAsync(dtoff.p, toff.data(), toff.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            if (poly_s > 0) {
+                const int64_t rb = std::max<int64_t>(1, std::min<int64_t>(((int64_t)d * poly_s * rt + 255) / 256, 4096));
+                hipLaunchKernelGGL(k_replicate, dim3((unsigned)rb), dim3(256), 0, st, poly_freq, d, poly_s, rt, drf.p);
+                MR1L_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_replicate, dim3((unsigned)rb), dim3(256), 0, st, (const int64_t *)poly_coef, 1,
+                                   poly_s * cw, rt, (int64_t *)drc.p);
+                MR1L_LAUNCH_CHECK();
             }
-            samples += nodes;
-            if ((rc = mr1l_fft(plan.p, fbuf.p, gbuf.p, P.theta, bitmap.p))) return rc;
+            if ((rc = mr1l_sample(plan.p, d, dtoff.p, poly_s * rt, drf.p, drc.p, d > t ? danc.p : nullptr, fbuf.p, 1)))
+                return rc;
+        }
+        samples += nodes;
+        if ((rc = mr1l_fft(plan.p, fbuf.p, gbuf.p, P.theta, bitmap.p))) return rc;
+
+        // Algorithm 4 on every repetition (Step 2c): short lists unless a step overflowed
+        if ((rc = n_det.need(rt)) || (rc = n_o.need(rt)) || (rc = out_idx.need((int64_t)rt * s_t)) ||
+            (rc = out_coef.need((int64_t)rt * s_t * esz)) || (rc = dstat.need(1 + rt)))
+            return rc;
+        auto extract = [&](int64_t ecap) -> int {
+            int r2;
+            if ((r2 = det_idx.need((int64_t)rt * ecap)) || (r2 = det_coef.need((int64_t)rt * ecap * esz))) return r2;
             mr1l_extract_opts o{P.theta, 0, P.postproc, s_t, ecap};
             mr1l_extract_out ex{};
             ex.n_det = n_det.p; ex.det_idx = det_idx.p; ex.det_coef = det_coef.p;
             ex.n_out = n_o.p; ex.out_idx = out_idx.p; ex.out_coef = out_coef.p;
-            if ((rc = mr1l_extract(plan.p, nJ, nullptr, dJ.p, gbuf.p, bitmap.p, &o, &ex))) return rc;
-            int64_t h_ndet = 0, h_nout = 0;
-            MR1L_HIP(hipMemcpyAsync(&h_ndet, n_det.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-            MR1L_HIP(hipMemcpyAsync(&h_nout, n_o.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-            MR1L_HIP(hipStreamSynchronize(st));
-            if (h_ndet > ecap) return fail(MR1L_E_CAPACITY, "detected set exceeds the capacity of one step");
-            std::vector<int64_t> oi(h_nout);
-            std::vector<unsigned char> oc(h_nout * esz);
-            if (h_nout > 0) {
-                MR1L_HIP(hipMemcpy(oi.data(), out_idx.p, h_nout * sizeof(int64_t), hipMemcpyDeviceToHost));
-                MR1L_HIP(hipMemcpy(oc.data(), out_coef.p, h_nout * esz, hipMemcpyDeviceToHost));
-            }
-            for (int64_t q = 0; q < h_nout; ++q) {
-                const int64_t a = oi[q] / Kt, b = oi[q] - a * Kt;
-                for (int u = 0; u < t - 1; ++u) cur.push_back(prev[(size_t)a * (t - 1) + u]);
-                cur.push_back(It[b]);
-            }
-            if (t == d) cur_coef = oc;
-            if (t == d && P.lsq_iters > 0 && h_nout > 0) {
-                // least squares on the output frequencies with this step's samples (Remark 2.9):
-                // every output is kept (theta 0, one vote), then CG on the normal equations
-                std::vector<int64_t> soa2((size_t)d * h_nout);
-                for (int64_t q = 0; q < h_nout; ++q)
-                    for (int u = 0; u < d; ++u) soa2[(size_t)u * h_nout + q] = cur[(size_t)q * d + u];
-                DevBuf<int64_t> dsel, n2, i2, o2n, o2i;
-                DevBuf<unsigned char> c2, o2c;
-                DevBuf<double> res;
-                if ((rc = dsel.need((int64_t)soa2.size())) || (rc = n2.need(1)) || (rc = i2.need(h_nout)) ||
-                    (rc = c2.need(h_nout * esz)) || (rc = o2n.need(1)) || (rc = o2i.need(h_nout)) ||
-                    (rc = o2c.need(h_nout * esz)) || (rc = res.need(1)))
-                    return rc;
-                MR1L_HIP(hipMemcpyAsync(dsel.p, soa2.data(), soa2.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-                if ((rc = launch_fill_u32(bitmap.p, (nodes + 31) / 32, 0xffffffffu, st))) return rc;
-                mr1l_extract_opts o2{0.0, 1, P.postproc, h_nout, h_nout};
-                mr1l_extract_out ex2{};
-                ex2.n_det = n2.p; ex2.det_idx = i2.p; ex2.det_coef = c2.p;
-                ex2.n_out = o2n.p; ex2.out_idx = o2i.p; ex2.out_coef = o2c.p;
-                if ((rc = mr1l_extract(plan.p, h_nout, nullptr, dsel.p, gbuf.p, bitmap.p, &o2, &ex2))) return rc;
-                Plan &pp = plan_of(plan.p);
-                if ((rc = mr1l_lsq(plan.p, h_nout, n2.p, i2.p, pp.d_ex_hash, pp.d_ex_mask, gbuf.p, P.lsq_iters,
-                                   1e-14, c2.p, res.p, nullptr, 0.0, 1, nullptr, nullptr, nullptr)))
-                    return rc;
-                // the detected list is every output in ascending position: coefficient q belongs to row q
-                std::vector<int64_t> hi2(h_nout);
-                MR1L_HIP(hipMemcpyAsync(hi2.data(), i2.p, h_nout * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-                std::vector<unsigned char> hc2(h_nout * esz);
-                MR1L_HIP(hipMemcpyAsync(hc2.data(), c2.p, h_nout * esz, hipMemcpyDeviceToHost, st));
-                MR1L_HIP(hipStreamSynchronize(st));
-                for (int64_t q = 0; q < h_nout; ++q)
-                    std::memcpy(cur_coef.data() + hi2[q] * esz, hc2.data() + q * esz, esz);
-            }
-            if ((int64_t)(cur.size() / t) > cap) return fail(MR1L_E_CAPACITY, "union exceeds cap");
-        }
-        const int64_t ncur = (int64_t)(cur.size() / t);
-        std::vector<int64_t> order(ncur);
-        for (int64_t q = 0; q < ncur; ++q) order[q] = q;
-        auto lex = [&](int64_t x, int64_t y) {
-            for (int u = 0; u < t; ++u) {
-                const int64_t a = cur[(size_t)x * t + u], b = cur[(size_t)y * t + u];
-                if (a != b) return a < b;
-            }
-            return x < y;
+            return mr1l_extract(plan.p, nJr, dsetoff.p, dJ.p, gbuf.p, bitmap.p, &o, &ex);
         };
-        std::sort(order.begin(), order.end(), lex);
-        if (t == d) {
-            for (int64_t q = 0; q < ncur; ++q) {
-                for (int u = 0; u < d; ++u) freq_out[q * d + u] = cur[(size_t)order[q] * d + u];
-                std::memcpy((unsigned char *)coef_out + q * esz, cur_coef.data() + order[q] * esz, esz);
+        const int64_t long_cap = std::min<int64_t>(kMaxCapLarge, std::max<int64_t>(nJ, s_t));
+        int64_t ecap = (long_lists || s_t > kMaxCap) ? long_cap : std::max<int64_t>(kMaxCap, s_t);
+        if ((rc = extract(ecap))) return rc;
+
+        if (t < d) {
+            // union of the repetitions' outputs (Step 2d), then the next step's tuples
+            const int64_t nwords = (nJ + 31) / 32;
+            const int nb = (int)((nwords + kUnionWords - 1) / kUnionWords);
+            const int64_t cap_prev = std::min<int64_t>(nJ, (int64_t)rt * s_t);
+            if ((rc = dbits.need(nwords)) || (rc = dcnt.need(nb)) || (rc = dnext.need(std::max<int64_t>(1, cap_prev * t))))
+                return rc;
+            auto unite = [&]() -> int {
+                int r2 = launch_fill_u32(dbits.p, nwords, 0u, st);
+                if (r2) return r2;
+                const dim3 gm((unsigned)std::max<int64_t>(1, std::min<int64_t>((s_t + 255) / 256, 64)), (unsigned)rt);
+                hipLaunchKernelGGL(k_union_mark, gm, dim3(256), 0, st, n_o.p, out_idx.p, s_t, rt, dbits.p);
+                MR1L_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_union_count, dim3((unsigned)nb), dim3(256), 0, st, dbits.p, nwords, dcnt.p);
+                MR1L_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_union_scan, dim3(1), dim3(64), 0, st, nb, dcnt.p, dstat.p);
+                MR1L_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_union_emit, dim3((unsigned)nb), dim3(256), 0, st, dbits.p, nwords, dcnt.p, dJ.p,
+                                   nJr, t, cap_prev, dnext.p);
+                MR1L_LAUNCH_CHECK();
+                MR1L_HIP(hipMemcpyAsync(dstat.p + 1, n_det.p, rt * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+                return MR1L_OK;
+            };
+            if ((rc = unite())) return rc;
+            std::vector<int64_t> hs(1 + rt);
+            MR1L_HIP(hipMemcpyAsync(hs.data(), dstat.p, hs.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            MR1L_HIP(hipStreamSynchronize(st));
+            bool over = false;
+            for (int f = 0; f < rt; ++f) over = over || hs[1 + f] > ecap;
+            if (over) {
+                if (ecap >= long_cap) return fail(MR1L_E_CAPACITY, "detected set exceeds the capacity of one step");
+                // a list overflowed the short capacity: this step again with the long path
+                long_lists = true;
+                ecap = long_cap;
+                if ((rc = extract(ecap)) || (rc = unite())) return rc;
+                MR1L_HIP(hipMemcpyAsync(hs.data(), dstat.p, hs.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+                MR1L_HIP(hipStreamSynchronize(st));
+                for (int f = 0; f < rt; ++f)
+                    if (hs[1 + f] > ecap) return fail(MR1L_E_CAPACITY, "detected set exceeds the capacity of one step");
             }
-            *n_out = ncur;
-        } else {
-            std::vector<int64_t> next;
-            for (int64_t q = 0; q < ncur; ++q) {
-                const int64_t *row = &cur[(size_t)order[q] * t];
-                if (!next.empty() && std::equal(row, row + t, next.end() - t)) continue;
-                next.insert(next.end(), row, row + t);
-            }
-            prev.swap(next);
-            nprev = (int64_t)(prev.size() / t);
+            if (hs[0] > cap) return fail(MR1L_E_CAPACITY, "union exceeds cap");
+            nprev = hs[0];
             if (nprev == 0) {
                 *n_out = 0;
                 if (total_samples) *total_samples = samples;
                 return MR1L_OK;   // nothing detected: the result is empty
             }
+            std::swap(dprev.p, dnext.p);
+            std::swap(dprev.n, dnext.n);
+            prev_stride = cap_prev;
+            continue;
         }
+
+        // t = d: the output list (one repetition) to the host, in lexicographic order
+        int64_t h_ndet = 0, h_nout = 0;
+        MR1L_HIP(hipMemcpyAsync(&h_ndet, n_det.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        MR1L_HIP(hipMemcpyAsync(&h_nout, n_o.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        MR1L_HIP(hipStreamSynchronize(st));
+        if (h_ndet > ecap) {
+            if (ecap >= long_cap) return fail(MR1L_E_CAPACITY, "detected set exceeds the capacity of one step");
+            ecap = long_cap;
+            if ((rc = extract(ecap))) return rc;
+            MR1L_HIP(hipMemcpyAsync(&h_ndet, n_det.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            MR1L_HIP(hipMemcpyAsync(&h_nout, n_o.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            MR1L_HIP(hipStreamSynchronize(st));
+            if (h_ndet > ecap) return fail(MR1L_E_CAPACITY, "detected set exceeds the capacity of one step");
+        }
+        std::vector<int64_t> oi(h_nout), hprev((size_t)(t - 1) * nprev);
+        std::vector<unsigned char> oc(h_nout * esz);
+        if (h_nout > 0) {
+            MR1L_HIP(hipMemcpy(oi.data(), out_idx.p, h_nout * sizeof(int64_t), hipMemcpyDeviceToHost));
+            MR1L_HIP(hipMemcpy(oc.data(), out_coef.p, h_nout * esz, hipMemcpyDeviceToHost));
+            for (int u = 0; u < t - 1; ++u)
+                MR1L_HIP(hipMemcpy(hprev.data() + (size_t)u * nprev, dprev.p + (int64_t)u * prev_stride,
+                                   nprev * sizeof(int64_t), hipMemcpyDeviceToHost));
+        }
+        std::vector<int64_t> cur;   // row-major d-tuples
+        std::vector<unsigned char> cur_coef = oc;
+        for (int64_t q = 0; q < h_nout; ++q) {
+            const int64_t a = oi[q] / Kt, b = oi[q] - a * Kt;
+            for (int u = 0; u < t - 1; ++u) cur.push_back(hprev[(size_t)u * nprev + a]);
+            cur.push_back(It[b]);
+        }
+        if (P.lsq_iters > 0 && h_nout > 0) {
+            // least squares on the output frequencies with this step's samples (Remark 2.9):
+            // every output is kept (theta 0, one vote), then CG on the normal equations
+            std::vector<int64_t> soa2((size_t)d * h_nout);
+            for (int64_t q = 0; q < h_nout; ++q)
+                for (int u = 0; u < d; ++u) soa2[(size_t)u * h_nout + q] = cur[(size_t)q * d + u];
+            DevBuf<int64_t> dsel, n2, i2, o2n, o2i;
+            DevBuf<unsigned char> c2, o2c;
+            DevBuf<double> res;
+            if ((rc = dsel.need((int64_t)soa2.size())) || (rc = n2.need(1)) || (rc = i2.need(h_nout)) ||
+                (rc = c2.need(h_nout * esz)) || (rc = o2n.need(1)) || (rc = o2i.need(h_nout)) ||
+                (rc = o2c.need(h_nout * esz)) || (rc = res.need(1)))
+                return rc;
+            MR1L_HIP(hipMemcpyAsync(dsel.p, soa2.data(), soa2.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            if ((rc = launch_fill_u32(bitmap.p, (nodes + 31) / 32, 0xffffffffu, st))) return rc;
+            mr1l_extract_opts o2{0.0, 1, P.postproc, h_nout, h_nout};
+            mr1l_extract_out ex2{};
+            ex2.n_det = n2.p; ex2.det_idx = i2.p; ex2.det_coef = c2.p;
+            ex2.n_out = o2n.p; ex2.out_idx = o2i.p; ex2.out_coef = o2c.p;
+            if ((rc = mr1l_extract(plan.p, h_nout, nullptr, dsel.p, gbuf.p, bitmap.p, &o2, &ex2))) return rc;
+            Plan &pp = plan_of(plan.p);
+            if ((rc = mr1l_lsq(plan.p, h_nout, n2.p, i2.p, pp.d_ex_hash, pp.d_ex_mask, gbuf.p, P.lsq_iters,
+                               1e-14, c2.p, res.p, nullptr, 0.0, 1, nullptr, nullptr, nullptr)))
+                return rc;
+            // the detected list is every output in ascending position: coefficient q belongs to row q
+            std::vector<int64_t> hi2(h_nout);
+            MR1L_HIP(hipMemcpyAsync(hi2.data(), i2.p, h_nout * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            std::vector<unsigned char> hc2(h_nout * esz);
+            MR1L_HIP(hipMemcpyAsync(hc2.data(), c2.p, h_nout * esz, hipMemcpyDeviceToHost, st));
+            MR1L_HIP(hipStreamSynchronize(st));
+            for (int64_t q = 0; q < h_nout; ++q)
+                std::memcpy(cur_coef.data() + hi2[q] * esz, hc2.data() + q * esz, esz);
+        }
+        if (h_nout > cap) return fail(MR1L_E_CAPACITY, "union exceeds cap");
+        // ascending J index is lexicographic order
+        std::vector<int64_t> order(h_nout);
+        for (int64_t q = 0; q < h_nout; ++q) order[q] = q;
+        std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return oi[x] < oi[y]; });
+        for (int64_t q = 0; q < h_nout; ++q) {
+            for (int u = 0; u < d; ++u) freq_out[q * d + u] = cur[(size_t)order[q] * d + u];
+            std::memcpy((unsigned char *)coef_out + q * esz, cur_coef.data() + order[q] * esz, esz);
+        }
+        *n_out = h_nout;
     }
     if (total_samples) *total_samples = samples;
     return MR1L_OK;

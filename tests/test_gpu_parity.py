@@ -1052,6 +1052,43 @@ def test_dimincr_matches_oracle_driver(m, seed):
     assert [tuple(r) for r in gf.tolist()] == [t[0] for t in truth]
 
 
+def test_dimincr_sampling_callback_matches_builtin_sampler(m):
+    """The driver with a sampling callback (here: the library sampler on a plan of the
+    lattices and anchors the callback receives, written to the driver's buffer) gives the
+    same support, coefficients and sample count as the built-in sampler, and the callback
+    sees every repetition's lattices: r per step t < d, one at t = d."""
+    import ctypes as C
+    say("dimincr callback")
+    d, s, N, r = 5, 10, 5, 3
+    freq, coef = synth.sparse_poly_box(3, d=d, s=s, box=N)
+    Mlat = synth.next_prime_above(10.33 * 2 * s)
+    pf, pc = T(freq), T(coef)
+    keep, calls = [], []
+
+    def cb(user, t, L, Mp, zp, ancp, fptr, stream):
+        Ms = np.ctypeslib.as_array(Mp, (L,)).copy()
+        z = np.ctypeslib.as_array(zp, (L * t,)).copy().reshape(L, t)
+        anc = None
+        if t < d:
+            anc = T(np.ctypeslib.as_array(ancp, (d - t,)).astype(np.int64).astype(np.uint32).view(np.int32))
+        plan = m.Plan(t, Ms, z)
+        rc = m.lib().mr1l_sample(plan.handle, d, None, s, pf.data_ptr(), pc.data_ptr(),
+                                 None if anc is None else anc.data_ptr(), fptr, 1)
+        keep.append((plan, anc))
+        calls.append(t)
+        return rc
+
+    g0, c0, n0 = m.mr1l_dimincr(d, N, s, 2 * s, r, 1e-12, Mlat, 17, poly_freq=pf, poly_coef=pc)
+    g1, c1, n1 = m.mr1l_dimincr(d, N, s, 2 * s, r, 1e-12, Mlat, 17, sample_fn=cb)
+    torch.cuda.synchronize()
+    assert calls == [t for t in range(2, d) for _ in range(r)] + [d]
+    assert n0 == n1
+    assert np.array_equal(g0, g1)
+    assert np.array_equal(c0, c1)
+    truth = sorted(zip(map(tuple, freq.T.tolist()), coef))
+    assert [tuple(x) for x in g1.tolist()] == [t[0] for t in truth]
+
+
 @pytest.mark.parametrize("d,s,N", [(4, 8, 60), (6, 12, 6)])
 def test_dimincr_step1_matches_oracle_driver(m, d, s, N):
     """Algorithm 3 with Step 1: same single-coordinate sets, lattices and output as the
