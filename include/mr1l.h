@@ -85,8 +85,11 @@ const char *mr1l_last_error(void);
  *          the default stream.
  * The plan precomputes the Bluestein chirps, kernel spectra and twiddle
  * tables of the per-lattice DFTs and the constants of the exact bucket
- * hash, and allocates its scratch.  Returns MR1L_E_NOT_PRIME, MR1L_E_ARG,
- * MR1L_E_NOMEM or MR1L_E_HIP on failure (*out is then NULL).
+ * hash, and allocates its scratch.  The tables are uploaded and the spectra
+ * computed on `stream` without waiting for it (spectra of another DFT
+ * schedule are computed when a size is switched to it).  Returns
+ * MR1L_E_NOT_PRIME, MR1L_E_ARG, MR1L_E_NOMEM or MR1L_E_HIP on failure (*out
+ * is then NULL).
  */
 int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L,
                      const int64_t *M, const int64_t *z, int32_t dtype,
@@ -97,7 +100,8 @@ int mr1l_plan_destroy(mr1l_plan p);
 /* Total number of nodes (sum of all M); sizes f, ghat, counts. */
 int64_t mr1l_plan_nodes(mr1l_plan p);
 
-/* Replace the plan's stream (the next calls are ordered on it). */
+/* Replace the plan's stream (the next calls are ordered on it, after the
+ * work queued so far on the old one). */
 int mr1l_plan_set_stream(mr1l_plan p, void *stream);
 
 /* Replace the generating vectors (host [F*L*d], same M), keeping the DFT

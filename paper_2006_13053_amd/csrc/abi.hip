@@ -174,6 +174,26 @@ static int32_t fast_bound(int d, const int64_t *M, int L)
     return (int32_t)std::max<int64_t>(kb, 0);
 }
 
+// A table for the plan's arena: copied to the host staging buffer at a 256-byte
+// boundary; *dst is pointed at its device copy when the arena is committed.
+static void stage(Plan &p, void **dst, const void *src, size_t bytes)
+{
+    const size_t off = (p.h_arena.size() + 255) & ~size_t(255);
+    p.h_arena.resize(off + std::max<size_t>(bytes, 16), 0);
+    if (src && bytes) std::memcpy(p.h_arena.data() + off, src, bytes);
+    p.arena_fix.push_back({dst, off});
+}
+
+static int arena_commit(Plan &p)
+{
+    MR1L_HIP(hipMalloc(&p.d_arena, std::max<size_t>(p.h_arena.size(), 16)));
+    for (auto &f : p.arena_fix) *f.first = (unsigned char *)p.d_arena + f.second;
+    p.arena_fix.clear();
+    if (!p.h_arena.empty())
+        MR1L_HIP(hipMemcpyAsync(p.d_arena, p.h_arena.data(), p.h_arena.size(), hipMemcpyHostToDevice, p.stream));
+    return MR1L_OK;
+}
+
 template <typename T>
 static int build_tables(Plan &p)
 {
@@ -289,19 +309,15 @@ static int build_tables(Plan &p)
     p.tw_len = (int64_t)tw.size() / 2;
     p.chirp_len = (int64_t)ch.size() / 2;
     const size_t esz = 2 * sizeof(T);
-    MR1L_HIP(hipMalloc(&p.d_rdesc, p.rdesc.size() * sizeof(RaderDesc)));
-    MR1L_HIP(hipMemcpy(p.d_rdesc, p.rdesc.data(), p.rdesc.size() * sizeof(RaderDesc), hipMemcpyHostToDevice));
+    stage(p, (void **)&p.d_rdesc, p.rdesc.data(), p.rdesc.size() * sizeof(RaderDesc));
     if (!ritab.empty()) {
-        MR1L_HIP(hipMalloc(&p.d_ritab, ritab.size() * sizeof(int32_t)));
-        MR1L_HIP(hipMemcpy(p.d_ritab, ritab.data(), ritab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        MR1L_HIP(hipMalloc(&p.d_rctab, rctab.size() * sizeof(T)));
-        MR1L_HIP(hipMemcpy(p.d_rctab, rctab.data(), rctab.size() * sizeof(T), hipMemcpyHostToDevice));
+        stage(p, (void **)&p.d_ritab, ritab.data(), ritab.size() * sizeof(int32_t));
+        stage(p, &p.d_rctab, rctab.data(), rctab.size() * sizeof(T));
     }
-    MR1L_HIP(hipMalloc(&p.d_spec, (size_t)spec_len * esz));
-    MR1L_HIP(hipMalloc(&p.d_tw, tw.size() * sizeof(T)));
-    MR1L_HIP(hipMemcpy(p.d_tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
-    MR1L_HIP(hipMalloc(&p.d_chirp, ch.size() * sizeof(T)));
-    MR1L_HIP(hipMemcpy(p.d_chirp, ch.data(), ch.size() * sizeof(T), hipMemcpyHostToDevice));
+    stage(p, &p.d_tw, tw.data(), tw.size() * sizeof(T));
+    stage(p, &p.d_chirp, ch.data(), ch.size() * sizeof(T));
+    // the spectra are written by the DFT kernels (only the layouts in use)
+    MR1L_HIP(hipMalloc(&p.d_spec, std::max<size_t>((size_t)spec_len * esz, 16)));
     return MR1L_OK;
 }
 
@@ -347,15 +363,11 @@ static int build_vote_records(Plan &p, std::vector<uint32_t> &vr)
 
 static int upload(Plan &p)
 {
-    MR1L_HIP(hipMalloc(&p.d_lat, p.lat.size() * sizeof(LatDesc)));
-    MR1L_HIP(hipMemcpy(p.d_lat, p.lat.data(), p.lat.size() * sizeof(LatDesc), hipMemcpyHostToDevice));
-    MR1L_HIP(hipMalloc(&p.d_mdesc, p.mdesc.size() * sizeof(MDesc)));
-    MR1L_HIP(hipMemcpy(p.d_mdesc, p.mdesc.data(), p.mdesc.size() * sizeof(MDesc), hipMemcpyHostToDevice));
+    stage(p, (void **)&p.d_lat, p.lat.data(), p.lat.size() * sizeof(LatDesc));
+    stage(p, (void **)&p.d_mdesc, p.mdesc.data(), p.mdesc.size() * sizeof(MDesc));
     std::vector<int32_t> z32(p.z.begin(), p.z.end());
-    MR1L_HIP(hipMalloc(&p.d_z32, z32.size() * sizeof(int32_t)));
-    MR1L_HIP(hipMemcpy(p.d_z32, z32.data(), z32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    MR1L_HIP(hipMalloc(&p.d_z64, p.z.size() * sizeof(int64_t)));
-    MR1L_HIP(hipMemcpy(p.d_z64, p.z.data(), p.z.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    stage(p, (void **)&p.d_z32, z32.data(), z32.size() * sizeof(int32_t));
+    stage(p, (void **)&p.d_z64, p.z.data(), p.z.size() * sizeof(int64_t));
     // packed 16-bit pairs of z for the dot2 hash (valid when every M <= 2^15)
     p.dot2 = true;
     for (auto m : p.M) p.dot2 = p.dot2 && m <= (int64_t(1) << 15);
@@ -366,39 +378,55 @@ static int upload(Plan &p)
         for (int64_t i = 0; i < nl; ++i)
             for (int u = 0; u < p.d; ++u)
                 z16[(size_t)i * dh + u / 2] |= (uint32_t)(p.z[(size_t)i * p.d + u] & 0xffff) << (16 * (u & 1));
-        MR1L_HIP(hipMalloc(&p.d_z16, z16.size() * sizeof(uint32_t)));
-        MR1L_HIP(hipMemcpy(p.d_z16, z16.data(), z16.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        stage(p, (void **)&p.d_z16, z16.data(), z16.size() * sizeof(uint32_t));
     }
-    MR1L_HIP(hipMalloc(&p.d_kb, p.kb.size() * sizeof(int32_t)));
     {
         std::vector<uint32_t> vr;
         int rc = build_vote_records(p, vr);
         if (rc) return rc;
-        MR1L_HIP(hipMalloc(&p.d_vrec, vr.size() * sizeof(uint32_t)));
-        MR1L_HIP(hipMemcpy(p.d_vrec, vr.data(), vr.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        stage(p, (void **)&p.d_vrec, vr.data(), vr.size() * sizeof(uint32_t));
     }
-    MR1L_HIP(hipMemcpy(p.d_kb, p.kb.data(), p.kb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    stage(p, (void **)&p.d_kb, p.kb.data(), p.kb.size() * sizeof(int32_t));
+    stage(p, (void **)&p.d_det_tmp, nullptr, sizeof(int64_t) * (size_t)p.F);
+    stage(p, (void **)&p.d_setoff_default, nullptr, 2 * sizeof(int64_t));
+    stage(p, (void **)&p.d_termoff_default, nullptr, 2 * sizeof(int64_t));
+    int rc = arena_commit(p);
+    if (rc) return rc;
     const size_t esz = p.dtype == MR1L_C128 ? 16 : 8;
     MR1L_HIP(hipMalloc(&p.d_nodes_scratch, (size_t)std::max<int64_t>(p.nodes, 1) * esz));
-    MR1L_HIP(hipMalloc(&p.d_det_tmp, sizeof(int64_t) * (size_t)p.F));
-    MR1L_HIP(hipMalloc(&p.d_setoff_default, 2 * sizeof(int64_t)));
-    MR1L_HIP(hipMalloc(&p.d_termoff_default, 2 * sizeof(int64_t)));
+    return MR1L_OK;
+}
+
+// The auxiliary DFT streams of the current device: created once per device, shared
+// by its plans (work of several plans on one of them runs in turn) and kept until
+// the process ends.
+static std::mutex g_aux_mu;
+static hipStream_t g_aux[64][Plan::kFftAux];
+
+static int aux_streams(hipStream_t *out)
+{
+    int dev = 0;
+    MR1L_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(MR1L_E_ARG, "device index beyond the stream pool");
+    std::lock_guard<std::mutex> g(g_aux_mu);
+    for (int i = 0; i < Plan::kFftAux; ++i) {
+        if (!g_aux[dev][i] && hipStreamCreateWithFlags(&g_aux[dev][i], hipStreamNonBlocking) != hipSuccess) {
+            g_aux[dev][i] = nullptr;
+            return fail(MR1L_E_HIP, "DFT stream creation failed");
+        }
+        out[i] = g_aux[dev][i];
+    }
     return MR1L_OK;
 }
 
 static void release(Plan *p)
 {
-    void *ptrs[] = {p->d_lat, p->d_mdesc, p->d_z32, p->d_z64, p->d_kb, p->d_z16, p->d_vrec, p->d_spec, p->d_chirp, p->d_tw,
-                    p->d_fft_scratch, p->d_nodes_scratch, p->d_cterm, p->d_thash, p->d_det_tmp,
-                    p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos, p->d_setoff_default,
-                    p->d_termoff_default, p->d_ls, p->d_gsort, p->d_single, p->d_dflag, p->d_bs_dims, p->d_rdesc,
-                    p->d_ritab, p->d_rctab};
+    // (the tables in the arena are not freed one by one)
+    void *ptrs[] = {p->d_arena, p->d_spec, p->d_glists, p->d_specwork, p->d_fft_scratch, p->d_nodes_scratch,
+                    p->d_cterm, p->d_thash, p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos,
+                    p->d_ls, p->d_gsort, p->d_single, p->d_dflag, p->d_bs_dims};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
-    for (FftGroup &g : p->fft_groups)
-        if (g.d_lats) (void)hipFree(g.d_lats);
-    for (auto &st : p->fft_aux)
-        if (st) (void)hipStreamDestroy(st);
     for (auto &ev : p->fft_ev)
         if (ev) (void)hipEventDestroy(ev);
     delete p;
@@ -520,14 +548,11 @@ int mr1l::plan_create_impl(mr1l_plan *out, int32_t d, int32_t F, int32_t L, cons
     int rc = dtype == MR1L_C128 ? build_tables<double>(*p) : build_tables<float>(*p);
     if (rc == MR1L_OK) rc = upload(*p);
     if (rc == MR1L_OK) rc = sample_static_scratch(&p->d_static_scratch);
-    for (int i = 0; rc == MR1L_OK && i < Plan::kFftAux; ++i)
-        if (hipStreamCreateWithFlags(&p->fft_aux[i], hipStreamNonBlocking) != hipSuccess)
-            rc = fail(MR1L_E_HIP, "DFT stream creation failed");
+    if (rc == MR1L_OK) rc = aux_streams(p->fft_aux);
     for (int i = 0; rc == MR1L_OK && i <= Plan::kFftAux; ++i)
         if (hipEventCreateWithFlags(&p->fft_ev[i], hipEventDisableTiming) != hipSuccess)
             rc = fail(MR1L_E_HIP, "DFT event creation failed");
-    if (rc == MR1L_OK) rc = fft_prepare_spectra(*p);
-    if (rc == MR1L_OK) rc = fft_apply_schedules(*p);
+    if (rc == MR1L_OK) rc = fft_apply_schedules(*p, true);
     if (rc != MR1L_OK) {
         std::string keep = g_err;
         release(p);
@@ -553,7 +578,18 @@ int64_t mr1l_plan_nodes(mr1l_plan p) { return p ? p->nodes : -1; }
 int mr1l_plan_set_stream(mr1l_plan p, void *stream)
 {
     if (!p) return fail(MR1L_E_ARG, "plan is NULL");
-    p->stream = (hipStream_t)stream;
+    const hipStream_t ns = (hipStream_t)stream;
+    if (ns != p->stream) {
+        // work queued on the old stream (the table upload of plan creation among it)
+        // comes before anything on the new one
+        hipEvent_t ev = nullptr;
+        MR1L_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        const hipError_t e1 = hipEventRecord(ev, p->stream);
+        const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(ns, ev, 0) : e1;
+        (void)hipEventDestroy(ev);
+        if (e2 != hipSuccess) return fail(MR1L_E_HIP, std::string("stream ordering failed: ") + hipGetErrorString(e2));
+    }
+    p->stream = ns;
     return MR1L_OK;
 }
 

@@ -113,7 +113,7 @@ __global__ void k_union_mark(const int64_t *__restrict__ n_out, const int64_t *_
     }
 }
 
-constexpr int kUnionWords = 1024;   // bitmap words per counting block (256 threads x 4)
+constexpr int kUnionWords = 256;   // bitmap words per counting block (one per thread)
 
 __device__ __forceinline__ int union_block_scan(int v, int *sh)
 {
@@ -129,14 +129,12 @@ __device__ __forceinline__ int union_block_scan(int v, int *sh)
     return sh[tid] - v;
 }
 
-__global__ __launch_bounds__(256) void k_union_count(const uint32_t *__restrict__ bits, int64_t nwords,
-                                                     int32_t *__restrict__ cnt)
+__global__ __launch_bounds__(kUnionWords) void k_union_count(const uint32_t *__restrict__ bits, int64_t nwords,
+                                                             int32_t *__restrict__ cnt)
 {
-    __shared__ int sh[256];
-    const int64_t w0 = (int64_t)blockIdx.x * kUnionWords + threadIdx.x * 4;
-    int c = 0;
-    for (int k = 0; k < 4; ++k)
-        if (w0 + k < nwords) c += __popc(bits[w0 + k]);
+    __shared__ int sh[kUnionWords];
+    const int64_t w = (int64_t)blockIdx.x * kUnionWords + threadIdx.x;
+    const int c = w < nwords ? __popc(bits[w]) : 0;
     const int before = union_block_scan(c, sh);
     if (threadIdx.x == blockDim.x - 1) cnt[blockIdx.x] = before + c;
 }
@@ -156,30 +154,22 @@ __global__ void k_union_scan(int nb, int32_t *__restrict__ cnt, int64_t *__restr
 
 // the union's tuples: column u of J at each set bit, in ascending order, to prev_out
 // (SoA [t][cap_prev]; entries beyond cap_prev are counted but not written)
-__global__ __launch_bounds__(256) void k_union_emit(const uint32_t *__restrict__ bits, int64_t nwords,
-                                                    const int32_t *__restrict__ off, const int64_t *__restrict__ J,
-                                                    int64_t Jstride, int t, int64_t cap_prev,
-                                                    int64_t *__restrict__ prev_out)
+__global__ __launch_bounds__(kUnionWords) void k_union_emit(const uint32_t *__restrict__ bits, int64_t nwords,
+                                                            const int32_t *__restrict__ off,
+                                                            const int64_t *__restrict__ J, int64_t Jstride, int t,
+                                                            int64_t cap_prev, int64_t *__restrict__ prev_out)
 {
-    __shared__ int sh[256];
-    const int64_t w0 = (int64_t)blockIdx.x * kUnionWords + threadIdx.x * 4;
-    uint32_t v[4];
-    int c = 0;
-    for (int k = 0; k < 4; ++k) {
-        v[k] = (w0 + k < nwords) ? bits[w0 + k] : 0u;
-        c += __popc(v[k]);
-    }
-    int64_t r = off[blockIdx.x] + union_block_scan(c, sh);
-    for (int k = 0; k < 4; ++k) {
-        uint32_t b = v[k];
-        while (b) {
-            const int j = __ffs(b) - 1;
-            b &= b - 1;
-            const int64_t q = (w0 + k) * 32 + j;
-            if (r < cap_prev)
-                for (int u = 0; u < t; ++u) prev_out[(int64_t)u * cap_prev + r] = J[(int64_t)u * Jstride + q];
-            ++r;
-        }
+    __shared__ int sh[kUnionWords];
+    const int64_t w = (int64_t)blockIdx.x * kUnionWords + threadIdx.x;
+    uint32_t b = w < nwords ? bits[w] : 0u;
+    int64_t r = off[blockIdx.x] + union_block_scan(__popc(b), sh);
+    while (b) {
+        const int j = __ffs(b) - 1;
+        b &= b - 1;
+        const int64_t q = w * 32 + j;
+        if (r < cap_prev)
+            for (int u = 0; u < t; ++u) prev_out[(int64_t)u * cap_prev + r] = J[(int64_t)u * Jstride + q];
+        ++r;
     }
 }
 
@@ -230,7 +220,7 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
 
     DevBuf<int64_t> dprev, dJ, n_det, det_idx, n_o, out_idx, dset;
     DevBuf<unsigned char> fbuf, gbuf, det_coef, out_coef;
-    DevBuf<uint32_t> bitmap, danc;
+    DevBuf<uint32_t> bitmap;
     int rc;
 
     // single-coordinate sets I^(t), t = 1..d
@@ -347,11 +337,14 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
     int64_t prev_stride = nprev;   // columns of the SoA tuples in dprev
     if ((rc = dprev.need(nprev))) return rc;
     MR1L_HIP(hipMemcpyAsync(dprev.p, I1[0].data(), nprev * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    DevBuf<int64_t> dnext, dstat, dsetoff, dtoff, drf;
+    DevBuf<int64_t> dnext, dstat, dstage, drf;
     DevBuf<unsigned char> drc;
     DevBuf<uint32_t> dbits;
     DevBuf<int32_t> dcnt;
-    bool long_lists = false;   // a step overflowed the short-list capacity: later steps take the long path
+    std::vector<int64_t> hst;   // a step's small host tables (uploaded in one copy)
+    std::vector<uint64_t> bdims;   // B-spline coordinate masks per repetition (uploaded by the sampler)
+    int rep_rt = 0;             // repetitions the replicated polynomial in drf/drc holds
+    bool long_lists = false;    // a step overflowed the short-list capacity: later steps take the long path
 
     for (int t = 2; t <= d; ++t) {
         const int rt = (t < d) ? P.r : 1;
@@ -379,56 +372,61 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
         std::vector<int64_t> Ms((size_t)rt * L, P.M);
         PlanHolder plan;
         if ((rc = mr1l_plan_create(&plan.p, t, rt, L, Ms.data(), z.data(), P.dtype, stream))) return rc;
-        // J in rt copies, and the sets' offsets
-        if ((rc = dJ.need(nJr * t)) || (rc = dset.need(Kt)) || (rc = dsetoff.need(rt + 1)) ||
-            (rc = danc.need((int64_t)anc.size())))
-            return rc;
-        std::vector<int64_t> so(rt + 1);
-        for (int f = 0; f <= rt; ++f) so[f] = (int64_t)f * nJ;
-        MR1L_HIP(hipMemcpyAsync(dset.p, It.data(), Kt * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        MR1L_HIP(hipMemcpyAsync(dsetoff.p, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        MR1L_HIP(hipMemcpyAsync(danc.p, anc.data(), anc.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        // the step's small tables in one upload: I^(t), the sets' offsets, the terms'
+        // offsets and the anchors (hst lives until the step's synchronisation)
+        const int64_t na = (int64_t)anc.size(), o_so = Kt, o_to = o_so + rt + 1, o_an = o_to + rt + 1;
+        hst.assign((size_t)(o_an + (na + 1) / 2), 0);
+        std::copy(It.begin(), It.end(), hst.begin());
+        for (int f = 0; f <= rt; ++f) {
+            hst[o_so + f] = (int64_t)f * nJ;
+            hst[o_to + f] = (int64_t)f * poly_s;
+        }
+        std::memcpy(hst.data() + o_an, anc.data(), (size_t)na * sizeof(uint32_t));
+        if ((rc = dJ.need(nJr * t)) || (rc = dstage.need((int64_t)hst.size()))) return rc;
+        MR1L_HIP(hipMemcpyAsync(dstage.p, hst.data(), hst.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        const int64_t *d_set = dstage.p, *d_setoff = dstage.p + o_so, *d_toff = dstage.p + o_to;
+        const uint32_t *d_anc = d > t ? (const uint32_t *)(dstage.p + o_an) : nullptr;
+        // J in rt copies
         const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((nJr + 255) / 256, 4096));
         hipLaunchKernelGGL(k_cartesian_rep, dim3((unsigned)blocks), dim3(256), 0, st, dprev.p, nprev, prev_stride,
-                           t - 1, dset.p, Kt, rt, dJ.p);
+                           t - 1, d_set, Kt, rt, dJ.p);
         MR1L_LAUNCH_CHECK();
 
         // samples of every repetition (Step 2b)
         const int64_t nodes_f = (int64_t)L * P.M, nodes = nodes_f * rt;
         if ((rc = fbuf.need(nodes * esz)) || (rc = gbuf.need(nodes * esz)) || (rc = bitmap.need((nodes + 31) / 32)))
             return rc;
-        std::vector<uint64_t> bdims;
-        std::vector<int64_t> toff(rt + 1);
         if (fn) {
             for (int i = 0; i < rt; ++i)
-                if (fn(user, t, L, Ms.data() + (size_t)i * L, z.data() + (size_t)i * L * t, anc.data() + (size_t)i * std::max(1, d - t),
-                       fbuf.p + (size_t)i * nodes_f * esz, stream) != 0)
+                if (fn(user, t, L, Ms.data() + (size_t)i * L, z.data() + (size_t)i * L * t,
+                       anc.data() + (size_t)i * std::max(1, d - t), fbuf.p + (size_t)i * nodes_f * esz, stream) != 0)
                     return fail(MR1L_E_ARG, "sampling callback failed");
         } else if (bsp) {
-            bdims.resize((size_t)rt * P.bs_n);
+            bdims.assign((size_t)rt * P.bs_n, 0u);
             for (int i = 0; i < rt; ++i)
                 for (int q = 0; q < P.bs_n; ++q) bdims[(size_t)i * P.bs_n + q] = P.bs_dims[q];
-            if ((rc = bspline_sample_run(plan_of(plan.p), d, P.bs_n, P.bs_order, bdims.data(), d > t ? danc.p : nullptr,
-                                         fbuf.p)))
+            if ((rc = bspline_sample_run(plan_of(plan.p), d, P.bs_n, P.bs_order, bdims.data(), d_anc, fbuf.p)))
                 return rc;
         } else {
-            // the polynomial's terms once per repetition
-            const int64_t cw = (int64_t)esz / 8;   // int64 words per coefficient
-            if ((rc = drf.need(std::max<int64_t>(1, (int64_t)d * poly_s * rt))) ||
-                (rc = drc.need(std::max<int64_t>(1, poly_s * rt) * (int64_t)esz)) || (rc = dtoff.need(rt + 1)))
-                return rc;
-            for (int f = 0; f <= rt; ++f) toff[f] = (int64_t)f * poly_s;
-            MR1L_HIP(hipMemcpyAsync(dtoff.p, toff.data(), toff.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-            if (poly_s > 0) {
-                const int64_t rb = std::max<int64_t>(1, std::min<int64_t>(((int64_t)d * poly_s * rt + 255) / 256, 4096));
-                hipLaunchKernelGGL(k_replicate, dim3((unsigned)rb), dim3(256), 0, st, poly_freq, d, poly_s, rt, drf.p);
-                MR1L_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_replicate, dim3((unsigned)rb), dim3(256), 0, st, (const int64_t *)poly_coef, 1,
-                                   poly_s * cw, rt, (int64_t *)drc.p);
-                MR1L_LAUNCH_CHECK();
+            // the polynomial's terms once per repetition (kept while rt stays the same)
+            if (rt != rep_rt) {
+                const int64_t cw = (int64_t)esz / 8;   // int64 words per coefficient
+                if ((rc = drf.need(std::max<int64_t>(1, (int64_t)d * poly_s * rt))) ||
+                    (rc = drc.need(std::max<int64_t>(1, poly_s * rt) * (int64_t)esz)))
+                    return rc;
+                if (poly_s > 0) {
+                    const int64_t rb =
+                        std::max<int64_t>(1, std::min<int64_t>(((int64_t)d * poly_s * rt + 255) / 256, 4096));
+                    hipLaunchKernelGGL(k_replicate, dim3((unsigned)rb), dim3(256), 0, st, poly_freq, d, poly_s, rt,
+                                       drf.p);
+                    MR1L_LAUNCH_CHECK();
+                    hipLaunchKernelGGL(k_replicate, dim3((unsigned)rb), dim3(256), 0, st, (const int64_t *)poly_coef,
+                                       1, poly_s * cw, rt, (int64_t *)drc.p);
+                    MR1L_LAUNCH_CHECK();
+                }
+                rep_rt = rt;
             }
-            if ((rc = mr1l_sample(plan.p, d, dtoff.p, poly_s * rt, drf.p, drc.p, d > t ? danc.p : nullptr, fbuf.p, 1)))
-                return rc;
+            if ((rc = mr1l_sample(plan.p, d, d_toff, poly_s * rt, drf.p, drc.p, d_anc, fbuf.p, 1))) return rc;
         }
         samples += nodes;
         if ((rc = mr1l_fft(plan.p, fbuf.p, gbuf.p, P.theta, bitmap.p))) return rc;
@@ -444,7 +442,7 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
             mr1l_extract_out ex{};
             ex.n_det = n_det.p; ex.det_idx = det_idx.p; ex.det_coef = det_coef.p;
             ex.n_out = n_o.p; ex.out_idx = out_idx.p; ex.out_coef = out_coef.p;
-            return mr1l_extract(plan.p, nJr, dsetoff.p, dJ.p, gbuf.p, bitmap.p, &o, &ex);
+            return mr1l_extract(plan.p, nJr, d_setoff, dJ.p, gbuf.p, bitmap.p, &o, &ex);
         };
         const int64_t long_cap = std::min<int64_t>(kMaxCapLarge, std::max<int64_t>(nJ, s_t));
         int64_t ecap = (long_lists || s_t > kMaxCap) ? long_cap : std::max<int64_t>(kMaxCap, s_t);
@@ -463,12 +461,13 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
                 const dim3 gm((unsigned)std::max<int64_t>(1, std::min<int64_t>((s_t + 255) / 256, 64)), (unsigned)rt);
                 hipLaunchKernelGGL(k_union_mark, gm, dim3(256), 0, st, n_o.p, out_idx.p, s_t, rt, dbits.p);
                 MR1L_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_union_count, dim3((unsigned)nb), dim3(256), 0, st, dbits.p, nwords, dcnt.p);
+                hipLaunchKernelGGL(k_union_count, dim3((unsigned)nb), dim3(kUnionWords), 0, st, dbits.p, nwords,
+                                   dcnt.p);
                 MR1L_LAUNCH_CHECK();
                 hipLaunchKernelGGL(k_union_scan, dim3(1), dim3(64), 0, st, nb, dcnt.p, dstat.p);
                 MR1L_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_union_emit, dim3((unsigned)nb), dim3(256), 0, st, dbits.p, nwords, dcnt.p, dJ.p,
-                                   nJr, t, cap_prev, dnext.p);
+                hipLaunchKernelGGL(k_union_emit, dim3((unsigned)nb), dim3(kUnionWords), 0, st, dbits.p, nwords,
+                                   dcnt.p, dJ.p, nJr, t, cap_prev, dnext.p);
                 MR1L_LAUNCH_CHECK();
                 MR1L_HIP(hipMemcpyAsync(dstat.p + 1, n_det.p, rt * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
                 return MR1L_OK;

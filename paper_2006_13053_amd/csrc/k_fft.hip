@@ -20,6 +20,7 @@
 // global scratch slot (it stays in L2/MALL) and the chirp and spectrum
 // products fused into the column load and the row store.
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 #include <initializer_list>
 #include <map>
@@ -970,23 +971,25 @@ static int ensure_scratch(Plan &p, int64_t len, int64_t slots)
     return MR1L_OK;
 }
 
-static int upload_list(int32_t **dst, const std::vector<int32_t> &v)
+// Spectrum layout kind of schedule s: 0 whole-LDS, 1 four-step, 2 split, 3 reg, -1
+// none (Rader keeps its own tables).
+static int spec_kind(int s)
 {
-    if (*dst) (void)hipFree(*dst);
-    *dst = nullptr;
-    if (v.empty()) return MR1L_OK;
-    MR1L_HIP(hipMalloc(dst, v.size() * sizeof(int32_t)));
-    MR1L_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    return MR1L_OK;
+    if (kSched[s].rader) return -1;
+    if (kSched[s].engine == 1) return 3;
+    if (kSched[s].engine == 2) return 2;
+    return kSched[s].four_step ? 1 : 0;
 }
 
-int fft_apply_schedules(Plan &p)
+static int fft_prepare_spectra(Plan &p);
+
+int fft_apply_schedules(Plan &p, bool fresh)
 {
-    MR1L_HIP(hipStreamSynchronize(p.stream));
+    // the device layout table and group lists may be read by queued work
+    if (!fresh) MR1L_HIP(hipStreamSynchronize(p.stream));
     for (size_t mid = 0; mid < p.minfo.size(); ++mid) p.mdesc[mid] = fft_layout(p, (int)mid, p.minfo[mid].sched);
-    MR1L_HIP(hipMemcpy(p.d_mdesc, p.mdesc.data(), p.mdesc.size() * sizeof(MDesc), hipMemcpyHostToDevice));
-    for (FftGroup &g : p.fft_groups)
-        if (g.d_lats) (void)hipFree(g.d_lats);
+    MR1L_HIP(hipMemcpyAsync(p.d_mdesc, p.mdesc.data(), p.mdesc.size() * sizeof(MDesc), hipMemcpyHostToDevice,
+                            p.stream));
     p.fft_groups.clear();
     std::map<std::pair<int, int>, size_t> gi;   // (schedule, class) -> group
     int64_t len = 0, slots = 0;
@@ -1013,15 +1016,35 @@ int fft_apply_schedules(Plan &p)
         if (kSched[mi.sched].four_step) len = std::max<int64_t>(len, mi.Np);
         if (kSched[mi.sched].engine == 2) len = std::max<int64_t>(len, (int64_t)(mi.Kq - 1) * mi.Nq);
     }
-    for (FftGroup &g : p.fft_groups) {
-        int rc = upload_list(&g.d_lats, g.lats);
-        if (rc) return rc;
+    // every group's lattice list in one device buffer (one copy)
+    p.h_glists.clear();
+    std::vector<size_t> goff;
+    for (const FftGroup &g : p.fft_groups) {
+        goff.push_back(p.h_glists.size());
+        p.h_glists.insert(p.h_glists.end(), g.lats.begin(), g.lats.end());
+    }
+    if ((int64_t)p.h_glists.size() > p.glists_cap) {
+        if (p.d_glists) (void)hipFree(p.d_glists);
+        p.d_glists = nullptr;
+        p.glists_cap = 0;
+        MR1L_HIP(hipMalloc(&p.d_glists, std::max<size_t>(p.h_glists.size(), 1) * sizeof(int32_t)));
+        p.glists_cap = (int64_t)p.h_glists.size();
+    }
+    if (!p.h_glists.empty())
+        MR1L_HIP(hipMemcpyAsync(p.d_glists, p.h_glists.data(), p.h_glists.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, p.stream));
+    for (size_t k = 0; k < p.fft_groups.size(); ++k) {
+        FftGroup &g = p.fft_groups[k];
+        g.d_lats = p.d_glists + goff[k];
         if (kSched[g.sched].four_step || kSched[g.sched].engine == 2)
             slots = std::max<int64_t>(slots, std::min<int64_t>((int64_t)g.lats.size(),
                                                                (int64_t)kSched[g.sched].per_cu * num_cus()));
     }
-    if (len > 0) return ensure_scratch(p, len, slots);
-    return MR1L_OK;
+    if (len > 0) {
+        const int rc = ensure_scratch(p, len, slots);
+        if (rc) return rc;
+    }
+    return fft_prepare_spectra(p);
 }
 
 int fft_time_plan(Plan &p, const void *in, void *out, int reps, float *ms)
@@ -1043,18 +1066,17 @@ int fft_time_plan(Plan &p, const void *in, void *out, int reps, float *ms)
     return rc;
 }
 
-// Kernel spectra of both layouts of every size: the LDS layout where it applies
-// and the power-of-two layout, computed by the DFT kernels themselves (SPEC mode)
-// on one representative lattice per size.
-int fft_prepare_spectra(Plan &p)
+// Kernel spectra of the layouts that the sizes' current schedules use and that are
+// not computed yet, computed by the DFT kernels themselves (SPEC mode) on one
+// representative lattice per size.  The passes' layout tables and representative
+// lists go to the plan's spectrum work buffer in one copy; work of an earlier call
+// that still reads that buffer has ended (it is only reused after a stream
+// synchronisation in fft_apply_schedules, or grown after one here).
+static int fft_prepare_spectra(Plan &p)
 {
     std::vector<int32_t> rep(p.minfo.size(), -1);
     for (size_t i = 0; i < p.lat.size(); ++i)
         if (rep[p.lat[i].mid] < 0) rep[p.lat[i].mid] = (int32_t)i;
-    MDesc *d_md = nullptr;
-    int32_t *d_rep = nullptr;
-    MR1L_HIP(hipMalloc(&d_md, p.mdesc.size() * sizeof(MDesc)));
-    int rc = MR1L_OK;
     // (schedule, class): the reg schedule runs one launch per transform length
     std::vector<std::pair<int, int>> passes = {{0, kLdsClasses - 1}, {kDefaultFourStep, 0}, {kSplitSched, 0}};
     {
@@ -1063,44 +1085,66 @@ int fft_prepare_spectra(Plan &p)
             if (mi.Nr && std::find(lens.begin(), lens.end(), mi.Nr) == lens.end()) lens.push_back(mi.Nr);
         for (int n : lens) passes.push_back({kRegSched, n});
     }
+    struct Pass {
+        int s, cls, n;
+        bool ltab;
+        size_t md_off, rep_off;
+    };
+    std::vector<Pass> todo;
+    std::vector<MDesc> mds;
+    std::vector<int32_t> reps;
+    int64_t len = 0, slots = 0;
     for (const auto &sc : passes) {
-        const int s = sc.first;
+        const int s = sc.first, kind = spec_kind(s);
         std::vector<MDesc> md(p.mdesc);
-        std::vector<int32_t> reps;
+        const size_t r0 = reps.size();
         bool ltab = true;
-        int64_t len = 0;
         for (size_t mid = 0; mid < p.minfo.size(); ++mid) {
-            if (!applies(p.minfo[mid], s) || rep[mid] < 0) continue;
-            if (s == kRegSched && p.minfo[mid].Nr != sc.second) continue;
+            const MInfo &mi = p.minfo[mid];
+            if (rep[mid] < 0 || spec_kind(mi.sched) != kind || (mi.spec_done >> kind & 1u)) continue;
+            if (s == kRegSched && mi.Nr != sc.second) continue;
             md[mid] = fft_layout(p, (int)mid, s);
             reps.push_back(rep[mid]);
-            ltab = ltab && p.minfo[mid].ltab;
-            len = std::max<int64_t>(len, s == kSplitSched ? (int64_t)(p.minfo[mid].Kq - 1) * p.minfo[mid].Nq
-                                                          : (int64_t)p.minfo[mid].Np);
+            ltab = ltab && mi.ltab;
+            len = std::max<int64_t>(len, s == kSplitSched ? (int64_t)(mi.Kq - 1) * mi.Nq : (int64_t)mi.Np);
         }
-        if (reps.empty()) continue;
-        if (kSched[s].four_step || kSched[s].engine == 2) {
-            rc = ensure_scratch(p, len, std::min<int64_t>((int64_t)reps.size(), (int64_t)kSched[s].per_cu * num_cus()));
-            if (rc) break;
-        }
-        rc = upload_list(&d_rep, reps);
-        if (rc) break;
-        if (hipMemcpy(d_md, md.data(), md.size() * sizeof(MDesc), hipMemcpyHostToDevice) != hipSuccess) {
-            rc = fail(MR1L_E_HIP, "copy of the spectrum layouts failed");
-            break;
-        }
-        // the largest LDS class holds every whole-LDS size
-        rc = launch_any(p, s, sc.second, d_rep, (int)reps.size(), d_md, ltab, nullptr, nullptr, 0.0, nullptr,
-                        FFT_SPEC, 1.0, 0);
-        if (rc) break;
-        if (hipStreamSynchronize(p.stream) != hipSuccess) {
-            rc = fail(MR1L_E_HIP, "spectrum computation failed");
-            break;
-        }
+        const int n = (int)(reps.size() - r0);
+        if (n == 0) continue;
+        if (kSched[s].four_step || kSched[s].engine == 2)
+            slots = std::max<int64_t>(slots, std::min<int64_t>(n, (int64_t)kSched[s].per_cu * num_cus()));
+        todo.push_back({s, sc.second, n, ltab, mds.size(), r0});
+        mds.insert(mds.end(), md.begin(), md.end());
     }
-    if (d_rep) (void)hipFree(d_rep);
-    (void)hipFree(d_md);
-    return rc;
+    if (todo.empty()) return MR1L_OK;
+    int rc = MR1L_OK;
+    if (slots > 0 && (rc = ensure_scratch(p, len, slots))) return rc;
+    const size_t md_bytes = mds.size() * sizeof(MDesc), rep_at = (md_bytes + 255) & ~size_t(255);
+    const size_t bytes = rep_at + reps.size() * sizeof(int32_t);
+    if ((int64_t)bytes > p.specwork_bytes) {
+        MR1L_HIP(hipStreamSynchronize(p.stream));
+        if (p.d_specwork) (void)hipFree(p.d_specwork);
+        p.d_specwork = nullptr;
+        p.specwork_bytes = 0;
+        MR1L_HIP(hipMalloc(&p.d_specwork, bytes));
+        p.specwork_bytes = (int64_t)bytes;
+    }
+    p.h_specwork.assign(bytes, 0);
+    std::memcpy(p.h_specwork.data(), mds.data(), md_bytes);
+    std::memcpy(p.h_specwork.data() + rep_at, reps.data(), reps.size() * sizeof(int32_t));
+    MR1L_HIP(hipMemcpyAsync(p.d_specwork, p.h_specwork.data(), bytes, hipMemcpyHostToDevice, p.stream));
+    const MDesc *d_md = (const MDesc *)p.d_specwork;
+    const int32_t *d_rep = (const int32_t *)((const unsigned char *)p.d_specwork + rep_at);
+    for (const Pass &ps : todo) {
+        rc = launch_any(p, ps.s, ps.cls, d_rep + ps.rep_off, ps.n, d_md + ps.md_off, ps.ltab, nullptr, nullptr, 0.0,
+                        nullptr, FFT_SPEC, 1.0, 0);
+        if (rc) return rc;
+    }
+    for (size_t mid = 0; mid < p.minfo.size(); ++mid) {
+        MInfo &mi = p.minfo[mid];
+        const int kind = spec_kind(mi.sched);
+        if (kind >= 0 && rep[mid] >= 0) mi.spec_done |= 1u << kind;
+    }
+    return MR1L_OK;
 }
 
 }  // namespace mr1l

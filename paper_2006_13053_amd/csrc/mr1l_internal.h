@@ -91,7 +91,7 @@ struct FftGroup {
     bool ltab = true;
     double work = 0.0;   // sum of M log M over the group (launch order)
     std::vector<int32_t> lats;
-    int32_t *d_lats = nullptr;
+    int32_t *d_lats = nullptr;   // into Plan::d_glists
 };
 constexpr int kLdsClasses = 3;     // whole-LDS transforms: N <= 1024, <= 4096, <= NMAX
 inline int lds_class(int64_t N) { return N <= 1024 ? 0 : (N <= 4096 ? 1 : 2); }
@@ -120,6 +120,7 @@ struct MInfo {
     int64_t spec_q = -1, tw_q = -1;
     int32_t sched = 0;
     int32_t nlat = 0;
+    uint32_t spec_done = 0;   // spectra computed, bit per layout kind (see fft_spec_kind)
 };
 
 // ---------------------------------------------------------------- plan
@@ -129,8 +130,22 @@ struct Plan {
     // DFT groups without scratch run concurrently on these (default priority) streams,
     // forked from and joined back into the plan's stream with the events
     static constexpr int kFftAux = 3;
-    hipStream_t fft_aux[kFftAux] = {};
+    hipStream_t fft_aux[kFftAux] = {};   // the device's shared pool (never destroyed)
     hipEvent_t fft_ev[kFftAux + 1] = {};
+    // the small device tables (descriptors, z, vote records, twiddles, chirps, Rader
+    // tables, counters) in one allocation, uploaded by one copy from h_arena (kept
+    // with the plan, so the copy may run after plan creation returns)
+    void *d_arena = nullptr;
+    std::vector<unsigned char> h_arena;
+    std::vector<std::pair<void **, size_t>> arena_fix;
+    // the DFT groups' lattice lists, concatenated (host copy kept for the async upload)
+    int32_t *d_glists = nullptr;
+    int64_t glists_cap = 0;
+    std::vector<int32_t> h_glists;
+    // spectrum passes: per-pass layout tables and representative lattices
+    void *d_specwork = nullptr;
+    int64_t specwork_bytes = 0;
+    std::vector<unsigned char> h_specwork;
     int64_t nodes = 0;
     std::vector<int64_t> M;          // host [F*L]
     std::vector<int64_t> z;          // host [F*L*d]
@@ -252,8 +267,9 @@ int grow_scratch(Plan &p, void **ptr, int64_t bytes, int64_t &have);
 
 int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap,
             int mode, double scale);
-int fft_prepare_spectra(Plan &p);
-int fft_apply_schedules(Plan &p);
+// Layouts, groups and (lazily) the spectra of the sizes' current schedules; a plan
+// that has run nothing yet (fresh) skips the stream synchronisation.
+int fft_apply_schedules(Plan &p, bool fresh = false);
 bool fft_schedule_applies(const MInfo &mi, int s);
 int tuned_schedule(int32_t dtype, int64_t M);
 MDesc fft_layout(const Plan &p, int mid, int s);   // table entry of size mid under schedule s
