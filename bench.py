@@ -653,6 +653,25 @@ def copy_bandwidth(torch, nbytes=1 << 31):
     return 2.0 * nbytes / (best * 1e-3) / 1e9
 
 
+def read_bandwidth(torch, nbytes=1 << 31):
+    """Measured HBM rate of a plain device read (torch's int64 sum reduction over nbytes):
+    bytes read over the best of four reductions, in GB/s (a read-only stream to set the
+    vote pass, which only reads, against)."""
+    a = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    best = None
+    for _ in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s = a.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    assert int(s.item()) == nbytes // 8
+    del a
+    return nbytes / (best * 1e-3) / 1e9
+
+
 def cpu_baseline_large(w, budget_s=10.0):
     """Oracle on one function of the batch, repeated until ~budget_s of CPU time: direct
     O(M^2) DFTs of its 20 lattices (on synthetic samples of the same size) and Algorithm 2
@@ -946,6 +965,7 @@ def headline(m, torch, args, w, cfg, dtype, F):
                 traffic = pmc.get("bytes_per_launch")
         vote["traffic"] = traffic
         vote["copy_GBps"] = copy_bandwidth(torch)
+        vote["read_GBps"] = read_bandwidth(torch)
         out["roofline"] = {k: vote[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
         out["roofline"].update({k: v for k, v in vote.items() if k not in out["roofline"]})
         out["fft_roofline"] = fft

@@ -2,7 +2,8 @@
 // output limitation.
 //
 //  k_sort_det    detected set of each function in ascending candidate order
-//                (one workgroup per function, bitonic sort in LDS).
+//                (one workgroup per function, bitonic sort in registers, lane
+//                shuffles and, for the longest distances only, LDS).
 //  k_det_hash    buckets h_l(k) of every detected candidate.
 //  k_singleton   whether each bucket holds one or several detected candidates,
 //                one workgroup per lattice with two LDS bitmaps; bit l of
@@ -14,7 +15,7 @@
 //                singleton average of Remark 2.9, plus the weights of the
 //                coefficient as a real-linear map of the lattice values.
 //  k_limit       Algorithm 4: |p| >= theta, descending modulus, ties by
-//                ascending candidate index, first s~ (bitonic sort in LDS).
+//                ascending candidate index, first s~ (the same block sort).
 //  k_adjoint_scatter  transpose of the gather/combination: coefficient
 //                gradients into buckets (the inverse lattice DFT follows).
 #include <algorithm>
@@ -42,38 +43,123 @@ __device__ __forceinline__ int64_t n_of(const int64_t *n_det, int f, int64_t cap
     return n < cap ? n : cap;
 }
 
+// ------------------------------------------------------------------ block sort
+// Bitonic sort of P = 2^p (key, value) pairs ascending by key, ties by value, held E
+// per thread in registers: thread t holds positions tE .. tE + E - 1 (threads t < P/E
+// take part; E <= P <= E x blockDim.x).  Compare-exchange partners closer than E sit
+// in the same thread, those closer than 64 E in the same wave (exchanged by lane
+// shuffles); only the stages with larger distances go through LDS (lk, lv: P entries
+// each), with two barriers each.  Every thread of the block must call it.
+__device__ __forceinline__ bool kv_gt(uint64_t ka, int32_t va, uint64_t kb, int32_t vb)
+{
+    return ka > kb || (ka == kb && va > vb);
+}
+
+template <int E>
+__device__ __forceinline__ void block_bitonic(uint64_t (&k)[E], int32_t (&v)[E], int P, uint64_t *lk, int32_t *lv)
+{
+    const int t = threadIdx.x, na = P / E;
+    const bool act = t < na;
+    for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= 64 * E) {
+                if (act)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) { lk[t * E + e] = k[e]; lv[t * E + e] = v[e]; }
+                __syncthreads();
+                if (act)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int p = t * E + e, q = p ^ j;
+                        const uint64_t kb = lk[q];
+                        const int32_t vb = lv[q];
+                        const bool gt = kv_gt(k[e], v[e], kb, vb);
+                        if ((((p & j) == 0) == ((p & kk) == 0)) ? gt : !gt) { k[e] = kb; v[e] = vb; }
+                    }
+                __syncthreads();
+            } else if (j >= E) {
+                const int m = j / E;
+                const bool lower = (t & m) == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const uint64_t kb = __shfl_xor(k[e], m);
+                    const int32_t vb = __shfl_xor(v[e], m);
+                    const bool asc = ((t * E + e) & kk) == 0;
+                    const bool gt = kv_gt(k[e], v[e], kb, vb);
+                    if (act && ((lower == asc) ? gt : !gt)) { k[e] = kb; v[e] = vb; }
+                }
+            } else {
+#pragma unroll
+                for (int jj = E / 2; jj >= 1; jj >>= 1)
+                    if (jj == j)
+#pragma unroll
+                        for (int e = 0; e < E; ++e)
+                            if ((e & jj) == 0) {
+                                const int e2 = e | jj;
+                                const bool asc = ((t * E + e) & kk) == 0;
+                                if (kv_gt(k[e], v[e], k[e2], v[e2]) == asc) {
+                                    const uint64_t tk = k[e]; k[e] = k[e2]; k[e2] = tk;
+                                    const int32_t tv = v[e]; v[e] = v[e2]; v[e2] = tv;
+                                }
+                            }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int sort_len(int n, int E)
+{
+    int P = E;
+    while (P < n) P <<= 1;
+    return P;
+}
+
 // ------------------------------------------------------------------ sort detected
-// Dynamic LDS: pow2ceil(cap) keys.
+// Dynamic LDS: pow2ceil(cap) x 12 bytes (the sort's exchange arrays); E = pow2ceil(cap)
+// / kSortThreads values per thread, at least 1.
+template <int E>
 __global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__restrict__ n_det, int64_t cap,
                                                            int64_t *__restrict__ det_idx)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    int64_t *key = reinterpret_cast<int64_t *>(smem);
-    const int f = blockIdx.x;
+    const int f = blockIdx.x, t = threadIdx.x;
     const int n = (int)n_of(n_det, f, cap);
     if (n <= 1) return;
-    int P = 1;
-    while (P < n) P <<= 1;
+    const int P = sort_len(n, E);
+    uint64_t *lk = reinterpret_cast<uint64_t *>(smem);
+    int32_t *lv = reinterpret_cast<int32_t *>(lk + P);
     int64_t *src = det_idx + (int64_t)f * cap;
-    for (int i = threadIdx.x; i < P; i += kSortThreads) key[i] = (i < n) ? src[i] : INT64_MAX;
-    __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += kSortThreads) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const bool asc = (i & k) == 0;
-                    const int64_t a = key[i], b = key[ixj];
-                    if ((a > b) == asc) { key[i] = b; key[ixj] = a; }
-                }
-            }
-            __syncthreads();
-        }
+    uint64_t k[E];
+    int32_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = t * E + e;
+        k[e] = (p < n) ? (uint64_t)src[p] : ~0ull;   // indices are non-negative
+        v[e] = 0;
     }
-    for (int i = threadIdx.x; i < n; i += kSortThreads) src[i] = key[i];
+    block_bitonic<E>(k, v, P, lk, lv);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (t * E + e < n) src[t * E + e] = (int64_t)k[e];
 }
 
 // ------------------------------------------------------------------ hashes of detected
+// Bucket of candidate column ci in lattice ld: the fast 32-bit hash when every
+// coordinate is within the function's bound kb, else the exact 64-bit reduction.
+__device__ __forceinline__ int32_t det_bucket(const int64_t *__restrict__ freq, int64_t n_total, int64_t ci, int d,
+                                              const LatDesc &ld, const int32_t *__restrict__ z32,
+                                              const int64_t *__restrict__ z64, int32_t kb)
+{
+    uint32_t s = ld.off32;
+    bool fast = true;
+    for (int u = 0; u < d; ++u) {
+        const int64_t k = freq[(int64_t)u * n_total + ci];
+        fast = fast & (k >= -kb) & (k <= kb);
+        s += (uint32_t)__mul24((int32_t)k, z32[ld.z_off + u]);
+    }
+    return fast ? (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m) : exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
+}
+
 // One thread per (detected candidate, lattice): the L threads of a candidate read
 // the same coordinates (cache hits after the first) and write adjacent buckets.
 __global__ __launch_bounds__(256) void k_det_hash(
@@ -88,18 +174,7 @@ __global__ __launch_bounds__(256) void k_det_hash(
     const int64_t q = t / L;
     const int l = (int)(t - q * L);
     const int64_t ci = set_off[f] + det_idx[(int64_t)f * cap + q];
-    const int32_t kb = kbound[f];
-    const LatDesc ld = lat[f * L + l];
-    uint32_t s = ld.off32;
-    bool fast = true;
-    for (int u = 0; u < d; ++u) {
-        const int64_t k = freq[(int64_t)u * n_total + ci];
-        fast = fast & (k >= -kb) & (k <= kb);
-        s += (uint32_t)__mul24((int32_t)k, z32[ld.z_off + u]);
-    }
-    const int32_t h = fast ? (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m)
-                           : exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
-    det_hash[((int64_t)f * cap + q) * L + l] = h;
+    det_hash[((int64_t)f * cap + q) * L + l] = det_bucket(freq, n_total, ci, d, lat[f * L + l], z32, z64, kbound[f]);
     }
 }
 
@@ -388,69 +463,60 @@ __global__ __launch_bounds__(64) void k_combine_wide(
 }
 
 // ------------------------------------------------------------------ limit (Algorithm 4)
-// Dynamic LDS: pow2ceil(cap) keys and positions.
+// Dynamic LDS: pow2ceil(cap) x 12 bytes (the sort's exchange arrays).
 template <typename T>
+__device__ __forceinline__ uint64_t limit_key(typename cvec<T>::type c, T th2, bool &pass)
+{
+    const T m2 = c.x * c.x + c.y * c.y;
+    pass = m2 >= th2;
+    return pass ? ~(uint64_t)__double_as_longlong((double)m2) : ~0ull;   // m2 >= 0: bits are monotonic
+}
+
+template <typename T, int E>
 __global__ __launch_bounds__(kSortThreads) void k_limit(
     const int64_t *__restrict__ n_det, int64_t cap, const int64_t *__restrict__ det_idx,
     const typename cvec<T>::type *__restrict__ det_coef, T th2, int64_t s_cap, int64_t *__restrict__ n_out,
     int64_t *__restrict__ out_idx, typename cvec<T>::type *__restrict__ out_coef, int32_t *__restrict__ out_pos)
 {
     using V = typename cvec<T>::type;
-    extern __shared__ __align__(16) unsigned char smem[];   // pow2ceil(cap) keys, then positions
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int npass;
-    int Pc = 1;
-    while (Pc < cap) Pc <<= 1;
-    uint64_t *key = reinterpret_cast<uint64_t *>(smem);
-    int32_t *pos = reinterpret_cast<int32_t *>(key + Pc);
-    const int f = blockIdx.x;
+    const int f = blockIdx.x, t = threadIdx.x;
     const int n = (int)n_of(n_det, f, cap);
-    if (threadIdx.x == 0) npass = 0;
-    int P = 1;
-    while (P < n) P <<= 1;
+    const int P = sort_len(n, E);
+    uint64_t *lk = reinterpret_cast<uint64_t *>(smem);
+    int32_t *lv = reinterpret_cast<int32_t *>(lk + P);
+    if (t == 0) npass = 0;
     __syncthreads();
     const V *dc = det_coef + (int64_t)f * cap;
-    for (int i = threadIdx.x; i < P; i += kSortThreads) {
-        uint64_t k = ~0ull;
-        int32_t ps = INT32_MAX;
-        if (i < n) {
-            const V c = dc[i];
-            const T m2 = c.x * c.x + c.y * c.y;
-            if (m2 >= th2) {
-                const double md = (double)m2;
-                k = ~(uint64_t)__double_as_longlong(md);   // m2 >= 0: bits are monotonic
-                ps = i;
-                atomicAdd(&npass, 1);
-            }
+    uint64_t k[E];
+    int32_t v[E];
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = t * E + e;
+        k[e] = ~0ull;
+        v[e] = INT32_MAX;
+        if (p < n) {
+            bool pass;
+            k[e] = limit_key<T>(dc[p], th2, pass);
+            if (pass) { v[e] = p; ++cnt; }
         }
-        key[i] = k;
-        pos[i] = ps;
     }
+    if (cnt) atomicAdd(&npass, cnt);
+    block_bitonic<E>(k, v, P, lk, lv);
     __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += kSortThreads) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const bool asc = (i & k) == 0;
-                    const uint64_t a = key[i], b = key[ixj];
-                    const int32_t pa = pos[i], pb = pos[ixj];
-                    const bool gt = (a > b) || (a == b && pa > pb);
-                    if (gt == asc) {
-                        key[i] = b; key[ixj] = a;
-                        pos[i] = pb; pos[ixj] = pa;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
     const int64_t no = min((int64_t)npass, s_cap);
-    if (threadIdx.x == 0) n_out[f] = no;
-    for (int o = threadIdx.x; o < no; o += kSortThreads) {
-        const int q = pos[o];
-        out_idx[(int64_t)f * s_cap + o] = det_idx[(int64_t)f * cap + q];
-        out_coef[(int64_t)f * s_cap + o] = dc[q];
-        if (out_pos) out_pos[(int64_t)f * s_cap + o] = q;
+    if (t == 0) n_out[f] = no;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int o = t * E + e;
+        if (o < no) {
+            const int q = v[e];
+            out_idx[(int64_t)f * s_cap + o] = det_idx[(int64_t)f * cap + q];
+            out_coef[(int64_t)f * s_cap + o] = dc[q];
+            if (out_pos) out_pos[(int64_t)f * s_cap + o] = q;
+        }
     }
 }
 
@@ -733,17 +799,26 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, int64_t nm
     return MR1L_OK;
 }
 
-int extract_init_attrs()
+template <int E>
+static int sort_attrs()
 {
     // dynamic LDS at the largest capacity (static LDS comes on top of it)
+    const void *ks[] = {(const void *)k_sort_det<E>, (const void *)k_limit<double, E>, (const void *)k_limit<float, E>};
+    for (const void *k : ks) MR1L_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxCap * 12));
+    return MR1L_OK;
+}
+
+int extract_init_attrs()
+{
     const std::pair<const void *, int> ks[] = {
         {(const void *)k_singleton, 2 * kSingleWords * (int)sizeof(uint32_t)},
-        {(const void *)k_single_count, 2 * kSingleWords * (int)sizeof(uint32_t)},
-        {(const void *)k_sort_det, kMaxCap * (int)sizeof(int64_t)},
-        {(const void *)k_limit<double>, kMaxCap * 12},
-        {(const void *)k_limit<float>, kMaxCap * 12}};
+        {(const void *)k_single_count, 2 * kSingleWords * (int)sizeof(uint32_t)}};
     for (const auto &k : ks) MR1L_HIP(hipFuncSetAttribute(k.first, hipFuncAttributeMaxDynamicSharedMemorySize, k.second));
-    return MR1L_OK;
+    int rc = sort_attrs<1>();
+    if (!rc) rc = sort_attrs<2>();
+    if (!rc) rc = sort_attrs<4>();
+    if (!rc) rc = sort_attrs<8>();
+    return rc;
 }
 
 static int64_t pow2ceil(int64_t n)
@@ -752,6 +827,20 @@ static int64_t pow2ceil(int64_t n)
     while (P < n) P <<= 1;
     return P;
 }
+
+// Values per thread of the block sorts for capacity cap <= kMaxCap: pow2ceil(cap) /
+// kSortThreads, at least 1.
+static int sort_e(int64_t cap)
+{
+    return (int)std::max<int64_t>(1, pow2ceil(std::max<int64_t>(cap, 1)) / kSortThreads);
+}
+#define MR1L_BY_E(E_, X)           \
+    switch (E_) {                  \
+    case 1: X(1); break;           \
+    case 2: X(2); break;           \
+    case 4: X(4); break;           \
+    default: X(8); break;          \
+    }
 
 static int grow_sort(Plan &p, int64_t P)
 {
@@ -814,6 +903,26 @@ static int long_list_size(Plan &p, const int64_t *n_det, int64_t cap, int64_t &n
     return grow_sort(p, P);
 }
 
+// Algorithm 4 on lists of at most kMaxCap entries: one workgroup per function.
+static int limit_short(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef,
+                       double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef, int32_t *out_pos)
+{
+    const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
+#define MR1L_LD(E)                                                                                                 \
+    hipLaunchKernelGGL((k_limit<double, E>), dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, n_det, cap, det_idx, \
+                       (const double2 *)det_coef, theta * theta, s_cap, n_out, out_idx, (double2 *)out_coef, out_pos)
+#define MR1L_LF(E)                                                                                                \
+    hipLaunchKernelGGL((k_limit<float, E>), dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, n_det, cap, det_idx, \
+                       (const float2 *)det_coef, (float)(theta * theta), s_cap, n_out, out_idx, (float2 *)out_coef,  \
+                       out_pos)
+    if (p.dtype == MR1L_C128) MR1L_BY_E(sort_e(cap), MR1L_LD)
+    else MR1L_BY_E(sort_e(cap), MR1L_LF)
+#undef MR1L_LD
+#undef MR1L_LF
+    MR1L_LAUNCH_CHECK();
+    return MR1L_OK;
+}
+
 int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, const void *ghat,
                      const mr1l_extract_opts &o, const mr1l_extract_out &out, int32_t *det_hash, double *det_w,
                      uint32_t *det_mask, void *det_med, int32_t *out_pos)
@@ -824,8 +933,10 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     int rc = MR1L_OK;
     if (!large) {
         const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
-        hipLaunchKernelGGL(k_sort_det, dim3(p.F), dim3(kSortThreads), pc * sizeof(int64_t), p.stream, out.n_det, cap,
-                           out.det_idx);
+#define MR1L_SD(E) \
+    hipLaunchKernelGGL(k_sort_det<E>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap, out.det_idx)
+        MR1L_BY_E(sort_e(cap), MR1L_SD)
+#undef MR1L_SD
         MR1L_LAUNCH_CHECK();
     } else {
         // the buffer sizes come from the detected counts and the set offsets
@@ -909,18 +1020,8 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
                                    det_med, det_w);
     if (rc) return rc;
     if (!large) {
-        const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
-        if (p.dtype == MR1L_C128) {
-            hipLaunchKernelGGL(k_limit<double>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap,
-                               out.det_idx, (const double2 *)out.det_coef, o.theta * o.theta, o.s_cap, out.n_out,
-                               out.out_idx, (double2 *)out.out_coef, out_pos);
-        } else {
-            hipLaunchKernelGGL(k_limit<float>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap,
-                               out.det_idx, (const float2 *)out.det_coef, (float)(o.theta * o.theta), o.s_cap,
-                               out.n_out, out.out_idx, (float2 *)out.out_coef, out_pos);
-        }
-        MR1L_LAUNCH_CHECK();
-        return MR1L_OK;
+        return limit_short(p, out.n_det, cap, out.det_idx, out.det_coef, o.theta, o.s_cap, out.n_out, out.out_idx,
+                           out.out_coef, out_pos);
     }
     return limit_long(p, out.n_det, cap, out.det_idx, out.det_coef, o.theta, o.s_cap, out.n_out, out.out_idx,
                       out.out_coef, out_pos, P);
@@ -935,17 +1036,7 @@ int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx
         const int rc = long_list_size(p, n_det, cap, nmax, P);
         return rc ? rc : limit_long(p, n_det, cap, det_idx, det_coef, theta, s_cap, n_out, out_idx, out_coef, nullptr, P);
     }
-    const size_t pc = (size_t)pow2ceil(cap);
-    if (p.dtype == MR1L_C128)
-        hipLaunchKernelGGL(k_limit<double>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, n_det, cap, det_idx,
-                           (const double2 *)det_coef, theta * theta, s_cap, n_out, out_idx, (double2 *)out_coef,
-                           (int32_t *)nullptr);
-    else
-        hipLaunchKernelGGL(k_limit<float>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, n_det, cap, det_idx,
-                           (const float2 *)det_coef, (float)(theta * theta), s_cap, n_out, out_idx,
-                           (float2 *)out_coef, (int32_t *)nullptr);
-    MR1L_LAUNCH_CHECK();
-    return MR1L_OK;
+    return limit_short(p, n_det, cap, det_idx, det_coef, theta, s_cap, n_out, out_idx, out_coef, nullptr);
 }
 
 int adjoint_run(Plan &p, int64_t cap, int64_t s_cap, const int64_t *n_out, const int32_t *out_pos,
