@@ -81,14 +81,19 @@ __global__ __launch_bounds__(rader_threads<P>()) void k_rader(
     }
     if ((tid & 63) == 0) { red[2 * (tid >> 6)] = sr; red[2 * (tid >> 6) + 1] = si; }
     __syncthreads();
-    // a[q] = f[g^q] in the first pass's input layout (q = t + NT c + m P / R0)
-    int gidx[E];
+    // a[q] = f[g^q] in the first pass's input layout (q = t + NT c + m P / R0); the
+    // gather positions (< P < 2^16) are kept two to a register
+    static_assert(E % 2 == 0 && P < 65536, "gather positions are packed in 16-bit pairs");
+    uint32_t gpk[E / 2];
+    auto gidx = [&](int e) -> int { return (int)((e & 1) ? (gpk[e >> 1] >> 16) : (gpk[e >> 1] & 0xffffu)); };
     if (act) {
         const int tt = lf::opq(t);
 #pragma unroll
-        for (int e = 0; e < E; ++e) gidx[e] = pin[lf::in_pos<P, E, R0>(tt, e / R0, e % R0)] - 1;
+        for (int e = 0; e < E; e += 2)
+            gpk[e / 2] = (uint32_t)(pin[lf::in_pos<P, E, R0>(tt, e / R0, e % R0)] - 1) |
+                         ((uint32_t)(pin[lf::in_pos<P, E, R0>(tt, (e + 1) / R0, (e + 1) % R0)] - 1) << 16);
 #pragma unroll
-        for (int e = 0; e < E; ++e) xr[e] = pl[lf::padq<T, E>(gidx[e])];
+        for (int e = 0; e < E; ++e) xr[e] = pl[lf::padq<T, E>(gidx(e))];
     }
     __syncthreads();
     if (act) {
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(rader_threads<P>()) void k_rader(
     __syncthreads();
     if (act)
 #pragma unroll
-        for (int e = 0; e < E; ++e) xi[e] = pl[lf::padq<T, E>(gidx[e])];
+        for (int e = 0; e < E; ++e) xi[e] = pl[lf::padq<T, E>(gidx(e))];
     __syncthreads();
 
     // forward length-P DFT of a; times the spectrum of b (with 1/P), conjugated; the
@@ -126,9 +131,11 @@ __global__ __launch_bounds__(rader_threads<P>()) void k_rader(
     if (act) {
         const int tt = lf::opq(t);
 #pragma unroll
-        for (int e = 0; e < E; ++e) gidx[e] = pout[tt + NT * (e / RL) + (e % RL) * (P / RL)] - 1;
+        for (int e = 0; e < E; e += 2)
+            gpk[e / 2] = (uint32_t)(pout[tt + NT * (e / RL) + (e % RL) * (P / RL)] - 1) |
+                         ((uint32_t)(pout[tt + NT * ((e + 1) / RL) + ((e + 1) % RL) * (P / RL)] - 1) << 16);
 #pragma unroll
-        for (int e = 0; e < E; ++e) pl[lf::padq<T, E>(gidx[e])] = (f0.x + xr[e]) * sc;
+        for (int e = 0; e < E; ++e) pl[lf::padq<T, E>(gidx(e))] = (f0.x + xr[e]) * sc;
     }
     __syncthreads();
     if (act) {
@@ -139,7 +146,7 @@ __global__ __launch_bounds__(rader_threads<P>()) void k_rader(
     __syncthreads();
     if (act)
 #pragma unroll
-        for (int e = 0; e < E; ++e) pl[lf::padq<T, E>(gidx[e])] = cj * (f0.y - xi[e]) * sc;
+        for (int e = 0; e < E; ++e) pl[lf::padq<T, E>(gidx(e))] = cj * (f0.y - xi[e]) * sc;
     __syncthreads();
     V *y = out + ld.node_off;
     const int tt = lf::opq(t);
