@@ -49,7 +49,8 @@ __device__ __forceinline__ int64_t n_of(const int64_t *n_det, int f, int64_t cap
 // take part; E <= P <= E x blockDim.x).  Compare-exchange partners closer than E sit
 // in the same thread, those closer than 64 E in the same wave (exchanged by lane
 // shuffles); only the stages with larger distances go through LDS (lk, lv: P entries
-// each), with two barriers each.  Every thread of the block must call it.
+// each, value e of thread t at e P/E + t), with two barriers each.  Every thread of
+// the block must call it.
 __device__ __forceinline__ bool kv_gt(uint64_t ka, int32_t va, uint64_t kb, int32_t vb)
 {
     return ka > kb || (ka == kb && va > vb);
@@ -63,16 +64,19 @@ __device__ __forceinline__ void block_bitonic(uint64_t (&k)[E], int32_t (&v)[E],
     for (int kk = 2; kk <= P; kk <<= 1) {
         for (int j = kk >> 1; j > 0; j >>= 1) {
             if (j >= 64 * E) {
+                // the partner of position tE + e is (t ^ m)E + e (m = j / E): value e of
+                // every thread sits at lk[e na + t], so a wave's lanes touch consecutive words
+                const int m = j / E;
                 if (act)
 #pragma unroll
-                    for (int e = 0; e < E; ++e) { lk[t * E + e] = k[e]; lv[t * E + e] = v[e]; }
+                    for (int e = 0; e < E; ++e) { lk[e * na + t] = k[e]; lv[e * na + t] = v[e]; }
                 __syncthreads();
                 if (act)
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
-                        const int p = t * E + e, q = p ^ j;
-                        const uint64_t kb = lk[q];
-                        const int32_t vb = lv[q];
+                        const int p = t * E + e;
+                        const uint64_t kb = lk[e * na + (t ^ m)];
+                        const int32_t vb = lv[e * na + (t ^ m)];
                         const bool gt = kv_gt(k[e], v[e], kb, vb);
                         if ((((p & j) == 0) == ((p & kk) == 0)) ? gt : !gt) { k[e] = kb; v[e] = vb; }
                     }
