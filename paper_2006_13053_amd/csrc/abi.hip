@@ -260,7 +260,7 @@ static int build_tables(Plan &p)
             mi.Kq = (int32_t)K;
             mi.Bq = (int32_t)((M + K - 1) / K);
             mi.spec_q = spec_len;
-            spec_len += (2 * K - 1) * kSplitLen;
+            spec_len += K * kSplitLen;   // segments 0 .. K - 1 (the chirp is even)
             mi.tw_q = twoff(kSplitLen);
         }
         // Rader's algorithm in registers for prime M with M - 1 = 2^a 5^b

@@ -119,20 +119,78 @@ __device__ __forceinline__ int sort_len(int n, int E)
 }
 
 // ------------------------------------------------------------------ sort detected
-// Dynamic LDS: pow2ceil(cap) x 12 bytes (the sort's exchange arrays); E = pow2ceil(cap)
-// / kSortThreads values per thread, at least 1.
+// Dynamic LDS: max(pow2ceil(cap) x 12, kSortBitmapBytes) bytes.  A function whose
+// candidate set has at most 8 x (that many) members takes the ordered compaction of a
+// bitmap over its set in LDS (one bit per detected candidate, then per-thread counts,
+// a block scan and the emission: O(|I_f| / 32 + n) work); larger sets take the block
+// sort, E = pow2ceil(cap) / kSortThreads values per thread, at least 1.
+constexpr int kSortBitmapBytes = 128 * 1024;
+
+__device__ __forceinline__ int block_excl_scan(int v, int *wsum)
+{
+    // inclusive scan within the wave, then the waves' totals
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int k = 0; k < nw; ++k) {
+            const int t = wsum[k];
+            wsum[k] = acc;
+            acc += t;
+        }
+    }
+    __syncthreads();
+    return wsum[w] + x - v;
+}
+
 template <int E>
 __global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__restrict__ n_det, int64_t cap,
-                                                           int64_t *__restrict__ det_idx)
+                                                           int64_t *__restrict__ det_idx,
+                                                           const int64_t *__restrict__ set_off, int64_t n_total,
+                                                           int region_bytes)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int wsum[kSortThreads / 64];
     const int f = blockIdx.x, t = threadIdx.x;
     const int n = (int)n_of(n_det, f, cap);
     if (n <= 1) return;
+    int64_t *src = det_idx + (int64_t)f * cap;
+    const int64_t nset = set_off ? set_off[f + 1] - set_off[f] : n_total;
+    if (nset <= (int64_t)region_bytes * 8) {
+        uint32_t *bm = reinterpret_cast<uint32_t *>(smem);
+        const int nw = (int)((nset + 31) >> 5);
+        for (int w = t; w < nw; w += kSortThreads) bm[w] = 0u;
+        __syncthreads();
+        for (int p = t; p < n; p += kSortThreads) {
+            const int64_t q = src[p];
+            atomicOr(bm + (q >> 5), 1u << (q & 31));
+        }
+        __syncthreads();
+        // thread t owns words [t c, t c + c)
+        const int c = (nw + kSortThreads - 1) / kSortThreads, w0 = min(nw, t * c), w1 = min(nw, w0 + c);
+        int cnt = 0;
+        for (int w = w0; w < w1; ++w) cnt += __popc(bm[w]);
+        int o = block_excl_scan(cnt, wsum);
+        for (int w = w0; w < w1; ++w) {
+            uint32_t b = bm[w];
+            while (b) {
+                const int k = __ffs(b) - 1;
+                b &= b - 1;
+                src[o++] = (int64_t)w * 32 + k;
+            }
+        }
+        return;
+    }
     const int P = sort_len(n, E);
     uint64_t *lk = reinterpret_cast<uint64_t *>(smem);
     int32_t *lv = reinterpret_cast<int32_t *>(lk + P);
-    int64_t *src = det_idx + (int64_t)f * cap;
     uint64_t k[E];
     int32_t v[E];
 #pragma unroll
@@ -808,7 +866,9 @@ static int sort_attrs()
 {
     // dynamic LDS at the largest capacity (static LDS comes on top of it)
     const void *ks[] = {(const void *)k_sort_det<E>, (const void *)k_limit<double, E>, (const void *)k_limit<float, E>};
-    for (const void *k : ks) MR1L_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxCap * 12));
+    for (const void *k : ks)
+        MR1L_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     std::max(kMaxCap * 12, kSortBitmapBytes)));
     return MR1L_OK;
 }
 
@@ -936,9 +996,10 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     int64_t nmax = cap, P = 1;
     int rc = MR1L_OK;
     if (!large) {
-        const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
+        const size_t sb = std::max<size_t>((size_t)pow2ceil(std::max<int64_t>(cap, 1)) * 12, kSortBitmapBytes);
 #define MR1L_SD(E) \
-    hipLaunchKernelGGL(k_sort_det<E>, dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, out.n_det, cap, out.det_idx)
+    hipLaunchKernelGGL(k_sort_det<E>, dim3(p.F), dim3(kSortThreads), sb, p.stream, out.n_det, cap, out.det_idx, \
+                       set_off, n_total, (int)sb)
         MR1L_BY_E(sort_e(cap), MR1L_SD)
 #undef MR1L_SD
         MR1L_LAUNCH_CHECK();

@@ -17,7 +17,9 @@
 //        (2B - 1 <= N = 16384).  Output block q is sum_p a_p * c_{q-p}, where a_p
 //        is input block p (chirped) and c_s[m] = cw[s B + m], |m| < B, is one of
 //        2K - 1 segments of the chirp; each term is a cyclic convolution of length
-//        N, so  Y_q = sum_p FFT(a_p) Cs_{q-p}  with the segment spectra Cs_s.
+//        N, so  Y_q = sum_p FFT(a_p) Cs_{q-p}  with the segment spectra Cs_s.  cw
+//        is even, so c_{-s}[m] = c_s[-m] (indices mod N) and Cs_{-s}[h] = Cs_s[-h]:
+//        only the K spectra s = 0 .. K - 1 are stored.
 //        One workgroup per lattice runs K forward and K inverse transforms; the
 //        spectra of the first K - 1 blocks wait in a global scratch slot of the
 //        workgroup (each thread reads back only what it wrote).
@@ -212,8 +214,8 @@ __global__ __launch_bounds__((lf::wg_threads<N, E, G>()), (lf::wg_threads<N, E, 
 // ------------------------------------------------------------------ split kernels
 // One workgroup of N/E threads per lattice (persistent over the list), one LDS plane
 // of N reals.  MDesc: N (transform length), N1 = B (block), N2 = K (blocks), spectra
-// of the segments s = -(K-1) .. K-1 at spec_off + (s + K - 1) N.  Scratch slot of the
-// workgroup: (K - 1) N complex.
+// of the segments s = 0 .. K-1 at spec_off + s N (segment -s is segment s at -h).
+// Scratch slot of the workgroup: (K - 1) N complex.
 
 // Segment spectra of one size (one workgroup per size, the segments in turn):
 // c_s[m'] = cw[s B + m'] at m' mod N for |m'| < B, transformed, times 1/(N M).
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(N / E) void k_blu_split_spec(
     __syncthreads();
     const V *tw = tw_tab + m.tw_N;
     T xr[E], xi[E];
-    for (int s = -(K - 1); s <= K - 1; ++s) {
+    for (int s = 0; s <= K - 1; ++s) {
         const int tt = lf::opq(t);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(N / E) void k_blu_split_spec(
         }
         lf::fft<T, N, E>(pl, pl, xr, xi, true, t, tw);
         const T sc = T(1) / ((T)N * (T)M);
-        V *dst = spec_tab + m.spec_off + (int64_t)(s + K - 1) * N;
+        V *dst = spec_tab + m.spec_off + (int64_t)s * N;
         const int t2 = lf::opq(t);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -342,7 +344,8 @@ __global__ __launch_bounds__(N / E) void k_blu_split(
                     T yr = 0, yi = 0;
 #pragma unroll
                     for (int p = 0; p < K; ++p) {
-                        const V s = sp[(int64_t)(q - p + K - 1) * N + h];
+                        // Cs_{q-p}[h], or Cs_{p-q}[-h mod N] for q < p
+                        const V s = q >= p ? sp[(int64_t)(q - p) * N + h] : sp[(int64_t)(p - q) * N + ((N - h) & (N - 1))];
                         yr += X[p].x * s.x - X[p].y * s.y;
                         yi += X[p].x * s.y + X[p].y * s.x;
                     }

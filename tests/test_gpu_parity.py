@@ -697,6 +697,45 @@ def test_injectivity_check_matches_definition(m):
     assert list(ok) == [c[3] for c in sel] and ok_all == all(c[3] for c in sel)
 
 
+@pytest.mark.parametrize("cap", [1, 2, 63, 1024, 1025, 4096, 8192])
+def test_detected_order_and_limit_at_sort_sizes(m, cap):
+    """The block sorts of the detected set and of Algorithm 4 at list lengths around
+    their size boundaries (one value per thread up to 1024 entries, then 2, 4 and 8;
+    lane-shuffle stages up to 64 values apart, LDS beyond): noise samples make every
+    bucket non-zero, so every candidate of a function is detected and its sorted list is
+    0, 1, ..., n - 1; Algorithm 4 against the oracle."""
+    say("sort sizes", cap)
+    rng = np.random.default_rng(7000 + cap)
+    d, L = 3, 5
+    sizes = sorted({n for n in (1, 2, 3, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 2047, 2048, 4095,
+                                4096, 4097, 8191, 8192) if n <= cap})
+    F = len(sizes)
+    sets, Ms, zs, fs = [], [], [], []
+    for n in sizes:
+        sets.append(synth.distinct_uniform_points(rng, n, d, -60, 60))
+        M, z = synth.draw_lattices(rng, L, d, 1500, 2500)
+        Ms.append(M)
+        zs.append(z)
+        fs.append(rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum())))
+    plan = m.Plan(d, np.concatenate(Ms), np.concatenate(zs), F=F)
+    g, bm = m.mr1l_fft(plan, T(np.concatenate(fs)), 1e-9)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    s_cap = max(1, cap // 2)
+    ex = m.mr1l_extract(plan, T(np.concatenate(sets, axis=1)), g, bm, 1e-9, s_cap=s_cap, cap=cap,
+                        set_off=T(off), want_w=False)
+    torch.cuda.synchronize()
+    for fi, n in enumerate(sizes):
+        assert int(ex["n_det"][fi]) == n
+        assert np.array_equal(ex["det_idx"][fi, :n].cpu().numpy(), np.arange(n))
+        go = oracle.dft(fs[fi], Ms[fi])
+        ro = oracle.extract(sets[fi], Ms[fi], zs[fi], go, 1e-9, s_cap=s_cap, cap=cap)
+        no = int(ex["n_out"][fi])
+        assert no == len(ro["out_idx"])
+        r = dict(out_idx=ex["out_idx"][fi, :no].cpu().numpy(), out_coef=ex["out_coef"][fi, :no].cpu().numpy())
+        check_limit(r, ro, EPS[torch.complex128], 1e-11)
+        assert np.array_equal(ex["out_pos"][fi, :no].long().cpu().numpy(), r["out_idx"])
+
+
 @pytest.mark.parametrize("seed,F,L", [(1, 1, 7), (2, 2, 7), (3, 1, 40)])
 def test_long_detected_lists_match_oracle(m, seed, F, L):
     """Detected lists longer than 8192 (global-memory sorts): noise samples make every
