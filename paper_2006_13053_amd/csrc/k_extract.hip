@@ -534,6 +534,9 @@ __device__ __forceinline__ uint64_t limit_key(typename cvec<T>::type c, T th2, b
     return pass ? ~(uint64_t)__double_as_longlong((double)m2) : ~0ull;   // m2 >= 0: bits are monotonic
 }
 
+// The entries with |p| >= theta are first compacted to the front of the LDS arrays
+// (a block scan keeps them in list order), so the sort runs over pow2ceil(#passing)
+// pairs only; the others would sort after them anyway.
 template <typename T, int E>
 __global__ __launch_bounds__(kSortThreads) void k_limit(
     const int64_t *__restrict__ n_det, int64_t cap, const int64_t *__restrict__ det_idx,
@@ -542,42 +545,56 @@ __global__ __launch_bounds__(kSortThreads) void k_limit(
 {
     using V = typename cvec<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int wsum[kSortThreads / 64];
     __shared__ int npass;
     const int f = blockIdx.x, t = threadIdx.x;
     const int n = (int)n_of(n_det, f, cap);
-    const int P = sort_len(n, E);
+    const int Pn = sort_len(n, E);
     uint64_t *lk = reinterpret_cast<uint64_t *>(smem);
-    int32_t *lv = reinterpret_cast<int32_t *>(lk + P);
-    if (t == 0) npass = 0;
-    __syncthreads();
+    int32_t *lv = reinterpret_cast<int32_t *>(lk + Pn);
     const V *dc = det_coef + (int64_t)f * cap;
     uint64_t k[E];
     int32_t v[E];
+    bool ps[E];
     int cnt = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int p = t * E + e;
+        ps[e] = false;
         k[e] = ~0ull;
-        v[e] = INT32_MAX;
-        if (p < n) {
-            bool pass;
-            k[e] = limit_key<T>(dc[p], th2, pass);
-            if (pass) { v[e] = p; ++cnt; }
-        }
+        if (p < n) k[e] = limit_key<T>(dc[p], th2, ps[e]);
+        cnt += ps[e];
     }
-    if (cnt) atomicAdd(&npass, cnt);
-    block_bitonic<E>(k, v, P, lk, lv);
+    int o = block_excl_scan(cnt, wsum);
+    if (t == kSortThreads - 1) npass = o + cnt;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (ps[e]) {
+            lk[o] = k[e];
+            lv[o] = t * E + e;
+            ++o;
+        }
     __syncthreads();
-    const int64_t no = min((int64_t)npass, s_cap);
+    const int np = npass;
+    const int P = sort_len(np, E);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = t * E + e;
+        k[e] = p < np ? lk[p] : ~0ull;
+        v[e] = p < np ? lv[p] : INT32_MAX;
+    }
+    __syncthreads();   // the sort's exchanges reuse the arrays
+    block_bitonic<E>(k, v, P, lk, lv);
+    const int64_t no = min((int64_t)np, s_cap);
     if (t == 0) n_out[f] = no;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int o = t * E + e;
-        if (o < no) {
+        const int o2 = t * E + e;
+        if (o2 < no) {
             const int q = v[e];
-            out_idx[(int64_t)f * s_cap + o] = det_idx[(int64_t)f * cap + q];
-            out_coef[(int64_t)f * s_cap + o] = dc[q];
-            if (out_pos) out_pos[(int64_t)f * s_cap + o] = q;
+            out_idx[(int64_t)f * s_cap + o2] = det_idx[(int64_t)f * cap + q];
+            out_coef[(int64_t)f * s_cap + o2] = dc[q];
+            if (out_pos) out_pos[(int64_t)f * s_cap + o2] = q;
         }
     }
 }
