@@ -180,6 +180,31 @@ def test_fft_matches_direct_dft(m, Ms, dtype):
         off += mm
 
 
+def test_plan_created_on_one_stream_runs_on_another(m):
+    """A plan's tables are uploaded and its spectra computed on the creation stream
+    without a host wait; moving the plan to another stream orders that stream after the
+    creation work, so the first transform on it already sees the tables (same values as a
+    plan created and run on the current stream)."""
+    say("plan stream switch")
+    rng = np.random.default_rng(77)
+    M = np.array([16001, 12007, 4133, 211, 7], np.int64)
+    z = np.stack([rng.integers(0, mm, size=3) for mm in M])
+    f = T(rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum())))
+    ref = m.Plan(3, M, z)
+    g0, _ = m.mr1l_fft(ref, f, 1e-9)
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(sa):
+            p = m.Plan(3, M, z)
+        p.set_stream(sb)
+        with torch.cuda.stream(sb):
+            g1, _ = m.mr1l_fft(p, f, 1e-9)
+        torch.cuda.synchronize()
+        assert torch.equal(g0, g1), rep
+        p.close()
+
+
 def _fft_check(m, plan, f, dtype, rng):
     g, _ = m.mr1l_fft(plan, T(f.astype(np.complex128)).to(dtype), theta=0.05)
     torch.cuda.synchronize()
