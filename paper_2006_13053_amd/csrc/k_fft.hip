@@ -859,6 +859,8 @@ template <typename T> static int allow_lds()
     return rc;
 }
 
+constexpr int64_t kFftForkNodes = int64_t(1) << 20;   // nodes from which DFT groups run concurrently
+
 int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap, int mode, double scale)
 {
     // mode FFT_INV with scale < 0 means "multiply by M" (used by the sampler)
@@ -882,9 +884,11 @@ int fft_run(Plan &p, const void *in, void *out, double theta, uint32_t *bitmap, 
         if (uses_scratch(a) != uses_scratch(b)) return uses_scratch(a);
         return p.fft_groups[a].work > p.fft_groups[b].work;
     });
+    // (small plans stay on one stream: the cross-stream waits cost more than the
+    // overlap gains when each group is a short launch)
     int nfork = 0;
     for (int i : order) nfork += !uses_scratch(i);
-    const bool fork = nfork > 1 && p.fft_aux[0] != nullptr;
+    const bool fork = nfork > 1 && p.fft_aux[0] != nullptr && p.nodes >= kFftForkNodes;
     if (fork) MR1L_HIP(hipEventRecord(p.fft_ev[Plan::kFftAux], p.stream));
     bool used[Plan::kFftAux] = {};
     int next = 0;
