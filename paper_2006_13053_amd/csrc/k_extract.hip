@@ -154,11 +154,13 @@ template <int E>
 __global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__restrict__ n_det, int64_t cap,
                                                            int64_t *__restrict__ det_idx,
                                                            const int64_t *__restrict__ set_off, int64_t n_total,
-                                                           int region_bytes)
+                                                           int region_bytes, uint32_t *__restrict__ mask, int mw)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int wsum[kSortThreads / 64];
     const int f = blockIdx.x, t = threadIdx.x;
+    // the function's singleton masks start cleared (the singleton pass only sets bits)
+    for (int64_t i = t; i < cap * mw; i += kSortThreads) mask[(int64_t)f * cap * mw + i] = 0u;
     const int n = (int)n_of(n_det, f, cap);
     if (n <= 1) return;
     int64_t *src = det_idx + (int64_t)f * cap;
@@ -1016,7 +1018,7 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
         const size_t sb = std::max<size_t>((size_t)pow2ceil(std::max<int64_t>(cap, 1)) * 12, kSortBitmapBytes);
 #define MR1L_SD(E) \
     hipLaunchKernelGGL(k_sort_det<E>, dim3(p.F), dim3(kSortThreads), sb, p.stream, out.n_det, cap, out.det_idx, \
-                       set_off, n_total, (int)sb)
+                       set_off, n_total, (int)sb, det_mask, mask_words(p.L))
         MR1L_BY_E(sort_e(cap), MR1L_SD)
 #undef MR1L_SD
         MR1L_LAUNCH_CHECK();
@@ -1061,8 +1063,10 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
                            p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
         MR1L_LAUNCH_CHECK();
     }
-    rc = launch_fill_u32(det_mask, (int64_t)p.F * cap * mask_words(p.L), 0u, p.stream);
-    if (rc) return rc;
+    if (large) {   // (short lists: k_sort_det cleared the masks)
+        rc = launch_fill_u32(det_mask, (int64_t)p.F * cap * mask_words(p.L), 0u, p.stream);
+        if (rc) return rc;
+    }
     int64_t maxM = 1;
     for (int64_t m : p.M) maxM = std::max(maxM, m);
     const int words = (int)std::min<int64_t>(kSingleWords, (maxM + 31) / 32);
