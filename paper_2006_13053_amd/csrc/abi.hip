@@ -437,10 +437,16 @@ __global__ void k_set_pair(int64_t *dst, int64_t a, int64_t b)
     if (threadIdx.x == 0) { dst[0] = a; dst[1] = b; }
 }
 
-static int default_offsets(Plan &p, int64_t *dst, int64_t n)
+// {0, n} for a one-function call without offsets.  The pair is rewritten only when n
+// changes (cached in `have`), except once a graph has recorded such a write: a replay
+// may then have left another n there, so every later call writes it again.
+static int default_offsets(Plan &p, int64_t *dst, int64_t n, int64_t &have)
 {
+    if (!p.capturing && have == n) return MR1L_OK;
     hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(64), 0, p.stream, dst, (int64_t)0, n);
     MR1L_LAUNCH_CHECK();
+    if (p.capturing) p.offsets_recorded = true;
+    have = p.offsets_recorded ? -1 : n;
     return MR1L_OK;
 }
 
@@ -633,7 +639,7 @@ int mr1l_sample(mr1l_plan p, int32_t d_poly, const int64_t *term_off, int64_t n_
     if (mode < 0 || mode > 2) return fail(MR1L_E_ARG, "mode must be 0, 1 or 2");
     if (!term_off) {
         if (p->F != 1) return fail(MR1L_E_ARG, "term_off required when F > 1");
-        int rc = default_offsets(*p, p->d_termoff_default, n_terms);
+        int rc = default_offsets(*p, p->d_termoff_default, n_terms, p->termoff_n);
         if (rc) return rc;
         term_off = p->d_termoff_default;
     }
@@ -675,7 +681,7 @@ int mr1l_hash_count(mr1l_plan p, int64_t n_total, const int64_t *set_off, const 
     if (n_total < 0 || (n_total > 0 && !freq)) return fail(MR1L_E_ARG, "invalid candidate set");
     if (!set_off) {
         if (p->F != 1) return fail(MR1L_E_ARG, "set_off required when F > 1");
-        int rc = default_offsets(*p, p->d_setoff_default, n_total);
+        int rc = default_offsets(*p, p->d_setoff_default, n_total, p->setoff_n);
         if (rc) return rc;
         set_off = p->d_setoff_default;
     }
@@ -695,7 +701,7 @@ int mr1l_extract(mr1l_plan p, int64_t n_total, const int64_t *set_off, const int
         return fail(MR1L_E_ARG, "required output NULL");
     if (!set_off) {
         if (p->F != 1) return fail(MR1L_E_ARG, "set_off required when F > 1");
-        int rc = default_offsets(*p, p->d_setoff_default, n_total);
+        int rc = default_offsets(*p, p->d_setoff_default, n_total, p->setoff_n);
         if (rc) return rc;
         set_off = p->d_setoff_default;
     }

@@ -212,9 +212,10 @@ struct Plan {
     void *d_ls = nullptr;            // least squares: [F][cap][L] int32 representatives + 4 [F][cap] complex
     int64_t ls_bytes = 0;
     int64_t *d_setoff_default = nullptr; // [2] = {0, n} for F == 1 calls
-    int64_t setoff_n = -1;
+    int64_t setoff_n = -1;           // n the default pair holds (-1: unknown)
     int64_t *d_termoff_default = nullptr;
     int64_t termoff_n = -1;
+    bool offsets_recorded = false;   // a graph recorded a write of a default pair
     bool capturing = false;
     // stage timing
     bool profiling = false;
