@@ -194,6 +194,8 @@ static int arena_commit(Plan &p)
     return MR1L_OK;
 }
 
+constexpr int64_t kFewLattices = 64;
+
 template <typename T>
 static int build_tables(Plan &p)
 {
@@ -273,11 +275,30 @@ static int build_tables(Plan &p)
         if (mi.sched >= 0 && !fft_schedule_applies(mi, mi.sched)) mi.sched = -1;
         // untuned: Rader where it applies (half the transform length of Bluestein),
         // else the register transforms, else the whole-LDS transform, else the four-step
+        mi.tuned = mi.sched >= 0;
         if (mi.sched < 0)
             mi.sched = mi.rader ? kRaderSched : mi.Nr ? kRegSched : mi.Nq ? kSplitSched : mi.Ns ? 0 : kDefaultFourStep;
         p.mdesc.push_back(md);
         p.minfo.push_back(mi);
         p.rdesc.push_back(rd);
+    }
+    // A plan of at most kFewLattices lattices runs its DFT as a few latency-bound
+    // launches, one per group: its untuned register-transform sizes take the whole-LDS
+    // transform instead when they all fit it and that needs fewer launches (three LDS
+    // size classes against one register length per power of two).
+    if ((int64_t)p.M.size() <= kFewLattices) {
+        std::vector<int> reg_n, lds_c;
+        bool fit = true;
+        for (const MInfo &mi : p.minfo)
+            if (!mi.tuned && mi.sched == kRegSched) {
+                fit = fit && mi.Ns > 0;
+                if (std::find(reg_n.begin(), reg_n.end(), mi.Nr) == reg_n.end()) reg_n.push_back(mi.Nr);
+                const int c = mi.Ns > 0 ? lds_class(mi.Ns) : -1;
+                if (std::find(lds_c.begin(), lds_c.end(), c) == lds_c.end()) lds_c.push_back(c);
+            }
+        if (fit && lds_c.size() < reg_n.size())
+            for (MInfo &mi : p.minfo)
+                if (!mi.tuned && mi.sched == kRegSched) mi.sched = 0;
     }
     p.lat.resize(p.M.size());
     int64_t off = 0;

@@ -119,6 +119,7 @@ struct MInfo {
     int32_t Nq = 0, Bq = 0, Kq = 0;   // split schedule: transform length, block, blocks (Nq 0: does not apply)
     int64_t spec_q = -1, tw_q = -1;
     int32_t sched = 0;
+    bool tuned = false;       // sched came from the autotuner's record
     int32_t nlat = 0;
     uint32_t spec_done = 0;   // spectra computed, bit per layout kind (see fft_spec_kind)
 };
