@@ -850,6 +850,245 @@ __global__ __launch_bounds__(256) void k_adjoint_scatter(
     }
 }
 
+// ------------------------------------------------------------------ selection (long lists)
+// Algorithm 4 on a long list keeps at most s~ entries: the s~-th smallest key of the
+// function (keys as k_limit_keys writes them, failing entries ~0) is found by an
+// 8-round radix selection, 8 bits per round from the top (per-block LDS histograms of
+// the keys that match the prefix found so far, then the digit where the cumulative
+// count reaches the remaining rank); an ordered compaction then keeps the entries
+// below it and, among those equal to it, the first ones by position, so only
+// min(s~, #passing) pairs are sorted.
+struct SelState {
+    uint64_t prefix, mask;
+    int64_t kk;    // rank still to reach among the keys matching the prefix
+    int64_t pad;   // after the scan: the number of keys below the threshold
+};
+
+__global__ void k_sel_init(int F, const int64_t *__restrict__ n_det, int64_t cap, int64_t s_cap,
+                           SelState *__restrict__ st, uint32_t *__restrict__ hist)
+{
+    const int f = blockIdx.x;
+    if (f >= F) return;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[(int64_t)f * 256 + i] = 0u;
+    if (threadIdx.x == 0) {
+        st[f].prefix = 0;
+        st[f].mask = 0;
+        st[f].kk = min(s_cap, n_of(n_det, f, cap));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sel_hist(const int64_t *__restrict__ n_det, int64_t cap, int64_t P,
+                                                  const uint64_t *__restrict__ key, int shift,
+                                                  const SelState *__restrict__ st, uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[256];
+    const int f = blockIdx.y;
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t n = n_of(n_det, f, cap);
+    const uint64_t pre = st[f].prefix, msk = st[f].mask;
+    // the keys share their top digits in the first rounds: the lanes of a wave with
+    // the same digit add their count with one atomic (one pass per distinct digit)
+    if (st[f].kk > 0) {
+        const int lane = threadIdx.x & 63;
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63);
+        for (int64_t w0 = i0; w0 < n; w0 += stride) {   // whole waves take part
+            const int64_t i = w0 + lane;
+            uint64_t k = 0;
+            bool m = false;
+            if (i < n) {
+                k = key[(int64_t)f * P + i];
+                m = (k & msk) == pre;
+            }
+            const uint32_t dg = (uint32_t)(k >> shift) & 255u;
+            uint64_t act = __ballot(m);
+            while (act) {
+                const int leader = __ffsll((unsigned long long)act) - 1;
+                const uint32_t dl = (uint32_t)__shfl((int)dg, leader);
+                const uint64_t same = __ballot(m && dg == dl);
+                if (lane == leader) atomicAdd(&h[dl], (uint32_t)__popcll(same));
+                act &= ~same;
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t c = h[threadIdx.x];
+    if (c) atomicAdd(hist + (int64_t)f * 256 + threadIdx.x, c);
+}
+
+// one workgroup of 256 threads per function: the digit whose cumulative count first
+// reaches the remaining rank (a block scan of the 256 bins), then the bins cleared
+__global__ __launch_bounds__(256) void k_sel_pick(int shift, SelState *__restrict__ st, uint32_t *__restrict__ hist)
+{
+    __shared__ int wsum[kSortThreads / 64];
+    __shared__ int pick;
+    const int f = blockIdx.x, t = threadIdx.x;
+    uint32_t *h = hist + (int64_t)f * 256;
+    const int64_t kk = st[f].kk;
+    const int c = (int)h[t];
+    const int below = block_excl_scan(c, wsum);
+    if (t == 0) pick = 255;
+    __syncthreads();
+    if (kk > 0 && (int64_t)below < kk && (int64_t)below + c >= kk) pick = t;   // exactly one thread
+    __syncthreads();
+    h[t] = 0u;
+    if (t == pick && kk > 0) {
+        st[f].kk = kk - below;
+        st[f].prefix |= (uint64_t)t << shift;
+        st[f].mask |= (uint64_t)255u << shift;
+    }
+}
+
+// per block of kSortThreads entries: how many keys are below the threshold T and how
+// many equal it (equal ones only when T is a passing key)
+__global__ __launch_bounds__(kSortThreads) void k_sel_count(const int64_t *__restrict__ n_det, int64_t cap, int64_t P,
+                                                            const uint64_t *__restrict__ key,
+                                                            const SelState *__restrict__ st, int nb,
+                                                            int32_t *__restrict__ cnt)
+{
+    __shared__ int wsum[kSortThreads / 64];
+    const int f = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)kSortThreads + threadIdx.x;
+    const int64_t n = n_of(n_det, f, cap);
+    const uint64_t T = st[f].prefix;
+    int lt = 0, eq = 0;
+    if (i < n) {
+        const uint64_t k = key[(int64_t)f * P + i];
+        lt = k < T;
+        eq = (k == T) && (T != ~0ull);
+    }
+    const int a = block_excl_scan(lt, wsum);
+    __syncthreads();
+    const int b = block_excl_scan(eq, wsum);
+    if (threadIdx.x == kSortThreads - 1) {
+        cnt[((int64_t)f * nb + blockIdx.x) * 2] = a + lt;
+        cnt[((int64_t)f * nb + blockIdx.x) * 2 + 1] = b + eq;
+    }
+}
+
+// exclusive offsets of the blocks' counts (one workgroup per function, kSortThreads
+// blocks' counts at a time); n_sel[f] = the number of pairs kept
+__global__ __launch_bounds__(kSortThreads) void k_sel_scan(int nb, const SelState *__restrict__ st,
+                                                           int32_t *__restrict__ cnt, int64_t *__restrict__ n_sel)
+{
+    __shared__ int wsum[kSortThreads / 64];
+    __shared__ int64_t tot[2];
+    const int f = blockIdx.x, t = threadIdx.x;
+    int32_t *c = cnt + (int64_t)f * nb * 2;
+    if (t == 0) { tot[0] = 0; tot[1] = 0; }
+    __syncthreads();
+    for (int x0 = 0; x0 < nb; x0 += kSortThreads) {
+        const int x = x0 + t;
+        const int ca = x < nb ? c[2 * x] : 0, cb = x < nb ? c[2 * x + 1] : 0;
+        const int ea = block_excl_scan(ca, wsum);
+        __syncthreads();
+        const int eb = block_excl_scan(cb, wsum);
+        const int64_t ba = tot[0], bb = tot[1];
+        if (x < nb) {
+            c[2 * x] = (int32_t)(ba + ea);
+            c[2 * x + 1] = (int32_t)(bb + eb);
+        }
+        __syncthreads();
+        if (t == kSortThreads - 1) { tot[0] = ba + ea + ca; tot[1] = bb + eb + cb; }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const bool pass_t = st[f].prefix != ~0ull;
+        n_sel[f] = tot[0] + (pass_t ? min(st[f].kk, tot[1]) : 0);
+    }
+}
+
+// the kept pairs, in position order: keys below T first, then the first kk equal to T
+__global__ __launch_bounds__(kSortThreads) void k_sel_emit(const int64_t *__restrict__ n_det, int64_t cap, int64_t P,
+                                                           const uint64_t *__restrict__ key,
+                                                           const int32_t *__restrict__ pos,
+                                                           const SelState *__restrict__ st, int nb,
+                                                           const int32_t *__restrict__ cnt, int64_t S,
+                                                           uint64_t *__restrict__ okey, int32_t *__restrict__ opos)
+{
+    __shared__ int wsum[kSortThreads / 64];
+    const int f = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)kSortThreads + threadIdx.x;
+    const int64_t n = n_of(n_det, f, cap);
+    const uint64_t T = st[f].prefix;
+    const int64_t kk = st[f].kk;
+    uint64_t k = ~0ull;
+    int lt = 0, eq = 0;
+    if (i < n) {
+        k = key[(int64_t)f * P + i];
+        lt = k < T;
+        eq = (k == T) && (T != ~0ull);
+    }
+    const int a = block_excl_scan(lt, wsum);
+    __syncthreads();
+    const int b = block_excl_scan(eq, wsum);
+    const int32_t *c = cnt + ((int64_t)f * nb + blockIdx.x) * 2;
+    if (lt) {
+        const int64_t o = c[0] + a;
+        okey[(int64_t)f * S + o] = k;
+        opos[(int64_t)f * S + o] = pos[(int64_t)f * P + i];
+    } else if (eq) {
+        const int64_t r = c[1] + b;
+        if (r < kk) {
+            const int64_t o = st[f].pad + r;   // after all keys below T
+            okey[(int64_t)f * S + o] = k;
+            opos[(int64_t)f * S + o] = pos[(int64_t)f * P + i];
+        }
+    }
+}
+
+// number of keys below the threshold (the kept entries equal to it go after them)
+__global__ void k_sel_below(int F, int nb, SelState *__restrict__ st, const int64_t *__restrict__ n_sel)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const bool pass_t = st[f].prefix != ~0ull;
+    // n_sel = below + min(kk, equal) when T passes, else below
+    st[f].pad = n_sel[f] - (pass_t ? st[f].kk : 0);
+}
+
+// Algorithm 4's order over the kept pairs of each function (at most E x kSortThreads),
+// one workgroup per function; dynamic LDS pow2ceil(S) x 12 bytes.
+template <typename T, int E>
+__global__ __launch_bounds__(kSortThreads) void k_limit_sel(int64_t cap, const int64_t *__restrict__ det_idx,
+                                                            const typename cvec<T>::type *__restrict__ det_coef,
+                                                            const int64_t *__restrict__ n_sel, int64_t S,
+                                                            const uint64_t *__restrict__ skey,
+                                                            const int32_t *__restrict__ spos, int64_t s_cap,
+                                                            int64_t *__restrict__ n_out, int64_t *__restrict__ out_idx,
+                                                            typename cvec<T>::type *__restrict__ out_coef,
+                                                            int32_t *__restrict__ out_pos)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int f = blockIdx.x, t = threadIdx.x;
+    const int np = (int)n_sel[f];
+    const int P = sort_len(np, E);
+    uint64_t *lk = reinterpret_cast<uint64_t *>(smem);
+    int32_t *lv = reinterpret_cast<int32_t *>(lk + P);
+    uint64_t k[E];
+    int32_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = t * E + e;
+        k[e] = p < np ? skey[(int64_t)f * S + p] : ~0ull;
+        v[e] = p < np ? spos[(int64_t)f * S + p] : INT32_MAX;
+    }
+    block_bitonic<E>(k, v, P, lk, lv);
+    const int64_t no = min((int64_t)np, s_cap);
+    if (t == 0) n_out[f] = no;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int o = t * E + e;
+        if (o < no) {
+            const int q = v[e];
+            out_idx[(int64_t)f * s_cap + o] = det_idx[(int64_t)f * cap + q];
+            out_coef[(int64_t)f * s_cap + o] = det_coef[(int64_t)f * cap + q];
+            if (out_pos) out_pos[(int64_t)f * s_cap + o] = q;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host
 template <typename T>
 static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, int64_t nmax, const int32_t *det_hash,
@@ -884,7 +1123,8 @@ template <int E>
 static int sort_attrs()
 {
     // dynamic LDS at the largest capacity (static LDS comes on top of it)
-    const void *ks[] = {(const void *)k_sort_det<E>, (const void *)k_limit<double, E>, (const void *)k_limit<float, E>};
+    const void *ks[] = {(const void *)k_sort_det<E>, (const void *)k_limit<double, E>, (const void *)k_limit<float, E>,
+                        (const void *)k_limit_sel<double, E>, (const void *)k_limit_sel<float, E>};
     for (const void *k : ks)
         MR1L_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      std::max(kMaxCap * 12, kSortBitmapBytes)));
@@ -938,16 +1178,47 @@ static int grow_sort(Plan &p, int64_t P)
     return MR1L_OK;
 }
 
-// Algorithm 4 on a long list (sort buffers sized for P >= every function's count):
-// keys, global sort, first s~
+// Algorithm 4 on a long list (sort buffers sized for P >= every function's count,
+// nmax the longest count): lists that fit one workgroup take the block sort; longer
+// ones keep min(s~, #passing) pairs by a radix selection and sort only those (in one
+// workgroup when they fit it, else by the global sort).
+static int limit_short(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef,
+                       double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef, int32_t *out_pos,
+                       int64_t nmax);
+
 static int limit_long(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef,
                       double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef,
-                      int32_t *out_pos, int64_t P)
+                      int32_t *out_pos, int64_t P, int64_t nmax)
 {
-    uint64_t *skey = (uint64_t *)p.d_gsort;
-    int32_t *spos = (int32_t *)(skey + p.F * P);
+    if (nmax <= kMaxCap)
+        return limit_short(p, n_det, cap, det_idx, det_coef, theta, s_cap, n_out, out_idx, out_coef, out_pos, nmax);
+    const int64_t F = p.F;
+    const int64_t S = pow2ceil(std::min(s_cap, nmax));   // kept pairs per function, padded
+    const int nb = (int)((nmax + kSortThreads - 1) / kSortThreads);
+    // sort buffers [F][P] keys + positions, then [F][S] kept pairs, the histograms, the
+    // selection states, the block counts and the kept counts
+    const int64_t b_keys = F * P * 12, b_kept = F * S * 12, b_hist = F * 256 * 4;
+    const int64_t b_st = F * (int64_t)sizeof(SelState), b_cnt = F * nb * 8, b_nsel = F * 8;
+    const int64_t bytes = b_keys + b_kept + b_hist + b_st + b_cnt + b_nsel + 64;
+    if (p.gsort_bytes < bytes || !p.d_gsort) {
+        if (p.capturing) return fail(MR1L_E_ARG, "lists longer than 8192 cannot be recorded in a graph");
+        if (p.d_gsort) (void)hipFree(p.d_gsort);
+        p.d_gsort = nullptr;
+        p.gsort_bytes = 0;
+        MR1L_HIP(hipMalloc(&p.d_gsort, (size_t)bytes));
+        p.gsort_bytes = bytes;
+    }
+    unsigned char *base = (unsigned char *)p.d_gsort;
+    uint64_t *skey = (uint64_t *)base;
+    int32_t *spos = (int32_t *)(skey + F * P);
+    uint64_t *kkey = (uint64_t *)(base + b_keys);
+    int32_t *kpos = (int32_t *)(kkey + F * S);
+    uint32_t *hist = (uint32_t *)(base + b_keys + b_kept);
+    SelState *st = (SelState *)(base + ((b_keys + b_kept + b_hist + 15) & ~int64_t(15)));
+    int32_t *cnt = (int32_t *)((unsigned char *)st + b_st);
+    int64_t *nsel = (int64_t *)(((uintptr_t)((unsigned char *)cnt + b_cnt) + 7) & ~(uintptr_t)7);
     int rc = MR1L_OK;
-    const dim3 gp((unsigned)((P + 255) / 256), (unsigned)p.F);
+    const dim3 gp((unsigned)((P + 255) / 256), (unsigned)F);
     if (p.dtype == MR1L_C128)
         hipLaunchKernelGGL(k_limit_keys<double>, gp, dim3(256), 0, p.stream, n_det, cap, (const double2 *)det_coef,
                            theta * theta, P, skey, spos);
@@ -955,14 +1226,57 @@ static int limit_long(Plan &p, const int64_t *n_det, int64_t cap, const int64_t 
         hipLaunchKernelGGL(k_limit_keys<float>, gp, dim3(256), 0, p.stream, n_det, cap, (const float2 *)det_coef,
                            (float)(theta * theta), P, skey, spos);
     MR1L_LAUNCH_CHECK();
-    if ((rc = gsort_run(p, skey, spos, P))) return rc;
-    const dim3 ge((unsigned)((s_cap + 255) / 256), (unsigned)p.F);
+    // the threshold: the s~-th smallest key of each function
+    hipLaunchKernelGGL(k_sel_init, dim3((unsigned)F), dim3(256), 0, p.stream, (int)F, n_det, cap, s_cap, st, hist);
+    MR1L_LAUNCH_CHECK();
+    const dim3 gh((unsigned)std::min<int64_t>((nmax + 255) / 256, std::max<int64_t>(1, 1024 / F + 1)), (unsigned)F);
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_sel_hist, gh, dim3(256), 0, p.stream, n_det, cap, P, skey, shift, st, hist);
+        MR1L_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sel_pick, dim3((unsigned)F), dim3(256), 0, p.stream, shift, st, hist);
+        MR1L_LAUNCH_CHECK();
+    }
+    // the kept pairs in position order
+    const dim3 gb((unsigned)nb, (unsigned)F);
+    hipLaunchKernelGGL(k_sel_count, gb, dim3(kSortThreads), 0, p.stream, n_det, cap, P, skey, st, nb, cnt);
+    MR1L_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sel_scan, dim3((unsigned)F), dim3(kSortThreads), 0, p.stream, nb, st, cnt, nsel);
+    MR1L_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sel_below, dim3((unsigned)((F + 63) / 64)), dim3(64), 0, p.stream, (int)F, nb, st, nsel);
+    MR1L_LAUNCH_CHECK();
+    if (S > kMaxCap) {
+        // padding sorts last: keys ~0, positions INT32_MAX
+        if ((rc = launch_fill_u32((uint32_t *)kkey, F * S * 2, 0xffffffffu, p.stream))) return rc;
+        if ((rc = launch_fill_u32((uint32_t *)kpos, F * S, 0x7fffffffu, p.stream))) return rc;
+    }
+    hipLaunchKernelGGL(k_sel_emit, gb, dim3(kSortThreads), 0, p.stream, n_det, cap, P, skey, spos, st, nb, cnt, S,
+                       kkey, kpos);
+    MR1L_LAUNCH_CHECK();
+    if (S <= kMaxCap) {
+        const size_t lds = (size_t)S * 12;
+#define MR1L_LSD(E)                                                                                               \
+    hipLaunchKernelGGL((k_limit_sel<double, E>), dim3((unsigned)F), dim3(kSortThreads), lds, p.stream, cap, det_idx, \
+                       (const double2 *)det_coef, nsel, S, kkey, kpos, s_cap, n_out, out_idx, (double2 *)out_coef,   \
+                       out_pos)
+#define MR1L_LSF(E)                                                                                              \
+    hipLaunchKernelGGL((k_limit_sel<float, E>), dim3((unsigned)F), dim3(kSortThreads), lds, p.stream, cap, det_idx, \
+                       (const float2 *)det_coef, nsel, S, kkey, kpos, s_cap, n_out, out_idx, (float2 *)out_coef,    \
+                       out_pos)
+        if (p.dtype == MR1L_C128) MR1L_BY_E(sort_e(S), MR1L_LSD)
+        else MR1L_BY_E(sort_e(S), MR1L_LSF)
+#undef MR1L_LSD
+#undef MR1L_LSF
+        MR1L_LAUNCH_CHECK();
+        return MR1L_OK;
+    }
+    if ((rc = gsort_run(p, kkey, kpos, S))) return rc;
+    const dim3 ge((unsigned)((s_cap + 255) / 256), (unsigned)F);
     if (p.dtype == MR1L_C128)
         hipLaunchKernelGGL(k_limit_emit<double>, ge, dim3(256), 0, p.stream, cap, det_idx, (const double2 *)det_coef,
-                           P, spos, s_cap, n_out, out_idx, (double2 *)out_coef, out_pos);
+                           S, kpos, s_cap, n_out, out_idx, (double2 *)out_coef, out_pos);
     else
         hipLaunchKernelGGL(k_limit_emit<float>, ge, dim3(256), 0, p.stream, cap, det_idx, (const float2 *)det_coef,
-                           P, spos, s_cap, n_out, out_idx, (float2 *)out_coef, out_pos);
+                           S, kpos, s_cap, n_out, out_idx, (float2 *)out_coef, out_pos);
     MR1L_LAUNCH_CHECK();
     return MR1L_OK;
 }
@@ -986,11 +1300,13 @@ static int long_list_size(Plan &p, const int64_t *n_det, int64_t cap, int64_t &n
     return grow_sort(p, P);
 }
 
-// Algorithm 4 on lists of at most kMaxCap entries: one workgroup per function.
+// Algorithm 4 on lists of at most nmax <= kMaxCap entries (cap is the lists' stride):
+// one workgroup per function.
 static int limit_short(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef,
-                       double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef, int32_t *out_pos)
+                       double theta, int64_t s_cap, int64_t *n_out, int64_t *out_idx, void *out_coef, int32_t *out_pos,
+                       int64_t nmax)
 {
-    const size_t pc = (size_t)pow2ceil(std::max<int64_t>(cap, 1));
+    const size_t pc = (size_t)pow2ceil(std::max<int64_t>(nmax, 1));
 #define MR1L_LD(E)                                                                                                 \
     hipLaunchKernelGGL((k_limit<double, E>), dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, n_det, cap, det_idx, \
                        (const double2 *)det_coef, theta * theta, s_cap, n_out, out_idx, (double2 *)out_coef, out_pos)
@@ -998,8 +1314,8 @@ static int limit_short(Plan &p, const int64_t *n_det, int64_t cap, const int64_t
     hipLaunchKernelGGL((k_limit<float, E>), dim3(p.F), dim3(kSortThreads), pc * 12, p.stream, n_det, cap, det_idx, \
                        (const float2 *)det_coef, (float)(theta * theta), s_cap, n_out, out_idx, (float2 *)out_coef,  \
                        out_pos)
-    if (p.dtype == MR1L_C128) MR1L_BY_E(sort_e(cap), MR1L_LD)
-    else MR1L_BY_E(sort_e(cap), MR1L_LF)
+    if (p.dtype == MR1L_C128) MR1L_BY_E(sort_e(nmax), MR1L_LD)
+    else MR1L_BY_E(sort_e(nmax), MR1L_LF)
 #undef MR1L_LD
 #undef MR1L_LF
     MR1L_LAUNCH_CHECK();
@@ -1107,10 +1423,10 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     if (rc) return rc;
     if (!large) {
         return limit_short(p, out.n_det, cap, out.det_idx, out.det_coef, o.theta, o.s_cap, out.n_out, out.out_idx,
-                           out.out_coef, out_pos);
+                           out.out_coef, out_pos, cap);
     }
     return limit_long(p, out.n_det, cap, out.det_idx, out.det_coef, o.theta, o.s_cap, out.n_out, out.out_idx,
-                      out.out_coef, out_pos, P);
+                      out.out_coef, out_pos, P, nmax);
 }
 
 int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx, const void *det_coef, double theta,
@@ -1120,9 +1436,10 @@ int limit_run(Plan &p, const int64_t *n_det, int64_t cap, const int64_t *det_idx
     if (cap > kMaxCap) {
         int64_t nmax = 0, P = 1;
         const int rc = long_list_size(p, n_det, cap, nmax, P);
-        return rc ? rc : limit_long(p, n_det, cap, det_idx, det_coef, theta, s_cap, n_out, out_idx, out_coef, nullptr, P);
+        return rc ? rc
+                  : limit_long(p, n_det, cap, det_idx, det_coef, theta, s_cap, n_out, out_idx, out_coef, nullptr, P, nmax);
     }
-    return limit_short(p, n_det, cap, det_idx, det_coef, theta, s_cap, n_out, out_idx, out_coef, nullptr);
+    return limit_short(p, n_det, cap, det_idx, det_coef, theta, s_cap, n_out, out_idx, out_coef, nullptr, cap);
 }
 
 int adjoint_run(Plan &p, int64_t cap, int64_t s_cap, const int64_t *n_out, const int32_t *out_pos,
