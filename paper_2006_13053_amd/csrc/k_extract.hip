@@ -208,37 +208,66 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__rest
 }
 
 // ------------------------------------------------------------------ hashes of detected
-// Bucket of candidate column ci in lattice ld: the fast 32-bit hash when every
-// coordinate is within the function's bound kb, else the exact 64-bit reduction.
-__device__ __forceinline__ int32_t det_bucket(const int64_t *__restrict__ freq, int64_t n_total, int64_t ci, int d,
-                                              const LatDesc &ld, const int32_t *__restrict__ z32,
-                                              const int64_t *__restrict__ z64, int32_t kb)
-{
-    uint32_t s = ld.off32;
-    bool fast = true;
-    for (int u = 0; u < d; ++u) {
-        const int64_t k = freq[(int64_t)u * n_total + ci];
-        fast = fast & (k >= -kb) & (k <= kb);
-        s += (uint32_t)__mul24((int32_t)k, z32[ld.z_off + u]);
-    }
-    return fast ? (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m) : exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
-}
+// Fast path (every |k_u| within the function's bound kb): 24-bit multiply-adds in 32-bit
+// integers and the float-reciprocal modulo; else the exact 64-bit reduction.  Both give
+// the same bucket.
+// One thread per detected candidate: its d coordinates are read once (adjacent threads
+// hold adjacent entries of the ascending list) and hashed into all L lattices of its
+// function, with L running sums in registers; the lattice records and z words are
+// workgroup-uniform (scalar loads).  The chunk's buckets go through LDS in output order
+// ([entry][lattice]) so that the stores are contiguous.  Dynamic LDS: 256 L int32.
+constexpr int kDetHashThreads = 256;
+constexpr int kDetHashBatch = 8;
 
-// One thread per (detected candidate, lattice): the L threads of a candidate read
-// the same coordinates (cache hits after the first) and write adjacent buckets.
-__global__ __launch_bounds__(256) void k_det_hash(
+template <int LM>
+__global__ __launch_bounds__(kDetHashThreads) void k_det_hash(
     const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int L, int d,
     const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32, const int64_t *__restrict__ z64,
     const int32_t *__restrict__ kbound, const int64_t *__restrict__ n_det, int64_t cap,
     const int64_t *__restrict__ det_idx, int32_t *__restrict__ det_hash)
 {
-    const int f = blockIdx.y;
-    const int64_t nl = n_of(n_det, f, cap) * L;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nl; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t q = t / L;
-    const int l = (int)(t - q * L);
-    const int64_t ci = set_off[f] + det_idx[(int64_t)f * cap + q];
-    det_hash[((int64_t)f * cap + q) * L + l] = det_bucket(freq, n_total, ci, d, lat[f * L + l], z32, z64, kbound[f]);
+    extern __shared__ int32_t hs[];
+    const int f = blockIdx.y, t = threadIdx.x;
+    const int64_t n = n_of(n_det, f, cap);
+    const int64_t base = set_off[f];
+    const int32_t kb = kbound[f];
+    const LatDesc *lf = lat + (int64_t)f * L;
+    for (int64_t q0 = (int64_t)blockIdx.x * kDetHashThreads; q0 < n; q0 += (int64_t)gridDim.x * kDetHashThreads) {
+        const int64_t q = q0 + t;
+        if (q < n) {
+            const int64_t ci = base + det_idx[(int64_t)f * cap + q];
+            uint32_t acc[LM];
+#pragma unroll
+            for (int l = 0; l < LM; ++l) acc[l] = l < L ? lf[l].off32 : 0u;
+            bool fast = true;
+            // the coordinates in batches whose loads are all in flight together
+            for (int u0 = 0; u0 < d; u0 += kDetHashBatch) {
+                int64_t kv[kDetHashBatch];
+#pragma unroll
+                for (int j = 0; j < kDetHashBatch; ++j)
+                    kv[j] = u0 + j < d ? freq[(int64_t)(u0 + j) * n_total + ci] : 0;
+#pragma unroll
+                for (int j = 0; j < kDetHashBatch; ++j) {
+                    if (u0 + j < d) {
+                        fast = fast & (kv[j] >= -kb) & (kv[j] <= kb);
+                        const int32_t k32 = (int32_t)kv[j];
+#pragma unroll
+                        for (int l = 0; l < LM; ++l)
+                            if (l < L) acc[l] += (uint32_t)__mul24(k32, z32[lf[l].z_off + u0 + j]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < LM; ++l)
+                if (l < L)
+                    hs[t * L + l] = fast ? (int32_t)fast_mod(acc[l], (uint32_t)lf[l].M, lf[l].inv_m)
+                                         : exact_bucket(freq + ci, n_total, d, z64 + lf[l].z_off, lf[l].M);
+        }
+        __syncthreads();
+        const int64_t cnt = min<int64_t>(kDetHashThreads, n - q0) * L;
+        int32_t *dst = det_hash + ((int64_t)f * cap + q0) * L;
+        for (int64_t i = t; i < cnt; i += kDetHashThreads) dst[i] = hs[i];
+        __syncthreads();
     }
 }
 
@@ -295,6 +324,7 @@ __global__ __launch_bounds__(256) void k_singleton(const LatDesc *__restrict__ l
 // above, then merges them word by word.  A bucket ends in `twice` when one chunk
 // saw it twice, or when it was already in `once` from another chunk.
 constexpr int kSingleThreads = 1024;
+constexpr int kSingleLoads = 8;
 
 __global__ __launch_bounds__(kSingleThreads) void k_single_count(
     const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ n_det, int64_t cap,
@@ -319,12 +349,22 @@ __global__ __launch_bounds__(kSingleThreads) void k_single_count(
         const int nw = (c1 - c0 + 31) >> 5;
         for (int i = threadIdx.x; i < nw; i += blockDim.x) { once[i] = 0u; twice[i] = 0u; }
         __syncthreads();
-        for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
-            const int h = hh[q * L + l];
-            if (h >= c0 && h < c1) {
-                const int r = h - c0;
-                const uint32_t bit = 1u << (r & 31);
-                if (atomicOr(once + (r >> 5), bit) & bit) atomicOr(twice + (r >> 5), bit);
+        // kSingleLoads buckets in flight per thread (the loop is latency-bound otherwise)
+        for (int64_t qb = q0 + threadIdx.x; qb < q1; qb += (int64_t)kSingleLoads * blockDim.x) {
+            int hv[kSingleLoads];
+#pragma unroll
+            for (int k = 0; k < kSingleLoads; ++k) {
+                const int64_t q = qb + (int64_t)k * blockDim.x;
+                hv[k] = q < q1 ? hh[q * L + l] : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < kSingleLoads; ++k) {
+                const int h = hv[k];
+                if (h >= c0 && h < c1) {
+                    const int r = h - c0;
+                    const uint32_t bit = 1u << (r & 31);
+                    if (atomicOr(once + (r >> 5), bit) & bit) atomicOr(twice + (r >> 5), bit);
+                }
             }
         }
         __syncthreads();
@@ -337,6 +377,59 @@ __global__ __launch_bounds__(kSingleThreads) void k_single_count(
             }
         }
         __syncthreads();
+    }
+}
+
+// The same with the lattices in groups: workgroup (chunk, group, f) counts its chunk for
+// the group's lattices [l0, l0 + ng), each in its own pair of LDS bitmaps (sw words per
+// lattice, sw >= ceil(M / 32) for every lattice), so that each entry's buckets of the
+// group are read together, once per workgroup (a chunk's rows were read by L workgroups,
+// spread over the chip, before).
+__global__ __launch_bounds__(kSingleThreads) void k_single_count_grp(
+    const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ n_det, int64_t cap,
+    const int32_t *__restrict__ det_hash, int chunks, int gs, int sw, int64_t wl, uint32_t *__restrict__ g_once,
+    uint32_t *__restrict__ g_twice)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *once = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *twice = once + gs * sw;
+    const int f = blockIdx.z, l0 = blockIdx.y * gs, ng = min(gs, L - l0);
+    const int64_t n = n_of(n_det, f, cap);
+    const int64_t per = (n + chunks - 1) / chunks;
+    const int64_t q0 = (int64_t)blockIdx.x * per, q1 = min(n, q0 + per);
+    if (q0 >= q1) return;
+    for (int i = threadIdx.x; i < ng * sw; i += blockDim.x) { once[i] = 0u; twice[i] = 0u; }
+    __syncthreads();
+    const int32_t *hh = det_hash + (int64_t)f * cap * L + l0;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+        const int32_t *hq = hh + q * L;
+        for (int j0 = 0; j0 < ng; j0 += kSingleLoads) {
+            int hv[kSingleLoads];
+#pragma unroll
+            for (int k = 0; k < kSingleLoads; ++k) hv[k] = j0 + k < ng ? hq[j0 + k] : 0;
+#pragma unroll
+            for (int k = 0; k < kSingleLoads; ++k) {
+                if (j0 + k < ng) {
+                    const int wi = (j0 + k) * sw + (hv[k] >> 5);
+                    const uint32_t bit = 1u << (hv[k] & 31);
+                    if (atomicOr(once + wi, bit) & bit) atomicOr(twice + wi, bit);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < ng; ++j) {
+        const int nw = (lat[f * L + l0 + j].M + 31) >> 5;
+        uint32_t *go = g_once + ((int64_t)f * L + l0 + j) * wl;
+        uint32_t *gt = g_twice + ((int64_t)f * L + l0 + j) * wl;
+        for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+            const uint32_t o = once[j * sw + i];
+            if (o) {
+                const uint32_t prev = atomicOr(go + i, o);
+                const uint32_t t = twice[j * sw + i] | (prev & o);
+                if (t) atomicOr(gt + i, t);
+            }
+        }
     }
 }
 
@@ -442,27 +535,41 @@ __device__ __forceinline__ uint64_t load_mask(const uint32_t *__restrict__ mask,
     return mk;
 }
 
-// Up to LMAX <= 40 lattices: the values stay in registers.
-template <typename T, int LMAX>
+// Up to LMAX <= 40 lattices: the values stay in registers.  TW (long lists): the
+// singleton mask is formed here from the merged `twice` bitmaps and the buckets already
+// loaded for the gather, and written whole, instead of being read.
+template <typename T, int LMAX, bool TW>
 __global__ __launch_bounds__(256) void k_combine(
     const LatDesc *__restrict__ lat, int L, const int64_t *__restrict__ n_det, int64_t cap,
-    const int32_t *__restrict__ det_hash, const uint32_t *__restrict__ mask,
+    const int32_t *__restrict__ det_hash, uint32_t *__restrict__ mask,
     const typename cvec<T>::type *__restrict__ ghat, int postproc,
     typename cvec<T>::type *__restrict__ det_coef, typename cvec<T>::type *__restrict__ det_med,
-    double *__restrict__ det_w)
+    double *__restrict__ det_w, const uint32_t *__restrict__ g_twice, int64_t wl)
 {
     using V = typename cvec<T>::type;
-    const int f = blockIdx.y;
+    int f = blockIdx.y, bx = blockIdx.x;
+    if constexpr (TW) {
+        // workgroups are dealt to the 8 XCDs in turn; renumbered so that each XCD takes a
+        // contiguous range of (function, block) pairs, i.e. the lattice values of one or
+        // two functions, which its L2 then holds (the host makes the count a multiple of 8)
+        const int G = gridDim.x * gridDim.y, w = blockIdx.y * gridDim.x + blockIdx.x;
+        const int i = (w & 7) * (G >> 3) + (w >> 3);
+        f = i / gridDim.x;
+        bx = i - f * gridDim.x;
+    }
     const int64_t n = n_of(n_det, f, cap);
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t q = bx * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = (int64_t)f * cap + q;
     T vr[LMAX], vi[LMAX];
+    int32_t hl[TW ? LMAX : 1];
     const T inf = __builtin_inf();
 #pragma unroll
     for (int l = 0; l < LMAX; ++l) {
         vr[l] = inf; vi[l] = inf;
         if (l < L) {
-            const V g = ghat[lat[f * L + l].node_off + det_hash[e * L + l]];
+            const int32_t h = det_hash[e * L + l];
+            if constexpr (TW) hl[l] = h;
+            const V g = ghat[lat[f * L + l].node_off + h];
             vr[l] = g.x; vi[l] = g.y;
         }
     }
@@ -470,7 +577,18 @@ __global__ __launch_bounds__(256) void k_combine(
     int r0, r1, i0, i1;
     median_sel<T, LMAX>(vr, L, mr, r0, r1);
     median_sel<T, LMAX>(vi, L, mi, i0, i1);
-    const uint64_t mk = load_mask(mask, e, L);
+    uint64_t mk = 0;
+    if constexpr (TW) {
+        const uint32_t *gt = g_twice + (int64_t)f * L * wl;
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l)
+            if (l < L && !((gt[(int64_t)l * wl + (hl[l] >> 5)] >> (hl[l] & 31)) & 1u)) mk |= 1ull << l;
+        const int W = mask_words(L);
+        mask[e * W] = (uint32_t)mk;
+        if (W > 1) mask[e * W + 1] = (uint32_t)(mk >> 32);
+    } else {
+        mk = load_mask(mask, e, L);
+    }
     T sr = 0, si = 0;
 #pragma unroll
     for (int l = 0; l < LMAX; ++l)
@@ -685,15 +803,29 @@ int gsort_run(Plan &p, uint64_t *key, int32_t *pos, int64_t P)
 // (counts per block of 1024 words, a scan of the counts, then the emission).
 constexpr int kFlagWordsPerBlock = 1024;   // 256 threads x 4 words
 
+// The vote appends each wave's detections as an ascending run, so the entries of a word
+// mostly sit in adjacent lanes: each lane ORs in the bits of the lanes after it that hit
+// the same word (a suffix OR over 32 lanes), and only the first lane of each such group
+// issues the atomic.  Lanes of one group that are not adjacent still set their own word.
 __global__ __launch_bounds__(256) void k_flag_det(const int64_t *__restrict__ n_det, int64_t cap,
                                                   const int64_t *__restrict__ det_idx,
                                                   const int64_t *__restrict__ set_off, uint32_t *__restrict__ flags)
 {
     const int f = blockIdx.y;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n_of(n_det, f, cap)) return;
-    const int64_t c = set_off[f] + det_idx[(int64_t)f * cap + q];
-    atomicOr(flags + (c >> 5), 1u << (c & 31));
+    const bool act = q < n_of(n_det, f, cap);
+    const int64_t c = act ? set_off[f] + det_idx[(int64_t)f * cap + q] : -64;
+    const int64_t w = c >> 5;   // lanes past the list: word -2, never a real one
+    uint32_t b = act ? 1u << (c & 31) : 0u;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+        const uint32_t nb = __shfl_down(b, o);
+        const int64_t nw = __shfl_down(w, o);
+        if (lane + o < 64 && nw == w) b |= nb;
+    }
+    const int64_t pw = __shfl_up(w, 1);
+    if (act && (lane == 0 || pw != w)) atomicOr(flags + w, b);
 }
 
 // bits of word w that belong to the candidate range [lo, hi)
@@ -1090,19 +1222,28 @@ __global__ __launch_bounds__(kSortThreads) void k_limit_sel(int64_t cap, const i
 }
 
 // ------------------------------------------------------------------ host
+// g_twice (long lists): the merged `twice` bitmaps, wl words per lattice, from which the
+// singleton masks are formed (by the combine kernel itself up to 40 lattices).
 template <typename T>
 static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, int64_t nmax, const int32_t *det_hash,
-                          const uint32_t *mask, const void *ghat, int postproc, void *det_coef, void *det_med,
-                          double *det_w)
+                          uint32_t *mask, const void *ghat, int postproc, void *det_coef, void *det_med,
+                          double *det_w, int64_t scale, const uint32_t *g_twice, int64_t wl)
 {
     using V = typename cvec<T>::type;
     // a bounded number of workgroups per function (the kernels loop): most functions' lists
     // are far shorter than the capacity, and launching a workgroup per 256 entries of it
-    // cost more than the work
-    dim3 grid(tail_blocks((nmax + 255) / 256, p.F), (unsigned)p.F), blk(256);
-#define MR1L_COMB(LM)                                                                                       \
-    hipLaunchKernelGGL((k_combine<T, LM>), grid, blk, 0, p.stream, p.d_lat, p.L, n_det, cap, det_hash, mask, \
-                       (const V *)ghat, postproc, (V *)det_coef, (V *)det_med, det_w)
+    // cost more than the work; long lists (scale > 1) need more waves in flight, since
+    // every entry gathers L scattered lattice values
+    dim3 grid(tail_blocks((nmax + 255) / 256, p.F, scale), (unsigned)p.F), blk(256);
+    if (g_twice) grid.x = (grid.x + 7) & ~7u;   // the long-list kernel's XCD renumbering
+#define MR1L_COMB(LM)                                                                                          \
+    if (g_twice)                                                                                               \
+        hipLaunchKernelGGL((k_combine<T, LM, true>), grid, blk, 0, p.stream, p.d_lat, p.L, n_det, cap, det_hash, \
+                           mask, (const V *)ghat, postproc, (V *)det_coef, (V *)det_med, det_w, g_twice, wl);    \
+    else                                                                                                       \
+        hipLaunchKernelGGL((k_combine<T, LM, false>), grid, blk, 0, p.stream, p.d_lat, p.L, n_det, cap,         \
+                           det_hash, mask, (const V *)ghat, postproc, (V *)det_coef, (V *)det_med, det_w,       \
+                           nullptr, (int64_t)0)
     if (p.L <= 8) MR1L_COMB(8);
     else if (p.L <= 12) MR1L_COMB(12);
     else if (p.L <= 16) MR1L_COMB(16);
@@ -1110,10 +1251,16 @@ static int combine_launch(Plan &p, const int64_t *n_det, int64_t cap, int64_t nm
     else if (p.L <= 24) MR1L_COMB(24);
     else if (p.L <= 32) MR1L_COMB(32);
     else if (p.L <= 40) MR1L_COMB(40);
-    else
+    else {
+        if (g_twice) {
+            hipLaunchKernelGGL(k_single_mask, dim3((unsigned)((nmax + 255) / 256), (unsigned)p.F), dim3(256), 0,
+                               p.stream, p.d_lat, p.L, n_det, cap, det_hash, wl, g_twice, mask);
+            MR1L_LAUNCH_CHECK();
+        }
         hipLaunchKernelGGL(k_combine_wide<T>, dim3(tail_blocks((nmax + 63) / 64, p.F, 4), (unsigned)p.F), dim3(64), 0, p.stream,
                            p.d_lat, p.L, n_det, cap, det_hash, mask, (const V *)ghat, postproc, (V *)det_coef,
                            (V *)det_med, det_w);
+    }
 #undef MR1L_COMB
     MR1L_LAUNCH_CHECK();
     return MR1L_OK;
@@ -1135,7 +1282,8 @@ int extract_init_attrs()
 {
     const std::pair<const void *, int> ks[] = {
         {(const void *)k_singleton, 2 * kSingleWords * (int)sizeof(uint32_t)},
-        {(const void *)k_single_count, 2 * kSingleWords * (int)sizeof(uint32_t)}};
+        {(const void *)k_single_count, 2 * kSingleWords * (int)sizeof(uint32_t)},
+        {(const void *)k_single_count_grp, 2 * kSingleWords * (int)sizeof(uint32_t)}};
     for (const auto &k : ks) MR1L_HIP(hipFuncSetAttribute(k.first, hipFuncAttributeMaxDynamicSharedMemorySize, k.second));
     int rc = sort_attrs<1>();
     if (!rc) rc = sort_attrs<2>();
@@ -1164,6 +1312,17 @@ static int sort_e(int64_t cap)
     case 4: X(4); break;           \
     default: X(8); break;          \
     }
+
+// Register arrays of the per-candidate kernels sized to the next of 8, 12, ..., 64 lattices.
+#define MR1L_BY_L(L_, X)                         \
+    if ((L_) <= 8) X(8);                         \
+    else if ((L_) <= 12) X(12);                  \
+    else if ((L_) <= 16) X(16);                  \
+    else if ((L_) <= 20) X(20);                  \
+    else if ((L_) <= 24) X(24);                  \
+    else if ((L_) <= 32) X(32);                  \
+    else if ((L_) <= 40) X(40);                  \
+    else X(64);
 
 static int grow_sort(Plan &p, int64_t P)
 {
@@ -1374,9 +1533,13 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
         }
     }
     if (nmax > 0) {
-        dim3 gq(tail_blocks((nmax * p.L + 255) / 256, p.F, 4), (unsigned)p.F);
-        hipLaunchKernelGGL(k_det_hash, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat, p.d_z32,
-                           p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
+        dim3 gq(tail_blocks((nmax + kDetHashThreads - 1) / kDetHashThreads, p.F, 4), (unsigned)p.F);
+        const size_t hb = (size_t)kDetHashThreads * p.L * sizeof(int32_t);
+#define MR1L_DH(LM)                                                                                          \
+    hipLaunchKernelGGL(k_det_hash<LM>, gq, dim3(kDetHashThreads), hb, p.stream, freq, n_total, set_off, p.L, \
+                       p.d, p.d_lat, p.d_z32, p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash)
+        MR1L_BY_L(p.L, MR1L_DH)
+#undef MR1L_DH
         MR1L_LAUNCH_CHECK();
     }
     if (large) {   // (short lists: k_sort_det cleared the masks)
@@ -1386,6 +1549,8 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
     int64_t maxM = 1;
     for (int64_t m : p.M) maxM = std::max(maxM, m);
     const int words = (int)std::min<int64_t>(kSingleWords, (maxM + 31) / 32);
+    const uint32_t *tw = nullptr;   // merged `twice` bitmaps of the long-list path
+    int64_t twl = 0;
     if (!large || nmax <= kMaxCap) {
         hipLaunchKernelGGL(k_singleton, dim3(p.L, p.F), dim3(256), 2 * (size_t)words * sizeof(uint32_t), p.stream,
                            p.d_lat, p.L, out.n_det, cap, det_hash, det_mask, words);
@@ -1403,23 +1568,34 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
         }
         uint32_t *g_once = p.d_single, *g_twice = p.d_single + (int64_t)p.F * p.L * wl;
         if ((rc = launch_fill_u32(p.d_single, 2 * (int64_t)p.F * p.L * wl, 0u, p.stream))) return rc;
-        const int64_t by_cus = std::max<int64_t>(1, 2 * (int64_t)num_cus() / std::max<int64_t>(1, (int64_t)p.L * p.F));
-        const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(by_cus, (nmax + 4095) / 4096));
-        hipLaunchKernelGGL(k_single_count, dim3((unsigned)chunks, (unsigned)p.L, (unsigned)p.F), dim3(kSingleThreads),
-                           2 * (size_t)words * sizeof(uint32_t), p.stream, p.d_lat, p.L, out.n_det, cap, det_hash,
-                           chunks, wl, g_once, g_twice, words);
+        if (wl <= kSingleWords) {
+            // as many lattices per workgroup as the LDS holds; about one workgroup per CU
+            const int gs = (int)std::min<int64_t>(p.L, kSingleWords / wl);
+            const int groups = (p.L + gs - 1) / gs;
+            const int64_t by_cus = std::max<int64_t>(1, (int64_t)num_cus() / ((int64_t)groups * p.F));
+            const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(by_cus, (nmax + 4095) / 4096));
+            hipLaunchKernelGGL(k_single_count_grp, dim3((unsigned)chunks, (unsigned)groups, (unsigned)p.F),
+                               dim3(kSingleThreads), 2 * (size_t)gs * wl * sizeof(uint32_t), p.stream, p.d_lat, p.L,
+                               out.n_det, cap, det_hash, chunks, gs, (int)wl, wl, g_once, g_twice);
+        } else {
+            const int64_t by_cus =
+                std::max<int64_t>(1, 2 * (int64_t)num_cus() / std::max<int64_t>(1, (int64_t)p.L * p.F));
+            const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(by_cus, (nmax + 4095) / 4096));
+            hipLaunchKernelGGL(k_single_count, dim3((unsigned)chunks, (unsigned)p.L, (unsigned)p.F),
+                               dim3(kSingleThreads), 2 * (size_t)words * sizeof(uint32_t), p.stream, p.d_lat, p.L,
+                               out.n_det, cap, det_hash, chunks, wl, g_once, g_twice, words);
+        }
         MR1L_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_single_mask, dim3((unsigned)((nmax + 255) / 256), (unsigned)p.F), dim3(256), 0, p.stream,
-                           p.d_lat, p.L, out.n_det, cap, det_hash, wl, g_twice, det_mask);
-        MR1L_LAUNCH_CHECK();
+        tw = g_twice;
+        twl = wl;
     }
     const int64_t ncomb = std::max<int64_t>(nmax, 1);
     if (p.dtype == MR1L_C128)
         rc = combine_launch<double>(p, out.n_det, cap, ncomb, det_hash, det_mask, ghat, o.postproc, out.det_coef,
-                                    det_med, det_w);
+                                    det_med, det_w, large ? 16 : 1, tw, twl);
     else
         rc = combine_launch<float>(p, out.n_det, cap, ncomb, det_hash, det_mask, ghat, o.postproc, out.det_coef,
-                                   det_med, det_w);
+                                   det_med, det_w, large ? 16 : 1, tw, twl);
     if (rc) return rc;
     if (!large) {
         return limit_short(p, out.n_det, cap, out.det_idx, out.det_coef, o.theta, o.s_cap, out.n_out, out.out_idx,

@@ -815,6 +815,43 @@ def test_long_detected_lists_match_oracle(m, seed, F, L):
         assert torch.equal(a["out_idx"][fi], b["out_idx"][fi]) and torch.equal(a["out_coef"][fi], b["out_coef"][fi])
 
 
+@pytest.mark.parametrize("L,mlo,mhi,F", [(20, 39000, 41000, 2), (3, 700000, 720000, 1), (48, 2500, 3500, 1)])
+def test_long_lists_lattice_groups_match_oracle(m, L, mlo, mhi, F):
+    """Long detected lists whose bucket bitmaps need several LDS passes: 20 lattices of
+    M ~ 40000 (the occupancy count takes the lattices in two groups), 3 lattices of
+    M ~ 700000 (one lattice exceeds the LDS: per-lattice passes over bucket spans), and
+    48 lattices (the LDS-column combine with a separate mask pass).  The lattice values
+    are random and every bit of the non-zero bitmap is set, so every candidate is
+    detected; against the oracle on the same values."""
+    say("long lists, lattice groups", L, mlo, F)
+    rng = np.random.default_rng(7000 + L)
+    d = 3
+    sets, Ms, zs, gs = [], [], [], []
+    for fi in range(F):
+        sets.append(synth.distinct_uniform_points(rng, 20000 - 3000 * fi, d, -200, 200))
+        M, z = synth.draw_lattices(rng, L, d, mlo, mhi)
+        Ms.append(M)
+        zs.append(z)
+        gs.append(rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum())))
+    plan = m.Plan(d, np.concatenate(Ms), np.concatenate(zs), F=F)
+    g = T(np.concatenate(gs))
+    bm = torch.full(((plan.nodes + 31) // 32,), -1, dtype=torch.int32, device=dev())
+    off = np.concatenate([[0], np.cumsum([x.shape[1] for x in sets])]).astype(np.int64)
+    ex = m.mr1l_extract(plan, T(np.concatenate(sets, axis=1)), g, bm, 1e-9, s_cap=2500, cap=32768,
+                        set_off=T(off), want_w=False)
+    torch.cuda.synchronize()
+    for fi in range(F):
+        ro = oracle.extract(sets[fi], Ms[fi], zs[fi], gs[fi], 1e-9, s_cap=2500, cap=32768)
+        nd = int(ex["n_det"][fi])
+        assert nd == ro["n_det"] == sets[fi].shape[1]
+        assert np.array_equal(ex["det_idx"][fi, :nd].cpu().numpy(), ro["det_idx"])
+        assert np.array_equal(mask64(ex["det_mask"][fi, :nd]), ro["det_mask"])
+        close(ex["det_coef"][fi, :nd].cpu().numpy(), ro["det_coef"], 1e-11, "coefficients")
+        no = int(ex["n_out"][fi])
+        r = dict(out_idx=ex["out_idx"][fi, :no].cpu().numpy(), out_coef=ex["out_coef"][fi, :no].cpu().numpy())
+        check_limit(r, ro, EPS[torch.complex128], 1e-11)
+
+
 def test_empty_and_ragged_inputs(m):
     say("empty/ragged")
     p = synth.small_config(8)
