@@ -95,7 +95,20 @@ int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L,
                      const int64_t *M, const int64_t *z, int32_t dtype,
                      void *stream);
 
+/*
+ * Waits for the plan's stream and releases the plan.  Its device memory
+ * goes to a per-device cache of blocks that later plans (and the
+ * dimension-incremental driver) reuse, so that a loop creating and
+ * destroying plans does not pay hipMalloc/hipFree each time; the cache
+ * holds at most 8 GiB per device, and an allocation that fails empties it
+ * and retries.
+ */
 int mr1l_plan_destroy(mr1l_plan p);
+
+/* Frees the cached device blocks of the current device (plans in use keep
+ * theirs).  Not to be called while another thread creates or grows a plan
+ * on the same device. */
+int mr1l_release_cache(void);
 
 /* Total number of nodes (sum of all M); sizes f, ghat, counts. */
 int64_t mr1l_plan_nodes(mr1l_plan p);

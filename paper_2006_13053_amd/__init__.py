@@ -61,6 +61,7 @@ SIGNATURES = {
     "mr1l_last_error": ([], C.c_char_p),
     "mr1l_plan_create": ([C.POINTER(_P), _I32, _I32, _I32, _P, _P, _I32, _P], C.c_int),
     "mr1l_plan_destroy": ([_P], C.c_int),
+    "mr1l_release_cache": ([], C.c_int),
     "mr1l_plan_nodes": ([_P], _I64),
     "mr1l_plan_set_stream": ([_P, _P], C.c_int),
     "mr1l_plan_set_z": ([_P, _P], C.c_int),
@@ -244,6 +245,11 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def mr1l_release_cache():
+    """Free the library's cached device blocks of the current device."""
+    _check(lib().mr1l_release_cache(), "mr1l_release_cache")
 
 
 def mr1l_check_injective(plan: Plan, freq, set_off=None):

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libmr1l.so")
-SOURCES = ["abi.hip", "k_fft.hip", "k_hash.hip", "k_extract.hip", "k_sample.hip", "k_valid.hip", "k_pfpn.hip", "k_lsq.hip", "k_bspline.hip", "k_rader.hip", "dimincr.hip", "k_lfft_d.hip", "k_lfft_f.hip"]
+SOURCES = ["abi.hip", "devmem.hip", "k_fft.hip", "k_hash.hip", "k_extract.hip", "k_sample.hip", "k_valid.hip", "k_pfpn.hip", "k_lsq.hip", "k_bspline.hip", "k_rader.hip", "dimincr.hip", "k_lfft_d.hip", "k_lfft_f.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",

@@ -186,7 +186,10 @@ static void stage(Plan &p, void **dst, const void *src, size_t bytes)
 
 static int arena_commit(Plan &p)
 {
-    MR1L_HIP(hipMalloc(&p.d_arena, std::max<size_t>(p.h_arena.size(), 16)));
+    {
+        const int rc = dev_alloc(&p.d_arena, std::max<size_t>(p.h_arena.size(), 16));
+        if (rc) return rc;
+    }
     for (auto &f : p.arena_fix) *f.first = (unsigned char *)p.d_arena + f.second;
     p.arena_fix.clear();
     if (!p.h_arena.empty())
@@ -338,8 +341,7 @@ static int build_tables(Plan &p)
     stage(p, &p.d_tw, tw.data(), tw.size() * sizeof(T));
     stage(p, &p.d_chirp, ch.data(), ch.size() * sizeof(T));
     // the spectra are written by the DFT kernels (only the layouts in use)
-    MR1L_HIP(hipMalloc(&p.d_spec, std::max<size_t>((size_t)spec_len * esz, 16)));
-    return MR1L_OK;
+    return dev_alloc(&p.d_spec, std::max<size_t>((size_t)spec_len * esz, 16));
 }
 
 // Records of the vote pass (see Plan::d_vrec).
@@ -414,8 +416,7 @@ static int upload(Plan &p)
     int rc = arena_commit(p);
     if (rc) return rc;
     const size_t esz = p.dtype == MR1L_C128 ? 16 : 8;
-    MR1L_HIP(hipMalloc(&p.d_nodes_scratch, (size_t)std::max<int64_t>(p.nodes, 1) * esz));
-    return MR1L_OK;
+    return dev_alloc(&p.d_nodes_scratch, (size_t)std::max<int64_t>(p.nodes, 1) * esz);
 }
 
 // The auxiliary DFT streams of the current device: created once per device, shared
@@ -446,8 +447,8 @@ static void release(Plan *p)
     void *ptrs[] = {p->d_arena, p->d_spec, p->d_glists, p->d_specwork, p->d_fft_scratch, p->d_nodes_scratch,
                     p->d_cterm, p->d_thash, p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos,
                     p->d_ls, p->d_gsort, p->d_single, p->d_dflag, p->d_bs_dims};
-    for (void *q : ptrs)
-        if (q) (void)hipFree(q);
+    (void)hipStreamSynchronize(p->stream);   // the blocks go back to the cache
+    for (void *q : ptrs) dev_free(q);
     for (auto &ev : p->fft_ev)
         if (ev) (void)hipEventDestroy(ev);
     delete p;
@@ -475,11 +476,21 @@ int grow_scratch(Plan &p, void **ptr, int64_t bytes, int64_t &have)
 {
     if (have >= bytes && *ptr) return MR1L_OK;
     if (p.capturing) return fail(MR1L_E_ARG, "scratch must be sized before graph capture (run the call once)");
-    if (*ptr) (void)hipFree(*ptr);
-    *ptr = nullptr;
-    MR1L_HIP(hipMalloc(ptr, (size_t)std::max<int64_t>(bytes, 16)));
+    have = 0;
+    const int rc = plan_regrow(p, ptr, (size_t)std::max<int64_t>(bytes, 16));
+    if (rc) return rc;
     have = bytes;
     return MR1L_OK;
+}
+
+int plan_regrow(Plan &p, void **ptr, size_t bytes)
+{
+    if (*ptr) {
+        MR1L_HIP(hipStreamSynchronize(p.stream));
+        dev_free(*ptr);
+        *ptr = nullptr;
+    }
+    return dev_alloc(ptr, bytes);
 }
 
 static int grow(Plan &p, void **ptr, int64_t bytes, int64_t &have) { return grow_scratch(p, ptr, bytes, have); }

@@ -173,16 +173,31 @@ __global__ __launch_bounds__(kUnionWords) void k_union_emit(const uint32_t *__re
     }
 }
 
+// A device buffer of the driver, grown on demand; blocks go back to the library's cache
+// once the driver's stream is done with them.
 template <typename P> struct DevBuf {
+    hipStream_t s;
     P *p = nullptr;
     int64_t n = 0;
-    ~DevBuf() { if (p) (void)hipFree(p); }
+    explicit DevBuf(hipStream_t st) : s(st) {}
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf()
+    {
+        if (!p) return;
+        (void)hipStreamSynchronize(s);
+        dev_free(p);
+    }
     int need(int64_t cnt)
     {
         if (cnt <= n) return MR1L_OK;
-        if (p) (void)hipFree(p);
+        if (p) {
+            MR1L_HIP(hipStreamSynchronize(s));
+            dev_free(p);
+        }
         p = nullptr;
-        MR1L_HIP(hipMalloc(&p, sizeof(P) * (size_t)std::max<int64_t>(cnt, 1)));
+        n = 0;
+        if (int rc = dev_alloc((void **)&p, sizeof(P) * (size_t)std::max<int64_t>(cnt, 1))) return rc;
         n = cnt;
         return MR1L_OK;
     }
@@ -218,9 +233,9 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
     *n_out = 0;
     int64_t samples = 0;
 
-    DevBuf<int64_t> dprev, dJ, n_det, det_idx, n_o, out_idx, dset;
-    DevBuf<unsigned char> fbuf, gbuf, det_coef, out_coef;
-    DevBuf<uint32_t> bitmap;
+    DevBuf<int64_t> dprev{st}, dJ{st}, n_det{st}, det_idx{st}, n_o{st}, out_idx{st}, dset{st};
+    DevBuf<unsigned char> fbuf{st}, gbuf{st}, det_coef{st}, out_coef{st};
+    DevBuf<uint32_t> bitmap{st};
     int rc;
 
     // single-coordinate sets I^(t), t = 1..d
@@ -270,9 +285,9 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
             for (int j = 0; j < d - 1; ++j) anc1[(size_t)f * (d - 1) + j] = (uint32_t)(rs.next() >> 32);
         }
         toff[F1] = T1;
-        DevBuf<int64_t> drf, dtoff;
-        DevBuf<unsigned char> drc;
-        DevBuf<uint32_t> danc1;
+        DevBuf<int64_t> drf{st}, dtoff{st};
+        DevBuf<unsigned char> drc{st};
+        DevBuf<uint32_t> danc1{st};
         if ((rc = drf.need(std::max<int64_t>(1, (int64_t)rf.size()))) || (rc = dtoff.need(F1 + 1)) ||
             (rc = drc.need(std::max<int64_t>(1, (int64_t)rcf.size()))) || (rc = danc1.need((int64_t)anc1.size())))
             return rc;
@@ -337,10 +352,10 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
     int64_t prev_stride = nprev;   // columns of the SoA tuples in dprev
     if ((rc = dprev.need(nprev))) return rc;
     MR1L_HIP(hipMemcpyAsync(dprev.p, I1[0].data(), nprev * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    DevBuf<int64_t> dnext, dstat, dstage, drf;
-    DevBuf<unsigned char> drc;
-    DevBuf<uint32_t> dbits;
-    DevBuf<int32_t> dcnt;
+    DevBuf<int64_t> dnext{st}, dstat{st}, dstage{st}, drf{st};
+    DevBuf<unsigned char> drc{st};
+    DevBuf<uint32_t> dbits{st};
+    DevBuf<int32_t> dcnt{st};
     std::vector<int64_t> hst;   // a step's small host tables (uploaded in one copy)
     std::vector<uint64_t> bdims;   // B-spline coordinate masks per repetition (uploaded by the sampler)
     int rep_rt = 0;             // repetitions the replicated polynomial in drf/drc holds
@@ -538,9 +553,9 @@ extern "C" int mr1l_dimincr(const mr1l_dimincr_params *prm, mr1l_sample_fn fn, v
             std::vector<int64_t> soa2((size_t)d * h_nout);
             for (int64_t q = 0; q < h_nout; ++q)
                 for (int u = 0; u < d; ++u) soa2[(size_t)u * h_nout + q] = cur[(size_t)q * d + u];
-            DevBuf<int64_t> dsel, n2, i2, o2n, o2i;
-            DevBuf<unsigned char> c2, o2c;
-            DevBuf<double> res;
+            DevBuf<int64_t> dsel{st}, n2{st}, i2{st}, o2n{st}, o2i{st};
+            DevBuf<unsigned char> c2{st}, o2c{st};
+            DevBuf<double> res{st};
             if ((rc = dsel.need((int64_t)soa2.size())) || (rc = n2.need(1)) || (rc = i2.need(h_nout)) ||
                 (rc = c2.need(h_nout * esz)) || (rc = o2n.need(1)) || (rc = o2i.need(h_nout)) ||
                 (rc = o2c.need(h_nout * esz)) || (rc = res.need(1)))

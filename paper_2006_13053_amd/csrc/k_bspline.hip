@@ -126,10 +126,8 @@ int bspline_sample_run(Plan &p, int32_t d_poly, int32_t n_prod, const int32_t *o
         if (d_poly < 64 && (dims[i] >> d_poly)) return fail(MR1L_E_ARG, "dims names a coordinate >= d_poly");
     if (p.bs_bytes < nd * 8) {
         if (p.capturing) return fail(MR1L_E_ARG, "size the B-spline sampler before graph capture");
-        if (p.d_bs_dims) (void)hipFree(p.d_bs_dims);
-        p.d_bs_dims = nullptr;
         p.bs_bytes = 0;
-        MR1L_HIP(hipMalloc(&p.d_bs_dims, (size_t)nd * 8));
+        if (int rc = plan_regrow(p, (void **)&p.d_bs_dims, (size_t)nd * 8)) return rc;
         p.bs_bytes = nd * 8;
     }
     MR1L_HIP(hipMemcpyAsync(p.d_bs_dims, dims, (size_t)nd * 8, hipMemcpyHostToDevice, p.stream));

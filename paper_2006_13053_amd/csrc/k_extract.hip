@@ -1329,10 +1329,9 @@ static int grow_sort(Plan &p, int64_t P)
     const int64_t bytes = p.F * P * 12;
     if (p.gsort_bytes >= bytes && p.d_gsort) return MR1L_OK;
     if (p.capturing) return fail(MR1L_E_ARG, "lists longer than 8192 cannot be recorded in a graph");
-    if (p.d_gsort) (void)hipFree(p.d_gsort);
-    p.d_gsort = nullptr;
     p.gsort_bytes = 0;
-    MR1L_HIP(hipMalloc(&p.d_gsort, (size_t)bytes));
+    const int rc = plan_regrow(p, (void **)&p.d_gsort, (size_t)bytes);
+    if (rc) return rc;
     p.gsort_bytes = bytes;
     return MR1L_OK;
 }
@@ -1361,10 +1360,8 @@ static int limit_long(Plan &p, const int64_t *n_det, int64_t cap, const int64_t 
     const int64_t bytes = b_keys + b_kept + b_hist + b_st + b_cnt + b_nsel + 64;
     if (p.gsort_bytes < bytes || !p.d_gsort) {
         if (p.capturing) return fail(MR1L_E_ARG, "lists longer than 8192 cannot be recorded in a graph");
-        if (p.d_gsort) (void)hipFree(p.d_gsort);
-        p.d_gsort = nullptr;
         p.gsort_bytes = 0;
-        MR1L_HIP(hipMalloc(&p.d_gsort, (size_t)bytes));
+        if (int rc = plan_regrow(p, (void **)&p.d_gsort, (size_t)bytes)) return rc;
         p.gsort_bytes = bytes;
     }
     unsigned char *base = (unsigned char *)p.d_gsort;
@@ -1510,10 +1507,8 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
             const int64_t fwords = (n_total + 31) / 32 + 1;
             const int64_t bytes = fwords * 4 + (int64_t)p.F * nx * 4;
             if (p.dflag_bytes < bytes || !p.d_dflag) {
-                if (p.d_dflag) (void)hipFree(p.d_dflag);
-                p.d_dflag = nullptr;
                 p.dflag_bytes = 0;
-                MR1L_HIP(hipMalloc(&p.d_dflag, (size_t)bytes));
+                if ((rc = plan_regrow(p, (void **)&p.d_dflag, (size_t)bytes))) return rc;
                 p.dflag_bytes = bytes;
             }
             uint32_t *flags = p.d_dflag;
@@ -1560,10 +1555,8 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
         const int64_t wl = (maxM + 31) / 32;
         const int64_t bytes = 2 * (int64_t)p.F * p.L * wl * (int64_t)sizeof(uint32_t);
         if (p.single_bytes < bytes || !p.d_single) {
-            if (p.d_single) (void)hipFree(p.d_single);
-            p.d_single = nullptr;
             p.single_bytes = 0;
-            MR1L_HIP(hipMalloc(&p.d_single, (size_t)bytes));
+            if ((rc = plan_regrow(p, (void **)&p.d_single, (size_t)bytes))) return rc;
             p.single_bytes = bytes;
         }
         uint32_t *g_once = p.d_single, *g_twice = p.d_single + (int64_t)p.F * p.L * wl;

@@ -966,10 +966,8 @@ static int ensure_scratch(Plan &p, int64_t len, int64_t slots)
     slots = std::min(std::max<int64_t>({slots, (int64_t)p.fft_slots, 1}), cap);
     if (p.d_fft_scratch && len == p.fft_slot_len && slots == p.fft_slots) return MR1L_OK;
     MR1L_HIP(hipStreamSynchronize(p.stream));
-    if (p.d_fft_scratch) (void)hipFree(p.d_fft_scratch);
-    p.d_fft_scratch = nullptr;
     p.fft_slots = 0;
-    MR1L_HIP(hipMalloc(&p.d_fft_scratch, (size_t)(slots * len * esz)));
+    if (int rc = plan_regrow(p, &p.d_fft_scratch, (size_t)(slots * len * esz))) return rc;
     p.fft_slot_len = len;
     p.fft_slots = (int32_t)slots;
     return MR1L_OK;
@@ -1028,10 +1026,9 @@ int fft_apply_schedules(Plan &p, bool fresh)
         p.h_glists.insert(p.h_glists.end(), g.lats.begin(), g.lats.end());
     }
     if ((int64_t)p.h_glists.size() > p.glists_cap) {
-        if (p.d_glists) (void)hipFree(p.d_glists);
-        p.d_glists = nullptr;
         p.glists_cap = 0;
-        MR1L_HIP(hipMalloc(&p.d_glists, std::max<size_t>(p.h_glists.size(), 1) * sizeof(int32_t)));
+        if (int rc = plan_regrow(p, (void **)&p.d_glists, std::max<size_t>(p.h_glists.size(), 1) * sizeof(int32_t)))
+            return rc;
         p.glists_cap = (int64_t)p.h_glists.size();
     }
     if (!p.h_glists.empty())
@@ -1126,10 +1123,8 @@ static int fft_prepare_spectra(Plan &p)
     const size_t bytes = rep_at + reps.size() * sizeof(int32_t);
     if ((int64_t)bytes > p.specwork_bytes) {
         MR1L_HIP(hipStreamSynchronize(p.stream));
-        if (p.d_specwork) (void)hipFree(p.d_specwork);
-        p.d_specwork = nullptr;
         p.specwork_bytes = 0;
-        MR1L_HIP(hipMalloc(&p.d_specwork, bytes));
+        if (int rc = plan_regrow(p, &p.d_specwork, bytes)) return rc;
         p.specwork_bytes = (int64_t)bytes;
     }
     p.h_specwork.assign(bytes, 0);

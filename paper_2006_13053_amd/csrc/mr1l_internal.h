@@ -263,6 +263,14 @@ int fail(int code, const std::string &msg);
 int launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 int launch_fill_bytes(void *p, int64_t nbytes, hipStream_t s);  // zero fill
 
+// Device memory through the per-device block cache (devmem.hip).  dev_free takes blocks
+// the device is done with (the caller has synchronised the stream that used them).
+int dev_alloc(void **ptr, size_t bytes);
+void dev_free(void *ptr);
+// *ptr replaced by a block of at least `bytes` bytes (contents not kept); the old block
+// is released once the plan's stream is done with it.
+int plan_regrow(Plan &p, void **ptr, size_t bytes);
+
 // Plan scratch of at least `bytes` bytes in *ptr (capacity in `have`): reallocated when
 // smaller, refused while the plan records a graph (a recorded kernel keeps the pointer).
 int grow_scratch(Plan &p, void **ptr, int64_t bytes, int64_t &have);

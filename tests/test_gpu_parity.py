@@ -205,6 +205,37 @@ def test_plan_created_on_one_stream_runs_on_another(m):
         p.close()
 
 
+def test_plans_reuse_cached_device_blocks(m):
+    """Plans destroyed and created in turn reuse the library's cached device blocks (also
+    the long-list scratch, which grows inside the call): every round gives the first
+    round's results, before and after the cache is emptied."""
+    say("device block cache")
+    rng = np.random.default_rng(91)
+    d, L = 3, 7
+    cand = synth.distinct_uniform_points(rng, 12000, d, -100, 100)
+    M, z = synth.draw_lattices(rng, L, d, 3000, 4000)
+    g_np = rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum()))
+
+    def run():
+        plan = m.Plan(d, M, z)
+        g = T(g_np)
+        bm = torch.full(((plan.nodes + 31) // 32,), -1, dtype=torch.int32, device=dev())
+        ex = m.mr1l_extract(plan, T(cand), g, bm, 1e-9, s_cap=500, cap=16384, want_w=False)
+        torch.cuda.synchronize()
+        out = [ex[k].clone() for k in ("n_det", "det_idx", "det_coef", "det_mask", "n_out", "out_idx", "out_coef")]
+        plan.close()
+        return out
+
+    ref = run()
+    assert int(ref[0][0]) == 12000
+    for rep in range(4):
+        if rep == 2:
+            m.mr1l_release_cache()
+        got = run()
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b), rep
+
+
 def _fft_check(m, plan, f, dtype, rng):
     g, _ = m.mr1l_fft(plan, T(f.astype(np.complex128)).to(dtype), theta=0.05)
     torch.cuda.synchronize()
