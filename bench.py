@@ -625,7 +625,8 @@ def bench_bspline(m, torch, args):
         out_rows.append(dict(N=N, s=s, M=Mlat, runs=args.reps, max_rel_l2_error=max(errs),
                              max_rel_l2_error_least_squares=max(errs_ls),
                              printed_max_rel_l2_error=row["max_rel_l2_error"], max_samples=max(samp),
-                             printed_max_samples=row["max_samples"], s_per_run=float(np.mean(ts))))
+                             printed_max_samples=row["max_samples"], s_per_run=float(np.mean(ts)),
+                             s_runs=[round(float(x), 4) for x in ts]))
         times += ts
     out = {"metric": "dimension-incremental run time on the eq. (4.3) function (mean over the Table 4.4 grid)",
            "value": float(np.mean(times)), "unit": "s", "n_gpus": 1, "steps": len(times), "warmup": 0,

@@ -99,8 +99,9 @@ int mr1l_plan_create(mr1l_plan *out, int32_t d, int32_t F, int32_t L,
  * Waits for the plan's stream and releases the plan.  Its device memory
  * goes to a per-device cache of blocks that later plans (and the
  * dimension-incremental driver) reuse, so that a loop creating and
- * destroying plans does not pay hipMalloc/hipFree each time; the cache
- * holds at most 8 GiB per device, and an allocation that fails empties it
+ * destroying plans does not pay hipMalloc/hipFree each time (a request
+ * takes a cached block of up to twice its size); the cache holds at most an
+ * eighth of the device's memory, and an allocation that fails empties it
  * and retries.
  */
 int mr1l_plan_destroy(mr1l_plan p);

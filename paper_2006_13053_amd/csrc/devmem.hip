@@ -3,11 +3,14 @@
 // then reuses the blocks of the previous plans instead of paying hipMalloc and hipFree
 // (which waits for the whole device) every time.
 //
-// Blocks are handed out in size classes of four per octave (at most 25% over the request)
-// and matched by class.  A block goes back to the cache only once the device is done with
-// it: every caller synchronises the stream its work ran on before dev_free.  The cache
-// keeps at most kCacheMax bytes per device; beyond that, and on mr1l_release_cache, blocks
+// Blocks are allocated in size classes of four per octave (at most 25% over the request);
+// a request takes the smallest cached block of its class or up to twice its class (buffers
+// that grow from call to call, like the driver's candidate lists, then find the previous
+// call's blocks).  A block goes back to the cache only once the device is done with it:
+// every caller synchronises the stream its work ran on before dev_free.  The cache keeps
+// at most an eighth of the device's memory; beyond that, and on mr1l_release_cache, blocks
 // are freed.  An allocation that fails empties the device's cache and tries once more.
+#include <map>
 #include <mutex>
 #include <unordered_map>
 
@@ -18,13 +21,13 @@ namespace mr1l {
 namespace {
 
 constexpr int kMaxDevices = 64;
-constexpr size_t kCacheMax = size_t(8) << 30;
 
 struct Cache {
     std::mutex mu;
-    std::unordered_map<size_t, std::vector<void *>> free;   // class bytes -> cached blocks
-    std::unordered_map<void *, size_t> cls;                 // every live or cached block
+    std::map<size_t, std::vector<void *>> free;   // class bytes -> cached blocks (none empty)
+    std::unordered_map<void *, size_t> cls;       // every live or cached block
     size_t cached = 0;
+    size_t limit = 0;                             // an eighth of the device memory
 };
 
 Cache g_cache[kMaxDevices];
@@ -65,11 +68,16 @@ int dev_alloc(void **ptr, size_t bytes)
     Cache &c = g_cache[dev];
     const size_t k = size_class(std::max<size_t>(bytes, 16));
     std::lock_guard<std::mutex> g(c.mu);
-    auto it = c.free.find(k);
-    if (it != c.free.end() && !it->second.empty()) {
+    if (c.limit == 0) {
+        size_t fr = 0, total = 0;
+        c.limit = hipMemGetInfo(&fr, &total) == hipSuccess && total > 0 ? total / 8 : size_t(8) << 30;
+    }
+    auto it = c.free.lower_bound(k);
+    if (it != c.free.end() && it->first <= 2 * k) {
         *ptr = it->second.back();
         it->second.pop_back();
-        c.cached -= k;
+        c.cached -= it->first;
+        if (it->second.empty()) c.free.erase(it);
         return MR1L_OK;
     }
     hipError_t e = hipMalloc(ptr, k);
@@ -102,7 +110,7 @@ void dev_free(void *ptr)
         return;
     }
     const size_t k = it->second;
-    if (c.cached + k > kCacheMax) {
+    if (c.cached + k > c.limit) {
         c.cls.erase(it);
         (void)hipFree(ptr);
         return;
