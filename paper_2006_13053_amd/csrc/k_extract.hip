@@ -4,7 +4,9 @@
 //  k_sort_det    detected set of each function in ascending candidate order
 //                (one workgroup per function, bitonic sort in registers, lane
 //                shuffles and, for the longest distances only, LDS).
-//  k_det_hash    buckets h_l(k) of every detected candidate.
+//  k_det_hash_pairs / k_det_hash  buckets h_l(k) of every detected candidate
+//                (one thread per candidate and lattice for short lists, one per
+//                candidate for long ones).
 //  k_singleton   whether each bucket holds one or several detected candidates,
 //                one workgroup per lattice with two LDS bitmaps; bit l of
 //                mask[q] is set when candidate q is alone in its bucket (the
@@ -211,6 +213,44 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__rest
 // Fast path (every |k_u| within the function's bound kb): 24-bit multiply-adds in 32-bit
 // integers and the float-reciprocal modulo; else the exact 64-bit reduction.  Both give
 // the same bucket.
+__device__ __forceinline__ int32_t det_bucket(const int64_t *__restrict__ freq, int64_t n_total, int64_t ci, int d,
+                                              const LatDesc &ld, const int32_t *__restrict__ z32,
+                                              const int64_t *__restrict__ z64, int32_t kb)
+{
+    uint32_t s = ld.off32;
+    bool fast = true;
+    for (int u = 0; u < d; ++u) {
+        const int64_t k = freq[(int64_t)u * n_total + ci];
+        fast = fast & (k >= -kb) & (k <= kb);
+        s += (uint32_t)__mul24((int32_t)k, z32[ld.z_off + u]);
+    }
+    return fast ? (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m)
+                : exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
+}
+
+// Short lists (capacity <= 8192): one thread per (detected candidate, lattice); the L
+// threads of a candidate read the same coordinates (cache hits after the first) and
+// write adjacent buckets.  With few, scattered detections in a large candidate set the
+// coordinate reads are random, and the L-fold parallelism hides their latency better
+// than one thread per candidate.
+__global__ __launch_bounds__(256) void k_det_hash_pairs(
+    const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int L, int d,
+    const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32, const int64_t *__restrict__ z64,
+    const int32_t *__restrict__ kbound, const int64_t *__restrict__ n_det, int64_t cap,
+    const int64_t *__restrict__ det_idx, int32_t *__restrict__ det_hash)
+{
+    const int f = blockIdx.y;
+    const int64_t nl = n_of(n_det, f, cap) * L;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nl; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = t / L;
+        const int l = (int)(t - q * L);
+        const int64_t ci = set_off[f] + det_idx[(int64_t)f * cap + q];
+        det_hash[((int64_t)f * cap + q) * L + l] =
+            det_bucket(freq, n_total, ci, d, lat[f * L + l], z32, z64, kbound[f]);
+    }
+}
+
+// Long lists: one thread per detected candidate.
 // One thread per detected candidate: its d coordinates are read once (adjacent threads
 // hold adjacent entries of the ascending list) and hashed into all L lattices of its
 // function, with L running sums in registers; the lattice records and z words are
@@ -1527,7 +1567,12 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
             MR1L_LAUNCH_CHECK();
         }
     }
-    if (nmax > 0) {
+    if (nmax > 0 && !large) {
+        dim3 gq(tail_blocks((nmax * p.L + 255) / 256, p.F, 4), (unsigned)p.F);
+        hipLaunchKernelGGL(k_det_hash_pairs, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat,
+                           p.d_z32, p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
+        MR1L_LAUNCH_CHECK();
+    } else if (nmax > 0) {
         dim3 gq(tail_blocks((nmax + kDetHashThreads - 1) / kDetHashThreads, p.F, 4), (unsigned)p.F);
         const size_t hb = (size_t)kDetHashThreads * p.L * sizeof(int32_t);
 #define MR1L_DH(LM)                                                                                          \
