@@ -282,12 +282,13 @@ __device__ __forceinline__ int in_pos(int t, int c, int m)
 
 // LDS index of plane entry q: one pad entry after every 16 doubles (32 floats), so
 // that the first pass's outputs (stride E entries across the lanes) fall in distinct
-// banks; runs of 16 or more consecutive lanes stay conflict-free.  This holds for E a
-// multiple of 8 (16, 32, 40: stride 40 without the pad puts a half-wave's doubles in
-// two bank pairs, a 16-way conflict; with it the Rader transform of length 16000 takes
-// 7% less time).  With E = 20 (the other radix-20 transforms) the plane is left
-// unpadded.
-template <typename T, int E = 16> constexpr int pad_shift() { return E % 8 ? 30 : (sizeof(T) == 8 ? 4 : 5); }
+// banks; runs of 16 or more consecutive lanes stay conflict-free.  E = 40 (the Rader
+// transform of length 16000) takes one pad entry per 8 entries: its first pass's
+// stride-40 stores, unpadded, put a half-wave's doubles in two bank pairs (a 16-way
+// conflict), and with period 8 the base 40 t of those stores stays a multiple of the
+// period, so every offset is an immediate (period 16 gave 5% more time).  With E = 20
+// (the other radix-20 transforms) the plane is left unpadded.
+template <typename T, int E = 16> constexpr int pad_shift() { return E % 8 ? 30 : E % 16 ? 3 : (sizeof(T) == 8 ? 4 : 5); }
 template <typename T, int E = 16> __device__ __forceinline__ int padq(int q) { return q + (q >> pad_shift<T, E>()); }
 // Entries of one padded plane of length N.
 template <typename T, int E = 16> constexpr int plane_len(int N) { return N + (N >> pad_shift<T, E>()); }
@@ -297,11 +298,12 @@ template <typename T, int E = 16> constexpr int plane_len(int N) { return N + (N
 // because NT and the sub-length are powers of two, one dividing the other); where K
 // is a multiple of the pad period the padded index is padq(base) + K + the pad of K,
 // so the address is one register plus an immediate offset.
-template <typename T, int E>
+// BAL: base is a multiple of the pad period, so every K gives an immediate offset.
+template <typename T, int E, bool BAL = false>
 __device__ __forceinline__ int padded(int base, int pbase, int K)
 {
     constexpr int sh = pad_shift<T, E>();
-    return (sh >= 30 || K % (1 << sh) == 0) ? pbase + K + (K >> sh) : padq<T, E>(base + K);
+    return (sh >= 30 || BAL || K % (1 << sh) == 0) ? pbase + K + (K >> sh) : padq<T, E>(base + K);
 }
 
 template <typename T, int N, int E, int RO, int LO>
@@ -309,6 +311,9 @@ __device__ __forceinline__ void put_plane(T *pl, const T (&x)[E], int t)
 {
     constexpr int NT = N / E;
     constexpr bool A = NT % LO == 0, B = LO % NT == 0;
+    constexpr int sh = pad_shift<T, E>();
+    // first pass (LO = 1): base = t RO, a multiple of the pad period when RO is
+    constexpr bool BAL = A && LO == 1 && sh < 30 && RO % (1 << (sh < 30 ? sh : 0)) == 0;
     const int base = A ? (t / LO) * LO * RO + (t % LO) : t;
     const int pb = padq<T, E>(base);
 #pragma unroll
@@ -318,7 +323,7 @@ __device__ __forceinline__ void put_plane(T *pl, const T (&x)[E], int t)
             if constexpr (A || B) {
                 const int qc = (NT * c) / LO, rc = (NT * c) % LO;   // B: NT c = qc LO + rc, rc + t < LO
                 const int K = A ? NT * c * RO + p * LO : qc * LO * RO + rc + p * LO;
-                pl[padded<T, E>(base, pb, K)] = x[c * RO + p];
+                pl[padded<T, E, BAL>(base, pb, K)] = x[c * RO + p];
             } else {
                 pl[padq<T, E>(out_pos<N, E, RO, LO>(t, c, p))] = x[c * RO + p];
             }
