@@ -205,7 +205,7 @@ def stage_rooflines(w, plan, stages, ex, n_total, dtype):
     ffrac = fbytes / (fft_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
     fft = {"achieved": fbytes / (fft_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": ffrac, "target_frac": 0.6, "gap_to_target": 0.6 - ffrac,
-           "bound": "in-register transforms and LDS exchanges (VALU busy about a third of the time); with "
+           "bound": "in-register transforms and LDS exchanges (VALU busy 21-42% of the time); with "
                     "distinct sizes also one kernel-spectrum read per lattice, so the HBM traffic exceeds "
                     "the algorithmic bytes 2-5x",
            "ms_per_launch": fft_ms,
