@@ -207,8 +207,8 @@ def test_plan_created_on_one_stream_runs_on_another(m):
 
 def test_plans_reuse_cached_device_blocks(m):
     """Plans destroyed and created in turn reuse the library's cached device blocks (also
-    the long-list scratch, which grows inside the call): every round gives the first
-    round's results, before and after the cache is emptied."""
+    the long-list scratch, which grows inside the call): every repetition gives the first
+    one's results, before and after the cache is emptied."""
     say("device block cache")
     rng = np.random.default_rng(91)
     d, L = 3, 7
