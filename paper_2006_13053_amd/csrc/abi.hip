@@ -446,6 +446,7 @@ static void release(Plan *p)
     // (the tables in the arena are not freed one by one)
     void *ptrs[] = {p->d_arena, p->d_spec, p->d_glists, p->d_specwork, p->d_fft_scratch, p->d_nodes_scratch,
                     p->d_cterm, p->d_thash, p->d_ex_hash, p->d_ex_w, p->d_ex_mask, p->d_ex_med, p->d_ex_pos,
+                    p->d_ex_cstage,
                     p->d_ls, p->d_gsort, p->d_single, p->d_dflag, p->d_bs_dims};
     (void)hipStreamSynchronize(p->stream);   // the blocks go back to the cache
     for (void *q : ptrs) dev_free(q);
@@ -752,16 +753,26 @@ int mr1l_extract(mr1l_plan p, int64_t n_total, const int64_t *set_off, const int
     if (!dm) dm = p->d_ex_mask;
     if (!dpos && (rc = grow(*p, (void **)&p->d_ex_pos, F * o->s_cap * 4, p->pos_bytes))) return rc;
     if (!dpos) dpos = p->d_ex_pos;
+    // short lists: the vote stages each detection's coordinates, the ordering pass records
+    // the permutation, and the bucket pass reads them from there
+    int32_t *cstage = nullptr, *perm = nullptr;
+    if (cap <= kMaxCap) {
+        const int64_t W = p->dot2 ? (p->d + 1) / 2 : p->d;
+        if ((rc = grow(*p, (void **)&p->d_ex_cstage, F * cap * (W + 1) * 4, p->cstage_bytes))) return rc;
+        cstage = p->d_ex_cstage;
+        perm = p->d_ex_cstage + F * cap * W;
+    }
     (void)dmed;
     (void)esz;
     if ((rc = launch_fill_bytes(out->n_det, (int64_t)sizeof(int64_t) * p->F, p->stream))) return rc;
     {
         StageTimer tm(*p, MR1L_STAGE_VOTE);
-        rc = vote_run(*p, n_total, set_off, freq, nz_bitmap, vmin, cap, out->n_det, out->det_idx, out->votes);
+        rc = vote_run(*p, n_total, set_off, freq, nz_bitmap, vmin, cap, out->n_det, out->det_idx, out->votes,
+                      cstage);
     }
     if (rc) return rc;
     StageTimer tm(*p, MR1L_STAGE_TAIL);
-    return extract_tail_run(*p, n_total, set_off, freq, ghat, *o, *out, dh, dw, dm, dmed, dpos);
+    return extract_tail_run(*p, n_total, set_off, freq, ghat, *o, *out, dh, dw, dm, dmed, dpos, cstage, perm);
 }
 
 int mr1l_adjoint(mr1l_plan p, int64_t cap, int64_t s_cap, const int64_t *n_out, const int32_t *out_pos,

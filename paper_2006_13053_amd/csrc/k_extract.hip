@@ -4,9 +4,9 @@
 //  k_sort_det    detected set of each function in ascending candidate order
 //                (one workgroup per function, bitonic sort in registers, lane
 //                shuffles and, for the longest distances only, LDS).
-//  k_det_hash_pairs / k_det_hash  buckets h_l(k) of every detected candidate
-//                (one thread per candidate and lattice for short lists, one per
-//                candidate for long ones).
+//  k_det_hash_staged / k_det_hash  buckets h_l(k) of every detected candidate,
+//                one thread per candidate: short lists from the coordinates the
+//                vote staged, long ones from the candidate set.
 //  k_singleton   whether each bucket holds one or several detected candidates,
 //                one workgroup per lattice with two LDS bitmaps; bit l of
 //                mask[q] is set when candidate q is alone in its bucket (the
@@ -152,43 +152,62 @@ __device__ __forceinline__ int block_excl_scan(int v, int *wsum)
     return wsum[w] + x - v;
 }
 
+// perm (or NULL): [F][cap] append position of the entry at each place of the ordered list.
 template <int E>
 __global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__restrict__ n_det, int64_t cap,
                                                            int64_t *__restrict__ det_idx,
                                                            const int64_t *__restrict__ set_off, int64_t n_total,
-                                                           int region_bytes, uint32_t *__restrict__ mask, int mw)
+                                                           int region_bytes, uint32_t *__restrict__ mask, int mw,
+                                                           int32_t *__restrict__ perm)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int wsum[kSortThreads / 64];
+    __shared__ int offs[kSortThreads];
     const int f = blockIdx.x, t = threadIdx.x;
+    const int64_t fb = (int64_t)f * cap;
     // the function's singleton masks start cleared (the singleton pass only sets bits)
-    for (int64_t i = t; i < cap * mw; i += kSortThreads) mask[(int64_t)f * cap * mw + i] = 0u;
+    for (int64_t i = t; i < cap * mw; i += kSortThreads) mask[fb * mw + i] = 0u;
     const int n = (int)n_of(n_det, f, cap);
-    if (n <= 1) return;
-    int64_t *src = det_idx + (int64_t)f * cap;
+    if (n == 0) return;
+    int64_t *src = det_idx + fb;
+    if (n == 1) {
+        if (perm && t == 0) perm[fb] = 0;
+        return;
+    }
     const int64_t nset = set_off ? set_off[f + 1] - set_off[f] : n_total;
     if (nset <= (int64_t)region_bytes * 8) {
+        // each entry's place in the ordered list from a bitmap over the function's set: the
+        // bits before it in its word plus the counts of the words before (a block scan over
+        // per-thread runs of words); entry p is held by thread p mod kSortThreads
+        int64_t cv[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = t + kSortThreads * e;
+            cv[e] = p < n ? src[p] : -1;
+        }
         uint32_t *bm = reinterpret_cast<uint32_t *>(smem);
         const int nw = (int)((nset + 31) >> 5);
         for (int w = t; w < nw; w += kSortThreads) bm[w] = 0u;
         __syncthreads();
-        for (int p = t; p < n; p += kSortThreads) {
-            const int64_t q = src[p];
-            atomicOr(bm + (q >> 5), 1u << (q & 31));
-        }
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (cv[e] >= 0) atomicOr(bm + (cv[e] >> 5), 1u << (cv[e] & 31));
         __syncthreads();
         // thread t owns words [t c, t c + c)
         const int c = (nw + kSortThreads - 1) / kSortThreads, w0 = min(nw, t * c), w1 = min(nw, w0 + c);
         int cnt = 0;
         for (int w = w0; w < w1; ++w) cnt += __popc(bm[w]);
-        int o = block_excl_scan(cnt, wsum);
-        for (int w = w0; w < w1; ++w) {
-            uint32_t b = bm[w];
-            while (b) {
-                const int k = __ffs(b) - 1;
-                b &= b - 1;
-                src[o++] = (int64_t)w * 32 + k;
-            }
+        offs[t] = block_excl_scan(cnt, wsum);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (cv[e] < 0) continue;
+            const int w = (int)(cv[e] >> 5), own = w / c;
+            int r = offs[own];
+            for (int x = own * c; x < w; ++x) r += __popc(bm[x]);
+            r += __popc(bm[w] & ((1u << (cv[e] & 31)) - 1u));
+            src[r] = cv[e];
+            if (perm) perm[fb + r] = t + kSortThreads * e;
         }
         return;
     }
@@ -201,57 +220,23 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_det(const int64_t *__rest
     for (int e = 0; e < E; ++e) {
         const int p = t * E + e;
         k[e] = (p < n) ? (uint64_t)src[p] : ~0ull;   // indices are non-negative
-        v[e] = 0;
+        v[e] = p;                                    // the entry's append position
     }
     block_bitonic<E>(k, v, P, lk, lv);
 #pragma unroll
     for (int e = 0; e < E; ++e)
-        if (t * E + e < n) src[t * E + e] = (int64_t)k[e];
+        if (t * E + e < n) {
+            src[t * E + e] = (int64_t)k[e];
+            if (perm) perm[fb + t * E + e] = v[e];
+        }
 }
 
 // ------------------------------------------------------------------ hashes of detected
 // Fast path (every |k_u| within the function's bound kb): 24-bit multiply-adds in 32-bit
 // integers and the float-reciprocal modulo; else the exact 64-bit reduction.  Both give
 // the same bucket.
-__device__ __forceinline__ int32_t det_bucket(const int64_t *__restrict__ freq, int64_t n_total, int64_t ci, int d,
-                                              const LatDesc &ld, const int32_t *__restrict__ z32,
-                                              const int64_t *__restrict__ z64, int32_t kb)
-{
-    uint32_t s = ld.off32;
-    bool fast = true;
-    for (int u = 0; u < d; ++u) {
-        const int64_t k = freq[(int64_t)u * n_total + ci];
-        fast = fast & (k >= -kb) & (k <= kb);
-        s += (uint32_t)__mul24((int32_t)k, z32[ld.z_off + u]);
-    }
-    return fast ? (int32_t)fast_mod(s, (uint32_t)ld.M, ld.inv_m)
-                : exact_bucket(freq + ci, n_total, d, z64 + ld.z_off, ld.M);
-}
-
-// Short lists (capacity <= 8192): one thread per (detected candidate, lattice); the L
-// threads of a candidate read the same coordinates (cache hits after the first) and
-// write adjacent buckets.  With few, scattered detections in a large candidate set the
-// coordinate reads are random, and the L-fold parallelism hides their latency better
-// than one thread per candidate.
-__global__ __launch_bounds__(256) void k_det_hash_pairs(
-    const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int L, int d,
-    const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32, const int64_t *__restrict__ z64,
-    const int32_t *__restrict__ kbound, const int64_t *__restrict__ n_det, int64_t cap,
-    const int64_t *__restrict__ det_idx, int32_t *__restrict__ det_hash)
-{
-    const int f = blockIdx.y;
-    const int64_t nl = n_of(n_det, f, cap) * L;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nl; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = t / L;
-        const int l = (int)(t - q * L);
-        const int64_t ci = set_off[f] + det_idx[(int64_t)f * cap + q];
-        det_hash[((int64_t)f * cap + q) * L + l] =
-            det_bucket(freq, n_total, ci, d, lat[f * L + l], z32, z64, kbound[f]);
-    }
-}
-
-// Long lists: one thread per detected candidate.
-// One thread per detected candidate: its d coordinates are read once (adjacent threads
+//
+// Long lists: one thread per detected candidate: its d coordinates are read once (adjacent threads
 // hold adjacent entries of the ascending list) and hashed into all L lattices of its
 // function, with L running sums in registers; the lattice records and z words are
 // workgroup-uniform (scalar loads).  The chunk's buckets go through LDS in output order
@@ -306,6 +291,61 @@ __global__ __launch_bounds__(kDetHashThreads) void k_det_hash(
         __syncthreads();
         const int64_t cnt = min<int64_t>(kDetHashThreads, n - q0) * L;
         int32_t *dst = det_hash + ((int64_t)f * cap + q0) * L;
+        for (int64_t i = t; i < cnt; i += kDetHashThreads) dst[i] = hs[i];
+        __syncthreads();
+    }
+}
+
+// Short lists: one thread per entry of the ordered list, from the coordinates the vote
+// staged at the entry's append position (perm): W = ceil(d/2) packed 16-bit pairs or d low
+// words, read once, hashed into all L lattices with the 32-bit fast path (valid: the vote
+// staged only candidates within the batch's fast bound, which no function's exceeds); an
+// entry marked INT32_MIN takes the exact path from the candidate set.  Buckets staged in
+// LDS for contiguous stores, as above.
+template <int LM>
+__global__ __launch_bounds__(kDetHashThreads) void k_det_hash_staged(
+    const int64_t *__restrict__ freq, int64_t n_total, const int64_t *__restrict__ set_off, int L, int d,
+    int packed, const LatDesc *__restrict__ lat, const int32_t *__restrict__ z32, const int64_t *__restrict__ z64,
+    const int64_t *__restrict__ n_det, int64_t cap, const int64_t *__restrict__ det_idx,
+    const int32_t *__restrict__ cstage, const int32_t *__restrict__ perm, int32_t *__restrict__ det_hash)
+{
+    extern __shared__ int32_t hs[];
+    const int f = blockIdx.y, t = threadIdx.x;
+    const int64_t n = n_of(n_det, f, cap);
+    const int64_t fb = (int64_t)f * cap;
+    const int W = packed ? (d + 1) / 2 : d;
+    const LatDesc *lf = lat + (int64_t)f * L;
+    for (int64_t q0 = (int64_t)blockIdx.x * kDetHashThreads; q0 < n; q0 += (int64_t)gridDim.x * kDetHashThreads) {
+        const int64_t q = q0 + t;
+        if (q < n) {
+            const int32_t *cs = cstage + (fb + perm[fb + q]) * W;
+            if (cs[0] != INT32_MIN) {
+                uint32_t acc[LM];
+#pragma unroll
+                for (int l = 0; l < LM; ++l) acc[l] = l < L ? lf[l].off32 : 0u;
+                for (int w = 0; w < W; ++w) {
+                    const int32_t x = cs[w];
+                    const int nu = packed ? min(2, d - 2 * w) : 1;
+                    for (int h = 0; h < nu; ++h) {
+                        const int u = packed ? 2 * w + h : w;
+                        const int32_t k = packed ? (int32_t)(int16_t)(x >> (16 * h)) : x;
+#pragma unroll
+                        for (int l = 0; l < LM; ++l)
+                            if (l < L) acc[l] += (uint32_t)__mul24(k, z32[lf[l].z_off + u]);
+                    }
+                }
+#pragma unroll
+                for (int l = 0; l < LM; ++l)
+                    if (l < L) hs[t * L + l] = (int32_t)fast_mod(acc[l], (uint32_t)lf[l].M, lf[l].inv_m);
+            } else {
+                const int64_t ci = set_off[f] + det_idx[fb + q];
+                for (int l = 0; l < L; ++l)
+                    hs[t * L + l] = exact_bucket(freq + ci, n_total, d, z64 + lf[l].z_off, lf[l].M);
+            }
+        }
+        __syncthreads();
+        const int64_t cnt = min<int64_t>(kDetHashThreads, n - q0) * L;
+        int32_t *dst = det_hash + (fb + q0) * L;
         for (int64_t i = t; i < cnt; i += kDetHashThreads) dst[i] = hs[i];
         __syncthreads();
     }
@@ -1520,7 +1560,7 @@ static int limit_short(Plan &p, const int64_t *n_det, int64_t cap, const int64_t
 
 int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq, const void *ghat,
                      const mr1l_extract_opts &o, const mr1l_extract_out &out, int32_t *det_hash, double *det_w,
-                     uint32_t *det_mask, void *det_med, int32_t *out_pos)
+                     uint32_t *det_mask, void *det_med, int32_t *out_pos, const int32_t *cstage, int32_t *perm)
 {
     const int64_t cap = o.cap;
     const bool large = cap > kMaxCap;
@@ -1530,7 +1570,7 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
         const size_t sb = std::max<size_t>((size_t)pow2ceil(std::max<int64_t>(cap, 1)) * 12, kSortBitmapBytes);
 #define MR1L_SD(E) \
     hipLaunchKernelGGL(k_sort_det<E>, dim3(p.F), dim3(kSortThreads), sb, p.stream, out.n_det, cap, out.det_idx, \
-                       set_off, n_total, (int)sb, det_mask, mask_words(p.L))
+                       set_off, n_total, (int)sb, det_mask, mask_words(p.L), perm)
         MR1L_BY_E(sort_e(cap), MR1L_SD)
 #undef MR1L_SD
         MR1L_LAUNCH_CHECK();
@@ -1567,10 +1607,16 @@ int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int
             MR1L_LAUNCH_CHECK();
         }
     }
+    if (!large && !cstage) return fail(MR1L_E_ARG, "short lists need the staged coordinates");
     if (nmax > 0 && !large) {
-        dim3 gq(tail_blocks((nmax * p.L + 255) / 256, p.F, 4), (unsigned)p.F);
-        hipLaunchKernelGGL(k_det_hash_pairs, gq, dim3(256), 0, p.stream, freq, n_total, set_off, p.L, p.d, p.d_lat,
-                           p.d_z32, p.d_z64, p.d_kb, out.n_det, cap, out.det_idx, det_hash);
+        dim3 gq(tail_blocks((nmax + kDetHashThreads - 1) / kDetHashThreads, p.F, 4), (unsigned)p.F);
+        const size_t hb = (size_t)kDetHashThreads * p.L * sizeof(int32_t);
+#define MR1L_DS(LM)                                                                                               \
+    hipLaunchKernelGGL(k_det_hash_staged<LM>, gq, dim3(kDetHashThreads), hb, p.stream, freq, n_total, set_off, p.L, \
+                       p.d, (int)p.dot2, p.d_lat, p.d_z32, p.d_z64, out.n_det, cap, out.det_idx, cstage, perm,      \
+                       det_hash)
+        MR1L_BY_L(p.L, MR1L_DS)
+#undef MR1L_DS
         MR1L_LAUNCH_CHECK();
     } else if (nmax > 0) {
         dim3 gq(tail_blocks((nmax + kDetHashThreads - 1) / kDetHashThreads, p.F, 4), (unsigned)p.F);

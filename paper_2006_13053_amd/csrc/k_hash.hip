@@ -77,7 +77,8 @@ void k_vote(
     int L, int d_rt, const LatDesc *__restrict__ lat, const int64_t *__restrict__ z64,
     const uint32_t *__restrict__ vrec, int rs, int32_t kb_min,
     const uint32_t *__restrict__ bitmap, int64_t bm_words, int vote_min, int64_t cap,
-    int64_t *__restrict__ det_cnt, int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes)
+    int64_t *__restrict__ det_cnt, int64_t *__restrict__ det_idx, uint8_t *__restrict__ votes,
+    int32_t *__restrict__ cstage)
 {
     // D > 0: exactly D coordinates; D < 0: runtime d <= -D; D == 0: runtime d <= kMaxD
     const int d = D > 0 ? D : d_rt;
@@ -305,7 +306,27 @@ void k_vote(
                 unsigned long long base = 0;
                 if (lane == first) base = atomicAdd((unsigned long long *)(det_cnt + f), (unsigned long long)cnt);
                 base = __shfl(base, first);
-                if (det && (int64_t)(base + rank) < cap) det_idx[f * cap + base + rank] = c - f_lo;
+                const int64_t pos = (int64_t)(base + rank);
+                if (det && pos < cap) {
+                    det_idx[f * cap + pos] = c - f_lo;
+                    // short lists: the detected candidate's coordinates as hashed here (the
+                    // packed pairs or the low words), at its append position, so that the
+                    // bucket pass reads a compact list instead of the candidate set
+                    if (cstage) {
+                        int32_t *cs = cstage + (f * cap + pos) * (int64_t)zw;
+                        if (!fast) {
+                            cs[0] = INT32_MIN;   // beyond the fast bound: the exact path rereads it
+                        } else if constexpr (DOT2) {
+#pragma unroll
+                            for (int j = 0; j < ZW; ++j)
+                                if (j < zw) cs[j] = (int32_t)kp[j];
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < DM; ++u)
+                                if (u < d) cs[u] = lo[u];
+                        }
+                    }
+                }
             }
             seg = sEnd;
         }
@@ -315,7 +336,7 @@ void k_vote(
 #define MR1L_VOTE_LAUNCH(Dv, LD, D2)                                                                       \
     hipLaunchKernelGGL((k_vote<Dv, LD, D2>), grid, blk, shm, p.stream, freq, n_total, set_off, p.F, p.L, p.d, \
                        p.d_lat, p.d_z64, p.d_vrec, p.vrec_stride, kb_min, bitmap, bm_words, vote_min, cap, n_det,   \
-                       det_idx, votes)
+                       det_idx, votes, cstage)
 #define MR1L_VOTE_DISPATCH(Dv)                                          \
     case Dv:                                                            \
         if (lds) {                                                      \
@@ -344,7 +365,7 @@ int vote_init_attrs()
 
 int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
              const uint32_t *bitmap, int32_t vote_min, int64_t cap, int64_t *n_det, int64_t *det_idx,
-             uint8_t *votes)
+             uint8_t *votes, int32_t *cstage)
 {
     // n_det is zero-filled by the caller (outside the timed vote stage)
     if (n_total <= 0) return MR1L_OK;

@@ -201,6 +201,8 @@ struct Plan {
     uint32_t *d_ex_mask = nullptr;   // [F][cap][mask_words(L)]
     void *d_ex_med = nullptr;        // [F][cap] complex
     int32_t *d_ex_pos = nullptr;     // [F][s_cap]
+    int32_t *d_ex_cstage = nullptr;  // short lists: staged coordinates [F][cap][W] and the order
+    int64_t cstage_bytes = 0;        //   pass's permutation [F][cap] behind them
     int64_t ex_scap = 0;
     void *d_gsort = nullptr;         // global sort pairs of long detected lists: [F][P] uint64 + [F][P] int32
     int64_t gsort_bytes = 0;
@@ -307,15 +309,18 @@ int fft_init_attrs();
 int extract_init_attrs();
 int vote_init_attrs();
 
+// cstage (or NULL): [F][cap][W] coordinates of every detected candidate at its append
+// position as the vote hashed them: W = ceil(d/2) packed 16-bit pairs when p.dot2, else d
+// low words; first word INT32_MIN for a candidate beyond the fast bound.
 int vote_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
              const uint32_t *bitmap, int32_t vote_min, int64_t cap, int64_t *n_det,
-             int64_t *det_idx, uint8_t *votes);
+             int64_t *det_idx, uint8_t *votes, int32_t *cstage);
 int hash_count_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
                    int32_t *hash, int32_t *counts);
 int extract_tail_run(Plan &p, int64_t n_total, const int64_t *set_off, const int64_t *freq,
                      const void *ghat, const mr1l_extract_opts &o, const mr1l_extract_out &out,
                      int32_t *det_hash, double *det_w, uint32_t *det_mask, void *det_med,
-                     int32_t *out_pos);
+                     int32_t *out_pos, const int32_t *cstage, int32_t *perm);
 int sample_init_attrs();
 // Address of the static term scratch on the current device (looked up once per device).
 int sample_static_scratch(void **out);

@@ -883,6 +883,43 @@ def test_long_lists_lattice_groups_match_oracle(m, L, mlo, mhi, F):
         check_limit(r, ro, EPS[torch.complex128], 1e-11)
 
 
+@pytest.mark.parametrize("mlo,mhi", [(2000, 3000), (40000, 50000)])
+def test_short_lists_staged_coordinates_match_oracle(m, mlo, mhi):
+    """Short detected lists take their buckets from the coordinates the vote pass staged:
+    packed 16-bit pairs when every M <= 2^15 (first case), 32-bit words otherwise (second),
+    and for candidates beyond the fast bound (|k| near 2^40 here) the exact path from the
+    candidate set.  Random lattice values with every bitmap bit set, so that every
+    candidate is detected; against the oracle, two functions of unequal size."""
+    say("short lists, staged coordinates", mlo)
+    rng = np.random.default_rng(mlo)
+    d, L = 3, 7
+    sets, Ms, zs, gs = [], [], [], []
+    for fi in range(2):
+        c = synth.distinct_uniform_points(rng, 3000 - 700 * fi, d, -200, 200)
+        big = np.array([[(1 << 40) + 7 * j + fi, -(1 << 40) - j, 3 * j] for j in range(5)], np.int64).T
+        sets.append(np.concatenate([c[:, :1000], big, c[:, 1000:]], axis=1))
+        M, z = synth.draw_lattices(rng, L, d, mlo, mhi)
+        Ms.append(M)
+        zs.append(z)
+        gs.append(rng.standard_normal(int(M.sum())) + 1j * rng.standard_normal(int(M.sum())))
+    plan = m.Plan(d, np.concatenate(Ms), np.concatenate(zs), F=2)
+    bm = torch.full(((plan.nodes + 31) // 32,), -1, dtype=torch.int32, device=dev())
+    off = np.concatenate([[0], np.cumsum([x.shape[1] for x in sets])]).astype(np.int64)
+    ex = m.mr1l_extract(plan, T(np.concatenate(sets, axis=1)), T(np.concatenate(gs)), bm, 1e-9, s_cap=500,
+                        cap=4096, set_off=T(off), want_w=False)
+    torch.cuda.synchronize()
+    for fi in range(2):
+        ro = oracle.extract(sets[fi], Ms[fi], zs[fi], gs[fi], 1e-9, s_cap=500, cap=4096)
+        nd = int(ex["n_det"][fi])
+        assert nd == ro["n_det"] == sets[fi].shape[1]
+        assert np.array_equal(ex["det_idx"][fi, :nd].cpu().numpy(), ro["det_idx"])
+        assert np.array_equal(mask64(ex["det_mask"][fi, :nd]), ro["det_mask"])
+        close(ex["det_coef"][fi, :nd].cpu().numpy(), ro["det_coef"], 1e-11, "coefficients")
+        no = int(ex["n_out"][fi])
+        r = dict(out_idx=ex["out_idx"][fi, :no].cpu().numpy(), out_coef=ex["out_coef"][fi, :no].cpu().numpy())
+        check_limit(r, ro, EPS[torch.complex128], 1e-11)
+
+
 def test_empty_and_ragged_inputs(m):
     say("empty/ragged")
     p = synth.small_config(8)
