@@ -628,10 +628,11 @@ __global__ __launch_bounds__(256) void k_combine(
 {
     using V = typename cvec<T>::type;
     int f = blockIdx.y, bx = blockIdx.x;
-    if constexpr (TW) {
+    if ((gridDim.x * gridDim.y) % 8 == 0) {
         // workgroups are dealt to the 8 XCDs in turn; renumbered so that each XCD takes a
-        // contiguous range of (function, block) pairs, i.e. the lattice values of one or
-        // two functions, which its L2 then holds (the host makes the count a multiple of 8)
+        // contiguous range of (function, block) pairs, i.e. the lattice values of few
+        // functions, which its L2 then holds (whenever the count is a multiple of 8; the
+        // host rounds it up for long lists)
         const int G = gridDim.x * gridDim.y, w = blockIdx.y * gridDim.x + blockIdx.x;
         const int i = (w & 7) * (G >> 3) + (w >> 3);
         f = i / gridDim.x;
