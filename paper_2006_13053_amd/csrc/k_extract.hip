@@ -367,7 +367,15 @@ __global__ __launch_bounds__(256) void k_singleton(const LatDesc *__restrict__ l
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *once = reinterpret_cast<uint32_t *>(smem);
     uint32_t *twice = once + words;
-    const int l = blockIdx.x, f = blockIdx.y;
+    int l = blockIdx.x, f = blockIdx.y;
+    if ((gridDim.x * gridDim.y) % 8 == 0) {
+        // the L workgroups of a function on one XCD (workgroups are dealt to the 8 XCDs in
+        // turn): they read the same bucket rows and set bits in the same mask words
+        const int G = gridDim.x * gridDim.y, w = blockIdx.y * gridDim.x + blockIdx.x;
+        const int i = (w & 7) * (G >> 3) + (w >> 3);
+        f = i / gridDim.x;
+        l = i - f * gridDim.x;
+    }
     const int n = (int)n_of(n_det, f, cap);
     if (n == 0) return;
     const int M = lat[f * L + l].M;
